@@ -1,0 +1,259 @@
+/*
+ * CPU oracle for the StereoVAE hot path -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, scalar loops that state each operation as its definition.
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * may load this library.  It shares no source, header or helper with the GPU
+ * library: it has its own declarations below and is built by gcc, not hipcc.
+ *
+ * Integer steps (downsample, census, Hamming cost, winner-take-all) are exact.
+ * Network primitives (convolution, bilinear resize and their adjoints) work in
+ * FP64 on NCHW arrays; the network is composed from them in oracle/vae.py.
+ *
+ * Pins: every function here is checked by the CPU tests against brute force,
+ * closed forms, invariants or an independent library routine (torch CPU
+ * float64), never against the GPU library.
+ */
+#include <stdint.h>
+#include <stddef.h>
+#include <string.h>
+#include <math.h>
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* ------------------------------------------------------------------------ */
+/* Matching: the coarse disparity map of Sec. III-A, computed on the reduced */
+/* ("small") image pair.                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* Reduced-resolution image ("small image pairs", Sec. IV-C; quarter-size
+ * inputs, Table I).  The paper does not state the filter; this is the f x f
+ * block mean with round-half-up, partial edge blocks averaged over their
+ * in-bounds pixels.  out[b][i][j] for i < ceil(H/f), j < ceil(W/f). */
+void or_downsample(const uint8_t *img, int B, int H, int W, int pitch, int f, uint8_t *out)
+{
+    int h = (H + f - 1) / f, w = (W + f - 1) / f;
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < w; ++j) {
+                long S = 0, n = 0;
+                for (int y = f * i; y < f * i + f && y < H; ++y)
+                    for (int x = f * j; x < f * j + f && x < W; ++x) {
+                        S += img[(size_t)b * H * pitch + (size_t)y * pitch + x];
+                        ++n;
+                    }
+                out[((size_t)b * h + i) * w + j] = (uint8_t)((S + n / 2) / n);
+            }
+}
+
+/* Census transform (named in Sec. I and Sec. III; robustness variants S1/S2 of
+ * Sec. IV-C).  Window win_w wide and win_h tall, both odd; offsets enumerated
+ * row by row (dy outer, dx inner) skipping the centre, bit k set when the
+ * k-th neighbour is strictly darker than the centre.  Borders clamp to the
+ * edge.  Bits at and above nbits = win_w*win_h - 1 are zero. */
+void or_census(const uint8_t *img, int B, int h, int w, int win_w, int win_h, uint64_t *out)
+{
+    int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < w; ++j) {
+                const uint8_t *im = img + (size_t)b * h * w;
+                int centre = im[(size_t)i * w + j];
+                uint64_t code = 0;
+                int k = 0;
+                for (int dy = -ry; dy <= ry; ++dy)
+                    for (int dx = -rx; dx <= rx; ++dx) {
+                        if (dy == 0 && dx == 0)
+                            continue;
+                        int y = clampi(i + dy, 0, h - 1), x = clampi(j + dx, 0, w - 1);
+                        if (im[(size_t)y * w + x] < centre)
+                            code |= (uint64_t)1 << k;
+                        ++k;
+                    }
+                out[((size_t)b * h + i) * w + j] = code;
+            }
+}
+
+static int popcount64(uint64_t v)
+{
+    int c = 0;
+    while (v) {
+        c += (int)(v & 1u);
+        v >>= 1;
+    }
+    return c;
+}
+
+/* Matching cost volume C(x, y, d) between reference pixel (x, y) of the left
+ * view and target pixel (x - d, y) of the right view (the indexing of Eq. (1)
+ * and Eq. (4)), here the Hamming distance of census codes.  A target column
+ * outside the image costs nbits + 1.  cost[b][i][j][d], d < D. */
+void or_cost_volume(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
+                    int32_t *cost)
+{
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < w; ++j)
+                for (int d = 0; d < D; ++d) {
+                    size_t o = (((size_t)b * h + i) * w + j) * D + d;
+                    if (j - d < 0)
+                        cost[o] = nbits + 1;
+                    else
+                        cost[o] = popcount64(cl[((size_t)b * h + i) * w + j] ^
+                                             cr[((size_t)b * h + i) * w + (j - d)]);
+                }
+}
+
+/* Winner-take-all, Eq. (6): the disparity of least cost, the lowest one on ties. */
+void or_wta(const int32_t *cost, int B, int h, int w, int D, uint8_t *disp)
+{
+    for (size_t p = 0; p < (size_t)B * h * w; ++p) {
+        int best = 0;
+        for (int d = 1; d < D; ++d)
+            if (cost[p * D + d] < cost[p * D + best])
+                best = d;
+        disp[p] = (uint8_t)best;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Network primitives (Table I), FP64, NCHW.                                 */
+/* ------------------------------------------------------------------------ */
+
+/* 2-D convolution (cross-correlation), zero padding:
+ *   y[b,o,p,q] = bias[o] + sum_{c,u,v} wt[o,c,u,v] * x[b,c, s*p+u-pad, s*q+v-pad]
+ * Output size Ho = (H + 2*pad - k)/s + 1. */
+void or_conv2d(const double *x, int B, int C, int H, int W, const double *wt, const double *bias,
+               int O, int k, int s, int pad, double *y)
+{
+    int Ho = (H + 2 * pad - k) / s + 1, Wo = (W + 2 * pad - k) / s + 1;
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < O; ++o)
+            for (int p = 0; p < Ho; ++p)
+                for (int q = 0; q < Wo; ++q) {
+                    double acc = bias ? bias[o] : 0.0;
+                    for (int c = 0; c < C; ++c)
+                        for (int u = 0; u < k; ++u)
+                            for (int v = 0; v < k; ++v) {
+                                int yy = s * p + u - pad, xx = s * q + v - pad;
+                                if (yy < 0 || yy >= H || xx < 0 || xx >= W)
+                                    continue;
+                                acc += wt[(((size_t)o * C + c) * k + u) * k + v] *
+                                       x[(((size_t)b * C + c) * H + yy) * W + xx];
+                            }
+                    y[(((size_t)b * O + o) * Ho + p) * Wo + q] = acc;
+                }
+}
+
+/* Adjoint of or_conv2d with respect to x: every term of the forward sum that
+ * reads x[...] sends wt * dy back to it.  dx is overwritten. */
+void or_conv2d_dx(const double *dy, int B, int C, int H, int W, const double *wt, int O, int k,
+                  int s, int pad, double *dx)
+{
+    int Ho = (H + 2 * pad - k) / s + 1, Wo = (W + 2 * pad - k) / s + 1;
+    memset(dx, 0, sizeof(double) * (size_t)B * C * H * W);
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < O; ++o)
+            for (int p = 0; p < Ho; ++p)
+                for (int q = 0; q < Wo; ++q) {
+                    double g = dy[(((size_t)b * O + o) * Ho + p) * Wo + q];
+                    for (int c = 0; c < C; ++c)
+                        for (int u = 0; u < k; ++u)
+                            for (int v = 0; v < k; ++v) {
+                                int yy = s * p + u - pad, xx = s * q + v - pad;
+                                if (yy < 0 || yy >= H || xx < 0 || xx >= W)
+                                    continue;
+                                dx[(((size_t)b * C + c) * H + yy) * W + xx] +=
+                                    wt[(((size_t)o * C + c) * k + u) * k + v] * g;
+                            }
+                }
+}
+
+/* Adjoint of or_conv2d with respect to wt and bias (overwritten). */
+void or_conv2d_dw(const double *x, const double *dy, int B, int C, int H, int W, int O, int k,
+                  int s, int pad, double *dwt, double *dbias)
+{
+    int Ho = (H + 2 * pad - k) / s + 1, Wo = (W + 2 * pad - k) / s + 1;
+    memset(dwt, 0, sizeof(double) * (size_t)O * C * k * k);
+    if (dbias)
+        memset(dbias, 0, sizeof(double) * (size_t)O);
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < O; ++o)
+            for (int p = 0; p < Ho; ++p)
+                for (int q = 0; q < Wo; ++q) {
+                    double g = dy[(((size_t)b * O + o) * Ho + p) * Wo + q];
+                    if (dbias)
+                        dbias[o] += g;
+                    for (int c = 0; c < C; ++c)
+                        for (int u = 0; u < k; ++u)
+                            for (int v = 0; v < k; ++v) {
+                                int yy = s * p + u - pad, xx = s * q + v - pad;
+                                if (yy < 0 || yy >= H || xx < 0 || xx >= W)
+                                    continue;
+                                dwt[(((size_t)o * C + c) * k + u) * k + v] +=
+                                    x[(((size_t)b * C + c) * H + yy) * W + xx] * g;
+                            }
+                }
+}
+
+/* Source index pair and weight of bilinear resampling along one axis
+ * (half-pixel centres, no corner alignment): s = (o + 1/2) * n_in / n_out - 1/2,
+ * clamped below at 0; i0 = floor(s), i1 = min(i0 + 1, n_in - 1), lambda = s - i0. */
+static void bilinear_axis(int o, int n_in, int n_out, int *i0, int *i1, double *lam)
+{
+    double s = ((double)o + 0.5) * (double)n_in / (double)n_out - 0.5;
+    if (s < 0.0)
+        s = 0.0;
+    int a = (int)floor(s);
+    if (a > n_in - 1)
+        a = n_in - 1;
+    *i0 = a;
+    *i1 = a + 1 < n_in ? a + 1 : n_in - 1;
+    *lam = s - (double)a;
+}
+
+/* Bilinear resize of N planes from Hi x Wi to Ho x Wo (upsampling layers of
+ * the decoder and the final upsampling layer, Table I):
+ *   y[n,p,q] = sum over the 2x2 source neighbourhood of (1-ly|ly)(1-lx|lx) x[...] */
+void or_resize_bilinear(const double *x, int N, int Hi, int Wi, int Ho, int Wo, double *y)
+{
+    for (int n = 0; n < N; ++n)
+        for (int p = 0; p < Ho; ++p) {
+            int y0, y1;
+            double ly;
+            bilinear_axis(p, Hi, Ho, &y0, &y1, &ly);
+            for (int q = 0; q < Wo; ++q) {
+                int x0, x1;
+                double lx;
+                bilinear_axis(q, Wi, Wo, &x0, &x1, &lx);
+                const double *src = x + (size_t)n * Hi * Wi;
+                double top = (1.0 - lx) * src[(size_t)y0 * Wi + x0] + lx * src[(size_t)y0 * Wi + x1];
+                double bot = (1.0 - lx) * src[(size_t)y1 * Wi + x0] + lx * src[(size_t)y1 * Wi + x1];
+                y[((size_t)n * Ho + p) * Wo + q] = (1.0 - ly) * top + ly * bot;
+            }
+        }
+}
+
+/* Adjoint of or_resize_bilinear: each output's gradient goes back to its four
+ * sources with the same weights.  dx is overwritten. */
+void or_resize_bilinear_adj(const double *dy, int N, int Hi, int Wi, int Ho, int Wo, double *dx)
+{
+    memset(dx, 0, sizeof(double) * (size_t)N * Hi * Wi);
+    for (int n = 0; n < N; ++n)
+        for (int p = 0; p < Ho; ++p) {
+            int y0, y1;
+            double ly;
+            bilinear_axis(p, Hi, Ho, &y0, &y1, &ly);
+            for (int q = 0; q < Wo; ++q) {
+                int x0, x1;
+                double lx;
+                bilinear_axis(q, Wi, Wo, &x0, &x1, &lx);
+                double g = dy[((size_t)n * Ho + p) * Wo + q];
+                double *d = dx + (size_t)n * Hi * Wi;
+                d[(size_t)y0 * Wi + x0] += (1.0 - ly) * (1.0 - lx) * g;
+                d[(size_t)y0 * Wi + x1] += (1.0 - ly) * lx * g;
+                d[(size_t)y1 * Wi + x0] += ly * (1.0 - lx) * g;
+                d[(size_t)y1 * Wi + x1] += ly * lx * g;
+            }
+        }
+}
