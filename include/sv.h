@@ -1,0 +1,280 @@
+/*
+ * sv.h -- C ABI of libsv.so, the MI355X (gfx950) hot path of StereoVAE
+ * (Chang et al., "StereoVAE: A lightweight stereo-matching system using
+ * embedded GPUs", arXiv 2305.11566).
+ *
+ * A rectified uint8 stereo pair goes in, a dense full-resolution disparity
+ * map comes out (the problem statement of Sec. I and Sec. III-B1): the pair is
+ * reduced by a factor f, matched by census + Hamming cost + winner-take-all
+ * at the reduced resolution, and the tiny VAE of Table I upsamples and refines
+ * the coarse map.
+ *
+ * Conventions shared by every entry point
+ *  - Pointers marked (device) are device memory owned by the caller; pointers
+ *    marked (host) are read during the call only.  The library never
+ *    allocates inside these calls, except sv_batch_plan_create/_destroy and
+ *    sv_autotune, which own what they allocate.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *    call is asynchronous on it; nothing here synchronises the host.
+ *  - All arguments are validated before anything is enqueued, and validation
+ *    makes no HIP call; a failed check returns a negative code and enqueues
+ *    nothing.  A HIP launch error is returned as SV_ERR_HIP; errors raised
+ *    later on the device surface on a later call or at synchronisation.
+ *  - Image layouts are row-major; network tensors are NHWC.  Disparities are
+ *    in pixels of the resolution they are stored at, the left view is the
+ *    reference and a left pixel x matches right pixel x - d.
+ *  - Integer results are bitwise deterministic; floating-point results are
+ *    deterministic for a fixed tile configuration (no floating-point atomics).
+ */
+#ifndef SV_H_
+#define SV_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sv_status;
+
+#define SV_OK 0
+#define SV_ERR_NULL (-1)        /* a required pointer is NULL */
+#define SV_ERR_SHAPE (-2)       /* a size is non-positive or inconsistent */
+#define SV_ERR_RANGE (-3)       /* a parameter is outside its supported range */
+#define SV_ERR_DTYPE (-4)       /* unknown dtype code */
+#define SV_ERR_WORKSPACE (-5)   /* workspace / saved buffer smaller than required */
+#define SV_ERR_UNSUPPORTED (-6) /* valid but not supported by this build */
+#define SV_ERR_HIP (-7)         /* the HIP runtime reported an error */
+
+/* Compute / storage precision of the network's convolutions.  Accumulation is
+ * FP32 in every case; the residual base, the latent, KL and loss stay FP32. */
+#define SV_F32 0
+#define SV_BF16 1
+#define SV_F16 2
+
+/* Human-readable name of a status code (static storage). */
+const char *sv_status_str(sv_status s);
+
+/* Last HIP error text seen by this thread (static per thread). */
+const char *sv_last_error(void);
+
+/* ------------------------------------------------------------------------ */
+/* Coarse matching (Sec. III-A)                                              */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Reduce and census-transform a batch of images.
+ *
+ * Reduction ("small image pairs", Sec. IV-C; quarter-size inputs, Table I):
+ * low[b][i][j] = round-half-up mean of the in-bounds pixels of the f x f block
+ * at (f*i, f*j), for i < h = ceil(H/f), j < w = ceil(W/f); f = 1 copies.
+ * Census (named in Sec. I and Sec. III; variants S1/S2 of Sec. IV-C): for a
+ * win_w x win_h window (both odd), neighbours enumerated row by row skipping
+ * the centre, bit k of census[b][i][j] is 1 when neighbour k is strictly
+ * smaller than the centre; borders clamp to the edge; nbits = win_w*win_h - 1
+ * <= 64 and higher bits are 0.
+ *
+ * img        (device) uint8 [B][H][pitch], pitch >= W bytes per row
+ * factor     1..8
+ * low_out    (device, nullable) uint8 [B][h][w]
+ * census_out (device) uint64 [B][h][w]
+ * Errors: SV_ERR_NULL (img, census_out), SV_ERR_SHAPE (B,H,W <= 0, pitch < W),
+ *         SV_ERR_RANGE (factor, even or < 1 window, nbits > 64).
+ */
+sv_status sv_census(const uint8_t *img, int B, int H, int W, int pitch, int factor, int win_w,
+                    int win_h, uint8_t *low_out, uint64_t *census_out, void *stream);
+
+/*
+ * Both views of a batch of pairs in one launch: same contract as sv_census
+ * applied to `left` (reduced image written to low_left when non-NULL) and to
+ * `right`.
+ */
+sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H, int W,
+                         int pitch, int factor, int win_w, int win_h, uint8_t *low_left,
+                         uint64_t *cen_left, uint64_t *cen_right, void *stream);
+
+/*
+ * Hamming matching cost and winner-take-all, Eq. (6).
+ *
+ * cost(i, j, d) = popcount(cen_l[i][j] XOR cen_r[i][j-d]) for j-d >= 0, and
+ * nbits + 1 when j - d < 0 (the target column of Eq. (1) leaves the image);
+ * disp_out[b][i][j] = the least-cost d in [0, D), the lowest d on ties.  The
+ * cost volume is never stored.
+ *
+ * cen_l, cen_r (device) uint64 [B][h][w]
+ * D            1..256;  nbits 1..64
+ * disp_out     (device) uint8 [B][h][w], in reduced-resolution pixels
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE (D, nbits).
+ */
+sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D,
+                      int nbits, uint8_t *disp_out, void *stream);
+
+/* Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8; default 4).  The
+ * result does not depend on it.  Process-wide; not for concurrent use. */
+sv_status sv_set_cost_wta_split(int dsplit);
+
+/* ------------------------------------------------------------------------ */
+/* Refinement network (Sec. III-B, Table I)                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Network shape.  Encoder: three 3x3 stride-2 convolutions 2 -> c1 -> c2 -> c3
+ * with leaky ReLU (slope 0.1); head: 1x1 conv c3 -> 2*latent = [mu | logvar];
+ * decoder: G3 = 1x1 conv latent -> c3, then three levels that bilinearly
+ * resize the previous map to the next encoder level (half-pixel centres),
+ * concatenate that level's encoder map (skip connection) and apply a 3x3
+ * conv (c3+c2 -> c2, c2+c1 -> c1, c1+2 -> c1); final layer: resize
+ * [G0, x0] to H x W and apply a 3x3 conv to one channel, added to the
+ * bilinear upscaling of the coarse map.  Input x0 = [f*d/256, I/256] and
+ * the output is scaled back by 256 (Sec. III-B2), in full-resolution pixels.
+ *
+ * Canonical parameter vector (FP32): per layer in the order E1, E2, E3, HEAD,
+ * G3, G2, G1, G0, F, the weights in OIHW order followed by the bias.
+ */
+typedef struct sv_vae_desc {
+    int32_t c1, c2, c3; /* encoder widths, each a multiple of 8, <= 256 */
+    int32_t latent;     /* latent channels L, multiple of 8, <= 256 */
+    int32_t factor;     /* reduction factor f between the pair and the coarse map, 1..8 */
+    int32_t dtype;      /* SV_F32, SV_BF16 or SV_F16 */
+} sv_vae_desc;
+
+/* Number of FP32 values in the canonical parameter vector (negative on error). */
+int64_t sv_vae_param_count(const sv_vae_desc *desc);
+
+/* Bytes of the packed device weight image that sv_vae_pack_weights writes. */
+size_t sv_vae_packed_bytes(const sv_vae_desc *desc);
+
+/*
+ * Pack the canonical FP32 parameters into the kernels' layout and precision.
+ * params (device) float [sv_vae_param_count]; packed_out (device)
+ * [sv_vae_packed_bytes], 256-byte aligned.
+ */
+sv_status sv_vae_pack_weights(const sv_vae_desc *desc, const float *params, void *packed_out,
+                              void *stream);
+
+/* Workspace bytes sv_vae_forward / sv_vae_backward need for a batch of B pairs
+ * of full resolution H x W (0 on invalid input). */
+size_t sv_vae_workspace_bytes(const sv_vae_desc *desc, int B, int H, int W);
+
+/* Bytes of the activations a training forward saves for sv_vae_backward. */
+size_t sv_vae_saved_bytes(const sv_vae_desc *desc, int B, int H, int W);
+
+/*
+ * Refine a batch of coarse maps.
+ *
+ * disp_low (device) uint8 [B][h][w], h = ceil(H/f), w = ceil(W/f), coarse
+ *          disparity in reduced-resolution pixels (as from sv_cost_wta)
+ * img_low  (device) uint8 [B][h][w], the reduced left image
+ * eps      (device, nullable) float [B][h3][w3][latent]: NULL = inference,
+ *          z = mu; otherwise training, z = mu + eps * exp(logvar/2)
+ *          (Eq. (8) in the standard form), h3/w3 = the size after three
+ *          stride-2 halvings (ceil each time)
+ * out      (device) float [B][H][W], refined disparity in full-res pixels
+ * mu_logvar(device, nullable) float [B][h3][w3][2*latent]
+ * saved    (device) [sv_vae_saved_bytes]; required when eps != NULL, else ignored
+ * workspace(device) [ws_bytes >= sv_vae_workspace_bytes]
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE, SV_ERR_DTYPE, SV_ERR_WORKSPACE.
+ */
+sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const uint8_t *disp_low,
+                         const uint8_t *img_low, int B, int H, int W, const float *eps, float *out,
+                         float *mu_logvar, void *saved, void *workspace, size_t ws_bytes,
+                         void *stream);
+
+/*
+ * Gradient of  sum(dout * out) + kl_weight * KL  with respect to every
+ * parameter, for the training forward whose activations are in `saved`
+ * (same desc, B, H, W, eps).  KL is the mean over latent elements of
+ * 0.5 * (mu^2 + exp(logvar) - 1 - logvar) (Eq. (11) in the standard form).
+ * The encoder is recomputed from x0 (activation checkpointing).
+ *
+ * dout     (device) float [B][H][W], gradient w.r.t. out (per full-res pixel)
+ * grad_out (device) float [sv_vae_param_count], canonical order, overwritten
+ */
+sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const void *saved,
+                          int B, int H, int W, const float *eps, const float *dout,
+                          float kl_weight, float *grad_out, void *workspace, size_t ws_bytes,
+                          void *stream);
+
+/*
+ * Training loss (a reading of Eqs. (9)-(11)): mean smooth-L1 (beta = 1 px) of
+ * out - gt over n pixels plus kl_weight * mean KL over the n_pix_lat * latent
+ * latent elements of mu_logvar (rows of 2*latent FP32: mu then logvar;
+ * nullable, then KL = 0).
+ * loss_out (device) float[3] = {total, data term, KL}; dout (device, nullable)
+ * float [n] = clamp(out - gt, -1, 1) / n.  Partial sums in FP64 over a fixed
+ * grid and a fixed tree: the result does not depend on scheduling.
+ * workspace (device, 8-byte aligned) >= sv_loss_workspace_bytes().
+ */
+size_t sv_loss_workspace_bytes(void);
+sv_status sv_loss(const float *out, const float *gt, int64_t n, const float *mu_logvar,
+                  int64_t n_pix_lat, int latent, float kl_weight, float *loss_out, float *dout,
+                  void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * One Adam step on FP32 master weights (Sec. IV-A: beta1 = 0.99,
+ * beta2 = 0.999, lr = 5e-4; eps is not given in the paper, 1e-8 is usual):
+ * m = b1 m + (1-b1) g; v = b2 v + (1-b2) g^2;
+ * w -= lr * (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).  step >= 1.
+ */
+sv_status sv_adam_step(float *w, const float *g, float *m, float *v, int64_t n, int step,
+                       float lr, float beta1, float beta2, float eps, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Whole path and batches of uneven pairs                                     */
+/* ------------------------------------------------------------------------ */
+
+/* One stereo pair of a batch; all pointers (device). */
+typedef struct sv_pair {
+    const uint8_t *left;  /* [H][W] */
+    const uint8_t *right; /* [H][W] */
+    float *out;           /* [H][W] refined disparity, full-res pixels */
+    uint8_t *disp_low;    /* nullable: [ceil(H/f)][ceil(W/f)] coarse map written here */
+    int32_t H, W;
+    int32_t D;            /* reduced-resolution disparity range, 1..256 */
+} sv_pair;
+
+typedef struct sv_batch_plan sv_batch_plan;
+
+/*
+ * Create a plan that runs up to max_n pairs of sizes up to max_H x max_W and
+ * ranges up to max_D through the whole path (census, cost + WTA, network)
+ * with one launch per stage over all pairs, captured as one hipGraph and
+ * replayed per call.  The plan owns its device buffers and graph.
+ * win_w, win_h: census window.  Tile shapes come from the autotune cache when
+ * it has an entry for these sizes (see sv_autotune), else from defaults.
+ */
+sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, int max_W,
+                               int max_D, int win_w, int win_h, sv_batch_plan **plan);
+sv_status sv_batch_plan_destroy(sv_batch_plan *plan);
+
+/* Run n pairs (host array) through the plan on `stream`.  Uses the graph
+ * unless the environment sets SV_DISABLE_GRAPH=1 (then: the same launches,
+ * eager).  Results are bitwise identical either way. */
+sv_status sv_stereo_batch(sv_batch_plan *plan, const sv_pair *pairs, int n, const void *packed_w,
+                          void *stream);
+
+/*
+ * Time the candidate tile shapes of every stage for this desc and shape on
+ * the current device and store the fastest in the autotune cache (a JSON
+ * file at $SV_AUTOTUNE_CACHE, default ~/.cache/sv_autotune.json, keyed by
+ * stage, shape, dtype and gfx arch).  A missing or corrupt cache falls back
+ * to defaults.  Allocates and frees its own scratch buffers; synchronises.
+ */
+sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int win_w, int win_h);
+
+/* Tile shape of network layer `layer` (0..8 in the canonical order) for all
+ * later calls: cfg in [0, sv_num_layer_cfgs()), or -1 for the default /
+ * autotuned choice.  Results do not depend on it.  Process-wide. */
+sv_status sv_set_layer_cfg(int layer, int cfg);
+int sv_num_layer_cfgs(void);
+
+/* Tile configuration chosen for a stage (for tests and reports):
+ * stage 0 = census, 1 = cost+WTA, 2..12 = network layers; writes a short text. */
+sv_status sv_tile_config(int stage, char *buf, int buflen);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SV_H_ */

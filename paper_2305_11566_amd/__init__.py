@@ -1,0 +1,17 @@
+"""StereoVAE hot path on MI355X (gfx950): census + Hamming cost + winner-take-all
+at reduced resolution, then the tiny VAE that upsamples and refines the coarse
+map -- hand-written HIP kernels behind the C ABI of include/sv.h (libsv.so).
+
+Python here only marshals arguments; see ``ops`` for the entry points.
+"""
+from ._lib import lib, header_symbols, SvError, SV_F32, SV_BF16, SV_F16, DTYPES  # noqa: F401
+from .ops import (  # noqa: F401
+    sv_census,
+    sv_census_pair,
+    sv_cost_wta,
+    sv_set_cost_wta_split,
+    sv_set_layer_cfg,
+    sv_num_layer_cfgs,
+    Refiner,
+    vae_param_count,
+)

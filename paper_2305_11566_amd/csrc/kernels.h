@@ -1,0 +1,66 @@
+// Internal launcher declarations shared by the host sources of libsv.so.
+#pragma once
+
+#include "common.h"
+
+namespace sv {
+
+// ---- matching ----------------------------------------------------------------
+sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
+                               int pitch, int f, int win_w, int win_h, uint8_t *low0,
+                               uint8_t *low1, uint64_t *cen0, uint64_t *cen1, hipStream_t s);
+sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,
+                          int nbits, uint8_t *disp, int dsplit, hipStream_t s);
+
+// ---- convolution as implicit GEMM ---------------------------------------------
+// A convolution input is the channel concatenation of up to two sources.
+enum SrcKind { SRC_NONE = 0, SRC_TENSOR = 1, SRC_RESIZE = 2, SRC_X0 = 3 };
+
+struct ConvSrc {
+    const void *ptr;     // TENSOR / RESIZE: NHWC base; X0: coarse disparity (uint8 [B][h][w])
+    const uint8_t *img;  // X0: reduced left image (uint8 [B][h][w])
+    int kind;            // SrcKind
+    int C;               // channels this source contributes
+    int pitch;           // TENSOR / RESIZE: elements per pixel in memory
+    int coff;            // TENSOR / RESIZE: first channel within a pixel
+    int hs, ws;          // stored spatial size (RESIZE: the smaller map being resized)
+    float scale0;        // X0: factor / 256 applied to the disparity channel
+    int f32;             // TENSOR / RESIZE: stored as FP32 (else in the compute dtype)
+};
+
+struct ConvParams {
+    ConvSrc src[2];
+    int B;
+    int Hi, Wi;          // input grid (after any resize)
+    int Ho, Wo;          // output grid
+    int Cin, Cout;
+    int cin_pad;         // packed weight row length (Cin rounded up to 8)
+    int n_pad;           // packed weight rows (Cout rounded up to 16)
+    const void *wpk;     // packed weights [taps][n_pad][cin_pad], compute dtype
+    const float *bias;   // [Cout] or NULL
+    void *out;           // NHWC output
+    int out_pitch, out_coff;
+    int act;             // 1: leaky ReLU (slope 0.1)
+    int out_f32;         // 1: store FP32 whatever the compute dtype
+};
+
+// cfg selects the tile shape (see conv.hip); ks = 1 or 3, stride = 1 or 2.
+sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s);
+int conv_num_cfgs();
+const char *conv_cfg_name(int cfg);
+
+// Packs canonical OIHW FP32 weights of one layer into [taps][n_pad][cin_pad].
+// tapmajor_out: for the final layer's per-tap split, out channel t = tap and
+// every source tap is collapsed to a 1x1 (taps = 1, rows = k*k).
+sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad,
+                      int tap_split, void *dst, hipStream_t s);
+
+// ---- network glue ---------------------------------------------------------------
+// out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X))
+sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float scale0,
+                       const float *biasF, int B, int h, int w, int H, int W, float *out,
+                       hipStream_t s);
+sv_status launch_reparam(const float *ml, const float *eps, int npix, int L, void *z, int dtype,
+                         hipStream_t s);
+
+}  // namespace sv

@@ -1,0 +1,147 @@
+// Coarse matching kernels: block-mean reduction + census transform, and
+// Hamming cost + winner-take-all with the disparity sweep held in registers.
+//
+// Census is named but not defined in the paper (Sec. I, Sec. III, variants S1/S2
+// of Sec. IV-C); the definition used is the usual one: a bit per window
+// neighbour, set when the neighbour is strictly darker than the centre.
+// Winner-take-all is Eq. (6) on the raw (unaggregated) Hamming cost.
+#include "common.h"
+#include "kernels.h"
+
+namespace sv {
+
+// ---------------------------------------------------------------------------
+// Reduction + census.  One workgroup = CEN_TW x CEN_TH reduced pixels of one
+// image.  The reduced patch with its clamped halo is built once in LDS (each
+// patch pixel is the block mean of f x f full-resolution bytes read by
+// consecutive threads from consecutive addresses), then every thread packs
+// the census word of its pixel from LDS.
+// ---------------------------------------------------------------------------
+constexpr int CEN_TW = 64, CEN_TH = 4, CEN_MAXR = 8;
+
+__global__ void __launch_bounds__(CEN_TW * CEN_TH)
+k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
+                int W, int pitch, int f, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
+                uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
+                uint64_t *__restrict__ cen1)
+{
+    __shared__ uint8_t patch[CEN_TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
+    const int view = blockIdx.z % 2;
+    const int b = blockIdx.z / 2;
+    const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
+    uint8_t *low = view ? low1 : low0;
+    uint64_t *cen = view ? cen1 : cen0;
+    if (view && !img1) return;
+    const int i0 = blockIdx.y * CEN_TH, j0 = blockIdx.x * CEN_TW;
+    const int PH = CEN_TH + 2 * ry, PW = CEN_TW + 2 * rx;
+    const int tid = threadIdx.x;
+
+    for (int e = tid; e < PH * PW; e += CEN_TW * CEN_TH) {
+        const int py = e / PW, px = e - py * PW;
+        const int i = min(max(i0 + py - ry, 0), h - 1);
+        const int j = min(max(j0 + px - rx, 0), w - 1);
+        const int y1 = min(f * i + f, H), x1 = min(f * j + f, W);
+        uint32_t s = 0;
+        for (int y = f * i; y < y1; ++y) {
+            const uint8_t *row = img + (size_t)y * pitch;
+            for (int x = f * j; x < x1; ++x) s += row[x];
+        }
+        const uint32_t n = (uint32_t)((y1 - f * i) * (x1 - f * j));
+        patch[py][px] = (uint8_t)((s + n / 2) / n);
+    }
+    __syncthreads();
+
+    const int ty = tid / CEN_TW, tx = tid - ty * CEN_TW;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= h || j >= w) return;
+    const uint8_t c = patch[ty + ry][tx + rx];
+    uint64_t code = 0;
+    int k = 0;
+    for (int dy = -ry; dy <= ry; ++dy)
+        for (int dx = -rx; dx <= rx; ++dx) {
+            if (dy == 0 && dx == 0) continue;
+            code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
+            ++k;
+        }
+    const size_t o = ((size_t)b * h + i) * w + j;
+    cen[o] = code;
+    if (low) low[o] = c;
+}
+
+sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
+                               int pitch, int f, int win_w, int win_h, uint8_t *low0,
+                               uint8_t *low1, uint64_t *cen0, uint64_t *cen1, hipStream_t s)
+{
+    const int h = cdiv(H, f), w = cdiv(W, f);
+    dim3 grid(cdiv(w, CEN_TW), cdiv(h, CEN_TH), 2 * B);
+    hipLaunchKernelGGL(k_reduce_census, grid, dim3(CEN_TW * CEN_TH), 0, s, img0, img1, B, H, W,
+                       pitch, f, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0, cen1);
+    SV_LAUNCH_CHECK("k_reduce_census");
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Hamming cost + WTA.  One workgroup = one row segment of CW_TW pixels; each
+// pixel is served by DSPLIT adjacent lanes that sweep d = k, k + DSPLIT, ...
+// in registers, keeping the packed key (cost << 8) | d; an unsigned min over
+// keys picks the least cost and, among equal costs, the lowest d, in any
+// reduction order.  The right census row segment [j0 - D + 1, j0 + CW_TW) is
+// staged once in LDS.  The lanes of one pixel then combine keys by shuffle.
+// ---------------------------------------------------------------------------
+constexpr int CW_THREADS = 256;
+
+template <int DSPLIT>
+__global__ void __launch_bounds__(CW_THREADS)
+k_cost_wta(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int h, int w, int D,
+           int nbits, uint8_t *__restrict__ disp)
+{
+    constexpr int TW = CW_THREADS / DSPLIT;
+    __shared__ uint64_t rseg[TW + 256];
+    const int b = blockIdx.z, i = blockIdx.y, j0 = blockIdx.x * TW;
+    const size_t row = ((size_t)b * h + i) * w;
+    const int base = j0 - (D - 1);  // column of rseg[0]
+    for (int e = threadIdx.x; e < TW + D - 1; e += CW_THREADS) {
+        const int x = base + e;
+        rseg[e] = (x >= 0 && x < w) ? cr[row + x] : 0;
+    }
+    __syncthreads();
+    const int p = threadIdx.x / DSPLIT, k = threadIdx.x % DSPLIT;
+    const int j = j0 + p;
+    const uint64_t lv = (j < w) ? cl[row + j] : 0;
+    uint32_t best = 0xffffffffu;
+    const uint32_t sentinel = (uint32_t)(nbits + 1) << 8;
+    for (int d = k; d < D; d += DSPLIT) {
+        // column j - d of the right view sits at rseg[p + D - 1 - d]
+        const uint32_t c = (j - d >= 0) ? ((uint32_t)__popcll(lv ^ rseg[p + D - 1 - d]) << 8)
+                                        : sentinel;
+        best = min(best, c | (uint32_t)d);
+    }
+#pragma unroll
+    for (int m = 1; m < DSPLIT; m <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, m));
+    if (k == 0 && j < w) disp[row + j] = (uint8_t)(best & 0xffu);
+}
+
+sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,
+                          int nbits, uint8_t *disp, int dsplit, hipStream_t s)
+{
+    switch (dsplit) {
+#define SV_CW_CASE(N)                                                                      \
+    case N: {                                                                              \
+        dim3 grid(cdiv(w, CW_THREADS / N), h, B);                                          \
+        hipLaunchKernelGGL(k_cost_wta<N>, grid, dim3(CW_THREADS), 0, s, cl, cr, h, w, D,   \
+                           nbits, disp);                                                   \
+        break;                                                                             \
+    }
+        SV_CW_CASE(1)
+        SV_CW_CASE(2)
+        SV_CW_CASE(4)
+        SV_CW_CASE(8)
+#undef SV_CW_CASE
+    default:
+        return SV_ERR_RANGE;
+    }
+    SV_LAUNCH_CHECK("k_cost_wta");
+    return SV_OK;
+}
+
+}  // namespace sv

@@ -1,0 +1,60 @@
+// Shape bookkeeping of the refinement network: layer table, level sizes,
+// packed-weight layout and activation layout (host side).
+#pragma once
+
+#include "kernels.h"
+
+namespace sv {
+
+enum Layer { L_E1 = 0, L_E2, L_E3, L_HEAD, L_G3, L_G2, L_G1, L_G0, L_F, NLAYERS };
+
+struct LayerSpec { int cout, cin, k, stride; };
+
+struct NetShape {
+    int c1, c2, c3, L, f, dtype, es;  // es: bytes per stored element of the compute dtype
+    LayerSpec ly[NLAYERS];
+    int n_pad[NLAYERS], cin_pad[NLAYERS];
+    size_t w_off[NLAYERS], b_off[NLAYERS], packed_bytes;
+    int64_t p_off[NLAYERS], nparams;  // canonical vector: weights at p_off, bias after them
+};
+
+// Validates and fills the shape from a descriptor; SV_OK or an error code.
+sv_status net_shape(const sv_vae_desc *d, NetShape &ns);
+
+// Spatial sizes: level 0 is the coarse map (ceil(H/f) x ceil(W/f)); level k+1
+// halves level k (ceil); full resolution is H x W.
+struct Levels {
+    int H, W, h[4], w[4];
+};
+Levels net_levels(const NetShape &ns, int H, int W);
+
+// Device tensors of one forward pass.  "saved" holds what the backward needs
+// beyond the recomputed encoder; at inference it lives inside the workspace.
+struct ActLayout {
+    // workspace
+    size_t E1, E2, E3, T, ws_fwd;
+    // saved (offsets within the saved region)
+    size_t disp, img, ML, Z, G3, G2, G1, G0, saved;
+};
+ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B);
+
+// Extra workspace of the backward pass (after the forward's workspace part).
+size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B);
+
+// Tile configuration per layer (index into the conv kernel's table); the
+// defaults may be replaced by the autotuner.
+int net_default_cfg(const NetShape &ns, int layer, int M);
+void net_set_cfg_override(int layer, int cfg);   // -1 restores the default
+int net_get_cfg_override(int layer);
+
+sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
+                      const uint8_t *img, int B, int H, int W, const float *eps, float *out,
+                      float *ml_user, void *saved, void *ws, hipStream_t st);
+
+sv_status net_backward(const NetShape &ns, const void *packed, const void *saved, int B, int H,
+                       int W, const float *eps, const float *dout, float kl_weight,
+                       float *grad, void *ws, hipStream_t st);
+
+sv_status net_pack(const NetShape &ns, const float *params, void *packed, hipStream_t st);
+
+}  // namespace sv

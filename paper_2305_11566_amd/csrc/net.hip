@@ -1,0 +1,210 @@
+// Host-side runner of the refinement network's forward pass (Table I in the
+// shape described in sv.h): one implicit-GEMM launch per layer, then the
+// final gather kernel.  No host synchronisation, no allocation.
+#include <atomic>
+
+#include "net.h"
+
+namespace sv {
+
+static inline int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+sv_status net_shape(const sv_vae_desc *d, NetShape &ns) {
+    if (!d) return SV_ERR_NULL;
+    const int cs[4] = {d->c1, d->c2, d->c3, d->latent};
+    for (int c : cs)
+        if (c < 8 || c > 256 || c % 8) return SV_ERR_RANGE;
+    if (d->factor < 1 || d->factor > 8) return SV_ERR_RANGE;
+    if (d->dtype != SV_F32 && d->dtype != SV_BF16 && d->dtype != SV_F16) return SV_ERR_DTYPE;
+    ns.c1 = d->c1; ns.c2 = d->c2; ns.c3 = d->c3; ns.L = d->latent; ns.f = d->factor;
+    ns.dtype = d->dtype;
+    ns.es = dtype_bytes(d->dtype);
+    const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
+    const LayerSpec t[NLAYERS] = {
+        {c1, 2, 3, 2},      {c2, c1, 3, 2},      {c3, c2, 3, 2},
+        {2 * L, c3, 1, 1},  {c3, L, 1, 1},       {c2, c3 + c2, 3, 1},
+        {c1, c2 + c1, 3, 1}, {c1, c1 + 2, 3, 1}, {1, c1 + 2, 3, 1},
+    };
+    size_t off = 0;
+    int64_t poff = 0;
+    for (int i = 0; i < NLAYERS; ++i) {
+        ns.ly[i] = t[i];
+        ns.p_off[i] = poff;
+        poff += (int64_t)t[i].cout * t[i].cin * t[i].k * t[i].k + t[i].cout;
+        ns.cin_pad[i] = rup(t[i].cin, 8);
+        // the final layer is packed as a 1x1 layer with one output row per tap
+        ns.n_pad[i] = (i == L_F) ? 16 : rup(t[i].cout, 16);
+        const int taps = (i == L_F) ? 1 : t[i].k * t[i].k;
+        ns.w_off[i] = off;
+        off = align256(off + (size_t)taps * ns.n_pad[i] * ns.cin_pad[i] * ns.es);
+        ns.b_off[i] = off;
+        off = align256(off + (size_t)t[i].cout * sizeof(float));
+    }
+    ns.packed_bytes = off;
+    ns.nparams = poff;
+    return SV_OK;
+}
+
+Levels net_levels(const NetShape &ns, int H, int W) {
+    Levels lv;
+    lv.H = H; lv.W = W;
+    lv.h[0] = cdiv(H, ns.f); lv.w[0] = cdiv(W, ns.f);
+    for (int k = 1; k < 4; ++k) { lv.h[k] = cdiv(lv.h[k - 1], 2); lv.w[k] = cdiv(lv.w[k - 1], 2); }
+    return lv;
+}
+
+ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
+    ActLayout a;
+    auto px = [&](int k) { return (size_t)B * lv.h[k] * lv.w[k]; };
+    size_t o = 0;
+    a.E1 = o; o = align256(o + px(1) * ns.c1 * ns.es);
+    a.E2 = o; o = align256(o + px(2) * ns.c2 * ns.es);
+    a.E3 = o; o = align256(o + px(3) * ns.c3 * ns.es);
+    a.T = o;  o = align256(o + px(0) * 12 * sizeof(float));
+    a.ws_fwd = o;
+    o = 0;
+    a.disp = o; o = align256(o + px(0));
+    a.img = o;  o = align256(o + px(0));
+    a.ML = o;   o = align256(o + px(3) * 2 * ns.L * sizeof(float));
+    a.Z = o;    o = align256(o + px(3) * ns.L * ns.es);
+    a.G3 = o;   o = align256(o + px(3) * ns.c3 * ns.es);
+    a.G2 = o;   o = align256(o + px(2) * ns.c2 * ns.es);
+    a.G1 = o;   o = align256(o + px(1) * ns.c1 * ns.es);
+    a.G0 = o;   o = align256(o + px(0) * ns.c1 * ns.es);
+    a.saved = o;
+    return a;
+}
+
+// ---- tile configuration per layer ----------------------------------------------
+static std::atomic<int> g_cfg_override[NLAYERS] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+
+void net_set_cfg_override(int layer, int cfg) {
+    if (layer >= 0 && layer < NLAYERS) g_cfg_override[layer].store(cfg);
+}
+int net_get_cfg_override(int layer) {
+    return (layer >= 0 && layer < NLAYERS) ? g_cfg_override[layer].load() : -1;
+}
+
+int net_default_cfg(const NetShape &ns, int layer, int M) {
+    const int ov = net_get_cfg_override(layer);
+    if (ov >= 0 && ov < conv_num_cfgs()) return ov;
+    const int cout = layer == L_F ? 16 : ns.ly[layer].cout;
+    (void)M;
+    if (cout <= 16) return 5;   // th4_tn16
+    if (cout <= 32) return 2;   // th4_tn32
+    return 0;                   // th4_tn64
+}
+
+// ---- forward ------------------------------------------------------------------------
+static ConvSrc src_tensor(const void *p, int C, int pitch, int coff, int hs, int ws, int f32) {
+    ConvSrc s{};
+    s.ptr = p; s.kind = SRC_TENSOR; s.C = C; s.pitch = pitch; s.coff = coff; s.hs = hs; s.ws = ws;
+    s.f32 = f32;
+    return s;
+}
+static ConvSrc src_resize(const void *p, int C, int hs, int ws) {
+    ConvSrc s = src_tensor(p, C, C, 0, hs, ws, 0);
+    s.kind = SRC_RESIZE;
+    return s;
+}
+static ConvSrc src_x0(const uint8_t *disp, const uint8_t *img, int hs, int ws, int f) {
+    ConvSrc s{};
+    s.ptr = disp; s.img = img; s.kind = SRC_X0; s.C = 2; s.hs = hs; s.ws = ws;
+    s.scale0 = (float)f / 256.0f;
+    return s;
+}
+
+static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
+                           int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
+                           int out_f32, int act, hipStream_t st) {
+    ConvParams p{};
+    p.src[0] = s0; p.src[1] = s1;
+    p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
+    p.Cin = s0.C + (s1.kind ? s1.C : 0);
+    const bool tsplit = li == L_F;
+    p.Cout = tsplit ? 9 : ns.ly[li].cout;
+    p.cin_pad = ns.cin_pad[li];
+    p.n_pad = ns.n_pad[li];
+    p.wpk = (const char *)packed + ns.w_off[li];
+    p.bias = tsplit ? nullptr : (const float *)((const char *)packed + ns.b_off[li]);
+    p.out = out; p.out_pitch = out_pitch; p.out_coff = 0;
+    p.act = act; p.out_f32 = out_f32;
+    const int ks = tsplit ? 1 : ns.ly[li].k;
+    const int stride = tsplit ? 1 : ns.ly[li].stride;
+    return launch_conv(ns.dtype, ks, stride, net_default_cfg(ns, li, B * Ho * Wo), p, st);
+}
+
+#define SV_TRY(x)                       \
+    do {                                \
+        sv_status r_ = (x);             \
+        if (r_ != SV_OK) return r_;     \
+    } while (0)
+
+sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
+                      const uint8_t *img, int B, int H, int W, const float *eps, float *out,
+                      float *ml_user, void *saved, void *ws, hipStream_t st) {
+    const Levels lv = net_levels(ns, H, W);
+    const ActLayout a = net_act_layout(ns, lv, B);
+    char *w = (char *)ws;
+    char *sv_ = eps ? (char *)saved : w + a.ws_fwd;  // inference keeps "saved" in the workspace
+    void *E1 = w + a.E1, *E2 = w + a.E2, *E3 = w + a.E3;
+    float *T = (float *)(w + a.T);
+    float *ML = ml_user ? ml_user : (float *)(sv_ + a.ML);
+    void *Z = sv_ + a.Z, *G3 = sv_ + a.G3, *G2 = sv_ + a.G2, *G1 = sv_ + a.G1, *G0 = sv_ + a.G0;
+    const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
+    const ConvSrc none{};
+
+    if (eps) {  // keep the coarse inputs for the backward pass
+        const size_t n0 = (size_t)B * lv.h[0] * lv.w[0];
+        SV_HIP(hipMemcpyAsync(sv_ + a.disp, disp, n0, hipMemcpyDeviceToDevice, st));
+        SV_HIP(hipMemcpyAsync(sv_ + a.img, img, n0, hipMemcpyDeviceToDevice, st));
+    }
+    const ConvSrc x0 = src_x0(disp, img, lv.h[0], lv.w[0], ns.f);
+    // encoder
+    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
+                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
+                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, st));
+    // latent head -> [mu | logvar] in FP32
+    SV_TRY(run_layer(ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
+                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, st));
+    ConvSrc zsrc;
+    if (eps) {
+        SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
+        zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
+    } else {
+        zsrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], 1);  // z = mu
+    }
+    // decoder
+    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
+                     src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
+                     lv.w[2], G2, c2, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
+                     src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
+                     lv.w[1], G1, c1, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
+                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, st));
+    // final layer: per-tap 1x1 projection at the coarse level, then the gather
+    SV_TRY(run_layer(ns, packed, L_F, src_tensor(G0, c1, c1, 0, lv.h[0], lv.w[0], 0), x0, B,
+                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, st));
+    const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
+    SV_TRY(launch_final(T, 12, disp, (float)ns.f / 256.0f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
+    return SV_OK;
+}
+
+sv_status net_pack(const NetShape &ns, const float *params, void *packed, hipStream_t st) {
+    for (int i = 0; i < NLAYERS; ++i) {
+        const LayerSpec &l = ns.ly[i];
+        const float *w = params + ns.p_off[i];
+        SV_TRY(launch_pack(ns.dtype, w, l.cout, l.cin, l.k, ns.n_pad[i], ns.cin_pad[i], i == L_F,
+                           (char *)packed + ns.w_off[i], st));
+        const float *b = w + (size_t)l.cout * l.cin * l.k * l.k;
+        SV_HIP(hipMemcpyAsync((char *)packed + ns.b_off[i], b, sizeof(float) * l.cout,
+                              hipMemcpyDeviceToDevice, st));
+    }
+    return SV_OK;
+}
+
+}  // namespace sv

@@ -1,0 +1,176 @@
+"""Python entry points with the C ABI's names, over torch tensors on the GPU.
+
+Each function only allocates outputs (torch), marshals pointers and calls
+libsv.so on the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from ._lib import (SV_F32, check, lib, make_desc, ptr, stream_ptr, VaeDesc, DTYPES)
+
+
+def _cdiv(a, b):
+    return -(-a // b)
+
+
+def _need(t, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+# ---------------------------------------------------------------- matching
+
+def sv_census(img: torch.Tensor, factor: int, win_w: int, win_h: int, want_low: bool = True):
+    """uint8 [B, H, W] -> (census int64-bits [B, h, w], reduced image uint8 [B, h, w] or None)."""
+    _need(img, torch.uint8, "img")
+    if img.dim() == 2:
+        img = img[None]
+    B, H, W = img.shape
+    h, w = _cdiv(H, factor), _cdiv(W, factor)
+    cen = torch.empty((B, h, w), dtype=torch.int64, device=img.device)
+    low = torch.empty((B, h, w), dtype=torch.uint8, device=img.device) if want_low else None
+    check(lib().sv_census(ptr(img), B, H, W, W, factor, win_w, win_h, ptr(low), ptr(cen),
+                          stream_ptr()), "sv_census")
+    return cen, low
+
+
+def sv_census_pair(left: torch.Tensor, right: torch.Tensor, factor: int, win_w: int, win_h: int):
+    """Both views in one launch -> (census L, census R, reduced left image)."""
+    _need(left, torch.uint8, "left")
+    _need(right, torch.uint8, "right")
+    if left.dim() == 2:
+        left, right = left[None], right[None]
+    if left.shape != right.shape:
+        raise ValueError("left and right must have the same shape")
+    B, H, W = left.shape
+    h, w = _cdiv(H, factor), _cdiv(W, factor)
+    cl = torch.empty((B, h, w), dtype=torch.int64, device=left.device)
+    cr = torch.empty_like(cl)
+    low = torch.empty((B, h, w), dtype=torch.uint8, device=left.device)
+    check(lib().sv_census_pair(ptr(left), ptr(right), B, H, W, W, factor, win_w, win_h, ptr(low),
+                               ptr(cl), ptr(cr), stream_ptr()), "sv_census_pair")
+    return cl, cr, low
+
+
+def sv_cost_wta(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int,
+                out: torch.Tensor | None = None):
+    """Census maps (int64 bits) [B, h, w] -> WTA disparity uint8 [B, h, w]."""
+    _need(cen_l, torch.int64, "cen_l")
+    _need(cen_r, torch.int64, "cen_r")
+    if cen_l.shape != cen_r.shape:
+        raise ValueError("census maps differ in shape")
+    B, h, w = cen_l.shape
+    if out is None:
+        out = torch.empty((B, h, w), dtype=torch.uint8, device=cen_l.device)
+    check(lib().sv_cost_wta(ptr(cen_l), ptr(cen_r), B, h, w, D, nbits, ptr(out), stream_ptr()),
+          "sv_cost_wta")
+    return out
+
+
+def sv_set_cost_wta_split(dsplit: int):
+    check(lib().sv_set_cost_wta_split(dsplit), "sv_set_cost_wta_split")
+
+
+def sv_set_layer_cfg(layer: int, cfg: int):
+    check(lib().sv_set_layer_cfg(layer, cfg), "sv_set_layer_cfg")
+
+
+def sv_num_layer_cfgs() -> int:
+    return lib().sv_num_layer_cfgs()
+
+
+# ----------------------------------------------------------------- network
+
+def _aligned_bytes(n: int, device) -> torch.Tensor:
+    """A uint8 buffer of at least n bytes whose start is 256-byte aligned."""
+    buf = torch.empty(max(n, 1) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf[off:off + max(n, 1)]
+
+
+class Refiner:
+    """Holds a network descriptor, packed weights and a workspace sized for
+    the last shape; forwards to sv_vae_forward / sv_vae_backward."""
+
+    def __init__(self, c1, c2, c3, latent, factor, dtype="f32", device="cuda"):
+        self.desc = make_desc(c1, c2, c3, latent, factor, dtype)
+        self.device = torch.device(device)
+        self.nparams = int(lib().sv_vae_param_count(ctypes.byref(self.desc)))
+        check(0 if self.nparams > 0 else self.nparams, "sv_vae_param_count")
+        self.packed = _aligned_bytes(lib().sv_vae_packed_bytes(ctypes.byref(self.desc)), self.device)
+        self._ws = None
+        self._ws_key = None
+
+    @property
+    def dtype_code(self):
+        return self.desc.dtype
+
+    def pack(self, params: torch.Tensor):
+        """params: FP32 canonical vector [nparams] on the device."""
+        _need(params, torch.float32, "params")
+        if params.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {params.numel()}")
+        check(lib().sv_vae_pack_weights(ctypes.byref(self.desc), ptr(params), ptr(self.packed),
+                                        stream_ptr()), "sv_vae_pack_weights")
+
+    def workspace(self, B, H, W):
+        key = (B, H, W)
+        if self._ws_key != key:
+            n = lib().sv_vae_workspace_bytes(ctypes.byref(self.desc), B, H, W)
+            if n == 0:
+                raise ValueError(f"invalid shape {key}")
+            self._ws = _aligned_bytes(n, self.device)
+            self._ws_key = key
+        return self._ws
+
+    def saved_buffer(self, B, H, W):
+        return _aligned_bytes(lib().sv_vae_saved_bytes(ctypes.byref(self.desc), B, H, W), self.device)
+
+    def latent_shape(self, B, H, W):
+        f = self.desc.factor
+        h, w = _cdiv(H, f), _cdiv(W, f)
+        for _ in range(3):
+            h, w = _cdiv(h, 2), _cdiv(w, 2)
+        return (B, h, w, self.desc.latent)
+
+    def forward(self, disp_low, img_low, H, W, eps=None, saved=None, out=None, mu_logvar=None):
+        """-> (out [B, H, W] full-res px, mu_logvar [B, h3, w3, 2L])."""
+        _need(disp_low, torch.uint8, "disp_low")
+        _need(img_low, torch.uint8, "img_low")
+        B = disp_low.shape[0]
+        if out is None:
+            out = torch.empty((B, H, W), dtype=torch.float32, device=self.device)
+        if mu_logvar is None:
+            s = self.latent_shape(B, H, W)
+            mu_logvar = torch.empty(s[:3] + (2 * s[3],), dtype=torch.float32, device=self.device)
+        if eps is not None:
+            _need(eps, torch.float32, "eps")
+            if saved is None:
+                raise ValueError("training forward needs a saved buffer")
+        ws = self.workspace(B, H, W)
+        check(lib().sv_vae_forward(ctypes.byref(self.desc), ptr(self.packed), ptr(disp_low),
+                                   ptr(img_low), B, H, W, ptr(eps), ptr(out), ptr(mu_logvar),
+                                   ptr(saved), ptr(ws), ws.numel(), stream_ptr()), "sv_vae_forward")
+        return out, mu_logvar
+
+    def backward(self, saved, B, H, W, eps, dout, kl_weight, grad=None):
+        _need(dout, torch.float32, "dout")
+        if grad is None:
+            grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        ws = self.workspace(B, H, W)
+        check(lib().sv_vae_backward(ctypes.byref(self.desc), ptr(self.packed), ptr(saved), B, H, W,
+                                    ptr(eps), ptr(dout), ctypes.c_float(kl_weight), ptr(grad),
+                                    ptr(ws), ws.numel(), stream_ptr()), "sv_vae_backward")
+        return grad
+
+
+def vae_param_count(c1, c2, c3, latent, factor=2, dtype="f32") -> int:
+    d = make_desc(c1, c2, c3, latent, factor, dtype)
+    return int(lib().sv_vae_param_count(ctypes.byref(d)))

@@ -17,3 +17,13 @@ def oracle_lib():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU case on the real stderr before it runs, so a run that dies
+    on the device still says which case it was in."""
+    if request.node.get_closest_marker("gpu"):
+        sys.__stderr__.write(f"[gpu-case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield

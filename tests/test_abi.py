@@ -1,0 +1,79 @@
+"""C ABI: the library loads, exports every symbol the header declares, and
+rejects bad arguments before touching the GPU (runs without a GPU)."""
+import ctypes
+
+import pytest
+
+import paper_2305_11566_amd as sv
+from paper_2305_11566_amd._lib import lib, header_symbols, make_desc
+
+
+def test_exports_every_declared_symbol():
+    l = lib()
+    missing = [s for s in header_symbols() if not hasattr(l, s)]
+    assert not missing, missing
+
+
+def test_status_strings():
+    assert lib().sv_status_str(0) == b"SV_OK"
+    assert lib().sv_status_str(-5) == b"SV_ERR_WORKSPACE"
+
+
+def test_param_counts_match_workload_shapes():
+    assert sv.vae_param_count(16, 32, 64, 64) == 73299
+    assert sv.vae_param_count(32, 64, 128, 128) == 290963
+
+
+P = ctypes.c_void_p(0x1000)   # never dereferenced: validation fails first
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 1, 8, 8, 8, 2, 5, 5, None, P, None), -1),
+    ((P, 0, 8, 8, 8, 2, 5, 5, None, P, None), -2),
+    ((P, 1, 8, 8, 4, 2, 5, 5, None, P, None), -2),       # pitch < W
+    ((P, 1, 8, 8, 8, 9, 5, 5, None, P, None), -3),       # factor
+    ((P, 1, 8, 8, 8, 2, 4, 5, None, P, None), -3),       # even window
+    ((P, 1, 8, 8, 8, 2, 9, 9, None, P, None), -3),       # nbits 80 > 64
+    ((P, 1, 8, 8, 8, 2, 19, 3, None, P, None), -3),      # window wider than 17
+])
+def test_census_validation(args, code):
+    assert lib().sv_census(*args) == code
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, P, 1, 4, 4, 8, 24, P, None), -1),
+    ((P, P, 1, 0, 4, 8, 24, P, None), -2),
+    ((P, P, 1, 4, 4, 257, 24, P, None), -3),
+    ((P, P, 1, 4, 4, 0, 24, P, None), -3),
+    ((P, P, 1, 4, 4, 8, 65, P, None), -3),
+])
+def test_cost_wta_validation(args, code):
+    assert lib().sv_cost_wta(*args) == code
+
+
+def test_vae_validation():
+    l = lib()
+    d = make_desc(16, 32, 64, 64, 2, "f32")
+    ws = l.sv_vae_workspace_bytes(ctypes.byref(d), 1, 128, 256)
+    assert ws > 0
+    A = ctypes.c_void_p(0x100000)
+    # workspace too small
+    assert l.sv_vae_forward(ctypes.byref(d), A, P, P, 1, 128, 256, None, P, None, None, A, ws - 1, None) == -5
+    # training without a saved buffer
+    assert l.sv_vae_forward(ctypes.byref(d), A, P, P, 1, 128, 256, P, P, None, None, A, ws, None) == -1
+    # misaligned workspace
+    assert l.sv_vae_forward(ctypes.byref(d), A, P, P, 1, 128, 256, None, P, None, None,
+                            ctypes.c_void_p(0x100010), ws, None) == -3
+    bad = make_desc(12, 32, 64, 64, 2, "f32")      # not a multiple of 8
+    assert l.sv_vae_param_count(ctypes.byref(bad)) == -3
+    bad = make_desc(16, 32, 64, 64, 2, 7)
+    assert l.sv_vae_param_count(ctypes.byref(bad)) == -4
+    assert l.sv_vae_workspace_bytes(ctypes.byref(d), 0, 128, 256) == 0
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    import paper_2305_11566_amd._lib as L
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
+    with pytest.raises(RuntimeError, match="not built"):
+        L.lib()

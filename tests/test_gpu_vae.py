@@ -1,0 +1,121 @@
+"""GPU parity of the refinement network's forward pass against the FP64 oracle.
+
+FP32: normwise max|y - y64| / max|y64| <= 1e-5 on the refined disparity and on
+mu / logvar.  BF16 / FP16: end-point error reported and bounded loosely (the
+bar for reduced precision is an EPE statement, not bitwise parity).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import vae
+from synth import gen_config, gen_pair, gen_eps
+from tests.gpu_util import cuda, flat_params, normwise, vae_params
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+def _inputs(H, W, f, ww, wh, D, seed, B=1):
+    disp, img = [], []
+    for b in range(B):
+        p = gen_pair(H, W, 4, 1.0, max(2.0, f * D * 0.8), seed=seed + b)
+        lo, _, _, d = oracle.match(p.left, p.right, f, ww, wh, D)
+        disp.append(d[0]); img.append(lo[0])
+    return np.stack(disp), np.stack(img)
+
+
+def _gpu_forward(C, L, f, dtype, params, disp, img, H, W, eps=None):
+    import paper_2305_11566_amd as sv
+    ref = sv.Refiner(*C, L, f, dtype)
+    ref.pack(cuda(flat_params(params)))
+    saved = ref.saved_buffer(disp.shape[0], H, W) if eps is not None else None
+    out, ml = ref.forward(cuda(disp), cuda(img), H, W, eps=None if eps is None else cuda(eps),
+                          saved=saved)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ml.cpu().numpy()
+
+
+def _compare(C, L, f, H, W, disp, img, seed=7, eps=None, dtype="f32", tol=TOL_F32):
+    params = vae_params(C, L, seed)
+    t = vae.forward(params, disp, img, f, H, W, eps=None if eps is None else eps.transpose(0, 3, 1, 2))
+    out, ml = _gpu_forward(C, L, f, dtype, params, disp, img, H, W, eps)
+    e_out = normwise(out, t["out"])
+    mu = ml[..., :L].transpose(0, 3, 1, 2)
+    lv = ml[..., L:].transpose(0, 3, 1, 2)
+    e_ml = max(normwise(mu, t["mu"]), normwise(lv, t["logvar"]))
+    assert e_out <= tol, f"out normwise {e_out:.3e}"
+    assert e_ml <= tol, f"mu/logvar normwise {e_ml:.3e}"
+    return e_out, out, t
+
+
+def test_f32_workload1():
+    p = gen_config(1)
+    lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
+    _compare((16, 32, 64), 64, 2, 128, 256, d, lo)
+
+
+def test_f32_workload2_full_size():
+    p = gen_config(2)
+    lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
+    _compare((32, 64, 128), 128, 4, 375, 1242, d, lo)
+
+
+@pytest.mark.parametrize("H,W,f,C,L,B", [
+    (45, 63, 4, (8, 16, 24), 16, 2),     # odd sizes, every level ragged
+    (18, 18, 2, (8, 8, 8), 8, 1),        # coarsest level 2x2 -> 1x1 ... small
+    (8, 8, 8, (16, 16, 16), 8, 3),       # coarse map 1x1: all levels 1x1
+    (100, 140, 2, (24, 40, 56), 32, 2),  # channel counts not multiples of 16
+    (64, 512, 4, (32, 64, 128), 128, 1), # wide
+])
+def test_f32_shapes(H, W, f, C, L, B):
+    rng = np.random.default_rng(H + W)
+    h, w = -(-H // f), -(-W // f)
+    disp = rng.integers(0, 40, (B, h, w)).astype(np.uint8)
+    img = rng.integers(0, 256, (B, h, w)).astype(np.uint8)
+    _compare(C, L, f, H, W, disp, img, seed=H)
+
+
+def test_f32_training_forward_with_eps():
+    p = gen_config(1)
+    lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
+    eps = gen_eps((1, 8, 16, 64), seed=9000)
+    _compare((16, 32, 64), 64, 2, 128, 256, d, lo, eps=eps)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_reduced_precision_epe(dtype):
+    """Mean end-point error against the FP64 oracle, in full-res px; He-init
+    weights make the residual large, so the bound here is loose."""
+    p = gen_config(1)
+    lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
+    params = vae_params((16, 32, 64), 64, 7)
+    t = vae.forward(params, d, lo, 2, 128, 256)
+    out, _ = _gpu_forward((16, 32, 64), 64, 2, dtype, params, d, lo, 128, 256)
+    epe = float(np.mean(np.abs(out - t["out"])))
+    scale = float(np.mean(np.abs(t["out"])))
+    print(f"{dtype}: mean EPE {epe:.4f} px, max {np.max(np.abs(out - t['out'])):.3f} px, mean |out| {scale:.2f}")
+    assert epe <= 0.02 * scale + 0.05
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_tile_configs_bitwise_identical(dtype):
+    import paper_2305_11566_amd as sv
+    rng = np.random.default_rng(5)
+    C, L, f, H, W = (32, 64, 128), 128, 4, 150, 330
+    h, w = -(-H // f), -(-W // f)
+    disp = rng.integers(0, 48, (2, h, w)).astype(np.uint8)
+    img = rng.integers(0, 256, (2, h, w)).astype(np.uint8)
+    params = vae_params(C, L, 11)
+    base, _ = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+    try:
+        for cfg in range(sv.sv_num_layer_cfgs()):
+            for layer in range(9):
+                sv.sv_set_layer_cfg(layer, cfg)
+            out, _ = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+            assert (out == base).all(), f"cfg {cfg}"
+    finally:
+        for layer in range(9):
+            sv.sv_set_layer_cfg(layer, -1)
