@@ -1,0 +1,290 @@
+#!/usr/bin/env python3
+"""Throughput of the StereoVAE hot path on one MI355X.
+
+One step = one pass of the whole inference path over a batch of pairs:
+reduction + census of both views, Hamming cost + WTA, and the refinement
+network's forward pass, on seeded synthetic 1242x375 pairs (9x7 census at
+1/4 resolution = 311x94, D = 48 there = 192 full-res, network widths
+2-32-64-128, latent 128) with inputs resident in HBM.
+
+Timed regions (each: W warm-up steps, then exactly K steps bracketed by
+torch.cuda.synchronize()):
+  * the headline: the step replayed from a hipGraph, FP32 network, batch 1;
+  * a profiled eager pass of the same step: HIP events around every kernel,
+    on the stream it runs on, give each kernel's average duration, from which
+    the dominant kernel's roofline fraction is computed;
+  * variants: BF16 network at batch 1, FP32 / BF16 at batch 64.
+The CPU oracle is timed on a bounded sample of the same workload.
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# workload (one pair): KITTI-sized synthetic scene
+H, W, F, WIN_W, WIN_H, D = 375, 1242, 4, 9, 7, 48
+C1, C2, C3, LAT = 32, 64, 128, 128
+NBITS = WIN_W * WIN_H - 1
+WEIGHT_SEED = 7002
+
+PEAK = {  # MI355X published peaks
+    "hbm_GBs": 8000.0,
+    "mfma_TFLOPs": {"f32": 157.3, "bf16": 2500.0, "f16": 2500.0},
+    "alu_Tops": 256 * 64 * 2.4e9 / 1e12,   # 256 CUs x 64 lanes x 2.4 GHz, one int op per lane-cycle
+}
+
+
+def levels(B):
+    h0, w0 = -(-H // F), -(-W // F)
+    hs, ws = [h0], [w0]
+    for _ in range(3):
+        hs.append(-(-hs[-1] // 2))
+        ws.append(-(-ws[-1] // 2))
+    return hs, ws
+
+
+def stage_work(stage, B, dtype):
+    """Algorithmic work of one launch of `stage` on a batch of B pairs:
+    (bound, amount, unit) with unit GB or TFLOP or Tops."""
+    hs, ws = levels(B)
+    px = [B * hs[k] * ws[k] for k in range(4)]
+    conv = {  # (M, N, K) of the implicit GEMM
+        "E1": (px[1], C1, 2 * 9), "E2": (px[2], C2, C1 * 9), "E3": (px[3], C3, C2 * 9),
+        "HEAD": (px[3], 2 * LAT, C3), "G3": (px[3], C3, LAT),
+        "G2": (px[2], C2, (C3 + C2) * 9), "G1": (px[1], C1, (C2 + C1) * 9),
+        "G0": (px[0], C1, (C1 + 2) * 9), "final_proj": (px[0], 9, C1 + 2),
+    }
+    if stage in conv:
+        M, N, K = conv[stage]
+        return "mfma", 2.0 * M * N * K / 1e12, "TFLOP"
+    if stage == "census":   # read both full-res views, write both census maps + reduced left
+        return "hbm", (2.0 * B * H * W + 2 * 8.0 * px[0] + px[0]) / 1e9, "GB"
+    if stage == "cost_wta":  # 6 integer ops per (pixel, d): 2 xor, 2 popcount, pack, min
+        return "alu", 6.0 * D * px[0] / 1e12, "Tops"
+    if stage == "final_gather":  # write the full-res map, read 9 projections + coarse map
+        return "hbm", (4.0 * B * H * W + 36.0 * px[0] + px[0]) / 1e9, "GB"
+    return None, 0.0, ""
+
+
+def make_inputs(B, device):
+    import torch
+    from synth import gen_config
+    pairs = [gen_config(2, i) for i in range(B)]
+    left = torch.from_numpy(np.stack([p.left for p in pairs])).to(device)
+    right = torch.from_numpy(np.stack([p.right for p in pairs])).to(device)
+    gt = np.stack([p.gt for p in pairs])
+    return left, right, gt
+
+
+def make_params():
+    from synth import he_init_params
+    shapes = [(C1, 2, 3), (C2, C1, 3), (C3, C2, 3), (2 * LAT, C3, 1), (C3, LAT, 1),
+              (C2, C3 + C2, 3), (C1, C2 + C1, 3), (C1, C1 + 2, 3), (1, C1 + 2, 3)]
+    params = he_init_params(shapes, seed=WEIGHT_SEED)
+    flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+    return params, flat
+
+
+class Path:
+    """Preallocated buffers and the step of the whole path for one batch size and dtype."""
+
+    def __init__(self, B, dtype, flat, left, right):
+        import torch
+        import paper_2305_11566_amd as sv
+        self.sv, self.torch = sv, torch
+        self.B, self.dtype = B, dtype
+        self.left, self.right = left, right
+        hs, ws = levels(B)
+        dev = left.device
+        self.cl = torch.empty((B, hs[0], ws[0]), dtype=torch.int64, device=dev)
+        self.cr = torch.empty_like(self.cl)
+        self.low = torch.empty((B, hs[0], ws[0]), dtype=torch.uint8, device=dev)
+        self.disp = torch.empty_like(self.low)
+        self.out = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+        self.ml = torch.empty((B, hs[3], ws[3], 2 * LAT), dtype=torch.float32, device=dev)
+        self.ref = sv.Refiner(C1, C2, C3, LAT, F, dtype)
+        self.ref.pack(torch.from_numpy(flat).to(dev))
+        self.ref.workspace(B, H, W)
+        self.graph = None
+
+    def step(self):
+        sv = self.sv
+        sv.sv_census_pair(self.left, self.right, F, WIN_W, WIN_H, out=(self.cl, self.cr, self.low))
+        sv.sv_cost_wta(self.cl, self.cr, D, NBITS, out=self.disp)
+        self.ref.forward(self.disp, self.low, H, W, out=self.out, mu_logvar=self.ml)
+
+    def capture(self):
+        torch = self.torch
+        self.step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+
+    def timed(self, steps, warmup, graph=True):
+        torch = self.torch
+        run = self.graph.replay if (graph and self.graph is not None) else self.step
+        for _ in range(warmup):
+            run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle, as it stands, on whole config frames until the budget is spent."""
+    import oracle
+    from oracle import vae
+    from synth import gen_config
+    params, _ = make_params()
+    n, t0 = 0, time.perf_counter()
+    while True:
+        p = gen_config(2, n)
+        lo, _, _, d = oracle.match(p.left, p.right, F, WIN_W, WIN_H, D)
+        vae.forward(params, d, lo, F, H, W)
+        n += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or n >= 8:
+            break
+    return {"value": n / el, "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} whole frames (1242x375, census+WTA+FP64 network), single thread, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--big-batch", type=int, default=64)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: --gpus {args.gpus} (WORLD_SIZE {world}) is not "
+              "supported; the path runs on a single MI355X and has no multi-GPU mode.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2305_11566_amd as sv
+    dev = torch.device("cuda:0")
+    K, Wm = args.steps, args.warmup
+    _, flat = make_params()
+    left, right, gt = make_inputs(args.batch, dev)
+
+    # ---- headline: FP32 network, graph replay -------------------------------------
+    p32 = Path(args.batch, "f32", flat, left, right)
+    for _ in range(Wm):
+        p32.step()
+    torch.cuda.synchronize()
+    # profiled eager pass: per-kernel HIP events on the launch stream
+    sv.sv_profile_enable(K)
+    eager_ms = p32.timed(K, 0, graph=False)
+    prof = sv.sv_profile_read()
+    sv.sv_profile_enable(0)
+    p32.capture()
+    ms = p32.timed(K, Wm, graph=True)
+    fps = args.batch * 1e3 / ms
+
+    kernels = {}
+    for stage, (tot, cnt) in prof.items():
+        if cnt == 0:
+            continue
+        avg_ms = tot / cnt
+        bound, amount, unit = stage_work(stage, args.batch, "f32")
+        rec = {"avg_us": round(avg_ms * 1e3, 3), "launches": cnt}
+        if bound:
+            rate = amount / (avg_ms * 1e-3)
+            if bound == "hbm":
+                peak, runit, ach = PEAK["hbm_GBs"], "GB/s", rate
+            elif bound == "mfma":
+                peak, runit, ach = PEAK["mfma_TFLOPs"]["f32"], "TFLOP/s", rate
+            else:
+                peak, runit, ach = PEAK["alu_Tops"], "Tops/s", rate
+            rec.update(bound=bound, achieved=round(ach, 3), unit=runit, frac=round(ach / peak, 5))
+        kernels[stage] = rec
+    dom = max(kernels, key=lambda s: kernels[s]["avg_us"])
+    d = kernels[dom]
+    peak = {"GB/s": PEAK["hbm_GBs"], "TFLOP/s": PEAK["mfma_TFLOPs"]["f32"],
+            "Tops/s": PEAK["alu_Tops"]}.get(d.get("unit"), None)
+    roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"), "peak": peak,
+                "unit": d.get("unit"), "frac": d.get("frac"), "traffic": None,
+                "avg_us": d["avg_us"]}
+
+    # ---- variants and EPE ---------------------------------------------------------------
+    variants = []
+    epe = None
+    if not args.no_variants:
+        pbf = Path(args.batch, "bf16", flat, left, right)
+        pbf.capture()
+        ms_bf = pbf.timed(K, Wm)
+        variants.append({"dtype": "bf16", "batch": args.batch, "ms_per_step": round(ms_bf, 4),
+                         "frames_per_s": round(args.batch * 1e3 / ms_bf, 1)})
+        o32 = p32.out.double().cpu().numpy()
+        obf = pbf.out.double().cpu().numpy()
+        epe = {"bf16_vs_f32_mean_px": float(np.mean(np.abs(obf - o32))),
+               "bf16_vs_f32_max_px": float(np.max(np.abs(obf - o32))),
+               "f32_vs_gt_mean_px": float(np.mean(np.abs(o32 - gt))),
+               "coarse_linear_vs_gt_mean_px": None}
+        del pbf
+        bb = args.big_batch
+        if bb and bb > 1:
+            lb, rb, _ = make_inputs(bb, dev)
+            for dt in ("f32", "bf16"):
+                pb = Path(bb, dt, flat, lb, rb)
+                pb.capture()
+                kb = max(5, min(K, 20))
+                msb = pb.timed(kb, 3)
+                variants.append({"dtype": dt, "batch": bb, "ms_per_step": round(msb, 4),
+                                 "frames_per_s": round(bb * 1e3 / msb, 1)})
+                del pb
+            torch.cuda.synchronize()
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline()
+
+    rec = {
+        "metric": "frames/s at 1242x375 D=192 (census+WTA+VAE), BF16 vs FP32 at EPE; % roofline",
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded planar-cell scenes, KITTI-sized; random He-init weights)",
+        "config": {"workload": "1242x375 pair, batch 1: 9x7 census at 1/4 res (311x94), D=48 "
+                               "(192 full-res), WTA, VAE 2-32-64-128 latent 128 FP32, hipGraph replay",
+                   "batch": args.batch, "H": H, "W": W, "factor": F, "D_low": D},
+        "eager_ms_per_step": round(eager_ms, 5),
+        "roofline": roofline,
+        "kernels": kernels,
+        "variants": variants,
+        "epe": epe,
+        "cpu_baseline": cpu,
+        "context": {"paper_ms_per_frame_jetson_agx": 29.88,
+                    "note": "paper: ZNCC+SGM+StereoVAE on Jetson AGX Xavier (Table II), not this pipeline"},
+    }
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -269,6 +269,20 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
 sv_status sv_set_layer_cfg(int layer, int cfg);
 int sv_num_layer_cfgs(void);
 
+/*
+ * Profiling: after sv_profile_enable(max_calls) (1..4096), each of the first
+ * max_calls launches of every stage records a hipEvent pair around itself on
+ * its stream.  Stages: 0 census, 1 cost + WTA, then the network's launches
+ * 2 E1, 3 E2, 4 E3, 5 HEAD, 6 reparameterisation (training), 7 G3, 8 G2,
+ * 9 G1, 10 G0, 11 final-layer projection, 12 final gather.
+ * sv_profile_read synchronises on the recorded events, writes the summed
+ * milliseconds and launch counts of each stage into ms_sum[13] / counts[13]
+ * and restarts the counts.  sv_profile_enable(0) disables and frees.
+ * Process-wide; the library creates and owns the events.
+ */
+sv_status sv_profile_enable(int max_calls);
+sv_status sv_profile_read(float *ms_sum, int *counts);
+
 /* Tile configuration chosen for a stage (for tests and reports):
  * stage 0 = census, 1 = cost+WTA, 2..12 = network layers; writes a short text. */
 sv_status sv_tile_config(int stage, char *buf, int buflen);

@@ -14,4 +14,7 @@ from .ops import (  # noqa: F401
     sv_num_layer_cfgs,
     Refiner,
     vae_param_count,
+    sv_profile_enable,
+    sv_profile_read,
+    PROFILE_STAGES,
 )

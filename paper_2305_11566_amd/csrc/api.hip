@@ -5,6 +5,7 @@
 #include <string>
 
 #include "net.h"
+#include "prof.h"
 
 namespace sv {
 
@@ -53,8 +54,11 @@ sv_status sv_census(const uint8_t *img, int B, int H, int W, int pitch, int fact
     if (factor < 1 || factor > 8) return SV_ERR_RANGE;
     sv_status r = check_window(win_w, win_h);
     if (r != SV_OK) return r;
-    return launch_reduce_census(img, nullptr, B, H, W, pitch, factor, win_w, win_h, low_out,
-                                nullptr, census_out, nullptr, (hipStream_t)stream);
+    prof_mark(PROF_CENSUS, 0, (hipStream_t)stream);
+    r = launch_reduce_census(img, nullptr, B, H, W, pitch, factor, win_w, win_h, low_out, nullptr,
+                             census_out, nullptr, (hipStream_t)stream);
+    prof_mark(PROF_CENSUS, 1, (hipStream_t)stream);
+    return r;
 }
 
 // Both views in one launch (the left view's reduced image is written when
@@ -67,8 +71,11 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
     if (factor < 1 || factor > 8) return SV_ERR_RANGE;
     sv_status r = check_window(win_w, win_h);
     if (r != SV_OK) return r;
-    return launch_reduce_census(left, right, B, H, W, pitch, factor, win_w, win_h, low_left,
-                                nullptr, cen_left, cen_right, (hipStream_t)stream);
+    prof_mark(PROF_CENSUS, 0, (hipStream_t)stream);
+    r = launch_reduce_census(left, right, B, H, W, pitch, factor, win_w, win_h, low_left, nullptr,
+                             cen_left, cen_right, (hipStream_t)stream);
+    prof_mark(PROF_CENSUS, 1, (hipStream_t)stream);
+    return r;
 }
 
 static int g_dsplit = 4;
@@ -78,7 +85,11 @@ sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h
     if (!cen_l || !cen_r || !disp_out) return SV_ERR_NULL;
     if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > kMaxSide) return SV_ERR_SHAPE;
     if (D < 1 || D > 256 || nbits < 1 || nbits > 64) return SV_ERR_RANGE;
-    return launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, g_dsplit, (hipStream_t)stream);
+    prof_mark(PROF_COST_WTA, 0, (hipStream_t)stream);
+    sv_status r = launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, g_dsplit,
+                                  (hipStream_t)stream);
+    prof_mark(PROF_COST_WTA, 1, (hipStream_t)stream);
+    return r;
 }
 
 // Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8); for tuning and tests.

@@ -41,8 +41,10 @@ def sv_census(img: torch.Tensor, factor: int, win_w: int, win_h: int, want_low: 
     return cen, low
 
 
-def sv_census_pair(left: torch.Tensor, right: torch.Tensor, factor: int, win_w: int, win_h: int):
-    """Both views in one launch -> (census L, census R, reduced left image)."""
+def sv_census_pair(left: torch.Tensor, right: torch.Tensor, factor: int, win_w: int, win_h: int,
+                   out=None):
+    """Both views in one launch -> (census L, census R, reduced left image).
+    out: optional preallocated (census L, census R, reduced left)."""
     _need(left, torch.uint8, "left")
     _need(right, torch.uint8, "right")
     if left.dim() == 2:
@@ -51,9 +53,12 @@ def sv_census_pair(left: torch.Tensor, right: torch.Tensor, factor: int, win_w: 
         raise ValueError("left and right must have the same shape")
     B, H, W = left.shape
     h, w = _cdiv(H, factor), _cdiv(W, factor)
-    cl = torch.empty((B, h, w), dtype=torch.int64, device=left.device)
-    cr = torch.empty_like(cl)
-    low = torch.empty((B, h, w), dtype=torch.uint8, device=left.device)
+    if out is None:
+        cl = torch.empty((B, h, w), dtype=torch.int64, device=left.device)
+        cr = torch.empty_like(cl)
+        low = torch.empty((B, h, w), dtype=torch.uint8, device=left.device)
+    else:
+        cl, cr, low = out
     check(lib().sv_census_pair(ptr(left), ptr(right), B, H, W, W, factor, win_w, win_h, ptr(low),
                                ptr(cl), ptr(cr), stream_ptr()), "sv_census_pair")
     return cl, cr, low
@@ -169,6 +174,23 @@ class Refiner:
                                     ptr(eps), ptr(dout), ctypes.c_float(kl_weight), ptr(grad),
                                     ptr(ws), ws.numel(), stream_ptr()), "sv_vae_backward")
         return grad
+
+
+def sv_profile_enable(max_calls: int):
+    check(lib().sv_profile_enable(max_calls), "sv_profile_enable")
+
+
+PROFILE_STAGES = ("census", "cost_wta", "E1", "E2", "E3", "HEAD", "reparam", "G3", "G2", "G1",
+                  "G0", "final_proj", "final_gather")
+
+
+def sv_profile_read():
+    """-> {stage: (summed ms, launches)}; synchronises on the recorded events."""
+    n = len(PROFILE_STAGES)
+    ms = (ctypes.c_float * n)()
+    cnt = (ctypes.c_int * n)()
+    check(lib().sv_profile_read(ms, cnt), "sv_profile_read")
+    return {PROFILE_STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
 
 
 def vae_param_count(c1, c2, c3, latent, factor=2, dtype="f32") -> int:
