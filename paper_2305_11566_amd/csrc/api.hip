@@ -148,7 +148,7 @@ sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const ui
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
     if (!packed_w || !disp_low || !img_low || !out || !workspace) return SV_ERR_NULL;
-    if (eps && !saved) return SV_ERR_NULL;
+    if (eps && !saved) return SV_ERR_NULL;   // sampling z is only for training
     if (!shape_ok(B, H, W)) return SV_ERR_SHAPE;
     if (ws_bytes < sv_vae_workspace_bytes(desc, B, H, W)) return SV_ERR_WORKSPACE;
     if ((uintptr_t)workspace % 256 || (saved && (uintptr_t)saved % 256) || (uintptr_t)packed_w % 256)

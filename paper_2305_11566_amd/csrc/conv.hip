@@ -170,6 +170,17 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
                         v[i] = (1.f - ly) * top + ly * bot;
                     }
                     out = pack_vec<DT, GS>(v);
+                } else if (s.kind == SRC_ZINS) {
+                    if (((yi | xi) & 1) == 0) {
+                        const size_t off =
+                            (((size_t)b * s.hs + (yi >> 1)) * s.ws + (xi >> 1)) * s.pitch + s.coff + cl;
+                        if (!sf32) {
+                            out = *(const vec *)((const T *)s.ptr + off);
+                        } else {
+                            load_px<DT, GS>(s.ptr, off, true, v);
+                            out = pack_vec<DT, GS>(v);
+                        }
+                    }
                 } else {  // SRC_X0: [f*d/256, I/256]
                     const size_t o = ((size_t)b * s.hs + yi) * s.ws + xi;
 #pragma unroll
@@ -237,6 +248,13 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
                 const int n = nbase + i;
                 float val = acc[mb][nb][i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
                 if (p.act) val = val > 0.f ? val : 0.1f * val;
+                if (n < p.Cout) {
+                    if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
+                    if (p.mask) {
+                        const float mv = Elem<DT>::load((const T *)p.mask + pix * p.mask_pitch + n);
+                        val *= mv > 0.f ? 1.0f : 0.1f;
+                    }
+                }
                 r[i] = val;
             }
             const size_t o = pix * p.out_pitch + p.out_coff + nbase;
@@ -320,9 +338,14 @@ sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &
 }
 
 // ---- weight packing ---------------------------------------------------------------
+// mode 0: forward [tap][n = out][c = in]; mode 1: the final layer, one row
+// per source tap; mode 2: adjoint [tap'][n = in][c = out] with the kernel
+// flipped (tap' = (k-1-u)*k + (k-1-v)), so the input gradient is an ordinary
+// convolution of the output gradient.
 template <int DT>
 __global__ void k_pack(const float *__restrict__ w, int Cout, int Cin, int k, int n_pad, int cin_pad,
-                       int tap_split, typename Mfma<DT>::T *__restrict__ dst) {
+                       int mode, typename Mfma<DT>::T *__restrict__ dst) {
+    const int tap_split = mode == 1;
     const int taps = tap_split ? 1 : k * k;
     const size_t total = (size_t)taps * n_pad * cin_pad;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
@@ -334,6 +357,9 @@ __global__ void k_pack(const float *__restrict__ w, int Cout, int Cin, int k, in
         if (tap_split) {
             // one output row per source tap of the single-output layer
             if (n < k * k && c < Cin) val = w[(size_t)c * k * k + n];
+        } else if (mode == 2) {
+            // n runs over the layer's inputs, c over its outputs
+            if (n < Cin && c < Cout) val = w[((size_t)c * Cin + n) * k * k + (k * k - 1 - tap)];
         } else if (n < Cout && c < Cin) {
             val = w[((size_t)n * Cin + c) * k * k + tap];
         }
@@ -343,7 +369,7 @@ __global__ void k_pack(const float *__restrict__ w, int Cout, int Cin, int k, in
 
 sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad,
                       int tap_split, void *dst, hipStream_t s) {
-    const size_t total = (size_t)(tap_split ? 1 : k * k) * n_pad * cin_pad;
+    const size_t total = (size_t)(tap_split == 1 ? 1 : k * k) * n_pad * cin_pad;
     const int blocks = (int)((total + 255) / 256 < 1024 ? (total + 255) / 256 : 1024);
     switch (dtype) {
     case SV_F32:

@@ -14,7 +14,10 @@ sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, 
 
 // ---- convolution as implicit GEMM ---------------------------------------------
 // A convolution input is the channel concatenation of up to two sources.
-enum SrcKind { SRC_NONE = 0, SRC_TENSOR = 1, SRC_RESIZE = 2, SRC_X0 = 3 };
+// SRC_ZINS: the map seen with zeros inserted between its samples (value at
+// (y, x) = map[y/2][x/2] for even y and x, else 0), which turns the adjoint
+// of a stride-2 convolution into a stride-1 one.
+enum SrcKind { SRC_NONE = 0, SRC_TENSOR = 1, SRC_RESIZE = 2, SRC_X0 = 3, SRC_ZINS = 4 };
 
 struct ConvSrc {
     const void *ptr;     // TENSOR / RESIZE: NHWC base; X0: coarse disparity (uint8 [B][h][w])
@@ -42,6 +45,11 @@ struct ConvParams {
     int out_pitch, out_coff;
     int act;             // 1: leaky ReLU (slope 0.1)
     int out_f32;         // 1: store FP32 whatever the compute dtype
+    // optional epilogue terms of the backward pass, on the output grid:
+    const float *add;    // += add[pix * add_pitch + add_coff + n] (FP32)
+    int add_pitch, add_coff;
+    const void *mask;    // *= (mask[pix * mask_pitch + n] > 0 ? 1 : 0.1), compute dtype
+    int mask_pitch;
 };
 
 // cfg selects the tile shape (see conv.hip); ks = 1 or 3, stride = 1 or 2.
@@ -50,10 +58,11 @@ int conv_num_cfgs();
 const char *conv_cfg_name(int cfg);
 
 // Packs canonical OIHW FP32 weights of one layer into [taps][n_pad][cin_pad].
-// tapmajor_out: for the final layer's per-tap split, out channel t = tap and
-// every source tap is collapsed to a 1x1 (taps = 1, rows = k*k).
+// mode 0: forward rows = output channels; mode 1 (final layer): taps = 1 and
+// row t = source tap t; mode 2: adjoint, rows = input channels, columns =
+// output channels, kernel flipped.
 sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad,
-                      int tap_split, void *dst, hipStream_t s);
+                      int mode, void *dst, hipStream_t s);
 
 // ---- network glue ---------------------------------------------------------------
 // out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X))

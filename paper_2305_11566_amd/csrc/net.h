@@ -15,6 +15,10 @@ struct NetShape {
     LayerSpec ly[NLAYERS];
     int n_pad[NLAYERS], cin_pad[NLAYERS];
     size_t w_off[NLAYERS], b_off[NLAYERS], packed_bytes;
+    // adjoint weights (rows = the layer's inputs, columns = its outputs, kernel
+    // flipped) for the layers whose input gradient is needed
+    int bn_pad[NLAYERS], bcin_pad[NLAYERS];
+    size_t bw_off[NLAYERS];  // 0 when absent (E1, F)
     int64_t p_off[NLAYERS], nparams;  // canonical vector: weights at p_off, bias after them
 };
 

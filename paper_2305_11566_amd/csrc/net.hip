@@ -41,6 +41,15 @@ sv_status net_shape(const sv_vae_desc *d, NetShape &ns) {
         ns.b_off[i] = off;
         off = align256(off + (size_t)t[i].cout * sizeof(float));
     }
+    for (int i = 0; i < NLAYERS; ++i) {
+        ns.bw_off[i] = 0;
+        ns.bn_pad[i] = ns.bcin_pad[i] = 0;
+        if (i == L_E1 || i == L_F) continue;
+        ns.bn_pad[i] = rup(t[i].cin, 16);
+        ns.bcin_pad[i] = rup(t[i].cout, 8);
+        ns.bw_off[i] = off;
+        off = align256(off + (size_t)t[i].k * t[i].k * ns.bn_pad[i] * ns.bcin_pad[i] * ns.es);
+    }
     ns.packed_bytes = off;
     ns.nparams = poff;
     return SV_OK;
@@ -150,15 +159,16 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     const Levels lv = net_levels(ns, H, W);
     const ActLayout a = net_act_layout(ns, lv, B);
     char *w = (char *)ws;
-    char *sv_ = eps ? (char *)saved : w + a.ws_fwd;  // inference keeps "saved" in the workspace
+    const bool train = saved != nullptr;                   // keep what the backward needs
+    char *sv_ = train ? (char *)saved : w + a.ws_fwd;      // else it lives in the workspace
     void *E1 = w + a.E1, *E2 = w + a.E2, *E3 = w + a.E3;
     float *T = (float *)(w + a.T);
-    float *ML = ml_user ? ml_user : (float *)(sv_ + a.ML);
+    float *ML = (!train && ml_user) ? ml_user : (float *)(sv_ + a.ML);
     void *Z = sv_ + a.Z, *G3 = sv_ + a.G3, *G2 = sv_ + a.G2, *G1 = sv_ + a.G1, *G0 = sv_ + a.G0;
     const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
     const ConvSrc none{};
 
-    if (eps) {  // keep the coarse inputs for the backward pass
+    if (train) {  // keep the coarse inputs for the backward pass
         const size_t n0 = (size_t)B * lv.h[0] * lv.w[0];
         SV_HIP(hipMemcpyAsync(sv_ + a.disp, disp, n0, hipMemcpyDeviceToDevice, st));
         SV_HIP(hipMemcpyAsync(sv_ + a.img, img, n0, hipMemcpyDeviceToDevice, st));
@@ -217,6 +227,9 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     ev_rec(10, 0, st);
     SV_TRY(launch_final(T, 12, disp, (float)ns.f / 256.0f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
     ev_rec(10, 1, st);
+    if (train && ml_user)
+        SV_HIP(hipMemcpyAsync(ml_user, ML, (size_t)B * lv.h[3] * lv.w[3] * 2 * L * sizeof(float),
+                              hipMemcpyDeviceToDevice, st));
     return SV_OK;
 }
 
@@ -224,8 +237,11 @@ sv_status net_pack(const NetShape &ns, const float *params, void *packed, hipStr
     for (int i = 0; i < NLAYERS; ++i) {
         const LayerSpec &l = ns.ly[i];
         const float *w = params + ns.p_off[i];
-        SV_TRY(launch_pack(ns.dtype, w, l.cout, l.cin, l.k, ns.n_pad[i], ns.cin_pad[i], i == L_F,
-                           (char *)packed + ns.w_off[i], st));
+        SV_TRY(launch_pack(ns.dtype, w, l.cout, l.cin, l.k, ns.n_pad[i], ns.cin_pad[i],
+                           i == L_F ? 1 : 0, (char *)packed + ns.w_off[i], st));
+        if (ns.bw_off[i])
+            SV_TRY(launch_pack(ns.dtype, w, l.cout, l.cin, l.k, ns.bn_pad[i], ns.bcin_pad[i], 2,
+                               (char *)packed + ns.bw_off[i], st));
         const float *b = w + (size_t)l.cout * l.cin * l.k * l.k;
         SV_HIP(hipMemcpyAsync((char *)packed + ns.b_off[i], b, sizeof(float) * l.cout,
                               hipMemcpyDeviceToDevice, st));

@@ -1,0 +1,156 @@
+"""GPU parity of the training path: backward (hand-written adjoint kernels)
+against the oracle's FP64 gradient (itself pinned by finite differences and
+torch float64 autograd), the loss, and Adam."""
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import vae
+from synth import gen_pair, gen_eps
+from tests.gpu_util import cuda, flat_params, normwise, vae_params
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(H, W, f, C, L, B, seed, D=8):
+    disp, img, gt = [], [], []
+    for b in range(B):
+        p = gen_pair(H, W, 3, 1.0, max(2.0, 0.8 * f * D), seed=seed + b)
+        lo, _, _, d = oracle.match(p.left, p.right, f, 5, 5, D)
+        disp.append(d[0]); img.append(lo[0]); gt.append(p.gt)
+    return np.stack(disp), np.stack(img), np.stack(gt).astype(np.float64)
+
+
+def _gpu_grad(C, L, f, dtype, params, disp, img, H, W, eps, dout, klw):
+    import paper_2305_11566_amd as sv
+    ref = sv.Refiner(*C, L, f, dtype)
+    ref.pack(cuda(flat_params(params)))
+    B = disp.shape[0]
+    saved = ref.saved_buffer(B, H, W)
+    e = None if eps is None else cuda(eps)
+    out, ml = ref.forward(cuda(disp), cuda(img), H, W, eps=e, saved=saved)
+    g = ref.backward(saved, B, H, W, e, cuda(dout.astype(np.float32)), klw)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().astype(np.float64), out.cpu().numpy()
+
+
+def _oracle_grad(params, disp, img, f, H, W, eps, gt, klw):
+    t = vae.forward(params, disp, img, f, H, W, eps=None if eps is None else eps.transpose(0, 3, 1, 2))
+    total, data, kl, dout = vae.loss(t, gt, klw)
+    g = vae.backward(params, t, dout, klw)
+    return vae.flatten(g), dout, t
+
+
+def _layer_slices(C, L):
+    out, o = [], 0
+    for (co, ci, k, s) in vae.layer_shapes(*C, L):
+        n = co * ci * k * k + co
+        out.append(slice(o, o + n))
+        o += n
+    return out
+
+
+CASES = [
+    # H, W, f, C, L, B
+    (32, 16, 2, (8, 8, 8), 8, 2),
+    (64, 48, 2, (8, 16, 24), 16, 2),
+    (45, 63, 4, (8, 16, 24), 16, 2),         # odd sizes, factor 4
+    (128, 256, 2, (16, 32, 64), 64, 1),      # the 256x128 workload's network
+]
+
+
+@pytest.mark.parametrize("H,W,f,C,L,B", CASES)
+@pytest.mark.parametrize("with_eps", [True, False])
+def test_backward_f32_matches_oracle(H, W, f, C, L, B, with_eps):
+    disp, img, gt = _problem(H, W, f, C, L, B, seed=40 + H)
+    params = vae_params(C, L, seed=H + W)
+    h3 = -(-(-(-(-(-H // f) // 2)) // 2) // 2)
+    w3 = -(-(-(-(-(-W // f) // 2)) // 2) // 2)
+    eps = gen_eps((B, h3, w3, L), seed=9000 + H) if with_eps else None
+    klw = 0.25
+    g_or, dout, _ = _oracle_grad(params, disp, img, f, H, W, eps, gt, klw)
+    g_gpu, _ = _gpu_grad(C, L, f, "f32", params, disp, img, H, W, eps, dout, klw)
+    names = vae.LAYERS
+    for name, sl in zip(names, _layer_slices(C, L)):
+        e = normwise(g_gpu[sl], g_or[sl])
+        assert e <= 1e-4, f"{name}: normwise {e:.2e}"
+    assert normwise(g_gpu, g_or) <= 1e-5 * 10
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_backward_reduced_precision_cosine(dtype):
+    H, W, f, C, L, B = 128, 256, 2, (16, 32, 64), 64, 2
+    disp, img, gt = _problem(H, W, f, C, L, B, seed=77)
+    params = vae_params(C, L, seed=5)
+    eps = gen_eps((B, 8, 16, L), seed=9100)
+    g_or, dout, _ = _oracle_grad(params, disp, img, f, H, W, eps, gt, 1e-3)
+    g_gpu, _ = _gpu_grad(C, L, f, dtype, params, disp, img, H, W, eps, dout, 1e-3)
+    cos = float(np.dot(g_gpu, g_or) / (np.linalg.norm(g_gpu) * np.linalg.norm(g_or)))
+    per = []
+    for name, sl in zip(vae.LAYERS, _layer_slices(C, L)):
+        a, b = g_gpu[sl], g_or[sl]
+        per.append((name, float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b) + 1e-30))))
+    print(dtype, "cosine", cos, per)
+    assert cos >= 0.999
+    assert min(c for _, c in per) >= 0.99
+
+
+def test_backward_deterministic():
+    H, W, f, C, L, B = 64, 128, 2, (16, 32, 64), 64, 2
+    disp, img, gt = _problem(H, W, f, C, L, B, seed=91)
+    params = vae_params(C, L, seed=3)
+    eps = gen_eps((B, 4, 8, L), seed=9200)
+    _, dout, _ = _oracle_grad(params, disp, img, f, H, W, eps, gt, 1e-3)
+    a, _ = _gpu_grad(C, L, f, "bf16", params, disp, img, H, W, eps, dout, 1e-3)
+    b, _ = _gpu_grad(C, L, f, "bf16", params, disp, img, H, W, eps, dout, 1e-3)
+    assert (a == b).all()
+
+
+def test_loss_matches_oracle():
+    from paper_2305_11566_amd._lib import lib, ptr, stream_ptr, check
+    rng = np.random.default_rng(3)
+    out = rng.normal(10, 3, (2, 40, 60))
+    gt = out + rng.normal(0, 1.5, out.shape)
+    ml = rng.normal(0, 0.7, (2, 3, 4, 16))
+    klw = 1e-3
+    mu, lv = ml[..., :8].transpose(0, 3, 1, 2), ml[..., 8:].transpose(0, 3, 1, 2)
+    data, dref = vae.smooth_l1(out, gt)
+    kl = vae.kl_divergence(mu, lv)
+    o_t, g_t, ml_t = cuda(out.astype(np.float32)), cuda(gt.astype(np.float32)), cuda(ml.astype(np.float32))
+    # the oracle's reference uses the FP32-rounded inputs the GPU sees
+    data, dref = vae.smooth_l1(out.astype(np.float32), gt.astype(np.float32))
+    ml32 = ml.astype(np.float32).astype(np.float64)
+    kl = vae.kl_divergence(ml32[..., :8].transpose(0, 3, 1, 2), ml32[..., 8:].transpose(0, 3, 1, 2))
+    loss = torch.empty(3, dtype=torch.float32, device="cuda")
+    dout = torch.empty_like(o_t)
+    ws = torch.empty(lib().sv_loss_workspace_bytes(), dtype=torch.uint8, device="cuda")
+    check(lib().sv_loss(ptr(o_t), ptr(g_t), out.size, ptr(ml_t), 2 * 3 * 4, 8, ctypes.c_float(klw),
+                        ptr(loss), ptr(dout), ptr(ws), ws.numel(), stream_ptr()), "sv_loss")
+    torch.cuda.synchronize()
+    l = loss.cpu().numpy()
+    assert abs(l[1] - data) <= 1e-6 * abs(data)
+    assert abs(l[2] - kl) <= 1e-6 * abs(kl)
+    assert abs(l[0] - (data + klw * kl)) <= 1e-6 * abs(data)
+    np.testing.assert_allclose(dout.cpu().numpy(), dref, rtol=1e-6, atol=1e-12)
+
+
+def test_adam_matches_oracle():
+    from paper_2305_11566_amd._lib import lib, ptr, stream_ptr, check
+    rng = np.random.default_rng(4)
+    n = 10007
+    w = rng.standard_normal(n).astype(np.float32)
+    m = np.zeros(n, np.float32); v = np.zeros(n, np.float32)
+    wt, mt, vt = cuda(w), cuda(m), cuda(v)
+    wr, mr, vr = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for step in range(1, 6):
+        g = rng.standard_normal(n).astype(np.float32)
+        check(lib().sv_adam_step(ptr(wt), ptr(cuda(g)), ptr(mt), ptr(vt), n, step,
+                                 ctypes.c_float(5e-4), ctypes.c_float(0.99), ctypes.c_float(0.999),
+                                 ctypes.c_float(1e-8), stream_ptr()), "sv_adam_step")
+        wr, mr, vr = vae.adam_step(wr, g.astype(np.float64), mr, vr, step)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(wt.cpu().numpy(), wr, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(mt.cpu().numpy(), mr, rtol=1e-5, atol=1e-7)
