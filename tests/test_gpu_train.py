@@ -67,8 +67,9 @@ CASES = [
 def test_backward_f32_matches_oracle(H, W, f, C, L, B, with_eps):
     disp, img, gt = _problem(H, W, f, C, L, B, seed=40 + H)
     params = vae_params(C, L, seed=H + W)
-    h3 = -(-(-(-(-(-H // f) // 2)) // 2) // 2)
-    w3 = -(-(-(-(-(-W // f) // 2)) // 2) // 2)
+    cd = lambda a, b: -(-a // b)
+    h3 = cd(cd(cd(cd(H, f), 2), 2), 2)
+    w3 = cd(cd(cd(cd(W, f), 2), 2), 2)
     eps = gen_eps((B, h3, w3, L), seed=9000 + H) if with_eps else None
     klw = 0.25
     g_or, dout, _ = _oracle_grad(params, disp, img, f, H, W, eps, gt, klw)
