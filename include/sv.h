@@ -189,12 +189,14 @@ sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const ui
  * The encoder is recomputed from x0 (activation checkpointing).
  *
  * dout     (device) float [B][H][W], gradient w.r.t. out (per full-res pixel)
+ * dmu_logvar (device, nullable) float [B][h3][w3][2*latent]: an extra
+ *          gradient w.r.t. [mu | logvar], added to the KL term's
  * grad_out (device) float [sv_vae_param_count], canonical order, overwritten
  */
 sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const void *saved,
                           int B, int H, int W, const float *eps, const float *dout,
-                          float kl_weight, float *grad_out, void *workspace, size_t ws_bytes,
-                          void *stream);
+                          const float *dmu_logvar, float kl_weight, float *grad_out,
+                          void *workspace, size_t ws_bytes, void *stream);
 
 /*
  * Training loss (a reading of Eqs. (9)-(11)): mean smooth-L1 (beta = 1 px) of

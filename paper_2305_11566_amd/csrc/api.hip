@@ -160,8 +160,8 @@ sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const ui
 
 sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const void *saved,
                           int B, int H, int W, const float *eps, const float *dout,
-                          float kl_weight, float *grad_out, void *workspace, size_t ws_bytes,
-                          void *stream) {
+                          const float *dmu_logvar, float kl_weight, float *grad_out,
+                          void *workspace, size_t ws_bytes, void *stream) {
     NetShape ns;
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
@@ -170,8 +170,8 @@ sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const v
     if (ws_bytes < sv_vae_workspace_bytes(desc, B, H, W)) return SV_ERR_WORKSPACE;
     if ((uintptr_t)workspace % 256 || (uintptr_t)saved % 256 || (uintptr_t)packed_w % 256)
         return SV_ERR_RANGE;
-    return net_backward(ns, packed_w, saved, B, H, W, eps, dout, kl_weight, grad_out, workspace,
-                        (hipStream_t)stream);
+    return net_backward(ns, packed_w, saved, B, H, W, eps, dout, dmu_logvar, kl_weight, grad_out,
+                        workspace, (hipStream_t)stream);
 }
 
 // Selects the tile configuration of one network layer (0..8; -1 = default).

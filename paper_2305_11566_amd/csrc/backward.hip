@@ -447,8 +447,8 @@ __global__ void k_final_bwd(const float *__restrict__ dout, int H, int W, int h,
 
 // Reparameterisation and KL adjoint: from dz to d[mu | logvar].
 __global__ void k_latent_bwd(const float *__restrict__ dz, const float *__restrict__ ml,
-                             const float *__restrict__ eps, int npix, int L, float klw,
-                             float *__restrict__ dml)
+                             const float *__restrict__ eps, const float *__restrict__ extra,
+                             int npix, int L, float klw, float *__restrict__ dml)
 {
     const size_t n = (size_t)npix * L;
     const float inv = 1.0f / (float)n;
@@ -460,7 +460,12 @@ __global__ void k_latent_bwd(const float *__restrict__ dz, const float *__restri
         const float g = dz[e];
         float dlv = klw * 0.5f * (expf(lv) - 1.0f) * inv;
         if (eps) dlv += g * eps[e] * 0.5f * expf(0.5f * lv);
-        dml[p * 2 * L + c] = g + klw * mu * inv;
+        float dmu = g + klw * mu * inv;
+        if (extra) {
+            dmu += extra[p * 2 * L + c];
+            dlv += extra[p * 2 * L + L + c];
+        }
+        dml[p * 2 * L + c] = dmu;
         dml[p * 2 * L + L + c] = dlv;
     }
 }
@@ -579,8 +584,8 @@ static sv_status dgrad(const NetShape &ns, const void *packed, int li, ConvSrc d
 }
 
 sv_status net_backward(const NetShape &ns, const void *packed, const void *saved, int B, int H,
-                       int W, const float *eps, const float *dout, float klw, float *grad, void *ws,
-                       hipStream_t st) {
+                       int W, const float *eps, const float *dout, const float *dml_extra,
+                       float klw, float *grad, void *ws, hipStream_t st) {
     const Levels lv = net_levels(ns, H, W);
     const ActLayout a = net_act_layout(ns, lv, B);
     const BwdLayout bl = bwd_layout(ns, lv, B);
@@ -684,8 +689,8 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
         const int npix = B * h[3] * wd[3];
         const size_t n = (size_t)npix * L;
         const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
-        hipLaunchKernelGGL(k_latent_bwd, dim3(blocks), dim3(256), 0, st, F(bl.dz), ML, eps, npix, L,
-                           klw, F(bl.dML));
+        hipLaunchKernelGGL(k_latent_bwd, dim3(blocks), dim3(256), 0, st, F(bl.dz), ML, eps,
+                           dml_extra, npix, L, klw, F(bl.dML));
         SV_LAUNCH_CHECK("k_latent_bwd");
     }
     // ---- HEAD: [mu | logvar] = conv1x1(E3) -------------------------------------------

@@ -56,8 +56,8 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                       float *ml_user, void *saved, void *ws, hipStream_t st);
 
 sv_status net_backward(const NetShape &ns, const void *packed, const void *saved, int B, int H,
-                       int W, const float *eps, const float *dout, float kl_weight,
-                       float *grad, void *ws, hipStream_t st);
+                       int W, const float *eps, const float *dout, const float *dml_extra,
+                       float kl_weight, float *grad, void *ws, hipStream_t st);
 
 sv_status net_pack(const NetShape &ns, const float *params, void *packed, hipStream_t st);
 

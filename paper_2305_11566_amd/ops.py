@@ -165,14 +165,17 @@ class Refiner:
                                    ptr(saved), ptr(ws), ws.numel(), stream_ptr()), "sv_vae_forward")
         return out, mu_logvar
 
-    def backward(self, saved, B, H, W, eps, dout, kl_weight, grad=None):
+    def backward(self, saved, B, H, W, eps, dout, kl_weight, grad=None, dmu_logvar=None):
+        """Gradient of sum(dout * out) + kl_weight * KL (+ sum(dmu_logvar * mu_logvar))."""
         _need(dout, torch.float32, "dout")
+        if dmu_logvar is not None:
+            _need(dmu_logvar, torch.float32, "dmu_logvar")
         if grad is None:
             grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
         ws = self.workspace(B, H, W)
         check(lib().sv_vae_backward(ctypes.byref(self.desc), ptr(self.packed), ptr(saved), B, H, W,
-                                    ptr(eps), ptr(dout), ctypes.c_float(kl_weight), ptr(grad),
-                                    ptr(ws), ws.numel(), stream_ptr()), "sv_vae_backward")
+                                    ptr(eps), ptr(dout), ptr(dmu_logvar), ctypes.c_float(kl_weight),
+                                    ptr(grad), ptr(ws), ws.numel(), stream_ptr()), "sv_vae_backward")
         return grad
 
 
@@ -196,3 +199,31 @@ def sv_profile_read():
 def vae_param_count(c1, c2, c3, latent, factor=2, dtype="f32") -> int:
     d = make_desc(c1, c2, c3, latent, factor, dtype)
     return int(lib().sv_vae_param_count(ctypes.byref(d)))
+
+
+# ----------------------------------------------------------------- training
+
+def sv_loss(out, gt, mu_logvar, latent, kl_weight, loss_out=None, dout=None, workspace=None):
+    """-> (loss[3] = {total, data, KL} on the device, dout).  mu_logvar may be None."""
+    _need(out, torch.float32, "out")
+    _need(gt, torch.float32, "gt")
+    dev = out.device
+    if loss_out is None:
+        loss_out = torch.empty(3, dtype=torch.float32, device=dev)
+    if dout is None:
+        dout = torch.empty_like(out)
+    if workspace is None:
+        workspace = torch.empty(lib().sv_loss_workspace_bytes(), dtype=torch.uint8, device=dev)
+    n_lat = 0 if mu_logvar is None else mu_logvar.numel() // (2 * latent)
+    check(lib().sv_loss(ptr(out), ptr(gt), out.numel(), ptr(mu_logvar), n_lat, latent,
+                        ctypes.c_float(kl_weight), ptr(loss_out), ptr(dout), ptr(workspace),
+                        workspace.numel(), stream_ptr()), "sv_loss")
+    return loss_out, dout
+
+
+def sv_adam_step(w, g, m, v, step, lr=5e-4, beta1=0.99, beta2=0.999, eps=1e-8):
+    for t, n in ((w, "w"), (g, "g"), (m, "m"), (v, "v")):
+        _need(t, torch.float32, n)
+    check(lib().sv_adam_step(ptr(w), ptr(g), ptr(m), ptr(v), w.numel(), step, ctypes.c_float(lr),
+                             ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps),
+                             stream_ptr()), "sv_adam_step")
