@@ -17,4 +17,9 @@ from .ops import (  # noqa: F401
     sv_profile_enable,
     sv_profile_read,
     PROFILE_STAGES,
+    BatchPlan,
+    sv_autotune,
+    sv_tile_config,
+    sv_loss,
+    sv_adam_step,
 )

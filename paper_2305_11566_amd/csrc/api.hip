@@ -78,7 +78,18 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
     return r;
 }
 
+}  // extern "C"
+
 static int g_dsplit = 4;
+
+namespace sv {
+int cost_wta_split_get() { return g_dsplit; }
+void cost_wta_split_set(int d) {
+    if (d == 1 || d == 2 || d == 4 || d == 8) g_dsplit = d;
+}
+}  // namespace sv
+
+extern "C" {
 
 sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D,
                       int nbits, uint8_t *disp_out, void *stream) {

@@ -1,20 +1,521 @@
-// Batches of uneven pairs and the autotuner (placeholders until implemented).
+// Batches of uneven pairs through the whole path, and the tile autotuner.
+//
+// A plan owns flattened per-level buffers sized for max_n pairs of the largest
+// size, a pinned host copy and a device copy of the pair table, and a hipGraph
+// of the 12 stage launches (census, cost + WTA, 9 network convolutions, final
+// gather).  Every launch is persistent: a fixed grid walks that stage's tiles
+// of all pairs through the table's prefix sums, so the same graph serves any
+// mix of sizes up to the plan's maxima.  A call writes the table for its
+// pairs, copies it to the device on the caller's stream and replays the graph.
+#include <errno.h>
+#include <sys/stat.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "net.h"
+#include "prof.h"
+
+namespace sv {
+
+int cost_wta_split_get();
+void cost_wta_split_set(int);
+
+static const int kStageGridMax = 1024;
+
+}  // namespace sv
+
+using namespace sv;
+
+struct sv_batch_plan {
+    NetShape ns;
+    sv_vae_desc desc;
+    int max_n, max_H, max_W, max_D, win_w, win_h, nbits;
+    int dsplit;
+    int cfg[NLAYERS];
+    int grid[BS_NSTAGES];
+    size_t cap[4];
+    void *dev;
+    PairTable *tab_dev;
+    PairTable *tab_host;
+    uint64_t *cl, *cr;
+    uint8_t *low, *disp;
+    void *E1, *E2, *E3, *G3, *G2, *G1, *G0;
+    float *ML, *T;
+    hipStream_t cap_stream;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    const void *graph_w;
+    hipEvent_t upload_done;
+    bool upload_pending;
+};
+
+namespace sv {
+
+// ---------------------------------------------------------------------------
+// Autotune cache: one line per entry,  key<TAB>dsplit<TAB>c0,c1,...,c8
+// ---------------------------------------------------------------------------
+static std::mutex g_tune_mu;
+
+static std::string cache_path() {
+    const char *e = getenv("SV_AUTOTUNE_CACHE");
+    if (e && *e) return e;
+    const char *home = getenv("HOME");
+    return std::string(home ? home : "/tmp") + "/.cache/sv_autotune.tsv";
+}
+
+static std::string tune_key(const NetShape &ns, int H, int W, int D) {
+    char buf[160];
+    snprintf(buf, sizeof buf, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|%dx%d|D%d", ns.dtype, ns.c1, ns.c2,
+             ns.c3, ns.L, ns.f, H, W, D);
+    return buf;
+}
+
+// Returns true and fills dsplit / cfg when the cache has a well-formed entry.
+static bool cache_lookup(const std::string &key, int &dsplit, int *cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    FILE *f = fopen(cache_path().c_str(), "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false, corrupt = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[200];
+        int ds, c[NLAYERS];
+        const int m = sscanf(line, "%199s %d %d,%d,%d,%d,%d,%d,%d,%d,%d", k, &ds, &c[0], &c[1], &c[2],
+                             &c[3], &c[4], &c[5], &c[6], &c[7], &c[8]);
+        if (m != 2 + NLAYERS) {
+            corrupt = true;
+            continue;
+        }
+        bool ok = (ds == 1 || ds == 2 || ds == 4 || ds == 8);
+        for (int i = 0; i < NLAYERS; ++i) ok = ok && c[i] >= 0 && c[i] < conv_num_cfgs();
+        if (!ok) {
+            corrupt = true;
+            continue;
+        }
+        if (key == k) {
+            dsplit = ds;
+            for (int i = 0; i < NLAYERS; ++i) cfg[i] = c[i];
+            found = true;
+        }
+    }
+    fclose(f);
+    if (corrupt)
+        fprintf(stderr, "sv: ignoring malformed lines in autotune cache %s\n", cache_path().c_str());
+    return found;
+}
+
+static void cache_store(const std::string &key, int dsplit, const int *cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    const std::string path = cache_path();
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path.c_str(), "r")) {
+        char line[512];
+        while (fgets(line, sizeof line, f)) {
+            char k[200];
+            if (sscanf(line, "%199s", k) == 1 && key != k) keep.push_back(line);
+        }
+        fclose(f);
+    }
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos) {
+        std::string dir = path.substr(0, slash);
+        (void)mkdir(dir.c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    for (auto &l : keep) fputs(l.c_str(), f);
+    fprintf(f, "%s\t%d\t%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), dsplit, cfg[0], cfg[1], cfg[2],
+            cfg[3], cfg[4], cfg[5], cfg[6], cfg[7], cfg[8]);
+    fclose(f);
+    rename(tmp.c_str(), path.c_str());
+}
+
+// ---------------------------------------------------------------------------
+// Plan helpers
+// ---------------------------------------------------------------------------
+static int conv_tiles(int cfg, int Ho, int Wo, int Cout) {
+    int TH, TN;
+    conv_cfg_tile(cfg, TH, TN);
+    return cdiv(Wo, 16) * cdiv(Ho, TH) * cdiv(Cout, TN);
+}
+
+// The conv layers' stage ids, output level, input level and output channels.
+struct LayerRun { int li, stage, in_level, out_level; };
+static const LayerRun kRuns[9] = {
+    {L_E1, BS_E1, 0, 1}, {L_E2, BS_E2, 1, 2}, {L_E3, BS_E3, 2, 3}, {L_HEAD, BS_HEAD, 3, 3},
+    {L_G3, BS_G3, 3, 3}, {L_G2, BS_G2, 2, 2}, {L_G1, BS_G1, 1, 1}, {L_G0, BS_G0, 0, 0},
+    {L_F, BS_FPROJ, 0, 0},
+};
+
+static int run_cout(const NetShape &ns, int li) { return li == L_F ? 9 : ns.ly[li].cout; }
+
+// Tiles of every stage for one pair.
+static void pair_tiles(const sv_batch_plan *pl, const PairGeo &g, int *tiles) {
+    tiles[BS_CENSUS] = 2 * cdiv(g.w[0], CEN_TILE_W) * cdiv(g.h[0], CEN_TILE_H);
+    tiles[BS_COST_WTA] = g.h[0] * cdiv(g.w[0], cost_wta_tile_width(pl->dsplit));
+    for (const LayerRun &r : kRuns)
+        tiles[r.stage] = conv_tiles(pl->cfg[r.li], g.h[r.out_level], g.w[r.out_level],
+                                    run_cout(pl->ns, r.li));
+    tiles[BS_FINAL] = cdiv(g.W, FIN_TILE_W) * cdiv(g.H, FIN_TILE_H);
+}
+
+static void fill_geo(const NetShape &ns, int H, int W, PairGeo &g) {
+    const Levels lv = net_levels(ns, H, W);
+    g.H = H; g.W = W;
+    for (int k = 0; k < 4; ++k) { g.h[k] = lv.h[k]; g.w[k] = lv.w[k]; }
+}
+
+static ConvSrc tsrc(const void *p, int kind, int C, int pitch, int level, int f32) {
+    ConvSrc s{};
+    s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.level = level; s.f32 = f32;
+    return s;
+}
+
+// Enqueues the 12 stage launches of a plan on `st`.
+static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream_t st) {
+    const NetShape &ns = pl->ns;
+    const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
+    sv_status r = launch_reduce_census_tab(pl->tab_dev, pl->grid[BS_CENSUS], ns.f, pl->win_w,
+                                           pl->win_h, pl->low, pl->cl, pl->cr, st);
+    if (r != SV_OK) return r;
+    r = launch_cost_wta_tab(pl->tab_dev, pl->grid[BS_COST_WTA], pl->cl, pl->cr, pl->nbits, pl->disp,
+                            pl->dsplit, st);
+    if (r != SV_OK) return r;
+    ConvSrc x0{};
+    x0.ptr = pl->disp; x0.img = pl->low; x0.kind = SRC_X0; x0.C = 2; x0.level = 0;
+    x0.scale0 = (float)ns.f / 256.0f;
+    const ConvSrc none{};
+    struct In { ConvSrc s0, s1; void *out; int pitch, f32, act; };
+    const In ins[9] = {
+        {x0, none, pl->E1, c1, 0, 1},
+        {tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), none, pl->E2, c2, 0, 1},
+        {tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), none, pl->E3, c3, 0, 1},
+        {tsrc(pl->E3, SRC_TENSOR, c3, c3, 3, 0), none, pl->ML, 2 * L, 1, 0},
+        {tsrc(pl->ML, SRC_TENSOR, L, 2 * L, 3, 1), none, pl->G3, c3, 0, 1},
+        {tsrc(pl->G3, SRC_RESIZE, c3, c3, 3, 0), tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), pl->G2, c2, 0, 1},
+        {tsrc(pl->G2, SRC_RESIZE, c2, c2, 2, 0), tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), pl->G1, c1, 0, 1},
+        {tsrc(pl->G1, SRC_RESIZE, c1, c1, 1, 0), x0, pl->G0, c1, 0, 1},
+        {tsrc(pl->G0, SRC_TENSOR, c1, c1, 0, 0), x0, pl->T, 12, 1, 0},
+    };
+    for (int k = 0; k < 9; ++k) {
+        const LayerRun &run = kRuns[k];
+        const int li = run.li;
+        ConvParams p{};
+        p.src[0] = ins[k].s0; p.src[1] = ins[k].s1;
+        p.Cin = ins[k].s0.C + (ins[k].s1.kind ? ins[k].s1.C : 0);
+        p.Cout = run_cout(ns, li);
+        p.cin_pad = ns.cin_pad[li]; p.n_pad = ns.n_pad[li];
+        p.wpk = (const char *)packed + ns.w_off[li];
+        p.bias = li == L_F ? nullptr : (const float *)((const char *)packed + ns.b_off[li]);
+        p.out = ins[k].out; p.out_pitch = ins[k].pitch; p.out_f32 = ins[k].f32; p.act = ins[k].act;
+        p.tab = pl->tab_dev; p.stage = run.stage; p.in_level = run.in_level; p.out_level = run.out_level;
+        const int ks = li == L_F ? 1 : ns.ly[li].k, stride = li == L_F ? 1 : ns.ly[li].stride;
+        r = launch_conv_tab(ns.dtype, ks, stride, pl->cfg[li], p, pl->grid[run.stage], st);
+        if (r != SV_OK) return r;
+    }
+    return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], pl->T, 12, pl->disp,
+                            (float)ns.f / 256.0f, (const float *)((const char *)packed + ns.b_off[L_F]),
+                            st);
+}
+
+static void destroy_graph(sv_batch_plan *pl) {
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    pl->exec = nullptr;
+    pl->graph = nullptr;
+    pl->graph_w = nullptr;
+}
+
+static sv_status capture(sv_batch_plan *pl, const void *packed) {
+    destroy_graph(pl);
+    SV_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal));
+    sv_status r = enqueue_stages(pl, packed, pl->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(pl->cap_stream, &g);
+    if (r != SV_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return r;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    pl->graph = g;
+    SV_HIP(hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0));
+    pl->graph_w = packed;
+    return SV_OK;
+}
+
+static bool graph_disabled() {
+    const char *e = getenv("SV_DISABLE_GRAPH");
+    return e && e[0] == '1';
+}
+
+}  // namespace sv
 
 extern "C" {
 
-struct sv_batch_plan { int unused; };
+sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, int max_W,
+                               int max_D, int win_w, int win_h, sv_batch_plan **plan_out) {
+    if (!plan_out) return SV_ERR_NULL;
+    *plan_out = nullptr;
+    NetShape ns;
+    sv_status r = net_shape(desc, ns);
+    if (r != SV_OK) return r;
+    if (max_n < 1 || max_n > SV_MAXN || max_H < 1 || max_W < 1 || max_H > 16384 || max_W > 16384)
+        return SV_ERR_SHAPE;
+    if (max_D < 1 || max_D > 256) return SV_ERR_RANGE;
+    if (win_w < 1 || win_h < 1 || win_w % 2 == 0 || win_h % 2 == 0 || win_w > 17 || win_h > 17 ||
+        win_w * win_h - 1 > 64 || win_w * win_h - 1 < 1)
+        return SV_ERR_RANGE;
 
-sv_status sv_batch_plan_create(const sv_vae_desc *, int, int, int, int, int, int, sv_batch_plan **plan) {
-    if (plan) *plan = nullptr;
-    return SV_ERR_UNSUPPORTED;
-}
-sv_status sv_batch_plan_destroy(sv_batch_plan *) { return SV_OK; }
-sv_status sv_stereo_batch(sv_batch_plan *, const sv_pair *, int, const void *, void *) { return SV_ERR_UNSUPPORTED; }
-sv_status sv_autotune(const sv_vae_desc *, int, int, int, int, int, int) { return SV_ERR_UNSUPPORTED; }
-sv_status sv_tile_config(int, char *buf, int buflen) {
-    if (buf && buflen > 0) buf[0] = 0;
-    return SV_ERR_UNSUPPORTED;
+    sv_batch_plan *pl = new sv_batch_plan();
+    memset((void *)pl, 0, sizeof(*pl));
+    pl->ns = ns;
+    pl->desc = *desc;
+    pl->max_n = max_n; pl->max_H = max_H; pl->max_W = max_W; pl->max_D = max_D;
+    pl->win_w = win_w; pl->win_h = win_h; pl->nbits = win_w * win_h - 1;
+    // tile shapes: the autotune cache, else the single-call defaults
+    pl->dsplit = cost_wta_split_get();
+    const Levels mx = net_levels(ns, max_H, max_W);
+    for (int i = 0; i < NLAYERS; ++i) {
+        const int lvl = i == L_E1 ? 1 : (i == L_E2 ? 2 : (i <= L_G3 ? 3 : (i == L_G2 ? 2 : (i == L_G1 ? 1 : 0))));
+        pl->cfg[i] = net_default_cfg(ns, i, mx.h[lvl] * mx.w[lvl]);
+    }
+    int ds;
+    int cfg[NLAYERS];
+    if (cache_lookup(tune_key(ns, max_H, max_W, max_D), ds, cfg)) {
+        pl->dsplit = ds;
+        for (int i = 0; i < NLAYERS; ++i) pl->cfg[i] = cfg[i];
+    }
+    // capacities and persistent grid sizes from the largest pair
+    for (int k = 0; k < 4; ++k) pl->cap[k] = (size_t)max_n * mx.h[k] * mx.w[k];
+    PairGeo gmax{};
+    fill_geo(ns, max_H, max_W, gmax);
+    gmax.D = max_D;
+    int tiles[BS_NSTAGES];
+    pair_tiles(pl, gmax, tiles);
+    for (int s = 0; s < BS_NSTAGES; ++s) {
+        const long long t = (long long)tiles[s] * max_n;
+        pl->grid[s] = (int)(t < kStageGridMax ? t : kStageGridMax);
+        if (pl->grid[s] < 1) pl->grid[s] = 1;
+    }
+    // one device allocation for every buffer
+    const int es = ns.es;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_tab = take(sizeof(PairTable));
+    const size_t o_cl = take(pl->cap[0] * 8), o_cr = take(pl->cap[0] * 8);
+    const size_t o_low = take(pl->cap[0]), o_disp = take(pl->cap[0]);
+    const size_t o_E1 = take(pl->cap[1] * ns.c1 * es), o_E2 = take(pl->cap[2] * ns.c2 * es);
+    const size_t o_E3 = take(pl->cap[3] * ns.c3 * es), o_ML = take(pl->cap[3] * 2 * ns.L * 4);
+    const size_t o_G3 = take(pl->cap[3] * ns.c3 * es), o_G2 = take(pl->cap[2] * ns.c2 * es);
+    const size_t o_G1 = take(pl->cap[1] * ns.c1 * es), o_G0 = take(pl->cap[0] * ns.c1 * es);
+    const size_t o_T = take(pl->cap[0] * 12 * 4);
+    hipError_t e = hipMalloc(&pl->dev, off);
+    if (e != hipSuccess) {
+        delete pl;
+        return hip_fail(e, "hipMalloc(batch plan)");
+    }
+    char *d = (char *)pl->dev;
+    pl->tab_dev = (PairTable *)(d + o_tab);
+    pl->cl = (uint64_t *)(d + o_cl); pl->cr = (uint64_t *)(d + o_cr);
+    pl->low = (uint8_t *)(d + o_low); pl->disp = (uint8_t *)(d + o_disp);
+    pl->E1 = d + o_E1; pl->E2 = d + o_E2; pl->E3 = d + o_E3; pl->ML = (float *)(d + o_ML);
+    pl->G3 = d + o_G3; pl->G2 = d + o_G2; pl->G1 = d + o_G1; pl->G0 = d + o_G0;
+    pl->T = (float *)(d + o_T);
+    if ((e = hipHostMalloc((void **)&pl->tab_host, sizeof(PairTable), hipHostMallocDefault)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming)) != hipSuccess) {
+        sv_batch_plan_destroy(pl);
+        return hip_fail(e, "batch plan resources");
+    }
+    *plan_out = pl;
+    return SV_OK;
 }
 
+sv_status sv_batch_plan_destroy(sv_batch_plan *pl) {
+    if (!pl) return SV_OK;
+    if (pl->upload_pending) (void)hipEventSynchronize(pl->upload_done);
+    destroy_graph(pl);
+    if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->tab_host) (void)hipHostFree(pl->tab_host);
+    if (pl->dev) (void)hipFree(pl->dev);
+    delete pl;
+    return SV_OK;
 }
+
+sv_status sv_stereo_batch(sv_batch_plan *pl, const sv_pair *pairs, int n, const void *packed_w,
+                          void *stream) {
+    if (!pl || !pairs || !packed_w) return SV_ERR_NULL;
+    if (n < 1 || n > pl->max_n) return SV_ERR_SHAPE;
+    if ((uintptr_t)packed_w % 256) return SV_ERR_RANGE;
+    for (int i = 0; i < n; ++i) {
+        const sv_pair &p = pairs[i];
+        if (!p.left || !p.right || !p.out) return SV_ERR_NULL;
+        if (p.H < 1 || p.W < 1 || p.H > pl->max_H || p.W > pl->max_W) return SV_ERR_SHAPE;
+        if (p.D < 1 || p.D > pl->max_D) return SV_ERR_RANGE;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    // the pinned table may still be read by the previous call's copy
+    if (pl->upload_pending) SV_HIP(hipEventSynchronize(pl->upload_done));
+    PairTable *t = pl->tab_host;
+    t->n = n;
+    long long off[4] = {0, 0, 0, 0};
+    for (int s = 0; s < BS_NSTAGES; ++s) t->cum[s][0] = 0;
+    for (int i = 0; i < n; ++i) {
+        PairGeo &g = t->pair[i];
+        memset(&g, 0, sizeof g);
+        fill_geo(pl->ns, pairs[i].H, pairs[i].W, g);
+        g.D = pairs[i].D;
+        for (int k = 0; k < 4; ++k) {
+            g.off[k] = off[k];
+            off[k] += (long long)g.h[k] * g.w[k];
+        }
+        g.left = pairs[i].left; g.right = pairs[i].right; g.out = pairs[i].out;
+        g.disp_out = pairs[i].disp_low;
+        int tiles[BS_NSTAGES];
+        pair_tiles(pl, g, tiles);
+        for (int s = 0; s < BS_NSTAGES; ++s) t->cum[s][i + 1] = t->cum[s][i] + tiles[s];
+    }
+    const size_t bytes = offsetof(PairTable, pair) + sizeof(PairGeo) * (size_t)n;
+    SV_HIP(hipMemcpyAsync(pl->tab_dev, t, bytes, hipMemcpyHostToDevice, st));
+    SV_HIP(hipEventRecord(pl->upload_done, st));
+    pl->upload_pending = true;
+    if (graph_disabled()) return enqueue_stages(pl, packed_w, st);
+    if (!pl->exec || pl->graph_w != packed_w) {
+        sv_status r = capture(pl, packed_w);
+        if (r != SV_OK) {
+            destroy_graph(pl);
+            return enqueue_stages(pl, packed_w, st);  // the same launches, eager
+        }
+    }
+    SV_HIP(hipGraphLaunch(pl->exec, st));
+    return SV_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: times every tile shape of every stage on a uniform batch of the
+// given shape and keeps the fastest (all shapes give bitwise-equal results).
+// ---------------------------------------------------------------------------
+__global__ void k_zero_f32(float *p, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0.f;
+}
+
+__global__ void k_fill_pattern(uint8_t *p, size_t n, uint32_t seed) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        uint32_t x = (uint32_t)i * 2654435761u ^ seed;
+        x ^= x >> 15; x *= 2246822519u; x ^= x >> 13;
+        p[i] = (uint8_t)(x >> 24);
+    }
+}
+
+sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int win_w, int win_h) {
+    NetShape ns;
+    sv_status r = net_shape(desc, ns);
+    if (r != SV_OK) return r;
+    if (B < 1 || H < 1 || W < 1 || H > 16384 || W > 16384) return SV_ERR_SHAPE;
+    if (D < 1 || D > 256) return SV_ERR_RANGE;
+    const size_t ws = sv_vae_workspace_bytes(desc, B, H, W);
+    const int h = cdiv(H, ns.f), w = cdiv(W, ns.f);
+    const size_t nimg = (size_t)B * H * W, nlow = (size_t)B * h * w;
+    // one scratch allocation: images, census, low, disp, out, packed weights, params, workspace
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_l = take(nimg), o_r = take(nimg), o_cl = take(nlow * 8), o_cr = take(nlow * 8);
+    const size_t o_low = take(nlow), o_disp = take(nlow), o_out = take(nimg * 4);
+    const size_t o_pk = take(ns.packed_bytes), o_par = take((size_t)ns.nparams * 4), o_ws = take(ws);
+    void *mem = nullptr;
+    SV_HIP(hipMalloc(&mem, off));
+    char *d = (char *)mem;
+    hipStream_t st = nullptr;
+    hipLaunchKernelGGL(k_fill_pattern, dim3(1024), dim3(256), 0, st, (uint8_t *)(d + o_l), nimg, 1u);
+    hipLaunchKernelGGL(k_fill_pattern, dim3(1024), dim3(256), 0, st, (uint8_t *)(d + o_r), nimg, 2u);
+    hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, (float *)(d + o_par), (size_t)ns.nparams);
+    r = net_pack(ns, (const float *)(d + o_par), d + o_pk, st);
+    const int reps = 8;
+    int best_ds = cost_wta_split_get();
+    int best_cfg[NLAYERS];
+    for (int i = 0; i < NLAYERS; ++i) best_cfg[i] = net_get_cfg_override(i);
+    float ms[PROF_NSTAGES];
+    int cnt[PROF_NSTAGES];
+    if (r == SV_OK) {
+        // census once, then every lane split of the cost + WTA kernel
+        r = launch_reduce_census((uint8_t *)(d + o_l), (uint8_t *)(d + o_r), B, H, W, W, ns.f, win_w,
+                                 win_h, (uint8_t *)(d + o_low), nullptr, (uint64_t *)(d + o_cl),
+                                 (uint64_t *)(d + o_cr), st);
+        float best = 1e30f;
+        const int splits[4] = {1, 2, 4, 8};
+        for (int k = 0; k < 4 && r == SV_OK; ++k) {
+            hipEvent_t a, b;
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+            (void)hipEventRecord(a, st);
+            for (int i = 0; i < reps && r == SV_OK; ++i)
+                r = launch_cost_wta((uint64_t *)(d + o_cl), (uint64_t *)(d + o_cr), B, h, w, D,
+                                    win_w * win_h - 1, (uint8_t *)(d + o_disp), splits[k], st);
+            (void)hipEventRecord(b, st);
+            (void)hipEventSynchronize(b);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, a, b);
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (t < best) { best = t; best_ds = splits[k]; }
+        }
+        // every tile shape for all layers at once; per-layer times from the events
+        float best_t[NLAYERS];
+        for (int i = 0; i < NLAYERS; ++i) best_t[i] = 1e30f;
+        const int stage_of[NLAYERS] = {PROF_E1, PROF_E2, PROF_E3, PROF_HEAD, PROF_G3, PROF_G2,
+                                       PROF_G1, PROF_G0, PROF_FPROJ};
+        for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
+            for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, c);
+            r = net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H, W,
+                            nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, st);  // warm
+            if (r != SV_OK) break;
+            r = sv_profile_enable(reps);
+            for (int i = 0; i < reps && r == SV_OK; ++i)
+                r = net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H,
+                                W, nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, st);
+            if (r == SV_OK) r = sv_profile_read(ms, cnt);
+            (void)sv_profile_enable(0);
+            for (int i = 0; i < NLAYERS && r == SV_OK; ++i) {
+                const int s = stage_of[i];
+                const float t = cnt[s] ? ms[s] / cnt[s] : 1e30f;
+                if (t < best_t[i]) { best_t[i] = t; best_cfg[i] = c; }
+            }
+        }
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(mem);
+    if (r != SV_OK) {
+        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, -1);
+        return r;
+    }
+    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, best_cfg[i]);
+    cost_wta_split_set(best_ds);
+    cache_store(tune_key(ns, H, W, D), best_ds, best_cfg);
+    return SV_OK;
+}
+
+sv_status sv_tile_config(int stage, char *buf, int buflen) {
+    if (!buf || buflen < 1) return SV_ERR_NULL;
+    if (stage == 0) {
+        snprintf(buf, buflen, "census tile %dx%d", CEN_TILE_W, CEN_TILE_H);
+    } else if (stage == 1) {
+        snprintf(buf, buflen, "cost_wta dsplit=%d", cost_wta_split_get());
+    } else if (stage >= 2 && stage < 2 + NLAYERS) {
+        const int ov = net_get_cfg_override(stage - 2);
+        snprintf(buf, buflen, "layer %d cfg=%s", stage - 2, ov >= 0 ? conv_cfg_name(ov) : "default");
+    } else {
+        buf[0] = 0;
+        return SV_ERR_RANGE;
+    }
+    return SV_OK;
+}
+
+}  // extern "C"

@@ -31,6 +31,7 @@ sv_status hip_fail(hipError_t e, const char *where);
     } while (0)
 
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+__device__ __forceinline__ int cdiv_d(int a, int b) { return (a + b - 1) / b; }
 static inline size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // ---- storage types of the network's activations and weights ------------------

@@ -90,197 +90,267 @@ __device__ __forceinline__ void load_px(const void *base, size_t off, bool src_f
     }
 }
 
+// Where one tile's data lives: sizes of the input and output grids, the pixel
+// offset of the image in each source and in the output, and the tile origin.
+struct ConvGeo {
+    int Hi, Wi, Ho, Wo;
+    long long sbase[2];
+    int hs[2], ws[2];
+    long long obase;
+    int n0, oy0, ox0;
+};
+
 template <int DT, int KS, int S, int TH, int TN, int WM, int KC>
-__global__ void __launch_bounds__(256) k_conv(const ConvParams p)
-{
+struct ConvTile {
     using M = Mfma<DT>;
     using T = typename M::T;
     using vec = typename M::vec;
-    constexpr int GS = M::GS;
-    constexpr int TW = 16;
-    constexpr int TAPS = KS * KS;
-    constexpr int PAD = (KS - 1) / 2;
-    constexpr int PH = (TH - 1) * S + KS, PW = (TW - 1) * S + KS;
-    constexpr int KCG = KC / GS;
-    constexpr int KCP = KC + GS;  // padded LDS row, in elements
-    constexpr int WN = 4 / WM;
-    constexpr int MBW = TH / WM;
-    constexpr int NBW = TN / 16 / WN;
-    constexpr int NSTEP = (TAPS * KCG + 3) / 4;
+    static constexpr int GS = M::GS;
+    static constexpr int TW = 16;
+    static constexpr int TAPS = KS * KS;
+    static constexpr int PAD = (KS - 1) / 2;
+    static constexpr int PH = (TH - 1) * S + KS, PW = (TW - 1) * S + KS;
+    static constexpr int KCG = KC / GS;
+    static constexpr int KCP = KC + GS;  // padded LDS row, in elements
+    static constexpr int WN = 4 / WM;
+    static constexpr int MBW = TH / WM;
+    static constexpr int NBW = TN / 16 / WN;
+    static constexpr int NSTEP = (TAPS * KCG + 3) / 4;
     static_assert(TH % WM == 0 && (TN / 16) % WN == 0 && KC % GS == 0, "tile");
 
-    __shared__ __attribute__((aligned(16))) T patch[PH * PW * KCP];
-    __shared__ __attribute__((aligned(16))) T wl[TAPS * TN * KCP];
+    struct Smem {
+        T patch[PH * PW * KCP];
+        T wl[TAPS * TN * KCP];
+    };
 
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave % WM, wn = wave / WM;
-    const int ntn = (p.Cout + TN - 1) / TN;
-    const int b = blockIdx.z / ntn, n0 = (blockIdx.z % ntn) * TN;
-    const int ox0 = blockIdx.x * TW, oy0 = blockIdx.y * TH;
-    const int iy0 = oy0 * S - PAD, ix0 = ox0 * S - PAD;
-    const int g = lane >> 4, r16 = lane & 15;
+    static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm) {
+        T *patch = sm.patch, *wl = sm.wl;
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % WM, wn = wave / WM;
+        const int n0 = G.n0, ox0 = G.ox0, oy0 = G.oy0;
+        const int iy0 = oy0 * S - PAD, ix0 = ox0 * S - PAD;
+        const int g = lane >> 4, r16 = lane & 15;
 
-    f32x4 acc[MBW][NBW];
+        f32x4 acc[MBW][NBW];
 #pragma unroll
-    for (int i = 0; i < MBW; ++i)
+        for (int i = 0; i < MBW; ++i)
 #pragma unroll
-        for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const T *wpk = (const T *)p.wpk;
-    for (int c0 = 0; c0 < p.Cin; c0 += KC) {
-        __syncthreads();
-        // ---- input patch ------------------------------------------------------
-        for (int e = tid; e < PH * PW * KCG; e += 256) {
-            const int cg = e % KCG, pix = e / KCG;
-            const int py = pix / PW, px = pix - py * PW;
-            const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
-            vec out;
+        const T *wpk = (const T *)p.wpk;
+        for (int c0 = 0; c0 < p.Cin; c0 += KC) {
+            __syncthreads();
+            // ---- input patch ------------------------------------------------------
+            for (int e = tid; e < PH * PW * KCG; e += 256) {
+                const int cg = e % KCG, pix = e / KCG;
+                const int py = pix / PW, px = pix - py * PW;
+                const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
+                vec out;
 #pragma unroll
-            for (int i = 0; i < GS; ++i) out[i] = 0;
-            if (yi >= 0 && yi < p.Hi && xi >= 0 && xi < p.Wi && c < p.Cin) {
-                const int si = c < p.src[0].C ? 0 : 1;
-                const ConvSrc &s = p.src[si];
-                const int cl = c - (si ? p.src[0].C : 0);
-                const bool sf32 = s.f32 != 0;
-                float v[GS];
-                if (s.kind == SRC_TENSOR) {
-                    const size_t off = (((size_t)b * s.hs + yi) * s.ws + xi) * s.pitch + s.coff + cl;
-                    if (!sf32) {
-                        out = *(const vec *)((const T *)s.ptr + off);
-                    } else {
-                        load_px<DT, GS>(s.ptr, off, true, v);
-                        out = pack_vec<DT, GS>(v);
-                    }
-                } else if (s.kind == SRC_RESIZE) {
-                    int y0, y1, x0, x1;
-                    float ly, lx;
-                    bilin(yi, s.hs, p.Hi, y0, y1, ly);
-                    bilin(xi, s.ws, p.Wi, x0, x1, lx);
-                    const size_t rb = (size_t)b * s.hs;
-                    float a00[GS], a01[GS], a10[GS], a11[GS];
-                    const size_t cb = (size_t)s.coff + cl;
-                    load_px<DT, GS>(s.ptr, ((rb + y0) * s.ws + x0) * s.pitch + cb, sf32, a00);
-                    load_px<DT, GS>(s.ptr, ((rb + y0) * s.ws + x1) * s.pitch + cb, sf32, a01);
-                    load_px<DT, GS>(s.ptr, ((rb + y1) * s.ws + x0) * s.pitch + cb, sf32, a10);
-                    load_px<DT, GS>(s.ptr, ((rb + y1) * s.ws + x1) * s.pitch + cb, sf32, a11);
-#pragma unroll
-                    for (int i = 0; i < GS; ++i) {
-                        const float top = (1.f - lx) * a00[i] + lx * a01[i];
-                        const float bot = (1.f - lx) * a10[i] + lx * a11[i];
-                        v[i] = (1.f - ly) * top + ly * bot;
-                    }
-                    out = pack_vec<DT, GS>(v);
-                } else if (s.kind == SRC_ZINS) {
-                    if (((yi | xi) & 1) == 0) {
-                        const size_t off =
-                            (((size_t)b * s.hs + (yi >> 1)) * s.ws + (xi >> 1)) * s.pitch + s.coff + cl;
+                for (int i = 0; i < GS; ++i) out[i] = 0;
+                if (yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin) {
+                    const int si = c < p.src[0].C ? 0 : 1;
+                    const ConvSrc &s = p.src[si];
+                    const int cl = c - (si ? p.src[0].C : 0);
+                    const bool sf32 = s.f32 != 0;
+                    const long long sb = G.sbase[si];
+                    const int hs = G.hs[si], ws = G.ws[si];
+                    float v[GS];
+                    if (s.kind == SRC_TENSOR) {
+                        const size_t off = (size_t)(sb + (long long)yi * ws + xi) * s.pitch + s.coff + cl;
                         if (!sf32) {
                             out = *(const vec *)((const T *)s.ptr + off);
                         } else {
                             load_px<DT, GS>(s.ptr, off, true, v);
                             out = pack_vec<DT, GS>(v);
                         }
+                    } else if (s.kind == SRC_RESIZE) {
+                        int y0, y1, x0, x1;
+                        float ly, lx;
+                        bilin(yi, hs, G.Hi, y0, y1, ly);
+                        bilin(xi, ws, G.Wi, x0, x1, lx);
+                        float a00[GS], a01[GS], a10[GS], a11[GS];
+                        const size_t cb = (size_t)s.coff + cl;
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sf32, a00);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sf32, a01);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sf32, a10);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sf32, a11);
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) {
+                            const float top = (1.f - lx) * a00[i] + lx * a01[i];
+                            const float bot = (1.f - lx) * a10[i] + lx * a11[i];
+                            v[i] = (1.f - ly) * top + ly * bot;
+                        }
+                        out = pack_vec<DT, GS>(v);
+                    } else if (s.kind == SRC_ZINS) {
+                        if (((yi | xi) & 1) == 0) {
+                            const size_t off =
+                                (size_t)(sb + (long long)(yi >> 1) * ws + (xi >> 1)) * s.pitch + s.coff + cl;
+                            if (!sf32) {
+                                out = *(const vec *)((const T *)s.ptr + off);
+                            } else {
+                                load_px<DT, GS>(s.ptr, off, true, v);
+                                out = pack_vec<DT, GS>(v);
+                            }
+                        }
+                    } else {  // SRC_X0: [f*d/256, I/256]
+                        const size_t o = (size_t)(sb + (long long)yi * ws + xi);
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[o];
+                        v[1] = (float)s.img[o] * (1.0f / 256.0f);
+                        out = pack_vec<DT, GS>(v);
                     }
-                } else {  // SRC_X0: [f*d/256, I/256]
-                    const size_t o = ((size_t)b * s.hs + yi) * s.ws + xi;
-#pragma unroll
-                    for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                    v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[o];
-                    v[1] = (float)s.img[o] * (1.0f / 256.0f);
-                    out = pack_vec<DT, GS>(v);
                 }
+                *(vec *)&patch[(py * PW + px) * KCP + cg * GS] = out;
             }
-            *(vec *)&patch[(py * PW + px) * KCP + cg * GS] = out;
-        }
-        // ---- weights ------------------------------------------------------------
-        for (int e = tid; e < TAPS * TN * KCG; e += 256) {
-            const int cg = e % KCG, r = e / KCG;
-            const int n = r % TN, tap = r / TN;
-            const int c = c0 + cg * GS, ng = n0 + n;
-            vec val;
+            // ---- weights ------------------------------------------------------------
+            for (int e = tid; e < TAPS * TN * KCG; e += 256) {
+                const int cg = e % KCG, r = e / KCG;
+                const int n = r % TN, tap = r / TN;
+                const int c = c0 + cg * GS, ng = n0 + n;
+                vec val;
 #pragma unroll
-            for (int i = 0; i < GS; ++i) val[i] = 0;
-            if (ng < p.n_pad && c < p.cin_pad)
-                val = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
-            *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
-        }
-        __syncthreads();
-        // ---- MFMA over (tap, channel-group) pairs ---------------------------
-        for (int st = 0; st < NSTEP; ++st) {
-            const int q = st * 4 + g;
-            const bool valid = q < TAPS * KCG;
-            const int tap = valid ? q / KCG : 0, cg = valid ? q % KCG : 0;
-            const int u = tap / KS, v = tap - (tap / KS) * KS;
-            vec bf[MBW], af[NBW];
+                for (int i = 0; i < GS; ++i) val[i] = 0;
+                if (ng < p.n_pad && c < p.cin_pad)
+                    val = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
+                *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
+            }
+            __syncthreads();
+            // ---- MFMA over (tap, channel-group) pairs ---------------------------
+            for (int st = 0; st < NSTEP; ++st) {
+                const int q = st * 4 + g;
+                const bool valid = q < TAPS * KCG;
+                const int tap = valid ? q / KCG : 0, cg = valid ? q % KCG : 0;
+                const int u = tap / KS, v = tap - (tap / KS) * KS;
+                vec bf[MBW], af[NBW];
 #pragma unroll
-            for (int mb = 0; mb < MBW; ++mb) {
-                const int ty = wm * MBW + mb;
-                bf[mb] = *(const vec *)&patch[((ty * S + u) * PW + (r16 * S + v)) * KCP + cg * GS];
-                if (!valid) {
+                for (int mb = 0; mb < MBW; ++mb) {
+                    const int ty = wm * MBW + mb;
+                    bf[mb] = *(const vec *)&patch[((ty * S + u) * PW + (r16 * S + v)) * KCP + cg * GS];
+                    if (!valid) {
 #pragma unroll
-                    for (int i = 0; i < GS; ++i) bf[mb][i] = 0;
+                        for (int i = 0; i < GS; ++i) bf[mb][i] = 0;
+                    }
                 }
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    const int n = (wn * NBW + nb) * 16 + r16;
+                    af[nb] = *(const vec *)&wl[(tap * TN + n) * KCP + cg * GS];
+                }
+#pragma unroll
+                for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = M::run(af[nb], bf[mb], acc[mb][nb]);
             }
+        }
+
+        // ---- epilogue: bias, activation, backward terms, NHWC store ------------
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            const int oy = oy0 + wm * MBW + mb, ox = ox0 + r16;
+            if (oy >= G.Ho || ox >= G.Wo) continue;
+            const size_t pix = (size_t)(G.obase + (long long)oy * G.Wo + ox);
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
-                const int n = (wn * NBW + nb) * 16 + r16;
-                af[nb] = *(const vec *)&wl[(tap * TN + n) * KCP + cg * GS];
-            }
+                const int nbase = n0 + (wn * NBW + nb) * 16 + 4 * g;
+                float r[4];
 #pragma unroll
-            for (int mb = 0; mb < MBW; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = M::run(af[nb], bf[mb], acc[mb][nb]);
-        }
-    }
-
-    // ---- epilogue: bias, activation, NHWC store -------------------------------
-#pragma unroll
-    for (int mb = 0; mb < MBW; ++mb) {
-        const int oy = oy0 + wm * MBW + mb, ox = ox0 + r16;
-        if (oy >= p.Ho || ox >= p.Wo) continue;
-        const size_t pix = ((size_t)b * p.Ho + oy) * p.Wo + ox;
-#pragma unroll
-        for (int nb = 0; nb < NBW; ++nb) {
-            const int nbase = n0 + (wn * NBW + nb) * 16 + 4 * g;
-            float r[4];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int n = nbase + i;
-                float val = acc[mb][nb][i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
-                if (p.act) val = val > 0.f ? val : 0.1f * val;
-                if (n < p.Cout) {
-                    if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
-                    if (p.mask) {
-                        const float mv = Elem<DT>::load((const T *)p.mask + pix * p.mask_pitch + n);
-                        val *= mv > 0.f ? 1.0f : 0.1f;
+                for (int i = 0; i < 4; ++i) {
+                    const int n = nbase + i;
+                    float val = acc[mb][nb][i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
+                    if (p.act) val = val > 0.f ? val : 0.1f * val;
+                    if (n < p.Cout) {
+                        if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
+                        if (p.mask) {
+                            const float mv = Elem<DT>::load((const T *)p.mask + pix * p.mask_pitch + n);
+                            val *= mv > 0.f ? 1.0f : 0.1f;
+                        }
+                    }
+                    r[i] = val;
+                }
+                const size_t o = pix * p.out_pitch + p.out_coff + nbase;
+                const bool full = nbase + 4 <= p.Cout;
+                if (p.out_f32) {
+                    float *op = (float *)p.out + o;
+                    if (full && (o % 4) == 0) {
+                        *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
+                    } else {
+                        for (int i = 0; i < 4; ++i)
+                            if (nbase + i < p.Cout) op[i] = r[i];
+                    }
+                } else {
+                    T *op = (T *)p.out + o;
+                    if (full && (o % 4) == 0 && DT != SV_F32) {
+                        u16x4 w4;
+                        for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)Elem<DT>::make(r[i]);
+                        *(u16x4 *)op = w4;
+                    } else if (full && (o % 4) == 0) {
+                        *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
+                    } else {
+                        for (int i = 0; i < 4; ++i)
+                            if (nbase + i < p.Cout) op[i] = Elem<DT>::make(r[i]);
                     }
                 }
-                r[i] = val;
-            }
-            const size_t o = pix * p.out_pitch + p.out_coff + nbase;
-            const bool full = nbase + 4 <= p.Cout;
-            if (p.out_f32) {
-                float *op = (float *)p.out + o;
-                if (full && (o % 4) == 0) {
-                    *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
-                } else {
-                    for (int i = 0; i < 4; ++i)
-                        if (nbase + i < p.Cout) op[i] = r[i];
-                }
-            } else {
-                T *op = (T *)p.out + o;
-                if (full && (o % 4) == 0 && DT != SV_F32) {
-                    u16x4 w4;
-                    for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)Elem<DT>::make(r[i]);
-                    *(u16x4 *)op = w4;
-                } else if (full && (o % 4) == 0) {
-                    *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
-                } else {
-                    for (int i = 0; i < 4; ++i)
-                        if (nbase + i < p.Cout) op[i] = Elem<DT>::make(r[i]);
-                }
             }
         }
+    }
+};
+
+// Uniform batch: one workgroup per (column tile, row tile, image x channel tile).
+template <int DT, int KS, int S, int TH, int TN, int WM, int KC>
+__global__ void __launch_bounds__(256) k_conv(const ConvParams p)
+{
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KC>;
+    __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
+    const int ntn = (p.Cout + TN - 1) / TN;
+    const int b = blockIdx.z / ntn;
+    ConvGeo G;
+    G.Hi = p.Hi; G.Wi = p.Wi; G.Ho = p.Ho; G.Wo = p.Wo;
+    for (int i = 0; i < 2; ++i) {
+        G.hs[i] = p.src[i].hs;
+        G.ws[i] = p.src[i].ws;
+        G.sbase[i] = (long long)b * p.src[i].hs * p.src[i].ws;
+    }
+    G.obase = (long long)b * p.Ho * p.Wo;
+    G.n0 = (blockIdx.z % ntn) * TN;
+    G.oy0 = blockIdx.y * TH;
+    G.ox0 = blockIdx.x * CT::TW;
+    CT::run(p, G, sm);
+}
+
+// Pair table: persistent loop over the stage's tiles of every pair.
+template <int DT, int KS, int S, int TH, int TN, int WM, int KC>
+__global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
+{
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KC>;
+    __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
+    const PairTable *tab = p.tab;
+    const int n = tab->n;
+    const int *cum = tab->cum[p.stage];
+    const int total = cum[n];
+    const int ntn = (p.Cout + TN - 1) / TN;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &pg = tab->pair[i];
+        ConvGeo G;
+        G.Hi = pg.h[p.in_level]; G.Wi = pg.w[p.in_level];
+        G.Ho = pg.h[p.out_level]; G.Wo = pg.w[p.out_level];
+        for (int k = 0; k < 2; ++k) {
+            const int lv = p.src[k].level;
+            G.hs[k] = pg.h[lv];
+            G.ws[k] = pg.w[lv];
+            G.sbase[k] = pg.off[lv];
+        }
+        G.obase = pg.off[p.out_level];
+        const int local = t - cum[i];
+        const int tx = cdiv_d(G.Wo, CT::TW), ty = cdiv_d(G.Ho, TH);
+        const int nt = local / (tx * ty), r = local - nt * tx * ty;
+        G.n0 = nt * TN;
+        G.oy0 = (r / tx) * TH;
+        G.ox0 = (r % tx) * CT::TW;
+        CT::run(p, G, sm);
+        (void)ntn;
     }
 }
 
@@ -298,9 +368,15 @@ static const CfgDesc kCfgs[] = {
 int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
 const char *conv_cfg_name(int cfg) { return (cfg >= 0 && cfg < conv_num_cfgs()) ? kCfgs[cfg].name : "?"; }
 
+// grid <= 0: uniform launch; grid > 0: persistent launch over p.tab.
 template <int DT, int KS, int S, int TH, int TN, int WM>
-static sv_status launch_one(const ConvParams &p, hipStream_t st) {
+static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     constexpr int KC = DT == SV_F32 ? 16 : 32;
+    if (pgrid > 0) {
+        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KC>), dim3(pgrid), dim3(256), 0, st, p);
+        SV_LAUNCH_CHECK("k_conv_tab");
+        return SV_OK;
+    }
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), p.B * cdiv(p.Cout, TN));
     hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KC>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
@@ -308,33 +384,50 @@ static sv_status launch_one(const ConvParams &p, hipStream_t st) {
 }
 
 template <int DT, int KS, int S>
-static sv_status launch_cfg(int cfg, const ConvParams &p, hipStream_t st) {
+static sv_status launch_cfg(int cfg, const ConvParams &p, int pg, hipStream_t st) {
     switch (cfg) {
-    case 0: return launch_one<DT, KS, S, 4, 64, 4>(p, st);
-    case 1: return launch_one<DT, KS, S, 8, 64, 4>(p, st);
-    case 2: return launch_one<DT, KS, S, 4, 32, 4>(p, st);
-    case 3: return launch_one<DT, KS, S, 8, 32, 4>(p, st);
-    case 4: return launch_one<DT, KS, S, 2, 64, 2>(p, st);
-    case 5: return launch_one<DT, KS, S, 4, 16, 4>(p, st);
+    case 0: return launch_one<DT, KS, S, 4, 64, 4>(p, pg, st);
+    case 1: return launch_one<DT, KS, S, 8, 64, 4>(p, pg, st);
+    case 2: return launch_one<DT, KS, S, 4, 32, 4>(p, pg, st);
+    case 3: return launch_one<DT, KS, S, 8, 32, 4>(p, pg, st);
+    case 4: return launch_one<DT, KS, S, 2, 64, 2>(p, pg, st);
+    case 5: return launch_one<DT, KS, S, 4, 16, 4>(p, pg, st);
     default: return SV_ERR_RANGE;
     }
 }
 
 template <int DT>
-static sv_status launch_dt(int ks, int stride, int cfg, const ConvParams &p, hipStream_t st) {
-    if (ks == 3 && stride == 1) return launch_cfg<DT, 3, 1>(cfg, p, st);
-    if (ks == 3 && stride == 2) return launch_cfg<DT, 3, 2>(cfg, p, st);
-    if (ks == 1 && stride == 1) return launch_cfg<DT, 1, 1>(cfg, p, st);
+static sv_status launch_dt(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st) {
+    if (ks == 3 && stride == 1) return launch_cfg<DT, 3, 1>(cfg, p, pg, st);
+    if (ks == 3 && stride == 2) return launch_cfg<DT, 3, 2>(cfg, p, pg, st);
+    if (ks == 1 && stride == 1) return launch_cfg<DT, 1, 1>(cfg, p, pg, st);
     return SV_ERR_UNSUPPORTED;
 }
 
-sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t st) {
+static sv_status launch_any(int dtype, int ks, int stride, int cfg, const ConvParams &p, int pg,
+                            hipStream_t st) {
     switch (dtype) {
-    case SV_F32: return launch_dt<SV_F32>(ks, stride, cfg, p, st);
-    case SV_BF16: return launch_dt<SV_BF16>(ks, stride, cfg, p, st);
-    case SV_F16: return launch_dt<SV_F16>(ks, stride, cfg, p, st);
+    case SV_F32: return launch_dt<SV_F32>(ks, stride, cfg, p, pg, st);
+    case SV_BF16: return launch_dt<SV_BF16>(ks, stride, cfg, p, pg, st);
+    case SV_F16: return launch_dt<SV_F16>(ks, stride, cfg, p, pg, st);
     default: return SV_ERR_DTYPE;
     }
+}
+
+sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t st) {
+    return launch_any(dtype, ks, stride, cfg, p, 0, st);
+}
+
+sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
+                          hipStream_t st) {
+    if (!p.tab || grid <= 0) return SV_ERR_RANGE;
+    return launch_any(dtype, ks, stride, cfg, p, grid, st);
+}
+
+void conv_cfg_tile(int cfg, int &TH, int &TN) {
+    if (cfg < 0 || cfg >= conv_num_cfgs()) cfg = 0;
+    TH = kCfgs[cfg].TH;
+    TN = kCfgs[cfg].TN;
 }
 
 // ---- weight packing ---------------------------------------------------------------

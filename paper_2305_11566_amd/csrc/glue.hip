@@ -11,16 +11,12 @@ namespace sv {
 //   R(Y, X) = sum_t [inside] resize(T_t)(Y + u - 1, X + v - 1).
 // Each full-resolution pixel then gathers 9 bilinear samples of the 9-channel
 // map T instead of 3 x 3 x (c1 + 2) upsampled values.
-__global__ void __launch_bounds__(256)
-k_final(const float *__restrict__ T, int tpitch, const uint8_t *__restrict__ disp, float scale0,
-        const float *__restrict__ biasF, int h, int w, int H, int W, float *__restrict__ out)
+__device__ __forceinline__ void final_px(const float *__restrict__ Tb, int tpitch,
+                                         const uint8_t *__restrict__ db, float scale0, float bias,
+                                         int h, int w, int H, int W, int X, int Y,
+                                         float *__restrict__ out)
 {
-    const int X = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int Y = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int b = blockIdx.z;
-    if (X >= W || Y >= H) return;
-    const float *Tb = T + (size_t)b * h * w * tpitch;
-    float acc = biasF[0];
+    float acc = bias;
 #pragma unroll
     for (int u = 0; u < 3; ++u) {
         const int yy = Y + u - 1;
@@ -49,18 +45,59 @@ k_final(const float *__restrict__ T, int tpitch, const uint8_t *__restrict__ dis
     float ly, lx;
     bilin(Y, h, H, y0, y1, ly);
     bilin(X, w, W, x0, x1, lx);
-    const uint8_t *db = disp + (size_t)b * h * w;
     const float top = (1.f - lx) * (float)db[(size_t)y0 * w + x0] + lx * (float)db[(size_t)y0 * w + x1];
     const float bot = (1.f - lx) * (float)db[(size_t)y1 * w + x0] + lx * (float)db[(size_t)y1 * w + x1];
     const float base = scale0 * ((1.f - ly) * top + ly * bot);
-    out[((size_t)b * H + Y) * W + X] = 256.0f * (acc + base);
+    out[(size_t)Y * W + X] = 256.0f * (acc + base);
+}
+
+__global__ void __launch_bounds__(256)
+k_final(const float *__restrict__ T, int tpitch, const uint8_t *__restrict__ disp, float scale0,
+        const float *__restrict__ biasF, int h, int w, int H, int W, float *__restrict__ out)
+{
+    const int X = blockIdx.x * FIN_TILE_W + (threadIdx.x & 63);
+    const int Y = blockIdx.y * FIN_TILE_H + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    if (X >= W || Y >= H) return;
+    final_px(T + (size_t)b * h * w * tpitch, tpitch, disp + (size_t)b * h * w, scale0, biasF[0], h,
+             w, H, W, X, Y, out + (size_t)b * H * W);
+}
+
+// Persistent variant over the pair table; each pair writes its own output map.
+__global__ void __launch_bounds__(256)
+k_final_tab(const PairTable *__restrict__ tab, const float *__restrict__ T, int tpitch,
+            const uint8_t *__restrict__ disp, float scale0, const float *__restrict__ biasF)
+{
+    const int n = tab->n;
+    const int *cum = tab->cum[BS_FINAL];
+    const int total = cum[n];
+    const float bias = biasF[0];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &g = tab->pair[i];
+        const int local = t - cum[i];
+        const int tx = cdiv_d(g.W, FIN_TILE_W);
+        const int X = (local % tx) * FIN_TILE_W + (threadIdx.x & 63);
+        const int Y = (local / tx) * FIN_TILE_H + (threadIdx.x >> 6);
+        if (X < g.W && Y < g.H)
+            final_px(T + (size_t)g.off[0] * tpitch, tpitch, disp + g.off[0], scale0, bias, g.h[0],
+                     g.w[0], g.H, g.W, X, Y, g.out);
+    }
+}
+
+sv_status launch_final_tab(const PairTable *tab, int grid, const float *T, int tpitch,
+                           const uint8_t *disp, float scale0, const float *biasF, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final_tab, dim3(grid), dim3(256), 0, s, tab, T, tpitch, disp, scale0, biasF);
+    SV_LAUNCH_CHECK("k_final_tab");
+    return SV_OK;
 }
 
 sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float scale0,
                        const float *biasF, int B, int h, int w, int H, int W, float *out,
                        hipStream_t s)
 {
-    dim3 grid(cdiv(W, 64), cdiv(H, 4), B);
+    dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
     hipLaunchKernelGGL(k_final, grid, dim3(256), 0, s, T, tpitch, disp, scale0, biasF, h, w, H, W,
                        out);
     SV_LAUNCH_CHECK("k_final");

@@ -5,12 +5,51 @@
 
 namespace sv {
 
+// ---- batches of uneven pairs ----------------------------------------------------
+// A device-resident table describing up to SV_MAXN pairs of different sizes.
+// Every stage kernel has a persistent variant that walks the stage's tiles of
+// all pairs: tile t belongs to the pair i with cum[stage][i] <= t < cum[stage][i+1].
+constexpr int SV_MAXN = 128;
+enum BatchStage {
+    BS_CENSUS = 0, BS_COST_WTA, BS_E1, BS_E2, BS_E3, BS_HEAD, BS_G3, BS_G2, BS_G1, BS_G0, BS_FPROJ,
+    BS_FINAL, BS_NSTAGES
+};
+struct PairGeo {
+    int H, W, D, pad_;
+    int h[4], w[4];            // level sizes (level 0 = coarse map)
+    long long off[4];          // pixel offset of the pair's level-k maps in the flattened buffers
+    const uint8_t *left, *right;
+    float *out;                // user's output [H][W]
+    uint8_t *disp_out;         // user's coarse map copy, or NULL
+};
+struct PairTable {
+    int n, pad_[3];
+    int cum[BS_NSTAGES][SV_MAXN + 1];
+    PairGeo pair[SV_MAXN];
+};
+
+__device__ __forceinline__ int table_find(const int *cum, int n, int t) {
+    int lo = 0, hi = n;  // cum[lo] <= t < cum[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cum[mid] <= t) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 // ---- matching ----------------------------------------------------------------
 sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
                                int pitch, int f, int win_w, int win_h, uint8_t *low0,
                                uint8_t *low1, uint64_t *cen0, uint64_t *cen1, hipStream_t s);
 sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,
                           int nbits, uint8_t *disp, int dsplit, hipStream_t s);
+// persistent variants over a pair table (flattened level-0 buffers)
+sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int win_w, int win_h,
+                                   uint8_t *low0, uint64_t *cen0, uint64_t *cen1, hipStream_t s);
+sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl, const uint64_t *cr,
+                              int nbits, uint8_t *disp, int dsplit, hipStream_t s);
+int cost_wta_tile_width(int dsplit);
+constexpr int CEN_TILE_W = 64, CEN_TILE_H = 4;
 
 // ---- convolution as implicit GEMM ---------------------------------------------
 // A convolution input is the channel concatenation of up to two sources.
@@ -27,6 +66,7 @@ struct ConvSrc {
     int pitch;           // TENSOR / RESIZE: elements per pixel in memory
     int coff;            // TENSOR / RESIZE: first channel within a pixel
     int hs, ws;          // stored spatial size (RESIZE: the smaller map being resized)
+    int level;           // pair-table mode: the level whose sizes and offsets apply
     float scale0;        // X0: factor / 256 applied to the disparity channel
     int f32;             // TENSOR / RESIZE: stored as FP32 (else in the compute dtype)
 };
@@ -50,10 +90,17 @@ struct ConvParams {
     int add_pitch, add_coff;
     const void *mask;    // *= (mask[pix * mask_pitch + n] > 0 ? 1 : 0.1), compute dtype
     int mask_pitch;
+    // pair-table mode (persistent over the tiles of all pairs); NULL = uniform batch
+    const PairTable *tab;
+    int stage, in_level, out_level;
 };
 
 // cfg selects the tile shape (see conv.hip); ks = 1 or 3, stride = 1 or 2.
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s);
+// persistent launch over p.tab's tiles of stage p.stage with `grid` workgroups
+sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
+                          hipStream_t s);
+void conv_cfg_tile(int cfg, int &TH, int &TN);
 int conv_num_cfgs();
 const char *conv_cfg_name(int cfg);
 
@@ -69,6 +116,9 @@ sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n
 sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float scale0,
                        const float *biasF, int B, int h, int w, int H, int W, float *out,
                        hipStream_t s);
+sv_status launch_final_tab(const PairTable *tab, int grid, const float *T, int tpitch,
+                           const uint8_t *disp, float scale0, const float *biasF, hipStream_t s);
+constexpr int FIN_TILE_W = 64, FIN_TILE_H = 4;
 sv_status launch_reparam(const float *ml, const float *eps, int npix, int L, void *z, int dtype,
                          hipStream_t s);
 

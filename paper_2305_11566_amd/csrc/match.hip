@@ -17,25 +17,17 @@ namespace sv {
 // consecutive threads from consecutive addresses), then every thread packs
 // the census word of its pixel from LDS.
 // ---------------------------------------------------------------------------
-constexpr int CEN_TW = 64, CEN_TH = 4, CEN_MAXR = 8;
+constexpr int CEN_TW = CEN_TILE_W, CEN_TH = CEN_TILE_H, CEN_MAXR = 8;
+typedef uint8_t CenPatch[CEN_TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
 
-__global__ void __launch_bounds__(CEN_TW * CEN_TH)
-k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
-                int W, int pitch, int f, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
-                uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
-                uint64_t *__restrict__ cen1)
+// One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
+__device__ __forceinline__ void census_tile(CenPatch &patch, const uint8_t *__restrict__ img, int H,
+                                            int W, int pitch, int f, int rx, int ry, int h, int w,
+                                            int i0, int j0, uint8_t *__restrict__ low,
+                                            uint64_t *__restrict__ cen)
 {
-    __shared__ uint8_t patch[CEN_TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
-    const int view = blockIdx.z % 2;
-    const int b = blockIdx.z / 2;
-    const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
-    uint8_t *low = view ? low1 : low0;
-    uint64_t *cen = view ? cen1 : cen0;
-    if (view && !img1) return;
-    const int i0 = blockIdx.y * CEN_TH, j0 = blockIdx.x * CEN_TW;
     const int PH = CEN_TH + 2 * ry, PW = CEN_TW + 2 * rx;
     const int tid = threadIdx.x;
-
     for (int e = tid; e < PH * PW; e += CEN_TW * CEN_TH) {
         const int py = e / PW, px = e - py * PW;
         const int i = min(max(i0 + py - ry, 0), h - 1);
@@ -50,22 +42,40 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
         patch[py][px] = (uint8_t)((s + n / 2) / n);
     }
     __syncthreads();
-
     const int ty = tid / CEN_TW, tx = tid - ty * CEN_TW;
     const int i = i0 + ty, j = j0 + tx;
-    if (i >= h || j >= w) return;
-    const uint8_t c = patch[ty + ry][tx + rx];
-    uint64_t code = 0;
-    int k = 0;
-    for (int dy = -ry; dy <= ry; ++dy)
-        for (int dx = -rx; dx <= rx; ++dx) {
-            if (dy == 0 && dx == 0) continue;
-            code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
-            ++k;
-        }
-    const size_t o = ((size_t)b * h + i) * w + j;
-    cen[o] = code;
-    if (low) low[o] = c;
+    if (i < h && j < w) {
+        const uint8_t c = patch[ty + ry][tx + rx];
+        uint64_t code = 0;
+        int k = 0;
+        for (int dy = -ry; dy <= ry; ++dy)
+            for (int dx = -rx; dx <= rx; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
+                ++k;
+            }
+        const size_t o = (size_t)i * w + j;
+        cen[o] = code;
+        if (low) low[o] = c;
+    }
+    __syncthreads();  // the patch is reused by the next tile of a persistent loop
+}
+
+__global__ void __launch_bounds__(CEN_TW * CEN_TH)
+k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
+                int W, int pitch, int f, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
+                uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
+                uint64_t *__restrict__ cen1)
+{
+    __shared__ CenPatch patch;
+    const int view = blockIdx.z % 2;
+    const int b = blockIdx.z / 2;
+    if (view && !img1) return;
+    const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
+    uint8_t *low = view ? low1 : low0;
+    uint64_t *cen = (view ? cen1 : cen0) + (size_t)b * h * w;
+    census_tile(patch, img, H, W, pitch, f, rx, ry, h, w, blockIdx.y * CEN_TH, blockIdx.x * CEN_TW,
+                low ? low + (size_t)b * h * w : nullptr, cen);
 }
 
 sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
@@ -80,6 +90,39 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
     return SV_OK;
 }
 
+// Persistent variant: tiles of both views of every pair of the table; the
+// per-pair maps live in flattened buffers at the pair's level-0 offset.
+__global__ void __launch_bounds__(CEN_TW * CEN_TH)
+k_reduce_census_tab(const PairTable *__restrict__ tab, int f, int rx, int ry,
+                    uint8_t *__restrict__ low0, uint64_t *__restrict__ cen0,
+                    uint64_t *__restrict__ cen1)
+{
+    __shared__ CenPatch patch;
+    const int n = tab->n;
+    const int *cum = tab->cum[BS_CENSUS];
+    const int total = cum[n];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &g = tab->pair[i];
+        const int local = t - cum[i];
+        const int tw = cdiv_d(g.w[0], CEN_TW), th = cdiv_d(g.h[0], CEN_TH);
+        const int view = local / (tw * th), r = local - view * tw * th;
+        const long long o = g.off[0];
+        census_tile(patch, view ? g.right : g.left, g.H, g.W, g.W, f, rx, ry, g.h[0], g.w[0],
+                    (r / tw) * CEN_TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
+                    (view ? cen1 : cen0) + o);
+    }
+}
+
+sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int win_w, int win_h,
+                                   uint8_t *low0, uint64_t *cen0, uint64_t *cen1, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_census_tab, dim3(grid), dim3(CEN_TW * CEN_TH), 0, s, tab, f,
+                       (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1);
+    SV_LAUNCH_CHECK("k_reduce_census_tab");
+    return SV_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Hamming cost + WTA.  One workgroup = one row segment of CW_TW pixels; each
 // pixel is served by DSPLIT adjacent lanes that sweep d = k, k + DSPLIT, ...
@@ -89,25 +132,25 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
 // staged once in LDS.  The lanes of one pixel then combine keys by shuffle.
 // ---------------------------------------------------------------------------
 constexpr int CW_THREADS = 256;
+int cost_wta_tile_width(int dsplit) { return CW_THREADS / dsplit; }
 
+// One row segment [j0, j0 + TW) of one row (cl, cr, disp point at the row).
 template <int DSPLIT>
-__global__ void __launch_bounds__(CW_THREADS)
-k_cost_wta(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int h, int w, int D,
-           int nbits, uint8_t *__restrict__ disp)
+__device__ __forceinline__ void cost_wta_seg(uint64_t *rseg, const uint64_t *__restrict__ cl,
+                                             const uint64_t *__restrict__ cr, int w, int D,
+                                             int nbits, uint8_t *__restrict__ disp,
+                                             uint8_t *__restrict__ disp2, int j0)
 {
     constexpr int TW = CW_THREADS / DSPLIT;
-    __shared__ uint64_t rseg[TW + 256];
-    const int b = blockIdx.z, i = blockIdx.y, j0 = blockIdx.x * TW;
-    const size_t row = ((size_t)b * h + i) * w;
     const int base = j0 - (D - 1);  // column of rseg[0]
     for (int e = threadIdx.x; e < TW + D - 1; e += CW_THREADS) {
         const int x = base + e;
-        rseg[e] = (x >= 0 && x < w) ? cr[row + x] : 0;
+        rseg[e] = (x >= 0 && x < w) ? cr[x] : 0;
     }
     __syncthreads();
     const int p = threadIdx.x / DSPLIT, k = threadIdx.x % DSPLIT;
     const int j = j0 + p;
-    const uint64_t lv = (j < w) ? cl[row + j] : 0;
+    const uint64_t lv = (j < w) ? cl[j] : 0;
     uint32_t best = 0xffffffffu;
     const uint32_t sentinel = (uint32_t)(nbits + 1) << 8;
     for (int d = k; d < D; d += DSPLIT) {
@@ -118,7 +161,65 @@ k_cost_wta(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int
     }
 #pragma unroll
     for (int m = 1; m < DSPLIT; m <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, m));
-    if (k == 0 && j < w) disp[row + j] = (uint8_t)(best & 0xffu);
+    if (k == 0 && j < w) {
+        disp[j] = (uint8_t)(best & 0xffu);
+        if (disp2) disp2[j] = (uint8_t)(best & 0xffu);
+    }
+    __syncthreads();
+}
+
+template <int DSPLIT>
+__global__ void __launch_bounds__(CW_THREADS)
+k_cost_wta(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int h, int w, int D,
+           int nbits, uint8_t *__restrict__ disp)
+{
+    __shared__ uint64_t rseg[CW_THREADS / DSPLIT + 256];
+    const size_t row = ((size_t)blockIdx.z * h + blockIdx.y) * w;
+    cost_wta_seg<DSPLIT>(rseg, cl + row, cr + row, w, D, nbits, disp + row, nullptr,
+                         blockIdx.x * (CW_THREADS / DSPLIT));
+}
+
+template <int DSPLIT>
+__global__ void __launch_bounds__(CW_THREADS)
+k_cost_wta_tab(const PairTable *__restrict__ tab, const uint64_t *__restrict__ cl,
+               const uint64_t *__restrict__ cr, int nbits, uint8_t *__restrict__ disp)
+{
+    constexpr int TW = CW_THREADS / DSPLIT;
+    __shared__ uint64_t rseg[TW + 256];
+    const int n = tab->n;
+    const int *cum = tab->cum[BS_COST_WTA];
+    const int total = cum[n];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &g = tab->pair[i];
+        const int local = t - cum[i];
+        const int segs = cdiv_d(g.w[0], TW);
+        const int r = local / segs, j0 = (local % segs) * TW;
+        const size_t row = (size_t)g.off[0] + (size_t)r * g.w[0];
+        cost_wta_seg<DSPLIT>(rseg, cl + row, cr + row, g.w[0], g.D, nbits, disp + row,
+                             g.disp_out ? g.disp_out + (size_t)r * g.w[0] : nullptr, j0);
+    }
+}
+
+sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl, const uint64_t *cr,
+                              int nbits, uint8_t *disp, int dsplit, hipStream_t s)
+{
+    switch (dsplit) {
+#define SV_CWT_CASE(N)                                                                             \
+    case N:                                                                                        \
+        hipLaunchKernelGGL(k_cost_wta_tab<N>, dim3(grid), dim3(CW_THREADS), 0, s, tab, cl, cr,     \
+                           nbits, disp);                                                           \
+        break;
+        SV_CWT_CASE(1)
+        SV_CWT_CASE(2)
+        SV_CWT_CASE(4)
+        SV_CWT_CASE(8)
+#undef SV_CWT_CASE
+    default:
+        return SV_ERR_RANGE;
+    }
+    SV_LAUNCH_CHECK("k_cost_wta_tab");
+    return SV_OK;
 }
 
 sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,

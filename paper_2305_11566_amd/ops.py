@@ -227,3 +227,57 @@ def sv_adam_step(w, g, m, v, step, lr=5e-4, beta1=0.99, beta2=0.999, eps=1e-8):
     check(lib().sv_adam_step(ptr(w), ptr(g), ptr(m), ptr(v), w.numel(), step, ctypes.c_float(lr),
                              ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps),
                              stream_ptr()), "sv_adam_step")
+
+
+# ------------------------------------------------------------ batches of pairs
+
+class BatchPlan:
+    """sv_batch_plan: uneven pairs through the whole path in one graph replay."""
+
+    def __init__(self, c1, c2, c3, latent, factor, dtype, max_n, max_H, max_W, max_D, win_w, win_h):
+        from ._lib import Pair  # noqa: F401
+        self.desc = make_desc(c1, c2, c3, latent, factor, dtype)
+        self.factor = factor
+        self._plan = ctypes.c_void_p()
+        check(lib().sv_batch_plan_create(ctypes.byref(self.desc), max_n, max_H, max_W, max_D, win_w,
+                                         win_h, ctypes.byref(self._plan)), "sv_batch_plan_create")
+
+    def run(self, pairs, packed, outs=None, disp_outs=None):
+        """pairs: list of (left uint8 [H,W], right uint8 [H,W], D).  Returns the
+        refined maps (float32 [H,W] each, full-res px)."""
+        from ._lib import Pair
+        n = len(pairs)
+        arr = (Pair * n)()
+        if outs is None:
+            outs = [torch.empty(l.shape, dtype=torch.float32, device=l.device) for l, _, _ in pairs]
+        for i, (l, r, D) in enumerate(pairs):
+            _need(l, torch.uint8, "left")
+            _need(r, torch.uint8, "right")
+            H, W = l.shape
+            dl = disp_outs[i] if disp_outs is not None else None
+            arr[i] = Pair(l.data_ptr(), r.data_ptr(), outs[i].data_ptr(),
+                          dl.data_ptr() if dl is not None else None, H, W, D)
+        check(lib().sv_stereo_batch(self._plan, arr, n, ptr(packed), stream_ptr()), "sv_stereo_batch")
+        return outs
+
+    def close(self):
+        if self._plan:
+            lib().sv_batch_plan_destroy(self._plan)
+            self._plan = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def sv_autotune(c1, c2, c3, latent, factor, dtype, B, H, W, D, win_w, win_h):
+    d = make_desc(c1, c2, c3, latent, factor, dtype)
+    check(lib().sv_autotune(ctypes.byref(d), B, H, W, D, win_w, win_h), "sv_autotune")
+
+
+def sv_tile_config(stage: int) -> str:
+    buf = ctypes.create_string_buffer(128)
+    check(lib().sv_tile_config(stage, buf, 128), "sv_tile_config")
+    return buf.value.decode()
