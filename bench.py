@@ -164,6 +164,101 @@ def cpu_baseline(budget_s=12.0):
             "sample": f"{n} whole frames (1242x375, census+WTA+FP64 network), single thread, {el:.1f} s"}
 
 
+def run_extras(sv, torch, dev, flat, K, Wm):
+    """Uneven batch (64 pairs, one graph) vs the per-pair loop; BF16 / FP16 vs
+    FP32 end-point error with briefly trained weights; training steps/s."""
+    from synth import gen_config
+    out = {}
+    # -- 64 uneven pairs, BF16 network ---------------------------------------------------
+    ps = [gen_config(4, i) for i in range(64)]
+    pairs = [(torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev), p.D) for p in ps]
+    maxH, maxW, maxD = max(p.left.shape[0] for p in ps), max(p.left.shape[1] for p in ps), max(p.D for p in ps)
+    sv.sv_autotune(C1, C2, C3, LAT, F, "bf16", 8, maxH, maxW, maxD, WIN_W, WIN_H)
+    ref = sv.Refiner(C1, C2, C3, LAT, F, "bf16")
+    ref.pack(torch.from_numpy(flat).to(dev))
+    plan = sv.BatchPlan(C1, C2, C3, LAT, F, "bf16", 64, maxH, maxW, maxD, WIN_W, WIN_H)
+    outs = [torch.empty(l.shape, dtype=torch.float32, device=dev) for l, _, _ in pairs]
+    for _ in range(3):
+        plan.run(pairs, ref.packed, outs=outs)
+    torch.cuda.synchronize()
+    kb = max(5, min(K, 20))
+    t0 = time.perf_counter()
+    for _ in range(kb):
+        plan.run(pairs, ref.packed, outs=outs)
+    torch.cuda.synchronize()
+    ms_batch = (time.perf_counter() - t0) * 1e3 / kb
+    px = sum(p.left.size for p in ps)
+
+    def one_by_one():
+        for (l, r, Dp), o in zip(pairs, outs):
+            cl, cr, low = sv.sv_census_pair(l[None], r[None], F, WIN_W, WIN_H)
+            disp = sv.sv_cost_wta(cl, cr, Dp, NBITS)
+            ref.forward(disp, low, l.shape[0], l.shape[1], out=o[None])
+    one_by_one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        one_by_one()
+    torch.cuda.synchronize()
+    ms_loop = (time.perf_counter() - t0) * 1e3 / 3
+    out["uneven_batch_64"] = {
+        "dtype": "bf16", "pairs": 64, "megapixels_per_view": round(px / 1e6, 3),
+        "graph_ms": round(ms_batch, 4), "graph_frames_per_s": round(64e3 / ms_batch, 1),
+        "loop_ms": round(ms_loop, 4), "loop_frames_per_s": round(64e3 / ms_loop, 1),
+        "speedup": round(ms_loop / ms_batch, 2),
+        # compulsory HBM bytes: both views read, the refined map written
+        "hbm_GBs_compulsory": round(6.0 * px / (ms_batch * 1e-3) / 1e9, 2),
+    }
+    plan.close()
+    del plan, outs
+
+    # -- precision on briefly trained weights (256x128 shapes, batch 8) ---------------------
+    from paper_2305_11566_amd.train import Trainer, layer_shapes, make_pool, batch_indices
+    from synth import he_init_params
+    c = (16, 32, 64)
+    p0 = he_init_params(layer_shapes(*c, 64), seed=7005)
+    f0 = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in p0])
+    tr = Trainer(f0, C=c, latent=64, dtype="bf16")
+    pl, pr, pg = make_pool(64, 256, 512, seed0=5000)
+    steps = 300
+    for _ in range(5):
+        idx = batch_indices(tr.step, 16, 64).to(dev)
+        tr.train_step(pl[idx], pr[idx], pg[idx])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n0 = tr.step
+    while tr.step < steps:
+        idx = batch_indices(tr.step, 16, 64).to(dev)
+        tr.train_step(pl[idx], pr[idx], pg[idx])
+    torch.cuda.synchronize()
+    sps = (tr.step - n0) / (time.perf_counter() - t0)
+    out["train_512x256_b16_bf16"] = {"steps_per_s": round(sps, 2), "steps": steps,
+                                     "ms_per_step": round(1e3 / sps, 4)}
+    w_trained = tr.w
+    vp = [gen_config(3, i) for i in range(8)]
+    vl = torch.from_numpy(np.stack([p.left for p in vp])).to(dev)
+    vr = torch.from_numpy(np.stack([p.right for p in vp])).to(dev)
+    vg = torch.from_numpy(np.stack([p.gt for p in vp])).to(dev)
+    cl, cr, low = sv.sv_census_pair(vl, vr, 2, 5, 5)
+    disp = sv.sv_cost_wta(cl, cr, 16, 24)
+    res = {}
+    for dt in ("f32", "bf16", "f16"):
+        r = sv.Refiner(*c, 64, 2, dt)
+        r.pack(w_trained)
+        res[dt], _ = r.forward(disp, low, 128, 256)
+    lin = torch.nn.functional.interpolate(disp[:, None].float() * 2, size=(128, 256), mode="bilinear",
+                                          align_corners=False)[:, 0]
+    prec = {"weights": f"{steps} training steps (512x256, batch 16, BF16)", "shape": "8 x 256x128"}
+    for dt in ("bf16", "f16"):
+        d = (res[dt] - res["f32"]).abs()
+        prec[f"{dt}_vs_f32_mean_px"] = float(d.mean())
+        prec[f"{dt}_vs_f32_max_px"] = float(d.max())
+    prec["f32_vs_gt_mean_px"] = float((res["f32"] - vg).abs().mean())
+    prec["linear_vs_gt_mean_px"] = float((lin - vg).abs().mean())
+    out["precision_trained"] = prec
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +268,9 @@ def main():
     ap.add_argument("--big-batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the uneven batch, precision and training measurements")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -187,6 +285,12 @@ def main():
     K, Wm = args.steps, args.warmup
     _, flat = make_params()
     left, right, gt = make_inputs(args.batch, dev)
+
+    # ---- tile shapes: the library's autotuner for this shape ---------------------------
+    if not args.no_autotune:
+        for dt in ("f32", "bf16"):
+            sv.sv_autotune(C1, C2, C3, LAT, F, dt, args.batch, H, W, D, WIN_W, WIN_H)
+    tiles = {sv.PROFILE_STAGES[s]: sv.sv_tile_config(s) for s in range(1, 11)}
 
     # ---- headline: FP32 network, graph replay -------------------------------------
     p32 = Path(args.batch, "f32", flat, left, right)
@@ -256,6 +360,8 @@ def main():
                 del pb
             torch.cuda.synchronize()
 
+    extras = {} if args.no_extras else run_extras(sv, torch, dev, flat, K, Wm)
+
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 
     rec = {
@@ -279,6 +385,8 @@ def main():
         "kernels": kernels,
         "variants": variants,
         "epe": epe,
+        "tiles": tiles,
+        "extras": extras,
         "cpu_baseline": cpu,
         "context": {"paper_ms_per_frame_jetson_agx": 29.88,
                     "note": "paper: ZNCC+SGM+StereoVAE on Jetson AGX Xavier (Table II), not this pipeline"},

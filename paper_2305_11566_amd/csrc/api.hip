@@ -185,11 +185,12 @@ sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const v
                         workspace, (hipStream_t)stream);
 }
 
-// Selects the tile configuration of one network layer (0..8; -1 = default).
+// Selects the tile configuration of one network layer (0..8; -1 = default)
+// for every compute dtype.
 sv_status sv_set_layer_cfg(int layer, int cfg) {
     if (layer < 0 || layer >= NLAYERS) return SV_ERR_RANGE;
     if (cfg < -1 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
-    net_set_cfg_override(layer, cfg);
+    for (int dt = 0; dt < 3; ++dt) net_set_cfg_override(dt, layer, cfg);
     return SV_OK;
 }
 

@@ -441,7 +441,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     const int reps = 8;
     int best_ds = cost_wta_split_get();
     int best_cfg[NLAYERS];
-    for (int i = 0; i < NLAYERS; ++i) best_cfg[i] = net_get_cfg_override(i);
+    for (int i = 0; i < NLAYERS; ++i) best_cfg[i] = net_default_cfg(ns, i, 0);
     float ms[PROF_NSTAGES];
     int cnt[PROF_NSTAGES];
     if (r == SV_OK) {
@@ -473,7 +473,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         const int stage_of[NLAYERS] = {PROF_E1, PROF_E2, PROF_E3, PROF_HEAD, PROF_G3, PROF_G2,
                                        PROF_G1, PROF_G0, PROF_FPROJ};
         for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
-            for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, c);
+            for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, c);
             r = net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H, W,
                             nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, st);  // warm
             if (r != SV_OK) break;
@@ -493,10 +493,10 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     (void)hipStreamSynchronize(st);
     (void)hipFree(mem);
     if (r != SV_OK) {
-        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, -1);
+        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
         return r;
     }
-    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(i, best_cfg[i]);
+    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, best_cfg[i]);
     cost_wta_split_set(best_ds);
     cache_store(tune_key(ns, H, W, D), best_ds, best_cfg);
     return SV_OK;
@@ -509,8 +509,9 @@ sv_status sv_tile_config(int stage, char *buf, int buflen) {
     } else if (stage == 1) {
         snprintf(buf, buflen, "cost_wta dsplit=%d", cost_wta_split_get());
     } else if (stage >= 2 && stage < 2 + NLAYERS) {
-        const int ov = net_get_cfg_override(stage - 2);
-        snprintf(buf, buflen, "layer %d cfg=%s", stage - 2, ov >= 0 ? conv_cfg_name(ov) : "default");
+        const int o32 = net_get_cfg_override(SV_F32, stage - 2), o16 = net_get_cfg_override(SV_BF16, stage - 2);
+        snprintf(buf, buflen, "layer %d f32=%s bf16=%s", stage - 2, o32 >= 0 ? conv_cfg_name(o32) : "default",
+                 o16 >= 0 ? conv_cfg_name(o16) : "default");
     } else {
         buf[0] = 0;
         return SV_ERR_RANGE;

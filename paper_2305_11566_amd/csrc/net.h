@@ -48,8 +48,8 @@ size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B);
 // Tile configuration per layer (index into the conv kernel's table); the
 // defaults may be replaced by the autotuner.
 int net_default_cfg(const NetShape &ns, int layer, int M);
-void net_set_cfg_override(int layer, int cfg);   // -1 restores the default
-int net_get_cfg_override(int layer);
+void net_set_cfg_override(int dtype, int layer, int cfg);   // -1 restores the default
+int net_get_cfg_override(int dtype, int layer);
 
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,

@@ -86,17 +86,25 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
 }
 
 // ---- tile configuration per layer ----------------------------------------------
-static std::atomic<int> g_cfg_override[NLAYERS] = {{-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}, {-1}};
+// per compute dtype and layer; -1 = default
+static std::atomic<int> g_cfg_override[3][NLAYERS];
+static struct CfgInit {
+    CfgInit() {
+        for (auto &d : g_cfg_override)
+            for (auto &v : d) v.store(-1);
+    }
+} g_cfg_init;
 
-void net_set_cfg_override(int layer, int cfg) {
-    if (layer >= 0 && layer < NLAYERS) g_cfg_override[layer].store(cfg);
+void net_set_cfg_override(int dtype, int layer, int cfg) {
+    if (dtype >= 0 && dtype < 3 && layer >= 0 && layer < NLAYERS) g_cfg_override[dtype][layer].store(cfg);
 }
-int net_get_cfg_override(int layer) {
-    return (layer >= 0 && layer < NLAYERS) ? g_cfg_override[layer].load() : -1;
+int net_get_cfg_override(int dtype, int layer) {
+    return (dtype >= 0 && dtype < 3 && layer >= 0 && layer < NLAYERS) ? g_cfg_override[dtype][layer].load()
+                                                                       : -1;
 }
 
 int net_default_cfg(const NetShape &ns, int layer, int M) {
-    const int ov = net_get_cfg_override(layer);
+    const int ov = net_get_cfg_override(ns.dtype, layer);
     if (ov >= 0 && ov < conv_num_cfgs()) return ov;
     const int cout = layer == L_F ? 16 : ns.ly[layer].cout;
     (void)M;
