@@ -219,16 +219,16 @@ def run_extras(sv, torch, dev, flat, K, Wm):
     p0 = he_init_params(layer_shapes(*c, 64), seed=7005)
     f0 = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in p0])
     tr = Trainer(f0, C=c, latent=64, dtype="bf16")
-    pl, pr, pg = make_pool(64, 256, 512, seed0=5000)
-    steps = 300
+    pl, pr, pg = make_pool(128, 256, 512, seed0=5000)
+    steps = 2000
     for _ in range(5):
-        idx = batch_indices(tr.step, 16, 64).to(dev)
+        idx = batch_indices(tr.step, 16, 128).to(dev)
         tr.train_step(pl[idx], pr[idx], pg[idx])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     n0 = tr.step
     while tr.step < steps:
-        idx = batch_indices(tr.step, 16, 64).to(dev)
+        idx = batch_indices(tr.step, 16, 128).to(dev)
         tr.train_step(pl[idx], pr[idx], pg[idx])
     torch.cuda.synchronize()
     sps = (tr.step - n0) / (time.perf_counter() - t0)
@@ -351,6 +351,8 @@ def main():
         if bb and bb > 1:
             lb, rb, _ = make_inputs(bb, dev)
             for dt in ("f32", "bf16"):
+                if not args.no_autotune:
+                    sv.sv_autotune(C1, C2, C3, LAT, F, dt, bb, H, W, D, WIN_W, WIN_H)
                 pb = Path(bb, dt, flat, lb, rb)
                 pb.capture()
                 kb = max(5, min(K, 20))

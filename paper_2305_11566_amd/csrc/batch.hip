@@ -8,6 +8,7 @@
 // mix of sizes up to the plan's maxima.  A call writes the table for its
 // pairs, copies it to the device on the caller's stream and replays the graph.
 #include <errno.h>
+#include <math.h>
 #include <sys/stat.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -57,9 +58,17 @@ struct sv_batch_plan {
 namespace sv {
 
 // ---------------------------------------------------------------------------
-// Autotune cache: one line per entry,  key<TAB>dsplit<TAB>c0,c1,...,c8
+// Autotune cache: a text file, one entry per line
+//   gfx950|dt<dtype>|c<c1>,<c2>,<c3>|L<latent>|f<factor>|B<batch>|<H>x<W> <dsplit> <cfg0>,...,<cfg8>
+// loaded once per process into memory; lookups take the entry of the same
+// network and image size with the nearest batch size.
 // ---------------------------------------------------------------------------
+struct TuneEntry {
+    int dt, c1, c2, c3, L, f, B, H, W, dsplit, cfg[NLAYERS];
+};
 static std::mutex g_tune_mu;
+static std::vector<TuneEntry> g_tune;
+static bool g_tune_loaded = false;
 
 static std::string cache_path() {
     const char *e = getenv("SV_AUTOTUNE_CACHE");
@@ -68,70 +77,89 @@ static std::string cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/sv_autotune.tsv";
 }
 
-static std::string tune_key(const NetShape &ns, int H, int W, int D) {
-    char buf[160];
-    snprintf(buf, sizeof buf, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|%dx%d|D%d", ns.dtype, ns.c1, ns.c2,
-             ns.c3, ns.L, ns.f, H, W, D);
-    return buf;
+static bool parse_entry(const char *line, TuneEntry &t) {
+    const int m = sscanf(line, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d %d %d,%d,%d,%d,%d,%d,%d,%d,%d",
+                         &t.dt, &t.c1, &t.c2, &t.c3, &t.L, &t.f, &t.B, &t.H, &t.W, &t.dsplit,
+                         &t.cfg[0], &t.cfg[1], &t.cfg[2], &t.cfg[3], &t.cfg[4], &t.cfg[5],
+                         &t.cfg[6], &t.cfg[7], &t.cfg[8]);
+    if (m != 10 + NLAYERS) return false;
+    bool ok = (t.dsplit == 1 || t.dsplit == 2 || t.dsplit == 4 || t.dsplit == 8) && t.B > 0;
+    for (int i = 0; i < NLAYERS; ++i) ok = ok && t.cfg[i] >= 0 && t.cfg[i] < conv_num_cfgs();
+    return ok;
 }
 
-// Returns true and fills dsplit / cfg when the cache has a well-formed entry.
-static bool cache_lookup(const std::string &key, int &dsplit, int *cfg) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+static void format_entry(const TuneEntry &t, char *buf, size_t n) {
+    snprintf(buf, n, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d\t%d\t%d,%d,%d,%d,%d,%d,%d,%d,%d\n", t.dt,
+             t.c1, t.c2, t.c3, t.L, t.f, t.B, t.H, t.W, t.dsplit, t.cfg[0], t.cfg[1], t.cfg[2],
+             t.cfg[3], t.cfg[4], t.cfg[5], t.cfg[6], t.cfg[7], t.cfg[8]);
+}
+
+static bool same_key(const TuneEntry &a, const TuneEntry &b, bool with_batch) {
+    return a.dt == b.dt && a.c1 == b.c1 && a.c2 == b.c2 && a.c3 == b.c3 && a.L == b.L && a.f == b.f &&
+           a.H == b.H && a.W == b.W && (!with_batch || a.B == b.B);
+}
+
+// caller holds g_tune_mu
+static void load_cache_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
     FILE *f = fopen(cache_path().c_str(), "r");
-    if (!f) return false;
+    if (!f) return;
     char line[512];
-    bool found = false, corrupt = false;
+    bool corrupt = false;
     while (fgets(line, sizeof line, f)) {
-        char k[200];
-        int ds, c[NLAYERS];
-        const int m = sscanf(line, "%199s %d %d,%d,%d,%d,%d,%d,%d,%d,%d", k, &ds, &c[0], &c[1], &c[2],
-                             &c[3], &c[4], &c[5], &c[6], &c[7], &c[8]);
-        if (m != 2 + NLAYERS) {
+        TuneEntry t;
+        if (parse_entry(line, t))
+            g_tune.push_back(t);
+        else if (line[0] != '\n')
             corrupt = true;
-            continue;
-        }
-        bool ok = (ds == 1 || ds == 2 || ds == 4 || ds == 8);
-        for (int i = 0; i < NLAYERS; ++i) ok = ok && c[i] >= 0 && c[i] < conv_num_cfgs();
-        if (!ok) {
-            corrupt = true;
-            continue;
-        }
-        if (key == k) {
-            dsplit = ds;
-            for (int i = 0; i < NLAYERS; ++i) cfg[i] = c[i];
-            found = true;
-        }
     }
     fclose(f);
     if (corrupt)
         fprintf(stderr, "sv: ignoring malformed lines in autotune cache %s\n", cache_path().c_str());
-    return found;
 }
 
-static void cache_store(const std::string &key, int dsplit, const int *cfg) {
+static TuneEntry make_key(const NetShape &ns, int B, int H, int W) {
+    TuneEntry k{};
+    k.dt = ns.dtype; k.c1 = ns.c1; k.c2 = ns.c2; k.c3 = ns.c3; k.L = ns.L; k.f = ns.f;
+    k.B = B; k.H = H; k.W = W;
+    return k;
+}
+
+bool tuned_lookup(const NetShape &ns, int B, int H, int W, int *cfg, int *dsplit) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    const TuneEntry key = make_key(ns, B, H, W);
+    const TuneEntry *best = nullptr;
+    double bd = 1e30;
+    for (const TuneEntry &t : g_tune) {
+        if (!same_key(t, key, false)) continue;
+        const double d = fabs(log((double)t.B / (double)B));
+        if (d < bd) { bd = d; best = &t; }
+    }
+    if (!best) return false;
+    for (int i = 0; i < NLAYERS; ++i) cfg[i] = best->cfg[i];
+    if (dsplit) *dsplit = best->dsplit;
+    return true;
+}
+
+static void cache_store(const TuneEntry &e) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    load_cache_locked();
+    for (auto it = g_tune.begin(); it != g_tune.end();)
+        it = same_key(*it, e, true) ? g_tune.erase(it) : it + 1;
+    g_tune.push_back(e);
     const std::string path = cache_path();
-    std::vector<std::string> keep;
-    if (FILE *f = fopen(path.c_str(), "r")) {
-        char line[512];
-        while (fgets(line, sizeof line, f)) {
-            char k[200];
-            if (sscanf(line, "%199s", k) == 1 && key != k) keep.push_back(line);
-        }
-        fclose(f);
-    }
     const size_t slash = path.rfind('/');
-    if (slash != std::string::npos) {
-        std::string dir = path.substr(0, slash);
-        (void)mkdir(dir.c_str(), 0755);
-    }
+    if (slash != std::string::npos) (void)mkdir(path.substr(0, slash).c_str(), 0755);
     const std::string tmp = path + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
-    for (auto &l : keep) fputs(l.c_str(), f);
-    fprintf(f, "%s\t%d\t%d,%d,%d,%d,%d,%d,%d,%d,%d\n", key.c_str(), dsplit, cfg[0], cfg[1], cfg[2],
-            cfg[3], cfg[4], cfg[5], cfg[6], cfg[7], cfg[8]);
+    char buf[256];
+    for (const TuneEntry &t : g_tune) {
+        format_entry(t, buf, sizeof buf);
+        fputs(buf, f);
+    }
     fclose(f);
     rename(tmp.c_str(), path.c_str());
 }
@@ -287,9 +315,12 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     }
     int ds;
     int cfg[NLAYERS];
-    if (cache_lookup(tune_key(ns, max_H, max_W, max_D), ds, cfg)) {
+    if (tuned_lookup(ns, max_n, max_H, max_W, cfg, &ds)) {
         pl->dsplit = ds;
-        for (int i = 0; i < NLAYERS; ++i) pl->cfg[i] = cfg[i];
+        for (int i = 0; i < NLAYERS; ++i) {
+            const int ov = net_get_cfg_override(ns.dtype, i);
+            pl->cfg[i] = ov >= 0 ? ov : cfg[i];
+        }
     }
     // capacities and persistent grid sizes from the largest pair
     for (int k = 0; k < 4; ++k) pl->cap[k] = (size_t)max_n * mx.h[k] * mx.w[k];
@@ -440,8 +471,11 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     r = net_pack(ns, (const float *)(d + o_par), d + o_pk, st);
     const int reps = 8;
     int best_ds = cost_wta_split_get();
-    int best_cfg[NLAYERS];
-    for (int i = 0; i < NLAYERS; ++i) best_cfg[i] = net_default_cfg(ns, i, 0);
+    int best_cfg[NLAYERS], saved_ov[NLAYERS];
+    for (int i = 0; i < NLAYERS; ++i) {
+        best_cfg[i] = net_default_cfg(ns, i, 0);
+        saved_ov[i] = net_get_cfg_override(ns.dtype, i);
+    }
     float ms[PROF_NSTAGES];
     int cnt[PROF_NSTAGES];
     if (r == SV_OK) {
@@ -492,13 +526,13 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     }
     (void)hipStreamSynchronize(st);
     (void)hipFree(mem);
-    if (r != SV_OK) {
-        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
-        return r;
-    }
-    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, best_cfg[i]);
+    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, saved_ov[i]);
+    if (r != SV_OK) return r;
     cost_wta_split_set(best_ds);
-    cache_store(tune_key(ns, H, W, D), best_ds, best_cfg);
+    TuneEntry e = make_key(ns, B, H, W);
+    e.dsplit = best_ds;
+    for (int i = 0; i < NLAYERS; ++i) e.cfg[i] = best_cfg[i];
+    cache_store(e);
     return SV_OK;
 }
 
@@ -510,8 +544,8 @@ sv_status sv_tile_config(int stage, char *buf, int buflen) {
         snprintf(buf, buflen, "cost_wta dsplit=%d", cost_wta_split_get());
     } else if (stage >= 2 && stage < 2 + NLAYERS) {
         const int o32 = net_get_cfg_override(SV_F32, stage - 2), o16 = net_get_cfg_override(SV_BF16, stage - 2);
-        snprintf(buf, buflen, "layer %d f32=%s bf16=%s", stage - 2, o32 >= 0 ? conv_cfg_name(o32) : "default",
-                 o16 >= 0 ? conv_cfg_name(o16) : "default");
+        snprintf(buf, buflen, "layer %d override f32=%s bf16=%s", stage - 2,
+                 o32 >= 0 ? conv_cfg_name(o32) : "none", o16 >= 0 ? conv_cfg_name(o16) : "none");
     } else {
         buf[0] = 0;
         return SV_ERR_RANGE;

@@ -48,6 +48,13 @@ size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B);
 // Tile configuration per layer (index into the conv kernel's table); the
 // defaults may be replaced by the autotuner.
 int net_default_cfg(const NetShape &ns, int layer, int M);
+// Per-layer tile configuration of a forward pass of batch B at H x W: an
+// explicit override, else the autotune cache entry for this shape, else the
+// default.
+void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg);
+// The autotune cache entry for this network and image size with the nearest
+// batch size; false if there is none.
+bool tuned_lookup(const NetShape &ns, int B, int H, int W, int *cfg, int *dsplit);
 void net_set_cfg_override(int dtype, int layer, int cfg);   // -1 restores the default
 int net_get_cfg_override(int dtype, int layer);
 

@@ -113,6 +113,15 @@ int net_default_cfg(const NetShape &ns, int layer, int M) {
     return 0;                   // th4_tn64
 }
 
+void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg) {
+    int tuned[NLAYERS];
+    const bool have = tuned_lookup(ns, B, H, W, tuned, nullptr);
+    for (int i = 0; i < NLAYERS; ++i) {
+        const int ov = net_get_cfg_override(ns.dtype, i);
+        cfg[i] = ov >= 0 ? ov : (have ? tuned[i] : net_default_cfg(ns, i, 0));
+    }
+}
+
 // ---- forward ------------------------------------------------------------------------
 static ConvSrc src_tensor(const void *p, int C, int pitch, int coff, int hs, int ws, int f32) {
     ConvSrc s{};
@@ -134,7 +143,7 @@ static ConvSrc src_x0(const uint8_t *disp, const uint8_t *img, int hs, int ws, i
 
 static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
                            int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
-                           int out_f32, int act, hipStream_t st) {
+                           int out_f32, int act, int cfg, hipStream_t st) {
     ConvParams p{};
     p.src[0] = s0; p.src[1] = s1;
     p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
@@ -149,7 +158,7 @@ static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvS
     p.act = act; p.out_f32 = out_f32;
     const int ks = tsplit ? 1 : ns.ly[li].k;
     const int stride = tsplit ? 1 : ns.ly[li].stride;
-    return launch_conv(ns.dtype, ks, stride, net_default_cfg(ns, li, B * Ho * Wo), p, st);
+    return launch_conv(ns.dtype, ks, stride, cfg, p, st);
 }
 
 // launch i of the forward pass is profiling stage PROF_E1 + i
@@ -166,6 +175,8 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                       float *ml_user, void *saved, void *ws, hipStream_t st) {
     const Levels lv = net_levels(ns, H, W);
     const ActLayout a = net_act_layout(ns, lv, B);
+    int cfg[NLAYERS];
+    net_layer_cfgs(ns, B, H, W, cfg);
     char *w = (char *)ws;
     const bool train = saved != nullptr;                   // keep what the backward needs
     char *sv_ = train ? (char *)saved : w + a.ws_fwd;      // else it lives in the workspace
@@ -184,20 +195,20 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     const ConvSrc x0 = src_x0(disp, img, lv.h[0], lv.w[0], ns.f);
     // encoder
     ev_rec(0, 0, st);
-    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
     SV_TRY(run_layer(ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
-                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, st));
+                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], st));
     ev_rec(1, 1, st);
     ev_rec(2, 0, st);
     SV_TRY(run_layer(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
-                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, st));
+                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], st));
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     ev_rec(3, 0, st);
     SV_TRY(run_layer(ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
-                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, st));
+                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], st));
     ev_rec(3, 1, st);
     ConvSrc zsrc;
     if (eps) {
@@ -210,26 +221,26 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     }
     // decoder
     ev_rec(5, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, st));
+    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], st));
     ev_rec(5, 1, st);
     ev_rec(6, 0, st);
     SV_TRY(run_layer(ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
-                     lv.w[2], G2, c2, 0, 1, st));
+                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], st));
     ev_rec(6, 1, st);
     ev_rec(7, 0, st);
     SV_TRY(run_layer(ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
-                     lv.w[1], G1, c1, 0, 1, st));
+                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], st));
     ev_rec(7, 1, st);
     ev_rec(8, 0, st);
     SV_TRY(run_layer(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, st));
+                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], st));
     ev_rec(8, 1, st);
     // final layer: per-tap 1x1 projection at the coarse level, then the gather
     ev_rec(9, 0, st);
     SV_TRY(run_layer(ns, packed, L_F, src_tensor(G0, c1, c1, 0, lv.h[0], lv.w[0], 0), x0, B,
-                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, st));
+                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, cfg[L_F], st));
     ev_rec(9, 1, st);
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);
