@@ -290,7 +290,9 @@ def main():
     if not args.no_autotune:
         for dt in ("f32", "bf16"):
             sv.sv_autotune(C1, C2, C3, LAT, F, dt, args.batch, H, W, D, WIN_W, WIN_H)
-    tiles = {sv.PROFILE_STAGES[s]: sv.sv_tile_config(s) for s in range(1, 11)}
+    tiles = {"cost_wta": sv.sv_tile_config(1),
+             "f32": sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "f32", args.batch, H, W),
+             "bf16": sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "bf16", args.batch, H, W)}
 
     # ---- headline: FP32 network, graph replay -------------------------------------
     p32 = Path(args.batch, "f32", flat, left, right)

@@ -285,6 +285,13 @@ int sv_num_layer_cfgs(void);
 sv_status sv_profile_enable(int max_calls);
 sv_status sv_profile_read(float *ms_sum, int *counts);
 
+/* The tile configuration (an index, see sv_conv_cfg_name) each of the 9
+ * network layers uses for a forward pass of batch B at H x W: an explicit
+ * sv_set_layer_cfg override, else the autotune cache entry for this shape,
+ * else the default.  cfg_out: (host) int[9]. */
+sv_status sv_layer_cfgs(const sv_vae_desc *desc, int B, int H, int W, int *cfg_out);
+const char *sv_conv_cfg_name(int cfg);
+
 /* Tile configuration chosen for a stage (for tests and reports):
  * stage 0 = census, 1 = cost+WTA, 2..12 = network layers; writes a short text. */
 sv_status sv_tile_config(int stage, char *buf, int buflen);

@@ -20,6 +20,7 @@ from .ops import (  # noqa: F401
     BatchPlan,
     sv_autotune,
     sv_tile_config,
+    sv_layer_cfgs,
     sv_loss,
     sv_adam_step,
 )

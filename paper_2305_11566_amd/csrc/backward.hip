@@ -55,9 +55,11 @@ template <> struct MfmaB<SV_F32> {
     }
 };
 
-template <int DT>
-__device__ __forceinline__ float ld_el(const void *p, size_t i, bool f32) {
-    return f32 ? ((const float *)p)[i] : Elem<DT>::load((const typename Elem<DT>::T *)p + i);
+// One element of a map stored in dtype sdt, as FP32.
+__device__ __forceinline__ float ld_el(const void *p, size_t i, int sdt) {
+    if (sdt == SV_F32) return ((const float *)p)[i];
+    const uint16_t h = ((const uint16_t *)p)[i];
+    return sdt == SV_BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
 }
 
 // ---------------------------------------------------------------------------
@@ -142,11 +144,11 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
                 const int si = c < p.src[0].C ? 0 : 1;
                 const ConvSrc &s = p.src[si];
                 const int cl = c - (si ? p.src[0].C : 0);
-                const bool f32 = s.f32 != 0;
+                const int sdt = s.sdt ? s.sdt - 1 : DT;
                 if (s.kind == SRC_TENSOR) {
                     const size_t off = (((size_t)b * s.hs + yi) * s.ws + xi) * s.pitch + s.coff + cl;
 #pragma unroll
-                    for (int i = 0; i < GS; ++i) v[i] = ld_el<DT>(s.ptr, off + i, f32);
+                    for (int i = 0; i < GS; ++i) v[i] = ld_el(s.ptr, off + i, sdt);
                 } else if (s.kind == SRC_RESIZE) {
                     int y0, y1, x0, x1;
                     float ly, lx;
@@ -159,8 +161,8 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
                     const size_t o11 = ((rb + y1) * s.ws + x1) * s.pitch + cb;
 #pragma unroll
                     for (int i = 0; i < GS; ++i) {
-                        const float top = (1.f - lx) * ld_el<DT>(s.ptr, o00 + i, f32) + lx * ld_el<DT>(s.ptr, o01 + i, f32);
-                        const float bot = (1.f - lx) * ld_el<DT>(s.ptr, o10 + i, f32) + lx * ld_el<DT>(s.ptr, o11 + i, f32);
+                        const float top = (1.f - lx) * ld_el(s.ptr, o00 + i, sdt) + lx * ld_el(s.ptr, o01 + i, sdt);
+                        const float bot = (1.f - lx) * ld_el(s.ptr, o10 + i, sdt) + lx * ld_el(s.ptr, o11 + i, sdt);
                         v[i] = (1.f - ly) * top + ly * bot;
                     }
                 } else if (s.kind == SRC_X0) {
@@ -434,12 +436,12 @@ __global__ void k_final_bwd(const float *__restrict__ dout, int H, int W, int h,
         float *dt = dT + pix * 16;
 #pragma unroll
         for (int k = 0; k < 16; ++k) dt[k] = k < 9 ? t[k] : 0.f;
-        const typename Elem<DT>::T *wf = (const typename Elem<DT>::T *)wF;
+        const float *wf = (const float *)wF;  // the final projection is always packed in FP32
         const typename Elem<DT>::T *g0 = (const typename Elem<DT>::T *)G0 + pix * c1;
         for (int c = 0; c < c1; ++c) {
             float s = 0.f;
 #pragma unroll
-            for (int k = 0; k < 9; ++k) s += Elem<DT>::load(wf + (size_t)k * wf_pitch + c) * t[k];
+            for (int k = 0; k < 9; ++k) s += wf[(size_t)k * wf_pitch + c] * t[k];
             dpre0[pix * c1 + c] = s * (Elem<DT>::load(g0 + c) > 0.f ? 1.f : 0.1f);
         }
     }
@@ -550,10 +552,10 @@ size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B) {
     return bwd_layout(ns, lv, B).total;
 }
 
-static ConvSrc bsrc(const void *p, int kind, int C, int pitch, int coff, int hs, int ws, int f32) {
+static ConvSrc bsrc(const void *p, int kind, int C, int pitch, int coff, int hs, int ws, int sdt) {
     ConvSrc s{};
     s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.coff = coff; s.hs = hs; s.ws = ws;
-    s.f32 = f32;
+    s.sdt = sdt;
     return s;
 }
 
@@ -605,7 +607,7 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
     x0.scale0 = (float)ns.f / 256.0f;
     auto T_ = [&](const void *p, int C, int k) { return bsrc(p, SRC_TENSOR, C, C, 0, h[k], wd[k], 0); };
     auto Rz = [&](const void *p, int C, int k) { return bsrc(p, SRC_RESIZE, C, C, 0, h[k], wd[k], 0); };
-    auto Gf = [&](float *p, int C, int pitch, int k) { return bsrc(p, SRC_TENSOR, C, pitch, 0, h[k], wd[k], 1); };
+    auto Gf = [&](float *p, int C, int pitch, int k) { return bsrc(p, SRC_TENSOR, C, pitch, 0, h[k], wd[k], SDT_F32); };
     float *part = F(bl.part);
     float *gl[NLAYERS];
     for (int i = 0; i < NLAYERS; ++i) gl[i] = grad + ns.p_off[i];
@@ -646,9 +648,9 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
         default: return SV_ERR_DTYPE;
         }
         SV_LAUNCH_CHECK("k_final_bwd");
-        // dW_F from X = [G0, x0] and dT (a 1x1 layer with the 9 taps as outputs)
-        SV_TRY(wgrad_layer(dt, 1, 1, T_(G0, c1, 0), x0, B, h[0], wd[0], h[0], wd[0], 9, F(bl.dT), 16,
-                           part, 1, gl[L_F], st));
+        // dW_F from X = [G0, x0] and dT (a 1x1 layer with the 9 taps as outputs), in FP32
+        SV_TRY(wgrad_layer(SV_F32, 1, 1, bsrc(G0, SRC_TENSOR, c1, c1, 0, h[0], wd[0], 1 + dt), x0, B,
+                           h[0], wd[0], h[0], wd[0], 9, F(bl.dT), 16, part, 1, gl[L_F], st));
         // db_F = 256 * sum(dout)
         hipLaunchKernelGGL(k_sum_partial, dim3(SUM_BLOCKS), dim3(256), 0, st, dout,
                            (int64_t)B * H * W, F(bl.sum));
@@ -679,7 +681,7 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
     SV_TRY(launch_resize_adj(dt, F(bl.dcat2), c3 + c2, 0, h[2], wd[2], h[3], wd[3], c3, G3,
                              F(bl.dpre3), B, st));
     // ---- G3 = lrelu(conv1x1(z)) -------------------------------------------------------
-    const ConvSrc zsrc = eps ? T_(Z, L, 3) : bsrc(ML, SRC_TENSOR, L, 2 * L, 0, h[3], wd[3], 1);
+    const ConvSrc zsrc = eps ? T_(Z, L, 3) : bsrc(ML, SRC_TENSOR, L, 2 * L, 0, h[3], wd[3], SDT_F32);
     SV_TRY(wgrad_layer(dt, 1, 1, zsrc, none, B, h[3], wd[3], h[3], wd[3], c3, F(bl.dpre3), c3, part,
                        0, gl[L_G3], st));
     SV_TRY(dgrad(ns, packed, L_G3, Gf(F(bl.dpre3), c3, c3, 3), B, h[3], wd[3], L, F(bl.dz), L,
@@ -701,11 +703,11 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
     // ---- encoder (stride 2): input gradients through the zero-inserted view ------------
     SV_TRY(wgrad_layer(dt, 3, 2, T_(E2, c2, 2), none, B, h[2], wd[2], h[3], wd[3], c3, F(bl.dpreE3),
                        c3, part, 0, gl[L_E3], st));
-    SV_TRY(dgrad(ns, packed, L_E3, bsrc(F(bl.dpreE3), SRC_ZINS, c3, c3, 0, h[3], wd[3], 1), B, h[2],
+    SV_TRY(dgrad(ns, packed, L_E3, bsrc(F(bl.dpreE3), SRC_ZINS, c3, c3, 0, h[3], wd[3], SDT_F32), B, h[2],
                  wd[2], c2, F(bl.dpreE2), c2, F(bl.dcat2), c3 + c2, c3, E2, c2, st));
     SV_TRY(wgrad_layer(dt, 3, 2, T_(E1, c1, 1), none, B, h[1], wd[1], h[2], wd[2], c2, F(bl.dpreE2),
                        c2, part, 0, gl[L_E2], st));
-    SV_TRY(dgrad(ns, packed, L_E2, bsrc(F(bl.dpreE2), SRC_ZINS, c2, c2, 0, h[2], wd[2], 1), B, h[1],
+    SV_TRY(dgrad(ns, packed, L_E2, bsrc(F(bl.dpreE2), SRC_ZINS, c2, c2, 0, h[2], wd[2], SDT_F32), B, h[1],
                  wd[1], c1, F(bl.dpreE1), c1, F(bl.dcat1), c2 + c1, c2, E1, c1, st));
     SV_TRY(wgrad_layer(dt, 3, 2, x0, none, B, h[0], wd[0], h[1], wd[1], c1, F(bl.dpreE1), c1, part,
                        0, gl[L_E1], st));

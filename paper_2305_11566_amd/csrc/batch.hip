@@ -199,9 +199,9 @@ static void fill_geo(const NetShape &ns, int H, int W, PairGeo &g) {
     for (int k = 0; k < 4; ++k) { g.h[k] = lv.h[k]; g.w[k] = lv.w[k]; }
 }
 
-static ConvSrc tsrc(const void *p, int kind, int C, int pitch, int level, int f32) {
+static ConvSrc tsrc(const void *p, int kind, int C, int pitch, int level, int sdt) {
     ConvSrc s{};
-    s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.level = level; s.f32 = f32;
+    s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.level = level; s.sdt = sdt;
     return s;
 }
 
@@ -225,11 +225,11 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
         {tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), none, pl->E2, c2, 0, 1},
         {tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), none, pl->E3, c3, 0, 1},
         {tsrc(pl->E3, SRC_TENSOR, c3, c3, 3, 0), none, pl->ML, 2 * L, 1, 0},
-        {tsrc(pl->ML, SRC_TENSOR, L, 2 * L, 3, 1), none, pl->G3, c3, 0, 1},
+        {tsrc(pl->ML, SRC_TENSOR, L, 2 * L, 3, SDT_F32), none, pl->G3, c3, 0, 1},
         {tsrc(pl->G3, SRC_RESIZE, c3, c3, 3, 0), tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), pl->G2, c2, 0, 1},
         {tsrc(pl->G2, SRC_RESIZE, c2, c2, 2, 0), tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), pl->G1, c1, 0, 1},
         {tsrc(pl->G1, SRC_RESIZE, c1, c1, 1, 0), x0, pl->G0, c1, 0, 1},
-        {tsrc(pl->G0, SRC_TENSOR, c1, c1, 0, 0), x0, pl->T, 12, 1, 0},
+        {tsrc(pl->G0, SRC_TENSOR, c1, c1, 0, 1 + ns.dtype), x0, pl->T, 12, 1, 0},
     };
     for (int k = 0; k < 9; ++k) {
         const LayerRun &run = kRuns[k];
@@ -244,7 +244,8 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
         p.out = ins[k].out; p.out_pitch = ins[k].pitch; p.out_f32 = ins[k].f32; p.act = ins[k].act;
         p.tab = pl->tab_dev; p.stage = run.stage; p.in_level = run.in_level; p.out_level = run.out_level;
         const int ks = li == L_F ? 1 : ns.ly[li].k, stride = li == L_F ? 1 : ns.ly[li].stride;
-        r = launch_conv_tab(ns.dtype, ks, stride, pl->cfg[li], p, pl->grid[run.stage], st);
+        r = launch_conv_tab(li == L_F ? SV_F32 : ns.dtype, ks, stride, pl->cfg[li], p,
+                            pl->grid[run.stage], st);
         if (r != SV_OK) return r;
     }
     return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], pl->T, 12, pl->disp,
@@ -501,6 +502,8 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
             (void)hipEventDestroy(b);
             if (t < best) { best = t; best_ds = splits[k]; }
         }
+        const char *ve = getenv("SV_AUTOTUNE_VERBOSE");
+        const bool verbose = ve && ve[0] == '1';
         // every tile shape for all layers at once; per-layer times from the events
         float best_t[NLAYERS];
         for (int i = 0; i < NLAYERS; ++i) best_t[i] = 1e30f;
@@ -521,6 +524,8 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
                 const int s = stage_of[i];
                 const float t = cnt[s] ? ms[s] / cnt[s] : 1e30f;
                 if (t < best_t[i]) { best_t[i] = t; best_cfg[i] = c; }
+                if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-12s %8.2f us\n",
+                                     ns.dtype, B, H, W, i, conv_cfg_name(c), t * 1e3f);
             }
         }
     }
@@ -535,6 +540,18 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     cache_store(e);
     return SV_OK;
 }
+
+sv_status sv_layer_cfgs(const sv_vae_desc *desc, int B, int H, int W, int *cfg_out) {
+    NetShape ns;
+    sv_status r = net_shape(desc, ns);
+    if (r != SV_OK) return r;
+    if (!cfg_out) return SV_ERR_NULL;
+    if (B < 1 || H < 1 || W < 1) return SV_ERR_SHAPE;
+    net_layer_cfgs(ns, B, H, W, cfg_out);
+    return SV_OK;
+}
+
+const char *sv_conv_cfg_name(int cfg) { return conv_cfg_name(cfg); }
 
 sv_status sv_tile_config(int stage, char *buf, int buflen) {
     if (!buf || buflen < 1) return SV_ERR_NULL;

@@ -67,11 +67,11 @@ __device__ __forceinline__ typename Mfma<DT>::vec pack_vec(const float (&v)[GS])
     return r;
 }
 
-// Reads GS consecutive channels of one pixel of a stored NHWC map into FP32.
-// src_f32: the map is stored as FP32 (the latent), else in the compute dtype.
+// Reads GS consecutive channels of one pixel of a stored NHWC map into FP32;
+// sdt is the map's storage dtype (SV_F32, SV_BF16 or SV_F16).
 template <int DT, int GS>
-__device__ __forceinline__ void load_px(const void *base, size_t off, bool src_f32, float (&v)[GS]) {
-    if (src_f32) {
+__device__ __forceinline__ void load_px(const void *base, size_t off, int sdt, float (&v)[GS]) {
+    if (sdt == SV_F32) {
         const float *p = (const float *)base + off;
 #pragma unroll
         for (int i = 0; i < GS; i += 4) {
@@ -79,10 +79,19 @@ __device__ __forceinline__ void load_px(const void *base, size_t off, bool src_f
             v[i] = q[0]; v[i + 1] = q[1]; v[i + 2] = q[2]; v[i + 3] = q[3];
         }
     } else {
-        const typename Mfma<DT>::T *p = (const typename Mfma<DT>::T *)base + off;
-        typename Mfma<DT>::vec q = *(const typename Mfma<DT>::vec *)p;
+        const uint16_t *p = (const uint16_t *)base + off;
+        uint16_t h[GS];
+        if (GS == 8) {
+            const u16x8 q = *(const u16x8 *)p;
 #pragma unroll
-        for (int i = 0; i < GS; ++i) v[i] = Elem<DT>::load((const typename Mfma<DT>::T *)&q + i);
+            for (int i = 0; i < GS; ++i) h[i] = q[i];
+        } else {
+            const u16x4 q = *(const u16x4 *)p;
+#pragma unroll
+            for (int i = 0; i < GS; ++i) h[i] = q[i];
+        }
+#pragma unroll
+        for (int i = 0; i < GS; ++i) v[i] = sdt == SV_BF16 ? bf16_bits_to_f32(h[i]) : f16_bits_to_f32(h[i]);
     }
 }
 
@@ -154,16 +163,17 @@ struct ConvTile {
                     const int si = c < p.src[0].C ? 0 : 1;
                     const ConvSrc &s = p.src[si];
                     const int cl = c - (si ? p.src[0].C : 0);
-                    const bool sf32 = s.f32 != 0;
+                    const int sdt = s.sdt ? s.sdt - 1 : DT;
+                    const bool raw = sdt == DT;
                     const long long sb = G.sbase[si];
                     const int hs = G.hs[si], ws = G.ws[si];
                     float v[GS];
                     if (s.kind == SRC_TENSOR) {
                         const size_t off = (size_t)(sb + (long long)yi * ws + xi) * s.pitch + s.coff + cl;
-                        if (!sf32) {
+                        if (raw) {
                             out = *(const vec *)((const T *)s.ptr + off);
                         } else {
-                            load_px<DT, GS>(s.ptr, off, true, v);
+                            load_px<DT, GS>(s.ptr, off, sdt, v);
                             out = pack_vec<DT, GS>(v);
                         }
                     } else if (s.kind == SRC_RESIZE) {
@@ -173,10 +183,10 @@ struct ConvTile {
                         bilin(xi, ws, G.Wi, x0, x1, lx);
                         float a00[GS], a01[GS], a10[GS], a11[GS];
                         const size_t cb = (size_t)s.coff + cl;
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sf32, a00);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sf32, a01);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sf32, a10);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sf32, a11);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sdt, a00);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sdt, a01);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sdt, a10);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sdt, a11);
 #pragma unroll
                         for (int i = 0; i < GS; ++i) {
                             const float top = (1.f - lx) * a00[i] + lx * a01[i];
@@ -188,10 +198,10 @@ struct ConvTile {
                         if (((yi | xi) & 1) == 0) {
                             const size_t off =
                                 (size_t)(sb + (long long)(yi >> 1) * ws + (xi >> 1)) * s.pitch + s.coff + cl;
-                            if (!sf32) {
+                            if (raw) {
                                 out = *(const vec *)((const T *)s.ptr + off);
                             } else {
-                                load_px<DT, GS>(s.ptr, off, true, v);
+                                load_px<DT, GS>(s.ptr, off, sdt, v);
                                 out = pack_vec<DT, GS>(v);
                             }
                         }

@@ -68,7 +68,7 @@ struct ConvSrc {
     int hs, ws;          // stored spatial size (RESIZE: the smaller map being resized)
     int level;           // pair-table mode: the level whose sizes and offsets apply
     float scale0;        // X0: factor / 256 applied to the disparity channel
-    int f32;             // TENSOR / RESIZE: stored as FP32 (else in the compute dtype)
+    int sdt;             // TENSOR / RESIZE / ZINS storage: 0 = the compute dtype, else 1 + SV_F32/SV_BF16/SV_F16
 };
 
 struct ConvParams {
@@ -110,6 +110,9 @@ const char *conv_cfg_name(int cfg);
 // output channels, kernel flipped.
 sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad,
                       int mode, void *dst, hipStream_t s);
+
+// storage dtype code of a source (see ConvSrc::sdt)
+constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F16 = 1 + SV_F16;
 
 // ---- network glue ---------------------------------------------------------------
 // out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X))

@@ -277,6 +277,14 @@ def sv_autotune(c1, c2, c3, latent, factor, dtype, B, H, W, D, win_w, win_h):
     check(lib().sv_autotune(ctypes.byref(d), B, H, W, D, win_w, win_h), "sv_autotune")
 
 
+def sv_layer_cfgs(c1, c2, c3, latent, factor, dtype, B, H, W):
+    """Names of the tile configurations the 9 layers use for this shape."""
+    d = make_desc(c1, c2, c3, latent, factor, dtype)
+    out = (ctypes.c_int * 9)()
+    check(lib().sv_layer_cfgs(ctypes.byref(d), B, H, W, out), "sv_layer_cfgs")
+    return [lib().sv_conv_cfg_name(out[i]).decode() for i in range(9)]
+
+
 def sv_tile_config(stage: int) -> str:
     buf = ctypes.create_string_buffer(128)
     check(lib().sv_tile_config(stage, buf, 128), "sv_tile_config")
