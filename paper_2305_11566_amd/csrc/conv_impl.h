@@ -134,12 +134,193 @@ struct ConvTile {
         T wl[TAPS * TN * KCP];
     };
 
+    // per-thread share of a chunk's staging work
+    static constexpr int EP = (PH * PW * KCG + 255) / 256;
+    static constexpr int EW = (TAPS * TN * KCG + 255) / 256;
+
+    // One patch vector as fetched from global memory, before conversion.
+    enum { R_ZERO = 0, R_RAW, R_F32, R_H16, R_RESIZE, R_RESIZE_CVT, R_X0 };
+    struct PRaw {
+        f32x4 r[4];      // one raw vector, 8 FP32 values, or 4 raw resize corners
+        uint16_t h[GS];  // 16-bit values of another storage dtype
+        float ly, lx;    // resize weights; ly = scale of the disparity byte for x0
+        uint32_t b0, b1; // x0: disparity and image bytes
+        int mode, sdt;   // how to commit; storage dtype for conversions
+    };
+
+    static __device__ __forceinline__ f32x4 as_f4(vec x) { return __builtin_bit_cast(f32x4, x); }
+    static __device__ __forceinline__ vec as_vec(f32x4 x) { return __builtin_bit_cast(vec, x); }
+
+    // Issues the global loads of chunk c0 (no use of the loaded values here).
+    static __device__ __forceinline__ void fetch(const ConvParams &p, const ConvGeo &G, int c0,
+                                                 PRaw (&pr)[EP], vec (&wr)[EW]) {
+        const int tid = threadIdx.x;
+        const int iy0 = G.oy0 * S - PAD, ix0 = G.ox0 * S - PAD;
+#pragma unroll
+        for (int k = 0; k < EP; ++k) {
+            const int e = tid + k * 256;
+            PRaw &R = pr[k];
+            R.mode = R_ZERO;
+            if (e >= PH * PW * KCG) continue;
+            const int cg = e % KCG, pix = e / KCG;
+            const int py = pix / PW, px = pix - py * PW;
+            const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
+            if (!(yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin)) continue;
+            const int si = c < p.src[0].C ? 0 : 1;
+            const ConvSrc &s = p.src[si];
+            const int cl = c - (si ? p.src[0].C : 0);
+            const int sdt = s.sdt ? s.sdt - 1 : DT;
+            const long long sb = G.sbase[si];
+            const int hs = G.hs[si], ws = G.ws[si];
+            R.sdt = sdt;
+            if (s.kind == SRC_TENSOR || s.kind == SRC_ZINS) {
+                int yy = yi, xx = xi;
+                if (s.kind == SRC_ZINS) {
+                    if ((yi | xi) & 1) continue;
+                    yy = yi >> 1;
+                    xx = xi >> 1;
+                }
+                const size_t off = (size_t)(sb + (long long)yy * ws + xx) * s.pitch + s.coff + cl;
+                if (sdt == DT) {
+                    R.r[0] = as_f4(*(const vec *)((const T *)s.ptr + off));
+                    R.mode = R_RAW;
+                } else if (sdt == SV_F32) {
+                    const float *q = (const float *)s.ptr + off;
+                    R.r[0] = *(const f32x4 *)q;
+                    if (GS == 8) R.r[1] = *(const f32x4 *)(q + 4);
+                    R.mode = R_F32;
+                } else {  // 16-bit storage of another dtype
+                    const uint16_t *q = (const uint16_t *)s.ptr + off;
+                    if (GS == 8) {
+                        const u16x8 hv = *(const u16x8 *)q;
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) R.h[i] = hv[i];
+                    } else {
+                        const u16x4 hv = *(const u16x4 *)q;
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) R.h[i] = hv[i];
+                    }
+                    R.mode = R_H16;
+                }
+            } else if (s.kind == SRC_RESIZE) {
+                int y0, y1, x0, x1;
+                bilin(yi, hs, G.Hi, y0, y1, R.ly);
+                bilin(xi, ws, G.Wi, x0, x1, R.lx);
+                const size_t cb = (size_t)s.coff + cl;
+                const size_t o[4] = {(size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb,
+                                     (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb,
+                                     (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb,
+                                     (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb};
+                if (sdt == DT) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) R.r[j] = as_f4(*(const vec *)((const T *)s.ptr + o[j]));
+                    R.mode = R_RESIZE;
+                } else {  // other storage: interpolate now (not on the network's path)
+                    float a[4][GS], v[GS];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) load_px<DT, GS>(s.ptr, o[j], sdt, a[j]);
+#pragma unroll
+                    for (int i = 0; i < GS; ++i) {
+                        const float top = (1.f - R.lx) * a[0][i] + R.lx * a[1][i];
+                        const float bot = (1.f - R.lx) * a[2][i] + R.lx * a[3][i];
+                        v[i] = (1.f - R.ly) * top + R.ly * bot;
+                    }
+                    R.r[0] = as_f4(pack_vec<DT, GS>(v));
+                    R.mode = R_RESIZE_CVT;
+                }
+            } else {  // SRC_X0: the two bytes, converted at commit
+                const size_t o = (size_t)(sb + (long long)yi * ws + xi);
+                R.ly = s.scale0;
+                R.b0 = ((const uint8_t *)s.ptr)[o];
+                R.b1 = s.img[o];
+                R.mode = R_X0;
+            }
+        }
+        const T *wpk = (const T *)p.wpk;
+#pragma unroll
+        for (int k = 0; k < EW; ++k) {
+            const int e = tid + k * 256;
+#pragma unroll
+            for (int i = 0; i < GS; ++i) wr[k][i] = 0;
+            if (e >= TAPS * TN * KCG) continue;
+            const int cg = e % KCG, r = e / KCG;
+            const int n = r % TN, tap = r / TN;
+            const int c = c0 + cg * GS, ng = G.n0 + n;
+            if (ng < p.n_pad && c < p.cin_pad)
+                wr[k] = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
+        }
+    }
+
+    // Converts the fetched values and writes them to LDS.
+    static __device__ __forceinline__ void commit(const PRaw (&pr)[EP], const vec (&wr)[EW], T *patch,
+                                                  T *wl) {
+        const int tid = threadIdx.x;
+#pragma unroll
+        for (int k = 0; k < EP; ++k) {
+            const int e = tid + k * 256;
+            if (e >= PH * PW * KCG) continue;
+            const PRaw &R = pr[k];
+            const int cg = e % KCG, pix = e / KCG;
+            vec out;
+            float v[GS];
+            switch (R.mode) {
+            case R_RAW:
+            case R_RESIZE_CVT:
+                out = as_vec(R.r[0]);
+                break;
+            case R_F32:
+#pragma unroll
+                for (int i = 0; i < GS; ++i) v[i] = i < 4 ? R.r[0][i] : R.r[1][i - 4];
+                out = pack_vec<DT, GS>(v);
+                break;
+            case R_H16:
+#pragma unroll
+                for (int i = 0; i < GS; ++i)
+                    v[i] = R.sdt == SV_BF16 ? bf16_bits_to_f32(R.h[i]) : f16_bits_to_f32(R.h[i]);
+                out = pack_vec<DT, GS>(v);
+                break;
+            case R_RESIZE: {
+                const vec a00 = as_vec(R.r[0]), a01 = as_vec(R.r[1]), a10 = as_vec(R.r[2]),
+                          a11 = as_vec(R.r[3]);
+#pragma unroll
+                for (int i = 0; i < GS; ++i) {
+                    const float top = (1.f - R.lx) * Elem<DT>::load((const T *)&a00 + i) +
+                                      R.lx * Elem<DT>::load((const T *)&a01 + i);
+                    const float bot = (1.f - R.lx) * Elem<DT>::load((const T *)&a10 + i) +
+                                      R.lx * Elem<DT>::load((const T *)&a11 + i);
+                    v[i] = (1.f - R.ly) * top + R.ly * bot;
+                }
+                out = pack_vec<DT, GS>(v);
+                break;
+            }
+            case R_X0:
+#pragma unroll
+                for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                v[0] = R.ly * (float)R.b0;
+                v[1] = (float)R.b1 * (1.0f / 256.0f);
+                out = pack_vec<DT, GS>(v);
+                break;
+            default:
+#pragma unroll
+                for (int i = 0; i < GS; ++i) out[i] = 0;
+            }
+            *(vec *)&patch[pix * KCP + cg * GS] = out;
+        }
+#pragma unroll
+        for (int k = 0; k < EW; ++k) {
+            const int e = tid + k * 256;
+            if (e >= TAPS * TN * KCG) continue;
+            const int cg = e % KCG, r = e / KCG;
+            const int n = r % TN, tap = r / TN;
+            *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = wr[k];
+        }
+    }
+
     static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm) {
         T *patch = sm.patch, *wl = sm.wl;
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int wm = wave % WM, wn = wave / WM;
         const int n0 = G.n0, ox0 = G.ox0, oy0 = G.oy0;
-        const int iy0 = oy0 * S - PAD, ix0 = ox0 * S - PAD;
         const int g = lane >> 4, r16 = lane & 15;
 
         f32x4 acc[MBW][NBW];
@@ -148,87 +329,17 @@ struct ConvTile {
 #pragma unroll
             for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-        const T *wpk = (const T *)p.wpk;
+        // Software pipeline over channel chunks: the global loads of chunk c+1
+        // are issued into registers (fetch) before the MFMAs of chunk c; they
+        // are converted / interpolated and written to LDS (commit) only after.
+        PRaw pr[EP];
+        vec wr[EW];
+        fetch(p, G, 0, pr, wr);
         for (int c0 = 0; c0 < p.Cin; c0 += KC) {
+            __syncthreads();  // the previous chunk's MFMAs are done with LDS
+            commit(pr, wr, patch, wl);
             __syncthreads();
-            // ---- input patch ------------------------------------------------------
-            for (int e = tid; e < PH * PW * KCG; e += 256) {
-                const int cg = e % KCG, pix = e / KCG;
-                const int py = pix / PW, px = pix - py * PW;
-                const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
-                vec out;
-#pragma unroll
-                for (int i = 0; i < GS; ++i) out[i] = 0;
-                if (yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin) {
-                    const int si = c < p.src[0].C ? 0 : 1;
-                    const ConvSrc &s = p.src[si];
-                    const int cl = c - (si ? p.src[0].C : 0);
-                    const int sdt = s.sdt ? s.sdt - 1 : DT;
-                    const bool raw = sdt == DT;
-                    const long long sb = G.sbase[si];
-                    const int hs = G.hs[si], ws = G.ws[si];
-                    float v[GS];
-                    if (s.kind == SRC_TENSOR) {
-                        const size_t off = (size_t)(sb + (long long)yi * ws + xi) * s.pitch + s.coff + cl;
-                        if (raw) {
-                            out = *(const vec *)((const T *)s.ptr + off);
-                        } else {
-                            load_px<DT, GS>(s.ptr, off, sdt, v);
-                            out = pack_vec<DT, GS>(v);
-                        }
-                    } else if (s.kind == SRC_RESIZE) {
-                        int y0, y1, x0, x1;
-                        float ly, lx;
-                        bilin(yi, hs, G.Hi, y0, y1, ly);
-                        bilin(xi, ws, G.Wi, x0, x1, lx);
-                        float a00[GS], a01[GS], a10[GS], a11[GS];
-                        const size_t cb = (size_t)s.coff + cl;
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sdt, a00);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sdt, a01);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sdt, a10);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sdt, a11);
-#pragma unroll
-                        for (int i = 0; i < GS; ++i) {
-                            const float top = (1.f - lx) * a00[i] + lx * a01[i];
-                            const float bot = (1.f - lx) * a10[i] + lx * a11[i];
-                            v[i] = (1.f - ly) * top + ly * bot;
-                        }
-                        out = pack_vec<DT, GS>(v);
-                    } else if (s.kind == SRC_ZINS) {
-                        if (((yi | xi) & 1) == 0) {
-                            const size_t off =
-                                (size_t)(sb + (long long)(yi >> 1) * ws + (xi >> 1)) * s.pitch + s.coff + cl;
-                            if (raw) {
-                                out = *(const vec *)((const T *)s.ptr + off);
-                            } else {
-                                load_px<DT, GS>(s.ptr, off, sdt, v);
-                                out = pack_vec<DT, GS>(v);
-                            }
-                        }
-                    } else {  // SRC_X0: [f*d/256, I/256]
-                        const size_t o = (size_t)(sb + (long long)yi * ws + xi);
-#pragma unroll
-                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                        v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[o];
-                        v[1] = (float)s.img[o] * (1.0f / 256.0f);
-                        out = pack_vec<DT, GS>(v);
-                    }
-                }
-                *(vec *)&patch[(py * PW + px) * KCP + cg * GS] = out;
-            }
-            // ---- weights ------------------------------------------------------------
-            for (int e = tid; e < TAPS * TN * KCG; e += 256) {
-                const int cg = e % KCG, r = e / KCG;
-                const int n = r % TN, tap = r / TN;
-                const int c = c0 + cg * GS, ng = n0 + n;
-                vec val;
-#pragma unroll
-                for (int i = 0; i < GS; ++i) val[i] = 0;
-                if (ng < p.n_pad && c < p.cin_pad)
-                    val = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
-                *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
-            }
-            __syncthreads();
+            if (c0 + KC < p.Cin) fetch(p, G, c0 + KC, pr, wr);
             // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
             for (int sub = 0; sub < KCM; ++sub) {
             if (c0 + sub * KCB >= p.Cin) break;
