@@ -5,19 +5,25 @@
 #include "kernels.h"
 
 // The tile configurations: (index, TH rows, TN output channels, WM waves along
-// rows, KCM base channel chunks staged at once, name).
-#define SV_CONV_CFGS(X)                    \
-    X(0, 4, 64, 4, 1, "th4_tn64")          \
-    X(1, 8, 64, 4, 1, "th8_tn64")          \
-    X(2, 4, 32, 4, 1, "th4_tn32")          \
-    X(3, 8, 32, 4, 1, "th8_tn32")          \
-    X(4, 2, 64, 2, 1, "th2_tn64")          \
-    X(5, 4, 16, 4, 1, "th4_tn16")          \
-    X(6, 4, 16, 4, 4, "th4_tn16_k4")       \
-    X(7, 4, 32, 4, 2, "th4_tn32_k2")       \
-    X(8, 4, 16, 4, 2, "th4_tn16_k2")       \
-    X(9, 8, 16, 4, 2, "th8_tn16_k2")       \
-    X(10, 4, 64, 4, 2, "th4_tn64_k2")
+// rows, KCM base channel chunks staged at once, FB batched staging, name).
+#define SV_CONV_CFGS(X)                          \
+    X(0, 4, 64, 4, 1, 0, "th4_tn64")             \
+    X(1, 8, 64, 4, 1, 0, "th8_tn64")             \
+    X(2, 4, 32, 4, 1, 0, "th4_tn32")             \
+    X(3, 8, 32, 4, 1, 0, "th8_tn32")             \
+    X(4, 2, 64, 2, 1, 0, "th2_tn64")             \
+    X(5, 4, 16, 4, 1, 0, "th4_tn16")             \
+    X(6, 4, 16, 4, 4, 0, "th4_tn16_k4")          \
+    X(7, 4, 32, 4, 2, 0, "th4_tn32_k2")          \
+    X(8, 4, 16, 4, 2, 0, "th4_tn16_k2")          \
+    X(9, 8, 16, 4, 2, 0, "th8_tn16_k2")          \
+    X(10, 4, 64, 4, 2, 0, "th4_tn64_k2")         \
+    X(11, 4, 16, 4, 1, 1, "th4_tn16_b")          \
+    X(12, 4, 16, 4, 2, 1, "th4_tn16_k2_b")       \
+    X(13, 4, 16, 4, 4, 1, "th4_tn16_k4_b")       \
+    X(14, 4, 32, 4, 1, 1, "th4_tn32_b")          \
+    X(15, 4, 64, 4, 1, 1, "th4_tn64_b")          \
+    X(16, 2, 64, 2, 1, 1, "th2_tn64_b")
 
 namespace sv {
 
@@ -105,7 +111,7 @@ struct ConvGeo {
     int n0, oy0, ox0;
 };
 
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
 struct ConvTile {
     using M = Mfma<DT>;
     using T = typename M::T;
@@ -140,13 +146,16 @@ struct ConvTile {
 
     // One patch vector as fetched from global memory, before conversion.
     enum { R_ZERO = 0, R_RAW, R_F32, R_H16, R_RESIZE, R_RESIZE_CVT, R_X0 };
+    // r holds raw bits only (moved, never used in arithmetic before commit):
+    // one vector of the compute dtype, 8 FP32 values, 4 resize corners, GS
+    // 16-bit values of another dtype, or the two x0 bytes.
     struct PRaw {
-        f32x4 r[4];      // one raw vector, 8 FP32 values, or 4 raw resize corners
-        uint16_t h[GS];  // 16-bit values of another storage dtype
+        f32x4 r[4];
         float ly, lx;    // resize weights; ly = scale of the disparity byte for x0
-        uint32_t b0, b1; // x0: disparity and image bytes
         int mode, sdt;   // how to commit; storage dtype for conversions
     };
+    static __device__ __forceinline__ float ubits(uint32_t u) { return __builtin_bit_cast(float, u); }
+    static __device__ __forceinline__ uint32_t fbits(float f) { return __builtin_bit_cast(uint32_t, f); }
 
     static __device__ __forceinline__ f32x4 as_f4(vec x) { return __builtin_bit_cast(f32x4, x); }
     static __device__ __forceinline__ vec as_vec(f32x4 x) { return __builtin_bit_cast(vec, x); }
@@ -192,13 +201,11 @@ struct ConvTile {
                 } else {  // 16-bit storage of another dtype
                     const uint16_t *q = (const uint16_t *)s.ptr + off;
                     if (GS == 8) {
-                        const u16x8 hv = *(const u16x8 *)q;
-#pragma unroll
-                        for (int i = 0; i < GS; ++i) R.h[i] = hv[i];
+                        R.r[0] = __builtin_bit_cast(f32x4, *(const u16x8 *)q);
                     } else {
                         const u16x4 hv = *(const u16x4 *)q;
-#pragma unroll
-                        for (int i = 0; i < GS; ++i) R.h[i] = hv[i];
+                        R.r[0][0] = ubits((uint32_t)hv[0] | ((uint32_t)hv[1] << 16));
+                        R.r[0][1] = ubits((uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
                     }
                     R.mode = R_H16;
                 }
@@ -231,8 +238,8 @@ struct ConvTile {
             } else {  // SRC_X0: the two bytes, converted at commit
                 const size_t o = (size_t)(sb + (long long)yi * ws + xi);
                 R.ly = s.scale0;
-                R.b0 = ((const uint8_t *)s.ptr)[o];
-                R.b1 = s.img[o];
+                R.r[0][0] = ubits(((const uint8_t *)s.ptr)[o]);
+                R.r[0][1] = ubits(s.img[o]);
                 R.mode = R_X0;
             }
         }
@@ -275,8 +282,10 @@ struct ConvTile {
                 break;
             case R_H16:
 #pragma unroll
-                for (int i = 0; i < GS; ++i)
-                    v[i] = R.sdt == SV_BF16 ? bf16_bits_to_f32(R.h[i]) : f16_bits_to_f32(R.h[i]);
+                for (int i = 0; i < GS; ++i) {
+                    const uint16_t h = (uint16_t)(fbits(R.r[0][i >> 1]) >> (16 * (i & 1)));
+                    v[i] = R.sdt == SV_BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
+                }
                 out = pack_vec<DT, GS>(v);
                 break;
             case R_RESIZE: {
@@ -296,8 +305,8 @@ struct ConvTile {
             case R_X0:
 #pragma unroll
                 for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                v[0] = R.ly * (float)R.b0;
-                v[1] = (float)R.b1 * (1.0f / 256.0f);
+                v[0] = R.ly * (float)fbits(R.r[0][0]);
+                v[1] = (float)fbits(R.r[0][1]) * (1.0f / 256.0f);
                 out = pack_vec<DT, GS>(v);
                 break;
             default:
@@ -321,6 +330,7 @@ struct ConvTile {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int wm = wave % WM, wn = wave / WM;
         const int n0 = G.n0, ox0 = G.ox0, oy0 = G.oy0;
+        const int iy0 = oy0 * S - PAD, ix0 = ox0 * S - PAD;
         const int g = lane >> 4, r16 = lane & 15;
 
         f32x4 acc[MBW][NBW];
@@ -329,20 +339,106 @@ struct ConvTile {
 #pragma unroll
             for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-        // Software pipeline over channel chunks: the global loads of chunk c+1
-        // are issued into registers (fetch) before the MFMAs of chunk c; they
-        // are converted / interpolated and written to LDS (commit) only after.
-        PRaw pr[EP];
-        vec wr[EW];
-        fetch(p, G, 0, pr, wr);
+        const T *wpk = (const T *)p.wpk;
         for (int c0 = 0; c0 < p.Cin; c0 += KC) {
+          if constexpr (FB) {
+            // batched staging: every global load of the chunk is issued first,
+            // then converted / interpolated and written to LDS
+            PRaw pr[EP];
+            vec wr[EW];
+            fetch(p, G, c0, pr, wr);
             __syncthreads();  // the previous chunk's MFMAs are done with LDS
             commit(pr, wr, patch, wl);
             __syncthreads();
-            if (c0 + KC < p.Cin) fetch(p, G, c0 + KC, pr, wr);
+          } else {
+            // serial staging: one element at a time (fewest registers)
+            __syncthreads();
+            // ---- input patch ------------------------------------------------------
+            for (int e = tid; e < PH * PW * KCG; e += 256) {
+                const int cg = e % KCG, pix = e / KCG;
+                const int py = pix / PW, px = pix - py * PW;
+                const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
+                vec out;
+#pragma unroll
+                for (int i = 0; i < GS; ++i) out[i] = 0;
+                if (yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin) {
+                    const int si = c < p.src[0].C ? 0 : 1;
+                    const ConvSrc &s = p.src[si];
+                    const int cl = c - (si ? p.src[0].C : 0);
+                    const int sdt = s.sdt ? s.sdt - 1 : DT;
+                    const bool raw = sdt == DT;
+                    const long long sb = G.sbase[si];
+                    const int hs = G.hs[si], ws = G.ws[si];
+                    float v[GS];
+                    if (s.kind == SRC_TENSOR) {
+                        const size_t off = (size_t)(sb + (long long)yi * ws + xi) * s.pitch + s.coff + cl;
+                        if (raw) {
+                            out = *(const vec *)((const T *)s.ptr + off);
+                        } else {
+                            load_px<DT, GS>(s.ptr, off, sdt, v);
+                            out = pack_vec<DT, GS>(v);
+                        }
+                    } else if (s.kind == SRC_RESIZE) {
+                        int y0, y1, x0, x1;
+                        float ly, lx;
+                        bilin(yi, hs, G.Hi, y0, y1, ly);
+                        bilin(xi, ws, G.Wi, x0, x1, lx);
+                        float a00[GS], a01[GS], a10[GS], a11[GS];
+                        const size_t cb = (size_t)s.coff + cl;
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sdt, a00);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sdt, a01);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sdt, a10);
+                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sdt, a11);
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) {
+                            const float top = (1.f - lx) * a00[i] + lx * a01[i];
+                            const float bot = (1.f - lx) * a10[i] + lx * a11[i];
+                            v[i] = (1.f - ly) * top + ly * bot;
+                        }
+                        out = pack_vec<DT, GS>(v);
+                    } else if (s.kind == SRC_ZINS) {
+                        if (((yi | xi) & 1) == 0) {
+                            const size_t off =
+                                (size_t)(sb + (long long)(yi >> 1) * ws + (xi >> 1)) * s.pitch + s.coff + cl;
+                            if (raw) {
+                                out = *(const vec *)((const T *)s.ptr + off);
+                            } else {
+                                load_px<DT, GS>(s.ptr, off, sdt, v);
+                                out = pack_vec<DT, GS>(v);
+                            }
+                        }
+                    } else {  // SRC_X0: [f*d/256, I/256]
+                        const size_t o = (size_t)(sb + (long long)yi * ws + xi);
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[o];
+                        v[1] = (float)s.img[o] * (1.0f / 256.0f);
+                        out = pack_vec<DT, GS>(v);
+                    }
+                }
+                *(vec *)&patch[(py * PW + px) * KCP + cg * GS] = out;
+            }
+            // ---- weights ------------------------------------------------------------
+            for (int e = tid; e < TAPS * TN * KCG; e += 256) {
+                const int cg = e % KCG, r = e / KCG;
+                const int n = r % TN, tap = r / TN;
+                const int c = c0 + cg * GS, ng = n0 + n;
+                vec val;
+#pragma unroll
+                for (int i = 0; i < GS; ++i) val[i] = 0;
+                if (ng < p.n_pad && c < p.cin_pad)
+                    val = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
+                *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
+            }
+            __syncthreads();
+          }
             // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
+#pragma unroll
             for (int sub = 0; sub < KCM; ++sub) {
             if (c0 + sub * KCB >= p.Cin) break;
+            // unrolled so the LDS operand loads of later steps are issued ahead
+            // of the MFMAs of earlier ones
+#pragma unroll
             for (int st = 0; st < NSTEP; ++st) {
                 const int q = st * 4 + g;
                 const bool valid = q < TAPS * KCGB;
@@ -425,10 +521,10 @@ struct ConvTile {
 };
 
 // Uniform batch: one workgroup per (column tile, row tile, image x channel tile).
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
 __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
 {
-    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM, FB>;
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const int ntn = (p.Cout + TN - 1) / TN;
     const int b = blockIdx.z / ntn;
@@ -447,10 +543,10 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
 }
 
 // Pair table: persistent loop over the stage's tiles of every pair.
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
 __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 {
-    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM, FB>;
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const PairTable *tab = p.tab;
     const int n = tab->n;
@@ -482,15 +578,15 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 }
 
 // grid <= 0: uniform launch; grid > 0: persistent launch over p.tab.
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
 static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     if (pgrid > 0) {
-        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM>), dim3(pgrid), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM, FB>), dim3(pgrid), dim3(256), 0, st, p);
         SV_LAUNCH_CHECK("k_conv_tab");
         return SV_OK;
     }
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), p.B * cdiv(p.Cout, TN));
-    hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM, FB>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
     return SV_OK;
 }
@@ -498,8 +594,8 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
 template <int DT, int KS, int S>
 static sv_status launch_cfg(int cfg, const ConvParams &p, int pg, hipStream_t st) {
     switch (cfg) {
-#define SV_CFG(i, TH, TN, WM, KCM, name) \
-    case i: return launch_one<DT, KS, S, TH, TN, WM, KCM>(p, pg, st);
+#define SV_CFG(i, TH, TN, WM, KCM, FB, name) \
+    case i: return launch_one<DT, KS, S, TH, TN, WM, KCM, FB>(p, pg, st);
         SV_CONV_CFGS(SV_CFG)
 #undef SV_CFG
     default: return SV_ERR_RANGE;
