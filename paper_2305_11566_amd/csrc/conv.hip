@@ -29,9 +29,9 @@
 namespace sv {
 
 // ---- tile configurations ---------------------------------------------------------
-struct CfgDesc { int TH, TN, WM, KCM, FB; const char *name; };
+struct CfgDesc { int TH, TN, WM, KCM; const char *name; };
 static const CfgDesc kCfgs[] = {
-#define SV_CFG(i, TH, TN, WM, KCM, FB, name) {TH, TN, WM, KCM, FB, name},
+#define SV_CFG(i, TH, TN, WM, KCM, name) {TH, TN, WM, KCM, name},
     SV_CONV_CFGS(SV_CFG)
 #undef SV_CFG
 };

@@ -5,25 +5,21 @@
 #include "kernels.h"
 
 // The tile configurations: (index, TH rows, TN output channels, WM waves along
-// rows, KCM base channel chunks staged at once, FB batched staging, name).
-#define SV_CONV_CFGS(X)                          \
-    X(0, 4, 64, 4, 1, 0, "th4_tn64")             \
-    X(1, 8, 64, 4, 1, 0, "th8_tn64")             \
-    X(2, 4, 32, 4, 1, 0, "th4_tn32")             \
-    X(3, 8, 32, 4, 1, 0, "th8_tn32")             \
-    X(4, 2, 64, 2, 1, 0, "th2_tn64")             \
-    X(5, 4, 16, 4, 1, 0, "th4_tn16")             \
-    X(6, 4, 16, 4, 4, 0, "th4_tn16_k4")          \
-    X(7, 4, 32, 4, 2, 0, "th4_tn32_k2")          \
-    X(8, 4, 16, 4, 2, 0, "th4_tn16_k2")          \
-    X(9, 8, 16, 4, 2, 0, "th8_tn16_k2")          \
-    X(10, 4, 64, 4, 2, 0, "th4_tn64_k2")         \
-    X(11, 4, 16, 4, 1, 1, "th4_tn16_b")          \
-    X(12, 4, 16, 4, 2, 1, "th4_tn16_k2_b")       \
-    X(13, 4, 16, 4, 4, 1, "th4_tn16_k4_b")       \
-    X(14, 4, 32, 4, 1, 1, "th4_tn32_b")          \
-    X(15, 4, 64, 4, 1, 1, "th4_tn64_b")          \
-    X(16, 2, 64, 2, 1, 1, "th2_tn64_b")
+// rows, KCM base channel chunks staged at once, name).
+#define SV_CONV_CFGS(X)                    \
+    X(0, 4, 64, 4, 1, "th4_tn64")          \
+    X(1, 8, 64, 4, 1, "th8_tn64")          \
+    X(2, 4, 32, 4, 1, "th4_tn32")          \
+    X(3, 8, 32, 4, 1, "th8_tn32")          \
+    X(4, 2, 64, 2, 1, "th2_tn64")          \
+    X(5, 4, 16, 4, 1, "th4_tn16")          \
+    X(6, 4, 16, 4, 4, "th4_tn16_k4")       \
+    X(7, 4, 32, 4, 2, "th4_tn32_k2")       \
+    X(8, 4, 16, 4, 2, "th4_tn16_k2")       \
+    X(9, 8, 16, 4, 2, "th8_tn16_k2")       \
+    X(10, 4, 64, 4, 2, "th4_tn64_k2")      \
+    X(11, 2, 32, 2, 2, "th2_tn32_k2")      \
+    X(12, 2, 64, 2, 2, "th2_tn64_k2")
 
 namespace sv {
 
@@ -111,7 +107,7 @@ struct ConvGeo {
     int n0, oy0, ox0;
 };
 
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 struct ConvTile {
     using M = Mfma<DT>;
     using T = typename M::T;
@@ -121,9 +117,10 @@ struct ConvTile {
     static constexpr int TAPS = KS * KS;
     static constexpr int PAD = (KS - 1) / 2;
     static constexpr int PH = (TH - 1) * S + KS, PW = (TW - 1) * S + KS;
+    static constexpr int NPIX = PH * PW;
     // The reduction runs over base chunks of KCB channels in a fixed order; a
-    // tile stages KCM base chunks at once (fewer round trips to memory) but
-    // consumes them in the same order, so results do not depend on KCM.
+    // tile stages KCM base chunks at once but consumes them in the same order,
+    // so results do not depend on KCM.
     static constexpr int KCB = DT == SV_F32 ? 16 : 32;
     static constexpr int KC = KCB * KCM;
     static constexpr int KCG = KC / GS;
@@ -135,193 +132,49 @@ struct ConvTile {
     static constexpr int NSTEP = (TAPS * KCGB + 3) / 4;
     static_assert(TH % WM == 0 && (TN / 16) % WN == 0 && KC % GS == 0, "tile");
 
+    // Where a patch pixel reads each source: pixel indices (p[0] < 0: zero
+    // padding) of the pixel, or of the four bilinear corners and their weights.
+    struct PixSrc {
+        int p[4];
+        float ly, lx;
+    };
+
     struct Smem {
-        T patch[PH * PW * KCP];
+        T patch[NPIX * KCP];
         T wl[TAPS * TN * KCP];
+        PixSrc ps[2][NPIX];
     };
+    static_assert(sizeof(Smem) <= 160 * 1024, "LDS per workgroup");
 
-    // per-thread share of a chunk's staging work
-    static constexpr int EP = (PH * PW * KCG + 255) / 256;
-    static constexpr int EW = (TAPS * TN * KCG + 255) / 256;
-
-    // One patch vector as fetched from global memory, before conversion.
-    enum { R_ZERO = 0, R_RAW, R_F32, R_H16, R_RESIZE, R_RESIZE_CVT, R_X0 };
-    // r holds raw bits only (moved, never used in arithmetic before commit):
-    // one vector of the compute dtype, 8 FP32 values, 4 resize corners, GS
-    // 16-bit values of another dtype, or the two x0 bytes.
-    struct PRaw {
-        f32x4 r[4];
-        float ly, lx;    // resize weights; ly = scale of the disparity byte for x0
-        int mode, sdt;   // how to commit; storage dtype for conversions
-    };
-    static __device__ __forceinline__ float ubits(uint32_t u) { return __builtin_bit_cast(float, u); }
-    static __device__ __forceinline__ uint32_t fbits(float f) { return __builtin_bit_cast(uint32_t, f); }
-
-    static __device__ __forceinline__ f32x4 as_f4(vec x) { return __builtin_bit_cast(f32x4, x); }
-    static __device__ __forceinline__ vec as_vec(f32x4 x) { return __builtin_bit_cast(vec, x); }
-
-    // Issues the global loads of chunk c0 (no use of the loaded values here).
-    static __device__ __forceinline__ void fetch(const ConvParams &p, const ConvGeo &G, int c0,
-                                                 PRaw (&pr)[EP], vec (&wr)[EW]) {
-        const int tid = threadIdx.x;
+    // Computed once per tile; every channel chunk reuses it.
+    static __device__ __forceinline__ void pix_table(const ConvParams &p, const ConvGeo &G, Smem &sm) {
         const int iy0 = G.oy0 * S - PAD, ix0 = G.ox0 * S - PAD;
-#pragma unroll
-        for (int k = 0; k < EP; ++k) {
-            const int e = tid + k * 256;
-            PRaw &R = pr[k];
-            R.mode = R_ZERO;
-            if (e >= PH * PW * KCG) continue;
-            const int cg = e % KCG, pix = e / KCG;
+        for (int e = threadIdx.x; e < 2 * NPIX; e += 256) {
+            const int si = e >= NPIX ? 1 : 0, pix = e - si * NPIX;
             const int py = pix / PW, px = pix - py * PW;
-            const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
-            if (!(yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin)) continue;
-            const int si = c < p.src[0].C ? 0 : 1;
-            const ConvSrc &s = p.src[si];
-            const int cl = c - (si ? p.src[0].C : 0);
-            const int sdt = s.sdt ? s.sdt - 1 : DT;
-            const long long sb = G.sbase[si];
-            const int hs = G.hs[si], ws = G.ws[si];
-            R.sdt = sdt;
-            if (s.kind == SRC_TENSOR || s.kind == SRC_ZINS) {
-                int yy = yi, xx = xi;
-                if (s.kind == SRC_ZINS) {
-                    if ((yi | xi) & 1) continue;
-                    yy = yi >> 1;
-                    xx = xi >> 1;
+            const int yi = iy0 + py, xi = ix0 + px;
+            const int kind = si ? p.src[1].kind : p.src[0].kind;
+            PixSrc q;
+            q.p[0] = q.p[1] = q.p[2] = q.p[3] = -1;
+            q.ly = q.lx = 0.f;
+            if (kind != SRC_NONE && yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi) {
+                const long long sb = si ? G.sbase[1] : G.sbase[0];
+                const int hs = si ? G.hs[1] : G.hs[0], ws = si ? G.ws[1] : G.ws[0];
+                if (kind == SRC_RESIZE) {
+                    int y0, y1, x0, x1;
+                    bilin(yi, hs, G.Hi, y0, y1, q.ly);
+                    bilin(xi, ws, G.Wi, x0, x1, q.lx);
+                    q.p[0] = (int)(sb + (long long)y0 * ws + x0);
+                    q.p[1] = (int)(sb + (long long)y0 * ws + x1);
+                    q.p[2] = (int)(sb + (long long)y1 * ws + x0);
+                    q.p[3] = (int)(sb + (long long)y1 * ws + x1);
+                } else if (kind == SRC_ZINS) {
+                    if (((yi | xi) & 1) == 0) q.p[0] = (int)(sb + (long long)(yi >> 1) * ws + (xi >> 1));
+                } else {
+                    q.p[0] = (int)(sb + (long long)yi * ws + xi);
                 }
-                const size_t off = (size_t)(sb + (long long)yy * ws + xx) * s.pitch + s.coff + cl;
-                if (sdt == DT) {
-                    R.r[0] = as_f4(*(const vec *)((const T *)s.ptr + off));
-                    R.mode = R_RAW;
-                } else if (sdt == SV_F32) {
-                    const float *q = (const float *)s.ptr + off;
-                    R.r[0] = *(const f32x4 *)q;
-                    if (GS == 8) R.r[1] = *(const f32x4 *)(q + 4);
-                    R.mode = R_F32;
-                } else {  // 16-bit storage of another dtype
-                    const uint16_t *q = (const uint16_t *)s.ptr + off;
-                    if (GS == 8) {
-                        R.r[0] = __builtin_bit_cast(f32x4, *(const u16x8 *)q);
-                    } else {
-                        const u16x4 hv = *(const u16x4 *)q;
-                        R.r[0][0] = ubits((uint32_t)hv[0] | ((uint32_t)hv[1] << 16));
-                        R.r[0][1] = ubits((uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
-                    }
-                    R.mode = R_H16;
-                }
-            } else if (s.kind == SRC_RESIZE) {
-                int y0, y1, x0, x1;
-                bilin(yi, hs, G.Hi, y0, y1, R.ly);
-                bilin(xi, ws, G.Wi, x0, x1, R.lx);
-                const size_t cb = (size_t)s.coff + cl;
-                const size_t o[4] = {(size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb,
-                                     (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb,
-                                     (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb,
-                                     (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb};
-                if (sdt == DT) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) R.r[j] = as_f4(*(const vec *)((const T *)s.ptr + o[j]));
-                    R.mode = R_RESIZE;
-                } else {  // other storage: interpolate now (not on the network's path)
-                    float a[4][GS], v[GS];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) load_px<DT, GS>(s.ptr, o[j], sdt, a[j]);
-#pragma unroll
-                    for (int i = 0; i < GS; ++i) {
-                        const float top = (1.f - R.lx) * a[0][i] + R.lx * a[1][i];
-                        const float bot = (1.f - R.lx) * a[2][i] + R.lx * a[3][i];
-                        v[i] = (1.f - R.ly) * top + R.ly * bot;
-                    }
-                    R.r[0] = as_f4(pack_vec<DT, GS>(v));
-                    R.mode = R_RESIZE_CVT;
-                }
-            } else {  // SRC_X0: the two bytes, converted at commit
-                const size_t o = (size_t)(sb + (long long)yi * ws + xi);
-                R.ly = s.scale0;
-                R.r[0][0] = ubits(((const uint8_t *)s.ptr)[o]);
-                R.r[0][1] = ubits(s.img[o]);
-                R.mode = R_X0;
             }
-        }
-        const T *wpk = (const T *)p.wpk;
-#pragma unroll
-        for (int k = 0; k < EW; ++k) {
-            const int e = tid + k * 256;
-#pragma unroll
-            for (int i = 0; i < GS; ++i) wr[k][i] = 0;
-            if (e >= TAPS * TN * KCG) continue;
-            const int cg = e % KCG, r = e / KCG;
-            const int n = r % TN, tap = r / TN;
-            const int c = c0 + cg * GS, ng = G.n0 + n;
-            if (ng < p.n_pad && c < p.cin_pad)
-                wr[k] = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
-        }
-    }
-
-    // Converts the fetched values and writes them to LDS.
-    static __device__ __forceinline__ void commit(const PRaw (&pr)[EP], const vec (&wr)[EW], T *patch,
-                                                  T *wl) {
-        const int tid = threadIdx.x;
-#pragma unroll
-        for (int k = 0; k < EP; ++k) {
-            const int e = tid + k * 256;
-            if (e >= PH * PW * KCG) continue;
-            const PRaw &R = pr[k];
-            const int cg = e % KCG, pix = e / KCG;
-            vec out;
-            float v[GS];
-            switch (R.mode) {
-            case R_RAW:
-            case R_RESIZE_CVT:
-                out = as_vec(R.r[0]);
-                break;
-            case R_F32:
-#pragma unroll
-                for (int i = 0; i < GS; ++i) v[i] = i < 4 ? R.r[0][i] : R.r[1][i - 4];
-                out = pack_vec<DT, GS>(v);
-                break;
-            case R_H16:
-#pragma unroll
-                for (int i = 0; i < GS; ++i) {
-                    const uint16_t h = (uint16_t)(fbits(R.r[0][i >> 1]) >> (16 * (i & 1)));
-                    v[i] = R.sdt == SV_BF16 ? bf16_bits_to_f32(h) : f16_bits_to_f32(h);
-                }
-                out = pack_vec<DT, GS>(v);
-                break;
-            case R_RESIZE: {
-                const vec a00 = as_vec(R.r[0]), a01 = as_vec(R.r[1]), a10 = as_vec(R.r[2]),
-                          a11 = as_vec(R.r[3]);
-#pragma unroll
-                for (int i = 0; i < GS; ++i) {
-                    const float top = (1.f - R.lx) * Elem<DT>::load((const T *)&a00 + i) +
-                                      R.lx * Elem<DT>::load((const T *)&a01 + i);
-                    const float bot = (1.f - R.lx) * Elem<DT>::load((const T *)&a10 + i) +
-                                      R.lx * Elem<DT>::load((const T *)&a11 + i);
-                    v[i] = (1.f - R.ly) * top + R.ly * bot;
-                }
-                out = pack_vec<DT, GS>(v);
-                break;
-            }
-            case R_X0:
-#pragma unroll
-                for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                v[0] = R.ly * (float)fbits(R.r[0][0]);
-                v[1] = (float)fbits(R.r[0][1]) * (1.0f / 256.0f);
-                out = pack_vec<DT, GS>(v);
-                break;
-            default:
-#pragma unroll
-                for (int i = 0; i < GS; ++i) out[i] = 0;
-            }
-            *(vec *)&patch[pix * KCP + cg * GS] = out;
-        }
-#pragma unroll
-        for (int k = 0; k < EW; ++k) {
-            const int e = tid + k * 256;
-            if (e >= TAPS * TN * KCG) continue;
-            const int cg = e % KCG, r = e / KCG;
-            const int n = r % TN, tap = r / TN;
-            *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = wr[k];
+            sm.ps[si][pix] = q;
         }
     }
 
@@ -330,8 +183,8 @@ struct ConvTile {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int wm = wave % WM, wn = wave / WM;
         const int n0 = G.n0, ox0 = G.ox0, oy0 = G.oy0;
-        const int iy0 = oy0 * S - PAD, ix0 = ox0 * S - PAD;
         const int g = lane >> 4, r16 = lane & 15;
+        const int C0 = p.src[0].C;
 
         f32x4 acc[MBW][NBW];
 #pragma unroll
@@ -339,87 +192,67 @@ struct ConvTile {
 #pragma unroll
             for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
+        __syncthreads();  // the previous tile of a persistent loop is done with LDS
+        pix_table(p, G, sm);
         const T *wpk = (const T *)p.wpk;
         for (int c0 = 0; c0 < p.Cin; c0 += KC) {
-          if constexpr (FB) {
-            // batched staging: every global load of the chunk is issued first,
-            // then converted / interpolated and written to LDS
-            PRaw pr[EP];
-            vec wr[EW];
-            fetch(p, G, c0, pr, wr);
-            __syncthreads();  // the previous chunk's MFMAs are done with LDS
-            commit(pr, wr, patch, wl);
             __syncthreads();
-          } else {
-            // serial staging: one element at a time (fewest registers)
-            __syncthreads();
-            // ---- input patch ------------------------------------------------------
-            for (int e = tid; e < PH * PW * KCG; e += 256) {
+            // ---- input patch: loads at the precomputed source pixels -------------
+#pragma unroll
+            for (int e0 = 0; e0 < NPIX * KCG; e0 += 256) {
+                const int e = e0 + tid;
+                if (e >= NPIX * KCG) break;
                 const int cg = e % KCG, pix = e / KCG;
-                const int py = pix / PW, px = pix - py * PW;
-                const int yi = iy0 + py, xi = ix0 + px, c = c0 + cg * GS;
+                const int c = c0 + cg * GS;
                 vec out;
 #pragma unroll
                 for (int i = 0; i < GS; ++i) out[i] = 0;
-                if (yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi && c < p.Cin) {
-                    const int si = c < p.src[0].C ? 0 : 1;
-                    const ConvSrc &s = p.src[si];
-                    const int cl = c - (si ? p.src[0].C : 0);
-                    const int sdt = s.sdt ? s.sdt - 1 : DT;
-                    const bool raw = sdt == DT;
-                    const long long sb = G.sbase[si];
-                    const int hs = G.hs[si], ws = G.ws[si];
-                    float v[GS];
-                    if (s.kind == SRC_TENSOR) {
-                        const size_t off = (size_t)(sb + (long long)yi * ws + xi) * s.pitch + s.coff + cl;
-                        if (raw) {
-                            out = *(const vec *)((const T *)s.ptr + off);
-                        } else {
-                            load_px<DT, GS>(s.ptr, off, sdt, v);
-                            out = pack_vec<DT, GS>(v);
-                        }
-                    } else if (s.kind == SRC_RESIZE) {
-                        int y0, y1, x0, x1;
-                        float ly, lx;
-                        bilin(yi, hs, G.Hi, y0, y1, ly);
-                        bilin(xi, ws, G.Wi, x0, x1, lx);
-                        float a00[GS], a01[GS], a10[GS], a11[GS];
-                        const size_t cb = (size_t)s.coff + cl;
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x0) * s.pitch + cb, sdt, a00);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y0 * ws + x1) * s.pitch + cb, sdt, a01);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x0) * s.pitch + cb, sdt, a10);
-                        load_px<DT, GS>(s.ptr, (size_t)(sb + (long long)y1 * ws + x1) * s.pitch + cb, sdt, a11);
+                if (c < p.Cin) {
+                    const int si = c < C0 ? 0 : 1;
+                    const PixSrc q = sm.ps[si][pix];
+                    if (q.p[0] >= 0) {
+                        const ConvSrc &s = si ? p.src[1] : p.src[0];
+                        const int cl = c - (si ? C0 : 0);
+                        const int sdt = s.sdt ? s.sdt - 1 : DT;
+                        float v[GS];
+                        if (s.kind == SRC_RESIZE) {
+                            float a00[GS], a01[GS], a10[GS], a11[GS];
+                            const size_t cb = (size_t)s.coff + cl;
+                            load_px<DT, GS>(s.ptr, (size_t)q.p[0] * s.pitch + cb, sdt, a00);
+                            load_px<DT, GS>(s.ptr, (size_t)q.p[1] * s.pitch + cb, sdt, a01);
+                            load_px<DT, GS>(s.ptr, (size_t)q.p[2] * s.pitch + cb, sdt, a10);
+                            load_px<DT, GS>(s.ptr, (size_t)q.p[3] * s.pitch + cb, sdt, a11);
 #pragma unroll
-                        for (int i = 0; i < GS; ++i) {
-                            const float top = (1.f - lx) * a00[i] + lx * a01[i];
-                            const float bot = (1.f - lx) * a10[i] + lx * a11[i];
-                            v[i] = (1.f - ly) * top + ly * bot;
-                        }
-                        out = pack_vec<DT, GS>(v);
-                    } else if (s.kind == SRC_ZINS) {
-                        if (((yi | xi) & 1) == 0) {
-                            const size_t off =
-                                (size_t)(sb + (long long)(yi >> 1) * ws + (xi >> 1)) * s.pitch + s.coff + cl;
-                            if (raw) {
+                            for (int i = 0; i < GS; ++i) {
+                                const float top = (1.f - q.lx) * a00[i] + q.lx * a01[i];
+                                const float bot = (1.f - q.lx) * a10[i] + q.lx * a11[i];
+                                v[i] = (1.f - q.ly) * top + q.ly * bot;
+                            }
+                            out = pack_vec<DT, GS>(v);
+                        } else if (s.kind == SRC_X0) {  // [f*d/256, I/256]
+#pragma unroll
+                            for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                            v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[q.p[0]];
+                            v[1] = (float)s.img[q.p[0]] * (1.0f / 256.0f);
+                            out = pack_vec<DT, GS>(v);
+                        } else {  // TENSOR or ZINS
+                            const size_t off = (size_t)q.p[0] * s.pitch + s.coff + cl;
+                            if (sdt == DT) {
                                 out = *(const vec *)((const T *)s.ptr + off);
                             } else {
                                 load_px<DT, GS>(s.ptr, off, sdt, v);
                                 out = pack_vec<DT, GS>(v);
                             }
                         }
-                    } else {  // SRC_X0: [f*d/256, I/256]
-                        const size_t o = (size_t)(sb + (long long)yi * ws + xi);
-#pragma unroll
-                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                        v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[o];
-                        v[1] = (float)s.img[o] * (1.0f / 256.0f);
-                        out = pack_vec<DT, GS>(v);
                     }
                 }
-                *(vec *)&patch[(py * PW + px) * KCP + cg * GS] = out;
+                *(vec *)&patch[pix * KCP + cg * GS] = out;
             }
             // ---- weights ------------------------------------------------------------
-            for (int e = tid; e < TAPS * TN * KCG; e += 256) {
+#pragma unroll
+            for (int e0 = 0; e0 < TAPS * TN * KCG; e0 += 256) {
+                const int e = e0 + tid;
+                if (e >= TAPS * TN * KCG) break;
                 const int cg = e % KCG, r = e / KCG;
                 const int n = r % TN, tap = r / TN;
                 const int c = c0 + cg * GS, ng = n0 + n;
@@ -431,7 +264,6 @@ struct ConvTile {
                 *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
             }
             __syncthreads();
-          }
             // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
 #pragma unroll
             for (int sub = 0; sub < KCM; ++sub) {
@@ -521,10 +353,10 @@ struct ConvTile {
 };
 
 // Uniform batch: one workgroup per (column tile, row tile, image x channel tile).
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
 {
-    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM, FB>;
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const int ntn = (p.Cout + TN - 1) / TN;
     const int b = blockIdx.z / ntn;
@@ -543,10 +375,10 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
 }
 
 // Pair table: persistent loop over the stage's tiles of every pair.
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 {
-    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM, FB>;
+    using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const PairTable *tab = p.tab;
     const int n = tab->n;
@@ -578,15 +410,15 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 }
 
 // grid <= 0: uniform launch; grid > 0: persistent launch over p.tab.
-template <int DT, int KS, int S, int TH, int TN, int WM, int KCM, int FB>
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     if (pgrid > 0) {
-        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM, FB>), dim3(pgrid), dim3(256), 0, st, p);
+        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM>), dim3(pgrid), dim3(256), 0, st, p);
         SV_LAUNCH_CHECK("k_conv_tab");
         return SV_OK;
     }
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), p.B * cdiv(p.Cout, TN));
-    hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM, FB>), grid, dim3(256), 0, st, p);
+    hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
     return SV_OK;
 }
@@ -594,8 +426,8 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
 template <int DT, int KS, int S>
 static sv_status launch_cfg(int cfg, const ConvParams &p, int pg, hipStream_t st) {
     switch (cfg) {
-#define SV_CFG(i, TH, TN, WM, KCM, FB, name) \
-    case i: return launch_one<DT, KS, S, TH, TN, WM, KCM, FB>(p, pg, st);
+#define SV_CFG(i, TH, TN, WM, KCM, name) \
+    case i: return launch_one<DT, KS, S, TH, TN, WM, KCM>(p, pg, st);
         SV_CONV_CFGS(SV_CFG)
 #undef SV_CFG
     default: return SV_ERR_RANGE;
