@@ -198,55 +198,101 @@ struct ConvTile {
         for (int c0 = 0; c0 < p.Cin; c0 += KC) {
             __syncthreads();
             // ---- input patch: loads at the precomputed source pixels -------------
-#pragma unroll
-            for (int e0 = 0; e0 < NPIX * KCG; e0 += 256) {
-                const int e = e0 + tid;
-                if (e >= NPIX * KCG) break;
-                const int cg = e % KCG, pix = e / KCG;
+            // e = pix * KCG + cg and 256 is a multiple of KCG, so a thread keeps
+            // one channel group -- one source and one kind -- for the whole chunk.
+            // Loads are issued in branch-free groups (padding reads pixel 0 and
+            // is zeroed afterwards) so several are in flight at once.
+            {
+                const int cg = tid % KCG;
                 const int c = c0 + cg * GS;
-                vec out;
+                const int si = c < C0 ? 0 : 1;
+                const ConvSrc &s = si ? p.src[1] : p.src[0];
+                const int kind = c < p.Cin ? s.kind : SRC_NONE;
+                const int cl = c - (si ? C0 : 0);
+                const int sdt = s.sdt ? s.sdt - 1 : DT;
+                const size_t cb = (size_t)s.coff + cl;
+                const PixSrc *tabp = sm.ps[si];
+                constexpr int PSTEP = 256 / KCG;              // pixels between a thread's elements
+                constexpr int NE = (NPIX + PSTEP - 1) / PSTEP;  // elements per thread
+                const int pix0 = tid / KCG;
+                if (kind == SRC_RESIZE) {
+                    constexpr int G2 = 2;
 #pragma unroll
-                for (int i = 0; i < GS; ++i) out[i] = 0;
-                if (c < p.Cin) {
-                    const int si = c < C0 ? 0 : 1;
-                    const PixSrc q = sm.ps[si][pix];
-                    if (q.p[0] >= 0) {
-                        const ConvSrc &s = si ? p.src[1] : p.src[0];
-                        const int cl = c - (si ? C0 : 0);
-                        const int sdt = s.sdt ? s.sdt - 1 : DT;
-                        float v[GS];
-                        if (s.kind == SRC_RESIZE) {
-                            float a00[GS], a01[GS], a10[GS], a11[GS];
-                            const size_t cb = (size_t)s.coff + cl;
-                            load_px<DT, GS>(s.ptr, (size_t)q.p[0] * s.pitch + cb, sdt, a00);
-                            load_px<DT, GS>(s.ptr, (size_t)q.p[1] * s.pitch + cb, sdt, a01);
-                            load_px<DT, GS>(s.ptr, (size_t)q.p[2] * s.pitch + cb, sdt, a10);
-                            load_px<DT, GS>(s.ptr, (size_t)q.p[3] * s.pitch + cb, sdt, a11);
+                    for (int k0 = 0; k0 < NE; k0 += G2) {
+                        float a[G2][4][GS];
+                        PixSrc q[G2];
+                        bool ok[G2];
+#pragma unroll
+                        for (int j = 0; j < G2; ++j) {
+                            const int pix = pix0 + (k0 + j) * PSTEP;
+                            const bool in = (k0 + j) < NE && pix < NPIX;
+                            q[j] = tabp[in ? pix : 0];
+                            ok[j] = in && q[j].p[0] >= 0;
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                load_px<DT, GS>(s.ptr, (size_t)(ok[j] ? q[j].p[r] : 0) * s.pitch + cb, sdt, a[j][r]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < G2; ++j) {
+                            const int pix = pix0 + (k0 + j) * PSTEP;
+                            if ((k0 + j) >= NE || pix >= NPIX) continue;
+                            float v[GS];
 #pragma unroll
                             for (int i = 0; i < GS; ++i) {
-                                const float top = (1.f - q.lx) * a00[i] + q.lx * a01[i];
-                                const float bot = (1.f - q.lx) * a10[i] + q.lx * a11[i];
-                                v[i] = (1.f - q.ly) * top + q.ly * bot;
+                                const float top = (1.f - q[j].lx) * a[j][0][i] + q[j].lx * a[j][1][i];
+                                const float bot = (1.f - q[j].lx) * a[j][2][i] + q[j].lx * a[j][3][i];
+                                v[i] = ok[j] ? (1.f - q[j].ly) * top + q[j].ly * bot : 0.f;
                             }
-                            out = pack_vec<DT, GS>(v);
-                        } else if (s.kind == SRC_X0) {  // [f*d/256, I/256]
-#pragma unroll
-                            for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                            v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[q.p[0]];
-                            v[1] = (float)s.img[q.p[0]] * (1.0f / 256.0f);
-                            out = pack_vec<DT, GS>(v);
-                        } else {  // TENSOR or ZINS
-                            const size_t off = (size_t)q.p[0] * s.pitch + s.coff + cl;
-                            if (sdt == DT) {
-                                out = *(const vec *)((const T *)s.ptr + off);
-                            } else {
-                                load_px<DT, GS>(s.ptr, off, sdt, v);
-                                out = pack_vec<DT, GS>(v);
-                            }
+                            *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                         }
                     }
+                } else if (kind == SRC_TENSOR || kind == SRC_ZINS) {
+                    constexpr int G4 = 4;
+#pragma unroll
+                    for (int k0 = 0; k0 < NE; k0 += G4) {
+                        vec raw[G4];
+                        float f[G4][GS];
+                        bool ok[G4];
+#pragma unroll
+                        for (int j = 0; j < G4; ++j) {
+                            const int pix = pix0 + (k0 + j) * PSTEP;
+                            const bool in = (k0 + j) < NE && pix < NPIX;
+                            const int pi = tabp[in ? pix : 0].p[0];
+                            ok[j] = in && pi >= 0;
+                            const size_t off = (size_t)(ok[j] ? pi : 0) * s.pitch + cb;
+                            if (sdt == DT) raw[j] = *(const vec *)((const T *)s.ptr + off);
+                            else load_px<DT, GS>(s.ptr, off, sdt, f[j]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < G4; ++j) {
+                            const int pix = pix0 + (k0 + j) * PSTEP;
+                            if ((k0 + j) >= NE || pix >= NPIX) continue;
+                            vec out = sdt == DT ? raw[j] : pack_vec<DT, GS>(f[j]);
+                            if (!ok[j]) {
+#pragma unroll
+                                for (int i = 0; i < GS; ++i) out[i] = 0;
+                            }
+                            *(vec *)&patch[pix * KCP + cg * GS] = out;
+                        }
+                    }
+                } else {  // SRC_X0 ([f*d/256, I/256]) or nothing
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) {
+                        const int pix = pix0 + k * PSTEP;
+                        if (pix >= NPIX) continue;
+                        float v[GS];
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        if (kind == SRC_X0) {
+                            const int pi = tabp[pix].p[0];
+                            if (pi >= 0) {
+                                v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[pi];
+                                v[1] = (float)s.img[pi] * (1.0f / 256.0f);
+                            }
+                        }
+                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
+                    }
                 }
-                *(vec *)&patch[pix * KCP + cg * GS] = out;
             }
             // ---- weights ------------------------------------------------------------
 #pragma unroll
