@@ -215,36 +215,64 @@ struct ConvTile {
                 constexpr int PSTEP = 256 / KCG;              // pixels between a thread's elements
                 constexpr int NE = (NPIX + PSTEP - 1) / PSTEP;  // elements per thread
                 const int pix0 = tid / KCG;
-                if (kind == SRC_RESIZE) {
-                    constexpr int G2 = 2;
+                if (kind == SRC_RESIZE && sdt == DT) {
+                    constexpr int GR = 4;  // elements (x 4 corners) in flight
 #pragma unroll
-                    for (int k0 = 0; k0 < NE; k0 += G2) {
-                        float a[G2][4][GS];
-                        PixSrc q[G2];
-                        bool ok[G2];
+                    for (int k0 = 0; k0 < NE; k0 += GR) {
+                        vec a[GR][4];
+                        PixSrc q[GR];
+                        bool ok[GR];
 #pragma unroll
-                        for (int j = 0; j < G2; ++j) {
+                        for (int j = 0; j < GR; ++j) {
                             const int pix = pix0 + (k0 + j) * PSTEP;
                             const bool in = (k0 + j) < NE && pix < NPIX;
                             q[j] = tabp[in ? pix : 0];
                             ok[j] = in && q[j].p[0] >= 0;
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                load_px<DT, GS>(s.ptr, (size_t)(ok[j] ? q[j].p[r] : 0) * s.pitch + cb, sdt, a[j][r]);
+                                a[j][r] = *(const vec *)((const T *)s.ptr +
+                                                         (size_t)(ok[j] ? q[j].p[r] : 0) * s.pitch + cb);
                         }
 #pragma unroll
-                        for (int j = 0; j < G2; ++j) {
+                        for (int j = 0; j < GR; ++j) {
                             const int pix = pix0 + (k0 + j) * PSTEP;
                             if ((k0 + j) >= NE || pix >= NPIX) continue;
                             float v[GS];
 #pragma unroll
                             for (int i = 0; i < GS; ++i) {
-                                const float top = (1.f - q[j].lx) * a[j][0][i] + q[j].lx * a[j][1][i];
-                                const float bot = (1.f - q[j].lx) * a[j][2][i] + q[j].lx * a[j][3][i];
+                                const float x00 = Elem<DT>::load((const T *)&a[j][0] + i);
+                                const float x01 = Elem<DT>::load((const T *)&a[j][1] + i);
+                                const float x10 = Elem<DT>::load((const T *)&a[j][2] + i);
+                                const float x11 = Elem<DT>::load((const T *)&a[j][3] + i);
+                                const float top = (1.f - q[j].lx) * x00 + q[j].lx * x01;
+                                const float bot = (1.f - q[j].lx) * x10 + q[j].lx * x11;
                                 v[i] = ok[j] ? (1.f - q[j].ly) * top + q[j].ly * bot : 0.f;
                             }
                             *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                         }
+                    }
+                } else if (kind == SRC_RESIZE) {  // another storage dtype: one at a time
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) {
+                        const int pix = pix0 + k * PSTEP;
+                        if (pix >= NPIX) continue;
+                        const PixSrc q = tabp[pix];
+                        float v[GS];
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        if (q.p[0] >= 0) {
+                            float a[4][GS];
+#pragma unroll
+                            for (int r = 0; r < 4; ++r)
+                                load_px<DT, GS>(s.ptr, (size_t)q.p[r] * s.pitch + cb, sdt, a[r]);
+#pragma unroll
+                            for (int i = 0; i < GS; ++i) {
+                                const float top = (1.f - q.lx) * a[0][i] + q.lx * a[1][i];
+                                const float bot = (1.f - q.lx) * a[2][i] + q.lx * a[3][i];
+                                v[i] = (1.f - q.ly) * top + q.ly * bot;
+                            }
+                        }
+                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                     }
                 } else if (kind == SRC_TENSOR || kind == SRC_ZINS) {
                     constexpr int G4 = 4;
@@ -294,20 +322,39 @@ struct ConvTile {
                     }
                 }
             }
-            // ---- weights ------------------------------------------------------------
+            // ---- weights: branch-free groups of loads (out-of-range reads the first
+            // element and is zeroed) -------------------------------------------------
+            {
+                constexpr int NW = TAPS * TN * KCG;
+                constexpr int EWT = (NW + 255) / 256;
+                constexpr int GW = 8;
 #pragma unroll
-            for (int e0 = 0; e0 < TAPS * TN * KCG; e0 += 256) {
-                const int e = e0 + tid;
-                if (e >= TAPS * TN * KCG) break;
-                const int cg = e % KCG, r = e / KCG;
-                const int n = r % TN, tap = r / TN;
-                const int c = c0 + cg * GS, ng = n0 + n;
-                vec val;
+                for (int k0 = 0; k0 < EWT; k0 += GW) {
+                    vec val[GW];
+                    bool ok[GW];
 #pragma unroll
-                for (int i = 0; i < GS; ++i) val[i] = 0;
-                if (ng < p.n_pad && c < p.cin_pad)
-                    val = *(const vec *)(wpk + ((size_t)tap * p.n_pad + ng) * p.cin_pad + c);
-                *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = val;
+                    for (int j = 0; j < GW; ++j) {
+                        const int e = (k0 + j) * 256 + tid;
+                        const int cg = e % KCG, r = e / KCG;
+                        const int n = r % TN, tap = r / TN;
+                        const int c = c0 + cg * GS, ng = n0 + n;
+                        ok[j] = (k0 + j) < EWT && e < NW && ng < p.n_pad && c < p.cin_pad;
+                        val[j] = *(const vec *)(wpk + (ok[j] ? ((size_t)tap * p.n_pad + ng) * p.cin_pad + c : 0));
+                    }
+#pragma unroll
+                    for (int j = 0; j < GW; ++j) {
+                        const int e = (k0 + j) * 256 + tid;
+                        if ((k0 + j) >= EWT || e >= NW) continue;
+                        const int cg = e % KCG, r = e / KCG;
+                        const int n = r % TN, tap = r / TN;
+                        vec o = val[j];
+                        if (!ok[j]) {
+#pragma unroll
+                            for (int i = 0; i < GS; ++i) o[i] = 0;
+                        }
+                        *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = o;
+                    }
+                }
             }
             __syncthreads();
             // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
