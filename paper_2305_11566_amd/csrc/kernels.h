@@ -121,7 +121,7 @@ sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float sc
                        hipStream_t s);
 sv_status launch_final_tab(const PairTable *tab, int grid, const float *T, int tpitch,
                            const uint8_t *disp, float scale0, const float *biasF, hipStream_t s);
-constexpr int FIN_TILE_W = 64, FIN_TILE_H = 4;
+constexpr int FIN_TILE_W = 64, FIN_TILE_H = 8;
 sv_status launch_reparam(const float *ml, const float *eps, int npix, int L, void *z, int dtype,
                          hipStream_t s);
 

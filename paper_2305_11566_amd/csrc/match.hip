@@ -13,33 +13,61 @@ namespace sv {
 // ---------------------------------------------------------------------------
 // Reduction + census.  One workgroup = CEN_TW x CEN_TH reduced pixels of one
 // image.  The reduced patch with its clamped halo is built once in LDS (each
-// patch pixel is the block mean of f x f full-resolution bytes read by
-// consecutive threads from consecutive addresses), then every thread packs
-// the census word of its pixel from LDS.
+// patch pixel is the block mean of F x F full-resolution bytes; F is a
+// template parameter so that the F * F byte loads of several patch pixels are
+// unrolled and in flight together), then every thread packs the census word
+// of its pixel from LDS.
 // ---------------------------------------------------------------------------
 constexpr int CEN_TW = CEN_TILE_W, CEN_TH = CEN_TILE_H, CEN_MAXR = 8;
+constexpr int CEN_THREADS = CEN_TW * CEN_TH;
 typedef uint8_t CenPatch[CEN_TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
 
 // One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
+template <int F>
 __device__ __forceinline__ void census_tile(CenPatch &patch, const uint8_t *__restrict__ img, int H,
-                                            int W, int pitch, int f, int rx, int ry, int h, int w,
-                                            int i0, int j0, uint8_t *__restrict__ low,
+                                            int W, int pitch, int rx, int ry, int h, int w, int i0,
+                                            int j0, uint8_t *__restrict__ low,
                                             uint64_t *__restrict__ cen)
 {
+    // patch pixels per thread whose loads are issued before any is summed
+    constexpr int R = F * F >= 48 ? 1 : (48 / (F * F) > 4 ? 4 : 48 / (F * F));
     const int PH = CEN_TH + 2 * ry, PW = CEN_TW + 2 * rx;
     const int tid = threadIdx.x;
-    for (int e = tid; e < PH * PW; e += CEN_TW * CEN_TH) {
-        const int py = e / PW, px = e - py * PW;
-        const int i = min(max(i0 + py - ry, 0), h - 1);
-        const int j = min(max(j0 + px - rx, 0), w - 1);
-        const int y1 = min(f * i + f, H), x1 = min(f * j + f, W);
-        uint32_t s = 0;
-        for (int y = f * i; y < y1; ++y) {
-            const uint8_t *row = img + (size_t)y * pitch;
-            for (int x = f * j; x < x1; ++x) s += row[x];
+    for (int e0 = 0; e0 < PH * PW; e0 += R * CEN_THREADS) {
+        uint32_t v[R][F * F];
+        int ny[R], nx[R];
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int e = e0 + k * CEN_THREADS + tid;
+            const int ee = e < PH * PW ? e : 0;
+            const int py = ee / PW, px = ee - py * PW;
+            const int i = min(max(i0 + py - ry, 0), h - 1);
+            const int j = min(max(j0 + px - rx, 0), w - 1);
+            ny[k] = min(F, H - F * i);
+            nx[k] = min(F, W - F * j);
+            const uint8_t *src = img + (size_t)(F * i) * pitch + F * j;
+#pragma unroll
+            for (int y = 0; y < F; ++y)
+#pragma unroll
+                for (int x = 0; x < F; ++x)
+                    // a row or column past the image edge re-reads the block's
+                    // first byte and is dropped from the sum below
+                    v[k][y * F + x] = src[(y < ny[k] ? (size_t)y * pitch : 0) + (x < nx[k] ? x : 0)];
         }
-        const uint32_t n = (uint32_t)((y1 - f * i) * (x1 - f * j));
-        patch[py][px] = (uint8_t)((s + n / 2) / n);
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            const int e = e0 + k * CEN_THREADS + tid;
+            if (e >= PH * PW) continue;
+            uint32_t sum = 0;
+#pragma unroll
+            for (int y = 0; y < F; ++y)
+#pragma unroll
+                for (int x = 0; x < F; ++x)
+                    sum += (y < ny[k] && x < nx[k]) ? v[k][y * F + x] : 0u;
+            const int py = e / PW, px = e - py * PW;
+            const uint32_t n = (uint32_t)(ny[k] * nx[k]);
+            patch[py][px] = (uint8_t)(n == F * F ? (sum + F * F / 2) / (F * F) : (sum + n / 2) / n);
+        }
     }
     __syncthreads();
     const int ty = tid / CEN_TW, tx = tid - ty * CEN_TW;
@@ -61,9 +89,10 @@ __device__ __forceinline__ void census_tile(CenPatch &patch, const uint8_t *__re
     __syncthreads();  // the patch is reused by the next tile of a persistent loop
 }
 
-__global__ void __launch_bounds__(CEN_TW * CEN_TH)
+template <int F>
+__global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
-                int W, int pitch, int f, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
+                int W, int pitch, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
                 uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
                 uint64_t *__restrict__ cen1)
 {
@@ -74,9 +103,22 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
     const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
     uint8_t *low = view ? low1 : low0;
     uint64_t *cen = (view ? cen1 : cen0) + (size_t)b * h * w;
-    census_tile(patch, img, H, W, pitch, f, rx, ry, h, w, blockIdx.y * CEN_TH, blockIdx.x * CEN_TW,
-                low ? low + (size_t)b * h * w : nullptr, cen);
+    census_tile<F>(patch, img, H, W, pitch, rx, ry, h, w, blockIdx.y * CEN_TH, blockIdx.x * CEN_TW,
+                   low ? low + (size_t)b * h * w : nullptr, cen);
 }
+
+#define SV_FACTOR_SWITCH(f, CALL) \
+    switch (f) {                  \
+    case 1: CALL(1); break;       \
+    case 2: CALL(2); break;       \
+    case 3: CALL(3); break;       \
+    case 4: CALL(4); break;       \
+    case 5: CALL(5); break;       \
+    case 6: CALL(6); break;       \
+    case 7: CALL(7); break;       \
+    case 8: CALL(8); break;       \
+    default: return SV_ERR_RANGE; \
+    }
 
 sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
                                int pitch, int f, int win_w, int win_h, uint8_t *low0,
@@ -84,18 +126,21 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
 {
     const int h = cdiv(H, f), w = cdiv(W, f);
     dim3 grid(cdiv(w, CEN_TW), cdiv(h, CEN_TH), 2 * B);
-    hipLaunchKernelGGL(k_reduce_census, grid, dim3(CEN_TW * CEN_TH), 0, s, img0, img1, B, H, W,
-                       pitch, f, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0, cen1);
+#define SV_CEN_LAUNCH(F)                                                                        \
+    hipLaunchKernelGGL(k_reduce_census<F>, grid, dim3(CEN_THREADS), 0, s, img0, img1, B, H, W, \
+                       pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0, cen1)
+    SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
+#undef SV_CEN_LAUNCH
     SV_LAUNCH_CHECK("k_reduce_census");
     return SV_OK;
 }
 
 // Persistent variant: tiles of both views of every pair of the table; the
 // per-pair maps live in flattened buffers at the pair's level-0 offset.
-__global__ void __launch_bounds__(CEN_TW * CEN_TH)
-k_reduce_census_tab(const PairTable *__restrict__ tab, int f, int rx, int ry,
-                    uint8_t *__restrict__ low0, uint64_t *__restrict__ cen0,
-                    uint64_t *__restrict__ cen1)
+template <int F>
+__global__ void __launch_bounds__(CEN_THREADS)
+k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *__restrict__ low0,
+                    uint64_t *__restrict__ cen0, uint64_t *__restrict__ cen1)
 {
     __shared__ CenPatch patch;
     const int n = tab->n;
@@ -108,17 +153,20 @@ k_reduce_census_tab(const PairTable *__restrict__ tab, int f, int rx, int ry,
         const int tw = cdiv_d(g.w[0], CEN_TW), th = cdiv_d(g.h[0], CEN_TH);
         const int view = local / (tw * th), r = local - view * tw * th;
         const long long o = g.off[0];
-        census_tile(patch, view ? g.right : g.left, g.H, g.W, g.W, f, rx, ry, g.h[0], g.w[0],
-                    (r / tw) * CEN_TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
-                    (view ? cen1 : cen0) + o);
+        census_tile<F>(patch, view ? g.right : g.left, g.H, g.W, g.W, rx, ry, g.h[0], g.w[0],
+                       (r / tw) * CEN_TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
+                       (view ? cen1 : cen0) + o);
     }
 }
 
 sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int win_w, int win_h,
                                    uint8_t *low0, uint64_t *cen0, uint64_t *cen1, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_reduce_census_tab, dim3(grid), dim3(CEN_TW * CEN_TH), 0, s, tab, f,
-                       (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1);
+#define SV_CEN_LAUNCH(F)                                                                         \
+    hipLaunchKernelGGL(k_reduce_census_tab<F>, dim3(grid), dim3(CEN_THREADS), 0, s, tab,        \
+                       (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1)
+    SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
+#undef SV_CEN_LAUNCH
     SV_LAUNCH_CHECK("k_reduce_census_tab");
     return SV_OK;
 }

@@ -62,6 +62,17 @@ def test_edge_shapes(H, W, f, ww, wh, D):
     _check(left, right, f, ww, wh, D)
 
 
+@pytest.mark.parametrize("f", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_every_factor_ragged(f):
+    # each reduction factor is its own kernel instantiation; sizes leave a
+    # partial block in both directions
+    H, W = 8 * f + f // 2 + 1, 64 * f + f - 1 if f > 1 else 131
+    rng = np.random.default_rng(f)
+    left = rng.integers(0, 256, (1, H, W), dtype=np.uint8)
+    right = np.roll(left, -2 * f, axis=2) ^ rng.integers(0, 4, (1, H, W), dtype=np.uint8)
+    _check(left, right, f, 7, 5, 12)
+
+
 def test_identical_images_zero():
     p = gen_pair(96, 200, 4, 2.0, 20.0, seed=3)
     _, _, _, d = _run_gpu(p.left[None], p.left[None], 2, 5, 5, 16)
