@@ -257,17 +257,24 @@ sv_status sv_stereo_batch(sv_batch_plan *plan, const sv_pair *pairs, int n, cons
                           void *stream);
 
 /*
- * Time the candidate tile shapes of every stage for this desc and shape on
- * the current device and store the fastest in the autotune cache (a JSON
- * file at $SV_AUTOTUNE_CACHE, default ~/.cache/sv_autotune.json, keyed by
- * stage, shape, dtype and gfx arch).  A missing or corrupt cache falls back
- * to defaults.  Allocates and frees its own scratch buffers; synchronises.
+ * Time the candidate configurations of every stage for this desc and shape
+ * on the current device and store the fastest in the autotune cache (a text
+ * file at $SV_AUTOTUNE_CACHE, default ~/.cache/sv_autotune.tsv, one line per
+ * gfx arch, dtype, channels, latent, factor, batch and size).  A missing or
+ * corrupt cache falls back to defaults.  Allocates and frees its own scratch
+ * buffers; synchronises.
  */
 sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int win_w, int win_h);
 
-/* Tile shape of network layer `layer` (0..8 in the canonical order) for all
- * later calls: cfg in [0, sv_num_layer_cfgs()), or -1 for the default /
- * autotuned choice.  Results do not depend on it.  Process-wide. */
+/* Configuration of network layer `layer` (0..8 in the canonical order) for
+ * all later calls: cfg in [0, sv_num_layer_cfgs()), or -1 for the default /
+ * autotuned choice.  Process-wide.  A configuration is a tile shape plus a
+ * split of the channel reduction into 1..4 parts (cfg = tile + ntiles *
+ * (split - 1); sv_conv_cfg_name names both).  Results do not depend on the
+ * tile shape.  A split > 1 adds the parts' FP32 partial sums in a fixed
+ * order, so results are deterministic per split but differ from the
+ * unsplit ones by rounding.  Splits apply to sv_vae_forward only (capped by
+ * its workspace); the batch plan and the backward pass run unsplit. */
 sv_status sv_set_layer_cfg(int layer, int cfg);
 int sv_num_layer_cfgs(void);
 

@@ -24,48 +24,82 @@
 // templates live in conv_impl.h and are instantiated per compute dtype in
 // conv_f32.hip / conv_bf16.hip / conv_f16.hip; this file holds the tile
 // table, the dispatch and the weight packing.
+#include <cstdio>
+#include <mutex>
+
 #include "conv_impl.h"
 
 namespace sv {
 
 // ---- tile configurations ---------------------------------------------------------
+// A configuration id is a tile shape plus a reduction split:
+// id = tile + kNumTiles * (ksplit - 1), ksplit = 1 .. kMaxSplit.  A split only
+// applies to uniform launches that bring a partial-sum buffer.
 struct CfgDesc { int TH, TN, WM, KCM; const char *name; };
 static const CfgDesc kCfgs[] = {
 #define SV_CFG(i, TH, TN, WM, KCM, name) {TH, TN, WM, KCM, name},
     SV_CONV_CFGS(SV_CFG)
 #undef SV_CFG
 };
-int conv_num_cfgs() { return (int)(sizeof(kCfgs) / sizeof(kCfgs[0])); }
-const char *conv_cfg_name(int cfg) { return (cfg >= 0 && cfg < conv_num_cfgs()) ? kCfgs[cfg].name : "?"; }
+static constexpr int kNumTiles = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
+static constexpr int kMaxSplit = CONV_MAX_SPLIT;
+int conv_num_tiles() { return kNumTiles; }
+int conv_num_cfgs() { return kNumTiles * kMaxSplit; }
+
+const char *conv_cfg_name(int cfg) {
+    static char names[kNumTiles * kMaxSplit][32];
+    static std::once_flag once;
+    std::call_once(once, [] {
+        for (int i = 0; i < kNumTiles * kMaxSplit; ++i) {
+            const int t = i % kNumTiles, sp = i / kNumTiles + 1;
+            if (sp == 1) snprintf(names[i], sizeof names[i], "%s", kCfgs[t].name);
+            else snprintf(names[i], sizeof names[i], "%s_s%d", kCfgs[t].name, sp);
+        }
+    });
+    return (cfg >= 0 && cfg < conv_num_cfgs()) ? names[cfg] : "?";
+}
 
 sv_status launch_conv_f32(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 sv_status launch_conv_bf16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 
-static sv_status launch_any(int dtype, int ks, int stride, int cfg, const ConvParams &p, int pg,
+static sv_status launch_any(int dtype, int ks, int stride, int tile, const ConvParams &p, int pg,
                             hipStream_t st) {
     switch (dtype) {
-    case SV_F32: return launch_conv_f32(ks, stride, cfg, p, pg, st);
-    case SV_BF16: return launch_conv_bf16(ks, stride, cfg, p, pg, st);
-    case SV_F16: return launch_conv_f16(ks, stride, cfg, p, pg, st);
+    case SV_F32: return launch_conv_f32(ks, stride, tile, p, pg, st);
+    case SV_BF16: return launch_conv_bf16(ks, stride, tile, p, pg, st);
+    case SV_F16: return launch_conv_f16(ks, stride, tile, p, pg, st);
     default: return SV_ERR_DTYPE;
     }
 }
 
-sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t st) {
-    return launch_any(dtype, ks, stride, cfg, p, 0, st);
+sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
+    if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    ConvParams p = p0;
+    int ksplit = cfg / kNumTiles + 1;
+    // at most one split per base chunk of input channels, and only when the
+    // partial sums fit the caller's buffer; otherwise one pass
+    const int kcb = dtype == SV_F32 ? 16 : 32;
+    ksplit = std::min(ksplit, cdiv(p.Cin, kcb));
+    const size_t need = (size_t)ksplit * p.B * p.Ho * p.Wo * p.n_pad * sizeof(float);
+    if (!p.part || need > p.part_bytes) ksplit = 1;
+    p.ksplit = ksplit;
+    return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
 }
 
-sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
+sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p0, int grid,
                           hipStream_t st) {
-    if (!p.tab || grid <= 0) return SV_ERR_RANGE;
-    return launch_any(dtype, ks, stride, cfg, p, grid, st);
+    if (!p0.tab || grid <= 0) return SV_ERR_RANGE;
+    if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    ConvParams p = p0;
+    p.ksplit = 1;  // the persistent path never splits
+    return launch_any(dtype, ks, stride, cfg % kNumTiles, p, grid, st);
 }
 
 void conv_cfg_tile(int cfg, int &TH, int &TN) {
     if (cfg < 0 || cfg >= conv_num_cfgs()) cfg = 0;
-    TH = kCfgs[cfg].TH;
-    TN = kCfgs[cfg].TN;
+    TH = kCfgs[cfg % kNumTiles].TH;
+    TN = kCfgs[cfg % kNumTiles].TN;
 }
 
 // ---- weight packing ---------------------------------------------------------------

@@ -2,6 +2,8 @@
 // instantiation files conv_f32.hip, conv_bf16.hip, conv_f16.hip).
 #pragma once
 
+#include <algorithm>
+
 #include "kernels.h"
 
 // The tile configurations: (index, TH rows, TN output channels, WM waves along
@@ -97,6 +99,64 @@ __device__ __forceinline__ void load_px(const void *base, size_t off, int sdt, f
     }
 }
 
+// Epilogue of four consecutive output channels nbase..nbase+3 of one output
+// pixel from their FP32 sums: bias, activation, the backward pass's extra
+// terms, then an NHWC store in the output dtype.
+template <int DT>
+__device__ __forceinline__ void conv_epilogue(const ConvParams &p, size_t pix, int nbase,
+                                              const float (&acc)[4]) {
+    using T = typename Elem<DT>::T;
+    float r[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int n = nbase + i;
+        float val = acc[i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
+        if (p.act) val = val > 0.f ? val : 0.1f * val;
+        if (n < p.Cout) {
+            if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
+            if (p.mask) {
+                const float mv = Elem<DT>::load((const T *)p.mask + pix * p.mask_pitch + n);
+                val *= mv > 0.f ? 1.0f : 0.1f;
+            }
+        }
+        r[i] = val;
+    }
+    const size_t o = pix * p.out_pitch + p.out_coff + nbase;
+    const bool full = nbase + 4 <= p.Cout;
+    if (p.out_f32) {
+        float *op = (float *)p.out + o;
+        if (full && (o % 4) == 0) {
+            *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
+        } else {
+            for (int i = 0; i < 4; ++i)
+                if (nbase + i < p.Cout) op[i] = r[i];
+        }
+    } else {
+        T *op = (T *)p.out + o;
+        if (full && (o % 4) == 0 && DT != SV_F32) {
+            u16x4 w4;
+            for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)Elem<DT>::make(r[i]);
+            *(u16x4 *)op = w4;
+        } else if (full && (o % 4) == 0) {
+            *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
+        } else {
+            for (int i = 0; i < 4; ++i)
+                if (nbase + i < p.Cout) op[i] = Elem<DT>::make(r[i]);
+        }
+    }
+}
+
+// The range [c_begin, c_end) of input channels that reduction part kz of
+// ksplit covers: ksplit contiguous runs of base chunks of kcb channels, the
+// same for every tile shape.
+__device__ __forceinline__ void split_range(int Cin, int kcb, int ksplit, int kz, int &c_begin,
+                                            int &c_end) {
+    const int nb = (Cin + kcb - 1) / kcb;
+    const int per = (nb + ksplit - 1) / ksplit;
+    c_begin = min(kz * per, nb) * kcb;
+    c_end = min(min((kz + 1) * per, nb) * kcb, Cin);
+}
+
 // Where one tile's data lives: sizes of the input and output grids, the pixel
 // offset of the image in each source and in the output, and the tile origin.
 struct ConvGeo {
@@ -178,7 +238,8 @@ struct ConvTile {
         }
     }
 
-    static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm) {
+    static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm,
+                                               int kz) {
         T *patch = sm.patch, *wl = sm.wl;
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int wm = wave % WM, wn = wave / WM;
@@ -195,13 +256,17 @@ struct ConvTile {
         __syncthreads();  // the previous tile of a persistent loop is done with LDS
         pix_table(p, G, sm);
         const T *wpk = (const T *)p.wpk;
-        for (int c0 = 0; c0 < p.Cin; c0 += KC) {
+        int c_begin = 0, c_end = p.Cin;
+        if (p.ksplit > 1) split_range(p.Cin, KCB, p.ksplit, kz, c_begin, c_end);
+        for (int c0 = c_begin; c0 < c_end; c0 += KC) {
             __syncthreads();
-            // ---- input patch: loads at the precomputed source pixels -------------
-            // e = pix * KCG + cg and 256 is a multiple of KCG, so a thread keeps
-            // one channel group -- one source and one kind -- for the whole chunk.
-            // Loads are issued in branch-free groups (padding reads pixel 0 and
-            // is zeroed afterwards) so several are in flight at once.
+            // ---- staging: the input patch (at the precomputed source pixels) and
+            // the chunk of weights.  e = pix * KCG + cg and 256 is a multiple of
+            // KCG, so a thread keeps one channel group -- one source and one kind
+            // -- for the whole chunk.  Loads are issued in branch-free groups
+            // (padding and out-of-range elements read a valid address and are
+            // zeroed afterwards); each step issues one patch group and one weight
+            // group before writing either to LDS, so both are in flight together.
             {
                 const int cg = tid % KCG;
                 const int c = c0 + cg * GS;
@@ -212,147 +277,151 @@ struct ConvTile {
                 const int sdt = s.sdt ? s.sdt - 1 : DT;
                 const size_t cb = (size_t)s.coff + cl;
                 const PixSrc *tabp = sm.ps[si];
-                constexpr int PSTEP = 256 / KCG;              // pixels between a thread's elements
-                constexpr int NE = (NPIX + PSTEP - 1) / PSTEP;  // elements per thread
+                const T *sp = (const T *)s.ptr;
+                constexpr int PSTEP = 256 / KCG;                // pixels between a thread's elements
+                constexpr int NE = (NPIX + PSTEP - 1) / PSTEP;  // patch elements per thread
+                constexpr int GR = 4;                           // resized elements (4 corners each) per step
+                constexpr int NGR = (NE + GR - 1) / GR;
+                constexpr int GT = NE < 8 ? NE : 8;             // plain elements per step
+                constexpr int NGT = (NE + GT - 1) / GT;
+                constexpr int NW = TAPS * TN * KCG;             // weight vectors of the chunk
+                constexpr int EWT = (NW + 255) / 256;
+                constexpr int GW = 8;
+                constexpr int NGW = (EWT + GW - 1) / GW;
+                constexpr int NG1 = NGR > NGT ? NGR : NGT;
+                constexpr int NG = NG1 > NGW ? NG1 : NGW;
                 const int pix0 = tid / KCG;
-                if (kind == SRC_RESIZE && sdt == DT) {
-                    constexpr int GR = 4;  // elements (x 4 corners) in flight
+                const bool fast_resize = kind == SRC_RESIZE && sdt == DT;
+                const bool fast_plain = (kind == SRC_TENSOR || kind == SRC_ZINS) && sdt == DT;
 #pragma unroll
-                    for (int k0 = 0; k0 < NE; k0 += GR) {
-                        vec a[GR][4];
-                        PixSrc q[GR];
-                        bool ok[GR];
+                for (int gi = 0; gi < NG; ++gi) {
+                    // -- issue
+                    vec ra[GR][4];
+                    PixSrc rq[GR];
+                    bool rok[GR];
+                    if (gi < NGR && fast_resize) {
 #pragma unroll
                         for (int j = 0; j < GR; ++j) {
-                            const int pix = pix0 + (k0 + j) * PSTEP;
-                            const bool in = (k0 + j) < NE && pix < NPIX;
-                            q[j] = tabp[in ? pix : 0];
-                            ok[j] = in && q[j].p[0] >= 0;
+                            const int k = gi * GR + j;
+                            const int pix = pix0 + k * PSTEP;
+                            const bool in = k < NE && pix < NPIX;
+                            rq[j] = tabp[in ? pix : 0];
+                            rok[j] = in && rq[j].p[0] >= 0;
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                a[j][r] = *(const vec *)((const T *)s.ptr +
-                                                         (size_t)(ok[j] ? q[j].p[r] : 0) * s.pitch + cb);
+                                ra[j][r] = *(const vec *)(sp + (size_t)(rok[j] ? rq[j].p[r] : 0) * s.pitch + cb);
                         }
+                    }
+                    vec ta[GT];
+                    bool tok[GT];
+                    if (gi < NGT && fast_plain) {
+#pragma unroll
+                        for (int j = 0; j < GT; ++j) {
+                            const int k = gi * GT + j;
+                            const int pix = pix0 + k * PSTEP;
+                            const bool in = k < NE && pix < NPIX;
+                            const int pi = tabp[in ? pix : 0].p[0];
+                            tok[j] = in && pi >= 0;
+                            ta[j] = *(const vec *)(sp + (size_t)(tok[j] ? pi : 0) * s.pitch + cb);
+                        }
+                    }
+                    vec wv[GW];
+                    bool wok[GW];
+                    if (gi < NGW) {
+#pragma unroll
+                        for (int j = 0; j < GW; ++j) {
+                            const int k = gi * GW + j;
+                            const int e = k * 256 + tid;
+                            const int wcg = e % KCG, r = e / KCG;
+                            const int n = r % TN, tap = r / TN;
+                            const int wc = c0 + wcg * GS, ng = n0 + n;
+                            wok[j] = k < EWT && e < NW && ng < p.n_pad && wc < p.cin_pad;
+                            wv[j] = *(const vec *)(wpk + (wok[j] ? ((size_t)tap * p.n_pad + ng) * p.cin_pad + wc : 0));
+                        }
+                    }
+                    // -- commit to LDS
+                    if (gi < NGR && fast_resize) {
 #pragma unroll
                         for (int j = 0; j < GR; ++j) {
-                            const int pix = pix0 + (k0 + j) * PSTEP;
-                            if ((k0 + j) >= NE || pix >= NPIX) continue;
+                            const int k = gi * GR + j;
+                            const int pix = pix0 + k * PSTEP;
+                            if (k >= NE || pix >= NPIX) continue;
                             float v[GS];
 #pragma unroll
                             for (int i = 0; i < GS; ++i) {
-                                const float x00 = Elem<DT>::load((const T *)&a[j][0] + i);
-                                const float x01 = Elem<DT>::load((const T *)&a[j][1] + i);
-                                const float x10 = Elem<DT>::load((const T *)&a[j][2] + i);
-                                const float x11 = Elem<DT>::load((const T *)&a[j][3] + i);
-                                const float top = (1.f - q[j].lx) * x00 + q[j].lx * x01;
-                                const float bot = (1.f - q[j].lx) * x10 + q[j].lx * x11;
-                                v[i] = ok[j] ? (1.f - q[j].ly) * top + q[j].ly * bot : 0.f;
+                                const float x00 = Elem<DT>::load((const T *)&ra[j][0] + i);
+                                const float x01 = Elem<DT>::load((const T *)&ra[j][1] + i);
+                                const float x10 = Elem<DT>::load((const T *)&ra[j][2] + i);
+                                const float x11 = Elem<DT>::load((const T *)&ra[j][3] + i);
+                                const float top = (1.f - rq[j].lx) * x00 + rq[j].lx * x01;
+                                const float bot = (1.f - rq[j].lx) * x10 + rq[j].lx * x11;
+                                v[i] = rok[j] ? (1.f - rq[j].ly) * top + rq[j].ly * bot : 0.f;
                             }
                             *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                         }
                     }
-                } else if (kind == SRC_RESIZE) {  // another storage dtype: one at a time
+                    if (gi < NGT && fast_plain) {
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) {
-                        const int pix = pix0 + k * PSTEP;
-                        if (pix >= NPIX) continue;
-                        const PixSrc q = tabp[pix];
-                        float v[GS];
+                        for (int j = 0; j < GT; ++j) {
+                            const int k = gi * GT + j;
+                            const int pix = pix0 + k * PSTEP;
+                            if (k >= NE || pix >= NPIX) continue;
+                            vec o = ta[j];
+                            if (!tok[j]) {
 #pragma unroll
-                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                        if (q.p[0] >= 0) {
-                            float a[4][GS];
-#pragma unroll
-                            for (int r = 0; r < 4; ++r)
-                                load_px<DT, GS>(s.ptr, (size_t)q.p[r] * s.pitch + cb, sdt, a[r]);
-#pragma unroll
-                            for (int i = 0; i < GS; ++i) {
-                                const float top = (1.f - q.lx) * a[0][i] + q.lx * a[1][i];
-                                const float bot = (1.f - q.lx) * a[2][i] + q.lx * a[3][i];
-                                v[i] = (1.f - q.ly) * top + q.ly * bot;
+                                for (int i = 0; i < GS; ++i) o[i] = 0;
                             }
-                        }
-                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
-                    }
-                } else if (kind == SRC_TENSOR || kind == SRC_ZINS) {
-                    constexpr int G4 = 4;
-#pragma unroll
-                    for (int k0 = 0; k0 < NE; k0 += G4) {
-                        vec raw[G4];
-                        float f[G4][GS];
-                        bool ok[G4];
-#pragma unroll
-                        for (int j = 0; j < G4; ++j) {
-                            const int pix = pix0 + (k0 + j) * PSTEP;
-                            const bool in = (k0 + j) < NE && pix < NPIX;
-                            const int pi = tabp[in ? pix : 0].p[0];
-                            ok[j] = in && pi >= 0;
-                            const size_t off = (size_t)(ok[j] ? pi : 0) * s.pitch + cb;
-                            if (sdt == DT) raw[j] = *(const vec *)((const T *)s.ptr + off);
-                            else load_px<DT, GS>(s.ptr, off, sdt, f[j]);
-                        }
-#pragma unroll
-                        for (int j = 0; j < G4; ++j) {
-                            const int pix = pix0 + (k0 + j) * PSTEP;
-                            if ((k0 + j) >= NE || pix >= NPIX) continue;
-                            vec out = sdt == DT ? raw[j] : pack_vec<DT, GS>(f[j]);
-                            if (!ok[j]) {
-#pragma unroll
-                                for (int i = 0; i < GS; ++i) out[i] = 0;
-                            }
-                            *(vec *)&patch[pix * KCP + cg * GS] = out;
+                            *(vec *)&patch[pix * KCP + cg * GS] = o;
                         }
                     }
-                } else {  // SRC_X0 ([f*d/256, I/256]) or nothing
+                    if (gi < NGW) {
 #pragma unroll
-                    for (int k = 0; k < NE; ++k) {
-                        const int pix = pix0 + k * PSTEP;
-                        if (pix >= NPIX) continue;
-                        float v[GS];
+                        for (int j = 0; j < GW; ++j) {
+                            const int k = gi * GW + j;
+                            const int e = k * 256 + tid;
+                            if (k >= EWT || e >= NW) continue;
+                            const int wcg = e % KCG, r = e / KCG;
+                            const int n = r % TN, tap = r / TN;
+                            vec o = wv[j];
+                            if (!wok[j]) {
 #pragma unroll
-                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
-                        if (kind == SRC_X0) {
-                            const int pi = tabp[pix].p[0];
-                            if (pi >= 0) {
-                                v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[pi];
-                                v[1] = (float)s.img[pi] * (1.0f / 256.0f);
+                                for (int i = 0; i < GS; ++i) o[i] = 0;
                             }
+                            *(vec *)&wl[(tap * TN + n) * KCP + wcg * GS] = o;
                         }
-                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                     }
                 }
-            }
-            // ---- weights: branch-free groups of loads (out-of-range reads the first
-            // element and is zeroed) -------------------------------------------------
-            {
-                constexpr int NW = TAPS * TN * KCG;
-                constexpr int EWT = (NW + 255) / 256;
-                constexpr int GW = 8;
+                // -- the remaining kinds, element by element: a source stored in
+                // another dtype, the network input x0, or nothing (zeros)
+                if (!fast_resize && !fast_plain) {
 #pragma unroll
-                for (int k0 = 0; k0 < EWT; k0 += GW) {
-                    vec val[GW];
-                    bool ok[GW];
+                    for (int k = 0; k < NE; ++k) {
+                        const int pix = pix0 + k * PSTEP;
+                        if (pix >= NPIX) continue;
+                        float v[GS];
 #pragma unroll
-                    for (int j = 0; j < GW; ++j) {
-                        const int e = (k0 + j) * 256 + tid;
-                        const int cg = e % KCG, r = e / KCG;
-                        const int n = r % TN, tap = r / TN;
-                        const int c = c0 + cg * GS, ng = n0 + n;
-                        ok[j] = (k0 + j) < EWT && e < NW && ng < p.n_pad && c < p.cin_pad;
-                        val[j] = *(const vec *)(wpk + (ok[j] ? ((size_t)tap * p.n_pad + ng) * p.cin_pad + c : 0));
-                    }
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        const PixSrc q = tabp[pix];
+                        if (q.p[0] >= 0) {
+                            if (kind == SRC_RESIZE) {
+                                float a4[4][GS];
 #pragma unroll
-                    for (int j = 0; j < GW; ++j) {
-                        const int e = (k0 + j) * 256 + tid;
-                        if ((k0 + j) >= EWT || e >= NW) continue;
-                        const int cg = e % KCG, r = e / KCG;
-                        const int n = r % TN, tap = r / TN;
-                        vec o = val[j];
-                        if (!ok[j]) {
+                                for (int r = 0; r < 4; ++r)
+                                    load_px<DT, GS>(s.ptr, (size_t)q.p[r] * s.pitch + cb, sdt, a4[r]);
 #pragma unroll
-                            for (int i = 0; i < GS; ++i) o[i] = 0;
+                                for (int i = 0; i < GS; ++i) {
+                                    const float top = (1.f - q.lx) * a4[0][i] + q.lx * a4[1][i];
+                                    const float bot = (1.f - q.lx) * a4[2][i] + q.lx * a4[3][i];
+                                    v[i] = (1.f - q.ly) * top + q.ly * bot;
+                                }
+                            } else if (kind == SRC_TENSOR || kind == SRC_ZINS) {
+                                load_px<DT, GS>(s.ptr, (size_t)q.p[0] * s.pitch + cb, sdt, v);
+                            } else if (kind == SRC_X0) {
+                                v[0] = s.scale0 * (float)((const uint8_t *)s.ptr)[q.p[0]];
+                                v[1] = (float)s.img[q.p[0]] * (1.0f / 256.0f);
+                            }
                         }
-                        *(vec *)&wl[(tap * TN + n) * KCP + cg * GS] = o;
+                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
                     }
                 }
             }
@@ -360,7 +429,7 @@ struct ConvTile {
             // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
 #pragma unroll
             for (int sub = 0; sub < KCM; ++sub) {
-            if (c0 + sub * KCB >= p.Cin) break;
+            if (c0 + sub * KCB >= c_end) break;
             // unrolled so the LDS operand loads of later steps are issued ahead
             // of the MFMAs of earlier ones
 #pragma unroll
@@ -393,7 +462,8 @@ struct ConvTile {
             }
         }
 
-        // ---- epilogue: bias, activation, backward terms, NHWC store ------------
+        // ---- epilogue: the FP32 partial of this channel range, or bias,
+        // activation, backward terms and the NHWC store ------------------------
 #pragma unroll
         for (int mb = 0; mb < MBW; ++mb) {
             const int oy = oy0 + wm * MBW + mb, ox = ox0 + r16;
@@ -402,43 +472,14 @@ struct ConvTile {
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
                 const int nbase = n0 + (wn * NBW + nb) * 16 + 4 * g;
-                float r[4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int n = nbase + i;
-                    float val = acc[mb][nb][i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
-                    if (p.act) val = val > 0.f ? val : 0.1f * val;
-                    if (n < p.Cout) {
-                        if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
-                        if (p.mask) {
-                            const float mv = Elem<DT>::load((const T *)p.mask + pix * p.mask_pitch + n);
-                            val *= mv > 0.f ? 1.0f : 0.1f;
-                        }
-                    }
-                    r[i] = val;
-                }
-                const size_t o = pix * p.out_pitch + p.out_coff + nbase;
-                const bool full = nbase + 4 <= p.Cout;
-                if (p.out_f32) {
-                    float *op = (float *)p.out + o;
-                    if (full && (o % 4) == 0) {
-                        *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
-                    } else {
-                        for (int i = 0; i < 4; ++i)
-                            if (nbase + i < p.Cout) op[i] = r[i];
-                    }
+                if (p.ksplit > 1) {
+                    // n_pad is a multiple of 16: the four channels are all in or all out
+                    if (nbase < p.n_pad)
+                        *(f32x4 *)&p.part[((size_t)kz * p.B * G.Ho * G.Wo + pix) * p.n_pad + nbase] =
+                            acc[mb][nb];
                 } else {
-                    T *op = (T *)p.out + o;
-                    if (full && (o % 4) == 0 && DT != SV_F32) {
-                        u16x4 w4;
-                        for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)Elem<DT>::make(r[i]);
-                        *(u16x4 *)op = w4;
-                    } else if (full && (o % 4) == 0) {
-                        *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
-                    } else {
-                        for (int i = 0; i < 4; ++i)
-                            if (nbase + i < p.Cout) op[i] = Elem<DT>::make(r[i]);
-                    }
+                    const float r[4] = {acc[mb][nb][0], acc[mb][nb][1], acc[mb][nb][2], acc[mb][nb][3]};
+                    conv_epilogue<DT>(p, pix, nbase, r);
                 }
             }
         }
@@ -452,7 +493,9 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
     using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const int ntn = (p.Cout + TN - 1) / TN;
-    const int b = blockIdx.z / ntn;
+    const int ksplit = p.ksplit > 1 ? p.ksplit : 1;
+    const int kz = blockIdx.z % ksplit, zz = blockIdx.z / ksplit;
+    const int b = zz / ntn;
     ConvGeo G;
     G.Hi = p.Hi; G.Wi = p.Wi; G.Ho = p.Ho; G.Wo = p.Wo;
     for (int i = 0; i < 2; ++i) {
@@ -461,10 +504,10 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
         G.sbase[i] = (long long)b * p.src[i].hs * p.src[i].ws;
     }
     G.obase = (long long)b * p.Ho * p.Wo;
-    G.n0 = (blockIdx.z % ntn) * TN;
+    G.n0 = (zz % ntn) * TN;
     G.oy0 = blockIdx.y * TH;
     G.ox0 = blockIdx.x * CT::TW;
-    CT::run(p, G, sm);
+    CT::run(p, G, sm, kz);
 }
 
 // Pair table: persistent loop over the stage's tiles of every pair.
@@ -497,12 +540,35 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
         G.n0 = nt * TN;
         G.oy0 = (r / tx) * TH;
         G.ox0 = (r % tx) * CT::TW;
-        CT::run(p, G, sm);
+        CT::run(p, G, sm, 0);
         (void)ntn;
     }
 }
 
-// grid <= 0: uniform launch; grid > 0: persistent launch over p.tab.
+// Second pass of a split reduction: adds the ksplit FP32 partials of four
+// channels of one pixel in range order, then applies the epilogue.
+template <int DT>
+__global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, int npix)
+{
+    const int ng = p.n_pad / 4;
+    const size_t total = (size_t)npix * ng;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const size_t pix = e / ng;
+        const int nbase = (int)(e - pix * ng) * 4;
+        if (nbase >= p.Cout) continue;
+        f32x4 s = *(const f32x4 *)&p.part[pix * p.n_pad + nbase];
+        for (int z = 1; z < p.ksplit; ++z) {
+            const f32x4 q = *(const f32x4 *)&p.part[((size_t)z * npix + pix) * p.n_pad + nbase];
+            s[0] += q[0]; s[1] += q[1]; s[2] += q[2]; s[3] += q[3];
+        }
+        const float r[4] = {s[0], s[1], s[2], s[3]};
+        conv_epilogue<DT>(p, pix, nbase, r);
+    }
+}
+
+// grid <= 0: uniform launch (split over p.ksplit channel ranges when p.ksplit > 1);
+// grid > 0: persistent launch over p.tab.
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     if (pgrid > 0) {
@@ -510,9 +576,19 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
         SV_LAUNCH_CHECK("k_conv_tab");
         return SV_OK;
     }
-    dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), p.B * cdiv(p.Cout, TN));
+    const int ksplit = p.ksplit > 1 ? p.ksplit : 1;
+    const long long gz = (long long)p.B * cdiv(p.Cout, TN) * ksplit;
+    if (gz > 65535) return SV_ERR_SHAPE;
+    dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), (unsigned)gz);
     hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
+    if (ksplit > 1) {
+        const int npix = p.B * p.Ho * p.Wo;
+        const long long work = (long long)npix * (p.n_pad / 4);
+        const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_conv_split_reduce<DT>, dim3(blocks), dim3(256), 0, st, p, npix);
+        SV_LAUNCH_CHECK("k_conv_split_reduce");
+    }
     return SV_OK;
 }
 

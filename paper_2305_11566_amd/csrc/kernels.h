@@ -93,14 +93,27 @@ struct ConvParams {
     // pair-table mode (persistent over the tiles of all pairs); NULL = uniform batch
     const PairTable *tab;
     int stage, in_level, out_level;
+    // split reduction (uniform mode only): the input channels are cut into
+    // ksplit contiguous ranges of base chunks, each workgroup writes its FP32
+    // partial sums to part[(range * B*Ho*Wo + pixel) * n_pad + n], and a second
+    // kernel adds the ranges in order and applies the epilogue.  part = NULL
+    // disables splitting; part_bytes is its capacity.
+    float *part;
+    size_t part_bytes;
+    int ksplit;
 };
 
-// cfg selects the tile shape (see conv.hip); ks = 1 or 3, stride = 1 or 2.
+// cfg selects the tile shape and the reduction split (see conv.hip); ks = 1 or
+// 3, stride = 1 or 2.
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s);
 // persistent launch over p.tab's tiles of stage p.stage with `grid` workgroups
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
                           hipStream_t s);
 void conv_cfg_tile(int cfg, int &TH, int &TN);
+int conv_num_tiles();  // tile shapes; cfg = tile + conv_num_tiles() * (ksplit - 1)
+constexpr int CONV_MAX_SPLIT = 4;
+// partial-sum buffer of a split launch: at most this many bytes per forward pass
+constexpr size_t CONV_PART_CAP = (size_t)16 << 20;
 int conv_num_cfgs();
 const char *conv_cfg_name(int cfg);
 

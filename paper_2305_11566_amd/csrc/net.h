@@ -36,7 +36,7 @@ Levels net_levels(const NetShape &ns, int H, int W);
 // beyond the recomputed encoder; at inference it lives inside the workspace.
 struct ActLayout {
     // workspace
-    size_t E1, E2, E3, T, ws_fwd;
+    size_t E1, E2, E3, T, part, part_bytes, ws_fwd;
     // saved (offsets within the saved region)
     size_t disp, img, ML, Z, G3, G2, G1, G0, saved;
 };

@@ -1,6 +1,7 @@
 // Host-side runner of the refinement network's forward pass (Table I in the
 // shape described in sv.h): one implicit-GEMM launch per layer, then the
 // final gather kernel.  No host synchronisation, no allocation.
+#include <algorithm>
 #include <atomic>
 
 #include "net.h"
@@ -74,6 +75,14 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
     a.E2 = o; o = align256(o + px(2) * ns.c2 * ns.es);
     a.E3 = o; o = align256(o + px(3) * ns.c3 * ns.es);
     a.T = o;  o = align256(o + px(0) * 12 * sizeof(float));
+    // partial sums of split-reduction launches: room for the largest layer
+    // output at the maximum split, capped
+    static const int out_level[NLAYERS] = {1, 2, 3, 3, 3, 2, 1, 0, 0};
+    size_t part = 0;
+    for (int i = 0; i < NLAYERS; ++i)
+        part = std::max(part, (size_t)CONV_MAX_SPLIT * px(out_level[i]) * ns.n_pad[i] * sizeof(float));
+    a.part_bytes = std::min(part, CONV_PART_CAP);
+    a.part = o; o = align256(o + a.part_bytes);
     a.ws_fwd = o;
     o = 0;
     a.disp = o; o = align256(o + px(0));
@@ -146,8 +155,11 @@ static ConvSrc src_x0(const uint8_t *disp, const uint8_t *img, int hs, int ws, i
 
 static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
                            int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
-                           int out_f32, int act, int cfg, hipStream_t st) {
+                           int out_f32, int act, int cfg, float *part, size_t part_bytes,
+                           hipStream_t st) {
     ConvParams p{};
+    p.part = part;
+    p.part_bytes = part_bytes;
     p.src[0] = s0; p.src[1] = s1;
     p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
     p.Cin = s0.C + (s1.kind ? s1.C : 0);
@@ -185,6 +197,7 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     char *sv_ = train ? (char *)saved : w + a.ws_fwd;      // else it lives in the workspace
     void *E1 = w + a.E1, *E2 = w + a.E2, *E3 = w + a.E3;
     float *T = (float *)(w + a.T);
+    float *part = (float *)(w + a.part);
     float *ML = (!train && ml_user) ? ml_user : (float *)(sv_ + a.ML);
     void *Z = sv_ + a.Z, *G3 = sv_ + a.G3, *G2 = sv_ + a.G2, *G1 = sv_ + a.G1, *G0 = sv_ + a.G0;
     const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
@@ -198,20 +211,20 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     const ConvSrc x0 = src_x0(disp, img, lv.h[0], lv.w[0], ns.f);
     // encoder
     ev_rec(0, 0, st);
-    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], st));
+    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
     SV_TRY(run_layer(ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
-                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], st));
+                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, st));
     ev_rec(1, 1, st);
     ev_rec(2, 0, st);
     SV_TRY(run_layer(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
-                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], st));
+                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, st));
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     ev_rec(3, 0, st);
     SV_TRY(run_layer(ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
-                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], st));
+                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, st));
     ev_rec(3, 1, st);
     ConvSrc zsrc;
     if (eps) {
@@ -224,26 +237,26 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     }
     // decoder
     ev_rec(5, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], st));
+    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, st));
     ev_rec(5, 1, st);
     ev_rec(6, 0, st);
     SV_TRY(run_layer(ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
-                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], st));
+                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, st));
     ev_rec(6, 1, st);
     ev_rec(7, 0, st);
     SV_TRY(run_layer(ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
-                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], st));
+                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, st));
     ev_rec(7, 1, st);
     ev_rec(8, 0, st);
     SV_TRY(run_layer(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], st));
+                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, st));
     ev_rec(8, 1, st);
     // final layer: per-tap 1x1 projection at the coarse level, then the gather
     ev_rec(9, 0, st);
     SV_TRY(run_layer(ns, packed, L_F, src_tensor(G0, c1, c1, 0, lv.h[0], lv.w[0], 1 + ns.dtype), x0, B,
-                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, cfg[L_F], st));
+                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, cfg[L_F], part, a.part_bytes, st));
     ev_rec(9, 1, st);
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);

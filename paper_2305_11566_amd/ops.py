@@ -91,6 +91,12 @@ def sv_num_layer_cfgs() -> int:
     return lib().sv_num_layer_cfgs()
 
 
+def sv_conv_cfg_name(cfg: int) -> str:
+    """Name of a layer configuration: the tile shape, plus "_s<k>" for a
+    k-way split of the channel reduction."""
+    return lib().sv_conv_cfg_name(cfg).decode()
+
+
 # ----------------------------------------------------------------- network
 
 def _aligned_bytes(n: int, device) -> torch.Tensor:

@@ -100,8 +100,15 @@ def test_reduced_precision_epe(dtype):
     assert epe <= 0.02 * scale + 0.05
 
 
+def _split_of(name):
+    return int(name.rsplit("_s", 1)[1]) if "_s" in name else 1
+
+
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
 def test_tile_configs_bitwise_identical(dtype):
+    """Every tile shape gives the same bits; a split channel reduction gives
+    the same bits for every tile shape at that split, and differs from the
+    unsplit result only by rounding."""
     import paper_2305_11566_amd as sv
     rng = np.random.default_rng(5)
     C, L, f, H, W = (32, 64, 128), 128, 4, 150, 330
@@ -110,12 +117,43 @@ def test_tile_configs_bitwise_identical(dtype):
     img = rng.integers(0, 256, (2, h, w)).astype(np.uint8)
     params = vae_params(C, L, 11)
     base, _ = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+    per_split = {1: base}
+    tol = 1e-5 if dtype == "f32" else 1e-2
     try:
         for cfg in range(sv.sv_num_layer_cfgs()):
             for layer in range(9):
                 sv.sv_set_layer_cfg(layer, cfg)
             out, _ = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
-            assert (out == base).all(), f"cfg {cfg}"
+            name = sv.sv_conv_cfg_name(cfg)
+            sp = _split_of(name)
+            if sp not in per_split:
+                per_split[sp] = out
+                err = normwise(out, base)
+                assert err <= tol, f"{name}: split result {err:.2e} from the unsplit one"
+            assert (out == per_split[sp]).all(), f"cfg {cfg} ({name})"
+    finally:
+        for layer in range(9):
+            sv.sv_set_layer_cfg(layer, -1)
+    assert sorted(per_split) == [1, 2, 3, 4]
+
+
+def test_split_reduction_against_oracle():
+    """Every layer forced to a 2-, 3- and 4-way channel split: FP32 forward
+    within 1e-5 normwise of the oracle at the paper-sized shape."""
+    import paper_2305_11566_amd as sv
+    names = [sv.sv_conv_cfg_name(c) for c in range(sv.sv_num_layer_cfgs())]
+    p = gen_config(2)
+    lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
+    params = vae_params((32, 64, 128), 128, 7002)
+    t = vae.forward(params, d, lo, 4, 375, 1242)
+    try:
+        for sp in (2, 3, 4):
+            cfg = names.index(f"th4_tn16_s{sp}")
+            for layer in range(9):
+                sv.sv_set_layer_cfg(layer, cfg)
+            out, _ = _gpu_forward((32, 64, 128), 128, 4, "f32", params, d, lo, 375, 1242)
+            err = normwise(out, t["out"])
+            assert err <= 1e-5, f"split {sp}: {err:.2e}"
     finally:
         for layer in range(9):
             sv.sv_set_layer_cfg(layer, -1)
