@@ -62,7 +62,7 @@ def stage_work(stage, B, dtype):
         "E1": (px[1], C1, 2 * 9), "E2": (px[2], C2, C1 * 9), "E3": (px[3], C3, C2 * 9),
         "HEAD": (px[3], 2 * LAT, C3), "G3": (px[3], C3, LAT),
         "G2": (px[2], C2, (C3 + C2) * 9), "G1": (px[1], C1, (C2 + C1) * 9),
-        "G0": (px[0], C1, (C1 + 2) * 9), "final_proj": (px[0], 9, C1 + 2),
+        "G0": (px[0], C1, (C1 + 2) * 9),
     }
     if stage in conv:
         M, N, K = conv[stage]
@@ -71,8 +71,9 @@ def stage_work(stage, B, dtype):
         return "hbm", (2.0 * B * H * W + 2 * 8.0 * px[0] + px[0]) / 1e9, "GB"
     if stage == "cost_wta":  # 6 integer ops per (pixel, d): 2 xor, 2 popcount, pack, min
         return "alu", 6.0 * D * px[0] / 1e12, "Tops"
-    if stage == "final_gather":  # write the full-res map, read 9 projections + coarse map
-        return "hbm", (4.0 * B * H * W + 36.0 * px[0] + px[0]) / 1e9, "GB"
+    if stage == "final_gather":  # write the full-res map; read G0, the coarse map and the reduced image
+        es = 4 if dtype == "f32" else 2
+        return "hbm", (4.0 * B * H * W + (C1 * es + 2.0) * px[0]) / 1e9, "GB"
     return None, 0.0, ""
 
 

@@ -46,7 +46,7 @@ struct sv_batch_plan {
     uint64_t *cl, *cr;
     uint8_t *low, *disp;
     void *E1, *E2, *E3, *G3, *G2, *G1, *G0;
-    float *ML, *T;
+    float *ML;
     hipStream_t cap_stream;
     hipGraph_t graph;
     hipGraphExec_t exec;
@@ -220,7 +220,7 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
     x0.scale0 = (float)ns.f / 256.0f;
     const ConvSrc none{};
     struct In { ConvSrc s0, s1; void *out; int pitch, f32, act; };
-    const In ins[9] = {
+    const In ins[8] = {
         {x0, none, pl->E1, c1, 0, 1},
         {tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), none, pl->E2, c2, 0, 1},
         {tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), none, pl->E3, c3, 0, 1},
@@ -229,9 +229,9 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
         {tsrc(pl->G3, SRC_RESIZE, c3, c3, 3, 0), tsrc(pl->E2, SRC_TENSOR, c2, c2, 2, 0), pl->G2, c2, 0, 1},
         {tsrc(pl->G2, SRC_RESIZE, c2, c2, 2, 0), tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), pl->G1, c1, 0, 1},
         {tsrc(pl->G1, SRC_RESIZE, c1, c1, 1, 0), x0, pl->G0, c1, 0, 1},
-        {tsrc(pl->G0, SRC_TENSOR, c1, c1, 0, 1 + ns.dtype), x0, pl->T, 12, 1, 0},
     };
-    for (int k = 0; k < 9; ++k) {
+    // the final layer's projection runs inside the final gather
+    for (int k = 0; k < 8; ++k) {
         const LayerRun &run = kRuns[k];
         const int li = run.li;
         ConvParams p{};
@@ -248,9 +248,9 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
                             pl->grid[run.stage], st);
         if (r != SV_OK) return r;
     }
-    return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], pl->T, 12, pl->disp,
-                            (float)ns.f / 256.0f, (const float *)((const char *)packed + ns.b_off[L_F]),
-                            st);
+    return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], ns.dtype, pl->G0, c1, pl->disp, pl->low,
+                            (const float *)((const char *)packed + ns.w_off[L_F]), ns.cin_pad[L_F],
+                            ns.f, (const float *)((const char *)packed + ns.b_off[L_F]), st);
 }
 
 static void destroy_graph(sv_batch_plan *pl) {
@@ -346,7 +346,6 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     const size_t o_E3 = take(pl->cap[3] * ns.c3 * es), o_ML = take(pl->cap[3] * 2 * ns.L * 4);
     const size_t o_G3 = take(pl->cap[3] * ns.c3 * es), o_G2 = take(pl->cap[2] * ns.c2 * es);
     const size_t o_G1 = take(pl->cap[1] * ns.c1 * es), o_G0 = take(pl->cap[0] * ns.c1 * es);
-    const size_t o_T = take(pl->cap[0] * 12 * 4);
     hipError_t e = hipMalloc(&pl->dev, off);
     if (e != hipSuccess) {
         delete pl;
@@ -358,7 +357,6 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     pl->low = (uint8_t *)(d + o_low); pl->disp = (uint8_t *)(d + o_disp);
     pl->E1 = d + o_E1; pl->E2 = d + o_E2; pl->E3 = d + o_E3; pl->ML = (float *)(d + o_ML);
     pl->G3 = d + o_G3; pl->G2 = d + o_G2; pl->G1 = d + o_G1; pl->G0 = d + o_G0;
-    pl->T = (float *)(d + o_T);
     if ((e = hipHostMalloc((void **)&pl->tab_host, sizeof(PairTable), hipHostMallocDefault)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming)) != hipSuccess) {
@@ -522,7 +520,10 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
             (void)sv_profile_enable(0);
             for (int i = 0; i < NLAYERS && r == SV_OK; ++i) {
                 const int s = stage_of[i];
-                const float t = cnt[s] ? ms[s] / cnt[s] : 1e30f;
+                if (cnt[s] == 0) continue;  // a layer without a launch of its own
+                // a split that falls back to one pass repeats an unsplit candidate
+                if (net_layer_split(ns, i, c, B, H, W) != c / conv_num_tiles() + 1) continue;
+                const float t = ms[s] / cnt[s];
                 if (t < best_t[i]) { best_t[i] = t; best_cfg[i] = c; }
                 if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-12s %8.2f us\n",
                                      ns.dtype, B, H, W, i, conv_cfg_name(c), t * 1e3f);

@@ -73,17 +73,23 @@ static sv_status launch_any(int dtype, int ks, int stride, int tile, const ConvP
     }
 }
 
-sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
-    if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
-    ConvParams p = p0;
+int conv_effective_split(int dtype, int cfg, int Cin, long long npix, int n_pad, const float *part,
+                         size_t part_bytes) {
     int ksplit = cfg / kNumTiles + 1;
     // at most one split per base chunk of input channels, and only when the
     // partial sums fit the caller's buffer; otherwise one pass
     const int kcb = dtype == SV_F32 ? 16 : 32;
-    ksplit = std::min(ksplit, cdiv(p.Cin, kcb));
-    const size_t need = (size_t)ksplit * p.B * p.Ho * p.Wo * p.n_pad * sizeof(float);
-    if (!p.part || need > p.part_bytes) ksplit = 1;
-    p.ksplit = ksplit;
+    ksplit = std::min(ksplit, cdiv(Cin, kcb));
+    const size_t need = (size_t)ksplit * (size_t)npix * n_pad * sizeof(float);
+    if (!part || need > part_bytes) ksplit = 1;
+    return ksplit;
+}
+
+sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
+    if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    ConvParams p = p0;
+    p.ksplit = conv_effective_split(dtype, cfg, p.Cin, (long long)p.B * p.Ho * p.Wo, p.n_pad, p.part,
+                                    p.part_bytes);
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
 }
 

@@ -1,4 +1,7 @@
 // Network glue: the final upsampling layer and the reparameterisation.
+#include <algorithm>
+#include <mutex>
+
 #include "kernels.h"
 
 namespace sv {
@@ -6,46 +9,86 @@ namespace sv {
 // Final layer (Table I, "UP-SAMPLING"): R = conv3x3(resize([G0, x0] -> H x W))
 // to one channel, plus the bilinear upscaling of the coarse map (the paper's
 // "Mini+Linear" baseline, Sec. IV-C) as the residual base.  Convolution and
-// resize are both linear, so with T_t(i) = sum_c W[c, t] X[c](i) computed at
-// the coarse level (one 1x1 output channel per tap t = (u, v)),
+// resize are both linear, so with the per-tap projections
+//   T_t(i) = sum_c W_F[c, t] X[c](i),  X = [G0, x0],  t = (u, v) in 3 x 3,
+// computed at the coarse level,
 //   R(Y, X) = sum_t [inside] resize(T_t)(Y + u - 1, X + v - 1).
-// Each full-resolution pixel then gathers 9 bilinear samples of the 9-channel
-// map T instead of 3 x 3 x (c1 + 2) upsampled values.
+// Bilinear resizing is separable as well, so the sum is taken in two passes:
+//   S_v(Y, x) = sum_u [row Y + u - 1 inside] lerp_rows(T_uv)(Y + u - 1, x)
+// on the coarse columns x, then
+//   R(Y, X) = sum_v [column X + v - 1 inside] lerp_cols(S_v(Y, .))(X + v - 1).
 //
-// One workgroup = FIN_TILE_W x FIN_TILE_H output pixels.  The bilinear indices
-// and weights of the tile's FIN_TILE_W + 2 columns and FIN_TILE_H + 2 rows
-// (the 3 x 3 neighbourhood reaches one pixel past each edge) are computed once
-// into LDS, together with the coarse window of T and of the coarse disparity
-// that the tile touches; every pixel then reads only LDS.  Since w <= W, the
-// lower bilinear index grows by at most one per output pixel, which bounds
-// the coarse window by (FIN_TILE_W + 3) x (FIN_TILE_H + 3).
+// One workgroup = FIN_TILE_W x FIN_TILE_H output pixels and everything in
+// LDS: the bilinear indices and weights of the tile's FIN_TILE_W + 2 columns
+// and FIN_TILE_H + 2 rows (the 3 x 3 neighbourhood reaches one pixel past
+// each edge), the 9 projections T and the coarse disparity on the coarse
+// window the tile touches (T computed there from G0 and x0 with the FP32
+// weights), then S.  For o in a run of K + 1 consecutive output positions
+// (K = tile + 1) the lower bilinear index grows by at most ceil(K n_in / n_out),
+// so with n_in = ceil(n_out / f) the window spans at most ceil(K / f) + 3 coarse
+// positions, and never more than K + 2: fin_window() gives that bound and
+// sizes the dynamic LDS.
 constexpr int FIN_CX = FIN_TILE_W + 2, FIN_CY = FIN_TILE_H + 2;
-constexpr int FIN_PW = FIN_TILE_W + 3, FIN_PH = FIN_TILE_H + 3;
 constexpr int FIN_THREADS = 256;
 static_assert(FIN_TILE_W == 64 && FIN_TILE_H % (FIN_THREADS / 64) == 0, "final tile shape");
 
-struct FinSmem {
-    float T[9][FIN_PH][FIN_PW];
-    float d[FIN_PH][FIN_PW];
+static inline void fin_window(int f, int &ph, int &pw) {
+    ph = std::min(FIN_TILE_H + 3, cdiv(FIN_TILE_H + 1, f) + 3);
+    pw = std::min(FIN_TILE_W + 3, cdiv(FIN_TILE_W + 1, f) + 3);
+}
+// dynamic LDS (floats): T[9][ph][pw], d[ph][pw], S[FIN_TILE_H][3][pw], D[FIN_TILE_H][pw],
+// W_F[9][c1 + 2]
+static inline size_t fin_lds_bytes(int f, int c1) {
+    int ph, pw;
+    fin_window(f, ph, pw);
+    return sizeof(float) * ((size_t)10 * ph * pw + (size_t)4 * FIN_TILE_H * pw + 9 * (c1 + 2));
+}
+
+struct FinTab {
     int cx0[FIN_CX], cx1[FIN_CX], cy0[FIN_CY], cy1[FIN_CY];  // -1: outside the image
     float clx[FIN_CX], cly[FIN_CY];
 };
 
-__device__ __forceinline__ void final_tile(FinSmem &sm, const float *__restrict__ Tb, int tpitch,
-                                           const uint8_t *__restrict__ db, float scale0,
-                                           float bias, int h, int w, int H, int W, int X0,
-                                           int Y0, float *__restrict__ out)
+// Loads 8 consecutive stored channels as FP32.
+template <int DT>
+__device__ __forceinline__ void load8(const typename Elem<DT>::T *p, float (&v)[8]) {
+    if constexpr (DT == SV_F32) {
+        const f32x4 a = *(const f32x4 *)p, b = *(const f32x4 *)(p + 4);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        v[4] = b[0]; v[5] = b[1]; v[6] = b[2]; v[7] = b[3];
+    } else {
+        const u16x8 q = *(const u16x8 *)p;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = Elem<DT>::load((const typename Elem<DT>::T *)&q + i);
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int PWm,
+                                           const typename Elem<DT>::T *__restrict__ G0, int c1,
+                                           const uint8_t *__restrict__ db,
+                                           const uint8_t *__restrict__ ib,
+                                           const float *__restrict__ wF, int wf_pitch,
+                                           float scale0, float bias, int h, int w, int H, int W,
+                                           int X0, int Y0, float *__restrict__ out)
 {
     const int tid = threadIdx.x;
-    // coarse window origin: the lower index of the first column / row in range
-    int xa, ya, i1;
+    float *sT = dyn;                           // [9][PHm][PWm]
+    float *sd = sT + 9 * PHm * PWm;            // [PHm][PWm]
+    float *sS = sd + PHm * PWm;                // [FIN_TILE_H][3][PWm]
+    float *sD = sS + FIN_TILE_H * 3 * PWm;     // [FIN_TILE_H][PWm]
+    float *sW = sD + FIN_TILE_H * PWm;         // [9][c1 + 2]
+    const int cw = c1 + 2;
+    // coarse window: from the lower index of the first column / row in range to
+    // the upper index of the last
+    int xa, ya, xb, yb, i1;
     float lam;
     bilin(max(X0 - 1, 0), w, W, xa, i1, lam);
     bilin(max(Y0 - 1, 0), h, H, ya, i1, lam);
-    int xb, yb;
     bilin(min(X0 + FIN_TILE_W, W - 1), w, W, i1, xb, lam);
     bilin(min(Y0 + FIN_TILE_H, H - 1), h, H, i1, yb, lam);
     const int pw = xb - xa + 1, ph = yb - ya + 1;
+    if (ph > PHm || pw > PWm) return;  // excluded by the window bound
     if (tid < FIN_CX) {
         const int X = X0 - 1 + tid;
         int x0 = -1, x1 = -1;
@@ -55,9 +98,9 @@ __device__ __forceinline__ void final_tile(FinSmem &sm, const float *__restrict_
             x0 -= xa;
             x1 -= xa;
         }
-        sm.cx0[tid] = x0;
-        sm.cx1[tid] = x1;
-        sm.clx[tid] = lx;
+        tb.cx0[tid] = x0;
+        tb.cx1[tid] = x1;
+        tb.clx[tid] = lx;
     } else if (tid >= 128 && tid < 128 + FIN_CY) {
         const int r = tid - 128, Y = Y0 - 1 + r;
         int y0 = -1, y1 = -1;
@@ -67,20 +110,75 @@ __device__ __forceinline__ void final_tile(FinSmem &sm, const float *__restrict_
             y0 -= ya;
             y1 -= ya;
         }
-        sm.cy0[r] = y0;
-        sm.cy1[r] = y1;
-        sm.cly[r] = ly;
+        tb.cy0[r] = y0;
+        tb.cy1[r] = y1;
+        tb.cly[r] = ly;
     }
-    for (int e = tid; e < ph * pw * 9; e += FIN_THREADS) {
-        const int t = e % 9, q = e / 9;
-        const int r = q / pw, c = q - r * pw;
-        sm.T[t][r][c] = Tb[((size_t)(ya + r) * w + xa + c) * tpitch + t];
+    for (int e = tid; e < 9 * cw; e += FIN_THREADS) {
+        const int t = e / cw, c = e - t * cw;
+        sW[e] = wF[(size_t)t * wf_pitch + c];
     }
     for (int e = tid; e < ph * pw; e += FIN_THREADS) {
         const int r = e / pw, c = e - r * pw;
-        sm.d[r][c] = (float)db[(size_t)(ya + r) * w + xa + c];
+        sd[r * PWm + c] = (float)db[(size_t)(ya + r) * w + xa + c];
     }
     __syncthreads();
+    // T on the window: work item = (coarse pixel, group of three taps)
+    for (int e = tid; e < ph * pw * 3; e += FIN_THREADS) {
+        const int q = e / 3, tg = e - q * 3;
+        const int r = q / pw, c = q - r * pw;
+        const size_t gp = (size_t)(ya + r) * w + xa + c;
+        const float *w0 = sW + (3 * tg) * cw, *w1 = w0 + cw, *w2 = w1 + cw;
+        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        const typename Elem<DT>::T *g = G0 + gp * c1;
+        for (int c0 = 0; c0 < c1; c0 += 8) {
+            float v[8];
+            load8<DT>(g + c0, v);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                a0 += w0[c0 + i] * v[i];
+                a1 += w1[c0 + i] * v[i];
+                a2 += w2[c0 + i] * v[i];
+            }
+        }
+        const float x0d = scale0 * sd[r * PWm + c], x0i = (float)ib[gp] * (1.0f / 256.0f);
+        a0 += w0[c1] * x0d + w0[c1 + 1] * x0i;
+        a1 += w1[c1] * x0d + w1[c1 + 1] * x0i;
+        a2 += w2[c1] * x0d + w2[c1 + 1] * x0i;
+        sT[((3 * tg + 0) * PHm + r) * PWm + c] = a0;
+        sT[((3 * tg + 1) * PHm + r) * PWm + c] = a1;
+        sT[((3 * tg + 2) * PHm + r) * PWm + c] = a2;
+    }
+    __syncthreads();
+    // vertical pass: S_v(Y, x) and the residual base's row interpolation D(Y, x)
+    for (int e = tid; e < FIN_TILE_H * 4 * pw; e += FIN_THREADS) {
+        const int ty = e / (4 * pw), rem = e - ty * 4 * pw;
+        const int v = rem / pw, c = rem - v * pw;
+        if (v < 3) {
+            float s = 0.f;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int y0 = tb.cy0[ty + u];
+                if (y0 < 0) continue;
+                const int y1 = tb.cy1[ty + u];
+                const float ly = tb.cly[ty + u];
+                const float *tt = sT + (u * 3 + v) * PHm * PWm;
+                s += (1.f - ly) * tt[y0 * PWm + c] + ly * tt[y1 * PWm + c];
+            }
+            sS[(ty * 3 + v) * PWm + c] = s;
+        } else {
+            const int y0 = tb.cy0[ty + 1];
+            float s = 0.f;
+            if (y0 >= 0) {
+                const int y1 = tb.cy1[ty + 1];
+                const float ly = tb.cly[ty + 1];
+                s = (1.f - ly) * sd[y0 * PWm + c] + ly * sd[y1 * PWm + c];
+            }
+            sD[ty * PWm + c] = s;
+        }
+    }
+    __syncthreads();
+    // horizontal pass, one output pixel per thread and row
     const int tx = tid & 63;
     const int X = X0 + tx;
 #pragma unroll
@@ -89,52 +187,50 @@ __device__ __forceinline__ void final_tile(FinSmem &sm, const float *__restrict_
         if (X < W && Y < H) {
             float acc = bias;
 #pragma unroll
-            for (int u = 0; u < 3; ++u) {
-                const int y0 = sm.cy0[ty + u];
-                if (y0 < 0) continue;
-                const int y1 = sm.cy1[ty + u];
-                const float ly = sm.cly[ty + u];
-#pragma unroll
-                for (int v = 0; v < 3; ++v) {
-                    const int x0 = sm.cx0[tx + v];
-                    if (x0 < 0) continue;
-                    const int x1 = sm.cx1[tx + v];
-                    const float lx = sm.clx[tx + v];
-                    const int t = u * 3 + v;
-                    const float top = (1.f - lx) * sm.T[t][y0][x0] + lx * sm.T[t][y0][x1];
-                    const float bot = (1.f - lx) * sm.T[t][y1][x0] + lx * sm.T[t][y1][x1];
-                    acc += (1.f - ly) * top + ly * bot;
-                }
+            for (int v = 0; v < 3; ++v) {
+                const int x0 = tb.cx0[tx + v];
+                if (x0 < 0) continue;
+                const int x1 = tb.cx1[tx + v];
+                const float lx = tb.clx[tx + v];
+                const float *ss = sS + (ty * 3 + v) * PWm;
+                acc += (1.f - lx) * ss[x0] + lx * ss[x1];
             }
-            const int y0 = sm.cy0[ty + 1], y1 = sm.cy1[ty + 1];
-            const int x0 = sm.cx0[tx + 1], x1 = sm.cx1[tx + 1];
-            const float ly = sm.cly[ty + 1], lx = sm.clx[tx + 1];
-            const float top = (1.f - lx) * sm.d[y0][x0] + lx * sm.d[y0][x1];
-            const float bot = (1.f - lx) * sm.d[y1][x0] + lx * sm.d[y1][x1];
-            const float base = scale0 * ((1.f - ly) * top + ly * bot);
+            const int x0 = tb.cx0[tx + 1], x1 = tb.cx1[tx + 1];
+            const float lx = tb.clx[tx + 1];
+            const float *dd = sD + ty * PWm;
+            const float base = scale0 * ((1.f - lx) * dd[x0] + lx * dd[x1]);
             out[(size_t)Y * W + X] = 256.0f * (acc + base);
         }
     }
     __syncthreads();  // the LDS is reused by the next tile of a persistent loop
 }
 
+template <int DT>
 __global__ void __launch_bounds__(FIN_THREADS)
-k_final(const float *__restrict__ T, int tpitch, const uint8_t *__restrict__ disp, float scale0,
-        const float *__restrict__ biasF, int h, int w, int H, int W, float *__restrict__ out)
+k_final(const typename Elem<DT>::T *__restrict__ G0, int c1, const uint8_t *__restrict__ disp,
+        const uint8_t *__restrict__ img, const float *__restrict__ wF, int wf_pitch, float scale0,
+        const float *__restrict__ biasF, int h, int w, int H, int W, int PHm, int PWm,
+        float *__restrict__ out)
 {
-    __shared__ FinSmem sm;
+    extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
+    __shared__ FinTab tb;
     const int b = blockIdx.z;
-    final_tile(sm, T + (size_t)b * h * w * tpitch, tpitch, disp + (size_t)b * h * w, scale0,
-               biasF[0], h, w, H, W, blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H,
-               out + (size_t)b * H * W);
+    const size_t o = (size_t)b * h * w;
+    final_tile<DT>(fin_dyn, tb, PHm, PWm, G0 + o * c1, c1, disp + o, img + o, wF, wf_pitch, scale0,
+                   biasF[0], h, w, H, W, blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H,
+                   out + (size_t)b * H * W);
 }
 
 // Persistent variant over the pair table; each pair writes its own output map.
+template <int DT>
 __global__ void __launch_bounds__(FIN_THREADS)
-k_final_tab(const PairTable *__restrict__ tab, const float *__restrict__ T, int tpitch,
-            const uint8_t *__restrict__ disp, float scale0, const float *__restrict__ biasF)
+k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__restrict__ G0, int c1,
+            const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img,
+            const float *__restrict__ wF, int wf_pitch, float scale0,
+            const float *__restrict__ biasF, int PHm, int PWm)
 {
-    __shared__ FinSmem sm;
+    extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
+    __shared__ FinTab tb;
     const int n = tab->n;
     const int *cum = tab->cum[BS_FINAL];
     const int total = cum[n];
@@ -144,27 +240,81 @@ k_final_tab(const PairTable *__restrict__ tab, const float *__restrict__ T, int 
         const PairGeo &g = tab->pair[i];
         const int local = t - cum[i];
         const int tx = cdiv_d(g.W, FIN_TILE_W);
-        final_tile(sm, T + (size_t)g.off[0] * tpitch, tpitch, disp + g.off[0], scale0, bias,
-                   g.h[0], g.w[0], g.H, g.W, (local % tx) * FIN_TILE_W, (local / tx) * FIN_TILE_H,
-                   g.out);
+        const size_t o = (size_t)g.off[0];
+        final_tile<DT>(fin_dyn, tb, PHm, PWm, G0 + o * c1, c1, disp + o, img + o, wF, wf_pitch,
+                       scale0, bias, g.h[0], g.w[0], g.H, g.W, (local % tx) * FIN_TILE_W,
+                       (local / tx) * FIN_TILE_H, g.out);
     }
 }
 
-sv_status launch_final_tab(const PairTable *tab, int grid, const float *T, int tpitch,
-                           const uint8_t *disp, float scale0, const float *biasF, hipStream_t s)
+// The dynamic LDS of the final layer stays under 80 KB (f = 1, c1 = 256); the
+// kernels are allowed that much once, before their first launch.
+static sv_status fin_allow_lds() {
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [] {
+        const int bytes = 96 * 1024;
+        const void *fns[6] = {(const void *)k_final<SV_F32>,     (const void *)k_final<SV_BF16>,
+                              (const void *)k_final<SV_F16>,     (const void *)k_final_tab<SV_F32>,
+                              (const void *)k_final_tab<SV_BF16>, (const void *)k_final_tab<SV_F16>};
+        for (const void *fn : fns) {
+            hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+            if (e != hipSuccess && err == hipSuccess) err = e;
+        }
+    });
+    if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute(k_final)");
+    return SV_OK;
+}
+
+sv_status launch_final_tab(const PairTable *tab, int grid, int dtype, const void *G0, int c1,
+                           const uint8_t *disp, const uint8_t *img, const float *wF, int wf_pitch,
+                           int f, const float *biasF, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_final_tab, dim3(grid), dim3(FIN_THREADS), 0, s, tab, T, tpitch, disp, scale0, biasF);
+    if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    int PHm, PWm;
+    fin_window(f, PHm, PWm);
+    const size_t lds = fin_lds_bytes(f, c1);
+    const float scale0 = (float)f / 256.0f;
+    switch (dtype) {
+#define SV_FT(D)                                                                                      \
+    case D:                                                                                           \
+        hipLaunchKernelGGL(k_final_tab<D>, dim3(grid), dim3(FIN_THREADS), lds, s, tab,                \
+                           (const typename Elem<D>::T *)G0, c1, disp, img, wF, wf_pitch, scale0,      \
+                           biasF, PHm, PWm);                                                          \
+        break;
+        SV_FT(SV_F32)
+        SV_FT(SV_BF16)
+        SV_FT(SV_F16)
+#undef SV_FT
+    default: return SV_ERR_DTYPE;
+    }
     SV_LAUNCH_CHECK("k_final_tab");
     return SV_OK;
 }
 
-sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float scale0,
-                       const float *biasF, int B, int h, int w, int H, int W, float *out,
-                       hipStream_t s)
+sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
+                       const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
+                       int w, int H, int W, float *out, hipStream_t s)
 {
+    if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    int PHm, PWm;
+    fin_window(f, PHm, PWm);
+    const size_t lds = fin_lds_bytes(f, c1);
+    const float scale0 = (float)f / 256.0f;
     dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
-    hipLaunchKernelGGL(k_final, grid, dim3(FIN_THREADS), 0, s, T, tpitch, disp, scale0, biasF, h, w, H, W,
-                       out);
+    switch (dtype) {
+#define SV_FU(D)                                                                                      \
+    case D:                                                                                           \
+        hipLaunchKernelGGL(k_final<D>, grid, dim3(FIN_THREADS), lds, s,                               \
+                           (const typename Elem<D>::T *)G0, c1, disp, img, wF, wf_pitch, scale0,      \
+                           biasF, h, w, H, W, PHm, PWm, out);                                         \
+        break;
+        SV_FU(SV_F32)
+        SV_FU(SV_BF16)
+        SV_FU(SV_F16)
+#undef SV_FU
+    default: return SV_ERR_DTYPE;
+    }
     SV_LAUNCH_CHECK("k_final");
     return SV_OK;
 }

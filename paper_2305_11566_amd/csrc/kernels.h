@@ -112,6 +112,9 @@ sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvPara
 void conv_cfg_tile(int cfg, int &TH, int &TN);
 int conv_num_tiles();  // tile shapes; cfg = tile + conv_num_tiles() * (ksplit - 1)
 constexpr int CONV_MAX_SPLIT = 4;
+// the split a launch of configuration cfg actually uses (1 when it cannot split)
+int conv_effective_split(int dtype, int cfg, int Cin, long long npix, int n_pad, const float *part,
+                         size_t part_bytes);
 // partial-sum buffer of a split launch: at most this many bytes per forward pass
 constexpr size_t CONV_PART_CAP = (size_t)16 << 20;
 int conv_num_cfgs();
@@ -128,13 +131,17 @@ sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n
 constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F16 = 1 + SV_F16;
 
 // ---- network glue ---------------------------------------------------------------
-// out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X))
-sv_status launch_final(const float *T, int tpitch, const uint8_t *disp, float scale0,
-                       const float *biasF, int B, int h, int w, int H, int W, float *out,
-                       hipStream_t s);
-sv_status launch_final_tab(const PairTable *tab, int grid, const float *T, int tpitch,
-                           const uint8_t *disp, float scale0, const float *biasF, hipStream_t s);
-constexpr int FIN_TILE_W = 64, FIN_TILE_H = 8;
+// The final layer from the coarse maps: with T[t] = W_F[t] . [G0, x0] (FP32
+// weights [9][wf_pitch], x0 = [f * d / 256, img / 256]),
+// out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X)).
+// G0: NHWC [B][h][w][c1] in dtype; disp, img: uint8 [B][h][w].
+sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
+                       const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
+                       int w, int H, int W, float *out, hipStream_t s);
+sv_status launch_final_tab(const PairTable *tab, int grid, int dtype, const void *G0, int c1,
+                           const uint8_t *disp, const uint8_t *img, const float *wF, int wf_pitch,
+                           int f, const float *biasF, hipStream_t s);
+constexpr int FIN_TILE_W = 64, FIN_TILE_H = 16;
 sv_status launch_reparam(const float *ml, const float *eps, int npix, int L, void *z, int dtype,
                          hipStream_t s);
 

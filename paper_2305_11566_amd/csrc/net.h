@@ -36,7 +36,7 @@ Levels net_levels(const NetShape &ns, int H, int W);
 // beyond the recomputed encoder; at inference it lives inside the workspace.
 struct ActLayout {
     // workspace
-    size_t E1, E2, E3, T, part, part_bytes, ws_fwd;
+    size_t E1, E2, E3, part, part_bytes, ws_fwd;
     // saved (offsets within the saved region)
     size_t disp, img, ML, Z, G3, G2, G1, G0, saved;
 };
@@ -52,6 +52,8 @@ int net_default_cfg(const NetShape &ns, int layer, int M);
 // explicit override, else the autotune cache entry for this shape, else the
 // default.
 void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg);
+// The reduction split a layer's configuration gives in a forward pass (1: none).
+int net_layer_split(const NetShape &ns, int layer, int cfg, int B, int H, int W);
 // The autotune cache entry for this network and image size with the nearest
 // batch size; false if there is none.
 bool tuned_lookup(const NetShape &ns, int B, int H, int W, int *cfg, int *dsplit);

@@ -74,12 +74,11 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
     a.E1 = o; o = align256(o + px(1) * ns.c1 * ns.es);
     a.E2 = o; o = align256(o + px(2) * ns.c2 * ns.es);
     a.E3 = o; o = align256(o + px(3) * ns.c3 * ns.es);
-    a.T = o;  o = align256(o + px(0) * 12 * sizeof(float));
     // partial sums of split-reduction launches: room for the largest layer
     // output at the maximum split, capped
     static const int out_level[NLAYERS] = {1, 2, 3, 3, 3, 2, 1, 0, 0};
     size_t part = 0;
-    for (int i = 0; i < NLAYERS; ++i)
+    for (int i = 0; i < L_F; ++i)
         part = std::max(part, (size_t)CONV_MAX_SPLIT * px(out_level[i]) * ns.n_pad[i] * sizeof(float));
     a.part_bytes = std::min(part, CONV_PART_CAP);
     a.part = o; o = align256(o + a.part_bytes);
@@ -132,6 +131,20 @@ void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg) {
         const int ov = net_get_cfg_override(ns.dtype, i);
         cfg[i] = ov >= 0 ? ov : (have ? tuned[i] : net_default_cfg(ns, i, 0));
     }
+}
+
+// The reduction split layer `layer` gets from configuration cfg in a forward
+// pass of batch B at H x W (1: no split).
+int net_layer_split(const NetShape &ns, int layer, int cfg, int B, int H, int W) {
+    if (layer < 0 || layer >= L_F) return 1;
+    static const int out_level[NLAYERS] = {1, 2, 3, 3, 3, 2, 1, 0, 0};
+    const Levels lv = net_levels(ns, H, W);
+    const ActLayout a = net_act_layout(ns, lv, B);
+    const int k = out_level[layer];
+    const long long npix = (long long)B * lv.h[k] * lv.w[k];
+    const int dt = ns.dtype;
+    static float dummy;
+    return conv_effective_split(dt, cfg, ns.ly[layer].cin, npix, ns.n_pad[layer], &dummy, a.part_bytes);
 }
 
 // ---- forward ------------------------------------------------------------------------
@@ -196,7 +209,6 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     const bool train = saved != nullptr;                   // keep what the backward needs
     char *sv_ = train ? (char *)saved : w + a.ws_fwd;      // else it lives in the workspace
     void *E1 = w + a.E1, *E2 = w + a.E2, *E3 = w + a.E3;
-    float *T = (float *)(w + a.T);
     float *part = (float *)(w + a.part);
     float *ML = (!train && ml_user) ? ml_user : (float *)(sv_ + a.ML);
     void *Z = sv_ + a.Z, *G3 = sv_ + a.G3, *G2 = sv_ + a.G2, *G1 = sv_ + a.G1, *G0 = sv_ + a.G0;
@@ -253,14 +265,11 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     SV_TRY(run_layer(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
                      lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, st));
     ev_rec(8, 1, st);
-    // final layer: per-tap 1x1 projection at the coarse level, then the gather
-    ev_rec(9, 0, st);
-    SV_TRY(run_layer(ns, packed, L_F, src_tensor(G0, c1, c1, 0, lv.h[0], lv.w[0], 1 + ns.dtype), x0, B,
-                     lv.h[0], lv.w[0], lv.h[0], lv.w[0], T, 12, 1, 0, cfg[L_F], part, a.part_bytes, st));
-    ev_rec(9, 1, st);
+    // final layer: per-tap projections of [G0, x0] and the gather, one kernel
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);
-    SV_TRY(launch_final(T, 12, disp, (float)ns.f / 256.0f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
+    SV_TRY(launch_final(ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
+                        ns.cin_pad[L_F], ns.f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
     ev_rec(10, 1, st);
     if (train && ml_user)
         SV_HIP(hipMemcpyAsync(ml_user, ML, (size_t)B * lv.h[3] * lv.w[3] * 2 * L * sizeof(float),
