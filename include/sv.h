@@ -283,7 +283,8 @@ int sv_num_layer_cfgs(void);
  * max_calls launches of every stage records a hipEvent pair around itself on
  * its stream.  Stages: 0 census, 1 cost + WTA, then the network's launches
  * 2 E1, 3 E2, 4 E3, 5 HEAD, 6 reparameterisation (training), 7 G3, 8 G2,
- * 9 G1, 10 G0, 11 final-layer projection, 12 final gather.
+ * 9 G1, 10 G0, 11 (not recorded: the final layer's projection runs inside
+ * stage 12), 12 final layer (projection and gather).
  * sv_profile_read synchronises on the recorded events, writes the summed
  * milliseconds and launch counts of each stage into ms_sum[13] / counts[13]
  * and restarts the counts.  sv_profile_enable(0) disables and frees.
