@@ -59,9 +59,11 @@ namespace sv {
 
 // ---------------------------------------------------------------------------
 // Autotune cache: a text file, one entry per line
-//   gfx950|dt<dtype>|c<c1>,<c2>,<c3>|L<latent>|f<factor>|B<batch>|<H>x<W> <dsplit> <cfg0>,...,<cfg8>
-// loaded once per process into memory; lookups take the entry of the same
-// network and image size with the nearest batch size.
+//   gfx950|dt<dtype>|c<c1>,<c2>,<c3>|L<latent>|f<factor>|B<batch>|<H>x<W> <dsplit> <name0>,...,<name8>
+// with the layers' configurations by name (sv_conv_cfg_name), loaded once per
+// process into memory; lookups take the entry of the same network and image
+// size with the nearest batch size.  A line that does not parse, or names a
+// configuration this library does not have, is ignored.
 // ---------------------------------------------------------------------------
 struct TuneEntry {
     int dt, c1, c2, c3, L, f, B, H, W, dsplit, cfg[NLAYERS];
@@ -77,21 +79,36 @@ static std::string cache_path() {
     return std::string(home ? home : "/tmp") + "/.cache/sv_autotune.tsv";
 }
 
+static int cfg_by_name(const std::string &name) {
+    for (int c = 0; c < conv_num_cfgs(); ++c)
+        if (name == conv_cfg_name(c)) return c;
+    return -1;
+}
+
 static bool parse_entry(const char *line, TuneEntry &t) {
-    const int m = sscanf(line, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d %d %d,%d,%d,%d,%d,%d,%d,%d,%d",
-                         &t.dt, &t.c1, &t.c2, &t.c3, &t.L, &t.f, &t.B, &t.H, &t.W, &t.dsplit,
-                         &t.cfg[0], &t.cfg[1], &t.cfg[2], &t.cfg[3], &t.cfg[4], &t.cfg[5],
-                         &t.cfg[6], &t.cfg[7], &t.cfg[8]);
-    if (m != 10 + NLAYERS) return false;
+    char names[400];
+    const int m = sscanf(line, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d %d %399s", &t.dt, &t.c1, &t.c2,
+                         &t.c3, &t.L, &t.f, &t.B, &t.H, &t.W, &t.dsplit, names);
+    if (m != 11) return false;
     bool ok = (t.dsplit == 1 || t.dsplit == 2 || t.dsplit == 4 || t.dsplit == 8) && t.B > 0;
-    for (int i = 0; i < NLAYERS; ++i) ok = ok && t.cfg[i] >= 0 && t.cfg[i] < conv_num_cfgs();
+    std::string rest(names);
+    size_t pos = 0;
+    for (int i = 0; i < NLAYERS && ok; ++i) {
+        const size_t comma = rest.find(',', pos);
+        const bool last = i == NLAYERS - 1;
+        if (last != (comma == std::string::npos)) return false;
+        t.cfg[i] = cfg_by_name(rest.substr(pos, last ? std::string::npos : comma - pos));
+        ok = t.cfg[i] >= 0;
+        pos = comma + 1;
+    }
     return ok;
 }
 
 static void format_entry(const TuneEntry &t, char *buf, size_t n) {
-    snprintf(buf, n, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d\t%d\t%d,%d,%d,%d,%d,%d,%d,%d,%d\n", t.dt,
-             t.c1, t.c2, t.c3, t.L, t.f, t.B, t.H, t.W, t.dsplit, t.cfg[0], t.cfg[1], t.cfg[2],
-             t.cfg[3], t.cfg[4], t.cfg[5], t.cfg[6], t.cfg[7], t.cfg[8]);
+    int k = snprintf(buf, n, "gfx950|dt%d|c%d,%d,%d|L%d|f%d|B%d|%dx%d\t%d\t", t.dt, t.c1, t.c2, t.c3,
+                     t.L, t.f, t.B, t.H, t.W, t.dsplit);
+    for (int i = 0; i < NLAYERS && k > 0 && (size_t)k < n; ++i)
+        k += snprintf(buf + k, n - k, "%s%s", conv_cfg_name(t.cfg[i]), i + 1 < NLAYERS ? "," : "\n");
 }
 
 static bool same_key(const TuneEntry &a, const TuneEntry &b, bool with_batch) {
@@ -155,7 +172,7 @@ static void cache_store(const TuneEntry &e) {
     const std::string tmp = path + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;
-    char buf[256];
+    char buf[512];
     for (const TuneEntry &t : g_tune) {
         format_entry(t, buf, sizeof buf);
         fputs(buf, f);
@@ -323,6 +340,8 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
             pl->cfg[i] = ov >= 0 ? ov : cfg[i];
         }
     }
+    for (int i = 0; i < L_F; ++i)
+        pl->cfg[i] = conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, pl->cfg[i]);
     // capacities and persistent grid sizes from the largest pair
     for (int k = 0; k < 4; ++k) pl->cap[k] = (size_t)max_n * mx.h[k] * mx.w[k];
     PairGeo gmax{};
@@ -521,6 +540,8 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
             for (int i = 0; i < NLAYERS && r == SV_OK; ++i) {
                 const int s = stage_of[i];
                 if (cnt[s] == 0) continue;  // a layer without a launch of its own
+                // a tile shape that does not fit this layer ran as the fallback
+                if (conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, c) != c) continue;
                 // a split that falls back to one pass repeats an unsplit candidate
                 if (net_layer_split(ns, i, c, B, H, W) != c / conv_num_tiles() + 1) continue;
                 const float t = ms[s] / cnt[s];

@@ -43,6 +43,7 @@ static const CfgDesc kCfgs[] = {
 };
 static constexpr int kNumTiles = (int)(sizeof(kCfgs) / sizeof(kCfgs[0]));
 static constexpr int kMaxSplit = CONV_MAX_SPLIT;
+static constexpr int kFallbackTile = 5;  // th4_tn16
 int conv_num_tiles() { return kNumTiles; }
 int conv_num_cfgs() { return kNumTiles * kMaxSplit; }
 
@@ -62,6 +63,25 @@ const char *conv_cfg_name(int cfg) {
 sv_status launch_conv_f32(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 sv_status launch_conv_bf16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
+bool conv_fits_f32(int ks, int stride, int tile);
+bool conv_fits_bf16(int ks, int stride, int tile);
+bool conv_fits_f16(int ks, int stride, int tile);
+
+// A configuration whose tile shape does not fit the LDS for this kernel size
+// and stride runs as th4_tn16 (which fits every case) with the same split;
+// the tile shape does not change results.
+int conv_resolve_cfg(int dtype, int ks, int stride, int cfg) {
+    if (cfg < 0 || cfg >= conv_num_cfgs()) return cfg;
+    const int tile = cfg % kNumTiles;
+    bool fits = false;
+    switch (dtype) {
+    case SV_F32: fits = conv_fits_f32(ks, stride, tile); break;
+    case SV_BF16: fits = conv_fits_bf16(ks, stride, tile); break;
+    case SV_F16: fits = conv_fits_f16(ks, stride, tile); break;
+    default: return cfg;
+    }
+    return fits ? cfg : cfg - tile + kFallbackTile;
+}
 
 static sv_status launch_any(int dtype, int ks, int stride, int tile, const ConvParams &p, int pg,
                             hipStream_t st) {
@@ -87,6 +107,7 @@ int conv_effective_split(int dtype, int cfg, int Cin, long long npix, int n_pad,
 
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
     if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    cfg = conv_resolve_cfg(dtype, ks, stride, cfg);
     ConvParams p = p0;
     p.ksplit = conv_effective_split(dtype, cfg, p.Cin, (long long)p.B * p.Ho * p.Wo, p.n_pad, p.part,
                                     p.part_bytes);
@@ -97,6 +118,7 @@ sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvPara
                           hipStream_t st) {
     if (!p0.tab || grid <= 0) return SV_ERR_RANGE;
     if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    cfg = conv_resolve_cfg(dtype, ks, stride, cfg);
     ConvParams p = p0;
     p.ksplit = 1;  // the persistent path never splits
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, grid, st);

@@ -7,4 +7,6 @@ sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int 
     return launch_dt<SV_F16>(ks, stride, cfg, p, pg, st);
 }
 
+bool conv_fits_f16(int ks, int stride, int tile) { return fits_dt<SV_F16>(ks, stride, tile); }
+
 }  // namespace sv

@@ -21,7 +21,10 @@
     X(9, 8, 16, 4, 2, "th8_tn16_k2")       \
     X(10, 4, 64, 4, 2, "th4_tn64_k2")      \
     X(11, 2, 32, 2, 2, "th2_tn32_k2")      \
-    X(12, 2, 64, 2, 2, "th2_tn64_k2")
+    X(12, 2, 64, 2, 2, "th2_tn64_k2")      \
+    X(13, 4, 16, 4, 8, "th4_tn16_k8")      \
+    X(14, 2, 32, 2, 4, "th2_tn32_k4")      \
+    X(15, 4, 32, 4, 4, "th4_tn32_k4")
 
 namespace sv {
 
@@ -103,14 +106,20 @@ __device__ __forceinline__ void load_px(const void *base, size_t off, int sdt, f
 // pixel from their FP32 sums: bias, activation, the backward pass's extra
 // terms, then an NHWC store in the output dtype.
 template <int DT>
+__device__ __forceinline__ void conv_bias4(const ConvParams &p, int nbase, float (&b)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) b[i] = (p.bias && nbase + i < p.Cout) ? p.bias[nbase + i] : 0.f;
+}
+
+template <int DT>
 __device__ __forceinline__ void conv_epilogue(const ConvParams &p, size_t pix, int nbase,
-                                              const float (&acc)[4]) {
+                                              const float (&acc)[4], const float (&bias)[4]) {
     using T = typename Elem<DT>::T;
     float r[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int n = nbase + i;
-        float val = acc[i] + ((p.bias && n < p.Cout) ? p.bias[n] : 0.f);
+        float val = acc[i] + bias[i];
         if (p.act) val = val > 0.f ? val : 0.1f * val;
         if (n < p.Cout) {
             if (p.add) val += p.add[pix * p.add_pitch + p.add_coff + n];
@@ -204,7 +213,8 @@ struct ConvTile {
         T wl[TAPS * TN * KCP];
         PixSrc ps[2][NPIX];
     };
-    static_assert(sizeof(Smem) <= 160 * 1024, "LDS per workgroup");
+    // tiles whose LDS exceeds a CU's 160 KB are never instantiated (conv_fits)
+    static constexpr bool FITS = sizeof(Smem) <= 160 * 1024;
 
     // Computed once per tile; every channel chunk reuses it.
     static __device__ __forceinline__ void pix_table(const ConvParams &p, const ConvGeo &G, Smem &sm) {
@@ -252,6 +262,12 @@ struct ConvTile {
         for (int i = 0; i < MBW; ++i)
 #pragma unroll
             for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+        // the bias of this lane's output channels, loaded ahead of the main loop
+        float bpre[NBW][4];
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb)
+            conv_bias4<DT>(p, n0 + (wn * NBW + nb) * 16 + 4 * g, bpre[nb]);
 
         __syncthreads();  // the previous tile of a persistent loop is done with LDS
         pix_table(p, G, sm);
@@ -479,7 +495,7 @@ struct ConvTile {
                             acc[mb][nb];
                 } else {
                     const float r[4] = {acc[mb][nb][0], acc[mb][nb][1], acc[mb][nb][2], acc[mb][nb][3]};
-                    conv_epilogue<DT>(p, pix, nbase, r);
+                    conv_epilogue<DT>(p, pix, nbase, r, bpre[nb]);
                 }
             }
         }
@@ -563,7 +579,9 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
             s[0] += q[0]; s[1] += q[1]; s[2] += q[2]; s[3] += q[3];
         }
         const float r[4] = {s[0], s[1], s[2], s[3]};
-        conv_epilogue<DT>(p, pix, nbase, r);
+        float b[4];
+        conv_bias4<DT>(p, nbase, b);
+        conv_epilogue<DT>(p, pix, nbase, r, b);
     }
 }
 
@@ -571,6 +589,9 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
 // grid > 0: persistent launch over p.tab.
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
+    if constexpr (!ConvTile<DT, KS, S, TH, TN, WM, KCM>::FITS) {
+        return SV_ERR_UNSUPPORTED;
+    } else {
     if (pgrid > 0) {
         hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM>), dim3(pgrid), dim3(256), 0, st, p);
         SV_LAUNCH_CHECK("k_conv_tab");
@@ -590,6 +611,7 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
         SV_LAUNCH_CHECK("k_conv_split_reduce");
     }
     return SV_OK;
+    }
 }
 
 template <int DT, int KS, int S>
@@ -601,6 +623,26 @@ static sv_status launch_cfg(int cfg, const ConvParams &p, int pg, hipStream_t st
 #undef SV_CFG
     default: return SV_ERR_RANGE;
     }
+}
+
+template <int DT, int KS, int S>
+static bool fits_cfg(int cfg) {
+    switch (cfg) {
+#define SV_CFG(i, TH, TN, WM, KCM, name) \
+    case i: return ConvTile<DT, KS, S, TH, TN, WM, KCM>::FITS;
+        SV_CONV_CFGS(SV_CFG)
+#undef SV_CFG
+    default: return false;
+    }
+}
+
+// Whether tile shape `cfg` fits the LDS for this kernel size and stride.
+template <int DT>
+static bool fits_dt(int ks, int stride, int cfg) {
+    if (ks == 3 && stride == 1) return fits_cfg<DT, 3, 1>(cfg);
+    if (ks == 3 && stride == 2) return fits_cfg<DT, 3, 2>(cfg);
+    if (ks == 1 && stride == 1) return fits_cfg<DT, 1, 1>(cfg);
+    return false;
 }
 
 template <int DT>

@@ -110,6 +110,9 @@ sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
                           hipStream_t s);
 void conv_cfg_tile(int cfg, int &TH, int &TN);
+// cfg, or the fallback tile shape (same split) when cfg's tile does not fit
+// the LDS for this kernel size and stride; launches resolve the same way
+int conv_resolve_cfg(int dtype, int ks, int stride, int cfg);
 int conv_num_tiles();  // tile shapes; cfg = tile + conv_num_tiles() * (ksplit - 1)
 constexpr int CONV_MAX_SPLIT = 4;
 // the split a launch of configuration cfg actually uses (1 when it cannot split)

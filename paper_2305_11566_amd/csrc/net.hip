@@ -130,6 +130,7 @@ void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg) {
     for (int i = 0; i < NLAYERS; ++i) {
         const int ov = net_get_cfg_override(ns.dtype, i);
         cfg[i] = ov >= 0 ? ov : (have ? tuned[i] : net_default_cfg(ns, i, 0));
+        if (i < L_F) cfg[i] = conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, cfg[i]);
     }
 }
 
