@@ -14,6 +14,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -494,8 +495,6 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         best_cfg[i] = net_default_cfg(ns, i, 0);
         saved_ov[i] = net_get_cfg_override(ns.dtype, i);
     }
-    float ms[PROF_NSTAGES];
-    int cnt[PROF_NSTAGES];
     if (r == SV_OK) {
         // census once, then every lane split of the cost + WTA kernel
         r = launch_reduce_census((uint8_t *)(d + o_l), (uint8_t *)(d + o_r), B, H, W, W, ns.f, win_w,
@@ -521,35 +520,128 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         }
         const char *ve = getenv("SV_AUTOTUNE_VERBOSE");
         const bool verbose = ve && ve[0] == '1';
-        // every tile shape for all layers at once; per-layer times from the events
-        float best_t[NLAYERS];
-        for (int i = 0; i < NLAYERS; ++i) best_t[i] = 1e30f;
-        const int stage_of[NLAYERS] = {PROF_E1, PROF_E2, PROF_E3, PROF_HEAD, PROF_G3, PROF_G2,
-                                       PROF_G1, PROF_G0, PROF_FPROJ};
-        for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
-            for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, c);
-            r = net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H, W,
-                            nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, st);  // warm
-            if (r != SV_OK) break;
-            r = sv_profile_enable(reps);
-            for (int i = 0; i < reps && r == SV_OK; ++i)
-                r = net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H,
-                                W, nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, st);
-            if (r == SV_OK) r = sv_profile_read(ms, cnt);
-            (void)sv_profile_enable(0);
-            for (int i = 0; i < NLAYERS && r == SV_OK; ++i) {
-                const int s = stage_of[i];
-                if (cnt[s] == 0) continue;  // a layer without a launch of its own
-                // a tile shape that does not fit this layer ran as the fallback
-                if (conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, c) != c) continue;
+        // Stage 1, screening: each layer alone, every configuration, timed over
+        // back-to-back launches of that one layer (on buffers a full forward
+        // pass has filled); the fastest few per layer go on to stage 2.
+        // Stage 2, in context: a whole forward pass captured in a graph and
+        // replayed back to back, one layer's candidate varied at a time with
+        // the others at their current best (layer by layer, twice over), so
+        // effects a lone layer does not show (inputs fresh from the previous
+        // layer, the extra launch of a split reduction) count.
+        constexpr int NKEEP = 5;
+        int keep[NLAYERS][NKEEP], nkeep[NLAYERS] = {};
+        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
+        auto fwd_on = [&](hipStream_t s_, int only) {
+            return net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H, W,
+                               nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, s_, only);
+        };
+        auto fwd = [&](int only) { return fwd_on(st, only); };
+        // mean time per replay of a graph holding one whole forward pass, best
+        // of two rounds (ms); the graph keeps launch overhead out of the timing
+        hipStream_t cs = nullptr;
+        if (r == SV_OK && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+            r = hip_fail(hipGetLastError(), "hipStreamCreateWithFlags");
+        auto graph_timed = [&](int reps_) {
+            float t = 1e30f;
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            if (r != SV_OK) return t;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) { r = hip_fail(e, "hipStreamBeginCapture"); return t; }
+            const sv_status rf = fwd_on(cs, -1);
+            e = hipStreamEndCapture(cs, &g);
+            if (rf != SV_OK) r = rf;
+            else if (e != hipSuccess) r = hip_fail(e, "hipStreamEndCapture");
+            if (r == SV_OK && (e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0)) != hipSuccess)
+                r = hip_fail(e, "hipGraphInstantiate");
+            for (int round = 0; round < 2 && r == SV_OK; ++round) {
+                for (int k = 0; k < 2; ++k) (void)hipGraphLaunch(ge, cs);
+                hipEvent_t ea, eb;
+                (void)hipEventCreate(&ea);
+                (void)hipEventCreate(&eb);
+                (void)hipEventRecord(ea, cs);
+                for (int k = 0; k < reps_; ++k) (void)hipGraphLaunch(ge, cs);
+                (void)hipEventRecord(eb, cs);
+                if ((e = hipEventSynchronize(eb)) != hipSuccess) r = hip_fail(e, "autotune graph replay");
+                float ms_ = 0.f;
+                (void)hipEventElapsedTime(&ms_, ea, eb);
+                (void)hipEventDestroy(ea);
+                (void)hipEventDestroy(eb);
+                t = std::min(t, ms_ / reps_);
+            }
+            if (ge) (void)hipGraphExecDestroy(ge);
+            if (g) (void)hipGraphDestroy(g);
+            return t;
+        };
+        // mean time per call of `reps` calls of f, best of two rounds (ms)
+        auto timed = [&](int reps_, int only) {
+            float t = 1e30f;
+            for (int round = 0; round < 2 && r == SV_OK; ++round) {
+                for (int k = 0; k < 2 && r == SV_OK; ++k) r = fwd(only);  // warm
+                hipEvent_t ea, eb;
+                (void)hipEventCreate(&ea);
+                (void)hipEventCreate(&eb);
+                (void)hipEventRecord(ea, st);
+                for (int k = 0; k < reps_ && r == SV_OK; ++k) r = fwd(only);
+                (void)hipEventRecord(eb, st);
+                (void)hipEventSynchronize(eb);
+                float ms_ = 0.f;
+                (void)hipEventElapsedTime(&ms_, ea, eb);
+                (void)hipEventDestroy(ea);
+                (void)hipEventDestroy(eb);
+                t = std::min(t, ms_ / reps_);
+            }
+            return t;
+        };
+        r = fwd(-1);
+        const int nrep = B >= 16 ? 6 : 24;
+        for (int i = 0; i < L_F && r == SV_OK; ++i) {
+            float kt[NKEEP];
+            for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
+                // a tile shape that does not fit this layer would run as the fallback,
                 // a split that falls back to one pass repeats an unsplit candidate
+                if (conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, c) != c) continue;
                 if (net_layer_split(ns, i, c, B, H, W) != c / conv_num_tiles() + 1) continue;
-                const float t = ms[s] / cnt[s];
-                if (t < best_t[i]) { best_t[i] = t; best_cfg[i] = c; }
-                if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-12s %8.2f us\n",
+                net_set_cfg_override(ns.dtype, i, c);
+                const float t = timed(nrep, i);
+                if (r != SV_OK) break;
+                if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-14s alone %8.2f us\n",
                                      ns.dtype, B, H, W, i, conv_cfg_name(c), t * 1e3f);
+                // insert into the sorted short list
+                int pos = nkeep[i];
+                while (pos > 0 && kt[pos - 1] > t) {
+                    if (pos < NKEEP) { kt[pos] = kt[pos - 1]; keep[i][pos] = keep[i][pos - 1]; }
+                    --pos;
+                }
+                if (pos < NKEEP) {
+                    kt[pos] = t;
+                    keep[i][pos] = c;
+                    if (nkeep[i] < NKEEP) ++nkeep[i];
+                }
+            }
+            if (nkeep[i] > 0) best_cfg[i] = keep[i][0];
+            net_set_cfg_override(ns.dtype, i, best_cfg[i]);
+        }
+        (void)hipStreamSynchronize(st);  // stage 1's launches are done before the replays
+        const int nrep2 = B >= 16 ? 6 : 50;
+        for (int pass = 0; pass < 2 && r == SV_OK; ++pass) {
+            for (int i = 0; i < L_F && r == SV_OK; ++i) {
+                if (nkeep[i] < 2) continue;
+                float best_t = 1e30f;
+                int best_c = best_cfg[i];
+                for (int k = 0; k < nkeep[i] && r == SV_OK; ++k) {
+                    net_set_cfg_override(ns.dtype, i, keep[i][k]);
+                    const float t = graph_timed(nrep2);
+                    if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-14s whole pass %8.2f us\n",
+                                         ns.dtype, B, H, W, i, conv_cfg_name(keep[i][k]), t * 1e3f);
+                    if (t < best_t) { best_t = t; best_c = keep[i][k]; }
+                }
+                best_cfg[i] = best_c;
+                net_set_cfg_override(ns.dtype, i, best_c);
             }
         }
+        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
+        if (cs) (void)hipStreamDestroy(cs);
     }
     (void)hipStreamSynchronize(st);
     (void)hipFree(mem);

@@ -69,8 +69,21 @@ template <> struct Mfma<SV_F32> {
 template <int DT, int GS>
 __device__ __forceinline__ typename Mfma<DT>::vec pack_vec(const float (&v)[GS]) {
     typename Mfma<DT>::vec r;
+    if constexpr (DT == SV_BF16) {
+        // two values per v_cvt_pk_bf16_f32 (round to nearest even, as Elem::make)
+        typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+        typedef float f32x2_t __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int i = 0; i < GS; ++i) r[i] = Elem<DT>::make(v[i]);
+        for (int i = 0; i < GS; i += 2) {
+            const bf16x2_t h = __builtin_convertvector((f32x2_t){v[i], v[i + 1]}, bf16x2_t);
+            const uint32_t u = __builtin_bit_cast(uint32_t, h);
+            r[i] = (uint16_t)(u & 0xffffu);
+            r[i + 1] = (uint16_t)(u >> 16);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < GS; ++i) r[i] = Elem<DT>::make(v[i]);
+    }
     return r;
 }
 
@@ -408,8 +421,9 @@ struct ConvTile {
                     }
                 }
                 // -- the remaining kinds, element by element: a source stored in
-                // another dtype, the network input x0, or nothing (zeros)
-                if (!fast_resize && !fast_plain) {
+                // another dtype or the network input x0 (groups past Cin are
+                // never read by the MFMA steps and are not written)
+                if (!fast_resize && !fast_plain && kind != SRC_NONE) {
 #pragma unroll
                     for (int k = 0; k < NE; ++k) {
                         const int pix = pix0 + k * PSTEP;
@@ -446,14 +460,21 @@ struct ConvTile {
 #pragma unroll
             for (int sub = 0; sub < KCM; ++sub) {
             if (c0 + sub * KCB >= c_end) break;
+            // channel groups of this base chunk that hold input channels (fewer
+            // than KCGB only in the chunk that ends at Cin): the (tap, group)
+            // pairs run over those alone, so a small Cin costs few steps
+            const int keff = min(KCGB, (c_end - c0 - sub * KCB + GS - 1) / GS);
+            const int npairs = TAPS * keff;
+            const int krcp = (256 + keff - 1) / keff;  // q / keff = (q * krcp) >> 8 for q < 40
             // unrolled so the LDS operand loads of later steps are issued ahead
             // of the MFMAs of earlier ones
 #pragma unroll
             for (int st = 0; st < NSTEP; ++st) {
+                if (st * 4 >= npairs) break;
                 const int q = st * 4 + g;
-                const bool valid = q < TAPS * KCGB;
-                const int tap = valid ? q / KCGB : 0;
-                const int cg = sub * KCGB + (valid ? q % KCGB : 0);
+                const bool valid = q < npairs;
+                const int tap = valid ? (q * krcp) >> 8 : 0;
+                const int cg = sub * KCGB + (valid ? q - tap * keff : 0);
                 const int u = tap / KS, v = tap - (tap / KS) * KS;
                 vec bf[MBW], af[NBW];
 #pragma unroll

@@ -36,12 +36,11 @@ static inline void fin_window(int f, int &ph, int &pw) {
     ph = std::min(FIN_TILE_H + 3, cdiv(FIN_TILE_H + 1, f) + 3);
     pw = std::min(FIN_TILE_W + 3, cdiv(FIN_TILE_W + 1, f) + 3);
 }
-// dynamic LDS (floats): T[9][ph][pw], d[ph][pw], S[FIN_TILE_H][3][pw], D[FIN_TILE_H][pw],
-// W_F[9][c1 + 2]
-static inline size_t fin_lds_bytes(int f, int c1) {
+// dynamic LDS (floats): T[9][ph][pw], d[ph][pw], S[FIN_TILE_H][3][pw], D[FIN_TILE_H][pw]
+static inline size_t fin_lds_bytes(int f) {
     int ph, pw;
     fin_window(f, ph, pw);
-    return sizeof(float) * ((size_t)10 * ph * pw + (size_t)4 * FIN_TILE_H * pw + 9 * (c1 + 2));
+    return sizeof(float) * ((size_t)10 * ph * pw + (size_t)4 * FIN_TILE_H * pw);
 }
 
 struct FinTab {
@@ -63,6 +62,11 @@ __device__ __forceinline__ void load8(const typename Elem<DT>::T *p, float (&v)[
     }
 }
 
+// q / d for 0 <= q < 8192 and 1 <= d <= 160 from inv = 1.0f / d (correctly
+// rounded): (q + 1/2) / d stays at least 1 / (2d) away from an integer, far
+// more than the rounding of the product (checked exhaustively for that range).
+__device__ __forceinline__ int fin_div(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
+
 template <int DT>
 __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int PWm,
                                            const typename Elem<DT>::T *__restrict__ G0, int c1,
@@ -77,8 +81,6 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
     float *sd = sT + 9 * PHm * PWm;            // [PHm][PWm]
     float *sS = sd + PHm * PWm;                // [FIN_TILE_H][3][PWm]
     float *sD = sS + FIN_TILE_H * 3 * PWm;     // [FIN_TILE_H][PWm]
-    float *sW = sD + FIN_TILE_H * PWm;         // [9][c1 + 2]
-    const int cw = c1 + 2;
     // coarse window: from the lower index of the first column / row in range to
     // the upper index of the last
     int xa, ya, xb, yb, i1;
@@ -114,46 +116,63 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
         tb.cy1[r] = y1;
         tb.cly[r] = ly;
     }
-    for (int e = tid; e < 9 * cw; e += FIN_THREADS) {
-        const int t = e / cw, c = e - t * cw;
-        sW[e] = wF[(size_t)t * wf_pitch + c];
-    }
-    for (int e = tid; e < ph * pw; e += FIN_THREADS) {
-        const int r = e / pw, c = e - r * pw;
-        sd[r * PWm + c] = (float)db[(size_t)(ya + r) * w + xa + c];
-    }
-    __syncthreads();
-    // T on the window: work item = (coarse pixel, group of three taps)
-    for (int e = tid; e < ph * pw * 3; e += FIN_THREADS) {
-        const int q = e / 3, tg = e - q * 3;
-        const int r = q / pw, c = q - r * pw;
+    // T and the coarse disparity on the window.  Work item = (group of three
+    // taps, coarse pixel), the tap group uniform across each wave (the pixel
+    // count is padded to a multiple of 64), so the weights are scalar loads;
+    // an item's channels are loaded 32 at a time, all in flight before any
+    // product.
+    const float inv_pw = 1.0f / (float)pw;
+    const int npx = ph * pw, qp = (npx + 63) & ~63;
+    for (int e = tid; e < 3 * qp; e += FIN_THREADS) {
+        const int tg = __builtin_amdgcn_readfirstlane((e >= qp) + (e >= 2 * qp));
+        const int q = e - tg * qp;
+        if (q >= npx) continue;
+        const int r = fin_div(q, inv_pw), c = q - r * pw;
         const size_t gp = (size_t)(ya + r) * w + xa + c;
-        const float *w0 = sW + (3 * tg) * cw, *w1 = w0 + cw, *w2 = w1 + cw;
-        float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+        const float dv = (float)db[gp];
+        const float x0d = scale0 * dv, x0i = (float)ib[gp] * (1.0f / 256.0f);
         const typename Elem<DT>::T *g = G0 + gp * c1;
-        for (int c0 = 0; c0 < c1; c0 += 8) {
-            float v[8];
-            load8<DT>(g + c0, v);
+        const float *wg = wF + (size_t)(3 * tg) * wf_pitch;
+        float a[3] = {0.f, 0.f, 0.f};
+        for (int c0 = 0; c0 < c1; c0 += 32) {
+            float v[32];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                a0 += w0[c0 + i] * v[i];
-                a1 += w1[c0 + i] * v[i];
-                a2 += w2[c0 + i] * v[i];
+            for (int k = 0; k < 4; ++k) {
+                if (c0 + 8 * k < c1) {
+                    float u[8];
+                    load8<DT>(g + c0 + 8 * k, u);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[8 * k + i] = u[i];
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[8 * k + i] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 3; ++t) {
+                const float *wt = wg + (size_t)t * wf_pitch + c0;
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    if (c0 + 8 * k < c1) {
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) a[t] += wt[8 * k + i] * v[8 * k + i];
+                    }
+                }
             }
         }
-        const float x0d = scale0 * sd[r * PWm + c], x0i = (float)ib[gp] * (1.0f / 256.0f);
-        a0 += w0[c1] * x0d + w0[c1 + 1] * x0i;
-        a1 += w1[c1] * x0d + w1[c1 + 1] * x0i;
-        a2 += w2[c1] * x0d + w2[c1 + 1] * x0i;
-        sT[((3 * tg + 0) * PHm + r) * PWm + c] = a0;
-        sT[((3 * tg + 1) * PHm + r) * PWm + c] = a1;
-        sT[((3 * tg + 2) * PHm + r) * PWm + c] = a2;
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const float *wt = wg + (size_t)t * wf_pitch + c1;
+            a[t] += wt[0] * x0d + wt[1] * x0i;
+            sT[((3 * tg + t) * PHm + r) * PWm + c] = a[t];
+        }
+        if (tg == 0) sd[r * PWm + c] = dv;
     }
     __syncthreads();
     // vertical pass: S_v(Y, x) and the residual base's row interpolation D(Y, x)
     for (int e = tid; e < FIN_TILE_H * 4 * pw; e += FIN_THREADS) {
-        const int ty = e / (4 * pw), rem = e - ty * 4 * pw;
-        const int v = rem / pw, c = rem - v * pw;
+        const int rr = fin_div(e, inv_pw), c = e - rr * pw;
+        const int ty = rr >> 2, v = rr & 3;
         if (v < 3) {
             float s = 0.f;
 #pragma unroll
@@ -247,8 +266,8 @@ k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__res
     }
 }
 
-// The dynamic LDS of the final layer stays under 80 KB (f = 1, c1 = 256); the
-// kernels are allowed that much once, before their first launch.
+// The dynamic LDS of the final layer stays under 80 KB (f = 1); the kernels
+// are allowed that much once, before their first launch.
 static sv_status fin_allow_lds() {
     static std::once_flag once;
     static hipError_t err = hipSuccess;
@@ -273,7 +292,7 @@ sv_status launch_final_tab(const PairTable *tab, int grid, int dtype, const void
     if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
     int PHm, PWm;
     fin_window(f, PHm, PWm);
-    const size_t lds = fin_lds_bytes(f, c1);
+    const size_t lds = fin_lds_bytes(f);
     const float scale0 = (float)f / 256.0f;
     switch (dtype) {
 #define SV_FT(D)                                                                                      \
@@ -299,7 +318,7 @@ sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, c
     if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
     int PHm, PWm;
     fin_window(f, PHm, PWm);
-    const size_t lds = fin_lds_bytes(f, c1);
+    const size_t lds = fin_lds_bytes(f);
     const float scale0 = (float)f / 256.0f;
     dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
     switch (dtype) {

@@ -60,9 +60,10 @@ bool tuned_lookup(const NetShape &ns, int B, int H, int W, int *cfg, int *dsplit
 void net_set_cfg_override(int dtype, int layer, int cfg);   // -1 restores the default
 int net_get_cfg_override(int dtype, int layer);
 
+// only >= 0: launch that network layer alone (for timing), nothing else
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,
-                      float *ml_user, void *saved, void *ws, hipStream_t st);
+                      float *ml_user, void *saved, void *ws, hipStream_t st, int only = -1);
 
 sv_status net_backward(const NetShape &ns, const void *packed, const void *saved, int B, int H,
                        int W, const float *eps, const float *dout, const float *dml_extra,

@@ -190,6 +190,14 @@ static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvS
     return launch_conv(tsplit ? SV_F32 : ns.dtype, ks, stride, cfg, p, st);
 }
 
+// with only >= 0, a forward pass launches that layer alone (the autotuner
+// times one layer at a time on buffers a full pass has filled)
+template <typename... A>
+static sv_status run_layer_if(int only, const NetShape &ns, const void *packed, int li, A... args) {
+    if (only >= 0 && only != li) return SV_OK;
+    return run_layer(ns, packed, li, args...);
+}
+
 // launch i of the forward pass is profiling stage PROF_E1 + i
 static inline void ev_rec(int i, int which, hipStream_t st) { prof_mark(PROF_E1 + i, which, st); }
 
@@ -201,7 +209,7 @@ static inline void ev_rec(int i, int which, hipStream_t st) { prof_mark(PROF_E1 
 
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,
-                      float *ml_user, void *saved, void *ws, hipStream_t st) {
+                      float *ml_user, void *saved, void *ws, hipStream_t st, int only) {
     const Levels lv = net_levels(ns, H, W);
     const ActLayout a = net_act_layout(ns, lv, B);
     int cfg[NLAYERS];
@@ -224,52 +232,53 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     const ConvSrc x0 = src_x0(disp, img, lv.h[0], lv.w[0], ns.f);
     // encoder
     ev_rec(0, 0, st);
-    SV_TRY(run_layer(ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, st));
+    SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
-    SV_TRY(run_layer(ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
+    SV_TRY(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
                      lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, st));
     ev_rec(1, 1, st);
     ev_rec(2, 0, st);
-    SV_TRY(run_layer(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
+    SV_TRY(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
                      lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, st));
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     ev_rec(3, 0, st);
-    SV_TRY(run_layer(ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
+    SV_TRY(run_layer_if(only, ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
                      lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, st));
     ev_rec(3, 1, st);
     ConvSrc zsrc;
     if (eps) {
         ev_rec(4, 0, st);
-    SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
-    ev_rec(4, 1, st);
+        if (only < 0) SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
+        ev_rec(4, 1, st);
         zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
     } else {
         zsrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], SDT_F32);  // z = mu
     }
     // decoder
     ev_rec(5, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, st));
+    SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, st));
     ev_rec(5, 1, st);
     ev_rec(6, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
+    SV_TRY(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
                      lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, st));
     ev_rec(6, 1, st);
     ev_rec(7, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
+    SV_TRY(run_layer_if(only, ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
                      lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, st));
     ev_rec(7, 1, st);
     ev_rec(8, 0, st);
-    SV_TRY(run_layer(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
+    SV_TRY(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
                      lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, st));
     ev_rec(8, 1, st);
     // final layer: per-tap projections of [G0, x0] and the gather, one kernel
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);
-    SV_TRY(launch_final(ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
+    if (only < 0)
+        SV_TRY(launch_final(ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
                         ns.cin_pad[L_F], ns.f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
     ev_rec(10, 1, st);
     if (train && ml_user)
