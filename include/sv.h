@@ -115,6 +115,58 @@ sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h
 sv_status sv_set_cost_wta_split(int dsplit);
 
 /* ------------------------------------------------------------------------ */
+/* Semi-global matching and post-processing (Sec. III-A2, III-A3)             */
+/* ------------------------------------------------------------------------ */
+
+/* Bytes of workspace sv_sgm needs: the four path-cost volumes, 4 * B*h*w*D. */
+size_t sv_sgm_workspace_bytes(int B, int h, int w, int D);
+
+/*
+ * Semi-global matching on the census cost, Eqs. (4)-(6): with C(i, j, d) the
+ * cost of sv_cost_wta, the path cost along direction r is
+ *   C_r(p, d) = C(p, d) + min(C_r(p-r, d), C_r(p-r, d-1) + P1,
+ *                             C_r(p-r, d+1) + P1, min_i C_r(p-r, i) + P2)
+ *               - min_k C_r(p-r, k),
+ * starting from C_r = C at the first pixel of each path, over the four axis
+ * directions (left to right, right to left, top to bottom, bottom to top);
+ * disp_out is the argmin over d of the sum of the four (Eq. (5)), the lowest
+ * d on ties.  Integer arithmetic throughout: bit-exact.
+ *
+ * cen_l, cen_r (device) uint64 [B][h][w]; D 1..256; nbits 1..64
+ * P1, P2       penalties, 0 <= P1 <= P2 and nbits + 1 + P2 <= 255 (path costs
+ *              are kept as uint8)
+ * disp_out     (device) uint8 [B][h][w]
+ * workspace    (device) >= sv_sgm_workspace_bytes(B, h, w, D) bytes, caller-owned
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE (D, nbits, P1, P2),
+ *         SV_ERR_WORKSPACE.
+ */
+sv_status sv_sgm(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D,
+                 int nbits, int P1, int P2, uint8_t *disp_out, void *workspace, size_t ws_bytes,
+                 void *stream);
+
+/* Bytes of workspace sv_smp_median needs: B*h*w. */
+size_t sv_smp_workspace_bytes(int B, int h, int w);
+
+/*
+ * Single matching phase (Eq. (7)) and a 3 x 3 median filter.  The target
+ * column of pixel (i, j) is j - disp_in[i][j]; no target column may be matched
+ * twice, and of two pixels j < j' of a row with the same target column the
+ * left one (the smaller disparity, hidden in the target view) is invalid: a
+ * pixel is invalid when some pixel (i, j + k), 0 < k < D, has its target
+ * column.  Invalid values are replaced by the nearest valid value of the same
+ * row (the smaller one at equal distances); then a 3 x 3 median with
+ * replicated borders.  Bit-exact.
+ *
+ * disp_in      (device) uint8 [B][h][w]; may alias disp_out
+ * D            the disparity range of disp_in, 1..256;  w <= 16384
+ * disp_out     (device) uint8 [B][h][w]
+ * workspace    (device) >= sv_smp_workspace_bytes(B, h, w) bytes, caller-owned
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE, SV_ERR_WORKSPACE.
+ */
+sv_status sv_smp_median(const uint8_t *disp_in, int B, int h, int w, int D, uint8_t *disp_out,
+                        void *workspace, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Refinement network (Sec. III-B, Table I)                                   */
 /* ------------------------------------------------------------------------ */
 

@@ -91,6 +91,59 @@ def match(left: np.ndarray, right: np.ndarray, f: int, win_w: int, win_h: int, D
     return lo_l, cl, cr, disp
 
 
+def sgm_path(cost: np.ndarray, P1: int, P2: int, direction: int) -> np.ndarray:
+    """Path cost of Eq. (4) along one direction (0 L->R, 1 R->L, 2 T->B, 3 B->T)."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    B, h, w, D = cost.shape
+    out = np.empty_like(cost)
+    lib().or_sgm_path(_p(cost), B, h, w, D, P1, P2, direction, _p(out))
+    return out
+
+
+def sgm(cost: np.ndarray, P1: int, P2: int) -> np.ndarray:
+    """Aggregated cost of Eq. (5) over the four axis directions."""
+    cost = np.ascontiguousarray(cost, dtype=np.int32)
+    B, h, w, D = cost.shape
+    out = np.empty_like(cost)
+    scratch = np.empty_like(cost)
+    lib().or_sgm(_p(cost), B, h, w, D, P1, P2, _p(out), _p(scratch))
+    return out
+
+
+def smp(disp: np.ndarray, D: int) -> np.ndarray:
+    """Single matching phase of Eq. (7) with nearest-valid filling."""
+    disp = np.ascontiguousarray(disp, dtype=np.uint8)
+    if disp.ndim == 2:
+        disp = disp[None]
+    B, h, w = disp.shape
+    assert w <= 1 << 16
+    out = np.empty_like(disp)
+    lib().or_smp(_p(disp), B, h, w, D, _p(out))
+    return out
+
+
+def median3(disp: np.ndarray) -> np.ndarray:
+    """3 x 3 median filter, borders replicated."""
+    disp = np.ascontiguousarray(disp, dtype=np.uint8)
+    if disp.ndim == 2:
+        disp = disp[None]
+    B, h, w = disp.shape
+    out = np.empty_like(disp)
+    lib().or_median3(_p(disp), B, h, w, _p(out))
+    return out
+
+
+def match_sgm(left: np.ndarray, right: np.ndarray, f: int, win_w: int, win_h: int, D: int,
+              P1: int, P2: int):
+    """Census + SGM + WTA + SMP + median: (low-res left image, raw SGM disparity,
+    post-processed disparity)."""
+    lo_l, lo_r = downsample(left, f), downsample(right, f)
+    cl, cr = census(lo_l, win_w, win_h), census(lo_r, win_w, win_h)
+    nbits = win_w * win_h - 1
+    raw = wta(sgm(cost_volume(cl, cr, D, nbits), P1, P2))
+    return lo_l, raw, median3(smp(raw, D))
+
+
 def conv2d(x, wt, bias, stride, pad):
     x = np.ascontiguousarray(x, dtype=np.float64)
     wt = np.ascontiguousarray(wt, dtype=np.float64)

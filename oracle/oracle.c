@@ -117,6 +117,127 @@ void or_wta(const int32_t *cost, int B, int h, int w, int D, uint8_t *disp)
 }
 
 /* ------------------------------------------------------------------------ */
+/* Semi-global matching and post-processing (Sec. III-A2, III-A3), the      */
+/* Census + SGM member of the paper's family (S2 of Sec. IV-C).               */
+/* ------------------------------------------------------------------------ */
+
+/* Path cost along one direction r, Eq. (4):
+ *   C_r(p, d) = C(p, d) + min(C_r(p - r, d), C_r(p - r, d - 1) + P1,
+ *                             C_r(p - r, d + 1) + P1, min_i C_r(p - r, i) + P2)
+ *               - min_k C_r(p - r, k),
+ * with C_r(p, d) = C(p, d) at the first pixel of each path and the d - 1 /
+ * d + 1 terms absent outside [0, D).  Directions: 0 = left to right (r is one
+ * column back), 1 = right to left, 2 = top to bottom, 3 = bottom to top.
+ * cost and out are [B][h][w][D]. */
+void or_sgm_path(const int32_t *cost, int B, int h, int w, int D, int P1, int P2, int dir,
+                 int32_t *out)
+{
+    const int dy = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
+    const int dx = dir == 0 ? 1 : (dir == 1 ? -1 : 0);
+    for (int b = 0; b < B; ++b) {
+        /* visit pixels in path order: the predecessor p - r is always done */
+        for (int ii = 0; ii < h; ++ii)
+            for (int jj = 0; jj < w; ++jj) {
+                const int i = dy < 0 ? h - 1 - ii : ii;
+                const int j = dx < 0 ? w - 1 - jj : jj;
+                const int pi = i - dy, pj = j - dx;
+                const size_t o = (((size_t)b * h + i) * w + j) * D;
+                if (pi < 0 || pi >= h || pj < 0 || pj >= w) {
+                    for (int d = 0; d < D; ++d) out[o + d] = cost[o + d];
+                    continue;
+                }
+                const int32_t *prev = out + (((size_t)b * h + pi) * w + pj) * D;
+                int32_t mprev = prev[0];
+                for (int k = 1; k < D; ++k)
+                    if (prev[k] < mprev) mprev = prev[k];
+                for (int d = 0; d < D; ++d) {
+                    int32_t m = prev[d];
+                    if (d > 0 && prev[d - 1] + P1 < m) m = prev[d - 1] + P1;
+                    if (d + 1 < D && prev[d + 1] + P1 < m) m = prev[d + 1] + P1;
+                    if (mprev + P2 < m) m = mprev + P2;
+                    out[o + d] = cost[o + d] + m - mprev;
+                }
+            }
+    }
+}
+
+/* Aggregated cost, Eq. (5): C_SGM(p, d) = sum over the directions of C_r(p, d)
+ * (paths: the four axis directions). */
+void or_sgm(const int32_t *cost, int B, int h, int w, int D, int P1, int P2, int32_t *sum,
+            int32_t *scratch)
+{
+    const size_t n = (size_t)B * h * w * D;
+    for (size_t k = 0; k < n; ++k) sum[k] = 0;
+    for (int dir = 0; dir < 4; ++dir) {
+        or_sgm_path(cost, B, h, w, D, P1, P2, dir, scratch);
+        for (size_t k = 0; k < n; ++k) sum[k] += scratch[k];
+    }
+}
+
+/* Single matching phase, Eq. (7), as read here: the target column of (x, y) is
+ * x - D(x, y), and no target column may be matched twice.  When two reference
+ * pixels x < x' of a row share a target column, x' has the larger disparity
+ * and hides x in the target view, so x is the occluded one: (x, y) is invalid
+ * when some pixel (x + k, y), 0 < k < D, has the same target column.  An
+ * invalid value is replaced by the nearest valid value of the same row (on
+ * equal distances the smaller of the two); a row with no valid pixel is left
+ * as it is. */
+void or_smp(const uint8_t *disp, int B, int h, int w, int D, uint8_t *out)
+{
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i) {
+            const uint8_t *row = disp + ((size_t)b * h + i) * w;
+            uint8_t *orow = out + ((size_t)b * h + i) * w;
+            int any = 0;
+            /* valid[] kept in the output's spare values: 1 = valid */
+            static unsigned char valid[1 << 16];
+            for (int x = 0; x < w; ++x) {
+                int ok = 1;
+                for (int k = 1; k < D && x + k < w; ++k)
+                    if ((x + k) - row[x + k] == x - row[x]) ok = 0;
+                valid[x] = (unsigned char)ok;
+                any |= ok;
+            }
+            for (int x = 0; x < w; ++x) {
+                if (valid[x] || !any) {
+                    orow[x] = row[x];
+                    continue;
+                }
+                int best = -1;
+                for (int dist = 1; best < 0; ++dist) {
+                    const int l = x - dist, r = x + dist;
+                    const int lv = l >= 0 && valid[l], rv = r < w && valid[r];
+                    if (lv && rv) best = row[l] < row[r] ? row[l] : row[r];
+                    else if (lv) best = row[l];
+                    else if (rv) best = row[r];
+                }
+                orow[x] = (uint8_t)best;
+            }
+        }
+}
+
+/* 3 x 3 median filter of a uint8 map, borders replicated. */
+void or_median3(const uint8_t *in, int B, int h, int w, uint8_t *out)
+{
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < w; ++j) {
+                int v[9], n = 0;
+                for (int u = -1; u <= 1; ++u)
+                    for (int t = -1; t <= 1; ++t)
+                        v[n++] = in[((size_t)b * h + clampi(i + u, 0, h - 1)) * w + clampi(j + t, 0, w - 1)];
+                /* insertion sort, then the middle element */
+                for (int a = 1; a < 9; ++a)
+                    for (int c = a; c > 0 && v[c - 1] > v[c]; --c) {
+                        int tmp = v[c];
+                        v[c] = v[c - 1];
+                        v[c - 1] = tmp;
+                    }
+                out[((size_t)b * h + i) * w + j] = (uint8_t)v[4];
+            }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Network primitives (Table I), FP64, NCHW.                                 */
 /* ------------------------------------------------------------------------ */
 

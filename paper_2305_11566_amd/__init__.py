@@ -9,6 +9,8 @@ from .ops import (  # noqa: F401
     sv_census,
     sv_census_pair,
     sv_cost_wta,
+    sv_sgm,
+    sv_smp_median,
     sv_set_cost_wta_split,
     sv_set_layer_cfg,
     sv_num_layer_cfgs,

@@ -103,6 +103,37 @@ sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h
     return r;
 }
 
+size_t sv_sgm_workspace_bytes(int B, int h, int w, int D) {
+    if (B <= 0 || h <= 0 || w <= 0 || D <= 0) return 0;
+    return sgm_volume_bytes(B, h, w, D);
+}
+
+sv_status sv_sgm(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D, int nbits,
+                 int P1, int P2, uint8_t *disp_out, void *workspace, size_t ws_bytes, void *stream) {
+    if (!cen_l || !cen_r || !disp_out || !workspace) return SV_ERR_NULL;
+    if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > kMaxSide) return SV_ERR_SHAPE;
+    if (D < 1 || D > 256 || nbits < 1 || nbits > 64) return SV_ERR_RANGE;
+    if (P1 < 0 || P2 < P1 || nbits + 1 + P2 > 255) return SV_ERR_RANGE;
+    if (ws_bytes < sv_sgm_workspace_bytes(B, h, w, D)) return SV_ERR_WORKSPACE;
+    return launch_sgm(cen_l, cen_r, B, h, w, D, nbits, P1, P2, (uint8_t *)workspace, disp_out,
+                      (hipStream_t)stream);
+}
+
+size_t sv_smp_workspace_bytes(int B, int h, int w) {
+    if (B <= 0 || h <= 0 || w <= 0) return 0;
+    return (size_t)B * h * w;
+}
+
+sv_status sv_smp_median(const uint8_t *disp_in, int B, int h, int w, int D, uint8_t *disp_out,
+                        void *workspace, size_t ws_bytes, void *stream) {
+    if (!disp_in || !disp_out || !workspace) return SV_ERR_NULL;
+    if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > 16384) return SV_ERR_SHAPE;
+    if (D < 1 || D > 256) return SV_ERR_RANGE;
+    if (ws_bytes < sv_smp_workspace_bytes(B, h, w)) return SV_ERR_WORKSPACE;
+    return launch_smp_median(disp_in, B, h, w, D, (uint8_t *)workspace, disp_out,
+                             (hipStream_t)stream);
+}
+
 // Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8); for tuning and tests.
 sv_status sv_set_cost_wta_split(int dsplit) {
     if (dsplit != 1 && dsplit != 2 && dsplit != 4 && dsplit != 8) return SV_ERR_RANGE;

@@ -1,0 +1,269 @@
+// Semi-global matching on the census cost (Sec. III-A2, Eqs. (4)-(5)), winner-
+// take-all on the aggregated cost (Eq. (6)), the single matching phase
+// (Sec. III-A3, Eq. (7)) and a 3 x 3 median filter: the Census + SGM member
+// of the paper's matching family (S2 of Sec. IV-C), at the reduced
+// resolution.
+//
+// Path costs (Eq. (4)) along the four axis directions.  One 16-lane DPP row
+// of a wavefront follows one path (four paths per wave); lane l holds the
+// disparities d = l * DPL + j, j < DPL, in registers, so d - 1 and d + 1 are
+// in the same lane except at the ends of its run, which come from the
+// neighbouring lanes by DPP row shifts, and min_k C_r(p - r, k) is a DPP row
+// rotate-and-min.  The matching cost C(p, d) (Hamming distance of the census
+// codes, nbits + 1 where x - d < 0) is recomputed on the fly and never
+// stored; each direction writes its path costs C_r as uint8 into a volume of
+// its own, and the WTA kernel sums the four (Eq. (5)).
+#include "common.h"
+#include "kernels.h"
+
+namespace sv {
+
+constexpr int SGM_INF = 0x3fff;        // above any path cost (uint8 range)
+constexpr int SGM_LANES = 16;          // lanes per path = one DPP row
+
+template <int CTRL>
+__device__ __forceinline__ int dpp(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, 0xf, 0xf, false);
+}
+// min over the 16 lanes of a DPP row, in every lane of the row
+__device__ __forceinline__ int row_min(int v) {
+    v = min(v, dpp<0x121>(0, v));  // row_ror:1
+    v = min(v, dpp<0x122>(0, v));  // row_ror:2
+    v = min(v, dpp<0x124>(0, v));  // row_ror:4
+    v = min(v, dpp<0x128>(0, v));  // row_ror:8
+    return v;
+}
+
+// Path p of npath: directions 0 (left to right) and 1 (right to left) run
+// along rows, 2 (top to bottom) and 3 (bottom to top) along columns;
+// vol[dir][b][y][x][d].
+template <int DPL>
+__global__ void __launch_bounds__(64)
+k_sgm_paths(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int B, int h, int w,
+            int D, int nbits, int P1, int P2, uint8_t *__restrict__ vol)
+{
+    const int lane = threadIdx.x & (SGM_LANES - 1);
+    const int path = blockIdx.x * 4 + (threadIdx.x >> 4);
+    const int nrow = B * h, ncol = B * w;
+    const int npath = 2 * nrow + 2 * ncol;
+    if (path >= npath) return;  // whole DPP rows leave together
+    int dir, line;
+    if (path < 2 * nrow) { dir = path / nrow; line = path - dir * nrow; }
+    else { const int q = path - 2 * nrow; dir = 2 + q / ncol; line = q - (dir - 2) * ncol; }
+    int b, x, y, dx, dy, len;
+    if (dir < 2) {
+        b = line / h; y = line - b * h;
+        dx = dir == 0 ? 1 : -1; dy = 0;
+        x = dir == 0 ? 0 : w - 1;
+        len = w;
+    } else {
+        b = line / w; x = line - b * w;
+        dx = 0; dy = dir == 2 ? 1 : -1;
+        y = dir == 2 ? 0 : h - 1;
+        len = h;
+    }
+    const uint64_t *clb = cl + (size_t)b * h * w, *crb = cr + (size_t)b * h * w;
+    uint8_t *vb = vol + ((size_t)dir * B + b) * (size_t)h * w * D;
+    const int d0 = lane * DPL;
+
+    int prev[DPL];
+    int mprev = 0;
+    for (int s = 0; s < len; ++s, x += dx, y += dy) {
+        const size_t row = (size_t)y * w;
+        const uint64_t lv = clb[row + x];
+        int c[DPL];
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            const int d = d0 + j;
+            const int xr = x - d;
+            c[j] = d >= D ? SGM_INF
+                          : (xr < 0 ? nbits + 1 : (int)__popcll(lv ^ crb[row + (xr < 0 ? 0 : xr)]));
+        }
+        int cur[DPL];
+        if (s == 0) {
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) cur[j] = c[j];
+        } else {
+            const int from_left = dpp<0x111>(SGM_INF, prev[DPL - 1]);  // row_shr:1: lane - 1
+            const int from_right = dpp<0x101>(SGM_INF, prev[0]);       // row_shl:1: lane + 1
+#pragma unroll
+            for (int j = 0; j < DPL; ++j) {
+                const int lft = j > 0 ? prev[j - 1] : from_left;
+                const int rgt = j + 1 < DPL ? prev[j + 1] : from_right;
+                int m = min(prev[j], min(lft, rgt) + P1);
+                m = min(m, mprev + P2);
+                cur[j] = c[j] >= SGM_INF ? SGM_INF : c[j] + m - mprev;
+            }
+        }
+        int mn = cur[0];
+#pragma unroll
+        for (int j = 1; j < DPL; ++j) mn = min(mn, cur[j]);
+        mprev = row_min(mn);
+        uint8_t *o = vb + (row + x) * D;
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) {
+            prev[j] = cur[j];
+            if (d0 + j < D) o[d0 + j] = (uint8_t)cur[j];
+        }
+    }
+}
+
+// Aggregated cost (Eq. (5)) and winner-take-all (Eq. (6)), lowest d on ties.
+__global__ void __launch_bounds__(256)
+k_sgm_wta(const uint8_t *__restrict__ vol, size_t nvox, int D, size_t npix, uint8_t *__restrict__ disp)
+{
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < npix;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const uint8_t *v0 = vol + p * D, *v1 = v0 + nvox, *v2 = v1 + nvox, *v3 = v2 + nvox;
+        int best = 0x7fffffff, bd = 0;
+        if ((D & 3) == 0) {
+            for (int d = 0; d < D; d += 4) {
+                const uint32_t a = *(const uint32_t *)(v0 + d), bq = *(const uint32_t *)(v1 + d);
+                const uint32_t cq = *(const uint32_t *)(v2 + d), dq = *(const uint32_t *)(v3 + d);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const int sh = 8 * k;
+                    const int s = (int)((a >> sh) & 0xff) + (int)((bq >> sh) & 0xff) +
+                                  (int)((cq >> sh) & 0xff) + (int)((dq >> sh) & 0xff);
+                    if (s < best) { best = s; bd = d + k; }
+                }
+            }
+        } else {
+            for (int d = 0; d < D; ++d) {
+                const int s = (int)v0[d] + v1[d] + v2[d] + v3[d];
+                if (s < best) { best = s; bd = d; }
+            }
+        }
+        disp[p] = (uint8_t)bd;
+    }
+}
+
+// Single matching phase (Eq. (7)) with nearest-valid filling, one wave per
+// row.  The target column of x is x - D(x); x is invalid when a pixel x + k,
+// 0 < k < D, has the same target column (the left pixel of such a pair is
+// the one hidden in the target view).  Validity is kept as one 64-bit ballot
+// per 64 pixels; each invalid pixel takes the nearest valid value of its row
+// (the smaller one at equal distances).  The row is staged in LDS.
+constexpr int SMP_MAXW = 16384;
+__global__ void __launch_bounds__(64)
+k_smp(const uint8_t *__restrict__ disp, int B, int h, int w, int D, uint8_t *__restrict__ out)
+{
+    __shared__ uint8_t row[SMP_MAXW];
+    __shared__ uint64_t valid[SMP_MAXW / 64];
+    const int lane = threadIdx.x;
+    const size_t base = (size_t)blockIdx.x * w;  // row blockIdx.x of B * h
+    for (int x = lane; x < w; x += 64) row[x] = disp[base + x];
+    __syncthreads();
+    const int nch = (w + 63) / 64;
+    for (int ch = 0; ch < nch; ++ch) {
+        const int x = ch * 64 + lane;
+        bool ok = x < w;
+        if (ok) {
+            const int t = x - row[x];
+            for (int k = 1; k < D && x + k < w; ++k)
+                if (x + k - row[x + k] == t) { ok = false; break; }
+        }
+        const uint64_t m = __ballot(ok);
+        if (lane == 0) valid[ch] = m;
+    }
+    __syncthreads();
+    bool any = false;
+    for (int ch = 0; ch < nch; ++ch) any |= valid[ch] != 0;
+    for (int x = lane; x < w; x += 64) {
+        const int ch = x >> 6, bit = x & 63;
+        uint8_t v = row[x];
+        if (any && !((valid[ch] >> bit) & 1)) {
+            // nearest valid index below x and above x (-1 / w when none)
+            int lo = -1, hi = w;
+            uint64_t mb = valid[ch] & ((bit ? (~0ull >> (64 - bit)) : 0ull));
+            for (int c = ch; c >= 0; --c) {
+                const uint64_t mm = c == ch ? mb : valid[c];
+                if (mm) { lo = c * 64 + 63 - __clzll(mm); break; }
+            }
+            uint64_t ma = bit == 63 ? 0ull : valid[ch] & (~0ull << (bit + 1));
+            for (int c = ch; c < nch; ++c) {
+                const uint64_t mm = c == ch ? ma : valid[c];
+                if (mm) { hi = c * 64 + __ffsll((unsigned long long)mm) - 1; break; }
+            }
+            const int dl = lo >= 0 ? x - lo : 0x7fffffff, dr = hi < w ? hi - x : 0x7fffffff;
+            if (dl < dr) v = row[lo];
+            else if (dr < dl) v = row[hi];
+            else v = min(row[lo], row[hi]);
+        }
+        out[base + x] = v;
+    }
+}
+
+// 3 x 3 median, borders replicated (median of nine by a fixed exchange network).
+__device__ __forceinline__ void sort2(int &a, int &b) {
+    const int t = min(a, b);
+    b = max(a, b);
+    a = t;
+}
+__global__ void __launch_bounds__(256)
+k_median3(const uint8_t *__restrict__ in, int B, int h, int w, uint8_t *__restrict__ out)
+{
+    const size_t n = (size_t)B * h * w;
+    for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < n;
+         p += (size_t)gridDim.x * blockDim.x) {
+        const int j = (int)(p % w);
+        const size_t r = p / w;
+        const int i = (int)(r % h);
+        const uint8_t *img = in + (r - i) * w;
+        const int ys[3] = {max(i - 1, 0), i, min(i + 1, h - 1)};
+        const int xs[3] = {max(j - 1, 0), j, min(j + 1, w - 1)};
+        int v[9];
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int t = 0; t < 3; ++t) v[u * 3 + t] = img[(size_t)ys[u] * w + xs[t]];
+        // Paeth's 19-exchange median-of-nine network
+        sort2(v[1], v[2]); sort2(v[4], v[5]); sort2(v[7], v[8]);
+        sort2(v[0], v[1]); sort2(v[3], v[4]); sort2(v[6], v[7]);
+        sort2(v[1], v[2]); sort2(v[4], v[5]); sort2(v[7], v[8]);
+        sort2(v[0], v[3]); sort2(v[5], v[8]); sort2(v[4], v[7]);
+        sort2(v[3], v[6]); sort2(v[1], v[4]); sort2(v[2], v[5]);
+        sort2(v[4], v[7]); sort2(v[4], v[2]); sort2(v[6], v[4]);
+        sort2(v[4], v[2]);
+        out[p] = (uint8_t)v[4];
+    }
+}
+
+size_t sgm_volume_bytes(int B, int h, int w, int D) { return (size_t)4 * B * h * w * D; }
+
+sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
+                     int P1, int P2, uint8_t *vol, uint8_t *disp, hipStream_t s)
+{
+    const int npath = 2 * B * h + 2 * B * w;
+    const dim3 grid(cdiv(npath, 4));
+    const int dpl = cdiv(D, SGM_LANES);
+#define SV_SGM(N)                                                                                  \
+    hipLaunchKernelGGL(k_sgm_paths<N>, grid, dim3(64), 0, s, cl, cr, B, h, w, D, nbits, P1, P2, vol)
+    if (dpl <= 1) SV_SGM(1);
+    else if (dpl <= 2) SV_SGM(2);
+    else if (dpl <= 4) SV_SGM(4);
+    else if (dpl <= 8) SV_SGM(8);
+    else SV_SGM(16);
+#undef SV_SGM
+    SV_LAUNCH_CHECK("k_sgm_paths");
+    const size_t npix = (size_t)B * h * w;
+    const int blocks = (int)std::min<size_t>((npix + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_sgm_wta, dim3(blocks), dim3(256), 0, s, vol, npix * D, D, npix, disp);
+    SV_LAUNCH_CHECK("k_sgm_wta");
+    return SV_OK;
+}
+
+sv_status launch_smp_median(const uint8_t *disp, int B, int h, int w, int D, uint8_t *tmp,
+                            uint8_t *out, hipStream_t s)
+{
+    if (w > SMP_MAXW) return SV_ERR_SHAPE;
+    hipLaunchKernelGGL(k_smp, dim3(B * h), dim3(64), 0, s, disp, B, h, w, D, tmp);
+    SV_LAUNCH_CHECK("k_smp");
+    const size_t n = (size_t)B * h * w;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_median3, dim3(blocks), dim3(256), 0, s, tmp, B, h, w, out);
+    SV_LAUNCH_CHECK("k_median3");
+    return SV_OK;
+}
+
+}  // namespace sv

@@ -79,6 +79,42 @@ def sv_cost_wta(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int,
     return out
 
 
+def sv_sgm(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int, P1: int, P2: int,
+           out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Census maps (int64 bits) [B, h, w] -> semi-global matching disparity uint8
+    [B, h, w] (four axis paths, Eqs. (4)-(6)).  The path-cost volumes live in
+    `workspace` (uint8, at least sv_sgm_workspace_bytes) when given."""
+    _need(cen_l, torch.int64, "cen_l")
+    _need(cen_r, torch.int64, "cen_r")
+    if cen_l.shape != cen_r.shape:
+        raise ValueError("census maps differ in shape")
+    B, h, w = cen_l.shape
+    need = lib().sv_sgm_workspace_bytes(B, h, w, D)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cen_l.device)
+    if out is None:
+        out = torch.empty((B, h, w), dtype=torch.uint8, device=cen_l.device)
+    check(lib().sv_sgm(ptr(cen_l), ptr(cen_r), B, h, w, D, nbits, P1, P2, ptr(out), ptr(workspace),
+                       workspace.numel(), stream_ptr()), "sv_sgm")
+    return out
+
+
+def sv_smp_median(disp: torch.Tensor, D: int, out: torch.Tensor | None = None,
+                  workspace: torch.Tensor | None = None):
+    """Single matching phase (Eq. (7)) with nearest-valid filling, then a 3 x 3
+    median: uint8 [B, h, w] -> uint8 [B, h, w]."""
+    _need(disp, torch.uint8, "disp")
+    B, h, w = disp.shape
+    if workspace is None:
+        workspace = torch.empty(max(lib().sv_smp_workspace_bytes(B, h, w), 1), dtype=torch.uint8,
+                                device=disp.device)
+    if out is None:
+        out = torch.empty_like(disp)
+    check(lib().sv_smp_median(ptr(disp), B, h, w, D, ptr(out), ptr(workspace), workspace.numel(),
+                              stream_ptr()), "sv_smp_median")
+    return out
+
+
 def sv_set_cost_wta_split(dsplit: int):
     check(lib().sv_set_cost_wta_split(dsplit), "sv_set_cost_wta_split")
 

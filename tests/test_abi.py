@@ -51,6 +51,31 @@ def test_cost_wta_validation(args, code):
     assert lib().sv_cost_wta(*args) == code
 
 
+@pytest.mark.parametrize("args,code", [
+    ((None, P, 1, 4, 4, 8, 24, 10, 120, P, P, 1024, None), -1),
+    ((P, P, 1, 4, 4, 8, 24, 10, 120, P, None, 1024, None), -1),
+    ((P, P, 1, 0, 4, 8, 24, 10, 120, P, P, 1024, None), -2),
+    ((P, P, 1, 4, 4, 257, 24, 10, 120, P, P, 10 ** 6, None), -3),
+    ((P, P, 1, 4, 4, 8, 24, 10, 5, P, P, 1024, None), -3),      # P2 < P1
+    ((P, P, 1, 4, 4, 8, 24, -1, 120, P, P, 1024, None), -3),    # P1 < 0
+    ((P, P, 1, 4, 4, 8, 62, 10, 193, P, P, 1024, None), -3),    # path costs beyond uint8
+    ((P, P, 1, 4, 4, 8, 24, 10, 120, P, P, 4 * 4 * 4 * 8 - 1, None), -5),
+])
+def test_sgm_validation(args, code):
+    assert lib().sv_sgm(*args) == code
+
+
+@pytest.mark.parametrize("args,code", [
+    ((None, 1, 4, 4, 8, P, P, 16, None), -1),
+    ((P, 1, 4, 4, 8, P, None, 16, None), -1),
+    ((P, 1, 4, 16385, 8, P, P, 10 ** 6, None), -2),
+    ((P, 1, 4, 4, 0, P, P, 16, None), -3),
+    ((P, 1, 4, 4, 8, P, P, 15, None), -5),
+])
+def test_smp_median_validation(args, code):
+    assert lib().sv_smp_median(*args) == code
+
+
 def test_vae_validation():
     l = lib()
     d = make_desc(16, 32, 64, 64, 2, "f32")

@@ -1,0 +1,80 @@
+"""GPU parity of semi-global matching (Eqs. (4)-(6)) and of the single matching
+phase + median (Eq. (7)): bit-exact against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import gen_config, gen_pair
+from tests.gpu_util import bits, cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(cl, cr, D, nbits, P1, P2):
+    import paper_2305_11566_amd as sv
+    tl = cuda(cl.view(np.int64))
+    tr = cuda(cr.view(np.int64))
+    raw = sv.sv_sgm(tl, tr, D, nbits, P1, P2)
+    post = sv.sv_smp_median(raw, D)
+    torch.cuda.synchronize()
+    return raw.cpu().numpy(), post.cpu().numpy()
+
+
+def _check(cl, cr, D, nbits, P1, P2):
+    raw, post = _gpu(cl, cr, D, nbits, P1, P2)
+    ref_raw = oracle.wta(oracle.sgm(oracle.cost_volume(cl, cr, D, nbits), P1, P2))
+    assert (raw == ref_raw).all(), f"SGM disparity: {np.sum(raw != ref_raw)} of {raw.size} differ"
+    ref_post = oracle.median3(oracle.smp(ref_raw, D))
+    assert (post == ref_post).all(), f"SMP + median: {np.sum(post != ref_post)} of {post.size} differ"
+    return raw, post
+
+
+def _census_pair(left, right, f, ww, wh):
+    lo_l, lo_r = oracle.downsample(left, f), oracle.downsample(right, f)
+    return oracle.census(lo_l, ww, wh), oracle.census(lo_r, ww, wh)
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_workload_pairs(k):
+    p = gen_config(k)
+    f, ww, wh, D = {1: (2, 5, 5, 16), 2: (4, 9, 7, 48)}[k]
+    cl, cr = _census_pair(p.left[None], p.right[None], f, ww, wh)
+    _check(cl, cr, D, ww * wh - 1, 10, 120)
+
+
+def test_uneven_batch_pairs_wide_ranges():
+    # the 64-pair workload's ranges reach 80 (two and more disparities per lane)
+    for i in (0, 7, 63):
+        p = gen_config(4, i)
+        cl, cr = _census_pair(p.left[None], p.right[None], 4, 9, 7)
+        _check(cl, cr, p.D, 62, 10, 120)
+
+
+@pytest.mark.parametrize("h,w,D,P1,P2", [
+    (1, 1, 1, 10, 120),       # single pixel
+    (7, 5, 16, 10, 120),      # w < D
+    (3, 300, 256, 10, 120),   # D = 256: 16 disparities per lane
+    (9, 40, 33, 10, 120),     # ragged lane split
+    (12, 17, 8, 0, 0),        # zero penalties: plain winner-take-all
+    (5, 70, 64, 1, 2),
+    (40, 1, 4, 3, 9),         # one column
+])
+def test_edge_shapes(h, w, D, P1, P2):
+    rng = np.random.default_rng(h * 100 + w)
+    cl = rng.integers(0, 2 ** 62, (2, h, w), dtype=np.uint64)
+    cr = np.roll(cl, 2, axis=2) ^ rng.integers(0, 2 ** 3, (2, h, w), dtype=np.uint64)
+    raw, _ = _check(cl, cr, D, 62, P1, P2)
+    if P1 == 0 and P2 == 0:
+        assert (raw == oracle.wta(oracle.cost_volume(cl, cr, D, 62))).all()
+
+
+def test_sgm_then_network_runs_and_is_deterministic():
+    import paper_2305_11566_amd as sv
+    p = gen_config(2)
+    l, r = cuda(p.left[None]), cuda(p.right[None])
+    cl, cr, low = sv.sv_census_pair(l, r, 4, 9, 7)
+    a = sv.sv_smp_median(sv.sv_sgm(cl, cr, 48, 62, 10, 120), 48)
+    b = sv.sv_smp_median(sv.sv_sgm(cl, cr, 48, 62, 10, 120), 48)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
