@@ -77,13 +77,20 @@ def stage_work(stage, B, dtype):
     return None, 0.0, ""
 
 
+_INPUTS = {}
+
+
 def make_inputs(B, device):
+    """B seeded 1242x375 pairs (seeds 2000..2000+B-1), cached per batch size."""
+    if (B, str(device)) in _INPUTS:
+        return _INPUTS[(B, str(device))]
     import torch
     from synth import gen_config
     pairs = [gen_config(2, i) for i in range(B)]
     left = torch.from_numpy(np.stack([p.left for p in pairs])).to(device)
     right = torch.from_numpy(np.stack([p.right for p in pairs])).to(device)
     gt = np.stack([p.gt for p in pairs])
+    _INPUTS[(B, str(device))] = (left, right, gt)
     return left, right, gt
 
 
@@ -163,6 +170,77 @@ def cpu_baseline(budget_s=12.0):
             break
     return {"value": n / el, "unit": "frames/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} whole frames (1242x375, census+WTA+FP64 network), single thread, {el:.1f} s"}
+
+
+def run_sgm(sv, torch, dev, flat, K, Wm):
+    """Census + SGM (four axis paths) + single matching phase + median on the
+    1242x375 pairs, graph replayed: frames/s of the matching stage at batch 1
+    and 64, of matching + FP32 network at batch 1, and the SGM call's HBM rate
+    (algorithmic bytes: both census maps read once per path direction, the
+    four uint8 path-cost volumes written and read back, the map written)."""
+    P1, P2 = 10, 120
+    out = {"penalties": [P1, P2], "paths": 4}
+    for B in (1, 64):
+        left, right, _ = make_inputs(B, dev)
+        hs, ws = levels(B)
+        h, w = hs[0], ws[0]
+        cl = torch.empty((B, h, w), dtype=torch.int64, device=dev)
+        cr, low = torch.empty_like(cl), torch.empty((B, h, w), dtype=torch.uint8, device=dev)
+        raw, disp = torch.empty_like(low), torch.empty_like(low)
+        wsg = torch.empty(sv.lib().sv_sgm_workspace_bytes(B, h, w, D), dtype=torch.uint8, device=dev)
+        wsm = torch.empty(sv.lib().sv_smp_workspace_bytes(B, h, w), dtype=torch.uint8, device=dev)
+        ref = None
+        if B == 1:
+            ref = sv.Refiner(C1, C2, C3, LAT, F, "f32")
+            ref.pack(torch.from_numpy(flat).to(dev))
+            ref.workspace(B, H, W)
+            res = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+
+        def match():
+            sv.sv_census_pair(left, right, F, WIN_W, WIN_H, out=(cl, cr, low))
+            sv.sv_sgm(cl, cr, D, NBITS, P1, P2, out=raw, workspace=wsg)
+            sv.sv_smp_median(raw, D, out=disp, workspace=wsm)
+
+        def full():
+            match()
+            ref.forward(disp, low, H, W, out=res)
+
+        def graph_ms(fn):
+            fn()
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                fn()
+            for _ in range(Wm):
+                g.replay()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(K):
+                g.replay()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t0) * 1e3 / K
+
+        ms_m = graph_ms(match)
+        rec = {"match_ms": round(ms_m, 4), "match_frames_per_s": round(B * 1e3 / ms_m, 1)}
+        if ref is not None:
+            ms_f = graph_ms(full)
+            rec.update(with_network_f32_ms=round(ms_f, 4),
+                       with_network_f32_frames_per_s=round(B * 1e3 / ms_f, 1))
+        # the SGM call alone (path sweeps + aggregation / WTA), HIP events on its stream
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        sv.sv_sgm(cl, cr, D, NBITS, P1, P2, out=raw, workspace=wsg)
+        e0.record()
+        for _ in range(K):
+            sv.sv_sgm(cl, cr, D, NBITS, P1, P2, out=raw, workspace=wsg)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / K
+        npx = B * h * w
+        nbytes = npx * (4 * 16 + 4 * D + 4 * D + 1)
+        rec.update(sgm_us=round(us, 2), sgm_hbm_GBs=round(nbytes / (us * 1e-6) / 1e9, 1),
+                   sgm_hbm_frac=round(nbytes / (us * 1e-6) / 1e9 / PEAK["hbm_GBs"], 4))
+        out[f"batch_{B}"] = rec
+    return out
 
 
 def run_extras(sv, torch, dev, flat, K, Wm):
@@ -366,6 +444,8 @@ def main():
             torch.cuda.synchronize()
 
     extras = {} if args.no_extras else run_extras(sv, torch, dev, flat, K, Wm)
+    if not args.no_extras:
+        extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 

@@ -118,7 +118,9 @@ sv_status sv_set_cost_wta_split(int dsplit);
 /* Semi-global matching and post-processing (Sec. III-A2, III-A3)             */
 /* ------------------------------------------------------------------------ */
 
-/* Bytes of workspace sv_sgm needs: the four path-cost volumes, 4 * B*h*w*D. */
+/* Bytes of workspace sv_sgm needs: the matching-cost volume and the four
+ * path-cost volumes, uint8 each, 5 * B*h*w*Dp with Dp = D rounded up to a
+ * multiple of 4. */
 size_t sv_sgm_workspace_bytes(int B, int h, int w, int D);
 
 /*

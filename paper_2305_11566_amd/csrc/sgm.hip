@@ -4,15 +4,14 @@
 // of the paper's matching family (S2 of Sec. IV-C), at the reduced
 // resolution.
 //
-// Path costs (Eq. (4)) along the four axis directions.  One 16-lane DPP row
-// of a wavefront follows one path (four paths per wave); lane l holds the
+// The matching cost is first written as a uint8 volume.  Path costs (Eq. (4))
+// run along the four axis directions: one 16-lane DPP row of a wavefront
+// follows one path (four paths per wave); lane l holds the
 // disparities d = l * DPL + j, j < DPL, in registers, so d - 1 and d + 1 are
 // in the same lane except at the ends of its run, which come from the
 // neighbouring lanes by DPP row shifts, and min_k C_r(p - r, k) is a DPP row
-// rotate-and-min.  The matching cost C(p, d) (Hamming distance of the census
-// codes, nbits + 1 where x - d < 0) is recomputed on the fly and never
-// stored; each direction writes its path costs C_r as uint8 into a volume of
-// its own, and the WTA kernel sums the four (Eq. (5)).
+// rotate-and-min.  Each direction writes its path costs C_r as uint8 into a
+// volume of its own, and the WTA kernel sums the four (Eq. (5)).
 #include "common.h"
 #include "kernels.h"
 
@@ -34,13 +33,87 @@ __device__ __forceinline__ int row_min(int v) {
     return v;
 }
 
+// Matching cost volume C(p, d) (the cost of Eq. (6): Hamming distance of the
+// census codes, nbits + 1 where x - d < 0) as uint8 [B][h][w][Dp], Dp = D
+// rounded up to a multiple of 4 (the padding is never read as a cost).  One
+// workgroup = a row segment of CV_TW pixels; the right census codes it needs,
+// [j0 - D + 1, j0 + CV_TW), are staged in LDS once; a thread writes four
+// disparities of a pixel as one 32-bit word.
+constexpr int CV_TW = 64;
+__global__ void __launch_bounds__(256)
+k_sgm_cost(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int h, int w, int D,
+           int Dp, int nbits, uint8_t *__restrict__ cost)
+{
+    __shared__ uint64_t seg[CV_TW + 256];
+    const size_t row = ((size_t)blockIdx.z * h + blockIdx.y) * w;
+    const int j0 = blockIdx.x * CV_TW;
+    const int base = j0 - (D - 1);
+    for (int e = threadIdx.x; e < CV_TW + D - 1; e += blockDim.x) {
+        const int x = base + e;
+        seg[e] = (x >= 0 && x < w) ? cr[row + x] : 0;
+    }
+    __syncthreads();
+    const int ng = Dp / 4;
+    for (int e = threadIdx.x; e < CV_TW * ng; e += blockDim.x) {
+        const int px = e / ng, g = e - px * ng;
+        const int j = j0 + px;
+        if (j >= w) continue;
+        const uint64_t lv = cl[row + j];
+        uint32_t word = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int d = 4 * g + k;
+            // column j - d of the right view is seg[px + D - 1 - d]
+            const uint32_t c = d >= D ? 0u
+                             : (j - d < 0 ? (uint32_t)(nbits + 1)
+                                          : (uint32_t)__popcll(lv ^ seg[px + D - 1 - (d < D ? d : 0)]));
+            word |= c << (8 * k);
+        }
+        *(uint32_t *)(cost + (row + j) * Dp + 4 * g) = word;
+    }
+}
+
 // Path p of npath: directions 0 (left to right) and 1 (right to left) run
 // along rows, 2 (top to bottom) and 3 (bottom to top) along columns;
-// vol[dir][b][y][x][d].
+// vol[dir][b][y][x][Dp].  The step's costs are loaded SGM_PF steps ahead into
+// a ring of registers, so the dependent chain of a step is arithmetic and DPP
+// only.
+constexpr int SGM_PF = 16;
+template <int DPL>
+struct CostWords {
+    static constexpr int N = DPL >= 4 ? DPL / 4 : 1;
+    uint32_t v[N];
+    uint32_t ok;  // bit k: word k holds costs (else it is read as zero)
+};
+
+// The costs of disparities d0 .. d0 + DPL - 1 of one pixel (p points at d0).
+// The loads are unconditional (a word at or past Dp, or of a step past the
+// path's end, reads `safe` instead) and the mask is applied where the costs
+// are used, so nothing waits for a load until its step comes.
+template <int DPL>
+__device__ __forceinline__ void load_costs(const uint8_t *__restrict__ p, const uint8_t *safe, bool ok,
+                                           int d0, int Dp, CostWords<DPL> &c) {
+    c.ok = 0;
+    if constexpr (DPL >= 4) {
+#pragma unroll
+        for (int k = 0; k < DPL / 4; ++k) {
+            const bool okk = ok && d0 + 4 * k < Dp;
+            c.v[k] = *(const uint32_t *)(okk ? p + 4 * k : safe);
+            c.ok |= (uint32_t)okk << k;
+        }
+    } else if constexpr (DPL == 2) {
+        c.v[0] = *(const uint16_t *)(ok ? p : safe);
+        c.ok = ok;
+    } else {
+        c.v[0] = *(ok ? p : safe);
+        c.ok = ok;
+    }
+}
+
 template <int DPL>
 __global__ void __launch_bounds__(64)
-k_sgm_paths(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int B, int h, int w,
-            int D, int nbits, int P1, int P2, uint8_t *__restrict__ vol)
+k_sgm_paths(const uint8_t *__restrict__ cost, int B, int h, int w, int D, int Dp, int P1, int P2,
+            uint8_t *__restrict__ vol, uint8_t *__restrict__ sink)
 {
     const int lane = threadIdx.x & (SGM_LANES - 1);
     const int path = blockIdx.x * 4 + (threadIdx.x >> 4);
@@ -50,35 +123,53 @@ k_sgm_paths(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, in
     int dir, line;
     if (path < 2 * nrow) { dir = path / nrow; line = path - dir * nrow; }
     else { const int q = path - 2 * nrow; dir = 2 + q / ncol; line = q - (dir - 2) * ncol; }
-    int b, x, y, dx, dy, len;
+    int b, x0, y0, dx, dy, len;
     if (dir < 2) {
-        b = line / h; y = line - b * h;
+        b = line / h; y0 = line - b * h;
         dx = dir == 0 ? 1 : -1; dy = 0;
-        x = dir == 0 ? 0 : w - 1;
+        x0 = dir == 0 ? 0 : w - 1;
         len = w;
     } else {
-        b = line / w; x = line - b * w;
+        b = line / w; x0 = line - b * w;
         dx = 0; dy = dir == 2 ? 1 : -1;
-        y = dir == 2 ? 0 : h - 1;
+        y0 = dir == 2 ? 0 : h - 1;
         len = h;
     }
-    const uint64_t *clb = cl + (size_t)b * h * w, *crb = cr + (size_t)b * h * w;
-    uint8_t *vb = vol + ((size_t)dir * B + b) * (size_t)h * w * D;
+    const size_t plane = (size_t)h * w;
+    const uint8_t *cb = cost + (size_t)b * plane * Dp;
+    uint8_t *vb = vol + ((size_t)dir * B + b) * plane * Dp;
     const int d0 = lane * DPL;
+    const bool lane_ok = d0 < Dp;
+    // pixel offset (in pixels) of step s
+    const long long step_px = (long long)dy * w + dx;
+    const long long px0 = (long long)y0 * w + x0;
+    // words of lanes past Dp are stored to a per-lane sink (never read), so
+    // stores, like loads, need no branch
+    uint8_t *my_sink = sink + (size_t)(threadIdx.x & 63) * 64;
+
+    CostWords<DPL> ring[SGM_PF];
+#pragma unroll
+    for (int k = 0; k < SGM_PF; ++k)
+        load_costs<DPL>(cb + (size_t)(px0 + (long long)(k < len ? k : 0) * step_px) * Dp + d0, cb,
+                        lane_ok && k < len, d0, Dp, ring[k]);
 
     int prev[DPL];
+#pragma unroll
+    for (int j = 0; j < DPL; ++j) prev[j] = SGM_INF;
     int mprev = 0;
-    for (int s = 0; s < len; ++s, x += dx, y += dy) {
-        const size_t row = (size_t)y * w;
-        const uint64_t lv = clb[row + x];
+    // one step s of the path, its costs in ring slot k (refilled with step s + SGM_PF)
+    auto step = [&](int k, int s) {
         int c[DPL];
 #pragma unroll
         for (int j = 0; j < DPL; ++j) {
-            const int d = d0 + j;
-            const int xr = x - d;
-            c[j] = d >= D ? SGM_INF
-                          : (xr < 0 ? nbits + 1 : (int)__popcll(lv ^ crb[row + (xr < 0 ? 0 : xr)]));
+            const int q = DPL >= 4 ? j / 4 : 0;
+            const uint32_t word = ((ring[k].ok >> q) & 1u) ? ring[k].v[q] : 0u;
+            const int sh = DPL >= 4 ? 8 * (j % 4) : 8 * j;
+            c[j] = d0 + j < D ? (int)((word >> sh) & 0xffu) : SGM_INF;
         }
+        const int sn = s + SGM_PF;
+        load_costs<DPL>(cb + (size_t)(px0 + (long long)(sn < len ? sn : 0) * step_px) * Dp + d0, cb,
+                        lane_ok && sn < len, d0, Dp, ring[k]);
         int cur[DPL];
         if (s == 0) {
 #pragma unroll
@@ -99,39 +190,53 @@ k_sgm_paths(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, in
 #pragma unroll
         for (int j = 1; j < DPL; ++j) mn = min(mn, cur[j]);
         mprev = row_min(mn);
-        uint8_t *o = vb + (row + x) * D;
+        uint8_t *o = vb + (size_t)(px0 + (long long)s * step_px) * Dp + d0;
+        if constexpr (DPL >= 4) {
 #pragma unroll
-        for (int j = 0; j < DPL; ++j) {
-            prev[j] = cur[j];
-            if (d0 + j < D) o[d0 + j] = (uint8_t)cur[j];
+            for (int q = 0; q < DPL / 4; ++q) {
+                uint32_t word = 0;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) word |= (uint32_t)(cur[4 * q + t] & 0xff) << (8 * t);
+                const bool okq = lane_ok && d0 + 4 * q < Dp;
+                *(uint32_t *)(okq ? o + 4 * q : my_sink + 4 * q) = word;
+            }
+        } else if constexpr (DPL == 2) {
+            *(uint16_t *)(lane_ok ? o : my_sink) = (uint16_t)((cur[0] & 0xff) | ((cur[1] & 0xff) << 8));
+        } else {
+            *(lane_ok ? o : my_sink) = (uint8_t)cur[0];
         }
+#pragma unroll
+        for (int j = 0; j < DPL; ++j) prev[j] = cur[j];
+    };
+    int s0 = 0;
+    for (; s0 + SGM_PF <= len; s0 += SGM_PF) {
+#pragma unroll
+        for (int k = 0; k < SGM_PF; ++k) step(k, s0 + k);
     }
+#pragma unroll
+    for (int k = 0; k < SGM_PF; ++k)
+        if (s0 + k < len) step(k, s0 + k);
 }
 
-// Aggregated cost (Eq. (5)) and winner-take-all (Eq. (6)), lowest d on ties.
+// Aggregated cost (Eq. (5)) and winner-take-all (Eq. (6)), lowest d on ties;
+// the four volumes are [B][h][w][Dp].
 __global__ void __launch_bounds__(256)
-k_sgm_wta(const uint8_t *__restrict__ vol, size_t nvox, int D, size_t npix, uint8_t *__restrict__ disp)
+k_sgm_wta(const uint8_t *__restrict__ vol, size_t nvox, int D, int Dp, size_t npix,
+          uint8_t *__restrict__ disp)
 {
     for (size_t p = blockIdx.x * (size_t)blockDim.x + threadIdx.x; p < npix;
          p += (size_t)gridDim.x * blockDim.x) {
-        const uint8_t *v0 = vol + p * D, *v1 = v0 + nvox, *v2 = v1 + nvox, *v3 = v2 + nvox;
+        const uint8_t *v0 = vol + p * Dp, *v1 = v0 + nvox, *v2 = v1 + nvox, *v3 = v2 + nvox;
         int best = 0x7fffffff, bd = 0;
-        if ((D & 3) == 0) {
-            for (int d = 0; d < D; d += 4) {
-                const uint32_t a = *(const uint32_t *)(v0 + d), bq = *(const uint32_t *)(v1 + d);
-                const uint32_t cq = *(const uint32_t *)(v2 + d), dq = *(const uint32_t *)(v3 + d);
+        for (int d = 0; d < D; d += 4) {
+            const uint32_t a = *(const uint32_t *)(v0 + d), bq = *(const uint32_t *)(v1 + d);
+            const uint32_t cq = *(const uint32_t *)(v2 + d), dq = *(const uint32_t *)(v3 + d);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const int sh = 8 * k;
-                    const int s = (int)((a >> sh) & 0xff) + (int)((bq >> sh) & 0xff) +
-                                  (int)((cq >> sh) & 0xff) + (int)((dq >> sh) & 0xff);
-                    if (s < best) { best = s; bd = d + k; }
-                }
-            }
-        } else {
-            for (int d = 0; d < D; ++d) {
-                const int s = (int)v0[d] + v1[d] + v2[d] + v3[d];
-                if (s < best) { best = s; bd = d; }
+            for (int k = 0; k < 4; ++k) {
+                const int sh = 8 * k;
+                const int s = (int)((a >> sh) & 0xff) + (int)((bq >> sh) & 0xff) +
+                              (int)((cq >> sh) & 0xff) + (int)((dq >> sh) & 0xff);
+                if (d + k < D && s < best) { best = s; bd = d + k; }
             }
         }
         disp[p] = (uint8_t)bd;
@@ -229,16 +334,29 @@ k_median3(const uint8_t *__restrict__ in, int B, int h, int w, uint8_t *__restri
     }
 }
 
-size_t sgm_volume_bytes(int B, int h, int w, int D) { return (size_t)4 * B * h * w * D; }
+static inline int sgm_dpad(int D) { return (D + 3) & ~3; }
+
+// the cost volume, the four path-cost volumes, and a 4 KB sink for the
+// stores of lanes past the padded disparity range
+constexpr size_t SGM_SINK = 4096;
+size_t sgm_volume_bytes(int B, int h, int w, int D) {
+    return (size_t)5 * B * h * w * sgm_dpad(D) + SGM_SINK;
+}
 
 sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
-                     int P1, int P2, uint8_t *vol, uint8_t *disp, hipStream_t s)
+                     int P1, int P2, uint8_t *ws, uint8_t *disp, hipStream_t s)
 {
+    const int Dp = sgm_dpad(D);
+    const size_t nvox = (size_t)B * h * w * Dp;
+    uint8_t *cost = ws, *vol = ws + nvox, *sink = ws + 5 * nvox;
+    hipLaunchKernelGGL(k_sgm_cost, dim3(cdiv(w, CV_TW), h, B), dim3(256), 0, s, cl, cr, h, w, D, Dp,
+                       nbits, cost);
+    SV_LAUNCH_CHECK("k_sgm_cost");
     const int npath = 2 * B * h + 2 * B * w;
     const dim3 grid(cdiv(npath, 4));
     const int dpl = cdiv(D, SGM_LANES);
-#define SV_SGM(N)                                                                                  \
-    hipLaunchKernelGGL(k_sgm_paths<N>, grid, dim3(64), 0, s, cl, cr, B, h, w, D, nbits, P1, P2, vol)
+#define SV_SGM(N) \
+    hipLaunchKernelGGL(k_sgm_paths<N>, grid, dim3(64), 0, s, cost, B, h, w, D, Dp, P1, P2, vol, sink)
     if (dpl <= 1) SV_SGM(1);
     else if (dpl <= 2) SV_SGM(2);
     else if (dpl <= 4) SV_SGM(4);
@@ -248,7 +366,7 @@ sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w
     SV_LAUNCH_CHECK("k_sgm_paths");
     const size_t npix = (size_t)B * h * w;
     const int blocks = (int)std::min<size_t>((npix + 255) / 256, 8192);
-    hipLaunchKernelGGL(k_sgm_wta, dim3(blocks), dim3(256), 0, s, vol, npix * D, D, npix, disp);
+    hipLaunchKernelGGL(k_sgm_wta, dim3(blocks), dim3(256), 0, s, vol, nvox, D, Dp, npix, disp);
     SV_LAUNCH_CHECK("k_sgm_wta");
     return SV_OK;
 }
