@@ -38,6 +38,7 @@ struct sv_batch_plan {
     sv_vae_desc desc;
     int max_n, max_H, max_W, max_D, win_w, win_h, nbits;
     int dsplit;
+    int cen_th;  // census tile height (4 or 16)
     int cfg[NLAYERS];
     int grid[BS_NSTAGES];
     size_t cap[4];
@@ -203,7 +204,7 @@ static int run_cout(const NetShape &ns, int li) { return li == L_F ? 9 : ns.ly[l
 
 // Tiles of every stage for one pair.
 static void pair_tiles(const sv_batch_plan *pl, const PairGeo &g, int *tiles) {
-    tiles[BS_CENSUS] = 2 * cdiv(g.w[0], CEN_TILE_W) * cdiv(g.h[0], CEN_TILE_H);
+    tiles[BS_CENSUS] = 2 * cdiv(g.w[0], CEN_TILE_W) * cdiv(g.h[0], pl->cen_th);
     tiles[BS_COST_WTA] = g.h[0] * cdiv(g.w[0], cost_wta_tile_width(pl->dsplit));
     for (const LayerRun &r : kRuns)
         tiles[r.stage] = conv_tiles(pl->cfg[r.li], g.h[r.out_level], g.w[r.out_level],
@@ -227,8 +228,8 @@ static ConvSrc tsrc(const void *p, int kind, int C, int pitch, int level, int sd
 static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream_t st) {
     const NetShape &ns = pl->ns;
     const int c1 = ns.c1, c2 = ns.c2, c3 = ns.c3, L = ns.L;
-    sv_status r = launch_reduce_census_tab(pl->tab_dev, pl->grid[BS_CENSUS], ns.f, pl->win_w,
-                                           pl->win_h, pl->low, pl->cl, pl->cr, st);
+    sv_status r = launch_reduce_census_tab(pl->tab_dev, pl->grid[BS_CENSUS], ns.f, pl->cen_th,
+                                           pl->win_w, pl->win_h, pl->low, pl->cl, pl->cr, st);
     if (r != SV_OK) return r;
     r = launch_cost_wta_tab(pl->tab_dev, pl->grid[BS_COST_WTA], pl->cl, pl->cr, pl->nbits, pl->disp,
                             pl->dsplit, st);
@@ -328,6 +329,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     // tile shapes: the autotune cache, else the single-call defaults
     pl->dsplit = cost_wta_split_get();
     const Levels mx = net_levels(ns, max_H, max_W);
+    pl->cen_th = census_tile_height(max_n, mx.h[0], mx.w[0]);
     for (int i = 0; i < NLAYERS; ++i) {
         const int lvl = i == L_E1 ? 1 : (i == L_E2 ? 2 : (i <= L_G3 ? 3 : (i == L_G2 ? 2 : (i == L_G1 ? 1 : 0))));
         pl->cfg[i] = net_default_cfg(ns, i, mx.h[lvl] * mx.w[lvl]);
@@ -670,7 +672,8 @@ const char *sv_conv_cfg_name(int cfg) { return conv_cfg_name(cfg); }
 sv_status sv_tile_config(int stage, char *buf, int buflen) {
     if (!buf || buflen < 1) return SV_ERR_NULL;
     if (stage == 0) {
-        snprintf(buf, buflen, "census tile %dx%d", CEN_TILE_W, CEN_TILE_H);
+        snprintf(buf, buflen, "census tile %dx4 (one frame) or %dx16 (from 512 tall tiles)", CEN_TILE_W,
+                 CEN_TILE_W);
     } else if (stage == 1) {
         snprintf(buf, buflen, "cost_wta dsplit=%d", cost_wta_split_get());
     } else if (stage >= 2 && stage < 2 + NLAYERS) {

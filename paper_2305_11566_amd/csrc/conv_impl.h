@@ -320,8 +320,14 @@ struct ConvTile {
                 constexpr int NG1 = NGR > NGT ? NGR : NGT;
                 constexpr int NG = NG1 > NGW ? NG1 : NGW;
                 const int pix0 = tid / KCG;
-                const bool fast_resize = kind == SRC_RESIZE && sdt == DT;
-                const bool fast_plain = (kind == SRC_TENSOR || kind == SRC_ZINS) && sdt == DT;
+                // a chunk that holds only the two channels of the network input x0
+                // (the first layer, and the last chunk of the layer before the final
+                // one) is staged by all threads below, one patch pixel each
+                const bool x0_only = c0 + GS >= p.Cin &&
+                                     ((c0 == 0 && p.src[0].kind == SRC_X0) ||
+                                      (c0 == C0 && p.src[1].kind == SRC_X0));
+                const bool fast_resize = kind == SRC_RESIZE && sdt == DT && !x0_only;
+                const bool fast_plain = (kind == SRC_TENSOR || kind == SRC_ZINS) && sdt == DT && !x0_only;
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     // -- issue
@@ -423,7 +429,34 @@ struct ConvTile {
                 // -- the remaining kinds, element by element: a source stored in
                 // another dtype or the network input x0 (groups past Cin are
                 // never read by the MFMA steps and are not written)
-                if (!fast_resize && !fast_plain && kind != SRC_NONE) {
+                if (x0_only) {
+                    const ConvSrc &sx = c0 == 0 ? p.src[0] : p.src[1];
+                    const PixSrc *tx = sm.ps[c0 == 0 ? 0 : 1];
+                    constexpr int NX = (NPIX + 255) / 256;
+                    uint32_t dv[NX], iv[NX];
+                    bool okx[NX];
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) {  // all loads first
+                        const int pix = tid + k * 256;
+                        const int pi = pix < NPIX ? tx[pix].p[0] : -1;
+                        okx[k] = pi >= 0;
+                        dv[k] = ((const uint8_t *)sx.ptr)[okx[k] ? pi : 0];
+                        iv[k] = sx.img[okx[k] ? pi : 0];
+                    }
+#pragma unroll
+                    for (int k = 0; k < NX; ++k) {
+                        const int pix = tid + k * 256;
+                        if (pix >= NPIX) continue;
+                        float v[GS];
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = 0.f;
+                        if (okx[k]) {
+                            v[0] = sx.scale0 * (float)dv[k];
+                            v[1] = (float)iv[k] * (1.0f / 256.0f);
+                        }
+                        *(vec *)&patch[pix * KCP] = pack_vec<DT, GS>(v);
+                    }
+                } else if (!fast_resize && !fast_plain && kind != SRC_NONE) {
 #pragma unroll
                     for (int k = 0; k < NE; ++k) {
                         const int pix = pix0 + k * PSTEP;

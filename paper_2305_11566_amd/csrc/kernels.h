@@ -44,8 +44,11 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
 sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,
                           int nbits, uint8_t *disp, int dsplit, hipStream_t s);
 // persistent variants over a pair table (flattened level-0 buffers)
-sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int win_w, int win_h,
-                                   uint8_t *low0, uint64_t *cen0, uint64_t *cen1, hipStream_t s);
+sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int th, int win_w,
+                                   int win_h, uint8_t *low0, uint64_t *cen0, uint64_t *cen1,
+                                   hipStream_t s);
+// census tile height (4 or 16 reduced rows) for a uniform launch of B images
+int census_tile_height(int B, int h, int w);
 size_t sgm_volume_bytes(int B, int h, int w, int D);
 sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
                      int P1, int P2, uint8_t *vol, uint8_t *disp, hipStream_t s);
@@ -54,7 +57,7 @@ sv_status launch_smp_median(const uint8_t *disp, int B, int h, int w, int D, uin
 sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl, const uint64_t *cr,
                               int nbits, uint8_t *disp, int dsplit, hipStream_t s);
 int cost_wta_tile_width(int dsplit);
-constexpr int CEN_TILE_W = 64, CEN_TILE_H = 4;
+constexpr int CEN_TILE_W = 64;
 
 // ---- convolution as implicit GEMM ---------------------------------------------
 // A convolution input is the channel concatenation of up to two sources.

@@ -11,27 +11,29 @@
 namespace sv {
 
 // ---------------------------------------------------------------------------
-// Reduction + census.  One workgroup = CEN_TW x CEN_TH reduced pixels of one
-// image.  The reduced patch with its clamped halo is built once in LDS (each
-// patch pixel is the block mean of F x F full-resolution bytes; F is a
-// template parameter so that the F * F byte loads of several patch pixels are
-// unrolled and in flight together), then every thread packs the census word
-// of its pixel from LDS.
+// Reduction + census.  One workgroup (256 threads) = CEN_TW x TH reduced pixels
+// of one image, TH = 4 or 16 (taller tiles re-read less halo; shorter ones
+// give more workgroups for a single small frame).  The reduced patch with its
+// clamped halo is built once in LDS (each patch pixel is the block mean of
+// F x F full-resolution bytes; F is a template parameter so that the F * F
+// byte loads of several patch pixels are unrolled and in flight together),
+// then every thread packs the census words of its pixels from LDS.
 // ---------------------------------------------------------------------------
-constexpr int CEN_TW = CEN_TILE_W, CEN_TH = CEN_TILE_H, CEN_MAXR = 8;
-constexpr int CEN_THREADS = CEN_TW * CEN_TH;
-typedef uint8_t CenPatch[CEN_TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
+constexpr int CEN_TW = CEN_TILE_W, CEN_MAXR = 8;
+constexpr int CEN_THREADS = 256;
+template <int TH>
+using CenPatch = uint8_t[TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
 
 // One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
-template <int F>
-__device__ __forceinline__ void census_tile(CenPatch &patch, const uint8_t *__restrict__ img, int H,
-                                            int W, int pitch, int rx, int ry, int h, int w, int i0,
-                                            int j0, uint8_t *__restrict__ low,
+template <int F, int TH>
+__device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *__restrict__ img,
+                                            int H, int W, int pitch, int rx, int ry, int h, int w,
+                                            int i0, int j0, uint8_t *__restrict__ low,
                                             uint64_t *__restrict__ cen)
 {
     // patch pixels per thread whose loads are issued before any is summed
     constexpr int R = F * F >= 48 ? 1 : (48 / (F * F) > 4 ? 4 : 48 / (F * F));
-    const int PH = CEN_TH + 2 * ry, PW = CEN_TW + 2 * rx;
+    const int PH = TH + 2 * ry, PW = CEN_TW + 2 * rx;
     const int tid = threadIdx.x;
     for (int e0 = 0; e0 < PH * PW; e0 += R * CEN_THREADS) {
         uint32_t v[R][F * F];
@@ -70,41 +72,43 @@ __device__ __forceinline__ void census_tile(CenPatch &patch, const uint8_t *__re
         }
     }
     __syncthreads();
-    const int ty = tid / CEN_TW, tx = tid - ty * CEN_TW;
-    const int i = i0 + ty, j = j0 + tx;
-    if (i < h && j < w) {
-        const uint8_t c = patch[ty + ry][tx + rx];
-        uint64_t code = 0;
-        int k = 0;
-        for (int dy = -ry; dy <= ry; ++dy)
-            for (int dx = -rx; dx <= rx; ++dx) {
-                if (dy == 0 && dx == 0) continue;
-                code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
-                ++k;
-            }
-        const size_t o = (size_t)i * w + j;
-        cen[o] = code;
-        if (low) low[o] = c;
+    const int tx = tid % CEN_TW;
+    for (int ty = tid / CEN_TW; ty < TH; ty += CEN_THREADS / CEN_TW) {
+        const int i = i0 + ty, j = j0 + tx;
+        if (i < h && j < w) {
+            const uint8_t c = patch[ty + ry][tx + rx];
+            uint64_t code = 0;
+            int k = 0;
+            for (int dy = -ry; dy <= ry; ++dy)
+                for (int dx = -rx; dx <= rx; ++dx) {
+                    if (dy == 0 && dx == 0) continue;
+                    code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
+                    ++k;
+                }
+            const size_t o = (size_t)i * w + j;
+            cen[o] = code;
+            if (low) low[o] = c;
+        }
     }
     __syncthreads();  // the patch is reused by the next tile of a persistent loop
 }
 
-template <int F>
+template <int F, int TH>
 __global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
                 int W, int pitch, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
                 uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
                 uint64_t *__restrict__ cen1)
 {
-    __shared__ CenPatch patch;
+    __shared__ CenPatch<TH> patch;
     const int view = blockIdx.z % 2;
     const int b = blockIdx.z / 2;
     if (view && !img1) return;
     const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
     uint8_t *low = view ? low1 : low0;
     uint64_t *cen = (view ? cen1 : cen0) + (size_t)b * h * w;
-    census_tile<F>(patch, img, H, W, pitch, rx, ry, h, w, blockIdx.y * CEN_TH, blockIdx.x * CEN_TW,
-                   low ? low + (size_t)b * h * w : nullptr, cen);
+    census_tile<F, TH>(patch, img, H, W, pitch, rx, ry, h, w, blockIdx.y * TH, blockIdx.x * CEN_TW,
+                       low ? low + (size_t)b * h * w : nullptr, cen);
 }
 
 #define SV_FACTOR_SWITCH(f, CALL) \
@@ -120,15 +124,28 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
     default: return SV_ERR_RANGE; \
     }
 
+// Tall tiles once they still give two workgroups per CU.
+int census_tile_height(int B, int h, int w) {
+    const long long tall = 2LL * B * cdiv(w, CEN_TW) * cdiv(h, 16);
+    return tall >= 512 ? 16 : 4;
+}
+
 sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, int H, int W,
                                int pitch, int f, int win_w, int win_h, uint8_t *low0,
                                uint8_t *low1, uint64_t *cen0, uint64_t *cen1, hipStream_t s)
 {
     const int h = cdiv(H, f), w = cdiv(W, f);
-    dim3 grid(cdiv(w, CEN_TW), cdiv(h, CEN_TH), 2 * B);
-#define SV_CEN_LAUNCH(F)                                                                        \
-    hipLaunchKernelGGL(k_reduce_census<F>, grid, dim3(CEN_THREADS), 0, s, img0, img1, B, H, W, \
-                       pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0, cen1)
+    const int th = census_tile_height(B, h, w);
+    dim3 grid(cdiv(w, CEN_TW), cdiv(h, th), 2 * B);
+#define SV_CEN_LAUNCH(F)                                                                          \
+    if (th == 16)                                                                                 \
+        hipLaunchKernelGGL((k_reduce_census<F, 16>), grid, dim3(CEN_THREADS), 0, s, img0, img1, B, \
+                           H, W, pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0,  \
+                           cen1);                                                                 \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_reduce_census<F, 4>), grid, dim3(CEN_THREADS), 0, s, img0, img1, B,  \
+                           H, W, pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0,  \
+                           cen1)
     SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
 #undef SV_CEN_LAUNCH
     SV_LAUNCH_CHECK("k_reduce_census");
@@ -137,12 +154,12 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
 
 // Persistent variant: tiles of both views of every pair of the table; the
 // per-pair maps live in flattened buffers at the pair's level-0 offset.
-template <int F>
+template <int F, int TH>
 __global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *__restrict__ low0,
                     uint64_t *__restrict__ cen0, uint64_t *__restrict__ cen1)
 {
-    __shared__ CenPatch patch;
+    __shared__ CenPatch<TH> patch;
     const int n = tab->n;
     const int *cum = tab->cum[BS_CENSUS];
     const int total = cum[n];
@@ -150,21 +167,27 @@ k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *
         const int i = table_find(cum, n, t);
         const PairGeo &g = tab->pair[i];
         const int local = t - cum[i];
-        const int tw = cdiv_d(g.w[0], CEN_TW), th = cdiv_d(g.h[0], CEN_TH);
+        const int tw = cdiv_d(g.w[0], CEN_TW), th = cdiv_d(g.h[0], TH);
         const int view = local / (tw * th), r = local - view * tw * th;
         const long long o = g.off[0];
-        census_tile<F>(patch, view ? g.right : g.left, g.H, g.W, g.W, rx, ry, g.h[0], g.w[0],
-                       (r / tw) * CEN_TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
-                       (view ? cen1 : cen0) + o);
+        census_tile<F, TH>(patch, view ? g.right : g.left, g.H, g.W, g.W, rx, ry, g.h[0], g.w[0],
+                           (r / tw) * TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
+                           (view ? cen1 : cen0) + o);
     }
 }
 
-sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int win_w, int win_h,
-                                   uint8_t *low0, uint64_t *cen0, uint64_t *cen1, hipStream_t s)
+sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int th, int win_w,
+                                   int win_h, uint8_t *low0, uint64_t *cen0, uint64_t *cen1,
+                                   hipStream_t s)
 {
-#define SV_CEN_LAUNCH(F)                                                                         \
-    hipLaunchKernelGGL(k_reduce_census_tab<F>, dim3(grid), dim3(CEN_THREADS), 0, s, tab,        \
-                       (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1)
+    if (th != 4 && th != 16) return SV_ERR_RANGE;
+#define SV_CEN_LAUNCH(F)                                                                          \
+    if (th == 16)                                                                                 \
+        hipLaunchKernelGGL((k_reduce_census_tab<F, 16>), dim3(grid), dim3(CEN_THREADS), 0, s, tab, \
+                           (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1);                   \
+    else                                                                                          \
+        hipLaunchKernelGGL((k_reduce_census_tab<F, 4>), dim3(grid), dim3(CEN_THREADS), 0, s, tab,  \
+                           (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1)
     SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
 #undef SV_CEN_LAUNCH
     SV_LAUNCH_CHECK("k_reduce_census_tab");

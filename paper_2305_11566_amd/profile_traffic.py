@@ -1,0 +1,156 @@
+"""HBM traffic of the headline path's kernels from rocprofv3 counters.
+
+Two modes:
+
+``python -m paper_2305_11566_amd.profile_traffic run``
+    One 1242x375 pair (the benchmark's inputs and weights), matched once, then
+    one FP32 forward pass of the network per layer configuration with every
+    layer set to that configuration (a tile shape that does not fit a layer
+    runs as the fallback and is recorded under the fallback's name), then a
+    plain 64 MiB device copy.  Meant to run under
+    ``rocprofv3 --pmc FETCH_SIZE`` and, separately, ``--pmc WRITE_SIZE``.
+
+``python -m paper_2305_11566_amd.profile_traffic summarize FETCH_DIR WRITE_DIR OUT_JSON``
+    Reads the two counter collections, scales each counter by what it reads
+    for the copy (bytes moved / counter), and writes per-launch HBM bytes for
+    every (layer, configuration) plus census, cost + WTA and the final layer,
+    keyed by a hash of the HIP sources so that a reader can tell whether the
+    kernels have changed since.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+import sys
+
+H, W, F, WIN_W, WIN_H, D = 375, 1242, 4, 9, 7, 48
+C1, C2, C3, LAT = 32, 64, 128, 128
+LAYERS = ("E1", "E2", "E3", "HEAD", "G3", "G2", "G1", "G0")
+COPY_BYTES = 64 << 20
+
+
+def source_hash() -> str:
+    """sha256 over the HIP sources and headers of libsv.so (and include/sv.h)."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    files = sorted(glob.glob(os.path.join(here, "csrc", "*.hip")) +
+                   glob.glob(os.path.join(here, "csrc", "*.h")) +
+                   [os.path.join(here, "..", "include", "sv.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def run() -> None:
+    import numpy as np
+    import torch
+
+    import paper_2305_11566_amd as sv
+    from synth import gen_config, he_init_params
+
+    dev = torch.device("cuda:0")
+    p = gen_config(2, 0)
+    left = torch.from_numpy(p.left[None]).to(dev)
+    right = torch.from_numpy(p.right[None]).to(dev)
+    shapes = [(C1, 2, 3), (C2, C1, 3), (C3, C2, 3), (2 * LAT, C3, 1), (C3, LAT, 1),
+              (C2, C3 + C2, 3), (C1, C2 + C1, 3), (C1, C1 + 2, 3), (1, C1 + 2, 3)]
+    params = he_init_params(shapes, seed=7002)
+    flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+    cl, cr, low = sv.sv_census_pair(left, right, F, WIN_W, WIN_H)
+    disp = sv.sv_cost_wta(cl, cr, D, WIN_W * WIN_H - 1)
+    ref = sv.Refiner(C1, C2, C3, LAT, F, "f32")
+    ref.pack(torch.from_numpy(flat).to(dev))
+    ref.workspace(1, H, W)
+    out = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    names = []
+    try:
+        for c in range(sv.sv_num_layer_cfgs()):
+            for layer in range(9):
+                sv.sv_set_layer_cfg(layer, c)
+            names.append(sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "f32", 1, H, W))
+            ref.forward(disp, low, H, W, out=out)
+            torch.cuda.synchronize()
+    finally:
+        for layer in range(9):
+            sv.sv_set_layer_cfg(layer, -1)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    with open(os.environ.get("SV_TRAFFIC_NAMES", "traffic_names.json"), "w") as f:
+        json.dump(names, f)
+    print("done", flush=True)
+
+
+def _dispatches(d: str):
+    """[(kernel name, counter value)] in dispatch order from a rocprofv3 counter collection."""
+    rows = []
+    for path in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    acc = {}
+    for r in rows:
+        k = int(r["Dispatch_Id"])
+        name, v = r["Kernel_Name"], float(r["Counter_Value"])
+        acc[k] = (name, acc.get(k, (name, 0.0))[1] + v)
+    return [acc[k] for k in sorted(acc)]
+
+
+def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) -> None:
+    fe, wr = _dispatches(fetch_dir), _dispatches(write_dir)
+    assert [n for n, _ in fe] == [n for n, _ in wr], "the two runs dispatched different kernels"
+    with open(names_json) as f:
+        cfg_names = json.load(f)
+    copy = [i for i, (n, _) in enumerate(fe) if "copyBuffer" in n or "elementwise" in n]
+    ci = copy[-1]
+    # counters are in KiB; the copy reads and writes COPY_BYTES
+    s_fetch = COPY_BYTES / (fe[ci][1] * 1024.0)
+    s_write = COPY_BYTES / (wr[ci][1] * 1024.0)
+    seq = [(n, fe[i][1] * 1024.0 * s_fetch, wr[i][1] * 1024.0 * s_write) for i, (n, _) in enumerate(fe)]
+    entries = {}
+    census = cost = None
+    forwards, cur = [], []
+    for n, fb, wb in seq:
+        if "k_reduce_census" in n:
+            census = {"fetch_bytes": fb, "write_bytes": wb}
+        elif "k_cost_wta" in n:
+            cost = {"fetch_bytes": fb, "write_bytes": wb}
+        elif "k_conv_split_reduce" in n:
+            cur[-1][1] += fb
+            cur[-1][2] += wb
+        elif "k_conv<" in n:
+            cur.append([n, fb, wb])
+        elif "k_final" in n:
+            forwards.append((cur, (fb, wb)))
+            cur = []
+    assert len(forwards) == len(cfg_names), (len(forwards), len(cfg_names))
+    final = None
+    for (convs, fin), cfgs in zip(forwards, cfg_names):
+        assert len(convs) == len(LAYERS)
+        for layer, (n, fb, wb), cfg in zip(LAYERS, convs, cfgs):
+            entries[f"f32|B1|{H}x{W}|{layer}|{cfg}"] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
+                                                        "kernel": n.split("(")[0]}
+        final = {"fetch_bytes": round(fin[0]), "write_bytes": round(fin[1])}
+    doc = {"source_hash": source_hash(), "counter_scale": {"FETCH_SIZE": s_fetch, "WRITE_SIZE": s_write},
+           "census": census, "cost_wta": cost, "final_gather": final, "layers": entries}
+    with open(out_json, "w") as f:
+        json.dump(doc, f, indent=1, sort_keys=True)
+    print(f"wrote {out_json}: {len(entries)} layer entries, scales {s_fetch:.3f} / {s_write:.3f}")
+
+
+if __name__ == "__main__":
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    if here not in sys.path:
+        sys.path.insert(0, here)
+    if sys.argv[1] == "run":
+        run()
+    elif sys.argv[1] == "summarize":
+        summarize(*sys.argv[2:6])
+    else:
+        raise SystemExit("usage: profile_traffic run | summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON")

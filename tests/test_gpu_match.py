@@ -73,6 +73,14 @@ def test_every_factor_ragged(f):
     _check(left, right, f, 7, 5, 12)
 
 
+def test_tall_census_tiles():
+    # enough tiles for the 16-row census tiles (two 1024x2048 views at f = 2)
+    rng = np.random.default_rng(11)
+    left = rng.integers(0, 256, (2, 1024, 2048), dtype=np.uint8)
+    right = np.roll(left, -6, axis=2) ^ rng.integers(0, 4, (2, 1024, 2048), dtype=np.uint8)
+    _check(left, right, 2, 9, 7, 24)
+
+
 def test_identical_images_zero():
     p = gen_pair(96, 200, 4, 2.0, 20.0, seed=3)
     _, _, _, d = _run_gpu(p.left[None], p.left[None], 2, 5, 5, 16)
