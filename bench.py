@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--dtype", choices=("f32", "bf16", "f16"), default="f32",
+                    help="network compute dtype of the headline step (the metric is quoted on f32)")
     ap.add_argument("--big-batch", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -399,8 +401,9 @@ def main():
              "f32": sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "f32", args.batch, H, W),
              "bf16": sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "bf16", args.batch, H, W)}
 
-    # ---- headline: FP32 network, graph replay -------------------------------------
-    p32 = Path(args.batch, "f32", flat, left, right)
+    # ---- headline: FP32 network (or --dtype), graph replay --------------------------------
+    hdt = args.dtype
+    p32 = Path(args.batch, hdt, flat, left, right)
     for _ in range(Wm):
         p32.step()
     torch.cuda.synchronize()
@@ -418,26 +421,26 @@ def main():
         if cnt == 0:
             continue
         avg_ms = tot / cnt
-        bound, amount, unit = stage_work(stage, args.batch, "f32")
+        bound, amount, unit = stage_work(stage, args.batch, hdt)
         rec = {"avg_us": round(avg_ms * 1e3, 3), "launches": cnt}
         if bound:
             rate = amount / (avg_ms * 1e-3)
             if bound == "hbm":
                 peak, runit, ach = PEAK["hbm_GBs"], "GB/s", rate
             elif bound == "mfma":
-                peak, runit, ach = PEAK["mfma_TFLOPs"]["f32"], "TFLOP/s", rate
+                peak, runit, ach = PEAK["mfma_TFLOPs"][hdt], "TFLOP/s", rate
             else:
                 peak, runit, ach = PEAK["alu_Tops"], "Tops/s", rate
             rec.update(bound=bound, achieved=round(ach, 3), unit=runit, frac=round(ach / peak, 5))
         kernels[stage] = rec
     dom = max(kernels, key=lambda s: kernels[s]["avg_us"])
     d = kernels[dom]
-    peak = {"GB/s": PEAK["hbm_GBs"], "TFLOP/s": PEAK["mfma_TFLOPs"]["f32"],
+    peak = {"GB/s": PEAK["hbm_GBs"], "TFLOP/s": PEAK["mfma_TFLOPs"][hdt],
             "Tops/s": PEAK["alu_Tops"]}.get(d.get("unit"), None)
     roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"), "peak": peak,
                 "unit": d.get("unit"), "frac": d.get("frac"), "traffic": None,
                 "avg_us": d["avg_us"]}
-    if args.batch == 1:
+    if args.batch == 1 and hdt == "f32":
         roofline.update(traffic_lookup(dom, tiles["f32"]))
 
     # ---- variants and EPE ---------------------------------------------------------------
@@ -515,10 +518,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": hdt,
         "data": "synthetic (seeded planar-cell scenes, KITTI-sized; random He-init weights)",
-        "config": {"workload": "1242x375 pair, batch 1: 9x7 census at 1/4 res (311x94), D=48 "
-                               "(192 full-res), WTA, VAE 2-32-64-128 latent 128 FP32, hipGraph replay",
+        "config": {"workload": f"1242x375 pair, batch {args.batch}: 9x7 census at 1/4 res (311x94), D=48 "
+                               f"(192 full-res), WTA, VAE 2-32-64-128 latent 128 {hdt.upper()}, hipGraph replay",
                    "batch": args.batch, "H": H, "W": W, "factor": F, "D_low": D},
         "eager_ms_per_step": round(eager_ms, 5),
         "roofline": roofline,
