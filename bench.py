@@ -201,7 +201,8 @@ def traffic_lookup(stage, f32_cfgs):
 def run_sgm(sv, torch, dev, flat, K, Wm):
     """Census + SGM (four axis paths) + single matching phase + median on the
     1242x375 pairs, graph replayed: frames/s of the matching stage at batch 1
-    and 64, of matching + FP32 network at batch 1, and the SGM call's HBM rate
+    and 64 (also with the ZNCC cost in place of the census cost), of matching
+    + FP32 network at batch 1, and the SGM call's HBM rate
     (algorithmic bytes: both census maps read once per path direction, the
     four uint8 path-cost volumes written and read back, the map written)."""
     P1, P2 = 10, 120
@@ -222,9 +223,17 @@ def run_sgm(sv, torch, dev, flat, K, Wm):
             ref.workspace(B, H, W)
             res = torch.empty((B, H, W), dtype=torch.float32, device=dev)
 
+        low_r = torch.empty_like(low)
+
         def match():
             sv.sv_census_pair(left, right, F, WIN_W, WIN_H, out=(cl, cr, low))
             sv.sv_sgm(cl, cr, D, NBITS, P1, P2, out=raw, workspace=wsg)
+            sv.sv_smp_median(raw, D, out=disp, workspace=wsm)
+
+        def match_zncc():  # ZNCC + SGM (the paper's main matcher) on the reduced images
+            sv.sv_census(left, F, WIN_W, WIN_H, out=(cl, low))
+            sv.sv_census(right, F, WIN_W, WIN_H, out=(cr, low_r))
+            sv.sv_zncc_sgm(low, low_r, D, WIN_W, WIN_H, P1, P2, out=raw, workspace=wsg)
             sv.sv_smp_median(raw, D, out=disp, workspace=wsm)
 
         def full():
@@ -247,7 +256,9 @@ def run_sgm(sv, torch, dev, flat, K, Wm):
             return (time.perf_counter() - t0) * 1e3 / K
 
         ms_m = graph_ms(match)
-        rec = {"match_ms": round(ms_m, 4), "match_frames_per_s": round(B * 1e3 / ms_m, 1)}
+        ms_z = graph_ms(match_zncc)
+        rec = {"match_ms": round(ms_m, 4), "match_frames_per_s": round(B * 1e3 / ms_m, 1),
+               "zncc_match_ms": round(ms_z, 4), "zncc_match_frames_per_s": round(B * 1e3 / ms_z, 1)}
         if ref is not None:
             ms_f = graph_ms(full)
             rec.update(with_network_f32_ms=round(ms_f, 4),

@@ -146,6 +146,35 @@ sv_status sv_sgm(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int
                  int nbits, int P1, int P2, uint8_t *disp_out, void *workspace, size_t ws_bytes,
                  void *stream);
 
+/*
+ * Zero-mean normalised cross-correlation + SGM (Eqs. (1)-(6)): the paper's
+ * main coarse matcher, on the reduced images.  With the window clamped to the
+ * image edge and n = win_w * win_h,
+ *   C(i, j, d) = 1 - N / sqrt(A B),  N = n SRT - SR ST,  A = n SRR - SR^2,
+ *                B = n STT - ST^2
+ * over the window sums of reference (R = low_l around (i, j)) and target
+ * (T = low_r around (i, j - d)) values, C = 1 for a flat window and C = 2 when
+ * j - d < 0; the integer cost q = floor(32 C + 1/2) (0..64, FP64) feeds the
+ * path aggregation of sv_sgm with penalties P1, P2 in the same units, and
+ * disp_out is the WTA of the aggregated cost.  Bit-exact.
+ *
+ * low_l, low_r (device) uint8 [B][h][w] reduced images (e.g. sv_census's low_out)
+ * D 1..256; windows 3x3, 5x5, 7x7, 9x7 (9 wide), 7x9, 9x9, 5x3, 3x5
+ * P1, P2       0 <= P1 <= P2 <= 190
+ * disp_out     (device) uint8 [B][h][w]
+ * workspace    >= sv_sgm_workspace_bytes(B, h, w, D)
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE, SV_ERR_UNSUPPORTED (window),
+ *         SV_ERR_WORKSPACE.
+ */
+sv_status sv_zncc_sgm(const uint8_t *low_l, const uint8_t *low_r, int B, int h, int w, int D,
+                      int win_w, int win_h, int P1, int P2, uint8_t *disp_out, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+/* The integer ZNCC cost q of sv_zncc_sgm alone, uint8 [B][h][w][D] (device,
+ * caller-owned cost_out).  Same arguments and errors. */
+sv_status sv_zncc_cost(const uint8_t *low_l, const uint8_t *low_r, int B, int h, int w, int D,
+                       int win_w, int win_h, uint8_t *cost_out, void *stream);
+
 /* Bytes of workspace sv_smp_median needs: B*h*w. */
 size_t sv_smp_workspace_bytes(int B, int h, int w);
 

@@ -133,6 +133,27 @@ def median3(disp: np.ndarray) -> np.ndarray:
     return out
 
 
+def zncc_cost(low_l: np.ndarray, low_r: np.ndarray, D: int, win_w: int, win_h: int) -> np.ndarray:
+    """Quantised ZNCC cost of Eqs. (1)-(3): floor(32 C + 1/2), int32 [B, h, w, D]."""
+    low_l = np.ascontiguousarray(low_l, dtype=np.uint8)
+    low_r = np.ascontiguousarray(low_r, dtype=np.uint8)
+    if low_l.ndim == 2:
+        low_l, low_r = low_l[None], low_r[None]
+    B, h, w = low_l.shape
+    out = np.empty((B, h, w, D), dtype=np.int32)
+    lib().or_zncc_cost(_p(low_l), _p(low_r), B, h, w, D, win_w, win_h, _p(out))
+    return out
+
+
+def match_zncc_sgm(left: np.ndarray, right: np.ndarray, f: int, win_w: int, win_h: int, D: int,
+                   P1: int, P2: int):
+    """ZNCC + SGM + WTA + SMP + median (the paper's main coarse pipeline):
+    (low-res left image, raw disparity, post-processed disparity)."""
+    lo_l, lo_r = downsample(left, f), downsample(right, f)
+    raw = wta(sgm(zncc_cost(lo_l, lo_r, D, win_w, win_h), P1, P2))
+    return lo_l, raw, median3(smp(raw, D))
+
+
 def match_sgm(left: np.ndarray, right: np.ndarray, f: int, win_w: int, win_h: int, D: int,
               P1: int, P2: int):
     """Census + SGM + WTA + SMP + median: (low-res left image, raw SGM disparity,

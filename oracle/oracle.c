@@ -216,6 +216,49 @@ void or_smp(const uint8_t *disp, int B, int h, int w, int D, uint8_t *out)
         }
 }
 
+/* Zero-mean normalised cross-correlation cost, Eqs. (1)-(3), on the reduced
+ * images, window win_w x win_h centred on each pixel, window pixels clamped to
+ * the image edge, target pixel (x - d, y):
+ *   C = 1 - sum dR dT / (sigma_R sigma_T),  dR = I_R - mean_W(I_R), ...
+ * With n window pixels and exact integer sums SR, SRR, ST, STT, SRT,
+ *   sum dR dT = (n SRT - SR ST) / n,  sigma_R^2 = (n SRR - SR^2) / n, ...
+ * so C = 1 - N / sqrt(A B) with N = n SRT - SR ST, A = n SRR - SR^2,
+ * B = n STT - ST^2 (exact integers, then FP64).  A flat window (A or B zero)
+ * carries no correlation: C = 1.  A target column outside the image: C = 2.
+ * The cost kept for the path aggregation is q = floor(32 C + 1/2) in 0..64
+ * (FP64), out[b][i][j][d]. */
+void or_zncc_cost(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int win_w,
+                  int win_h, int32_t *out)
+{
+    const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+    const long long n = (long long)win_w * win_h;
+    for (int b = 0; b < B; ++b)
+        for (int i = 0; i < h; ++i)
+            for (int j = 0; j < w; ++j)
+                for (int d = 0; d < D; ++d) {
+                    double C;
+                    if (j - d < 0) {
+                        C = 2.0;
+                    } else {
+                        long long SR = 0, SRR = 0, ST = 0, STT = 0, SRT = 0;
+                        for (int dy = -ry; dy <= ry; ++dy)
+                            for (int dx = -rx; dx <= rx; ++dx) {
+                                const int y = clampi(i + dy, 0, h - 1);
+                                const long long r = ll[((size_t)b * h + y) * w + clampi(j + dx, 0, w - 1)];
+                                const long long t = lr[((size_t)b * h + y) * w + clampi(j - d + dx, 0, w - 1)];
+                                SR += r; SRR += r * r; ST += t; STT += t * t; SRT += r * t;
+                            }
+                        const long long N = n * SRT - SR * ST;
+                        const long long A = n * SRR - SR * SR, Bv = n * STT - ST * ST;
+                        if (A == 0 || Bv == 0)
+                            C = 1.0;
+                        else
+                            C = 1.0 - (double)N / sqrt((double)A * (double)Bv);
+                    }
+                    out[(((size_t)b * h + i) * w + j) * D + d] = (int32_t)floor(32.0 * C + 0.5);
+                }
+}
+
 /* 3 x 3 median filter of a uint8 map, borders replicated. */
 void or_median3(const uint8_t *in, int B, int h, int w, uint8_t *out)
 {

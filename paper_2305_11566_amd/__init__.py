@@ -11,6 +11,8 @@ from .ops import (  # noqa: F401
     sv_cost_wta,
     sv_sgm,
     sv_smp_median,
+    sv_zncc_sgm,
+    sv_zncc_cost,
     sv_set_cost_wta_split,
     sv_set_layer_cfg,
     sv_num_layer_cfgs,

@@ -58,6 +58,8 @@ _SIGS = {
     "sv_sgm_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I, _I]),
     "sv_sgm": (ctypes.c_int32, [_P, _P, _I, _I, _I, _I, _I, _I, _I, _P, _P, ctypes.c_size_t, _P]),
     "sv_smp_workspace_bytes": (ctypes.c_size_t, [_I, _I, _I]),
+    "sv_zncc_sgm": (ctypes.c_int32, [_P, _P, _I, _I, _I, _I, _I, _I, _I, _I, _P, _P, ctypes.c_size_t, _P]),
+    "sv_zncc_cost": (ctypes.c_int32, [_P, _P, _I, _I, _I, _I, _I, _I, _P, _P]),
     "sv_smp_median": (ctypes.c_int32, [_P, _I, _I, _I, _I, _P, _P, ctypes.c_size_t, _P]),
     "sv_vae_param_count": (_I64, [_DESC]),
     "sv_vae_packed_bytes": (_SZ, [_DESC]),

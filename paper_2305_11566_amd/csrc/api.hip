@@ -119,6 +119,35 @@ sv_status sv_sgm(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int
                       (hipStream_t)stream);
 }
 
+static sv_status check_zncc(const uint8_t *ll, const uint8_t *lr, const void *out, int B, int h,
+                            int w, int D, int win_w, int win_h) {
+    if (!ll || !lr || !out) return SV_ERR_NULL;
+    if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > kMaxSide) return SV_ERR_SHAPE;
+    if (D < 1 || D > 256) return SV_ERR_RANGE;
+    if (win_w < 1 || win_h < 1 || win_w % 2 == 0 || win_h % 2 == 0 || win_w > 17 || win_h > 17)
+        return SV_ERR_RANGE;
+    return SV_OK;
+}
+
+sv_status sv_zncc_sgm(const uint8_t *low_l, const uint8_t *low_r, int B, int h, int w, int D,
+                      int win_w, int win_h, int P1, int P2, uint8_t *disp_out, void *workspace,
+                      size_t ws_bytes, void *stream) {
+    sv_status r = check_zncc(low_l, low_r, disp_out, B, h, w, D, win_w, win_h);
+    if (r != SV_OK) return r;
+    if (!workspace) return SV_ERR_NULL;
+    if (P1 < 0 || P2 < P1 || 64 + P2 > 255) return SV_ERR_RANGE;
+    if (ws_bytes < sv_sgm_workspace_bytes(B, h, w, D)) return SV_ERR_WORKSPACE;
+    return launch_zncc_sgm(low_l, low_r, B, h, w, D, win_w, win_h, P1, P2, (uint8_t *)workspace,
+                           disp_out, (hipStream_t)stream);
+}
+
+sv_status sv_zncc_cost(const uint8_t *low_l, const uint8_t *low_r, int B, int h, int w, int D,
+                       int win_w, int win_h, uint8_t *cost_out, void *stream) {
+    sv_status r = check_zncc(low_l, low_r, cost_out, B, h, w, D, win_w, win_h);
+    if (r != SV_OK) return r;
+    return launch_zncc_cost(low_l, low_r, B, h, w, D, D, win_w, win_h, cost_out, (hipStream_t)stream);
+}
+
 size_t sv_smp_workspace_bytes(int B, int h, int w) {
     if (B <= 0 || h <= 0 || w <= 0) return 0;
     return (size_t)B * h * w;

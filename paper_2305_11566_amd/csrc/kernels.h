@@ -54,6 +54,10 @@ sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w
                      int P1, int P2, uint8_t *vol, uint8_t *disp, hipStream_t s);
 sv_status launch_smp_median(const uint8_t *disp, int B, int h, int w, int D, uint8_t *tmp,
                             uint8_t *out, hipStream_t s);
+sv_status launch_zncc_cost(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int Dp,
+                           int win_w, int win_h, uint8_t *cost, hipStream_t s);
+sv_status launch_zncc_sgm(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int win_w,
+                          int win_h, int P1, int P2, uint8_t *ws, uint8_t *disp, hipStream_t s);
 sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl, const uint64_t *cr,
                               int nbits, uint8_t *disp, int dsplit, hipStream_t s);
 int cost_wta_tile_width(int dsplit);

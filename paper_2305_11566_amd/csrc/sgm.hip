@@ -343,15 +343,15 @@ size_t sgm_volume_bytes(int B, int h, int w, int D) {
     return (size_t)5 * B * h * w * sgm_dpad(D) + SGM_SINK;
 }
 
-sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
-                     int P1, int P2, uint8_t *ws, uint8_t *disp, hipStream_t s)
+// Path sweeps + aggregation / WTA on a uint8 cost volume already in the
+// workspace (ws: cost, four path volumes, sink).
+static sv_status sgm_from_cost(int B, int h, int w, int D, int P1, int P2, uint8_t *ws, uint8_t *disp,
+                               hipStream_t s)
 {
     const int Dp = sgm_dpad(D);
     const size_t nvox = (size_t)B * h * w * Dp;
-    uint8_t *cost = ws, *vol = ws + nvox, *sink = ws + 5 * nvox;
-    hipLaunchKernelGGL(k_sgm_cost, dim3(cdiv(w, CV_TW), h, B), dim3(256), 0, s, cl, cr, h, w, D, Dp,
-                       nbits, cost);
-    SV_LAUNCH_CHECK("k_sgm_cost");
+    const uint8_t *cost = ws;
+    uint8_t *vol = ws + nvox, *sink = ws + 5 * nvox;
     const int npath = 2 * B * h + 2 * B * w;
     const dim3 grid(cdiv(npath, 4));
     const int dpl = cdiv(D, SGM_LANES);
@@ -369,6 +369,126 @@ sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w
     hipLaunchKernelGGL(k_sgm_wta, dim3(blocks), dim3(256), 0, s, vol, nvox, D, Dp, npix, disp);
     SV_LAUNCH_CHECK("k_sgm_wta");
     return SV_OK;
+}
+
+sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
+                     int P1, int P2, uint8_t *ws, uint8_t *disp, hipStream_t s)
+{
+    const int Dp = sgm_dpad(D);
+    hipLaunchKernelGGL(k_sgm_cost, dim3(cdiv(w, CV_TW), h, B), dim3(256), 0, s, cl, cr, h, w, D, Dp,
+                       nbits, ws);
+    SV_LAUNCH_CHECK("k_sgm_cost");
+    return sgm_from_cost(B, h, w, D, P1, P2, ws, disp, s);
+}
+
+// ---------------------------------------------------------------------------
+// Zero-mean normalised cross-correlation cost, Eqs. (1)-(3), on the reduced
+// images.  With n window pixels (clamped to the image edge) and the exact
+// integer window sums SR, SRR, ST, STT, SRT of the reference and target
+// values,
+//   C = 1 - N / sqrt(A B),  N = n SRT - SR ST,  A = n SRR - SR^2,  B = n STT - ST^2,
+// evaluated in FP64 (C = 1 for a flat window, 2 where x - d < 0), and kept as
+// q = floor(32 C + 1/2) in 0..64 for the path aggregation.  One workgroup =
+// ZN_TW x ZN_TH pixels; the reference tile and the target tile (widened by
+// D - 1 columns) with their window halos are staged in LDS; a thread holds its
+// reference window in registers and runs over the disparities.
+// ---------------------------------------------------------------------------
+constexpr int ZN_TW = 64, ZN_TH = 4;
+
+template <int RX, int RY>
+__global__ void __launch_bounds__(ZN_TW * ZN_TH)
+k_zncc_cost(const uint8_t *__restrict__ ll, const uint8_t *__restrict__ lr, int h, int w, int D,
+            int Dp, uint8_t *__restrict__ cost)
+{
+    constexpr int PH = ZN_TH + 2 * RY, PWL = ZN_TW + 2 * RX;
+    constexpr int NW = (2 * RX + 1) * (2 * RY + 1);
+    __shared__ uint8_t pr[PH][PWL];
+    __shared__ uint8_t pt[PH][ZN_TW + 2 * RX + 255];
+    const int b = blockIdx.z;
+    const int i0 = blockIdx.y * ZN_TH, j0 = blockIdx.x * ZN_TW;
+    const uint8_t *L = ll + (size_t)b * h * w, *R = lr + (size_t)b * h * w;
+    const int PWT = ZN_TW + 2 * RX + D - 1;  // target columns j0 - RX - (D - 1) ...
+    for (int e = threadIdx.x; e < PH * PWL; e += blockDim.x) {
+        const int py = e / PWL, px = e - py * PWL;
+        const int y = min(max(i0 + py - RY, 0), h - 1), x = min(max(j0 + px - RX, 0), w - 1);
+        pr[py][px] = L[(size_t)y * w + x];
+    }
+    for (int e = threadIdx.x; e < PH * PWT; e += blockDim.x) {
+        const int py = e / PWT, px = e - py * PWT;
+        const int y = min(max(i0 + py - RY, 0), h - 1);
+        const int x = min(max(j0 - RX - (D - 1) + px, 0), w - 1);
+        pt[py][px] = R[(size_t)y * w + x];
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / ZN_TW, tx = threadIdx.x - ty * ZN_TW;
+    const int i = i0 + ty, j = j0 + tx;
+    if (i >= h || j >= w) return;
+    int rv[NW];
+    int SR = 0, SRR = 0;
+#pragma unroll
+    for (int dy = 0; dy <= 2 * RY; ++dy)
+#pragma unroll
+        for (int dx = 0; dx <= 2 * RX; ++dx) {
+            const int r = pr[ty + dy][tx + dx];
+            rv[dy * (2 * RX + 1) + dx] = r;
+            SR += r;
+            SRR += r * r;
+        }
+    const long long n = NW;
+    const long long A = n * SRR - (long long)SR * SR;
+    uint8_t *o = cost + (((size_t)b * h + i) * w + j) * Dp;
+    for (int d = 0; d < Dp; ++d) {
+        int q = 0;
+        if (d < D) {
+            if (j - d < 0) {
+                q = 64;
+            } else {
+                // target window of column j - d: pt column tx + dx + (D - 1) - d
+                int ST = 0, STT = 0, SRT = 0;
+#pragma unroll
+                for (int dy = 0; dy <= 2 * RY; ++dy)
+#pragma unroll
+                    for (int dx = 0; dx <= 2 * RX; ++dx) {
+                        const int t = pt[ty + dy][tx + dx + (D - 1) - d];
+                        ST += t;
+                        STT += t * t;
+                        SRT += rv[dy * (2 * RX + 1) + dx] * t;
+                    }
+                const long long N = n * SRT - (long long)SR * ST;
+                const long long Bv = n * STT - (long long)ST * ST;
+                double C;
+                if (A == 0 || Bv == 0) C = 1.0;
+                else C = 1.0 - (double)N / sqrt((double)A * (double)Bv);
+                q = (int)floor(32.0 * C + 0.5);
+            }
+        }
+        o[d] = (uint8_t)q;
+    }
+}
+
+sv_status launch_zncc_cost(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int Dp,
+                           int win_w, int win_h, uint8_t *cost, hipStream_t s)
+{
+    const dim3 grid(cdiv(w, ZN_TW), cdiv(h, ZN_TH), B);
+    const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+#define SV_ZN(X, Y)                                                                                \
+    if (rx == X && ry == Y) {                                                                      \
+        hipLaunchKernelGGL((k_zncc_cost<X, Y>), grid, dim3(ZN_TW * ZN_TH), 0, s, ll, lr, h, w, D, Dp, \
+                           cost);                                                                  \
+        SV_LAUNCH_CHECK("k_zncc_cost");                                                            \
+        return SV_OK;                                                                              \
+    }
+    SV_ZN(1, 1) SV_ZN(2, 2) SV_ZN(3, 3) SV_ZN(4, 3) SV_ZN(3, 4) SV_ZN(4, 4) SV_ZN(2, 1) SV_ZN(1, 2)
+#undef SV_ZN
+    return SV_ERR_UNSUPPORTED;
+}
+
+sv_status launch_zncc_sgm(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int win_w,
+                          int win_h, int P1, int P2, uint8_t *ws, uint8_t *disp, hipStream_t s)
+{
+    sv_status r = launch_zncc_cost(ll, lr, B, h, w, D, sgm_dpad(D), win_w, win_h, ws, s);
+    if (r != SV_OK) return r;
+    return sgm_from_cost(B, h, w, D, P1, P2, ws, disp, s);
 }
 
 sv_status launch_smp_median(const uint8_t *disp, int B, int h, int w, int D, uint8_t *tmp,

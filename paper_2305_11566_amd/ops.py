@@ -27,15 +27,20 @@ def _need(t, dtype, name):
 
 # ---------------------------------------------------------------- matching
 
-def sv_census(img: torch.Tensor, factor: int, win_w: int, win_h: int, want_low: bool = True):
-    """uint8 [B, H, W] -> (census int64-bits [B, h, w], reduced image uint8 [B, h, w] or None)."""
+def sv_census(img: torch.Tensor, factor: int, win_w: int, win_h: int, want_low: bool = True,
+              out: tuple | None = None):
+    """uint8 [B, H, W] -> (census int64-bits [B, h, w], reduced image uint8 [B, h, w] or None);
+    `out` = (census, reduced image) preallocated."""
     _need(img, torch.uint8, "img")
     if img.dim() == 2:
         img = img[None]
     B, H, W = img.shape
     h, w = _cdiv(H, factor), _cdiv(W, factor)
-    cen = torch.empty((B, h, w), dtype=torch.int64, device=img.device)
-    low = torch.empty((B, h, w), dtype=torch.uint8, device=img.device) if want_low else None
+    if out is not None:
+        cen, low = out
+    else:
+        cen = torch.empty((B, h, w), dtype=torch.int64, device=img.device)
+        low = torch.empty((B, h, w), dtype=torch.uint8, device=img.device) if want_low else None
     check(lib().sv_census(ptr(img), B, H, W, W, factor, win_w, win_h, ptr(low), ptr(cen),
                           stream_ptr()), "sv_census")
     return cen, low
@@ -96,6 +101,35 @@ def sv_sgm(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int, P1: int
         out = torch.empty((B, h, w), dtype=torch.uint8, device=cen_l.device)
     check(lib().sv_sgm(ptr(cen_l), ptr(cen_r), B, h, w, D, nbits, P1, P2, ptr(out), ptr(workspace),
                        workspace.numel(), stream_ptr()), "sv_sgm")
+    return out
+
+
+def sv_zncc_sgm(low_l: torch.Tensor, low_r: torch.Tensor, D: int, win_w: int, win_h: int, P1: int,
+                P2: int, out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Reduced images uint8 [B, h, w] -> ZNCC + SGM disparity uint8 [B, h, w]."""
+    _need(low_l, torch.uint8, "low_l")
+    _need(low_r, torch.uint8, "low_r")
+    if low_l.shape != low_r.shape:
+        raise ValueError("images differ in shape")
+    B, h, w = low_l.shape
+    if workspace is None:
+        workspace = torch.empty(max(lib().sv_sgm_workspace_bytes(B, h, w, D), 1), dtype=torch.uint8,
+                                device=low_l.device)
+    if out is None:
+        out = torch.empty((B, h, w), dtype=torch.uint8, device=low_l.device)
+    check(lib().sv_zncc_sgm(ptr(low_l), ptr(low_r), B, h, w, D, win_w, win_h, P1, P2, ptr(out),
+                            ptr(workspace), workspace.numel(), stream_ptr()), "sv_zncc_sgm")
+    return out
+
+
+def sv_zncc_cost(low_l: torch.Tensor, low_r: torch.Tensor, D: int, win_w: int, win_h: int):
+    """Reduced images uint8 [B, h, w] -> integer ZNCC cost uint8 [B, h, w, D]."""
+    _need(low_l, torch.uint8, "low_l")
+    _need(low_r, torch.uint8, "low_r")
+    B, h, w = low_l.shape
+    out = torch.empty((B, h, w, D), dtype=torch.uint8, device=low_l.device)
+    check(lib().sv_zncc_cost(ptr(low_l), ptr(low_r), B, h, w, D, win_w, win_h, ptr(out), stream_ptr()),
+          "sv_zncc_cost")
     return out
 
 

@@ -76,6 +76,17 @@ def test_smp_median_validation(args, code):
     assert lib().sv_smp_median(*args) == code
 
 
+@pytest.mark.parametrize("args,code", [
+    ((None, P, 1, 4, 4, 8, 5, 5, 10, 120, P, P, 10 ** 6, None), -1),
+    ((P, P, 1, 0, 4, 8, 5, 5, 10, 120, P, P, 10 ** 6, None), -2),
+    ((P, P, 1, 4, 4, 8, 4, 5, 10, 120, P, P, 10 ** 6, None), -3),     # even window
+    ((P, P, 1, 4, 4, 8, 5, 5, 10, 192, P, P, 10 ** 6, None), -3),     # 64 + P2 > 255
+    ((P, P, 1, 4, 4, 8, 5, 5, 10, 120, P, P, 10, None), -5),
+])
+def test_zncc_sgm_validation(args, code):
+    assert lib().sv_zncc_sgm(*args) == code
+
+
 def test_vae_validation():
     l = lib()
     d = make_desc(16, 32, 64, 64, 2, "f32")

@@ -156,3 +156,66 @@ def test_sgm_lowers_the_error_on_the_workload_pair():
     e_sgm = np.mean(np.abs(raw[0] - gt))
     e_post = np.mean(np.abs(post[0] - gt))
     assert e_sgm < e_wta and e_post < e_sgm
+
+
+# ---------------------------------------------------------------- ZNCC cost
+
+def _zncc_direct(R, T, i, j, d, rx, ry):
+    """Eqs. (1)-(3) written with the window means and deviations, float64."""
+    h, w = R.shape
+    ys = np.clip(np.arange(i - ry, i + ry + 1), 0, h - 1)
+    xr = np.clip(np.arange(j - rx, j + rx + 1), 0, w - 1)
+    xt = np.clip(np.arange(j - d - rx, j - d + rx + 1), 0, w - 1)
+    r = R[np.ix_(ys, xr)].astype(np.float64)
+    t = T[np.ix_(ys, xt)].astype(np.float64)
+    dr, dt = r - r.mean(), t - t.mean()
+    sr, st = np.sqrt((dr ** 2).sum()), np.sqrt((dt ** 2).sum())
+    if sr == 0 or st == 0:
+        return 1.0
+    return 1.0 - (dr * dt).sum() / (sr * st)
+
+
+def test_zncc_matches_its_definition():
+    rng = np.random.default_rng(9)
+    R = rng.integers(0, 256, (9, 14), dtype=np.uint8)
+    T = rng.integers(0, 256, (9, 14), dtype=np.uint8)
+    T[2:5, 3:8] = 17          # a flat patch: windows inside it have no deviation
+    D, ww, wh = 6, 5, 3
+    q = oracle.zncc_cost(R, T, D, ww, wh)[0]
+    for i in range(9):
+        for j in range(14):
+            for d in range(D):
+                if j - d < 0:
+                    assert q[i, j, d] == 64
+                    continue
+                C = _zncc_direct(R, T, i, j, d, 2, 1)
+                x = 32.0 * C + 0.5
+                # the two float evaluations may differ only at a rounding tie
+                assert q[i, j, d] == np.floor(x) or abs(x - np.round(x)) < 1e-9, (i, j, d, C)
+
+
+def test_zncc_invariances():
+    rng = np.random.default_rng(10)
+    R = rng.integers(0, 120, (1, 12, 30), dtype=np.uint8)
+    s = 3
+    Ts = np.zeros_like(R)
+    Ts[:, :, :-s] = R[:, :, s:]                       # the right view is R shifted by s
+    T_aff = (2 * Ts.astype(np.int32) + 3).astype(np.uint8)   # and an affine intensity change
+    T_neg = (255 - Ts.astype(np.int32)).astype(np.uint8)     # and an inverted one
+    for T, expect in ((Ts, 0), (T_aff, 0), (T_neg, 64)):
+        q = oracle.zncc_cost(R, T, 8, 5, 5)[0]
+        # windows whose clamped targets equal the shifted reference: columns s+2 .. w-3-? inside
+        assert (q[:, s + 2:-3, s] == expect).all()
+    flat = np.full((1, 6, 10), 9, np.uint8)
+    assert (oracle.zncc_cost(flat, R[:, :6, :10], 3, 3, 3)[0][:, 2:, :] == 32).all()
+
+
+def test_zncc_sgm_recovers_shift():
+    rng = np.random.default_rng(12)
+    left = rng.integers(0, 256, (1, 40, 64), dtype=np.uint8)
+    s = 4
+    right = np.zeros_like(left)
+    right[:, :, :-s] = left[:, :, s:]
+    lo_l, lo_r = oracle.downsample(left, 1), oracle.downsample(right, 1)
+    d = oracle.wta(oracle.sgm(oracle.zncc_cost(lo_l, lo_r, 10, 5, 5), 10, 120))
+    assert (d[0, 3:-3, s + 3:-3] == s).all()
