@@ -564,7 +564,19 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
     __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const int ntn = (p.Cout + TN - 1) / TN;
     const int ksplit = p.ksplit > 1 ? p.ksplit : 1;
-    const int kz = blockIdx.z % ksplit, zz = blockIdx.z / ksplit;
+    // XCD-aware order: workgroups go round robin to the eight XCDs (each with
+    // its own L2), so hardware id i is given logical tile (i % 8) * q + i / 8,
+    // q = N / 8 (a transpose; the last N % 8 ids keep their own): each XCD then
+    // works on one contiguous run of the (image, channel tile, split, row,
+    // column) order and fetches only the weights and inputs of that run
+    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+    const int nblk = gx * gy * (int)gridDim.z;
+    const int hw = (int)blockIdx.x + gx * ((int)blockIdx.y + gy * (int)blockIdx.z);
+    const int q8 = nblk / 8;
+    const int lid = hw < 8 * q8 ? (hw % 8) * q8 + hw / 8 : hw;
+    const int bz = lid / (gx * gy), rem = lid - bz * (gx * gy);
+    const int by = rem / gx, bx = rem - by * gx;
+    const int kz = bz % ksplit, zz = bz / ksplit;
     const int b = zz / ntn;
     ConvGeo G;
     G.Hi = p.Hi; G.Wi = p.Wi; G.Ho = p.Ho; G.Wo = p.Wo;
@@ -575,8 +587,8 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
     }
     G.obase = (long long)b * p.Ho * p.Wo;
     G.n0 = (zz % ntn) * TN;
-    G.oy0 = blockIdx.y * TH;
-    G.ox0 = blockIdx.x * CT::TW;
+    G.oy0 = by * TH;
+    G.ox0 = bx * CT::TW;
     CT::run(p, G, sm, kz);
 }
 
