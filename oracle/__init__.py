@@ -202,6 +202,22 @@ def conv2d_dw(x, dy, k, stride, pad):
     return dw, db
 
 
+def tconv2d(x, wt, bias, stride, pad, Ho, Wo):
+    """Transposed convolution, weights [O][C][k][k]; output Ho x Wo (see or_tconv2d)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    wt = np.ascontiguousarray(wt, dtype=np.float64)
+    B, C, H, W = x.shape
+    O, C2, k, k2 = wt.shape
+    assert C2 == C and k == k2
+    y = np.empty((B, O, Ho, Wo), dtype=np.float64)
+    bp = None
+    if bias is not None:
+        bias = np.ascontiguousarray(bias, dtype=np.float64)
+        bp = _p(bias)
+    lib().or_tconv2d(_p(x), B, C, H, W, _p(wt), bp, O, k, stride, pad, Ho, Wo, _p(y))
+    return y
+
+
 def resize(x, Ho, Wo):
     x = np.ascontiguousarray(x, dtype=np.float64)
     lead = x.shape[:-2]

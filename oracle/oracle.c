@@ -360,6 +360,38 @@ void or_conv2d_dw(const double *x, const double *dy, int B, int C, int H, int W,
                 }
 }
 
+/* Transposed 2-D convolution (the upsampling "deconvolution" layers of the
+ * decoder and the final upsampling layer, Table I): every input sample
+ * x[b,c,i,j] spreads over the output through the kernel placed at
+ * (s*i - pad, s*j - pad):
+ *   y[b,o,Y,X] = bias[o] + sum of wt[o,c,u,v] * x[b,c,i,j]
+ *                over (c, i, j, u, v) with s*i + u - pad = Y, s*j + v - pad = X,
+ * for 0 <= Y < Ho, 0 <= X < Wo; terms that land outside are dropped.  Weights
+ * are [O][C][k][k] (output channel first).  y is overwritten. */
+void or_tconv2d(const double *x, int B, int C, int H, int W, const double *wt, const double *bias,
+                int O, int k, int s, int pad, int Ho, int Wo, double *y)
+{
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < O; ++o)
+            for (size_t e = 0; e < (size_t)Ho * Wo; ++e)
+                y[((size_t)b * O + o) * Ho * Wo + e] = bias ? bias[o] : 0.0;
+    for (int b = 0; b < B; ++b)
+        for (int o = 0; o < O; ++o)
+            for (int c = 0; c < C; ++c)
+                for (int i = 0; i < H; ++i)
+                    for (int j = 0; j < W; ++j) {
+                        double xv = x[(((size_t)b * C + c) * H + i) * W + j];
+                        for (int u = 0; u < k; ++u)
+                            for (int v = 0; v < k; ++v) {
+                                int Y = s * i + u - pad, X = s * j + v - pad;
+                                if (Y < 0 || Y >= Ho || X < 0 || X >= Wo)
+                                    continue;
+                                y[(((size_t)b * O + o) * Ho + Y) * Wo + X] +=
+                                    wt[(((size_t)o * C + c) * k + u) * k + v] * xv;
+                            }
+                    }
+}
+
 /* Source index pair and weight of bilinear resampling along one axis
  * (half-pixel centres, no corner alignment): s = (o + 1/2) * n_in / n_out - 1/2,
  * clamped below at 0; i0 = floor(s), i1 = min(i0 + 1, n_in - 1), lambda = s - i0. */
