@@ -387,6 +387,92 @@ const char *sv_conv_cfg_name(int cfg);
  * stage 0 = census, 1 = cost+WTA, 2..12 = network layers; writes a short text. */
 sv_status sv_tile_config(int stage, char *buf, int buflen);
 
+/* ---- The Table I network as printed (Sec. III-B1) ------------------------------
+ *
+ * The refinement network in the exact shape of Table I, separate from the
+ * configurable network above: feature extraction FE_1 = conv5x5(X_0) and
+ * FE_2 = conv5x5(X_1) (32 channels each) on the coarse grid h1 x w1 =
+ * ceil(H/f) x ceil(W/f); encoder EN_1 (16, 5x5 stride 2), EN_1_R (8, residual
+ * block), EN_2 (32, 5x5 stride 2), EN_2_R (16); a 1x1 head giving one mu and
+ * one sigma channel at h3 x w3 (h1 halved twice, rounding up); Eq. (8)
+ * z = (mu - 1) + eps * exp(sigma - 1) (eps NULL: z = mu - 1); decoder D_1
+ * (32, 1x1 deconvolution), D_1_R (16), D_2 (16, 5x5 stride-2 deconvolution),
+ * D_2_R (8), D (16, 5x5 stride-2 deconvolution); and the upsampling layer Y,
+ * a 5x5 deconvolution of stride f to one channel at H x W.  Inputs are the
+ * "&" concatenations in the table's order; X_0 = f * d / 256 (coarse
+ * disparity d), X_1 = I / 256 (reduced left image).  Leaky ReLU (slope 0.1)
+ * follows every layer except the head and Y.  A deconvolution has padding 2
+ * and its output is cut to the size of the level it feeds (H x W for Y).
+ * Output: 256 * Y, disparity in full-resolution px.
+ *
+ * Parameters: one FP32 vector of sv_tvae_param_count() values, layer by layer
+ * in the order FE_1, FE_2, EN_1, EN_1_R, EN_2, EN_2_R, mu&sigma, D_1, D_1_R,
+ * D_2, D_2_R, D, Y; each layer's weights [out][in][k][k] (deconvolutions
+ * too: y[o][s*i + u - 2][s*j + v - 2] += w[o][c][u][v] * x[c][i][j]), then
+ * its bias [out].
+ */
+int64_t sv_tvae_param_count(void);
+
+/* Bytes of the packed weight image for `dtype` (SV_F32, SV_BF16, SV_F16); 0 if
+ * the dtype is invalid. */
+size_t sv_tvae_packed_bytes(int dtype);
+
+/*
+ * Pack the canonical parameters (device FP32, sv_tvae_param_count() values)
+ * into packed_out (device, 256-byte aligned, sv_tvae_packed_bytes(dtype)
+ * bytes) in the kernels' layout and precision (the upsampling layer's weights
+ * stay FP32 in every dtype).
+ * Errors: SV_ERR_NULL, SV_ERR_DTYPE, SV_ERR_RANGE (misaligned packed_out).
+ */
+sv_status sv_tvae_pack_weights(int dtype, const float *params, void *packed_out, void *stream);
+
+/* Workspace bytes sv_tvae_forward needs for B pairs of full resolution H x W
+ * reduced by `factor`; 0 on invalid input. */
+size_t sv_tvae_workspace_bytes(int dtype, int factor, int B, int H, int W);
+
+/*
+ * Forward pass of the Table I network on B pairs.
+ *   disp_low, img_low (device) uint8 [B][h1][w1]: coarse disparity (reduced px)
+ *                     and reduced left image, h1 = ceil(H/factor), w1 = ceil(W/factor)
+ *   eps       (device, nullable) FP32 [B][h3][w3]: the noise of Eq. (8); NULL = inference
+ *   out       (device) FP32 [B][H][W]: disparity in full-resolution px
+ *   mu_sigma  (device, nullable) FP32 [B][h3][w3][2]: the head's mu and sigma
+ *   workspace (device, 256-byte aligned) >= sv_tvae_workspace_bytes(...)
+ * factor in [1, 8]; B * H * W < 2^31; B <= 16383.
+ * Errors: SV_ERR_NULL, SV_ERR_DTYPE, SV_ERR_RANGE, SV_ERR_SHAPE, SV_ERR_WORKSPACE.
+ */
+sv_status sv_tvae_forward(int dtype, int factor, const void *packed_w, const uint8_t *disp_low,
+                          const uint8_t *img_low, int B, int H, int W, const float *eps, float *out,
+                          float *mu_sigma, void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * The loss of Eqs. (9)-(11) with its gradient.  With N = the number of pixels
+ * where occ is set, Loss_1 = (sum over noc of |out - gt| + sum over occ of
+ * |out - gt|) / N in px (non-occluded points weigh twice), Loss_2 = 256 *
+ * mean over latent positions of 0.5 * ((mu - 1)^2 - 1 + exp(2 (sigma - 1)) -
+ * 2 (sigma - 1)), total = Loss_1 + Loss_2 (both already carry the factor 256
+ * of Eq. (9): out and gt are in px).
+ *   out, gt (device) FP32 [n]; noc, occ (device) uint8 [n] masks (nonzero = set)
+ *   mu_sigma (device) FP32 [n_lat][2]
+ *   loss_out (device) FP32 [3] = {total, Loss_1, Loss_2}
+ *   dout (device, nullable) FP32 [n]: d total / d out (0 where out == gt)
+ *   dmu_sigma (device, nullable) FP32 [n_lat][2]: d total / d (mu, sigma)
+ *   workspace (device, 8-byte aligned) >= sv_tvae_loss_workspace_bytes()
+ * Sums run in FP64 in a fixed order.
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_WORKSPACE, SV_ERR_RANGE.
+ */
+size_t sv_tvae_loss_workspace_bytes(void);
+sv_status sv_tvae_loss(const float *out, const float *gt, const uint8_t *noc, const uint8_t *occ,
+                       int64_t n, const float *mu_sigma, int64_t n_lat, float *loss_out, float *dout,
+                       float *dmu_sigma, void *workspace, size_t ws_bytes, void *stream);
+
+/* Tile configuration of launched layer `layer` (0 .. sv_tvae_num_layers()-1:
+ * FE, EN_1, EN_1_R, EN_2, EN_2_R, mu&sigma, D_1, D_1_R, D_2, D_2_R, D, Y's tap
+ * projection) of sv_tvae_forward, as sv_set_layer_cfg; -1 restores the
+ * default.  Results do not depend on the tile shape.  Errors: SV_ERR_RANGE. */
+sv_status sv_tvae_set_layer_cfg(int layer, int cfg);
+int sv_tvae_num_layers(void);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,4 +28,9 @@ from .ops import (  # noqa: F401
     sv_layer_cfgs,
     sv_loss,
     sv_adam_step,
+    TableVAE,
+    tvae_param_count,
+    sv_tvae_loss,
+    sv_tvae_set_layer_cfg,
+    sv_tvae_num_layers,
 )

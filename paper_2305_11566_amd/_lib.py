@@ -82,6 +82,15 @@ _SIGS = {
     "sv_layer_cfgs": (ctypes.c_int32, [_DESC, _I, _I, _I, ctypes.POINTER(ctypes.c_int)]),
     "sv_conv_cfg_name": (ctypes.c_char_p, [_I]),
     "sv_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int)]),
+    "sv_tvae_param_count": (_I64, []),
+    "sv_tvae_packed_bytes": (_SZ, [_I]),
+    "sv_tvae_pack_weights": (ctypes.c_int32, [_I, _P, _P, _P]),
+    "sv_tvae_workspace_bytes": (_SZ, [_I, _I, _I, _I, _I]),
+    "sv_tvae_forward": (ctypes.c_int32, [_I, _I, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _SZ, _P]),
+    "sv_tvae_loss_workspace_bytes": (_SZ, []),
+    "sv_tvae_loss": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
+    "sv_tvae_set_layer_cfg": (ctypes.c_int32, [_I, _I]),
+    "sv_tvae_num_layers": (_I, []),
 }
 
 

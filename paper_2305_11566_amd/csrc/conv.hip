@@ -66,25 +66,55 @@ sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int 
 bool conv_fits_f32(int ks, int stride, int tile);
 bool conv_fits_bf16(int ks, int stride, int tile);
 bool conv_fits_f16(int ks, int stride, int tile);
+#define SV_CONV5_DECL(S, dt)                                                                      \
+    sv_status launch_conv5_s##S##_##dt(int cfg, const ConvParams &p, int pg, hipStream_t st); \
+    bool conv5_fits_s##S##_##dt(int tile);
+SV_CONV5_DECL(1, f32) SV_CONV5_DECL(2, f32) SV_CONV5_DECL(1, bf16) SV_CONV5_DECL(2, bf16)
+SV_CONV5_DECL(1, f16) SV_CONV5_DECL(2, f16)
+#undef SV_CONV5_DECL
+
+static bool fits_any(int dtype, int ks, int stride, int tile) {
+    if (ks == 5) {
+        if (stride != 1 && stride != 2) return false;
+        switch (dtype) {
+        case SV_F32: return stride == 1 ? conv5_fits_s1_f32(tile) : conv5_fits_s2_f32(tile);
+        case SV_BF16: return stride == 1 ? conv5_fits_s1_bf16(tile) : conv5_fits_s2_bf16(tile);
+        case SV_F16: return stride == 1 ? conv5_fits_s1_f16(tile) : conv5_fits_s2_f16(tile);
+        default: return false;
+        }
+    }
+    switch (dtype) {
+    case SV_F32: return conv_fits_f32(ks, stride, tile);
+    case SV_BF16: return conv_fits_bf16(ks, stride, tile);
+    case SV_F16: return conv_fits_f16(ks, stride, tile);
+    default: return false;
+    }
+}
 
 // A configuration whose tile shape does not fit the LDS for this kernel size
 // and stride runs as th4_tn16 (which fits every case) with the same split;
 // the tile shape does not change results.
 int conv_resolve_cfg(int dtype, int ks, int stride, int cfg) {
     if (cfg < 0 || cfg >= conv_num_cfgs()) return cfg;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return cfg;
     const int tile = cfg % kNumTiles;
-    bool fits = false;
-    switch (dtype) {
-    case SV_F32: fits = conv_fits_f32(ks, stride, tile); break;
-    case SV_BF16: fits = conv_fits_bf16(ks, stride, tile); break;
-    case SV_F16: fits = conv_fits_f16(ks, stride, tile); break;
-    default: return cfg;
-    }
-    return fits ? cfg : cfg - tile + kFallbackTile;
+    return fits_any(dtype, ks, stride, tile) ? cfg : cfg - tile + kFallbackTile;
 }
 
 static sv_status launch_any(int dtype, int ks, int stride, int tile, const ConvParams &p, int pg,
                             hipStream_t st) {
+    if (ks == 5) {
+        if (stride != 1 && stride != 2) return SV_ERR_UNSUPPORTED;
+        switch (dtype) {
+        case SV_F32:
+            return stride == 1 ? launch_conv5_s1_f32(tile, p, pg, st) : launch_conv5_s2_f32(tile, p, pg, st);
+        case SV_BF16:
+            return stride == 1 ? launch_conv5_s1_bf16(tile, p, pg, st) : launch_conv5_s2_bf16(tile, p, pg, st);
+        case SV_F16:
+            return stride == 1 ? launch_conv5_s1_f16(tile, p, pg, st) : launch_conv5_s2_f16(tile, p, pg, st);
+        default: return SV_ERR_DTYPE;
+        }
+    }
     switch (dtype) {
     case SV_F32: return launch_conv_f32(ks, stride, tile, p, pg, st);
     case SV_BF16: return launch_conv_bf16(ks, stride, tile, p, pg, st);

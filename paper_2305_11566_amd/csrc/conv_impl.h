@@ -1,5 +1,6 @@
 // Implicit-GEMM convolution kernel templates (included by the per-dtype
-// instantiation files conv_f32.hip, conv_bf16.hip, conv_f16.hip).
+// instantiation files conv_f32.hip, conv_bf16.hip, conv_f16.hip, and by
+// conv5_<stride>_<dtype>.hip for 5x5 kernels).
 #pragma once
 
 #include <algorithm>
@@ -498,7 +499,7 @@ struct ConvTile {
             // pairs run over those alone, so a small Cin costs few steps
             const int keff = min(KCGB, (c_end - c0 - sub * KCB + GS - 1) / GS);
             const int npairs = TAPS * keff;
-            const int krcp = (256 + keff - 1) / keff;  // q / keff = (q * krcp) >> 8 for q < 40
+            const int krcp = (256 + keff - 1) / keff;  // q / keff = (q * krcp) >> 8 for q < 128 (keff <= 4)
             // unrolled so the LDS operand loads of later steps are issued ahead
             // of the MFMAs of earlier ones
 #pragma unroll
@@ -710,6 +711,14 @@ static bool fits_dt(int ks, int stride, int cfg) {
     if (ks == 1 && stride == 1) return fits_cfg<DT, 1, 1>(cfg);
     return false;
 }
+
+// 5x5 kernels (the Table I network), one stride per instantiation file
+template <int DT, int S>
+static sv_status launch_dt5(int cfg, const ConvParams &p, int pg, hipStream_t st) {
+    return launch_cfg<DT, 5, S>(cfg, p, pg, st);
+}
+template <int DT, int S>
+static bool fits_dt5(int cfg) { return fits_cfg<DT, 5, S>(cfg); }
 
 template <int DT>
 static sv_status launch_dt(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st) {

@@ -115,8 +115,8 @@ struct ConvParams {
     int ksplit;
 };
 
-// cfg selects the tile shape and the reduction split (see conv.hip); ks = 1 or
-// 3, stride = 1 or 2.
+// cfg selects the tile shape and the reduction split (see conv.hip); ks = 1, 3
+// or 5, stride = 1 or 2 (ks = 1: stride 1 only).
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s);
 // persistent launch over p.tab's tiles of stage p.stage with `grid` workgroups
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,

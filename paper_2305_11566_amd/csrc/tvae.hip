@@ -1,0 +1,540 @@
+// The refinement network exactly in the shape of Table I (Sec. III-B1):
+// feature extraction, encoder with residual blocks, the one-channel mu /
+// sigma head with the shifts of Eq. (8), decoder with 5x5 stride-2
+// deconvolutions and skip connections, and the final upsampling layer; plus
+// the loss of Eqs. (9)-(11).
+//
+// Layout: each level keeps one NHWC map whose channel ranges are the maps the
+// table concatenates, in the table's order, so every "A & B & C" input is one
+// contiguous channel range read by one convolution source:
+//   level 1 (h1 x w1 = the coarse map): [D 16 | FE_1 32 | FE_2 32]        80 ch
+//   level 2 (h1/2):                     [D_2 16 | EN_1 16 | EN_1_R 8 | D_2_R 8] 48 ch
+//   level 3 (h1/4):                     [D_1 32 | EN_2 32 | EN_2_R 16 | D_1_R 16] 96 ch
+// A stride-2 deconvolution is a stride-1 convolution with the flipped kernel
+// over its input seen with zeros inserted between samples (SRC_ZINS), cut to
+// the size of the level it feeds.  FE_1 and FE_2 run as one layer over the two
+// input channels with block-diagonal weights.  The final upsampling layer
+// (5x5, stride f, one output channel) runs as a 1x1 projection of the level-1
+// map and X_0 onto its 25 taps (MFMA), then a gather that adds, for each
+// full-resolution pixel, the taps that land on it.
+#include <algorithm>
+#include <atomic>
+
+#include "kernels.h"
+
+namespace sv {
+
+namespace {
+
+#define SV_TRY_STATUS(x)            \
+    do {                            \
+        sv_status r_ = (x);         \
+        if (r_ != SV_OK) return r_; \
+    } while (0)
+
+constexpr int TV_K = 5, TV_TAPS = 25;
+constexpr int L1C = 80, L2C = 48, L3C = 96, ZC = 8, TC = 32;
+
+// canonical layers, in the table's order: weights [out][in][k][k], then bias
+struct CanonLayer { int cout, cin, k; };
+constexpr CanonLayer kCanon[] = {
+    {32, 1, 5},   // FE_1
+    {32, 1, 5},   // FE_2
+    {16, 64, 5},  // EN_1
+    {8, 16, 5},   // EN_1_R
+    {32, 24, 5},  // EN_2
+    {16, 32, 5},  // EN_2_R
+    {2, 48, 1},   // mu & sigma
+    {32, 1, 1},   // D_1 (1x1 deconvolution)
+    {16, 80, 5},  // D_1_R
+    {16, 96, 5},  // D_2 (deconvolution, stride 2)
+    {8, 40, 5},   // D_2_R
+    {16, 48, 5},  // D (deconvolution, stride 2)
+    {1, 81, 5},   // Y (upsampling layer, stride f)
+};
+constexpr int NCANON = 13;
+enum { C_FE1 = 0, C_FE2, C_EN1, C_EN1R, C_EN2, C_EN2R, C_MS, C_D1, C_D1R, C_D2, C_D2R, C_D, C_Y };
+
+// launched layers (FE_1 and FE_2 fused; Y as its tap projection)
+enum { T_FE = 0, T_EN1, T_EN1R, T_EN2, T_EN2R, T_MS, T_D1, T_D1R, T_D2, T_D2R, T_D, T_YP, T_NL };
+struct TvLayer { int cout, cin, k, stride; };  // stride of the launched convolution
+constexpr TvLayer kLayers[T_NL] = {
+    {64, 2, 5, 1}, {16, 64, 5, 2}, {8, 16, 5, 1}, {32, 24, 5, 2}, {16, 32, 5, 1}, {2, 48, 1, 1},
+    {32, 1, 1, 1}, {16, 80, 5, 1}, {16, 96, 5, 1}, {8, 40, 5, 1}, {16, 48, 5, 1}, {TV_TAPS, 82, 1, 1},
+};
+
+int64_t canon_off(int i) {
+    int64_t o = 0;
+    for (int j = 0; j < i; ++j) o += (int64_t)kCanon[j].cout * kCanon[j].cin * kCanon[j].k * kCanon[j].k + kCanon[j].cout;
+    return o;
+}
+
+inline int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+struct TvShape {
+    int dtype, es;
+    int n_pad[T_NL], cin_pad[T_NL];
+    size_t w_off[T_NL], b_off[T_NL], bytes;
+};
+
+TvShape tv_shape(int dtype) {
+    TvShape s{};
+    s.dtype = dtype;
+    s.es = dtype_bytes(dtype);
+    size_t off = 0;
+    for (int i = 0; i < T_NL; ++i) {
+        const TvLayer &l = kLayers[i];
+        s.n_pad[i] = rup(l.cout, 16);
+        s.cin_pad[i] = rup(l.cin, 8);
+        // the tap projection stays FP32 in every mode, like the other network's
+        // final layer: its few weights dominate the reduced-precision error
+        const int les = i == T_YP ? 4 : s.es;
+        s.w_off[i] = off;
+        off = align256(off + (size_t)l.k * l.k * s.n_pad[i] * s.cin_pad[i] * les);
+        s.b_off[i] = off;
+        off = align256(off + (size_t)s.n_pad[i] * sizeof(float));
+    }
+    s.bytes = off;
+    return s;
+}
+
+struct TvLevels { int H, W, h[4], w[4]; };  // h[1..3]: levels 1..3
+
+TvLevels tv_levels(int f, int H, int W) {
+    TvLevels lv{};
+    lv.H = H; lv.W = W;
+    lv.h[1] = cdiv(H, f); lv.w[1] = cdiv(W, f);
+    for (int k = 2; k < 4; ++k) { lv.h[k] = cdiv(lv.h[k - 1], 2); lv.w[k] = cdiv(lv.w[k - 1], 2); }
+    return lv;
+}
+
+struct TvAct { size_t L1, L2, L3, Z, ML, T, total; };
+
+TvAct tv_act(int es, const TvLevels &lv, int B) {
+    auto px = [&](int k) { return (size_t)B * lv.h[k] * lv.w[k]; };
+    TvAct a{};
+    size_t o = 0;
+    a.L1 = o; o = align256(o + px(1) * L1C * es);
+    a.L2 = o; o = align256(o + px(2) * L2C * es);
+    a.L3 = o; o = align256(o + px(3) * L3C * es);
+    a.Z = o;  o = align256(o + px(3) * ZC * es);
+    a.ML = o; o = align256(o + px(3) * 2 * sizeof(float));
+    a.T = o;  o = align256(o + px(1) * TC * sizeof(float));
+    a.total = o;
+    return a;
+}
+
+std::atomic<int> g_tv_cfg[T_NL];
+struct TvCfgInit {
+    TvCfgInit() { for (auto &v : g_tv_cfg) v.store(-1); }
+} g_tv_cfg_init;
+
+int tv_default_cfg(int layer) {
+    const int ov = g_tv_cfg[layer].load();
+    if (ov >= 0 && ov < conv_num_cfgs()) return ov;
+    return kLayers[layer].cout <= 16 ? 5 /* th4_tn16 */ : 2 /* th4_tn32 */;
+}
+
+// ---- packing ------------------------------------------------------------------------
+// One job writes the rows [row0, row0 + cout) of a packed layer from one
+// canonical layer: column c of the packed row reads canonical input channel
+// cmap[c] (-1: zero); flip turns a deconvolution into the equivalent
+// correlation over the zero-inserted input; proj packs the upsampling layer as
+// one row per tap.
+struct PackJob {
+    const float *w;   // canonical weights of the layer
+    int cout, cin, k, row0, taps, n_pad, cin_pad, flip, proj;
+    int cmap[96];
+};
+
+template <int DT>
+__global__ void k_tv_pack_t(const PackJob j, typename Elem<DT>::T *__restrict__ dst) {
+    const int rows = j.proj ? TV_TAPS : j.cout;
+    const int total = j.taps * rows * j.cin_pad;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % j.cin_pad;
+        const int r = (e / j.cin_pad) % rows;
+        const int tap = e / (j.cin_pad * rows);
+        const int ci = c < 96 ? j.cmap[c] : -1;
+        float v = 0.f;
+        if (ci >= 0) {
+            if (j.proj) v = j.w[(size_t)ci * j.k * j.k + r];  // output channel 0, tap r
+            else v = j.w[((size_t)r * j.cin + ci) * j.k * j.k + (j.flip ? j.k * j.k - 1 - tap : tap)];
+        }
+        dst[((size_t)tap * j.n_pad + j.row0 + r) * j.cin_pad + c] = Elem<DT>::make(v);
+    }
+}
+
+__global__ void k_zero_bytes(uint32_t *__restrict__ p, size_t n_words) {
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n_words; e += (size_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+__global__ void k_tv_bias(const float *__restrict__ b, int n, float *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = b[i];
+}
+
+sv_status run_pack_job(int dt, const PackJob &j, void *dst, hipStream_t st) {
+    const int rows = j.proj ? TV_TAPS : j.cout;
+    const int total = j.taps * rows * j.cin_pad;
+    const int blocks = std::min((total + 255) / 256, 1024);
+    switch (dt) {
+    case SV_F32: hipLaunchKernelGGL(k_tv_pack_t<SV_F32>, dim3(blocks), dim3(256), 0, st, j, (float *)dst); break;
+    case SV_BF16: hipLaunchKernelGGL(k_tv_pack_t<SV_BF16>, dim3(blocks), dim3(256), 0, st, j, (uint16_t *)dst); break;
+    case SV_F16: hipLaunchKernelGGL(k_tv_pack_t<SV_F16>, dim3(blocks), dim3(256), 0, st, j, (uint16_t *)dst); break;
+    default: return SV_ERR_DTYPE;
+    }
+    SV_LAUNCH_CHECK("k_tv_pack");
+    return SV_OK;
+}
+
+sv_status tv_pack(const TvShape &s, const float *params, void *packed, hipStream_t st) {
+    // zero padding rows and columns first (a fill kernel, not a memset node)
+    const size_t words = s.bytes / 4;
+    hipLaunchKernelGGL(k_zero_bytes, dim3((unsigned)std::min<size_t>((words + 255) / 256, 4096)), dim3(256), 0, st,
+                       (uint32_t *)packed, words);
+    SV_LAUNCH_CHECK("k_zero_bytes");
+    char *P = (char *)packed;
+    auto job = [&](int canon, int layer, int row0, bool flip, auto colmap) -> sv_status {
+        PackJob j{};
+        const CanonLayer &c = kCanon[canon];
+        j.w = params + canon_off(canon);
+        j.cout = c.cout; j.cin = c.cin; j.k = c.k; j.row0 = row0;
+        j.proj = layer == T_YP;
+        j.taps = j.proj ? 1 : c.k * c.k;
+        j.n_pad = s.n_pad[layer]; j.cin_pad = s.cin_pad[layer];
+        j.flip = flip;
+        for (int q = 0; q < 96; ++q) j.cmap[q] = q < j.cin_pad ? colmap(q) : -1;
+        SV_TRY_STATUS(run_pack_job(layer == T_YP ? SV_F32 : s.dtype, j, P + s.w_off[layer], st));
+        // bias of these rows (the projection has none: the gather adds Y's bias)
+        if (!j.proj) {
+            hipLaunchKernelGGL(k_tv_bias, dim3(1), dim3(64), 0, st, j.w + (size_t)c.cout * c.cin * c.k * c.k, c.cout,
+                               (float *)(P + s.b_off[layer]) + row0);
+            SV_LAUNCH_CHECK("k_tv_bias");
+        }
+        return SV_OK;
+    };
+    auto ident = [](int cin) { return [cin](int q) { return q < cin ? q : -1; }; };
+    // FE: rows 0..31 read channel 0 (X_0), rows 32..63 channel 1 (X_1)
+    SV_TRY_STATUS(job(C_FE1, T_FE, 0, false, [](int q) { return q == 0 ? 0 : -1; }));
+    SV_TRY_STATUS(job(C_FE2, T_FE, 32, false, [](int q) { return q == 1 ? 0 : -1; }));
+    SV_TRY_STATUS(job(C_EN1, T_EN1, 0, false, ident(64)));
+    SV_TRY_STATUS(job(C_EN1R, T_EN1R, 0, false, ident(16)));
+    SV_TRY_STATUS(job(C_EN2, T_EN2, 0, false, ident(24)));
+    SV_TRY_STATUS(job(C_EN2R, T_EN2R, 0, false, ident(32)));
+    SV_TRY_STATUS(job(C_MS, T_MS, 0, false, ident(48)));
+    SV_TRY_STATUS(job(C_D1, T_D1, 0, false, ident(1)));
+    SV_TRY_STATUS(job(C_D1R, T_D1R, 0, false, ident(80)));
+    SV_TRY_STATUS(job(C_D2, T_D2, 0, true, ident(96)));
+    SV_TRY_STATUS(job(C_D2R, T_D2R, 0, false, ident(40)));
+    SV_TRY_STATUS(job(C_D, T_D, 0, true, ident(48)));
+    // projection columns: the level-1 map [D | FE_1 | FE_2], then X_0, X_1;
+    // the table's order is D & X_0 & FE_1 & FE_2 (X_1 does not enter)
+    SV_TRY_STATUS(job(C_Y, T_YP, 0, false, [](int q) { return q < 16 ? q : (q < 80 ? q + 1 : (q == 80 ? 16 : -1)); }));
+    // Y's bias goes to the projection's bias slot, read by the gather
+    hipLaunchKernelGGL(k_tv_bias, dim3(1), dim3(64), 0, st, params + canon_off(C_Y) + 81 * 25, 1,
+                       (float *)(P + s.b_off[T_YP]));
+    SV_LAUNCH_CHECK("k_tv_bias");
+    return SV_OK;
+}
+
+// ---- Eq. (8) and the final gather ------------------------------------------------
+// z = (mu - 1) + eps * exp(sigma - 1) (eps NULL: z = mu - 1), stored as channel 0
+// of an 8-channel row (channels 1..7 zero) so that the 1x1 deconvolution reads
+// whole channel groups.
+template <int DT>
+__global__ void k_tv_reparam(const float *__restrict__ ml, const float *__restrict__ eps, int n,
+                             typename Elem<DT>::T *__restrict__ z) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float v = ml[2 * i] - 1.0f;
+    if (eps) v += eps[i] * expf(ml[2 * i + 1] - 1.0f);
+    typename Elem<DT>::T *o = z + (size_t)i * ZC;
+    o[0] = Elem<DT>::make(v);
+#pragma unroll
+    for (int c = 1; c < ZC; ++c) o[c] = Elem<DT>::make(0.f);
+}
+
+// out[b][y][x] = 256 * (bias + sum over level-1 pixels (i, j) and taps (u, v)
+// with f*i + u - 2 = y, f*j + v - 2 = x of T[b][i][j][5u + v]), rows i and
+// columns j ascending.
+__global__ void __launch_bounds__(256)
+k_tv_final(const float *__restrict__ T, int B, int h, int w, int f, int H, int W,
+           const float *__restrict__ bias, float *__restrict__ out) {
+    const int x = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int y = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    if (x >= W || y >= H) return;
+    // i with 0 <= y + 2 - f i <= 4
+    const int ilo = max(0, (y - 2 + f - 1 + 2 * f) / f - 2), ihi = min(h - 1, (y + 2) / f);
+    const int jlo = max(0, (x - 2 + f - 1 + 2 * f) / f - 2), jhi = min(w - 1, (x + 2) / f);
+    float s = 0.f;
+    for (int i = ilo; i <= ihi; ++i) {
+        const int u = y + 2 - f * i;
+        for (int j = jlo; j <= jhi; ++j) {
+            const int v = x + 2 - f * j;
+            s += T[(((size_t)b * h + i) * w + j) * TC + u * TV_K + v];
+        }
+    }
+    out[((size_t)b * H + y) * W + x] = 256.0f * (s + bias[0]);
+}
+
+ConvSrc tsrc(const void *p, int C, int pitch, int coff, int hs, int ws, int kind, int sdt) {
+    ConvSrc s{};
+    s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.coff = coff; s.hs = hs; s.ws = ws; s.sdt = sdt;
+    return s;
+}
+
+sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, ConvSrc s1, int B, int Hi,
+                   int Wi, int Ho, int Wo, void *out, int out_pitch, int out_coff, int out_f32, int act,
+                   hipStream_t st) {
+    ConvParams p{};
+    p.src[0] = s0; p.src[1] = s1;
+    p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
+    p.Cin = s0.C + (s1.kind ? s1.C : 0);
+    p.Cout = kLayers[li].cout;
+    p.cin_pad = s.cin_pad[li];
+    p.n_pad = s.n_pad[li];
+    p.wpk = (const char *)packed + s.w_off[li];
+    p.bias = li == T_YP ? nullptr : (const float *)((const char *)packed + s.b_off[li]);
+    p.out = out; p.out_pitch = out_pitch; p.out_coff = out_coff;
+    p.act = act; p.out_f32 = out_f32;
+    const int dt = li == T_YP ? SV_F32 : s.dtype;
+    return launch_conv(dt, kLayers[li].k, kLayers[li].stride, tv_default_cfg(li), p, st);
+}
+
+sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t *disp, const uint8_t *img,
+                     int B, int H, int W, const float *eps, float *out, float *ml_user, void *ws,
+                     hipStream_t st) {
+    const TvLevels lv = tv_levels(f, H, W);
+    const TvAct a = tv_act(s.es, lv, B);
+    char *w = (char *)ws;
+    void *L1 = w + a.L1, *L2 = w + a.L2, *L3 = w + a.L3, *Z = w + a.Z;
+    float *ML = ml_user ? ml_user : (float *)(w + a.ML);
+    float *T = (float *)(w + a.T);
+    const int h1 = lv.h[1], w1 = lv.w[1], h2 = lv.h[2], w2 = lv.w[2], h3 = lv.h[3], w3 = lv.w[3];
+    const ConvSrc none{};
+    ConvSrc x0{};
+    x0.ptr = disp; x0.img = img; x0.kind = SRC_X0; x0.C = 2; x0.hs = h1; x0.ws = w1;
+    x0.scale0 = (float)f / 256.0f;
+    // feature extraction: [FE_1 | FE_2] into level 1, channels 16..79
+    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, st));
+    // encoder
+    SV_TRY_STATUS(tv_layer(s, packed, T_EN1, tsrc(L1, 64, L1C, 16, h1, w1, SRC_TENSOR, 0), none, B, h1, w1, h2, w2,
+                           L2, L2C, 16, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_EN1R, tsrc(L2, 16, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
+                           L2, L2C, 32, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_EN2, tsrc(L2, 24, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h3, w3,
+                           L3, L3C, 32, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_EN2R, tsrc(L3, 32, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
+                           L3, L3C, 64, 0, 1, st));
+    // mu & sigma (FP32), then Eq. (8)
+    SV_TRY_STATUS(tv_layer(s, packed, T_MS, tsrc(L3, 48, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
+                           ML, 2, 0, 1, 0, st));
+    const int nl = B * h3 * w3;
+    switch (s.dtype) {
+    case SV_F32: hipLaunchKernelGGL(k_tv_reparam<SV_F32>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (float *)Z); break;
+    case SV_BF16: hipLaunchKernelGGL(k_tv_reparam<SV_BF16>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (uint16_t *)Z); break;
+    default: hipLaunchKernelGGL(k_tv_reparam<SV_F16>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (uint16_t *)Z); break;
+    }
+    SV_LAUNCH_CHECK("k_tv_reparam");
+    // decoder
+    SV_TRY_STATUS(tv_layer(s, packed, T_D1, tsrc(Z, 1, ZC, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
+                           L3, L3C, 0, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_D1R, tsrc(L3, 80, L3C, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
+                           L3, L3C, 80, 0, 1, st));
+    // deconvolutions: the zero-inserted grid has 2n - 1 samples per axis
+    SV_TRY_STATUS(tv_layer(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, B, 2 * h3 - 1,
+                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_D2R, tsrc(L2, 40, L2C, 0, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
+                           L2, L2C, 40, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, B, 2 * h2 - 1,
+                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, st));
+    // upsampling layer: tap projection of [D | FE_1 | FE_2 | X_0 X_1] (FP32
+    // weights; the map is read in its stored dtype), then the gather
+    const int sdt = s.dtype == SV_F32 ? 0 : 1 + s.dtype;
+    SV_TRY_STATUS(tv_layer(s, packed, T_YP, tsrc(L1, 80, L1C, 0, h1, w1, SRC_TENSOR, sdt), x0, B, h1, w1, h1, w1,
+                           T, TC, 0, 1, 0, st));
+    hipLaunchKernelGGL(k_tv_final, dim3(cdiv(W, 64), cdiv(H, 4), B), dim3(256), 0, st, T, B, h1, w1, f, H, W,
+                       (const float *)((const char *)packed + s.b_off[T_YP]), out);
+    SV_LAUNCH_CHECK("k_tv_final");
+    return SV_OK;
+}
+
+// ---- loss (Eqs. (9)-(11)) -----------------------------------------------------------
+constexpr int TL_BLOCKS = 256, TL_THREADS = 256;
+
+__device__ __forceinline__ double tl_block_sum(double v, double *sh) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int k = TL_THREADS / 2; k > 0; k >>= 1) {
+        if (t < k) sh[t] += sh[t + k];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// per block: sum |out - gt| (noc + occ), the occ count and the KL sum
+__global__ void __launch_bounds__(TL_THREADS)
+k_tv_loss_partial(const float *__restrict__ out, const float *__restrict__ gt, const uint8_t *__restrict__ noc,
+                  const uint8_t *__restrict__ occ, int64_t n, const float *__restrict__ ml, int64_t nl,
+                  double *__restrict__ part) {
+    __shared__ double sh[TL_THREADS];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    double s = 0.0, cnt = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += TL_THREADS) {
+        const double a = fabs((double)out[i] - (double)gt[i]);
+        const int m = (noc[i] ? 1 : 0) + (occ[i] ? 1 : 0);
+        s += a * m;
+        cnt += occ[i] ? 1.0 : 0.0;
+    }
+    const int64_t perl = (nl + gridDim.x - 1) / gridDim.x;
+    const int64_t llo = blockIdx.x * perl, lhi = llo + perl < nl ? llo + perl : nl;
+    double k = 0.0;
+    for (int64_t i = llo + threadIdx.x; i < lhi; i += TL_THREADS) {
+        const double m = (double)ml[2 * i] - 1.0, sg = (double)ml[2 * i + 1] - 1.0;
+        k += 0.5 * (m * m - 1.0 + exp(2.0 * sg) - 2.0 * sg);
+    }
+    s = tl_block_sum(s, sh);
+    cnt = tl_block_sum(cnt, sh);
+    k = tl_block_sum(k, sh);
+    if (threadIdx.x == 0) {
+        part[3 * blockIdx.x] = s;
+        part[3 * blockIdx.x + 1] = cnt;
+        part[3 * blockIdx.x + 2] = k;
+    }
+}
+
+// loss_out = [total, 256 * Loss_1, 256 * Loss_2]; part[3 * TL_BLOCKS] keeps the
+// ground-truth count for the gradient kernel
+__global__ void __launch_bounds__(TL_THREADS)
+k_tv_loss_final(double *__restrict__ part, int64_t nl, float *__restrict__ loss_out) {
+    __shared__ double sh[TL_THREADS];
+    double s = 0.0, c = 0.0, k = 0.0;
+    for (int i = threadIdx.x; i < TL_BLOCKS; i += TL_THREADS) {
+        s += part[3 * i];
+        c += part[3 * i + 1];
+        k += part[3 * i + 2];
+    }
+    s = tl_block_sum(s, sh);
+    c = tl_block_sum(c, sh);
+    k = tl_block_sum(k, sh);
+    if (threadIdx.x == 0) {
+        const double nn = c > 1.0 ? c : 1.0;
+        const double l1 = s / nn, l2 = nl > 0 ? 256.0 * k / (double)nl : 0.0;
+        loss_out[0] = (float)(l1 + l2);
+        loss_out[1] = (float)l1;
+        loss_out[2] = (float)l2;
+        part[3 * TL_BLOCKS] = nn;
+    }
+}
+
+__global__ void k_tv_loss_grad(const float *__restrict__ out, const float *__restrict__ gt,
+                               const uint8_t *__restrict__ noc, const uint8_t *__restrict__ occ, int64_t n,
+                               const float *__restrict__ ml, int64_t nl, const double *__restrict__ part,
+                               float *__restrict__ dout, float *__restrict__ dml) {
+    const double inv = 1.0 / part[3 * TL_BLOCKS];
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!dout) break;
+        const float e = out[i] - gt[i];
+        const int sg = (e > 0.f) - (e < 0.f);
+        const int m = (noc[i] ? 1 : 0) + (occ[i] ? 1 : 0);
+        dout[i] = (float)((double)(sg * m) * inv);
+    }
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nl; i += (int64_t)gridDim.x * blockDim.x) {
+        if (!dml) break;
+        const double m = (double)ml[2 * i] - 1.0, sgm = (double)ml[2 * i + 1] - 1.0;
+        dml[2 * i] = (float)(256.0 * m / (double)nl);
+        dml[2 * i + 1] = (float)(256.0 * (exp(2.0 * sgm) - 1.0) / (double)nl);
+    }
+}
+
+}  // namespace
+
+}  // namespace sv
+
+using namespace sv;
+
+extern "C" {
+
+int64_t sv_tvae_param_count(void) { return canon_off(NCANON); }
+
+size_t sv_tvae_packed_bytes(int dtype) {
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return 0;
+    return tv_shape(dtype).bytes;
+}
+
+sv_status sv_tvae_pack_weights(int dtype, const float *params, void *packed_out, void *stream) {
+    if (!params || !packed_out) return SV_ERR_NULL;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;
+    if ((uintptr_t)packed_out % 256) return SV_ERR_RANGE;
+    return tv_pack(tv_shape(dtype), params, packed_out, (hipStream_t)stream);
+}
+
+static bool tv_shape_ok(int factor, int B, int H, int W) {
+    if (factor < 1 || factor > 8 || B < 1 || H < 1 || W < 1) return false;
+    if ((int64_t)B * H * W >= ((int64_t)1 << 31)) return false;
+    // one workgroup row per 4 images in z for the widest layer
+    return (int64_t)B * 4 <= 65535;
+}
+
+size_t sv_tvae_workspace_bytes(int dtype, int factor, int B, int H, int W) {
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return 0;
+    if (!tv_shape_ok(factor, B, H, W)) return 0;
+    return tv_act(dtype_bytes(dtype), tv_levels(factor, H, W), B).total;
+}
+
+sv_status sv_tvae_forward(int dtype, int factor, const void *packed_w, const uint8_t *disp_low,
+                          const uint8_t *img_low, int B, int H, int W, const float *eps, float *out,
+                          float *mu_sigma, void *workspace, size_t ws_bytes, void *stream) {
+    if (!packed_w || !disp_low || !img_low || !out || !workspace) return SV_ERR_NULL;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;
+    if (factor < 1 || factor > 8) return SV_ERR_RANGE;
+    if (!tv_shape_ok(factor, B, H, W)) return SV_ERR_SHAPE;
+    if (ws_bytes < sv_tvae_workspace_bytes(dtype, factor, B, H, W)) return SV_ERR_WORKSPACE;
+    if ((uintptr_t)workspace % 256 || (uintptr_t)packed_w % 256) return SV_ERR_RANGE;
+    return tv_forward(tv_shape(dtype), factor, packed_w, disp_low, img_low, B, H, W, eps, out, mu_sigma,
+                      workspace, (hipStream_t)stream);
+}
+
+size_t sv_tvae_loss_workspace_bytes(void) { return sizeof(double) * (3 * TL_BLOCKS + 1); }
+
+sv_status sv_tvae_loss(const float *out, const float *gt, const uint8_t *noc, const uint8_t *occ, int64_t n,
+                       const float *mu_sigma, int64_t n_lat, float *loss_out, float *dout, float *dmu_sigma,
+                       void *workspace, size_t ws_bytes, void *stream) {
+    if (!out || !gt || !noc || !occ || !mu_sigma || !loss_out || !workspace) return SV_ERR_NULL;
+    if (n <= 0 || n_lat <= 0) return SV_ERR_SHAPE;
+    if (ws_bytes < sv_tvae_loss_workspace_bytes()) return SV_ERR_WORKSPACE;
+    if ((uintptr_t)workspace % 8) return SV_ERR_RANGE;
+    hipStream_t st = (hipStream_t)stream;
+    double *part = (double *)workspace;
+    hipLaunchKernelGGL(k_tv_loss_partial, dim3(TL_BLOCKS), dim3(TL_THREADS), 0, st, out, gt, noc, occ, n, mu_sigma,
+                       n_lat, part);
+    SV_LAUNCH_CHECK("k_tv_loss_partial");
+    hipLaunchKernelGGL(k_tv_loss_final, dim3(1), dim3(TL_THREADS), 0, st, part, n_lat, loss_out);
+    SV_LAUNCH_CHECK("k_tv_loss_final");
+    if (dout || dmu_sigma) {
+        const int64_t m = n > n_lat ? n : n_lat;
+        const int blocks = (int)std::min<int64_t>((m + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_tv_loss_grad, dim3(blocks), dim3(256), 0, st, out, gt, noc, occ, n, mu_sigma, n_lat,
+                           (const double *)part, dout, dmu_sigma);
+        SV_LAUNCH_CHECK("k_tv_loss_grad");
+    }
+    return SV_OK;
+}
+
+sv_status sv_tvae_set_layer_cfg(int layer, int cfg) {
+    if (layer < 0 || layer >= T_NL) return SV_ERR_RANGE;
+    if (cfg < -1 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
+    g_tv_cfg[layer].store(cfg);
+    return SV_OK;
+}
+
+int sv_tvae_num_layers(void) { return T_NL; }
+
+}  // extern "C"

@@ -365,3 +365,92 @@ def sv_tile_config(stage: int) -> str:
     buf = ctypes.create_string_buffer(128)
     check(lib().sv_tile_config(stage, buf, 128), "sv_tile_config")
     return buf.value.decode()
+
+# ---------------------------------------------------------- Table I network
+
+def tvae_param_count() -> int:
+    return int(lib().sv_tvae_param_count())
+
+
+def sv_tvae_set_layer_cfg(layer: int, cfg: int):
+    check(lib().sv_tvae_set_layer_cfg(layer, cfg), "sv_tvae_set_layer_cfg")
+
+
+def sv_tvae_num_layers() -> int:
+    return int(lib().sv_tvae_num_layers())
+
+
+class TableVAE:
+    """The Table I network: packed weights and a workspace sized for the last
+    shape; forwards to sv_tvae_forward."""
+
+    def __init__(self, factor, dtype="f32", device="cuda"):
+        if dtype not in DTYPES:
+            raise ValueError(f"dtype must be one of {sorted(DTYPES)}")
+        self.dtype_code = DTYPES[dtype]
+        self.factor = factor
+        self.device = torch.device(device)
+        self.nparams = tvae_param_count()
+        self.packed = _aligned_bytes(lib().sv_tvae_packed_bytes(self.dtype_code), self.device)
+        self._ws = None
+        self._ws_key = None
+
+    def pack(self, params: torch.Tensor):
+        """params: FP32 canonical vector [nparams] on the device."""
+        _need(params, torch.float32, "params")
+        if params.numel() != self.nparams:
+            raise ValueError(f"expected {self.nparams} parameters, got {params.numel()}")
+        check(lib().sv_tvae_pack_weights(self.dtype_code, ptr(params), ptr(self.packed), stream_ptr()),
+              "sv_tvae_pack_weights")
+
+    def workspace(self, B, H, W):
+        key = (B, H, W)
+        if self._ws_key != key:
+            n = lib().sv_tvae_workspace_bytes(self.dtype_code, self.factor, B, H, W)
+            if n == 0:
+                raise ValueError(f"invalid shape {key}")
+            self._ws = _aligned_bytes(n, self.device)
+            self._ws_key = key
+        return self._ws
+
+    def latent_shape(self, B, H, W):
+        h, w = _cdiv(H, self.factor), _cdiv(W, self.factor)
+        for _ in range(2):
+            h, w = _cdiv(h, 2), _cdiv(w, 2)
+        return (B, h, w)
+
+    def forward(self, disp_low, img_low, H, W, eps=None, out=None, mu_sigma=None):
+        """-> (out [B, H, W] full-res px, mu_sigma [B, h3, w3, 2])."""
+        _need(disp_low, torch.uint8, "disp_low")
+        _need(img_low, torch.uint8, "img_low")
+        B = disp_low.shape[0]
+        if out is None:
+            out = torch.empty((B, H, W), dtype=torch.float32, device=self.device)
+        if mu_sigma is None:
+            mu_sigma = torch.empty(self.latent_shape(B, H, W) + (2,), dtype=torch.float32,
+                                   device=self.device)
+        if eps is not None:
+            _need(eps, torch.float32, "eps")
+        ws = self.workspace(B, H, W)
+        check(lib().sv_tvae_forward(self.dtype_code, self.factor, ptr(self.packed), ptr(disp_low),
+                                    ptr(img_low), B, H, W, ptr(eps), ptr(out), ptr(mu_sigma), ptr(ws),
+                                    ws.numel(), stream_ptr()), "sv_tvae_forward")
+        return out, mu_sigma
+
+
+def sv_tvae_loss(out, gt, noc, occ, mu_sigma, want_grad=True):
+    """Eqs. (9)-(11) -> (loss [3] = total, Loss_1, Loss_2; dout or None; dmu_sigma or None)."""
+    _need(out, torch.float32, "out")
+    _need(gt, torch.float32, "gt")
+    _need(noc, torch.uint8, "noc")
+    _need(occ, torch.uint8, "occ")
+    _need(mu_sigma, torch.float32, "mu_sigma")
+    loss = torch.empty(3, dtype=torch.float32, device=out.device)
+    dout = torch.empty_like(out) if want_grad else None
+    dml = torch.empty_like(mu_sigma) if want_grad else None
+    nb = lib().sv_tvae_loss_workspace_bytes()
+    ws = torch.empty((nb + 7) // 8, dtype=torch.float64, device=out.device)
+    check(lib().sv_tvae_loss(ptr(out), ptr(gt), ptr(noc), ptr(occ), out.numel(), ptr(mu_sigma),
+                             mu_sigma.numel() // 2, ptr(loss), ptr(dout), ptr(dml), ptr(ws), nb,
+                             stream_ptr()), "sv_tvae_loss")
+    return loss, dout, dml

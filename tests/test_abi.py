@@ -107,6 +107,41 @@ def test_vae_validation():
     assert l.sv_vae_workspace_bytes(ctypes.byref(d), 0, 128, 256) == 0
 
 
+def test_tvae_counts_and_sizes():
+    from oracle import tvae
+    assert lib().sv_tvae_param_count() == tvae.n_params() == 162380
+    assert lib().sv_tvae_packed_bytes(0) > 0 and lib().sv_tvae_packed_bytes(7) == 0
+    assert lib().sv_tvae_packed_bytes(0) % 256 == 0
+    assert lib().sv_tvae_workspace_bytes(0, 4, 1, 375, 1242) > 0
+    assert lib().sv_tvae_workspace_bytes(0, 9, 1, 375, 1242) == 0    # factor
+    assert lib().sv_tvae_workspace_bytes(0, 4, 0, 375, 1242) == 0    # batch
+    assert lib().sv_tvae_workspace_bytes(5, 4, 1, 375, 1242) == 0    # dtype
+    assert lib().sv_tvae_workspace_bytes(0, 4, 16384, 64, 64) == 0   # grid z limit
+    assert lib().sv_tvae_num_layers() == 12
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 4, None, P, P, 1, 64, 64, None, P, None, P, 1 << 30, None), -1),
+    ((0, 4, P, P, P, 1, 64, 64, None, None, None, P, 1 << 30, None), -1),
+    ((7, 4, P, P, P, 1, 64, 64, None, P, None, P, 1 << 30, None), -4),
+    ((0, 0, P, P, P, 1, 64, 64, None, P, None, P, 1 << 30, None), -3),
+    ((0, 4, P, P, P, 0, 64, 64, None, P, None, P, 1 << 30, None), -2),
+    ((0, 4, P, P, P, 1, 64, 64, None, P, None, P, 16, None), -5),
+])
+def test_tvae_forward_validation(args, code):
+    assert lib().sv_tvae_forward(*args) == code
+
+
+def test_tvae_loss_and_cfg_validation():
+    nb = lib().sv_tvae_loss_workspace_bytes()
+    assert lib().sv_tvae_loss(None, P, P, P, 10, P, 2, P, None, None, P, nb, None) == -1
+    assert lib().sv_tvae_loss(P, P, P, P, 0, P, 2, P, None, None, P, nb, None) == -2
+    assert lib().sv_tvae_loss(P, P, P, P, 10, P, 2, P, None, None, P, 8, None) == -5
+    assert lib().sv_tvae_set_layer_cfg(12, 0) == -3
+    assert lib().sv_tvae_set_layer_cfg(0, lib().sv_num_layer_cfgs()) == -3
+    assert lib().sv_tvae_set_layer_cfg(0, -1) == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     import paper_2305_11566_amd._lib as L
     monkeypatch.setattr(L, "_lib", None)

@@ -1,0 +1,148 @@
+"""GPU parity of the Table I network (Sec. III-B1) and its loss (Eqs. (9)-(11))
+against the FP64 oracle.
+
+FP32: normwise max|y - y64| / max|y64| <= 1e-5 on the refined disparity and on
+mu / sigma.  BF16 / FP16: mean end-point error bounded relative to the output
+scale.  Tile shapes must not change a single bit.  The loss: value within
+1e-6 relative, gradients within 1e-6 normwise.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import tvae
+from synth import gen_config, gen_pair, gen_eps, he_init_params
+from tests.gpu_util import cuda, flat_params, normwise
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+
+
+def _params(seed, bias_scale=0.1):
+    return he_init_params(tvae.layer_shapes(), seed=seed, bias_scale=bias_scale)
+
+
+def _latent_hw(H, W, f):
+    h, w = -(-H // f), -(-W // f)
+    for _ in range(2):
+        h, w = -(-h // 2), -(-w // 2)
+    return h, w
+
+
+def _gpu(dtype, f, params, disp, img, H, W, eps=None):
+    import paper_2305_11566_amd as sv
+    net = sv.TableVAE(f, dtype)
+    net.pack(cuda(flat_params(params)))
+    out, ms = net.forward(cuda(disp), cuda(img), H, W, eps=None if eps is None else cuda(eps))
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ms.cpu().numpy()
+
+
+def _compare(f, H, W, disp, img, seed=7, eps=None, dtype="f32", tol=TOL_F32):
+    params = _params(seed)
+    t = tvae.forward(params, disp, img, f, H, W, eps=None if eps is None else eps[:, None])
+    out, ms = _gpu(dtype, f, params, disp, img, H, W, eps)
+    e_out = normwise(out, t["out"])
+    e_ms = max(normwise(ms[..., 0], t["mu"][:, 0]), normwise(ms[..., 1], t["sigma"][:, 0]))
+    assert e_out <= tol, f"out normwise {e_out:.3e}"
+    assert e_ms <= tol, f"mu/sigma normwise {e_ms:.3e}"
+    return out, t
+
+
+def _rand_inputs(B, H, W, f, seed):
+    rng = np.random.default_rng(seed)
+    h, w = -(-H // f), -(-W // f)
+    return (rng.integers(0, 48, (B, h, w)).astype(np.uint8),
+            rng.integers(0, 256, (B, h, w)).astype(np.uint8))
+
+
+def test_f32_full_size_1242x375():
+    p = gen_config(2)
+    lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
+    _compare(4, 375, 1242, d, lo)
+
+
+def test_f32_table_factor_2():
+    p = gen_config(1)
+    lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
+    _compare(2, 128, 256, d, lo)
+
+
+@pytest.mark.parametrize("H,W,f,B", [
+    (45, 70, 4, 2),     # every level ragged, odd deconvolution outputs
+    (37, 53, 2, 1),
+    (30, 81, 3, 2),     # stride-3 upsampling layer
+    (13, 19, 1, 1),     # f = 1: the upsampling layer keeps the size
+    (8, 8, 8, 3),       # coarse map 1x1: every level 1x1
+    (64, 512, 4, 1),    # wide: many column tiles
+    (100, 36, 2, 2),    # tall
+])
+def test_f32_shapes(H, W, f, B):
+    d, im = _rand_inputs(B, H, W, f, H * W + f)
+    _compare(f, H, W, d, im, seed=H)
+
+
+def test_f32_training_eps():
+    H, W, f, B = 48, 80, 2, 2
+    d, im = _rand_inputs(B, H, W, f, 3)
+    eps = gen_eps((B,) + _latent_hw(H, W, f), seed=9001).astype(np.float32)
+    _compare(f, H, W, d, im, eps=eps)
+
+
+def test_tile_shapes_bitwise_identical():
+    import paper_2305_11566_amd as sv
+    H, W, f, B = 45, 70, 4, 2
+    d, im = _rand_inputs(B, H, W, f, 17)
+    params = _params(3)
+    base, _ = _gpu("f32", f, params, d, im, H, W)
+    try:
+        for cfg in (0, 1, 3, 4, 6, 7, 9, 11, 13, 15, 16 + 2):
+            for layer in range(sv.sv_tvae_num_layers()):
+                sv.sv_tvae_set_layer_cfg(layer, cfg)
+            out, _ = _gpu("f32", f, params, d, im, H, W)
+            assert np.array_equal(out, base), sv.sv_conv_cfg_name(cfg)
+    finally:
+        for layer in range(sv.sv_tvae_num_layers()):
+            sv.sv_tvae_set_layer_cfg(layer, -1)
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_reduced_precision_epe(dtype):
+    p = gen_config(1)
+    lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
+    params = _params(7)
+    t = tvae.forward(params, d, lo, 2, 128, 256)
+    out, _ = _gpu(dtype, 2, params, d, lo, 128, 256)
+    epe = float(np.mean(np.abs(out - t["out"])))
+    scale = float(np.mean(np.abs(t["out"])))
+    print(f"{dtype}: mean EPE {epe:.4f} px, max {np.max(np.abs(out - t['out'])):.3f} px, mean |out| {scale:.2f}")
+    assert epe <= 0.02 * scale + 0.05
+
+
+def test_loss_matches_oracle():
+    import paper_2305_11566_amd as sv
+    H, W, f, B = 40, 64, 2, 2
+    pairs = [gen_pair(H, W, 4, 2.0, 20.0, seed=5500 + b) for b in range(B)]
+    gt = np.stack([p.gt for p in pairs]).astype(np.float32)
+    noc = np.stack([p.noc for p in pairs])
+    occ = np.stack([p.occ for p in pairs])
+    occ[0, :3] = False          # some pixels without ground truth
+    noc &= occ
+    rng = np.random.default_rng(1)
+    out = (gt + rng.normal(0, 2.0, gt.shape)).astype(np.float32)
+    out[1, 5, 5] = gt[1, 5, 5]  # exact hit: zero gradient
+    ms = rng.normal(1.0, 0.3, (B,) + _latent_hw(H, W, f) + (2,)).astype(np.float32)
+    tot, l1, l2, dout, dmu, dsig = tvae.loss(out, gt, noc, occ, ms[..., 0], ms[..., 1])
+    loss, gdout, gdml = sv.sv_tvae_loss(cuda(out), cuda(gt), cuda(noc.astype(np.uint8)),
+                                        cuda(occ.astype(np.uint8)), cuda(ms))
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy().astype(np.float64)
+    for got, ref in zip(loss, (tot, l1, l2)):
+        assert abs(got - ref) <= 1e-6 * max(1.0, abs(ref)), (got, ref)
+    assert normwise(gdout.cpu().numpy(), dout) <= 1e-6
+    g = gdml.cpu().numpy()
+    assert normwise(g[..., 0], dmu) <= 1e-6
+    assert normwise(g[..., 1], dsig) <= 1e-6
+    assert gdout.cpu().numpy()[1, 5, 5] == 0.0
