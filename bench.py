@@ -280,6 +280,88 @@ def run_sgm(sv, torch, dev, flat, K, Wm):
     return out
 
 
+TABLE1_SEED = 7013
+
+
+def table1_flops(B):
+    """Algorithmic FLOPs of one Table I forward pass on B 1242x375 frames
+    (2 per multiply-add of the layer definitions; a deconvolution counts every
+    input sample times k^2 taps)."""
+    hs, ws = levels(B)
+    p1, p2, p3 = hs[0] * ws[0], hs[1] * ws[1], hs[2] * ws[2]
+    macs = (p1 * 64 * 25                      # FE_1 and FE_2 (one input channel each)
+            + p2 * 16 * 64 * 25 + p2 * 8 * 16 * 25      # EN_1, EN_1_R
+            + p3 * 32 * 24 * 25 + p3 * 16 * 32 * 25     # EN_2, EN_2_R
+            + p3 * 2 * 48 + p3 * 32                     # mu & sigma, D_1
+            + p3 * 16 * 80 * 25 + p3 * 96 * 16 * 25     # D_1_R, D_2 (over its input)
+            + p2 * 8 * 40 * 25 + p2 * 48 * 16 * 25      # D_2_R, D (over its input)
+            + p1 * 81 * 25)                             # Y (over its input)
+    return 2.0 * B * macs
+
+
+# (out, in, k) per layer of Table I in parameter order
+TABLE1_SHAPES = [(32, 1, 5), (32, 1, 5), (16, 64, 5), (8, 16, 5), (32, 24, 5), (16, 32, 5), (2, 48, 1),
+                 (32, 1, 1), (16, 80, 5), (16, 96, 5), (8, 40, 5), (16, 48, 5), (1, 81, 5)]
+
+
+def run_table1(sv, torch, dev, K, Wm):
+    """Census + WTA + the Table I network on the 1242x375 pairs, graph
+    replayed, FP32 and BF16 at batch 1 and 64 (He-init weights, seed 7013),
+    and the network alone with its MFMA-peak fraction."""
+    from synth import he_init_params
+    params = he_init_params(TABLE1_SHAPES, seed=TABLE1_SEED)
+    flat = torch.from_numpy(np.concatenate([np.concatenate([w.ravel(), b.ravel()])
+                                            for w, b in params]).astype(np.float32)).to(dev)
+    out = {"weights": "He-init, seed 7013", "params": int(flat.numel())}
+
+    def graph_ms(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        for _ in range(Wm):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            g.replay()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / k
+
+    for B in (1, 64):
+        left, right, _ = make_inputs(B, dev)
+        hs, ws = levels(B)
+        cl = torch.empty((B, hs[0], ws[0]), dtype=torch.int64, device=dev)
+        cr = torch.empty_like(cl)
+        low = torch.empty((B, hs[0], ws[0]), dtype=torch.uint8, device=dev)
+        disp = torch.empty_like(low)
+        res = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+        k = K if B == 1 else max(5, min(K, 20))
+        for dt in ("f32", "bf16"):
+            net = sv.TableVAE(F, dt)
+            net.pack(flat)
+            net.workspace(B, H, W)
+            ms_sig = torch.empty(net.latent_shape(B, H, W) + (2,), dtype=torch.float32, device=dev)
+
+            def path():
+                sv.sv_census_pair(left, right, F, WIN_W, WIN_H, out=(cl, cr, low))
+                sv.sv_cost_wta(cl, cr, D, NBITS, out=disp)
+                net.forward(disp, low, H, W, out=res, mu_sigma=ms_sig)
+
+            def net_only():
+                net.forward(disp, low, H, W, out=res, mu_sigma=ms_sig)
+
+            ms_p = graph_ms(path, k)
+            ms_n = graph_ms(net_only, k)
+            tf = table1_flops(B) / (ms_n * 1e-3) / 1e12
+            out[f"{dt}_batch_{B}"] = {
+                "path_ms": round(ms_p, 4), "frames_per_s": round(B * 1e3 / ms_p, 1),
+                "network_ms": round(ms_n, 4), "network_TFLOPs": round(tf, 3),
+                "network_mfma_frac": round(tf / PEAK["mfma_TFLOPs"][dt], 4)}
+            del net
+    out["gflop_per_frame"] = round(table1_flops(1) / 1e9, 4)
+    return out
 def run_extras(sv, torch, dev, flat, K, Wm):
     """Uneven batch (64 pairs, one graph) vs the per-pair loop; BF16 / FP16 vs
     FP32 end-point error with briefly trained weights; training steps/s."""
@@ -389,6 +471,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven batch, precision and training measurements")
+    ap.add_argument("--section", choices=("sgm", "table1"), default=None,
+                    help="run only this extras section (for profiling) and print it as the JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -402,6 +486,11 @@ def main():
     dev = torch.device("cuda:0")
     K, Wm = args.steps, args.warmup
     _, flat = make_params()
+    if args.section:
+        fn = {"sgm": lambda: run_sgm(sv, torch, dev, flat, K, Wm),
+              "table1": lambda: run_table1(sv, torch, dev, K, Wm)}[args.section]
+        print(json.dumps({"section": args.section, "steps": K, "warmup": Wm, "result": fn()}))
+        return
     left, right, gt = make_inputs(args.batch, dev)
 
     # ---- tile shapes: the library's autotuner for this shape ---------------------------
@@ -515,6 +604,7 @@ def main():
     extras = {} if args.no_extras else run_extras(sv, torch, dev, flat, K, Wm)
     if not args.no_extras:
         extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
+        extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 

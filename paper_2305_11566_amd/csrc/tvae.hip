@@ -108,18 +108,28 @@ TvLevels tv_levels(int f, int H, int W) {
     return lv;
 }
 
-struct TvAct { size_t L1, L2, L3, Z, ML, T, total; };
+struct TvAct { size_t L1, L2, L3, Z, ML, T, part, part_bytes, total; };
+
+// output level of each launched layer
+constexpr int kOutLevel[T_NL] = {1, 2, 2, 3, 3, 3, 3, 3, 2, 2, 1, 1};
 
 TvAct tv_act(int es, const TvLevels &lv, int B) {
     auto px = [&](int k) { return (size_t)B * lv.h[k] * lv.w[k]; };
     TvAct a{};
     size_t o = 0;
+    // partial sums of split-reduction launches (small grids): room for the
+    // largest layer output at the maximum split, capped
+    size_t part = 0;
+    for (int i = 0; i < T_NL; ++i)
+        part = std::max(part, (size_t)CONV_MAX_SPLIT * px(kOutLevel[i]) * rup(kLayers[i].cout, 16) * sizeof(float));
+    a.part_bytes = std::min(part, CONV_PART_CAP);
     a.L1 = o; o = align256(o + px(1) * L1C * es);
     a.L2 = o; o = align256(o + px(2) * L2C * es);
     a.L3 = o; o = align256(o + px(3) * L3C * es);
     a.Z = o;  o = align256(o + px(3) * ZC * es);
     a.ML = o; o = align256(o + px(3) * 2 * sizeof(float));
     a.T = o;  o = align256(o + px(1) * TC * sizeof(float));
+    a.part = o; o = align256(o + a.part_bytes);
     a.total = o;
     return a;
 }
@@ -129,10 +139,18 @@ struct TvCfgInit {
     TvCfgInit() { for (auto &v : g_tv_cfg) v.store(-1); }
 } g_tv_cfg_init;
 
-int tv_default_cfg(int layer) {
+// Tile th4_tn16 / th4_tn32 by output width; grids of fewer than 256
+// workgroups (the coarse levels of small batches) split the reduction over
+// up to four channel ranges so that more CUs take part.
+int tv_default_cfg(int layer, int B, int Ho, int Wo) {
     const int ov = g_tv_cfg[layer].load();
     if (ov >= 0 && ov < conv_num_cfgs()) return ov;
-    return kLayers[layer].cout <= 16 ? 5 /* th4_tn16 */ : 2 /* th4_tn32 */;
+    const int tn = kLayers[layer].cout <= 16 ? 16 : 32;
+    const int tile = tn == 16 ? 5 /* th4_tn16 */ : 2 /* th4_tn32 */;
+    const long long nwg = (long long)cdiv(Wo, 16) * cdiv(Ho, 4) * B * cdiv(kLayers[layer].cout, tn);
+    int split = 1;
+    while (split < CONV_MAX_SPLIT && nwg * split < 256) ++split;
+    return tile + conv_num_tiles() * (split - 1);
 }
 
 // ---- packing ------------------------------------------------------------------------
@@ -288,8 +306,10 @@ ConvSrc tsrc(const void *p, int C, int pitch, int coff, int hs, int ws, int kind
 
 sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, ConvSrc s1, int B, int Hi,
                    int Wi, int Ho, int Wo, void *out, int out_pitch, int out_coff, int out_f32, int act,
-                   hipStream_t st) {
+                   float *part, size_t part_bytes, hipStream_t st) {
     ConvParams p{};
+    p.part = part;
+    p.part_bytes = part_bytes;
     p.src[0] = s0; p.src[1] = s1;
     p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
     p.Cin = s0.C + (s1.kind ? s1.C : 0);
@@ -301,7 +321,7 @@ sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, Con
     p.out = out; p.out_pitch = out_pitch; p.out_coff = out_coff;
     p.act = act; p.out_f32 = out_f32;
     const int dt = li == T_YP ? SV_F32 : s.dtype;
-    return launch_conv(dt, kLayers[li].k, kLayers[li].stride, tv_default_cfg(li), p, st);
+    return launch_conv(dt, kLayers[li].k, kLayers[li].stride, tv_default_cfg(li, B, Ho, Wo), p, st);
 }
 
 sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t *disp, const uint8_t *img,
@@ -313,25 +333,26 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     void *L1 = w + a.L1, *L2 = w + a.L2, *L3 = w + a.L3, *Z = w + a.Z;
     float *ML = ml_user ? ml_user : (float *)(w + a.ML);
     float *T = (float *)(w + a.T);
+    float *part = (float *)(w + a.part);
     const int h1 = lv.h[1], w1 = lv.w[1], h2 = lv.h[2], w2 = lv.w[2], h3 = lv.h[3], w3 = lv.w[3];
     const ConvSrc none{};
     ConvSrc x0{};
     x0.ptr = disp; x0.img = img; x0.kind = SRC_X0; x0.C = 2; x0.hs = h1; x0.ws = w1;
     x0.scale0 = (float)f / 256.0f;
     // feature extraction: [FE_1 | FE_2] into level 1, channels 16..79
-    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, part, a.part_bytes, st));
     // encoder
     SV_TRY_STATUS(tv_layer(s, packed, T_EN1, tsrc(L1, 64, L1C, 16, h1, w1, SRC_TENSOR, 0), none, B, h1, w1, h2, w2,
-                           L2, L2C, 16, 0, 1, st));
+                           L2, L2C, 16, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN1R, tsrc(L2, 16, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
-                           L2, L2C, 32, 0, 1, st));
+                           L2, L2C, 32, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN2, tsrc(L2, 24, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h3, w3,
-                           L3, L3C, 32, 0, 1, st));
+                           L3, L3C, 32, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN2R, tsrc(L3, 32, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 64, 0, 1, st));
+                           L3, L3C, 64, 0, 1, part, a.part_bytes, st));
     // mu & sigma (FP32), then Eq. (8)
     SV_TRY_STATUS(tv_layer(s, packed, T_MS, tsrc(L3, 48, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           ML, 2, 0, 1, 0, st));
+                           ML, 2, 0, 1, 0, part, a.part_bytes, st));
     const int nl = B * h3 * w3;
     switch (s.dtype) {
     case SV_F32: hipLaunchKernelGGL(k_tv_reparam<SV_F32>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (float *)Z); break;
@@ -341,21 +362,21 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     SV_LAUNCH_CHECK("k_tv_reparam");
     // decoder
     SV_TRY_STATUS(tv_layer(s, packed, T_D1, tsrc(Z, 1, ZC, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 0, 0, 1, st));
+                           L3, L3C, 0, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D1R, tsrc(L3, 80, L3C, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 80, 0, 1, st));
+                           L3, L3C, 80, 0, 1, part, a.part_bytes, st));
     // deconvolutions: the zero-inserted grid has 2n - 1 samples per axis
     SV_TRY_STATUS(tv_layer(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, B, 2 * h3 - 1,
-                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, st));
+                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D2R, tsrc(L2, 40, L2C, 0, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
-                           L2, L2C, 40, 0, 1, st));
+                           L2, L2C, 40, 0, 1, part, a.part_bytes, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, B, 2 * h2 - 1,
-                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, st));
+                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, part, a.part_bytes, st));
     // upsampling layer: tap projection of [D | FE_1 | FE_2 | X_0 X_1] (FP32
     // weights; the map is read in its stored dtype), then the gather
     const int sdt = s.dtype == SV_F32 ? 0 : 1 + s.dtype;
     SV_TRY_STATUS(tv_layer(s, packed, T_YP, tsrc(L1, 80, L1C, 0, h1, w1, SRC_TENSOR, sdt), x0, B, h1, w1, h1, w1,
-                           T, TC, 0, 1, 0, st));
+                           T, TC, 0, 1, 0, part, a.part_bytes, st));
     hipLaunchKernelGGL(k_tv_final, dim3(cdiv(W, 64), cdiv(H, 4), B), dim3(256), 0, st, T, B, h1, w1, f, H, W,
                        (const float *)((const char *)packed + s.b_off[T_YP]), out);
     SV_LAUNCH_CHECK("k_tv_final");
