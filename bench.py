@@ -362,6 +362,30 @@ def run_table1(sv, torch, dev, K, Wm):
             del net
     out["gflop_per_frame"] = round(table1_flops(1) / 1e9, 4)
     return out
+def run_int8(sv, torch, dev, flat, K, Wm):
+    """Census + WTA + the INT8 network (per-channel weight scales, dynamic
+    per-tensor activation scales) on the 1242x375 pairs, graph replayed at
+    batch 1 and 64, and its end-point error against the FP32 network on the
+    same frames (He-init weights: a stress figure, not a trained accuracy)."""
+    out = {"weights": "He-init, seed 7002 (the headline network)"}
+    for B in (1, 64):
+        left, right, _ = make_inputs(B, dev)
+        k = K if B == 1 else max(5, min(K, 20))
+        res = {}
+        for dt in ("i8", "f32"):
+            p = Path(B, dt, flat, left, right)
+            p.capture()
+            ms = p.timed(k, Wm)
+            res[dt] = (ms, p.out.clone())
+            del p
+        d = (res["i8"][1] - res["f32"][1]).abs()
+        out[f"batch_{B}"] = {"ms_per_step": round(res["i8"][0], 4),
+                             "frames_per_s": round(B * 1e3 / res["i8"][0], 1),
+                             "f32_frames_per_s": round(B * 1e3 / res["f32"][0], 1),
+                             "i8_vs_f32_mean_px": float(d.mean()), "i8_vs_f32_max_px": float(d.max())}
+    return out
+
+
 def run_extras(sv, torch, dev, flat, K, Wm):
     """Uneven batch (64 pairs, one graph) vs the per-pair loop; BF16 / FP16 vs
     FP32 end-point error with briefly trained weights; training steps/s."""
@@ -471,7 +495,7 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the uneven batch, precision and training measurements")
-    ap.add_argument("--section", choices=("sgm", "table1"), default=None,
+    ap.add_argument("--section", choices=("sgm", "table1", "int8"), default=None,
                     help="run only this extras section (for profiling) and print it as the JSON line")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -488,7 +512,8 @@ def main():
     _, flat = make_params()
     if args.section:
         fn = {"sgm": lambda: run_sgm(sv, torch, dev, flat, K, Wm),
-              "table1": lambda: run_table1(sv, torch, dev, K, Wm)}[args.section]
+              "table1": lambda: run_table1(sv, torch, dev, K, Wm),
+              "int8": lambda: run_int8(sv, torch, dev, flat, K, Wm)}[args.section]
         print(json.dumps({"section": args.section, "steps": K, "warmup": Wm, "result": fn()}))
         return
     left, right, gt = make_inputs(args.batch, dev)
@@ -605,6 +630,7 @@ def main():
     if not args.no_extras:
         extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
         extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm)
+        extras["int8_network_1242x375"] = run_int8(sv, torch, dev, flat, K, Wm)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 

@@ -48,10 +48,21 @@ typedef int32_t sv_status;
 #define SV_ERR_HIP (-7)         /* the HIP runtime reported an error */
 
 /* Compute / storage precision of the network's convolutions.  Accumulation is
- * FP32 in every case; the residual base, the latent, KL and loss stay FP32. */
+ * FP32 for SV_F32 / SV_BF16 / SV_F16; the residual base, the latent, KL and
+ * loss stay FP32.
+ * SV_I8 (the configurable network's sv_vae_* inference only): the quantised
+ * network that the paper's closing section plans -- INT8 weights with one
+ * scale per output channel (code = clamp(rint(w * 127 / a), -127, 127), a =
+ * max |w| of the channel) and INT8 activations with one dynamic scale per
+ * tensor (every convolution's epilogue records max |stored value| of its
+ * output; a layer quantises what it reads with 127 / m, m the largest amax of
+ * its sources; x0's amax comes from the coarse maps), exact INT32 sums on the
+ * MFMA units, then y = float(sum) * (s_in * s_w) + bias in FP32, activations
+ * stored in BF16.  The final layer stays FP32 as in every mode. */
 #define SV_F32 0
 #define SV_BF16 1
 #define SV_F16 2
+#define SV_I8 3
 
 /* Human-readable name of a status code (static storage). */
 const char *sv_status_str(sv_status s);

@@ -4,7 +4,7 @@ map -- hand-written HIP kernels behind the C ABI of include/sv.h (libsv.so).
 
 Python here only marshals arguments; see ``ops`` for the entry points.
 """
-from ._lib import lib, header_symbols, SvError, SV_F32, SV_BF16, SV_F16, DTYPES  # noqa: F401
+from ._lib import lib, header_symbols, SvError, SV_F32, SV_BF16, SV_F16, SV_I8, DTYPES  # noqa: F401
 from .ops import (  # noqa: F401
     sv_census,
     sv_census_pair,

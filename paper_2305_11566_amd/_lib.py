@@ -16,8 +16,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsv.so")
 HEADER = os.path.join(os.path.dirname(_HERE), "include", "sv.h")
 
-SV_F32, SV_BF16, SV_F16 = 0, 1, 2
-DTYPES = {"f32": SV_F32, "fp32": SV_F32, "bf16": SV_BF16, "f16": SV_F16, "fp16": SV_F16}
+SV_F32, SV_BF16, SV_F16, SV_I8 = 0, 1, 2, 3
+DTYPES = {"f32": SV_F32, "fp32": SV_F32, "bf16": SV_BF16, "f16": SV_F16, "fp16": SV_F16, "i8": SV_I8,
+          "int8": SV_I8}
 
 STATUS = {0: "SV_OK", -1: "SV_ERR_NULL", -2: "SV_ERR_SHAPE", -3: "SV_ERR_RANGE",
           -4: "SV_ERR_DTYPE", -5: "SV_ERR_WORKSPACE", -6: "SV_ERR_UNSUPPORTED", -7: "SV_ERR_HIP"}

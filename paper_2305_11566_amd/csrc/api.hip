@@ -220,6 +220,7 @@ sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const ui
     if (r != SV_OK) return r;
     if (!packed_w || !disp_low || !img_low || !out || !workspace) return SV_ERR_NULL;
     if (eps && !saved) return SV_ERR_NULL;   // sampling z is only for training
+    if (ns.dtype == SV_I8 && (eps || saved)) return SV_ERR_UNSUPPORTED;  // INT8: inference only
     if (!shape_ok(B, H, W)) return SV_ERR_SHAPE;
     if (ws_bytes < sv_vae_workspace_bytes(desc, B, H, W)) return SV_ERR_WORKSPACE;
     if ((uintptr_t)workspace % 256 || (saved && (uintptr_t)saved % 256) || (uintptr_t)packed_w % 256)
@@ -236,6 +237,7 @@ sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const v
     NetShape ns;
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
+    if (ns.dtype == SV_I8) return SV_ERR_UNSUPPORTED;
     if (!packed_w || !saved || !dout || !grad_out || !workspace) return SV_ERR_NULL;
     if (!shape_ok(B, H, W)) return SV_ERR_SHAPE;
     if (ws_bytes < sv_vae_workspace_bytes(desc, B, H, W)) return SV_ERR_WORKSPACE;
@@ -250,7 +252,7 @@ sv_status sv_vae_backward(const sv_vae_desc *desc, const void *packed_w, const v
 sv_status sv_set_layer_cfg(int layer, int cfg) {
     if (layer < 0 || layer >= NLAYERS) return SV_ERR_RANGE;
     if (cfg < -1 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
-    for (int dt = 0; dt < 3; ++dt) net_set_cfg_override(dt, layer, cfg);
+    for (int dt = 0; dt < 4; ++dt) net_set_cfg_override(dt, layer, cfg);
     return SV_OK;
 }
 

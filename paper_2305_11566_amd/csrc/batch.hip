@@ -313,6 +313,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     NetShape ns;
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
+    if (ns.dtype == SV_I8) return SV_ERR_UNSUPPORTED;  // INT8: sv_vae_forward only
     if (max_n < 1 || max_n > SV_MAXN || max_H < 1 || max_W < 1 || max_H > 16384 || max_W > 16384)
         return SV_ERR_SHAPE;
     if (max_D < 1 || max_D > 256) return SV_ERR_RANGE;
@@ -471,6 +472,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     NetShape ns;
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
+    if (ns.dtype == SV_I8) return SV_ERR_UNSUPPORTED;  // INT8: sv_vae_forward only
     if (B < 1 || H < 1 || W < 1 || H > 16384 || W > 16384) return SV_ERR_SHAPE;
     if (D < 1 || D > 256) return SV_ERR_RANGE;
     const size_t ws = sv_vae_workspace_bytes(desc, B, H, W);

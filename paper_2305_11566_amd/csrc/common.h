@@ -12,6 +12,8 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
+typedef int8_t i8x8 __attribute__((ext_vector_type(8)));
+typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
 
 namespace sv {
 
@@ -64,6 +66,16 @@ template <> struct Elem<SV_F16> {
     typedef uint16_t T;
     static __device__ __forceinline__ float load(const T *p) { return f16_bits_to_f32(*p); }
     static __device__ __forceinline__ T make(float f) { return f32_to_f16_bits(f); }
+};
+
+// bytes of a stored activation (INT8 layers store BF16)
+// INT8 codes (clamped to +-127, round to nearest even)
+template <> struct Elem<SV_I8> {
+    typedef int8_t T;
+    static __device__ __forceinline__ float load(const T *p) { return (float)*p; }
+    static __device__ __forceinline__ T make(float f) {
+        return (int8_t)(int)fminf(fmaxf(rintf(f), -127.0f), 127.0f);
+    }
 };
 
 static inline int dtype_bytes(int dt) { return dt == SV_F32 ? 4 : 2; }

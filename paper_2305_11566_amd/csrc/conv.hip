@@ -24,6 +24,7 @@
 // templates live in conv_impl.h and are instantiated per compute dtype in
 // conv_f32.hip / conv_bf16.hip / conv_f16.hip; this file holds the tile
 // table, the dispatch and the weight packing.
+#include <algorithm>
 #include <cstdio>
 #include <mutex>
 
@@ -66,6 +67,8 @@ sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int 
 bool conv_fits_f32(int ks, int stride, int tile);
 bool conv_fits_bf16(int ks, int stride, int tile);
 bool conv_fits_f16(int ks, int stride, int tile);
+sv_status launch_conv_i8(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
+bool conv_fits_i8(int ks, int stride, int tile);
 #define SV_CONV5_DECL(S, dt)                                                                      \
     sv_status launch_conv5_s##S##_##dt(int cfg, const ConvParams &p, int pg, hipStream_t st); \
     bool conv5_fits_s##S##_##dt(int tile);
@@ -87,6 +90,7 @@ static bool fits_any(int dtype, int ks, int stride, int tile) {
     case SV_F32: return conv_fits_f32(ks, stride, tile);
     case SV_BF16: return conv_fits_bf16(ks, stride, tile);
     case SV_F16: return conv_fits_f16(ks, stride, tile);
+    case SV_I8: return conv_fits_i8(ks, stride, tile);
     default: return false;
     }
 }
@@ -96,7 +100,7 @@ static bool fits_any(int dtype, int ks, int stride, int tile) {
 // the tile shape does not change results.
 int conv_resolve_cfg(int dtype, int ks, int stride, int cfg) {
     if (cfg < 0 || cfg >= conv_num_cfgs()) return cfg;
-    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return cfg;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16 && dtype != SV_I8) return cfg;
     const int tile = cfg % kNumTiles;
     return fits_any(dtype, ks, stride, tile) ? cfg : cfg - tile + kFallbackTile;
 }
@@ -119,12 +123,16 @@ static sv_status launch_any(int dtype, int ks, int stride, int tile, const ConvP
     case SV_F32: return launch_conv_f32(ks, stride, tile, p, pg, st);
     case SV_BF16: return launch_conv_bf16(ks, stride, tile, p, pg, st);
     case SV_F16: return launch_conv_f16(ks, stride, tile, p, pg, st);
+    case SV_I8:
+        if (ks == 5) return SV_ERR_UNSUPPORTED;
+        return launch_conv_i8(ks, stride, tile, p, pg, st);
     default: return SV_ERR_DTYPE;
     }
 }
 
 int conv_effective_split(int dtype, int cfg, int Cin, long long npix, int n_pad, const float *part,
                          size_t part_bytes) {
+    if (dtype == SV_I8) return 1;  // integer sums are kept whole
     int ksplit = cfg / kNumTiles + 1;
     // at most one split per base chunk of input channels, and only when the
     // partial sums fit the caller's buffer; otherwise one pass
@@ -211,6 +219,70 @@ sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n
         return SV_ERR_DTYPE;
     }
     SV_LAUNCH_CHECK("k_pack");
+    return SV_OK;
+}
+
+// INT8 packing: one workgroup per output row n.  a = max |w[n]| over its
+// inputs and taps (FP32), code = clamp(rint(w * (127 / a)), -127, 127),
+// scale = a / 127; rows past Cout and columns past Cin are 0.
+__global__ void __launch_bounds__(256)
+k_pack_i8(const float *__restrict__ w, int Cout, int Cin, int k, int n_pad, int cin_pad, int8_t *__restrict__ dst,
+          float *__restrict__ scale) {
+    __shared__ float red[256];
+    const int n = blockIdx.x;
+    const int taps = k * k, len = Cin * taps;
+    float m = 0.f;
+    if (n < Cout)
+        for (int e = threadIdx.x; e < len; e += 256) m = fmaxf(m, fabsf(w[(size_t)n * len + e]));
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + s]);
+        __syncthreads();
+    }
+    const float a = red[0];
+    const float inv = a > 0.f ? 127.0f / a : 0.f;
+    if (threadIdx.x == 0) scale[n] = n < Cout ? a / 127.0f : 0.f;
+    for (int e = threadIdx.x; e < taps * cin_pad; e += 256) {
+        const int tap = e / cin_pad, c = e - tap * cin_pad;
+        const float v = (n < Cout && c < Cin) ? w[((size_t)n * Cin + c) * taps + tap] : 0.f;
+        dst[((size_t)tap * n_pad + n) * cin_pad + c] = quant_i8(v, inv);
+    }
+}
+
+sv_status launch_pack_i8(const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad, int8_t *dst,
+                         float *scale, hipStream_t s) {
+    hipLaunchKernelGGL(k_pack_i8, dim3(n_pad), dim3(256), 0, s, w, Cout, Cin, k, n_pad, cin_pad, dst, scale);
+    SV_LAUNCH_CHECK("k_pack_i8");
+    return SV_OK;
+}
+
+__global__ void k_amax_zero(uint32_t *__restrict__ amax, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) amax[i] = 0u;
+}
+
+// max(scale0 * d, img / 256) over the coarse pixels, one slot word per workgroup
+__global__ void __launch_bounds__(256)
+k_amax_x0(uint32_t *__restrict__ slot, const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img,
+          long long n, float scale0) {
+    float m = 0.f;
+    for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256)
+        m = fmaxf(m, fmaxf(scale0 * (float)disp[i], (float)img[i] * (1.0f / 256.0f)));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot + (blockIdx.x & (AMAX_SUB - 1)), __float_as_uint(m));
+}
+
+sv_status launch_amax_prologue(uint32_t *amax, int nslots, int x0_slot, const uint8_t *disp,
+                               const uint8_t *img, long long n, float scale0, hipStream_t s) {
+    const int nw = nslots * AMAX_SUB;
+    hipLaunchKernelGGL(k_amax_zero, dim3(cdiv(nw, 256)), dim3(256), 0, s, amax, nw);
+    SV_LAUNCH_CHECK("k_amax_zero");
+    const int blocks = (int)std::min<long long>((n + 255) / 256, 256);
+    hipLaunchKernelGGL(k_amax_x0, dim3(blocks), dim3(256), 0, s, amax + (size_t)x0_slot * AMAX_SUB, disp, img, n,
+                       scale0);
+    SV_LAUNCH_CHECK("k_amax_x0");
     return SV_OK;
 }
 

@@ -35,6 +35,7 @@ template <> struct Mfma<SV_BF16> {
     static constexpr int GS = 8;  // k values per lane per step
     typedef uint16_t T;
     typedef u16x8 vec;
+    typedef f32x4 acc;
     static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
                                                        __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
@@ -45,6 +46,7 @@ template <> struct Mfma<SV_F16> {
     static constexpr int GS = 8;
     typedef uint16_t T;
     typedef u16x8 vec;
+    typedef f32x4 acc;
     static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
@@ -57,6 +59,7 @@ template <> struct Mfma<SV_F32> {
     static constexpr int GS = 4;
     typedef float T;
     typedef f32x4 vec;
+    typedef f32x4 acc;
     static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
@@ -66,11 +69,37 @@ template <> struct Mfma<SV_F32> {
     }
 };
 
-// Converts GS FP32 values into one storage vector.
+// INT8: eight codes per lane per step, exact INT32 sums.
+template <> struct Mfma<SV_I8> {
+    static constexpr int GS = 8;
+    typedef int8_t T;
+    typedef i8x8 vec;
+    typedef i32x4 acc;
+    static __device__ __forceinline__ i32x4 run(vec a, vec b, i32x4 c) {
+        return __builtin_amdgcn_mfma_i32_16x16x32_i8(__builtin_bit_cast(long, a), __builtin_bit_cast(long, b), c,
+                                                     0, 0, 0);
+    }
+};
+
+// Storage dtype of a compute dtype's activations: INT8 layers keep BF16 maps.
+template <int DT> struct Store { static constexpr int v = DT; };
+template <> struct Store<SV_I8> { static constexpr int v = SV_BF16; };
+
+// INT8 code of an FP32 value for a tensor quantised with 127 / amax = qinv.
+__device__ __forceinline__ int8_t quant_i8(float v, float qinv) {
+    const float q = fminf(fmaxf(rintf(v * qinv), -127.0f), 127.0f);
+    return (int8_t)(int)q;
+}
+
+// Converts GS FP32 values into one LDS vector of the compute dtype (INT8:
+// quantised with qinv, ignored otherwise).
 template <int DT, int GS>
-__device__ __forceinline__ typename Mfma<DT>::vec pack_vec(const float (&v)[GS]) {
+__device__ __forceinline__ typename Mfma<DT>::vec pack_vec(const float (&v)[GS], float qinv) {
     typename Mfma<DT>::vec r;
-    if constexpr (DT == SV_BF16) {
+    if constexpr (DT == SV_I8) {
+#pragma unroll
+        for (int i = 0; i < GS; ++i) r[i] = quant_i8(v[i], qinv);
+    } else if constexpr (DT == SV_BF16) {
         // two values per v_cvt_pk_bf16_f32 (round to nearest even, as Elem::make)
         typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
         typedef float f32x2_t __attribute__((ext_vector_type(2)));
@@ -125,9 +154,11 @@ __device__ __forceinline__ void conv_bias4(const ConvParams &p, int nbase, float
     for (int i = 0; i < 4; ++i) b[i] = (p.bias && nbase + i < p.Cout) ? p.bias[nbase + i] : 0.f;
 }
 
-template <int DT>
-__device__ __forceinline__ void conv_epilogue(const ConvParams &p, size_t pix, int nbase,
-                                              const float (&acc)[4], const float (&bias)[4]) {
+// Returns max |stored value| over the channels it wrote (for amax_out).
+template <int DT0>
+__device__ __forceinline__ float conv_epilogue(const ConvParams &p, size_t pix, int nbase,
+                                               const float (&acc)[4], const float (&bias)[4]) {
+    constexpr int DT = Store<DT0>::v;
     using T = typename Elem<DT>::T;
     float r[4];
 #pragma unroll
@@ -146,6 +177,7 @@ __device__ __forceinline__ void conv_epilogue(const ConvParams &p, size_t pix, i
     }
     const size_t o = pix * p.out_pitch + p.out_coff + nbase;
     const bool full = nbase + 4 <= p.Cout;
+    float amax = 0.f;
     if (p.out_f32) {
         float *op = (float *)p.out + o;
         if (full && (o % 4) == 0) {
@@ -154,19 +186,49 @@ __device__ __forceinline__ void conv_epilogue(const ConvParams &p, size_t pix, i
             for (int i = 0; i < 4; ++i)
                 if (nbase + i < p.Cout) op[i] = r[i];
         }
+        for (int i = 0; i < 4; ++i)
+            if (nbase + i < p.Cout) amax = fmaxf(amax, fabsf(r[i]));
     } else {
         T *op = (T *)p.out + o;
+        T st[4];
+        for (int i = 0; i < 4; ++i) {
+            st[i] = Elem<DT>::make(r[i]);
+            if (nbase + i < p.Cout) amax = fmaxf(amax, fabsf(Elem<DT>::load(&st[i])));
+        }
         if (full && (o % 4) == 0 && DT != SV_F32) {
             u16x4 w4;
-            for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)Elem<DT>::make(r[i]);
+            for (int i = 0; i < 4; ++i) w4[i] = (uint16_t)st[i];
             *(u16x4 *)op = w4;
         } else if (full && (o % 4) == 0) {
             *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
         } else {
             for (int i = 0; i < 4; ++i)
-                if (nbase + i < p.Cout) op[i] = Elem<DT>::make(r[i]);
+                if (nbase + i < p.Cout) op[i] = st[i];
         }
     }
+    return amax;
+}
+
+// Adds one workgroup's output maximum to amax_out: a wave-wide max, then one
+// vector atomic per wave into the workgroup's slot.
+__device__ __forceinline__ void record_amax(const ConvParams &p, float m, int slot) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) atomicMax(p.amax_out + (slot & (AMAX_SUB - 1)), __float_as_uint(m));
+}
+
+// The input scale of an INT8 layer: m = the largest recorded amax of its
+// sources; qinv = 127 / m and s_in = m / 127 (both 0 when m = 0).  Lane j
+// reads word j of each source's slots, then a wave-wide max.
+__device__ __forceinline__ void input_scale(const ConvParams &p, float &qinv, float &s_in) {
+    const int lane = threadIdx.x & 63;
+    float m = 0.f;
+    for (int k = 0; k < 2; ++k)
+        if (p.amax_in[k]) m = fmaxf(m, __uint_as_float(p.amax_in[k][lane]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    qinv = m > 0.f ? 127.0f / m : 0.f;
+    s_in = m / 127.0f;
 }
 
 // The range [c_begin, c_end) of input channels that reduction part kz of
@@ -271,17 +333,31 @@ struct ConvTile {
         const int g = lane >> 4, r16 = lane & 15;
         const int C0 = p.src[0].C;
 
-        f32x4 acc[MBW][NBW];
+        typename M::acc acc[MBW][NBW];
 #pragma unroll
         for (int i = 0; i < MBW; ++i)
 #pragma unroll
-            for (int j = 0; j < NBW; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int j = 0; j < NBW; ++j) acc[i][j] = typename M::acc{0, 0, 0, 0};
 
         // the bias of this lane's output channels, loaded ahead of the main loop
         float bpre[NBW][4];
 #pragma unroll
         for (int nb = 0; nb < NBW; ++nb)
             conv_bias4<DT>(p, n0 + (wn * NBW + nb) * 16 + 4 * g, bpre[nb]);
+        // INT8: the input's quantisation step and, per output channel, the
+        // factor s_in * s_w that turns an integer sum into the FP32 value
+        float qinv = 0.f, spre[NBW][4];
+        if constexpr (DT == SV_I8) {
+            float s_in;
+            input_scale(p, qinv, s_in);
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int n = n0 + (wn * NBW + nb) * 16 + 4 * g + i;
+                    spre[nb][i] = n < p.Cout ? s_in * p.wscale[n] : 0.f;
+                }
+        }
 
         __syncthreads();  // the previous tile of a persistent loop is done with LDS
         pix_table(p, G, sm);
@@ -304,7 +380,7 @@ struct ConvTile {
                 const ConvSrc &s = si ? p.src[1] : p.src[0];
                 const int kind = c < p.Cin ? s.kind : SRC_NONE;
                 const int cl = c - (si ? C0 : 0);
-                const int sdt = s.sdt ? s.sdt - 1 : DT;
+                const int sdt = s.sdt ? s.sdt - 1 : Store<DT>::v;
                 const size_t cb = (size_t)s.coff + cl;
                 const PixSrc *tabp = sm.ps[si];
                 const T *sp = (const T *)s.ptr;
@@ -393,7 +469,7 @@ struct ConvTile {
                                 const float bot = (1.f - rq[j].lx) * x10 + rq[j].lx * x11;
                                 v[i] = rok[j] ? (1.f - rq[j].ly) * top + rq[j].ly * bot : 0.f;
                             }
-                            *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
+                            *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v, qinv);
                         }
                     }
                     if (gi < NGT && fast_plain) {
@@ -455,7 +531,7 @@ struct ConvTile {
                             v[0] = sx.scale0 * (float)dv[k];
                             v[1] = (float)iv[k] * (1.0f / 256.0f);
                         }
-                        *(vec *)&patch[pix * KCP] = pack_vec<DT, GS>(v);
+                        *(vec *)&patch[pix * KCP] = pack_vec<DT, GS>(v, qinv);
                     }
                 } else if (!fast_resize && !fast_plain && kind != SRC_NONE) {
 #pragma unroll
@@ -485,7 +561,7 @@ struct ConvTile {
                                 v[1] = (float)s.img[q.p[0]] * (1.0f / 256.0f);
                             }
                         }
-                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v);
+                        *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v, qinv);
                     }
                 }
             }
@@ -535,6 +611,7 @@ struct ConvTile {
 
         // ---- epilogue: the FP32 partial of this channel range, or bias,
         // activation, backward terms and the NHWC store ------------------------
+        float lmax = 0.f;
 #pragma unroll
         for (int mb = 0; mb < MBW; ++mb) {
             const int oy = oy0 + wm * MBW + mb, ox = ox0 + r16;
@@ -543,17 +620,26 @@ struct ConvTile {
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
                 const int nbase = n0 + (wn * NBW + nb) * 16 + 4 * g;
+                f32x4 av;
+                if constexpr (DT == SV_I8) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) av[i] = (float)acc[mb][nb][i] * spre[nb][i];
+                } else {
+                    av = acc[mb][nb];
+                }
                 if (p.ksplit > 1) {
                     // n_pad is a multiple of 16: the four channels are all in or all out
+                    // (INT8 layers never split)
                     if (nbase < p.n_pad)
-                        *(f32x4 *)&p.part[((size_t)kz * p.B * G.Ho * G.Wo + pix) * p.n_pad + nbase] =
-                            acc[mb][nb];
+                        *(f32x4 *)&p.part[((size_t)kz * p.B * G.Ho * G.Wo + pix) * p.n_pad + nbase] = av;
                 } else {
-                    const float r[4] = {acc[mb][nb][0], acc[mb][nb][1], acc[mb][nb][2], acc[mb][nb][3]};
-                    conv_epilogue<DT>(p, pix, nbase, r, bpre[nb]);
+                    const float r[4] = {av[0], av[1], av[2], av[3]};
+                    lmax = fmaxf(lmax, conv_epilogue<DT>(p, pix, nbase, r, bpre[nb]));
                 }
             }
         }
+        if (p.amax_out && p.ksplit <= 1)
+            record_amax(p, lmax, (int)(blockIdx.x * 7u + blockIdx.y * 13u + blockIdx.z));
     }
 };
 
@@ -635,6 +721,7 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
 {
     const int ng = p.n_pad / 4;
     const size_t total = (size_t)npix * ng;
+    float lmax = 0.f;
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const size_t pix = e / ng;
@@ -648,8 +735,9 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
         const float r[4] = {s[0], s[1], s[2], s[3]};
         float b[4];
         conv_bias4<DT>(p, nbase, b);
-        conv_epilogue<DT>(p, pix, nbase, r, b);
+        lmax = fmaxf(lmax, conv_epilogue<DT>(p, pix, nbase, r, b));
     }
+    if (p.amax_out) record_amax(p, lmax, (int)blockIdx.x);
 }
 
 // grid <= 0: uniform launch (split over p.ksplit channel ranges when p.ksplit > 1);

@@ -113,7 +113,16 @@ struct ConvParams {
     float *part;
     size_t part_bytes;
     int ksplit;
+    // INT8 layers: per-row weight scales, and the per-tensor maxima of the
+    // sources (amax_in, AMAX_SUB words each: max |value| as FP32 bits, NULL =
+    // no source) from which the input scale is formed; any layer with amax_out
+    // set records the max |stored value| of its output there (one word of
+    // AMAX_SUB per workgroup slot, combined by the reader)
+    const float *wscale;
+    const uint32_t *amax_in[2];
+    uint32_t *amax_out;
 };
+constexpr int AMAX_SUB = 64;
 
 // cfg selects the tile shape and the reduction split (see conv.hip); ks = 1, 3
 // or 5, stride = 1 or 2 (ks = 1: stride 1 only).
@@ -141,6 +150,14 @@ const char *conv_cfg_name(int cfg);
 // output channels, kernel flipped.
 sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad,
                       int mode, void *dst, hipStream_t s);
+// INT8 forward packing: codes [taps][n_pad][cin_pad] and the per-row scales
+// (FP32 [n_pad], 0 past Cout)
+sv_status launch_pack_i8(const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad, int8_t *dst,
+                         float *scale, hipStream_t s);
+// INT8 pass prologue: zero nslots * AMAX_SUB words, then record the amax of
+// x0 = [scale0 * d, img / 256] over n coarse pixels in slot x0_slot
+sv_status launch_amax_prologue(uint32_t *amax, int nslots, int x0_slot, const uint8_t *disp,
+                               const uint8_t *img, long long n, float scale0, hipStream_t s);
 
 // storage dtype code of a source (see ConvSrc::sdt)
 constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F16 = 1 + SV_F16;

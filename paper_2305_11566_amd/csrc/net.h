@@ -15,6 +15,7 @@ struct NetShape {
     LayerSpec ly[NLAYERS];
     int n_pad[NLAYERS], cin_pad[NLAYERS];
     size_t w_off[NLAYERS], b_off[NLAYERS], packed_bytes;
+    size_t s_off[NLAYERS];  // INT8: per-row weight scales (FP32 [n_pad]); 0 otherwise
     // adjoint weights (rows = the layer's inputs, columns = its outputs, kernel
     // flipped) for the layers whose input gradient is needed
     int bn_pad[NLAYERS], bcin_pad[NLAYERS];
@@ -36,7 +37,7 @@ Levels net_levels(const NetShape &ns, int H, int W);
 // beyond the recomputed encoder; at inference it lives inside the workspace.
 struct ActLayout {
     // workspace
-    size_t E1, E2, E3, part, part_bytes, ws_fwd;
+    size_t E1, E2, E3, part, part_bytes, amax, ws_fwd;
     // saved (offsets within the saved region)
     size_t disp, img, ML, Z, G3, G2, G1, G0, saved;
 };
@@ -44,6 +45,9 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B);
 
 // Extra workspace of the backward pass (after the forward's workspace part).
 size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B);
+
+// INT8 passes: amax slots (AMAX_SUB words each) of the maps a layer reads
+enum AmaxSlot { AM_E1 = 0, AM_E2, AM_E3, AM_ML, AM_G3, AM_G2, AM_G1, AM_G0, AM_X0, AM_NSLOTS };
 
 // Tile configuration per layer (index into the conv kernel's table); the
 // defaults may be replaced by the autotuner.

@@ -17,7 +17,8 @@ sv_status net_shape(const sv_vae_desc *d, NetShape &ns) {
     for (int c : cs)
         if (c < 8 || c > 256 || c % 8) return SV_ERR_RANGE;
     if (d->factor < 1 || d->factor > 8) return SV_ERR_RANGE;
-    if (d->dtype != SV_F32 && d->dtype != SV_BF16 && d->dtype != SV_F16) return SV_ERR_DTYPE;
+    if (d->dtype != SV_F32 && d->dtype != SV_BF16 && d->dtype != SV_F16 && d->dtype != SV_I8)
+        return SV_ERR_DTYPE;
     ns.c1 = d->c1; ns.c2 = d->c2; ns.c3 = d->c3; ns.L = d->latent; ns.f = d->factor;
     ns.dtype = d->dtype;
     ns.es = dtype_bytes(d->dtype);
@@ -39,16 +40,22 @@ sv_status net_shape(const sv_vae_desc *d, NetShape &ns) {
         const int taps = (i == L_F) ? 1 : t[i].k * t[i].k;
         // the final projection stays FP32 in every mode: rounding its few weights
         // dominates the reduced-precision error of the refined map
-        const int les = (i == L_F) ? 4 : ns.es;
+        const bool i8 = ns.dtype == SV_I8 && i != L_F;
+        const int les = (i == L_F) ? 4 : (i8 ? 1 : ns.es);
         ns.w_off[i] = off;
         off = align256(off + (size_t)taps * ns.n_pad[i] * ns.cin_pad[i] * les);
         ns.b_off[i] = off;
         off = align256(off + (size_t)t[i].cout * sizeof(float));
+        ns.s_off[i] = 0;
+        if (i8) {
+            ns.s_off[i] = off;
+            off = align256(off + (size_t)ns.n_pad[i] * sizeof(float));
+        }
     }
     for (int i = 0; i < NLAYERS; ++i) {
         ns.bw_off[i] = 0;
         ns.bn_pad[i] = ns.bcin_pad[i] = 0;
-        if (i == L_E1 || i == L_F) continue;
+        if (i == L_E1 || i == L_F || ns.dtype == SV_I8) continue;  // INT8: inference only
         ns.bn_pad[i] = rup(t[i].cin, 16);
         ns.bcin_pad[i] = rup(t[i].cout, 8);
         ns.bw_off[i] = off;
@@ -82,6 +89,7 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
         part = std::max(part, (size_t)CONV_MAX_SPLIT * px(out_level[i]) * ns.n_pad[i] * sizeof(float));
     a.part_bytes = std::min(part, CONV_PART_CAP);
     a.part = o; o = align256(o + a.part_bytes);
+    a.amax = o; o = align256(o + (size_t)AM_NSLOTS * AMAX_SUB * sizeof(uint32_t));
     a.ws_fwd = o;
     o = 0;
     a.disp = o; o = align256(o + px(0));
@@ -98,7 +106,7 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
 
 // ---- tile configuration per layer ----------------------------------------------
 // per compute dtype and layer; -1 = default
-static std::atomic<int> g_cfg_override[3][NLAYERS];
+static std::atomic<int> g_cfg_override[4][NLAYERS];
 static struct CfgInit {
     CfgInit() {
         for (auto &d : g_cfg_override)
@@ -107,10 +115,10 @@ static struct CfgInit {
 } g_cfg_init;
 
 void net_set_cfg_override(int dtype, int layer, int cfg) {
-    if (dtype >= 0 && dtype < 3 && layer >= 0 && layer < NLAYERS) g_cfg_override[dtype][layer].store(cfg);
+    if (dtype >= 0 && dtype < 4 && layer >= 0 && layer < NLAYERS) g_cfg_override[dtype][layer].store(cfg);
 }
 int net_get_cfg_override(int dtype, int layer) {
-    return (dtype >= 0 && dtype < 3 && layer >= 0 && layer < NLAYERS) ? g_cfg_override[dtype][layer].load()
+    return (dtype >= 0 && dtype < 4 && layer >= 0 && layer < NLAYERS) ? g_cfg_override[dtype][layer].load()
                                                                        : -1;
 }
 
@@ -167,11 +175,20 @@ static ConvSrc src_x0(const uint8_t *disp, const uint8_t *img, int hs, int ws, i
     return s;
 }
 
+// INT8 passes: the amax slots of the layer's sources and output
+struct LayerAmax { const uint32_t *in0, *in1; uint32_t *out; };
+
 static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
                            int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
                            int out_f32, int act, int cfg, float *part, size_t part_bytes,
-                           hipStream_t st) {
+                           LayerAmax am, hipStream_t st) {
     ConvParams p{};
+    if (ns.dtype == SV_I8 && li != L_F) {
+        p.wscale = (const float *)((const char *)packed + ns.s_off[li]);
+        p.amax_in[0] = am.in0;
+        p.amax_in[1] = am.in1;
+    }
+    p.amax_out = am.out;
     p.part = part;
     p.part_bytes = part_bytes;
     p.src[0] = s0; p.src[1] = s1;
@@ -230,22 +247,32 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
         SV_HIP(hipMemcpyAsync(sv_ + a.img, img, n0, hipMemcpyDeviceToDevice, st));
     }
     const ConvSrc x0 = src_x0(disp, img, lv.h[0], lv.w[0], ns.f);
+    // INT8: per-tensor amax slots, cleared, and x0's recorded, before the layers
+    const bool q8 = ns.dtype == SV_I8;
+    uint32_t *AM = q8 ? (uint32_t *)(w + a.amax) : nullptr;
+    auto am = [&](int i0, int i1, int o) {
+        auto slot = [&](int k) -> uint32_t * { return (AM && k >= 0) ? AM + (size_t)k * AMAX_SUB : nullptr; };
+        return LayerAmax{slot(i0), slot(i1), slot(o)};
+    };
+    if (q8)
+        SV_TRY(launch_amax_prologue(AM, AM_NSLOTS, AM_X0, disp, img, (long long)B * lv.h[0] * lv.w[0],
+                                    (float)ns.f / 256.0f, st));
     // encoder
     ev_rec(0, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, st));
+    SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
-                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, st));
+                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2), st));
     ev_rec(1, 1, st);
     ev_rec(2, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
-                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, st));
+                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, am(AM_E2, -1, AM_E3), st));
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     ev_rec(3, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
-                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, st));
+                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, am(AM_E3, -1, AM_ML), st));
     ev_rec(3, 1, st);
     ConvSrc zsrc;
     if (eps) {
@@ -258,27 +285,27 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     }
     // decoder
     ev_rec(5, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, st));
+    SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, am(AM_ML, -1, AM_G3), st));
     ev_rec(5, 1, st);
     ev_rec(6, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
-                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, st));
+                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, am(AM_G3, AM_E2, AM_G2), st));
     ev_rec(6, 1, st);
     ev_rec(7, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
-                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, st));
+                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, am(AM_G2, AM_E1, AM_G1), st));
     ev_rec(7, 1, st);
     ev_rec(8, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, st));
+                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, am(AM_G1, AM_X0, -1), st));
     ev_rec(8, 1, st);
     // final layer: per-tap projections of [G0, x0] and the gather, one kernel
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);
     if (only < 0)
-        SV_TRY(launch_final(ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
+        SV_TRY(launch_final(q8 ? SV_BF16 : ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
                         ns.cin_pad[L_F], ns.f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
     ev_rec(10, 1, st);
     if (train && ml_user)
@@ -291,8 +318,13 @@ sv_status net_pack(const NetShape &ns, const float *params, void *packed, hipStr
     for (int i = 0; i < NLAYERS; ++i) {
         const LayerSpec &l = ns.ly[i];
         const float *w = params + ns.p_off[i];
-        SV_TRY(launch_pack(i == L_F ? SV_F32 : ns.dtype, w, l.cout, l.cin, l.k, ns.n_pad[i],
-                           ns.cin_pad[i], i == L_F ? 1 : 0, (char *)packed + ns.w_off[i], st));
+        if (ns.dtype == SV_I8 && i != L_F)
+            SV_TRY(launch_pack_i8(w, l.cout, l.cin, l.k, ns.n_pad[i], ns.cin_pad[i],
+                                  (int8_t *)((char *)packed + ns.w_off[i]),
+                                  (float *)((char *)packed + ns.s_off[i]), st));
+        else
+            SV_TRY(launch_pack(i == L_F ? SV_F32 : ns.dtype, w, l.cout, l.cin, l.k, ns.n_pad[i],
+                               ns.cin_pad[i], i == L_F ? 1 : 0, (char *)packed + ns.w_off[i], st));
         if (ns.bw_off[i])
             SV_TRY(launch_pack(ns.dtype, w, l.cout, l.cin, l.k, ns.bn_pad[i], ns.bcin_pad[i], 2,
                                (char *)packed + ns.bw_off[i], st));

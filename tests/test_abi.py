@@ -107,6 +107,25 @@ def test_vae_validation():
     assert l.sv_vae_workspace_bytes(ctypes.byref(d), 0, 128, 256) == 0
 
 
+def test_int8_is_inference_only():
+    l = lib()
+    d = make_desc(16, 32, 64, 64, 2, "i8")
+    d16 = make_desc(16, 32, 64, 64, 2, "bf16")
+    assert l.sv_vae_param_count(ctypes.byref(d)) == 73299
+    assert 0 < l.sv_vae_packed_bytes(ctypes.byref(d)) < l.sv_vae_packed_bytes(ctypes.byref(d16))
+    ws = l.sv_vae_workspace_bytes(ctypes.byref(d), 1, 128, 256)
+    assert ws > 0
+    A = ctypes.c_void_p(0x100000)
+    # eps / saved (training) -> unsupported; backward -> unsupported
+    assert l.sv_vae_forward(ctypes.byref(d), A, P, P, 1, 128, 256, P, P, None, A, A, ws, None) == -6
+    assert l.sv_vae_forward(ctypes.byref(d), A, P, P, 1, 128, 256, None, P, None, A, A, ws, None) == -6
+    assert l.sv_vae_backward(ctypes.byref(d), A, A, 1, 128, 256, None, P, None, ctypes.c_float(0.0),
+                             P, A, ws, None) == -6
+    plan = ctypes.c_void_p()
+    assert l.sv_batch_plan_create(ctypes.byref(d), 4, 128, 256, 16, 5, 5, ctypes.byref(plan)) == -6
+    assert l.sv_autotune(ctypes.byref(d), 1, 128, 256, 16, 5, 5) == -6
+
+
 def test_tvae_counts_and_sizes():
     from oracle import tvae
     assert lib().sv_tvae_param_count() == tvae.n_params() == 162380
