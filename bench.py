@@ -362,7 +362,7 @@ def run_table1(sv, torch, dev, K, Wm):
             del net
     out["gflop_per_frame"] = round(table1_flops(1) / 1e9, 4)
     return out
-def run_int8(sv, torch, dev, flat, K, Wm):
+def run_int8(sv, torch, dev, flat, K, Wm, tune=True):
     """Census + WTA + the INT8 network (per-channel weight scales, dynamic
     per-tensor activation scales) on the 1242x375 pairs, graph replayed at
     batch 1 and 64, and its end-point error against the FP32 network on the
@@ -373,6 +373,8 @@ def run_int8(sv, torch, dev, flat, K, Wm):
         k = K if B == 1 else max(5, min(K, 20))
         res = {}
         for dt in ("i8", "f32"):
+            if tune:
+                sv.sv_autotune(C1, C2, C3, LAT, F, dt, B, H, W, D, WIN_W, WIN_H)
             p = Path(B, dt, flat, left, right)
             p.capture()
             ms = p.timed(k, Wm)
@@ -513,7 +515,7 @@ def main():
     if args.section:
         fn = {"sgm": lambda: run_sgm(sv, torch, dev, flat, K, Wm),
               "table1": lambda: run_table1(sv, torch, dev, K, Wm),
-              "int8": lambda: run_int8(sv, torch, dev, flat, K, Wm)}[args.section]
+              "int8": lambda: run_int8(sv, torch, dev, flat, K, Wm, not args.no_autotune)}[args.section]
         print(json.dumps({"section": args.section, "steps": K, "warmup": Wm, "result": fn()}))
         return
     left, right, gt = make_inputs(args.batch, dev)
@@ -630,7 +632,7 @@ def main():
     if not args.no_extras:
         extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
         extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm)
-        extras["int8_network_1242x375"] = run_int8(sv, torch, dev, flat, K, Wm)
+        extras["int8_network_1242x375"] = run_int8(sv, torch, dev, flat, K, Wm, not args.no_autotune)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()
 

@@ -472,7 +472,6 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     NetShape ns;
     sv_status r = net_shape(desc, ns);
     if (r != SV_OK) return r;
-    if (ns.dtype == SV_I8) return SV_ERR_UNSUPPORTED;  // INT8: sv_vae_forward only
     if (B < 1 || H < 1 || W < 1 || H > 16384 || W > 16384) return SV_ERR_SHAPE;
     if (D < 1 || D > 256) return SV_ERR_RANGE;
     const size_t ws = sv_vae_workspace_bytes(desc, B, H, W);

@@ -258,6 +258,10 @@ struct ConvTile {
     using T = typename M::T;
     using vec = typename M::vec;
     static constexpr int GS = M::GS;
+    // storage of the maps this layer reads in its own dtype, and a vector of GS of them
+    static constexpr int SD = Store<DT>::v;
+    using ST = typename Elem<SD>::T;
+    using SVec = typename Mfma<SD>::vec;
     static constexpr int TW = 16;
     static constexpr int TAPS = KS * KS;
     static constexpr int PAD = (KS - 1) / 2;
@@ -383,7 +387,7 @@ struct ConvTile {
                 const int sdt = s.sdt ? s.sdt - 1 : Store<DT>::v;
                 const size_t cb = (size_t)s.coff + cl;
                 const PixSrc *tabp = sm.ps[si];
-                const T *sp = (const T *)s.ptr;
+                const ST *sp = (const ST *)s.ptr;
                 constexpr int PSTEP = 256 / KCG;                // pixels between a thread's elements
                 constexpr int NE = (NPIX + PSTEP - 1) / PSTEP;  // patch elements per thread
                 constexpr int GR = 4;                           // resized elements (4 corners each) per step
@@ -403,12 +407,14 @@ struct ConvTile {
                 const bool x0_only = c0 + GS >= p.Cin &&
                                      ((c0 == 0 && p.src[0].kind == SRC_X0) ||
                                       (c0 == C0 && p.src[1].kind == SRC_X0));
-                const bool fast_resize = kind == SRC_RESIZE && sdt == DT && !x0_only;
-                const bool fast_plain = (kind == SRC_TENSOR || kind == SRC_ZINS) && sdt == DT && !x0_only;
+                // grouped fast paths for sources stored in the layer's storage dtype
+                // (INT8 layers: BF16 maps, quantised while staging)
+                const bool fast_resize = kind == SRC_RESIZE && sdt == SD && !x0_only;
+                const bool fast_plain = (kind == SRC_TENSOR || kind == SRC_ZINS) && sdt == SD && !x0_only;
 #pragma unroll
                 for (int gi = 0; gi < NG; ++gi) {
                     // -- issue
-                    vec ra[GR][4];
+                    SVec ra[GR][4];
                     PixSrc rq[GR];
                     bool rok[GR];
                     if (gi < NGR && fast_resize) {
@@ -421,10 +427,10 @@ struct ConvTile {
                             rok[j] = in && rq[j].p[0] >= 0;
 #pragma unroll
                             for (int r = 0; r < 4; ++r)
-                                ra[j][r] = *(const vec *)(sp + (size_t)(rok[j] ? rq[j].p[r] : 0) * s.pitch + cb);
+                                ra[j][r] = *(const SVec *)(sp + (size_t)(rok[j] ? rq[j].p[r] : 0) * s.pitch + cb);
                         }
                     }
-                    vec ta[GT];
+                    SVec ta[GT];
                     bool tok[GT];
                     if (gi < NGT && fast_plain) {
 #pragma unroll
@@ -434,7 +440,7 @@ struct ConvTile {
                             const bool in = k < NE && pix < NPIX;
                             const int pi = tabp[in ? pix : 0].p[0];
                             tok[j] = in && pi >= 0;
-                            ta[j] = *(const vec *)(sp + (size_t)(tok[j] ? pi : 0) * s.pitch + cb);
+                            ta[j] = *(const SVec *)(sp + (size_t)(tok[j] ? pi : 0) * s.pitch + cb);
                         }
                     }
                     vec wv[GW];
@@ -461,10 +467,10 @@ struct ConvTile {
                             float v[GS];
 #pragma unroll
                             for (int i = 0; i < GS; ++i) {
-                                const float x00 = Elem<DT>::load((const T *)&ra[j][0] + i);
-                                const float x01 = Elem<DT>::load((const T *)&ra[j][1] + i);
-                                const float x10 = Elem<DT>::load((const T *)&ra[j][2] + i);
-                                const float x11 = Elem<DT>::load((const T *)&ra[j][3] + i);
+                                const float x00 = Elem<SD>::load((const ST *)&ra[j][0] + i);
+                                const float x01 = Elem<SD>::load((const ST *)&ra[j][1] + i);
+                                const float x10 = Elem<SD>::load((const ST *)&ra[j][2] + i);
+                                const float x11 = Elem<SD>::load((const ST *)&ra[j][3] + i);
                                 const float top = (1.f - rq[j].lx) * x00 + rq[j].lx * x01;
                                 const float bot = (1.f - rq[j].lx) * x10 + rq[j].lx * x11;
                                 v[i] = rok[j] ? (1.f - rq[j].ly) * top + rq[j].ly * bot : 0.f;
@@ -478,12 +484,20 @@ struct ConvTile {
                             const int k = gi * GT + j;
                             const int pix = pix0 + k * PSTEP;
                             if (k >= NE || pix >= NPIX) continue;
-                            vec o = ta[j];
-                            if (!tok[j]) {
+                            if constexpr (SD != DT) {
+                                float v[GS];
 #pragma unroll
-                                for (int i = 0; i < GS; ++i) o[i] = 0;
+                                for (int i = 0; i < GS; ++i)
+                                    v[i] = tok[j] ? Elem<SD>::load((const ST *)&ta[j] + i) : 0.f;
+                                *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v, qinv);
+                            } else {
+                                vec o = ta[j];
+                                if (!tok[j]) {
+#pragma unroll
+                                    for (int i = 0; i < GS; ++i) o[i] = 0;
+                                }
+                                *(vec *)&patch[pix * KCP + cg * GS] = o;
                             }
-                            *(vec *)&patch[pix * KCP + cg * GS] = o;
                         }
                     }
                     if (gi < NGW) {

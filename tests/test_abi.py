@@ -123,7 +123,6 @@ def test_int8_is_inference_only():
                              P, A, ws, None) == -6
     plan = ctypes.c_void_p()
     assert l.sv_batch_plan_create(ctypes.byref(d), 4, 128, 256, 16, 5, 5, ctypes.byref(plan)) == -6
-    assert l.sv_autotune(ctypes.byref(d), 1, 128, 256, 16, 5, 5) == -6
 
 
 def test_tvae_counts_and_sizes():
