@@ -304,7 +304,7 @@ TABLE1_SHAPES = [(32, 1, 5), (32, 1, 5), (16, 64, 5), (8, 16, 5), (32, 24, 5), (
                  (32, 1, 1), (16, 80, 5), (16, 96, 5), (8, 40, 5), (16, 48, 5), (1, 81, 5)]
 
 
-def run_table1(sv, torch, dev, K, Wm):
+def run_table1(sv, torch, dev, K, Wm, tune=True):
     """Census + WTA + the Table I network on the 1242x375 pairs, graph
     replayed, FP32 and BF16 at batch 1 and 64 (He-init weights, seed 7013),
     and the network alone with its MFMA-peak fraction."""
@@ -339,6 +339,8 @@ def run_table1(sv, torch, dev, K, Wm):
         res = torch.empty((B, H, W), dtype=torch.float32, device=dev)
         k = K if B == 1 else max(5, min(K, 20))
         for dt in ("f32", "bf16"):
+            if tune:
+                sv.sv_tvae_autotune(dt, F, B, H, W)
             net = sv.TableVAE(F, dt)
             net.pack(flat)
             net.workspace(B, H, W)
@@ -356,6 +358,7 @@ def run_table1(sv, torch, dev, K, Wm):
             ms_n = graph_ms(net_only, k)
             tf = table1_flops(B) / (ms_n * 1e-3) / 1e12
             out[f"{dt}_batch_{B}"] = {
+                "layer_cfgs": sv.sv_tvae_layer_cfgs(dt, F, B, H, W),
                 "path_ms": round(ms_p, 4), "frames_per_s": round(B * 1e3 / ms_p, 1),
                 "network_ms": round(ms_n, 4), "network_TFLOPs": round(tf, 3),
                 "network_mfma_frac": round(tf / PEAK["mfma_TFLOPs"][dt], 4)}
@@ -514,7 +517,7 @@ def main():
     _, flat = make_params()
     if args.section:
         fn = {"sgm": lambda: run_sgm(sv, torch, dev, flat, K, Wm),
-              "table1": lambda: run_table1(sv, torch, dev, K, Wm),
+              "table1": lambda: run_table1(sv, torch, dev, K, Wm, not args.no_autotune),
               "int8": lambda: run_int8(sv, torch, dev, flat, K, Wm, not args.no_autotune)}[args.section]
         print(json.dumps({"section": args.section, "steps": K, "warmup": Wm, "result": fn()}))
         return
@@ -631,7 +634,7 @@ def main():
     extras = {} if args.no_extras else run_extras(sv, torch, dev, flat, K, Wm)
     if not args.no_extras:
         extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
-        extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm)
+        extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm, not args.no_autotune)
         extras["int8_network_1242x375"] = run_int8(sv, torch, dev, flat, K, Wm, not args.no_autotune)
 
     cpu = None if args.no_cpu_baseline else cpu_baseline()

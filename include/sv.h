@@ -484,6 +484,18 @@ sv_status sv_tvae_loss(const float *out, const float *gt, const uint8_t *noc, co
 sv_status sv_tvae_set_layer_cfg(int layer, int cfg);
 int sv_tvae_num_layers(void);
 
+/* Times every tile configuration of each launched layer of sv_tvae_forward
+ * alone for this shape (zero weights and inputs; timing does not depend on
+ * values), keeps the fastest per layer if the whole pass then runs faster
+ * than with the defaults, and uses them for later calls with exactly this
+ * (dtype, factor, B, H, W) in this process.  Allocates and frees its own
+ * device memory and synchronises the null stream.  Results do not depend on
+ * the tile shape (a split changes the FP32 summation order only).
+ * Errors: SV_ERR_DTYPE, SV_ERR_RANGE, SV_ERR_SHAPE, SV_ERR_HIP. */
+sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W);
+/* The configuration each launched layer uses for this shape (host int [12]). */
+sv_status sv_tvae_layer_cfgs(int dtype, int factor, int B, int H, int W, int *cfg_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -92,6 +92,8 @@ _SIGS = {
     "sv_tvae_loss": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "sv_tvae_set_layer_cfg": (ctypes.c_int32, [_I, _I]),
     "sv_tvae_num_layers": (_I, []),
+    "sv_tvae_autotune": (ctypes.c_int32, [_I, _I, _I, _I, _I]),
+    "sv_tvae_layer_cfgs": (ctypes.c_int32, [_I, _I, _I, _I, _I, ctypes.POINTER(ctypes.c_int)]),
 }
 
 

@@ -18,7 +18,11 @@
 // map and X_0 onto its 25 taps (MFMA), then a gather that adds, for each
 // full-resolution pixel, the taps that land on it.
 #include <algorithm>
+#include <array>
 #include <atomic>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "kernels.h"
 
@@ -139,18 +143,39 @@ struct TvCfgInit {
     TvCfgInit() { for (auto &v : g_tv_cfg) v.store(-1); }
 } g_tv_cfg_init;
 
-// Tile th4_tn16 / th4_tn32 by output width; grids of fewer than 256
+// Configurations sv_tvae_autotune chose, per (dtype, factor, B, H, W), for
+// this process.
+std::mutex g_tv_mu;
+std::map<std::tuple<int, int, int, int, int>, std::array<int, T_NL>> g_tv_tuned;
+
+// Default: tile th4_tn16 / th4_tn32 by output width; grids of fewer than 256
 // workgroups (the coarse levels of small batches) split the reduction over
 // up to four channel ranges so that more CUs take part.
-int tv_default_cfg(int layer, int B, int Ho, int Wo) {
-    const int ov = g_tv_cfg[layer].load();
-    if (ov >= 0 && ov < conv_num_cfgs()) return ov;
+int tv_heuristic_cfg(int layer, int B, int Ho, int Wo) {
     const int tn = kLayers[layer].cout <= 16 ? 16 : 32;
     const int tile = tn == 16 ? 5 /* th4_tn16 */ : 2 /* th4_tn32 */;
     const long long nwg = (long long)cdiv(Wo, 16) * cdiv(Ho, 4) * B * cdiv(kLayers[layer].cout, tn);
     int split = 1;
     while (split < CONV_MAX_SPLIT && nwg * split < 256) ++split;
     return tile + conv_num_tiles() * (split - 1);
+}
+
+// Per launched layer: an explicit override, else the tuned choice for this
+// shape, else the heuristic.
+void tv_layer_cfgs(int dtype, int f, int B, int H, int W, int *cfg) {
+    const TvLevels lv = tv_levels(f, H, W);
+    std::array<int, T_NL> tuned{};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> g(g_tv_mu);
+        auto it = g_tv_tuned.find(std::make_tuple(dtype, f, B, H, W));
+        if (it != g_tv_tuned.end()) { tuned = it->second; have = true; }
+    }
+    for (int i = 0; i < T_NL; ++i) {
+        const int ov = g_tv_cfg[i].load();
+        const int k = kOutLevel[i];
+        cfg[i] = (ov >= 0 && ov < conv_num_cfgs()) ? ov : (have ? tuned[i] : tv_heuristic_cfg(i, B, lv.h[k], lv.w[k]));
+    }
 }
 
 // ---- packing ------------------------------------------------------------------------
@@ -304,9 +329,12 @@ ConvSrc tsrc(const void *p, int C, int pitch, int coff, int hs, int ws, int kind
     return s;
 }
 
+// One launched layer with configuration cfg[li]; with only >= 0 every other
+// layer is skipped (the autotuner times one layer at a time).
 sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, ConvSrc s1, int B, int Hi,
                    int Wi, int Ho, int Wo, void *out, int out_pitch, int out_coff, int out_f32, int act,
-                   float *part, size_t part_bytes, hipStream_t st) {
+                   float *part, size_t part_bytes, const int *cfg, int only, hipStream_t st) {
+    if (only >= 0 && only != li) return SV_OK;
     ConvParams p{};
     p.part = part;
     p.part_bytes = part_bytes;
@@ -321,12 +349,14 @@ sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, Con
     p.out = out; p.out_pitch = out_pitch; p.out_coff = out_coff;
     p.act = act; p.out_f32 = out_f32;
     const int dt = li == T_YP ? SV_F32 : s.dtype;
-    return launch_conv(dt, kLayers[li].k, kLayers[li].stride, tv_default_cfg(li, B, Ho, Wo), p, st);
+    return launch_conv(dt, kLayers[li].k, kLayers[li].stride, cfg[li], p, st);
 }
 
 sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t *disp, const uint8_t *img,
                      int B, int H, int W, const float *eps, float *out, float *ml_user, void *ws,
-                     hipStream_t st) {
+                     hipStream_t st, int only = -1) {
+    int cfg[T_NL];
+    tv_layer_cfgs(s.dtype, f, B, H, W, cfg);
     const TvLevels lv = tv_levels(f, H, W);
     const TvAct a = tv_act(s.es, lv, B);
     char *w = (char *)ws;
@@ -340,21 +370,21 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     x0.ptr = disp; x0.img = img; x0.kind = SRC_X0; x0.C = 2; x0.hs = h1; x0.ws = w1;
     x0.scale0 = (float)f / 256.0f;
     // feature extraction: [FE_1 | FE_2] into level 1, channels 16..79
-    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, part, a.part_bytes, st));
+    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, part, a.part_bytes, cfg, only, st));
     // encoder
     SV_TRY_STATUS(tv_layer(s, packed, T_EN1, tsrc(L1, 64, L1C, 16, h1, w1, SRC_TENSOR, 0), none, B, h1, w1, h2, w2,
-                           L2, L2C, 16, 0, 1, part, a.part_bytes, st));
+                           L2, L2C, 16, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN1R, tsrc(L2, 16, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
-                           L2, L2C, 32, 0, 1, part, a.part_bytes, st));
+                           L2, L2C, 32, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN2, tsrc(L2, 24, L2C, 16, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h3, w3,
-                           L3, L3C, 32, 0, 1, part, a.part_bytes, st));
+                           L3, L3C, 32, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_EN2R, tsrc(L3, 32, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 64, 0, 1, part, a.part_bytes, st));
+                           L3, L3C, 64, 0, 1, part, a.part_bytes, cfg, only, st));
     // mu & sigma (FP32), then Eq. (8)
     SV_TRY_STATUS(tv_layer(s, packed, T_MS, tsrc(L3, 48, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           ML, 2, 0, 1, 0, part, a.part_bytes, st));
+                           ML, 2, 0, 1, 0, part, a.part_bytes, cfg, only, st));
     const int nl = B * h3 * w3;
-    switch (s.dtype) {
+    if (only < 0) switch (s.dtype) {
     case SV_F32: hipLaunchKernelGGL(k_tv_reparam<SV_F32>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (float *)Z); break;
     case SV_BF16: hipLaunchKernelGGL(k_tv_reparam<SV_BF16>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (uint16_t *)Z); break;
     default: hipLaunchKernelGGL(k_tv_reparam<SV_F16>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (uint16_t *)Z); break;
@@ -362,21 +392,22 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     SV_LAUNCH_CHECK("k_tv_reparam");
     // decoder
     SV_TRY_STATUS(tv_layer(s, packed, T_D1, tsrc(Z, 1, ZC, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 0, 0, 1, part, a.part_bytes, st));
+                           L3, L3C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D1R, tsrc(L3, 80, L3C, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
-                           L3, L3C, 80, 0, 1, part, a.part_bytes, st));
+                           L3, L3C, 80, 0, 1, part, a.part_bytes, cfg, only, st));
     // deconvolutions: the zero-inserted grid has 2n - 1 samples per axis
     SV_TRY_STATUS(tv_layer(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, B, 2 * h3 - 1,
-                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, part, a.part_bytes, st));
+                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D2R, tsrc(L2, 40, L2C, 0, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
-                           L2, L2C, 40, 0, 1, part, a.part_bytes, st));
+                           L2, L2C, 40, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, B, 2 * h2 - 1,
-                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, part, a.part_bytes, st));
+                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     // upsampling layer: tap projection of [D | FE_1 | FE_2 | X_0 X_1] (FP32
     // weights; the map is read in its stored dtype), then the gather
     const int sdt = s.dtype == SV_F32 ? 0 : 1 + s.dtype;
     SV_TRY_STATUS(tv_layer(s, packed, T_YP, tsrc(L1, 80, L1C, 0, h1, w1, SRC_TENSOR, sdt), x0, B, h1, w1, h1, w1,
-                           T, TC, 0, 1, 0, part, a.part_bytes, st));
+                           T, TC, 0, 1, 0, part, a.part_bytes, cfg, only, st));
+    if (only >= 0) return SV_OK;
     hipLaunchKernelGGL(k_tv_final, dim3(cdiv(W, 64), cdiv(H, 4), B), dim3(256), 0, st, T, B, h1, w1, f, H, W,
                        (const float *)((const char *)packed + s.b_off[T_YP]), out);
     SV_LAUNCH_CHECK("k_tv_final");
@@ -557,5 +588,101 @@ sv_status sv_tvae_set_layer_cfg(int layer, int cfg) {
 }
 
 int sv_tvae_num_layers(void) { return T_NL; }
+
+sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;
+    if (factor < 1 || factor > 8) return SV_ERR_RANGE;
+    if (!tv_shape_ok(factor, B, H, W)) return SV_ERR_SHAPE;
+    const TvShape s = tv_shape(dtype);
+    const TvLevels lv = tv_levels(factor, H, W);
+    const size_t ws = sv_tvae_workspace_bytes(dtype, factor, B, H, W);
+    const size_t nlow = (size_t)B * lv.h[1] * lv.w[1];
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_pk = take(s.bytes), o_par = take((size_t)canon_off(NCANON) * 4), o_ws = take(ws);
+    const size_t o_in = take(2 * nlow), o_out = take((size_t)B * H * W * 4);
+    void *mem = nullptr;
+    SV_HIP(hipMalloc(&mem, off));
+    char *d = (char *)mem;
+    hipStream_t st = nullptr;
+    // zero parameters and inputs: timing does not depend on the values
+    hipLaunchKernelGGL(k_zero_bytes, dim3(4096), dim3(256), 0, st, (uint32_t *)d, off / 4);
+    sv_status r = tv_pack(s, (const float *)(d + o_par), d + o_pk, st);
+    const uint8_t *disp = (const uint8_t *)(d + o_in), *img = disp + nlow;
+    auto run = [&](int only) {
+        return tv_forward(s, factor, d + o_pk, disp, img, B, H, W, nullptr, (float *)(d + o_out), nullptr,
+                          d + o_ws, st, only);
+    };
+    auto timed = [&](int only, int reps) {
+        hipEvent_t a, b;
+        float t = 1e30f;
+        if (hipEventCreate(&a) != hipSuccess) return t;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return t; }
+        for (int i = 0; i < 2 && r == SV_OK; ++i) r = run(only);
+        (void)hipEventRecord(a, st);
+        for (int i = 0; i < reps && r == SV_OK; ++i) r = run(only);
+        (void)hipEventRecord(b, st);
+        (void)hipEventSynchronize(b);
+        (void)hipEventElapsedTime(&t, a, b);
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return t / reps;
+    };
+    int saved[T_NL], base[T_NL], best[T_NL];
+    for (int i = 0; i < T_NL; ++i) saved[i] = g_tv_cfg[i].exchange(-1);
+    {
+        std::lock_guard<std::mutex> g(g_tv_mu);
+        g_tv_tuned.erase(std::make_tuple(dtype, factor, B, H, W));
+    }
+    tv_layer_cfgs(dtype, factor, B, H, W, base);
+    const int reps = B >= 16 ? 4 : 12;
+    for (int li = 0; li < T_NL && r == SV_OK; ++li) {
+        const int dt = li == T_YP ? SV_F32 : dtype;
+        const int k = kOutLevel[li];
+        const long long npix = (long long)B * lv.h[k] * lv.w[k];
+        float bt = 1e30f;
+        best[li] = base[li];
+        for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
+            if (conv_resolve_cfg(dt, kLayers[li].k, kLayers[li].stride, c) != c) continue;
+            // a split the launch would not take duplicates a smaller one
+            const int want = c / conv_num_tiles() + 1;
+            static float dummy;
+            const TvAct a = tv_act(s.es, lv, B);
+            if (conv_effective_split(dt, c, kLayers[li].cin, npix, s.n_pad[li], &dummy, a.part_bytes) != want) continue;
+            g_tv_cfg[li].store(c);
+            const float t = timed(li, reps);
+            if (t < bt) { bt = t; best[li] = c; }
+        }
+        g_tv_cfg[li].store(-1);
+    }
+    if (r == SV_OK) {
+        // keep the tuned set only if the whole pass is faster than the defaults
+        const float t0 = timed(-1, reps);
+        {
+            std::lock_guard<std::mutex> g(g_tv_mu);
+            std::array<int, T_NL> a;
+            for (int i = 0; i < T_NL; ++i) a[i] = best[i];
+            g_tv_tuned[std::make_tuple(dtype, factor, B, H, W)] = a;
+        }
+        const float t1 = timed(-1, reps);
+        if (!(t1 < t0)) {
+            std::lock_guard<std::mutex> g(g_tv_mu);
+            g_tv_tuned.erase(std::make_tuple(dtype, factor, B, H, W));
+        }
+    }
+    for (int i = 0; i < T_NL; ++i) g_tv_cfg[i].store(saved[i]);
+    const hipError_t e = hipFree(mem);
+    if (r == SV_OK && e != hipSuccess) r = hip_fail(e, "hipFree");
+    return r;
+}
+
+sv_status sv_tvae_layer_cfgs(int dtype, int factor, int B, int H, int W, int *cfg_out) {
+    if (!cfg_out) return SV_ERR_NULL;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;
+    if (factor < 1 || factor > 8) return SV_ERR_RANGE;
+    if (!tv_shape_ok(factor, B, H, W)) return SV_ERR_SHAPE;
+    tv_layer_cfgs(dtype, factor, B, H, W, cfg_out);
+    return SV_OK;
+}
 
 }  // extern "C"

@@ -380,6 +380,17 @@ def sv_tvae_num_layers() -> int:
     return int(lib().sv_tvae_num_layers())
 
 
+def sv_tvae_autotune(dtype: str, factor: int, B: int, H: int, W: int):
+    check(lib().sv_tvae_autotune(DTYPES[dtype], factor, B, H, W), "sv_tvae_autotune")
+
+
+def sv_tvae_layer_cfgs(dtype: str, factor: int, B: int, H: int, W: int) -> list[str]:
+    n = sv_tvae_num_layers()
+    arr = (ctypes.c_int * n)()
+    check(lib().sv_tvae_layer_cfgs(DTYPES[dtype], factor, B, H, W, arr), "sv_tvae_layer_cfgs")
+    return [lib().sv_conv_cfg_name(c).decode() for c in arr]
+
+
 class TableVAE:
     """The Table I network: packed weights and a workspace sized for the last
     shape; forwards to sv_tvae_forward."""

@@ -158,6 +158,12 @@ def test_tvae_loss_and_cfg_validation():
     assert lib().sv_tvae_set_layer_cfg(12, 0) == -3
     assert lib().sv_tvae_set_layer_cfg(0, lib().sv_num_layer_cfgs()) == -3
     assert lib().sv_tvae_set_layer_cfg(0, -1) == 0
+    assert lib().sv_tvae_autotune(7, 4, 1, 64, 64) == -4
+    assert lib().sv_tvae_autotune(0, 9, 1, 64, 64) == -3
+    assert lib().sv_tvae_layer_cfgs(0, 4, 1, 64, 64, None) == -1
+    arr = (ctypes.c_int * 12)()
+    assert lib().sv_tvae_layer_cfgs(0, 4, 1, 375, 1242, arr) == 0
+    assert all(0 <= c < lib().sv_num_layer_cfgs() for c in arr)
 
 
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):

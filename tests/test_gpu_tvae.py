@@ -159,3 +159,13 @@ def test_loss_matches_oracle():
     assert normwise(g[..., 0], dmu) <= 1e-6
     assert normwise(g[..., 1], dsig) <= 1e-6
     assert gdout.cpu().numpy()[1, 5, 5] == 0.0
+
+
+def test_autotuned_pass_keeps_parity():
+    import paper_2305_11566_amd as sv
+    H, W, f, B = 45, 70, 4, 2
+    d, im = _rand_inputs(B, H, W, f, 23)
+    sv.sv_tvae_autotune("f32", f, B, H, W)
+    names = sv.sv_tvae_layer_cfgs("f32", f, B, H, W)
+    assert len(names) == sv.sv_tvae_num_layers() and all(n != "?" for n in names)
+    _compare(f, H, W, d, im, seed=5)
