@@ -39,7 +39,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import conv2d, tconv2d
+from . import conv2d, conv2d_dw, conv2d_dx, tconv2d
 
 SLOPE = 0.1
 K = 5
@@ -142,6 +142,7 @@ def forward(params, disp_low, img_low, factor, H, W, eps=None):
     # upsampling to full resolution
     t["Y"] = _deconv(cat(t["D"], t["X_0"], t["FE_1"], t["FE_2"]), p["Y"], factor, H, W)[:, 0]
     t["out"] = 256.0 * t["Y"]
+    t["factor"] = factor
     return t
 
 
@@ -166,3 +167,74 @@ def loss(out, gt, noc, occ, mu, sigma):
     dmu = 256.0 * m / nl
     dsigma = 256.0 * (np.exp(2.0 * s) - 1.0) / nl
     return l1 + l2, l1, l2, dout, dmu, dsigma
+
+
+# ---- adjoint ---------------------------------------------------------------------
+# (name, inputs in "&" order, stride (0: the factor), transposed, activation)
+_GRAPH = (
+    ("FE_1", ("X_0",), 1, False, True),
+    ("FE_2", ("X_1",), 1, False, True),
+    ("EN_1", ("FE_1", "FE_2"), 2, False, True),
+    ("EN_1_R", ("EN_1",), 1, False, True),
+    ("EN_2", ("EN_1", "EN_1_R"), 2, False, True),
+    ("EN_2_R", ("EN_2",), 1, False, True),
+    ("MS", ("EN_2", "EN_2_R"), 1, False, False),
+    ("D_1", ("z",), 1, True, True),
+    ("D_1_R", ("D_1", "EN_2", "EN_2_R"), 1, False, True),
+    ("D_2", ("D_1", "EN_2", "EN_2_R", "D_1_R"), 2, True, True),
+    ("D_2_R", ("D_2", "EN_1", "EN_1_R"), 1, False, True),
+    ("D", ("D_2", "EN_1", "EN_1_R", "D_2_R"), 2, True, True),
+    ("Y", ("D", "X_0", "FE_1", "FE_2"), 0, True, False),
+)
+
+
+def backward(params, t, dout, dmu=None, dsigma=None):
+    """Adjoint of ``forward`` for the scalar sum(dout * out) + sum(dmu * mu) +
+    sum(dsigma * sigma) (the loss's gradients plug in as dout, dmu, dsigma).
+    Returns (dw, db) per layer in LAYERS order.  The leaky ReLU's derivative
+    is taken from the sign of the stored output (0.1 at exactly 0)."""
+    p = dict(zip(NAMES, [(np.asarray(w, np.float64), np.asarray(b, np.float64)) for (w, b) in params]))
+    g = {}
+
+    def acc(name, v):
+        g[name] = g.get(name, 0.0) + v
+
+    acc("Y", 256.0 * np.asarray(dout, np.float64)[:, None])
+    grads = {}
+    factor = t["factor"]
+    for (name, ins, stride, transposed, act) in reversed(_GRAPH):
+        w, b = p[name]
+        k = w.shape[-1]
+        pad = (k - 1) // 2
+        s = factor if stride == 0 else stride
+        if name == "MS":
+            dm = g.get("mu_z", 0.0) + (0.0 if dmu is None else np.asarray(dmu, np.float64).reshape(t["mu"].shape))
+            ds = g.get("sigma_z", 0.0) + (0.0 if dsigma is None else np.asarray(dsigma, np.float64).reshape(t["sigma"].shape))
+            dy = np.concatenate([np.broadcast_to(dm, t["mu"].shape), np.broadcast_to(ds, t["sigma"].shape)], axis=1)
+        else:
+            dy = g.get(name)
+            if dy is None:
+                dy = np.zeros_like(t[name] if name != "Y" else t["Y"][:, None])
+            if act:
+                dy = dy * np.where(t[name] > 0, 1.0, SLOPE)
+        x = cat(*[t[i] for i in ins])
+        if transposed:
+            # y = tconv(x): dW from the strided correlation of dy against x, dx = conv(dy; W^T)
+            dwt, _ = conv2d_dw(dy, x, k, s, pad)          # [C][O][k][k]
+            dw = np.ascontiguousarray(dwt.transpose(1, 0, 2, 3))
+            dx = conv2d(dy, np.ascontiguousarray(w.transpose(1, 0, 2, 3)), None, s, pad)
+        else:
+            dw, _ = conv2d_dw(x, dy, k, s, pad)
+            dx = conv2d_dx(dy, w, x.shape, s, pad)
+        grads[name] = (dw, dy.sum(axis=(0, 2, 3)))
+        c0 = 0
+        for i in ins:
+            c = t[i].shape[1]
+            if i == "z":
+                dz = dx[:, c0:c0 + c]
+                g["mu_z"] = dz
+                g["sigma_z"] = dz * t["eps"] * np.exp(t["sigma"] - 1.0) if "eps" in t else np.zeros_like(dz)
+            elif i not in ("X_0", "X_1"):
+                acc(i, dx[:, c0:c0 + c])
+            c0 += c
+    return [grads[n] for n in NAMES]

@@ -7,7 +7,9 @@ whole network is pinned against an independent torch float64 composition
 written here from Table I, plus closed forms: the last layer reduces to
 linear interpolation for a tent kernel on X_0, and with zero weights the
 head and the 1x1 deconvolution follow Eq. (8) in closed form.  The loss is
-pinned by closed forms and central finite differences.
+pinned by closed forms and central finite differences; the network's adjoint
+against torch float64 autograd of the independent composition and against
+central finite differences.
 """
 import numpy as np
 import pytest
@@ -239,3 +241,100 @@ def test_loss_gradient_matches_finite_differences():
             lm = tvae.loss(args_p[0], gt, noc, occ, args_p[1], args_p[2])[0]
             fd = (lp - lm) / (2 * h)
             assert abs(fd - grad[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, grad[idx])
+
+
+@pytest.mark.parametrize("f,H,W,train", [(2, 24, 40, True), (4, 30, 45, False), (3, 19, 26, True)])
+def test_backward_matches_torch_autograd(f, H, W, train):
+    r = _rng(100 + f)
+    h, w = -(-H // f), -(-W // f)
+    d = r.integers(0, 40, size=(2, h, w)).astype(np.uint8)
+    im = r.integers(0, 256, size=(2, h, w)).astype(np.uint8)
+    params = _params(31 + f)
+    h3, w3 = -(-(-(-h // 2)) // 2), -(-(-(-w // 2)) // 2)
+    eps = r.standard_normal((2, 1, h3, w3)) if train else None
+    dout = r.standard_normal((2, H, W))
+    dmu = r.standard_normal((2, 1, h3, w3))
+    dsg = r.standard_normal((2, 1, h3, w3))
+    t = tvae.forward(params, d, im, f, H, W, eps)
+    grads = tvae.backward(params, t, dout, dmu, dsg)
+    # torch float64 autograd of the independent composition
+    P = [(torch.tensor(np.asarray(w_), requires_grad=True), torch.tensor(np.asarray(b_), requires_grad=True))
+         for (w_, b_) in params]
+    import torch.nn.functional as Fn
+    act = lambda z: Fn.leaky_relu(z, 0.1)
+
+    def conv(x, wb, s):
+        return Fn.conv2d(x, wb[0], wb[1], stride=s, padding=(wb[0].shape[-1] - 1) // 2)
+
+    def deconv(x, wb, s, size):
+        k = wb[0].shape[-1]
+        pad = (k - 1) // 2
+        op = [size[i] - ((x.shape[2 + i] - 1) * s - 2 * pad + k) for i in range(2)]
+        return Fn.conv_transpose2d(x, wb[0].transpose(0, 1), wb[1], stride=s, padding=pad, output_padding=tuple(op))
+
+    (fe1, fe2, en1, en1r, en2, en2r, ms, d1, d1r, d2, d2r, dd, yy) = P
+    x0 = torch.from_numpy(f * d.astype(np.float64) / 256.0)[:, None]
+    x1 = torch.from_numpy(im.astype(np.float64) / 256.0)[:, None]
+    FE1, FE2 = act(conv(x0, fe1, 1)), act(conv(x1, fe2, 1))
+    E1 = act(conv(torch.cat([FE1, FE2], 1), en1, 2)); E1R = act(conv(E1, en1r, 1))
+    E2 = act(conv(torch.cat([E1, E1R], 1), en2, 2)); E2R = act(conv(E2, en2r, 1))
+    m = conv(torch.cat([E2, E2R], 1), ms, 1)
+    z = m[:, 0:1] - 1.0
+    if eps is not None:
+        z = z + torch.from_numpy(eps) * torch.exp(m[:, 1:2] - 1.0)
+    D1 = act(deconv(z, d1, 1, z.shape[2:])); D1R = act(conv(torch.cat([D1, E2, E2R], 1), d1r, 1))
+    D2 = act(deconv(torch.cat([D1, E2, E2R, D1R], 1), d2, 2, E1.shape[2:]))
+    D2R = act(conv(torch.cat([D2, E1, E1R], 1), d2r, 1))
+    DD = act(deconv(torch.cat([D2, E1, E1R, D2R], 1), dd, 2, FE1.shape[2:]))
+    Y = deconv(torch.cat([DD, x0, FE1, FE2], 1), yy, f, (H, W))[:, 0]
+    L = (torch.from_numpy(dout) * 256.0 * Y).sum() + (torch.from_numpy(dmu) * m[:, 0:1]).sum() \
+        + (torch.from_numpy(dsg) * m[:, 1:2]).sum()
+    L.backward()
+    for name, (gw, gb), (tw, tb) in zip(tvae.NAMES, grads, P):
+        np.testing.assert_allclose(gw, tw.grad.numpy(), rtol=1e-9, atol=1e-9 * max(1.0, np.abs(tw.grad.numpy()).max()),
+                                   err_msg=name)
+        np.testing.assert_allclose(gb, tb.grad.numpy(), rtol=1e-9, atol=1e-9 * max(1.0, np.abs(tb.grad.numpy()).max()),
+                                   err_msg=name)
+
+
+def test_backward_matches_finite_differences():
+    # independent of torch: central differences of the same scalar on a tiny instance
+    f, H, W = 2, 16, 24
+    r = _rng(77)
+    d = r.integers(0, 20, size=(1, 8, 12)).astype(np.uint8)
+    im = r.integers(0, 256, size=(1, 8, 12)).astype(np.uint8)
+    params = _params(5)
+    eps = r.standard_normal((1, 1, 2, 3))
+    dout = r.standard_normal((1, H, W))
+    dmu = r.standard_normal((1, 1, 2, 3))
+    dsg = r.standard_normal((1, 1, 2, 3))
+
+    def scalar(ps):
+        t = tvae.forward(ps, d, im, f, H, W, eps)
+        return float(np.sum(dout * t["out"]) + np.sum(dmu * t["mu"]) + np.sum(dsg * t["sigma"])), t
+
+    base, t = scalar(params)
+    grads = tvae.backward(params, t, dout, dmu, dsg)
+    checked = 0
+    for li in range(len(params)):
+        w, b = params[li]
+        for idx in [tuple(r.integers(0, s) for s in w.shape) for _ in range(3)] + [None]:
+            hh = 1e-6
+            ps_p = [(a.copy(), c.copy()) for (a, c) in params]
+            ps_m = [(a.copy(), c.copy()) for (a, c) in params]
+            if idx is None:
+                ps_p[li][1][0] += hh; ps_m[li][1][0] -= hh
+                g = grads[li][1][0]
+            else:
+                ps_p[li][0][idx] += hh; ps_m[li][0][idx] -= hh
+                g = grads[li][0][idx]
+            lp, tp = scalar(ps_p)
+            lm, tm = scalar(ps_m)
+            # skip coordinates whose step flips a leaky-ReLU sign somewhere
+            flips = any(np.any(np.sign(tp[k]) != np.sign(tm[k])) for k in tvae.NAMES[:-1] if k in tp and k != "MS")
+            if flips:
+                continue
+            fd = (lp - lm) / (2 * hh)
+            assert abs(fd - g) <= 1e-5 * max(1.0, abs(fd)), (tvae.NAMES[li], idx, fd, g)
+            checked += 1
+    assert checked >= 30
