@@ -477,6 +477,27 @@ sv_status sv_tvae_loss(const float *out, const float *gt, const uint8_t *noc, co
                        int64_t n, const float *mu_sigma, int64_t n_lat, float *loss_out, float *dout,
                        float *dmu_sigma, void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Backward pass of the Table I network: the gradient of
+ *   sum(dout * out) + sum(dmu_sigma * mu_sigma)
+ * with respect to every parameter, in the canonical layout (FP32, overwritten).
+ * With dout and dmu_sigma from sv_tvae_loss this is the gradient of the loss
+ * of Eqs. (9)-(11).  The forward pass must have run just before on the same
+ * inputs, eps and fwd_workspace (its activations are read from there).
+ *   disp_low, img_low, eps: as given to sv_tvae_forward (eps nullable)
+ *   fwd_workspace (device): the workspace sv_tvae_forward used, unchanged
+ *   dout (device) FP32 [B][H][W]; dmu_sigma (device, nullable) FP32 [B][h3][w3][2]
+ *   grad_out (device) FP32 [sv_tvae_param_count()]
+ *   workspace (device, 256-byte aligned) >= sv_tvae_backward_workspace_bytes(...)
+ * Weight gradients are reduced in a fixed order (no floating-point atomics).
+ * Errors: SV_ERR_NULL, SV_ERR_DTYPE, SV_ERR_RANGE, SV_ERR_SHAPE, SV_ERR_WORKSPACE.
+ */
+size_t sv_tvae_backward_workspace_bytes(int dtype, int factor, int B, int H, int W);
+sv_status sv_tvae_backward(int dtype, int factor, const void *packed_w, const uint8_t *disp_low,
+                           const uint8_t *img_low, int B, int H, int W, const float *eps,
+                           const void *fwd_workspace, const float *dout, const float *dmu_sigma,
+                           float *grad_out, void *workspace, size_t ws_bytes, void *stream);
+
 /* Tile configuration of launched layer `layer` (0 .. sv_tvae_num_layers()-1:
  * FE, EN_1, EN_1_R, EN_2, EN_2_R, mu&sigma, D_1, D_1_R, D_2, D_2_R, D, Y's tap
  * projection) of sv_tvae_forward, as sv_set_layer_cfg; -1 restores the

@@ -82,7 +82,7 @@ struct WgradParams {
 };
 
 constexpr int WG_TH = 4, WG_TW = 16, WG_MT = WG_TH * WG_TW, WG_OC = 32;
-static inline int wg_kcw(int ks) { return ks == 3 ? 16 : 64; }
+static inline int wg_kcw(int ks) { return ks == 1 ? 64 : 16; }
 
 template <int DT, int KS, int S>
 __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
@@ -92,7 +92,7 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
     using vec = typename M::vec;
     constexpr int GS = M::GS;
     constexpr int TAPS = KS * KS, PAD = (KS - 1) / 2;
-    constexpr int KCW = KS == 3 ? 16 : 64;
+    constexpr int KCW = KS == 1 ? 64 : 16;
     constexpr int PH = (WG_TH - 1) * S + KS, PW = (WG_TW - 1) * S + KS;
     constexpr int MTP = WG_MT + GS;        // padded pixel rows
     constexpr int KCP = KCW + GS;          // padded channel rows of the patch
@@ -149,6 +149,13 @@ __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
                     const size_t off = (((size_t)b * s.hs + yi) * s.ws + xi) * s.pitch + s.coff + cl;
 #pragma unroll
                     for (int i = 0; i < GS; ++i) v[i] = ld_el(s.ptr, off + i, sdt);
+                } else if (s.kind == SRC_ZINS) {
+                    // zeros between samples: only even positions hold the map
+                    if (((yi | xi) & 1) == 0) {
+                        const size_t off = (((size_t)b * s.hs + (yi >> 1)) * s.ws + (xi >> 1)) * s.pitch + s.coff + cl;
+#pragma unroll
+                        for (int i = 0; i < GS; ++i) v[i] = ld_el(s.ptr, off + i, sdt);
+                    }
                 } else if (s.kind == SRC_RESIZE) {
                     int y0, y1, x0, x1;
                     float ly, lx;
@@ -288,6 +295,10 @@ static sv_status launch_wgrad_dt(int ks, int stride, const WgradParams &p, const
         hipLaunchKernelGGL((k_wgrad<DT, 3, 2>), grid, dim3(256), 0, st, p);
     else if (ks == 1 && stride == 1)
         hipLaunchKernelGGL((k_wgrad<DT, 1, 1>), grid, dim3(256), 0, st, p);
+    else if (ks == 5 && stride == 1)
+        hipLaunchKernelGGL((k_wgrad<DT, 5, 1>), grid, dim3(256), 0, st, p);
+    else if (ks == 5 && stride == 2)
+        hipLaunchKernelGGL((k_wgrad<DT, 5, 2>), grid, dim3(256), 0, st, p);
     else
         return SV_ERR_UNSUPPORTED;
     SV_LAUNCH_CHECK("k_wgrad");
@@ -321,6 +332,35 @@ static sv_status wgrad_layer(int dtype, int ks, int stride, ConvSrc s0, ConvSrc 
                        w.splits, w.o_pad, w.taps, w.cinp, Cout, Cin, final_layer, grad);
     SV_LAUNCH_CHECK("k_wgrad_reduce");
     return SV_OK;
+}
+
+// The partial sums of one layer's weight and bias gradient (no reduction):
+// part[split][o_pad][taps][cinp], then part_b[split][o_pad]; the shape of that
+// layout is returned in `shape`.
+size_t wgrad_partial_floats(int B, int Ho, int Wo, int Cin, int Cout, int ks) {
+    return wgrad_part_floats(wgrad_plan(B, Ho, Wo, Cin, Cout, ks));
+}
+
+sv_status launch_wgrad_partials(int dtype, int ks, int stride, ConvSrc s0, ConvSrc s1, int B, int Hi, int Wi,
+                                int Ho, int Wo, int Cout, const float *dy, int dy_pitch, float *part,
+                                WgradShape &shape, hipStream_t st) {
+    const int Cin = s0.C + (s1.kind ? s1.C : 0);
+    const WgradPlan w = wgrad_plan(B, Ho, Wo, Cin, Cout, ks);
+    WgradParams p{};
+    p.src[0] = s0; p.src[1] = s1;
+    p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo; p.Cin = Cin; p.Cout = Cout;
+    p.dy = dy; p.dy_pitch = dy_pitch;
+    p.part = part;
+    p.part_b = part + (size_t)w.splits * w.o_pad * w.taps * w.cinp;
+    p.o_pad = w.o_pad; p.cinp = w.cinp;
+    p.ntiles = w.ntiles; p.tiles_x = w.tx; p.tiles_y = w.ty;
+    shape.splits = w.splits; shape.o_pad = w.o_pad; shape.taps = w.taps; shape.cinp = w.cinp;
+    switch (dtype) {
+    case SV_F32: return launch_wgrad_dt<SV_F32>(ks, stride, p, w, st);
+    case SV_BF16: return launch_wgrad_dt<SV_BF16>(ks, stride, p, w, st);
+    case SV_F16: return launch_wgrad_dt<SV_F16>(ks, stride, p, w, st);
+    default: return SV_ERR_DTYPE;
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -154,6 +154,15 @@ sv_status launch_pack(int dtype, const float *w, int Cout, int Cin, int k, int n
 // (FP32 [n_pad], 0 past Cout)
 sv_status launch_pack_i8(const float *w, int Cout, int Cin, int k, int n_pad, int cin_pad, int8_t *dst,
                          float *scale, hipStream_t s);
+// Weight-gradient partial sums of one layer (the backward's k_wgrad, kernel
+// sizes 1, 3, 5): part[split][o_pad][taps][cinp] then the bias partials
+// part_b[split][o_pad]; dy is the output gradient (FP32 NHWC, pitch dy_pitch).
+struct WgradShape { int splits, o_pad, taps, cinp; };
+size_t wgrad_partial_floats(int B, int Ho, int Wo, int Cin, int Cout, int ks);
+sv_status launch_wgrad_partials(int dtype, int ks, int stride, ConvSrc s0, ConvSrc s1, int B, int Hi, int Wi,
+                                int Ho, int Wo, int Cout, const float *dy, int dy_pitch, float *part,
+                                WgradShape &shape, hipStream_t st);
+
 // INT8 pass prologue: zero nslots * AMAX_SUB words, then record the amax of
 // x0 = [scale0 * d, img / 256] over n coarse pixels in slot x0_slot
 sv_status launch_amax_prologue(uint32_t *amax, int nslots, int x0_slot, const uint8_t *disp,

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <array>
 #include <atomic>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -79,7 +80,14 @@ struct TvShape {
     int dtype, es;
     int n_pad[T_NL], cin_pad[T_NL];
     size_t w_off[T_NL], b_off[T_NL], bytes;
+    // adjoint packs of the input gradient: rows = the layer's inputs (Y's
+    // projection: the 80 level-1 channels), columns = its outputs; 0 for FE
+    int bn_pad[T_NL], bcin_pad[T_NL];
+    size_t bw_off[T_NL];
 };
+
+// Launched layers' input rows of the adjoint pack (0: no input gradient).
+constexpr int kAdjRows[T_NL] = {0, 64, 16, 24, 32, 48, 1, 80, 96, 40, 48, 80};
 
 TvShape tv_shape(int dtype) {
     TvShape s{};
@@ -97,6 +105,16 @@ TvShape tv_shape(int dtype) {
         off = align256(off + (size_t)l.k * l.k * s.n_pad[i] * s.cin_pad[i] * les);
         s.b_off[i] = off;
         off = align256(off + (size_t)s.n_pad[i] * sizeof(float));
+    }
+    for (int i = 0; i < T_NL; ++i) {
+        s.bw_off[i] = 0;
+        s.bn_pad[i] = s.bcin_pad[i] = 0;
+        if (!kAdjRows[i]) continue;
+        s.bn_pad[i] = rup(kAdjRows[i], 16);
+        s.bcin_pad[i] = rup(kLayers[i].cout, 8);
+        const int les = i == T_YP ? 4 : s.es;
+        s.bw_off[i] = off;
+        off = align256(off + (size_t)kLayers[i].k * kLayers[i].k * s.bn_pad[i] * s.bcin_pad[i] * les);
     }
     s.bytes = off;
     return s;
@@ -208,6 +226,35 @@ __global__ void k_tv_pack_t(const PackJob j, typename Elem<DT>::T *__restrict__ 
     }
 }
 
+// Adjoint pack of one launched layer: dst[tap][n][c] with n over the layer's
+// inputs (canonical input channel rmap[n]) and c over its outputs.  A
+// convolution's input gradient correlates the output gradient with the
+// flipped kernel (over the zero-inserted gradient for stride 2); a
+// deconvolution's is the stride-2 correlation with the kernel as it is; proj:
+// the upsampling layer, one column per tap.
+struct AdjJob {
+    const float *w;
+    int cout, cin, k, rows, cols, taps, n_pad, cin_pad, flip, proj;
+    int rmap[96];
+};
+
+template <int DT>
+__global__ void k_tv_pack_adj(const AdjJob j, typename Elem<DT>::T *__restrict__ dst) {
+    const int total = j.taps * j.n_pad * j.cin_pad;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % j.cin_pad;
+        const int n = (e / j.cin_pad) % j.n_pad;
+        const int tap = e / (j.cin_pad * j.n_pad);
+        float v = 0.f;
+        const int ci = n < j.rows ? j.rmap[n] : -1;
+        if (ci >= 0 && c < j.cols) {
+            if (j.proj) v = j.w[(size_t)ci * j.k * j.k + c];  // output channel 0, tap c
+            else v = j.w[((size_t)c * j.cin + ci) * j.k * j.k + (j.flip ? j.k * j.k - 1 - tap : tap)];
+        }
+        dst[e] = Elem<DT>::make(v);
+    }
+}
+
 __global__ void k_zero_bytes(uint32_t *__restrict__ p, size_t n_words) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n_words; e += (size_t)gridDim.x * blockDim.x)
         p[e] = 0u;
@@ -279,6 +326,44 @@ sv_status tv_pack(const TvShape &s, const float *params, void *packed, hipStream
     hipLaunchKernelGGL(k_tv_bias, dim3(1), dim3(64), 0, st, params + canon_off(C_Y) + 81 * 25, 1,
                        (float *)(P + s.b_off[T_YP]));
     SV_LAUNCH_CHECK("k_tv_bias");
+    // adjoint packs (the backward pass)
+    auto adj = [&](int canon, int layer, bool flip, auto rowmap) -> sv_status {
+        AdjJob j{};
+        const CanonLayer &c = kCanon[canon];
+        j.w = params + canon_off(canon);
+        j.cout = c.cout; j.cin = c.cin; j.k = c.k;
+        j.proj = layer == T_YP;
+        j.rows = kAdjRows[layer];
+        j.cols = kLayers[layer].cout;
+        j.taps = kLayers[layer].k * kLayers[layer].k;
+        j.n_pad = s.bn_pad[layer]; j.cin_pad = s.bcin_pad[layer];
+        j.flip = flip;
+        for (int q = 0; q < 96; ++q) j.rmap[q] = q < j.rows ? rowmap(q) : -1;
+        const int total = j.taps * j.n_pad * j.cin_pad;
+        const int blocks = std::min((total + 255) / 256, 1024);
+        void *dst = P + s.bw_off[layer];
+        switch (layer == T_YP ? SV_F32 : s.dtype) {
+        case SV_F32: hipLaunchKernelGGL(k_tv_pack_adj<SV_F32>, dim3(blocks), dim3(256), 0, st, j, (float *)dst); break;
+        case SV_BF16: hipLaunchKernelGGL(k_tv_pack_adj<SV_BF16>, dim3(blocks), dim3(256), 0, st, j, (uint16_t *)dst); break;
+        default: hipLaunchKernelGGL(k_tv_pack_adj<SV_F16>, dim3(blocks), dim3(256), 0, st, j, (uint16_t *)dst); break;
+        }
+        SV_LAUNCH_CHECK("k_tv_pack_adj");
+        return SV_OK;
+    };
+    auto idr = [](int q) { return q; };
+    SV_TRY_STATUS(adj(C_EN1, T_EN1, true, idr));
+    SV_TRY_STATUS(adj(C_EN1R, T_EN1R, true, idr));
+    SV_TRY_STATUS(adj(C_EN2, T_EN2, true, idr));
+    SV_TRY_STATUS(adj(C_EN2R, T_EN2R, true, idr));
+    SV_TRY_STATUS(adj(C_MS, T_MS, false, idr));
+    SV_TRY_STATUS(adj(C_D1, T_D1, false, idr));
+    SV_TRY_STATUS(adj(C_D1R, T_D1R, true, idr));
+    SV_TRY_STATUS(adj(C_D2, T_D2, false, idr));
+    SV_TRY_STATUS(adj(C_D2R, T_D2R, true, idr));
+    SV_TRY_STATUS(adj(C_D, T_D, false, idr));
+    // the upsampling layer's rows: the level-1 channels [D | FE_1 | FE_2] in the
+    // table's order D & X_0 & FE_1 & FE_2 (X_0 needs no gradient)
+    SV_TRY_STATUS(adj(C_Y, T_YP, false, [](int q) { return q < 16 ? q : q + 1; }));
     return SV_OK;
 }
 
@@ -323,6 +408,11 @@ k_tv_final(const float *__restrict__ T, int B, int h, int w, int f, int H, int W
     out[((size_t)b * H + y) * W + x] = 256.0f * (s + bias[0]);
 }
 
+__global__ void k_tv_copy(const float *__restrict__ src, int n, float *__restrict__ dst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 ConvSrc tsrc(const void *p, int C, int pitch, int coff, int hs, int ws, int kind, int sdt) {
     ConvSrc s{};
     s.ptr = p; s.kind = kind; s.C = C; s.pitch = pitch; s.coff = coff; s.hs = hs; s.ws = ws; s.sdt = sdt;
@@ -361,7 +451,9 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     const TvAct a = tv_act(s.es, lv, B);
     char *w = (char *)ws;
     void *L1 = w + a.L1, *L2 = w + a.L2, *L3 = w + a.L3, *Z = w + a.Z;
-    float *ML = ml_user ? ml_user : (float *)(w + a.ML);
+    // mu / sigma stay in the workspace (the backward reads them there); the
+    // caller's buffer gets a copy
+    float *ML = (float *)(w + a.ML);
     float *T = (float *)(w + a.T);
     float *part = (float *)(w + a.part);
     const int h1 = lv.h[1], w1 = lv.w[1], h2 = lv.h[2], w2 = lv.w[2], h3 = lv.h[3], w3 = lv.w[3];
@@ -384,6 +476,10 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     SV_TRY_STATUS(tv_layer(s, packed, T_MS, tsrc(L3, 48, L3C, 32, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
                            ML, 2, 0, 1, 0, part, a.part_bytes, cfg, only, st));
     const int nl = B * h3 * w3;
+    if (ml_user && only < 0) {
+        hipLaunchKernelGGL(k_tv_copy, dim3(cdiv(2 * nl, 256)), dim3(256), 0, st, ML, 2 * nl, ml_user);
+        SV_LAUNCH_CHECK("k_tv_copy");
+    }
     if (only < 0) switch (s.dtype) {
     case SV_F32: hipLaunchKernelGGL(k_tv_reparam<SV_F32>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (float *)Z); break;
     case SV_BF16: hipLaunchKernelGGL(k_tv_reparam<SV_BF16>, dim3(cdiv(nl, 256)), dim3(256), 0, st, ML, eps, nl, (uint16_t *)Z); break;
@@ -411,6 +507,303 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     hipLaunchKernelGGL(k_tv_final, dim3(cdiv(W, 64), cdiv(H, 4), B), dim3(256), 0, st, T, B, h1, w1, f, H, W,
                        (const float *)((const char *)packed + s.b_off[T_YP]), out);
     SV_LAUNCH_CHECK("k_tv_final");
+    return SV_OK;
+}
+
+// ---- backward ----------------------------------------------------------------------
+// Gradient maps (FP32 NHWC): one per level, channel ranges as in the forward
+// maps; dZ [px3]; d(mu, sigma) [px3][8] (channels 2..7 zero, so that the 1x1
+// input-gradient convolution reads whole channel groups); the tap gradients
+// of the upsampling layer [px1][32] (taps 25..31 zero).
+constexpr int DMLC = 8;
+struct TvBwd { size_t dL1, dL2, dL3, dZ, dML, dT, part, sum, total; };
+
+TvBwd tv_bwd_layout(const TvShape &s, const TvLevels &lv, int B) {
+    auto px = [&](int k) { return (size_t)B * lv.h[k] * lv.w[k]; };
+    TvBwd l{};
+    size_t o = 0;
+    auto take = [&](size_t floats) { size_t r = o; o = align256(o + floats * sizeof(float)); return r; };
+    l.dL1 = take(px(1) * L1C);
+    l.dL2 = take(px(2) * L2C);
+    l.dL3 = take(px(3) * L3C);
+    l.dZ = take(px(3));
+    l.dML = take(px(3) * DMLC);
+    l.dT = take(px(1) * TC);
+    // weight-gradient partial sums of the largest layer (layers run one after another)
+    size_t mx = 0;
+    for (int i = 0; i < T_NL; ++i) {
+        const int k = kOutLevel[i];
+        mx = std::max(mx, wgrad_partial_floats(B, lv.h[k], lv.w[k], kLayers[i].cin, kLayers[i].cout, kLayers[i].k));
+    }
+    l.part = take(mx);
+    l.sum = take(256 + 1);
+    l.total = o;
+    (void)s;
+    return l;
+}
+
+// dT[b][i][j][t] = 256 * dout[b][f i + u - 2][f j + v - 2] (t = 5u + v; 0 where
+// that pixel is outside the image, and for t >= 25): each tap of a coarse
+// pixel lands on exactly one full-resolution pixel.
+__global__ void k_tv_final_bwd(const float *__restrict__ dout, int B, int h, int w, int f, int H, int W,
+                               float *__restrict__ dT) {
+    const size_t n = (size_t)B * h * w * TC;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const int t = (int)(e % TC);
+        const size_t pix = e / TC;
+        const int j = (int)(pix % w), i = (int)((pix / w) % h), b = (int)(pix / ((size_t)w * h));
+        float v = 0.f;
+        if (t < TV_TAPS) {
+            const int y = f * i + t / TV_K - 2, x = f * j + t % TV_K - 2;
+            if (y >= 0 && y < H && x >= 0 && x < W) v = 256.0f * dout[((size_t)b * H + y) * W + x];
+        }
+        dT[e] = v;
+    }
+}
+
+// sum of 256 * dout (Y's bias), two fixed-order passes
+__global__ void __launch_bounds__(256) k_tv_sum_partial(const float *__restrict__ x, int64_t n, float *__restrict__ part) {
+    __shared__ double sh[256];
+    const int64_t per = (n + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = blockIdx.x * per, hi = lo + per < n ? lo + per : n;
+    double acc = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += 256) acc += (double)x[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = (float)sh[0];
+}
+
+__global__ void __launch_bounds__(256) k_tv_sum_final(const float *__restrict__ part, float scale, float *__restrict__ out) {
+    __shared__ double sh[256];
+    sh[threadIdx.x] = (double)part[threadIdx.x];
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) sh[threadIdx.x] += sh[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = (float)(scale * sh[0]);
+}
+
+// leaky-ReLU derivative from the stored output (0.1 where it is <= 0)
+template <int DT>
+__global__ void k_tv_mask(float *__restrict__ g, int gpitch, int gcoff, const typename Elem<DT>::T *__restrict__ act,
+                          int apitch, int acoff, int C, size_t npix) {
+    const size_t n = npix * C;
+    for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+        const size_t pix = e / C;
+        const int c = (int)(e - pix * C);
+        const float a = Elem<DT>::load(act + pix * apitch + acoff + c);
+        if (!(a > 0.f)) g[pix * gpitch + gcoff + c] *= 0.1f;
+    }
+}
+
+// Eq. (8) backward: d mu = dz (+ the loss's), d sigma = dz * eps * exp(sigma - 1) (+ the loss's)
+__global__ void k_tv_reparam_bwd(const float *__restrict__ dz, const float *__restrict__ ml, const float *__restrict__ eps,
+                                 const float *__restrict__ dms, int n, float *__restrict__ dml) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float dm = dz[i], ds = eps ? dz[i] * eps[i] * expf(ml[2 * i + 1] - 1.0f) : 0.f;
+    if (dms) { dm += dms[2 * i]; ds += dms[2 * i + 1]; }
+    float *o = dml + (size_t)i * DMLC;
+    o[0] = dm;
+    o[1] = ds;
+#pragma unroll
+    for (int c = 2; c < DMLC; ++c) o[c] = 0.f;
+}
+
+// Canonical weight and bias gradient of one canonical layer from the partial
+// sums of the launched layer's weight gradient: row = row0 + o (proj: the
+// tap), tap = the canonical tap (flipped for a deconvolution's stride-1 form),
+// column = cmap[canonical input channel].
+struct GradJob {
+    int cout, cin, k, row0, flip, proj, bias;
+    int splits, o_pad, taps, cinp;
+    int cmap[96];
+};
+
+__global__ void k_tv_grad_reduce(const GradJob j, const float *__restrict__ part, float *__restrict__ grad) {
+    const int kk = j.k * j.k;
+    const int nw = j.cout * j.cin * kk;
+    const int n = nw + (j.bias ? j.cout : 0);
+    const float *part_b = part + (size_t)j.splits * j.o_pad * j.taps * j.cinp;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        float acc = 0.f;
+        if (e < nw) {
+            const int o = e / (j.cin * kk), ci = (e / kk) % j.cin, t = e % kk;
+            const int col = j.cmap[ci];
+            const int row = j.proj ? t : j.row0 + o;
+            const int tap = j.proj ? 0 : (j.flip ? kk - 1 - t : t);
+            if (col >= 0)
+                for (int sp = 0; sp < j.splits; ++sp)
+                    acc += part[(((size_t)sp * j.o_pad + row) * j.taps + tap) * j.cinp + col];
+        } else {
+            const int o = e - nw;
+            for (int sp = 0; sp < j.splits; ++sp) acc += part_b[(size_t)sp * j.o_pad + j.row0 + o];
+        }
+        grad[e] = acc;
+    }
+}
+
+ConvSrc fsrc(const float *p, int C, int pitch, int coff, int hs, int ws, int kind) {
+    return tsrc(p, C, pitch, coff, hs, ws, kind, SDT_F32);
+}
+
+// Input gradient of launched layer li through the forward convolution kernel
+// and the adjoint pack: `dy` is the output gradient as a source (plain, or
+// zero-inserted for a stride-2 convolution); out / add give the target range.
+sv_status tv_dgrad(const TvShape &s, const void *packed, int li, ConvSrc dy, int stride, int B, int Hi, int Wi,
+                   int Ho, int Wo, float *out, int out_pitch, int out_coff, bool add, hipStream_t st) {
+    ConvParams p{};
+    p.src[0] = dy;
+    p.B = B; p.Hi = Hi; p.Wi = Wi; p.Ho = Ho; p.Wo = Wo;
+    p.Cin = dy.C;
+    p.Cout = kAdjRows[li];
+    p.cin_pad = s.bcin_pad[li];
+    p.n_pad = s.bn_pad[li];
+    p.wpk = (const char *)packed + s.bw_off[li];
+    p.out = out; p.out_pitch = out_pitch; p.out_coff = out_coff; p.out_f32 = 1;
+    if (add) { p.add = out; p.add_pitch = out_pitch; p.add_coff = out_coff; }
+    const int cfg = p.Cout <= 16 ? 5 : 2;
+    return launch_conv(li == T_YP ? SV_F32 : s.dtype, kLayers[li].k, stride, cfg, p, st);
+}
+
+sv_status tv_backward(const TvShape &s, int f, const void *packed, const uint8_t *disp, const uint8_t *img, int B,
+                      int H, int W, const float *eps, const void *fws, const float *dout, const float *dms,
+                      float *grad, void *ws, hipStream_t st) {
+    const TvLevels lv = tv_levels(f, H, W);
+    const TvAct a = tv_act(s.es, lv, B);
+    const TvBwd l = tv_bwd_layout(s, lv, B);
+    const char *fw = (const char *)fws;
+    const void *L1 = fw + a.L1, *L2 = fw + a.L2, *L3 = fw + a.L3, *Z = fw + a.Z;
+    const float *ML = (const float *)(fw + a.ML);
+    char *bw = (char *)ws;
+    float *dL1 = (float *)(bw + l.dL1), *dL2 = (float *)(bw + l.dL2), *dL3 = (float *)(bw + l.dL3);
+    float *dZ = (float *)(bw + l.dZ), *dML = (float *)(bw + l.dML), *dT = (float *)(bw + l.dT);
+    float *part = (float *)(bw + l.part), *sum = (float *)(bw + l.sum);
+    const int h1 = lv.h[1], w1 = lv.w[1], h2 = lv.h[2], w2 = lv.w[2], h3 = lv.h[3], w3 = lv.w[3];
+    const size_t p1 = (size_t)B * h1 * w1, p2 = (size_t)B * h2 * w2, p3 = (size_t)B * h3 * w3;
+    const int sdt = s.dtype == SV_F32 ? 0 : 1 + s.dtype;  // the maps' storage, seen from an FP32 launch
+    const ConvSrc none{};
+    ConvSrc x0{};
+    x0.ptr = disp; x0.img = img; x0.kind = SRC_X0; x0.C = 2; x0.hs = h1; x0.ws = w1;
+    x0.scale0 = (float)f / 256.0f;
+    auto blocks = [](size_t n) { return (unsigned)std::min<size_t>((n + 255) / 256, 4096); };
+
+    // weight gradient of launched layer li into the canonical slices of `jobs`
+    auto wgrad = [&](int li, int ks, int stride, ConvSrc s0, ConvSrc s1, int Hi, int Wi, int Ho, int Wo,
+                     const float *dy, int dy_pitch, std::initializer_list<GradJob> jobs,
+                     std::initializer_list<int> canons) -> sv_status {
+        WgradShape sh{};
+        SV_TRY_STATUS(launch_wgrad_partials(li == T_YP ? SV_F32 : s.dtype, ks, stride, s0, s1, B, Hi, Wi, Ho, Wo,
+                                            kLayers[li].cout, dy, dy_pitch, part, sh, st));
+        auto cit = canons.begin();
+        for (GradJob j : jobs) {
+            j.splits = sh.splits; j.o_pad = sh.o_pad; j.taps = sh.taps; j.cinp = sh.cinp;
+            const int n = j.cout * j.cin * j.k * j.k + (j.bias ? j.cout : 0);
+            hipLaunchKernelGGL(k_tv_grad_reduce, dim3(cdiv(n, 256)), dim3(256), 0, st, j, part, grad + canon_off(*cit));
+            SV_LAUNCH_CHECK("k_tv_grad_reduce");
+            ++cit;
+        }
+        return SV_OK;
+    };
+    auto job = [&](int canon, int row0, bool flip, auto colmap) {
+        GradJob j{};
+        j.cout = kCanon[canon].cout; j.cin = kCanon[canon].cin; j.k = kCanon[canon].k;
+        j.row0 = row0; j.flip = flip; j.proj = canon == C_Y; j.bias = canon != C_Y;
+        for (int q = 0; q < 96; ++q) j.cmap[q] = q < j.cin ? colmap(q) : -1;
+        return j;
+    };
+    auto idc = [](int q) { return q; };
+    auto mask = [&](float *g, int gpitch, int gcoff, const void *act, int apitch, int acoff, int C, size_t npix) -> sv_status {
+        switch (s.dtype) {
+        case SV_F32: hipLaunchKernelGGL(k_tv_mask<SV_F32>, dim3(blocks(npix * C)), dim3(256), 0, st, g, gpitch, gcoff, (const float *)act, apitch, acoff, C, npix); break;
+        case SV_BF16: hipLaunchKernelGGL(k_tv_mask<SV_BF16>, dim3(blocks(npix * C)), dim3(256), 0, st, g, gpitch, gcoff, (const uint16_t *)act, apitch, acoff, C, npix); break;
+        default: hipLaunchKernelGGL(k_tv_mask<SV_F16>, dim3(blocks(npix * C)), dim3(256), 0, st, g, gpitch, gcoff, (const uint16_t *)act, apitch, acoff, C, npix); break;
+        }
+        SV_LAUNCH_CHECK("k_tv_mask");
+        return SV_OK;
+    };
+
+    // upsampling layer: tap gradients, Y's bias, its projection's weights and input gradient
+    hipLaunchKernelGGL(k_tv_final_bwd, dim3(blocks(p1 * TC)), dim3(256), 0, st, dout, B, h1, w1, f, H, W, dT);
+    SV_LAUNCH_CHECK("k_tv_final_bwd");
+    hipLaunchKernelGGL(k_tv_sum_partial, dim3(256), dim3(256), 0, st, dout, (int64_t)B * H * W, sum);
+    hipLaunchKernelGGL(k_tv_sum_final, dim3(1), dim3(256), 0, st, sum, 256.0f, grad + canon_off(C_Y) + 81 * 25);
+    SV_LAUNCH_CHECK("k_tv_sum");
+    SV_TRY_STATUS(wgrad(T_YP, 1, 1, tsrc(L1, 80, L1C, 0, h1, w1, SRC_TENSOR, sdt), x0, h1, w1, h1, w1, dT, TC,
+                        {job(C_Y, 0, false, [](int q) { return q < 16 ? q : (q == 16 ? 80 : q - 1); })}, {C_Y}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_YP, fsrc(dT, TV_TAPS, TC, 0, h1, w1, SRC_TENSOR), 1, B, h1, w1, h1, w1,
+                           dL1, L1C, 0, false, st));
+    // D (deconvolution into level 1)
+    SV_TRY_STATUS(mask(dL1, L1C, 0, L1, L1C, 0, 16, p1));
+    SV_TRY_STATUS(wgrad(T_D, 5, 1, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, 2 * h2 - 1, 2 * w2 - 1, h1, w1,
+                        dL1, L1C, {job(C_D, 0, true, idc)}, {C_D}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_D, fsrc(dL1, 16, L1C, 0, h1, w1, SRC_TENSOR), 2, B, h1, w1, h2, w2,
+                           dL2, L2C, 0, false, st));
+    // D_2_R
+    SV_TRY_STATUS(mask(dL2, L2C, 40, L2, L2C, 40, 8, p2));
+    SV_TRY_STATUS(wgrad(T_D2R, 5, 1, tsrc(L2, 40, L2C, 0, h2, w2, SRC_TENSOR, 0), none, h2, w2, h2, w2, dL2 + 40, L2C,
+                        {job(C_D2R, 0, false, idc)}, {C_D2R}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_D2R, fsrc(dL2, 8, L2C, 40, h2, w2, SRC_TENSOR), 1, B, h2, w2, h2, w2,
+                           dL2, L2C, 0, true, st));
+    // D_2 (deconvolution into level 2)
+    SV_TRY_STATUS(mask(dL2, L2C, 0, L2, L2C, 0, 16, p2));
+    SV_TRY_STATUS(wgrad(T_D2, 5, 1, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, 2 * h3 - 1, 2 * w3 - 1, h2, w2,
+                        dL2, L2C, {job(C_D2, 0, true, idc)}, {C_D2}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_D2, fsrc(dL2, 16, L2C, 0, h2, w2, SRC_TENSOR), 2, B, h2, w2, h3, w3,
+                           dL3, L3C, 0, false, st));
+    // D_1_R
+    SV_TRY_STATUS(mask(dL3, L3C, 80, L3, L3C, 80, 16, p3));
+    SV_TRY_STATUS(wgrad(T_D1R, 5, 1, tsrc(L3, 80, L3C, 0, h3, w3, SRC_TENSOR, 0), none, h3, w3, h3, w3, dL3 + 80, L3C,
+                        {job(C_D1R, 0, false, idc)}, {C_D1R}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_D1R, fsrc(dL3, 16, L3C, 80, h3, w3, SRC_TENSOR), 1, B, h3, w3, h3, w3,
+                           dL3, L3C, 0, true, st));
+    // D_1 (1x1 deconvolution of z)
+    SV_TRY_STATUS(mask(dL3, L3C, 0, L3, L3C, 0, 32, p3));
+    SV_TRY_STATUS(wgrad(T_D1, 1, 1, tsrc(Z, 1, ZC, 0, h3, w3, SRC_TENSOR, 0), none, h3, w3, h3, w3, dL3, L3C,
+                        {job(C_D1, 0, false, idc)}, {C_D1}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_D1, fsrc(dL3, 32, L3C, 0, h3, w3, SRC_TENSOR), 1, B, h3, w3, h3, w3,
+                           dZ, 1, 0, false, st));
+    // Eq. (8), then the head
+    hipLaunchKernelGGL(k_tv_reparam_bwd, dim3(cdiv((int)p3, 256)), dim3(256), 0, st, dZ, ML, eps, dms, (int)p3, dML);
+    SV_LAUNCH_CHECK("k_tv_reparam_bwd");
+    SV_TRY_STATUS(wgrad(T_MS, 1, 1, tsrc(L3, 48, L3C, 32, h3, w3, SRC_TENSOR, 0), none, h3, w3, h3, w3, dML, DMLC,
+                        {job(C_MS, 0, false, idc)}, {C_MS}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_MS, fsrc(dML, 2, DMLC, 0, h3, w3, SRC_TENSOR), 1, B, h3, w3, h3, w3,
+                           dL3, L3C, 32, true, st));
+    // EN_2_R
+    SV_TRY_STATUS(mask(dL3, L3C, 64, L3, L3C, 64, 16, p3));
+    SV_TRY_STATUS(wgrad(T_EN2R, 5, 1, tsrc(L3, 32, L3C, 32, h3, w3, SRC_TENSOR, 0), none, h3, w3, h3, w3, dL3 + 64, L3C,
+                        {job(C_EN2R, 0, false, idc)}, {C_EN2R}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_EN2R, fsrc(dL3, 16, L3C, 64, h3, w3, SRC_TENSOR), 1, B, h3, w3, h3, w3,
+                           dL3, L3C, 32, true, st));
+    // EN_2 (stride 2: its input gradient runs over the zero-inserted output gradient)
+    SV_TRY_STATUS(mask(dL3, L3C, 32, L3, L3C, 32, 32, p3));
+    SV_TRY_STATUS(wgrad(T_EN2, 5, 2, tsrc(L2, 24, L2C, 16, h2, w2, SRC_TENSOR, 0), none, h2, w2, h3, w3, dL3 + 32, L3C,
+                        {job(C_EN2, 0, false, idc)}, {C_EN2}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_EN2, fsrc(dL3, 32, L3C, 32, h3, w3, SRC_ZINS), 1, B, 2 * h3 - 1, 2 * w3 - 1,
+                           h2, w2, dL2, L2C, 16, true, st));
+    // EN_1_R
+    SV_TRY_STATUS(mask(dL2, L2C, 32, L2, L2C, 32, 8, p2));
+    SV_TRY_STATUS(wgrad(T_EN1R, 5, 1, tsrc(L2, 16, L2C, 16, h2, w2, SRC_TENSOR, 0), none, h2, w2, h2, w2, dL2 + 32, L2C,
+                        {job(C_EN1R, 0, false, idc)}, {C_EN1R}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_EN1R, fsrc(dL2, 8, L2C, 32, h2, w2, SRC_TENSOR), 1, B, h2, w2, h2, w2,
+                           dL2, L2C, 16, true, st));
+    // EN_1
+    SV_TRY_STATUS(mask(dL2, L2C, 16, L2, L2C, 16, 16, p2));
+    SV_TRY_STATUS(wgrad(T_EN1, 5, 2, tsrc(L1, 64, L1C, 16, h1, w1, SRC_TENSOR, 0), none, h1, w1, h2, w2, dL2 + 16, L2C,
+                        {job(C_EN1, 0, false, idc)}, {C_EN1}));
+    SV_TRY_STATUS(tv_dgrad(s, packed, T_EN1, fsrc(dL2, 16, L2C, 16, h2, w2, SRC_ZINS), 1, B, 2 * h2 - 1, 2 * w2 - 1,
+                           h1, w1, dL1, L1C, 16, true, st));
+    // FE_1 (rows 0..31, input channel 0) and FE_2 (rows 32..63, channel 1)
+    SV_TRY_STATUS(mask(dL1, L1C, 16, L1, L1C, 16, 64, p1));
+    SV_TRY_STATUS(wgrad(T_FE, 5, 1, x0, none, h1, w1, h1, w1, dL1 + 16, L1C,
+                        {job(C_FE1, 0, false, [](int) { return 0; }), job(C_FE2, 32, false, [](int) { return 1; })},
+                        {C_FE1, C_FE2}));
     return SV_OK;
 }
 
@@ -588,6 +981,26 @@ sv_status sv_tvae_set_layer_cfg(int layer, int cfg) {
 }
 
 int sv_tvae_num_layers(void) { return T_NL; }
+
+size_t sv_tvae_backward_workspace_bytes(int dtype, int factor, int B, int H, int W) {
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return 0;
+    if (!tv_shape_ok(factor, B, H, W)) return 0;
+    return tv_bwd_layout(tv_shape(dtype), tv_levels(factor, H, W), B).total;
+}
+
+sv_status sv_tvae_backward(int dtype, int factor, const void *packed_w, const uint8_t *disp_low,
+                           const uint8_t *img_low, int B, int H, int W, const float *eps,
+                           const void *fwd_workspace, const float *dout, const float *dmu_sigma, float *grad_out,
+                           void *workspace, size_t ws_bytes, void *stream) {
+    if (!packed_w || !disp_low || !img_low || !fwd_workspace || !dout || !grad_out || !workspace) return SV_ERR_NULL;
+    if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;
+    if (factor < 1 || factor > 8) return SV_ERR_RANGE;
+    if (!tv_shape_ok(factor, B, H, W)) return SV_ERR_SHAPE;
+    if (ws_bytes < sv_tvae_backward_workspace_bytes(dtype, factor, B, H, W)) return SV_ERR_WORKSPACE;
+    if ((uintptr_t)workspace % 256 || (uintptr_t)fwd_workspace % 256 || (uintptr_t)packed_w % 256) return SV_ERR_RANGE;
+    return tv_backward(tv_shape(dtype), factor, packed_w, disp_low, img_low, B, H, W, eps, fwd_workspace, dout,
+                       dmu_sigma, grad_out, workspace, (hipStream_t)stream);
+}
 
 sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
     if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return SV_ERR_DTYPE;

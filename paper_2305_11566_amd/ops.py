@@ -448,6 +448,26 @@ class TableVAE:
                                     ws.numel(), stream_ptr()), "sv_tvae_forward")
         return out, mu_sigma
 
+    def backward(self, disp_low, img_low, H, W, dout, eps=None, dmu_sigma=None, grad=None):
+        """Gradient of sum(dout * out) + sum(dmu_sigma * mu_sigma) after forward() on the
+        same inputs (its workspace holds the activations)."""
+        _need(dout, torch.float32, "dout")
+        B = disp_low.shape[0]
+        if self._ws_key != (B, H, W):
+            raise ValueError("backward() needs the forward pass of the same shape just before")
+        if grad is None:
+            grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+        key = ("bwd", B, H, W)
+        if getattr(self, "_bws_key", None) != key:
+            n = lib().sv_tvae_backward_workspace_bytes(self.dtype_code, self.factor, B, H, W)
+            self._bws = _aligned_bytes(n, self.device)
+            self._bws_key = key
+        check(lib().sv_tvae_backward(self.dtype_code, self.factor, ptr(self.packed), ptr(disp_low),
+                                     ptr(img_low), B, H, W, ptr(eps), ptr(self._ws), ptr(dout),
+                                     ptr(dmu_sigma), ptr(grad), ptr(self._bws), self._bws.numel(),
+                                     stream_ptr()), "sv_tvae_backward")
+        return grad
+
 
 def sv_tvae_loss(out, gt, noc, occ, mu_sigma, want_grad=True):
     """Eqs. (9)-(11) -> (loss [3] = total, Loss_1, Loss_2; dout or None; dmu_sigma or None)."""

@@ -169,3 +169,73 @@ def test_autotuned_pass_keeps_parity():
     names = sv.sv_tvae_layer_cfgs("f32", f, B, H, W)
     assert len(names) == sv.sv_tvae_num_layers() and all(n != "?" for n in names)
     _compare(f, H, W, d, im, seed=5)
+
+
+def _grad_case(dtype, f, H, W, B, train, seed):
+    import paper_2305_11566_amd as sv
+    d, im = _rand_inputs(B, H, W, f, seed)
+    params = _params(seed + 1)
+    r = np.random.default_rng(seed + 2)
+    h3, w3 = _latent_hw(H, W, f)
+    eps = gen_eps((B, h3, w3), seed=9000 + seed).astype(np.float32) if train else None
+    dout = r.standard_normal((B, H, W)).astype(np.float32)
+    dms = r.standard_normal((B, h3, w3, 2)).astype(np.float32)
+    t = tvae.forward(params, d, im, f, H, W, eps=None if eps is None else eps[:, None])
+    ref = tvae.backward(params, t, dout, dms[..., 0][:, None], dms[..., 1][:, None])
+    net = sv.TableVAE(f, dtype)
+    net.pack(cuda(flat_params(params)))
+    dd, ii = cuda(d), cuda(im)
+    e = None if eps is None else cuda(eps)
+    net.forward(dd, ii, H, W, eps=e)
+    g = net.backward(dd, ii, H, W, cuda(dout), eps=e, dmu_sigma=cuda(dms))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    out, o = [], 0
+    for (w_, b_) in ref:
+        nw = w_.size
+        out.append((g[o:o + nw].reshape(w_.shape), g[o + nw:o + nw + b_.size], w_, b_))
+        o += nw + b_.size
+    assert o == g.size
+    return out
+
+
+@pytest.mark.parametrize("f,H,W,B,train", [(2, 40, 64, 2, True), (4, 45, 70, 1, False), (3, 30, 44, 2, True)])
+def test_f32_gradients_match_oracle(f, H, W, B, train):
+    for name, (gw, gb, rw, rb) in zip(tvae.NAMES, _grad_case("f32", f, H, W, B, train, 40 + f)):
+        ew, eb = normwise(gw, rw), normwise(gb, rb)
+        assert ew <= 1e-4 and eb <= 1e-4, f"{name}: weights {ew:.2e}, bias {eb:.2e}"
+
+
+def test_bf16_gradients_cosine():
+    res = _grad_case("bf16", 2, 40, 64, 2, True, 60)
+    allg = np.concatenate([np.concatenate([gw.ravel(), gb.ravel()]) for (gw, gb, _, _) in res])
+    allr = np.concatenate([np.concatenate([rw.ravel(), rb.ravel()]) for (_, _, rw, rb) in res])
+    cos = float(allg @ allr / (np.linalg.norm(allg) * np.linalg.norm(allr)))
+    assert cos >= 0.999, cos
+    for name, (gw, gb, rw, rb) in zip(tvae.NAMES, res):
+        c = float(gw.ravel() @ rw.ravel() / max(np.linalg.norm(gw) * np.linalg.norm(rw), 1e-30))
+        assert c >= 0.99, (name, c)
+
+
+def test_loss_gradient_through_the_network():
+    # sv_tvae_loss's gradients fed to the backward give d loss / d parameters
+    import paper_2305_11566_amd as sv
+    H, W, f, B = 40, 64, 2, 1
+    p = gen_pair(H, W, 4, 2.0, 20.0, seed=5501)
+    lo, _, _, dsp = oracle.match(p.left, p.right, f, 5, 5, 16)
+    params = _params(71)
+    h3, w3 = _latent_hw(H, W, f)
+    eps = gen_eps((B, h3, w3), seed=9100).astype(np.float32)
+    t = tvae.forward(params, dsp, lo, f, H, W, eps=eps[:, None])
+    gt, noc, occ = p.gt[None].astype(np.float32), p.noc[None], p.occ[None]
+    _, _, _, dout, dmu, dsig = tvae.loss(t["out"], gt, noc, occ, t["mu"][:, 0], t["sigma"][:, 0])
+    ref = tvae.backward(params, t, dout, dmu[:, None], dsig[:, None])
+    net = sv.TableVAE(f, "f32")
+    net.pack(cuda(flat_params(params)))
+    dd, ii, e = cuda(dsp), cuda(lo), cuda(eps)
+    out, ms = net.forward(dd, ii, H, W, eps=e)
+    loss, gdout, gdms = sv.sv_tvae_loss(out, cuda(gt), cuda(noc.astype(np.uint8)), cuda(occ.astype(np.uint8)), ms)
+    g = net.backward(dd, ii, H, W, gdout, eps=e, dmu_sigma=gdms)
+    torch.cuda.synchronize()
+    gref = tvae.flatten([(w_, b_) for (w_, b_) in ref])
+    assert normwise(g.cpu().numpy(), gref) <= 1e-3
