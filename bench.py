@@ -364,6 +364,27 @@ def run_table1(sv, torch, dev, K, Wm, tune=True):
                 "network_mfma_frac": round(tf / PEAK["mfma_TFLOPs"][dt], 4)}
             del net
     out["gflop_per_frame"] = round(table1_flops(1) / 1e9, 4)
+    # training: 512x256 crops, batch 16, f = 2, 5x5 census, D = 16, BF16,
+    # loss of Eqs. (9)-(11), Adam; steps/s and the loss at the start and end
+    from paper_2305_11566_amd.train import TableTrainer, make_pool, batch_indices
+    tr = TableTrainer(flat.cpu().numpy(), factor=2, dtype="bf16")
+    pl, pr, pg, pn, po = make_pool(64, 256, 512, seed0=5000, masks=True)
+    losses = []
+
+    def one():
+        idx = batch_indices(tr.step, 16, 64).to(dev)
+        return tr.train_step(pl[idx], pr[idx], pg[idx], pn[idx], po[idx])
+    for _ in range(5):
+        losses.append(float(one()[0]))
+    torch.cuda.synchronize()
+    nsteps = 100
+    t0 = time.perf_counter()
+    for _ in range(nsteps):
+        l = one()
+    torch.cuda.synchronize()
+    sps = nsteps / (time.perf_counter() - t0)
+    out["train_512x256_b16_bf16"] = {"steps_per_s": round(sps, 2), "steps": 5 + nsteps,
+                                     "loss_first": losses[0], "loss_last": float(l[0])}
     return out
 def run_int8(sv, torch, dev, flat, K, Wm, tune=True):
     """Census + WTA + the INT8 network (per-channel weight scales, dynamic

@@ -104,12 +104,55 @@ class Trainer:
         self.step = int(z["step"])
 
 
-def make_pool(n, H, W, seed0, n_cells=6, dmin=4.0, dmax=24.0, device="cuda"):
+class TableTrainer:
+    """Training of the Table I network with the loss of Eqs. (9)-(11): census +
+    WTA of the batch, the forward with the noise of Eq. (8), sv_tvae_loss,
+    the hand-written backward, Adam on FP32 master weights, repack."""
+
+    def __init__(self, params: np.ndarray, factor=2, dtype="bf16", win=(5, 5), D=16, lr=5e-4,
+                 beta1=0.99, beta2=0.999, eps=1e-8, eps_seed=9000, device="cuda"):
+        self.f, self.win, self.D = factor, tuple(win), D
+        self.lr, self.b1, self.b2, self.adam_eps = lr, beta1, beta2, eps
+        self.eps_seed = eps_seed
+        self.dev = torch.device(device)
+        self.net = ops.TableVAE(factor, dtype, device=device)
+        self.w = torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).to(self.dev)
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.g = torch.empty_like(self.w)
+        self.step = 0
+
+    def coarse(self, left, right):
+        nbits = self.win[0] * self.win[1] - 1
+        cl, cr, low = sv_census_pair(left, right, self.f, *self.win)
+        return sv_cost_wta(cl, cr, self.D, nbits), low
+
+    def train_step(self, left, right, gt, noc, occ):
+        """One optimiser step; gt float32 [B,H,W] px, noc / occ uint8 masks."""
+        B, H, W = left.shape
+        self.net.pack(self.w)
+        disp, low = self.coarse(left, right)
+        gen = torch.Generator(device=self.dev)
+        gen.manual_seed(self.eps_seed + self.step)
+        eps = torch.randn(self.net.latent_shape(B, H, W), generator=gen, device=self.dev, dtype=torch.float32)
+        out, ms = self.net.forward(disp, low, H, W, eps=eps)
+        loss, dout, dms = ops.sv_tvae_loss(out, gt, noc, occ, ms)
+        self.net.backward(disp, low, H, W, dout, eps=eps, dmu_sigma=dms, grad=self.g)
+        self.step += 1
+        sv_adam_step(self.w, self.g, self.m, self.v, self.step, self.lr, self.b1, self.b2, self.adam_eps)
+        return loss
+
+
+def make_pool(n, H, W, seed0, n_cells=6, dmin=4.0, dmax=24.0, device="cuda", masks=False):
+    """Pairs, ground truth and (masks=True) the non-occluded / all-pixel masks as uint8."""
     from synth import gen_pair
     ps = [gen_pair(H, W, n_cells, dmin, dmax, seed=seed0 + i) for i in range(n)]
     t = lambda a, dt: torch.from_numpy(np.stack(a)).to(device=device, dtype=dt)
-    return (t([p.left for p in ps], torch.uint8), t([p.right for p in ps], torch.uint8),
+    base = (t([p.left for p in ps], torch.uint8), t([p.right for p in ps], torch.uint8),
             t([p.gt for p in ps], torch.float32))
+    if not masks:
+        return base
+    return base + (t([p.noc for p in ps], torch.uint8), t([p.occ for p in ps], torch.uint8))
 
 
 def batch_indices(step, batch, pool):

@@ -239,3 +239,16 @@ def test_loss_gradient_through_the_network():
     torch.cuda.synchronize()
     gref = tvae.flatten([(w_, b_) for (w_, b_) in ref])
     assert normwise(g.cpu().numpy(), gref) <= 1e-3
+
+
+def test_training_reduces_the_loss():
+    from paper_2305_11566_amd.train import TableTrainer, make_pool, batch_indices
+    params = _params(81, bias_scale=0.0)
+    tr = TableTrainer(flat_params(params), factor=2, dtype="f32", lr=1e-3)
+    pl, pr, pg, pn, po = make_pool(16, 64, 128, seed0=5000, masks=True)
+    losses = []
+    for _ in range(40):
+        idx = batch_indices(tr.step, 4, 16).to(pl.device)
+        losses.append(float(tr.train_step(pl[idx], pr[idx], pg[idx], pn[idx], po[idx])[0]))
+    assert all(np.isfinite(losses))
+    assert np.mean(losses[-5:]) < 0.8 * np.mean(losses[:5]), losses
