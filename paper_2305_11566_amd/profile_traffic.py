@@ -10,12 +10,16 @@ Two modes:
     plain 64 MiB device copy.  Meant to run under
     ``rocprofv3 --pmc FETCH_SIZE`` and, separately, ``--pmc WRITE_SIZE``.
 
-``python -m paper_2305_11566_amd.profile_traffic summarize FETCH_DIR WRITE_DIR OUT_JSON``
+``python -m paper_2305_11566_amd.profile_traffic summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON``
     Reads the two counter collections, scales each counter by what it reads
     for the copy (bytes moved / counter), and writes per-launch HBM bytes for
     every (layer, configuration) plus census, cost + WTA and the final layer,
     keyed by a hash of the HIP sources so that a reader can tell whether the
     kernels have changed since.
+
+``python -m paper_2305_11566_amd.profile_traffic busy PMC_DIR N``
+    MFMA busy fraction of the last N dispatches of a run profiled with
+    ``rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES ... GRBM_GUI_ACTIVE``.
 """
 from __future__ import annotations
 
@@ -144,6 +148,35 @@ def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) ->
     print(f"wrote {out_json}: {len(entries)} layer entries, scales {s_fetch:.3f} / {s_write:.3f}")
 
 
+def busy(pmc_dir: str, nkernels: int) -> None:
+    """MFMA busy fraction per kernel of the last step of a profiled run.  Per
+    dispatch, GRBM_GUI_ACTIVE comes summed over the eight XCDs (each counts the
+    kernel's duration in cycles) and SQ_VALU_MFMA_BUSY_CYCLES over all 1024
+    SIMDs, so the fraction is busy / (GRBM_GUI_ACTIVE / 8 x 1024).  Prints a
+    markdown table of the last `nkernels` dispatches."""
+    rows = []
+    for path in glob.glob(os.path.join(pmc_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    acc, names = {}, {}
+    for r in rows:
+        d = int(r["Dispatch_Id"])
+        acc.setdefault(d, {})
+        acc[d][r["Counter_Name"]] = acc[d].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        names[d] = r["Kernel_Name"].replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+    ds = sorted(acc)[-nkernels:]
+    print("| kernel | duration us (GRBM / 8 at 2.4 GHz) | MFMA busy cycles | MFMA busy fraction | MFMA instructions / wave | VALU instructions / wave |")
+    print("|---|---|---|---|---|---|")
+    for d in ds:
+        c = acc[d]
+        act = c.get("GRBM_GUI_ACTIVE", 0.0)
+        mb = c.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        w = max(c.get("SQ_WAVES", 1.0), 1.0)
+        frac = mb / (act / 8.0 * 1024.0) if act else 0.0
+        print(f"| `{names[d]}` | {act / 8.0 / 2400.0:.1f} | {mb:.0f} | {frac:.3f} | {c.get('SQ_INSTS_MFMA', 0) / w:.0f} | "
+              f"{c.get('SQ_INSTS_VALU', 0) / w:.0f} |")
+
+
 if __name__ == "__main__":
     here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     if here not in sys.path:
@@ -152,5 +185,7 @@ if __name__ == "__main__":
         run()
     elif sys.argv[1] == "summarize":
         summarize(*sys.argv[2:6])
+    elif sys.argv[1] == "busy":
+        busy(sys.argv[2], int(sys.argv[3]))
     else:
-        raise SystemExit("usage: profile_traffic run | summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON")
+        raise SystemExit("usage: profile_traffic run | summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON | busy PMC_DIR N")
