@@ -465,15 +465,34 @@ struct ConvTile {
                             const int pix = pix0 + k * PSTEP;
                             if (k >= NE || pix >= NPIX) continue;
                             float v[GS];
+                            if constexpr (DT == SV_I8) {
+                                // INT8 codes are defined on the separable FP32 expression
 #pragma unroll
-                            for (int i = 0; i < GS; ++i) {
-                                const float x00 = Elem<SD>::load((const ST *)&ra[j][0] + i);
-                                const float x01 = Elem<SD>::load((const ST *)&ra[j][1] + i);
-                                const float x10 = Elem<SD>::load((const ST *)&ra[j][2] + i);
-                                const float x11 = Elem<SD>::load((const ST *)&ra[j][3] + i);
-                                const float top = (1.f - rq[j].lx) * x00 + rq[j].lx * x01;
-                                const float bot = (1.f - rq[j].lx) * x10 + rq[j].lx * x11;
-                                v[i] = rok[j] ? (1.f - rq[j].ly) * top + rq[j].ly * bot : 0.f;
+                                for (int i = 0; i < GS; ++i) {
+                                    const float x00 = Elem<SD>::load((const ST *)&ra[j][0] + i);
+                                    const float x01 = Elem<SD>::load((const ST *)&ra[j][1] + i);
+                                    const float x10 = Elem<SD>::load((const ST *)&ra[j][2] + i);
+                                    const float x11 = Elem<SD>::load((const ST *)&ra[j][3] + i);
+                                    const float top = (1.f - rq[j].lx) * x00 + rq[j].lx * x01;
+                                    const float bot = (1.f - rq[j].lx) * x10 + rq[j].lx * x11;
+                                    v[i] = rok[j] ? (1.f - rq[j].ly) * top + rq[j].ly * bot : 0.f;
+                                }
+                            } else {
+                                // the four corner weights once per pixel, then one
+                                // multiply and three fused multiply-adds per channel
+                                const float ly = rq[j].ly, lx = rq[j].lx;
+                                const float wy0 = 1.f - ly;
+                                const float w00 = wy0 * (1.f - lx), w01 = wy0 * lx;
+                                const float w10 = ly * (1.f - lx), w11 = ly * lx;
+#pragma unroll
+                                for (int i = 0; i < GS; ++i) {
+                                    const float x00 = Elem<SD>::load((const ST *)&ra[j][0] + i);
+                                    const float x01 = Elem<SD>::load((const ST *)&ra[j][1] + i);
+                                    const float x10 = Elem<SD>::load((const ST *)&ra[j][2] + i);
+                                    const float x11 = Elem<SD>::load((const ST *)&ra[j][3] + i);
+                                    const float r = fmaf(w11, x11, fmaf(w10, x10, fmaf(w01, x01, w00 * x00)));
+                                    v[i] = rok[j] ? r : 0.f;
+                                }
                             }
                             *(vec *)&patch[pix * KCP + cg * GS] = pack_vec<DT, GS>(v, qinv);
                         }
