@@ -505,6 +505,14 @@ sv_status sv_tvae_backward(int dtype, int factor, const void *packed_w, const ui
 sv_status sv_tvae_set_layer_cfg(int layer, int cfg);
 int sv_tvae_num_layers(void);
 
+/* Form of the two stride-2 deconvolutions (D_2, D) in sv_tvae_forward: -1
+ * (default) by output size -- four polyphase 3x3 launches (one per output
+ * parity class, over the un-inserted input) from 131072 output pixels, else
+ * one 5x5 launch over the zero-inserted input; 0 always the zero-inserted
+ * form; 1 always polyphase.  Both compute the same deconvolution (they differ
+ * in FP32 summation order only).  Errors: SV_ERR_RANGE. */
+sv_status sv_tvae_set_deconv_form(int form);
+
 /* Times every tile configuration of each launched layer of sv_tvae_forward
  * alone for this shape (zero weights and inputs; timing does not depend on
  * values), keeps the fastest per layer if the whole pass then runs faster

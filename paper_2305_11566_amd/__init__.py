@@ -33,6 +33,7 @@ from .ops import (  # noqa: F401
     sv_tvae_loss,
     sv_tvae_set_layer_cfg,
     sv_tvae_num_layers,
+    sv_tvae_set_deconv_form,
     sv_tvae_autotune,
     sv_tvae_layer_cfgs,
 )

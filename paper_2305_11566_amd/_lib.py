@@ -92,6 +92,7 @@ _SIGS = {
     "sv_tvae_loss": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _P, _SZ, _P]),
     "sv_tvae_set_layer_cfg": (ctypes.c_int32, [_I, _I]),
     "sv_tvae_num_layers": (_I, []),
+    "sv_tvae_set_deconv_form": (ctypes.c_int32, [_I]),
     "sv_tvae_autotune": (ctypes.c_int32, [_I, _I, _I, _I, _I]),
     "sv_tvae_backward_workspace_bytes": (_SZ, [_I, _I, _I, _I, _I]),
     "sv_tvae_backward": (ctypes.c_int32, [_I, _I, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),

@@ -149,6 +149,7 @@ sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &
     ConvParams p = p0;
     p.ksplit = conv_effective_split(dtype, cfg, p.Cin, (long long)p.B * p.Ho * p.Wo, p.n_pad, p.part,
                                     p.part_bytes);
+    if (p.ophase) p.ksplit = 1;  // a phase launch writes its pixels straight into the full map
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
 }
 

@@ -249,7 +249,7 @@ struct ConvGeo {
     long long sbase[2];
     int hs[2], ws[2];
     long long obase;
-    int n0, oy0, ox0;
+    int n0, oy0, ox0, b;
 };
 
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
@@ -649,7 +649,11 @@ struct ConvTile {
         for (int mb = 0; mb < MBW; ++mb) {
             const int oy = oy0 + wm * MBW + mb, ox = ox0 + r16;
             if (oy >= G.Ho || ox >= G.Wo) continue;
-            const size_t pix = (size_t)(G.obase + (long long)oy * G.Wo + ox);
+            size_t pix = (size_t)(G.obase + (long long)oy * G.Wo + ox);
+            if (p.ophase) {  // one parity class of an interleaved output
+                const int py = (p.ophase - 1) >> 1, px = (p.ophase - 1) & 1;
+                pix = ((size_t)G.b * p.Ho_full + 2 * oy + py) * p.Wo_full + 2 * ox + px;
+            }
 #pragma unroll
             for (int nb = 0; nb < NBW; ++nb) {
                 const int nbase = n0 + (wn * NBW + nb) * 16 + 4 * g;
@@ -706,6 +710,7 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
         G.sbase[i] = (long long)b * p.src[i].hs * p.src[i].ws;
     }
     G.obase = (long long)b * p.Ho * p.Wo;
+    G.b = b;
     G.n0 = (zz % ntn) * TN;
     G.oy0 = by * TH;
     G.ox0 = bx * CT::TW;
@@ -736,6 +741,7 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
             G.sbase[k] = pg.off[lv];
         }
         G.obase = pg.off[p.out_level];
+        G.b = 0;
         const int local = t - cum[i];
         const int tx = cdiv_d(G.Wo, CT::TW), ty = cdiv_d(G.Ho, TH);
         const int nt = local / (tx * ty), r = local - nt * tx * ty;

@@ -121,6 +121,11 @@ struct ConvParams {
     const float *wscale;
     const uint32_t *amax_in[2];
     uint32_t *amax_out;
+    // output phase (uniform launches, never split): 0 = dense output; else
+    // output pixel (oy, ox) of this launch is (2 oy + py, 2 ox + px) of a
+    // Ho_full x Wo_full map, ophase = 1 + 2 py + px (one parity class of a
+    // stride-2 deconvolution)
+    int ophase, Ho_full, Wo_full;
 };
 constexpr int AMAX_SUB = 64;
 

@@ -84,6 +84,9 @@ struct TvShape {
     // projection: the 80 level-1 channels), columns = its outputs; 0 for FE
     int bn_pad[T_NL], bcin_pad[T_NL];
     size_t bw_off[T_NL];
+    // stride-2 deconvolutions (D_2, D) in polyphase form: per output parity
+    // class a 3x3 kernel [9][n_pad][cin_pad] over the un-inserted input
+    size_t ph_off[T_NL][4];
 };
 
 // Launched layers' input rows of the adjoint pack (0: no input gradient).
@@ -116,6 +119,13 @@ TvShape tv_shape(int dtype) {
         s.bw_off[i] = off;
         off = align256(off + (size_t)kLayers[i].k * kLayers[i].k * s.bn_pad[i] * s.bcin_pad[i] * les);
     }
+    for (int i = 0; i < T_NL; ++i)
+        for (int ph = 0; ph < 4; ++ph) {
+            s.ph_off[i][ph] = 0;
+            if (i != T_D2 && i != T_D) continue;
+            s.ph_off[i][ph] = off;
+            off = align256(off + (size_t)9 * s.n_pad[i] * s.cin_pad[i] * s.es);
+        }
     s.bytes = off;
     return s;
 }
@@ -255,6 +265,26 @@ __global__ void k_tv_pack_adj(const AdjJob j, typename Elem<DT>::T *__restrict__
     }
 }
 
+// One parity class (py, px) of a stride-2, padding-2 5x5 deconvolution as a
+// 3x3, padding-1 correlation over the un-inserted input: output 2a + py takes
+// input row a - 1 + t with the weight row u = py + 4 - 2t (none outside 0..4),
+// and likewise for columns.
+template <int DT>
+__global__ void k_tv_pack_phase(const float *__restrict__ w, int cout, int cin, int n_pad, int cin_pad, int py,
+                                int px, typename Elem<DT>::T *__restrict__ dst) {
+    const int total = 9 * n_pad * cin_pad;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % cin_pad;
+        const int o = (e / cin_pad) % n_pad;
+        const int tap = e / (cin_pad * n_pad);
+        const int u = py + 4 - 2 * (tap / 3), v = px + 4 - 2 * (tap % 3);
+        float val = 0.f;
+        if (o < cout && c < cin && u >= 0 && u < TV_K && v >= 0 && v < TV_K)
+            val = w[(((size_t)o * cin + c) * TV_K + u) * TV_K + v];
+        dst[e] = Elem<DT>::make(val);
+    }
+}
+
 __global__ void k_zero_bytes(uint32_t *__restrict__ p, size_t n_words) {
     for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n_words; e += (size_t)gridDim.x * blockDim.x)
         p[e] = 0u;
@@ -326,6 +356,23 @@ sv_status tv_pack(const TvShape &s, const float *params, void *packed, hipStream
     hipLaunchKernelGGL(k_tv_bias, dim3(1), dim3(64), 0, st, params + canon_off(C_Y) + 81 * 25, 1,
                        (float *)(P + s.b_off[T_YP]));
     SV_LAUNCH_CHECK("k_tv_bias");
+    // polyphase packs of the stride-2 deconvolutions
+    for (int li : {T_D2, T_D}) {
+        const int canon = li == T_D2 ? C_D2 : C_D;
+        const CanonLayer &c = kCanon[canon];
+        for (int ph = 0; ph < 4; ++ph) {
+            const int total = 9 * s.n_pad[li] * s.cin_pad[li];
+            const int blocks = std::min((total + 255) / 256, 1024);
+            void *dst = P + s.ph_off[li][ph];
+            const float *w = params + canon_off(canon);
+            switch (s.dtype) {
+            case SV_F32: hipLaunchKernelGGL(k_tv_pack_phase<SV_F32>, dim3(blocks), dim3(256), 0, st, w, c.cout, c.cin, s.n_pad[li], s.cin_pad[li], ph >> 1, ph & 1, (float *)dst); break;
+            case SV_BF16: hipLaunchKernelGGL(k_tv_pack_phase<SV_BF16>, dim3(blocks), dim3(256), 0, st, w, c.cout, c.cin, s.n_pad[li], s.cin_pad[li], ph >> 1, ph & 1, (uint16_t *)dst); break;
+            default: hipLaunchKernelGGL(k_tv_pack_phase<SV_F16>, dim3(blocks), dim3(256), 0, st, w, c.cout, c.cin, s.n_pad[li], s.cin_pad[li], ph >> 1, ph & 1, (uint16_t *)dst); break;
+            }
+            SV_LAUNCH_CHECK("k_tv_pack_phase");
+        }
+    }
     // adjoint packs (the backward pass)
     auto adj = [&](int canon, int layer, bool flip, auto rowmap) -> sv_status {
         AdjJob j{};
@@ -419,6 +466,45 @@ ConvSrc tsrc(const void *p, int C, int pitch, int coff, int hs, int ws, int kind
     return s;
 }
 
+// Form of the stride-2 deconvolutions: -1 by output size (polyphase from
+// TV_PHASE_MIN_PIX output pixels: four launches beat one only when each has
+// enough work), 0 always over the zero-inserted grid, 1 always polyphase.
+std::atomic<int> g_tv_deconv_form{-1};
+constexpr long long TV_PHASE_MIN_PIX = 131072;
+
+bool tv_polyphase(int B, int Ho, int Wo) {
+    const int f = g_tv_deconv_form.load();
+    if (f >= 0) return f == 1;
+    return (long long)B * Ho * Wo >= TV_PHASE_MIN_PIX;
+}
+
+// A stride-2 deconvolution (D_2 or D) as four 3x3 correlations over its
+// input, one per output parity class, each writing its pixels of the
+// interleaved Ho x Wo output.
+sv_status tv_deconv2(const TvShape &s, const void *packed, int li, ConvSrc src, int B, int Hi, int Wi, int Ho,
+                     int Wo, void *out, int out_pitch, int out_coff, const int *cfg, int only, hipStream_t st) {
+    if (only >= 0 && only != li) return SV_OK;
+    for (int ph = 0; ph < 4; ++ph) {
+        const int py = ph >> 1, px = ph & 1;
+        ConvParams p{};
+        p.src[0] = src;
+        p.B = B; p.Hi = Hi; p.Wi = Wi;
+        p.Ho = (Ho - py + 1) / 2; p.Wo = (Wo - px + 1) / 2;
+        if (p.Ho <= 0 || p.Wo <= 0) continue;
+        p.ophase = 1 + ph; p.Ho_full = Ho; p.Wo_full = Wo;
+        p.Cin = src.C;
+        p.Cout = kLayers[li].cout;
+        p.cin_pad = s.cin_pad[li];
+        p.n_pad = s.n_pad[li];
+        p.wpk = (const char *)packed + s.ph_off[li][ph];
+        p.bias = (const float *)((const char *)packed + s.b_off[li]);
+        p.out = out; p.out_pitch = out_pitch; p.out_coff = out_coff;
+        p.act = 1;
+        SV_TRY_STATUS(launch_conv(s.dtype, 3, 1, cfg[li] % conv_num_tiles(), p, st));
+    }
+    return SV_OK;
+}
+
 // One launched layer with configuration cfg[li]; with only >= 0 every other
 // layer is skipped (the autotuner times one layer at a time).
 sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, ConvSrc s1, int B, int Hi,
@@ -491,13 +577,22 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
                            L3, L3C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D1R, tsrc(L3, 80, L3C, 0, h3, w3, SRC_TENSOR, 0), none, B, h3, w3, h3, w3,
                            L3, L3C, 80, 0, 1, part, a.part_bytes, cfg, only, st));
-    // deconvolutions: the zero-inserted grid has 2n - 1 samples per axis
-    SV_TRY_STATUS(tv_layer(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, B, 2 * h3 - 1,
-                           2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
+    // stride-2 deconvolutions: polyphase for large outputs, else one launch over
+    // the zero-inserted grid (2n - 1 samples per axis)
+    if (tv_polyphase(B, h2, w2))
+        SV_TRY_STATUS(tv_deconv2(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_TENSOR, 0), B, h3, w3, h2, w2,
+                                 L2, L2C, 0, cfg, only, st));
+    else
+        SV_TRY_STATUS(tv_layer(s, packed, T_D2, tsrc(L3, 96, L3C, 0, h3, w3, SRC_ZINS, 0), none, B, 2 * h3 - 1,
+                               2 * w3 - 1, h2, w2, L2, L2C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     SV_TRY_STATUS(tv_layer(s, packed, T_D2R, tsrc(L2, 40, L2C, 0, h2, w2, SRC_TENSOR, 0), none, B, h2, w2, h2, w2,
                            L2, L2C, 40, 0, 1, part, a.part_bytes, cfg, only, st));
-    SV_TRY_STATUS(tv_layer(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, B, 2 * h2 - 1,
-                           2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
+    if (tv_polyphase(B, h1, w1))
+        SV_TRY_STATUS(tv_deconv2(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_TENSOR, 0), B, h2, w2, h1, w1,
+                                 L1, L1C, 0, cfg, only, st));
+    else
+        SV_TRY_STATUS(tv_layer(s, packed, T_D, tsrc(L2, 48, L2C, 0, h2, w2, SRC_ZINS, 0), none, B, 2 * h2 - 1,
+                               2 * w2 - 1, h1, w1, L1, L1C, 0, 0, 1, part, a.part_bytes, cfg, only, st));
     // upsampling layer: tap projection of [D | FE_1 | FE_2 | X_0 X_1] (FP32
     // weights; the map is read in its stored dtype), then the gather
     const int sdt = s.dtype == SV_F32 ? 0 : 1 + s.dtype;
@@ -981,6 +1076,12 @@ sv_status sv_tvae_set_layer_cfg(int layer, int cfg) {
 }
 
 int sv_tvae_num_layers(void) { return T_NL; }
+
+sv_status sv_tvae_set_deconv_form(int form) {
+    if (form < -1 || form > 1) return SV_ERR_RANGE;
+    g_tv_deconv_form.store(form);
+    return SV_OK;
+}
 
 size_t sv_tvae_backward_workspace_bytes(int dtype, int factor, int B, int H, int W) {
     if (dtype != SV_F32 && dtype != SV_BF16 && dtype != SV_F16) return 0;

@@ -376,6 +376,10 @@ def sv_tvae_set_layer_cfg(layer: int, cfg: int):
     check(lib().sv_tvae_set_layer_cfg(layer, cfg), "sv_tvae_set_layer_cfg")
 
 
+def sv_tvae_set_deconv_form(form: int):
+    check(lib().sv_tvae_set_deconv_form(form), "sv_tvae_set_deconv_form")
+
+
 def sv_tvae_num_layers() -> int:
     return int(lib().sv_tvae_num_layers())
 

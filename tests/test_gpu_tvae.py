@@ -58,7 +58,7 @@ def _rand_inputs(B, H, W, f, seed):
             rng.integers(0, 256, (B, h, w)).astype(np.uint8))
 
 
-def test_f32_full_size_1242x375():
+def test_f32_full_size_1242x375(deconv_form):
     p = gen_config(2)
     lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
     _compare(4, 375, 1242, d, lo)
@@ -70,6 +70,14 @@ def test_f32_table_factor_2():
     _compare(2, 128, 256, d, lo)
 
 
+@pytest.fixture(params=[0, 1], ids=["zero_inserted", "polyphase"])
+def deconv_form(request):
+    import paper_2305_11566_amd as sv
+    sv.sv_tvae_set_deconv_form(request.param)
+    yield request.param
+    sv.sv_tvae_set_deconv_form(-1)
+
+
 @pytest.mark.parametrize("H,W,f,B", [
     (45, 70, 4, 2),     # every level ragged, odd deconvolution outputs
     (37, 53, 2, 1),
@@ -79,19 +87,19 @@ def test_f32_table_factor_2():
     (64, 512, 4, 1),    # wide: many column tiles
     (100, 36, 2, 2),    # tall
 ])
-def test_f32_shapes(H, W, f, B):
+def test_f32_shapes(H, W, f, B, deconv_form):
     d, im = _rand_inputs(B, H, W, f, H * W + f)
     _compare(f, H, W, d, im, seed=H)
 
 
-def test_f32_training_eps():
+def test_f32_training_eps(deconv_form):
     H, W, f, B = 48, 80, 2, 2
     d, im = _rand_inputs(B, H, W, f, 3)
     eps = gen_eps((B,) + _latent_hw(H, W, f), seed=9001).astype(np.float32)
     _compare(f, H, W, d, im, eps=eps)
 
 
-def test_tile_shapes_bitwise_identical():
+def test_tile_shapes_bitwise_identical(deconv_form):
     # the reduction order is fixed by the base chunk and the split, not by the
     # tile shape: every tile shape gives the same bits at a given split, and a
     # split stays within the FP32 bar of the unsplit pass
@@ -122,7 +130,7 @@ def test_tile_shapes_bitwise_identical():
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
-def test_reduced_precision_epe(dtype):
+def test_reduced_precision_epe(dtype, deconv_form):
     p = gen_config(1)
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     params = _params(7)
@@ -252,3 +260,19 @@ def test_training_reduces_the_loss():
         losses.append(float(tr.train_step(pl[idx], pr[idx], pg[idx], pn[idx], po[idx])[0]))
     assert all(np.isfinite(losses))
     assert np.mean(losses[-5:]) < 0.8 * np.mean(losses[:5]), losses
+
+
+def test_deconvolution_forms_agree():
+    # the polyphase and the zero-inserted forms compute the same deconvolution
+    import paper_2305_11566_amd as sv
+    H, W, f, B = 45, 70, 4, 2
+    d, im = _rand_inputs(B, H, W, f, 31)
+    params = _params(9)
+    try:
+        sv.sv_tvae_set_deconv_form(0)
+        a, _ = _gpu("f32", f, params, d, im, H, W)
+        sv.sv_tvae_set_deconv_form(1)
+        b, _ = _gpu("f32", f, params, d, im, H, W)
+    finally:
+        sv.sv_tvae_set_deconv_form(-1)
+    assert normwise(b, a) <= 1e-6
