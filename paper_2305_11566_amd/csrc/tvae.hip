@@ -478,6 +478,90 @@ bool tv_polyphase(int B, int Ho, int Wo) {
     return (long long)B * Ho * Wo >= TV_PHASE_MIN_PIX;
 }
 
+// Feature extraction (FE_1 = conv5x5(X_0), FE_2 = conv5x5(X_1), 32 outputs
+// each, leaky ReLU) as a direct stencil: with one input channel per branch an
+// MFMA reduction would run almost empty.  A workgroup owns 16 x 4 coarse
+// pixels; the X_0 / X_1 patch with its 2-pixel halo is built in LDS from the
+// uint8 maps; wave g accumulates outputs 16g .. 16g + 15 (waves 0-1: FE_1 on
+// X_0, 2-3: FE_2 on X_1) of every pixel in FP32 from weights staged once in
+// LDS as FP32 [tap][output] (the packed layer: rows 0..31 on channel 0, rows
+// 32..63 on channel 1), then stores them into channels 16..79 of the level-1
+// map.
+constexpr int FE_TW = 16, FE_TH = 4, FE_PW = FE_TW + 4, FE_PH = FE_TH + 4;
+
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_tv_fe(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, int h, int w, float scale0,
+        const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad, const float *__restrict__ bias,
+        typename Elem<DT>::T *__restrict__ out) {
+    __shared__ float xs[2][FE_PH * FE_PW];
+    __shared__ __attribute__((aligned(16))) float wsh[TV_TAPS * 64];  // [tap][output], FP32
+    const int b = blockIdx.z;
+    const int x0 = blockIdx.x * FE_TW, y0 = blockIdx.y * FE_TH;
+    const size_t ib = (size_t)b * h * w;
+    for (int e = threadIdx.x; e < TV_TAPS * 64; e += 256) {
+        const int t = e >> 6, o = e & 63;
+        wsh[e] = Elem<DT>::load(wpk + ((size_t)t * n_pad + o) * cin_pad + (o >> 5));
+    }
+    for (int e = threadIdx.x; e < FE_PH * FE_PW; e += 256) {
+        const int py = e / FE_PW, px = e - py * FE_PW;
+        const int y = y0 + py - 2, x = x0 + px - 2;
+        float a = 0.f, c = 0.f;
+        if (y >= 0 && y < h && x >= 0 && x < w) {
+            a = scale0 * (float)disp[ib + (size_t)y * w + x];
+            c = (float)img[ib + (size_t)y * w + x] * (1.0f / 256.0f);
+        }
+        xs[0][e] = a;
+        xs[1][e] = c;
+    }
+    __syncthreads();
+    // the output group is the wave's: the weight reads below are the same LDS
+    // address for the whole wave (a broadcast)
+    const int lane = threadIdx.x & 63, grp = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int tx = lane & (FE_TW - 1), ty = lane / FE_TW;
+    const int x = x0 + tx, y = y0 + ty;
+    if (x >= w || y >= h) return;
+    const int ch = grp >> 1, o0 = grp * 16;
+    const float *xp = xs[ch];
+    float acc[16];
+#pragma unroll
+    for (int o = 0; o < 16; ++o) acc[o] = bias[o0 + o];
+#pragma unroll
+    for (int t = 0; t < TV_TAPS; ++t) {
+        const int u = t / TV_K, v = t % TV_K;
+        const float xv = xp[(ty + u) * FE_PW + tx + v];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const f32x4 wv = *(const f32x4 *)&wsh[t * 64 + o0 + 4 * q];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[4 * q + i] = fmaf(wv[i], xv, acc[4 * q + i]);
+        }
+    }
+    typename Elem<DT>::T *op = out + ((ib + (size_t)y * w + x) * L1C + 16 + o0);
+#pragma unroll
+    for (int o = 0; o < 16; ++o) {
+        const float r = acc[o] > 0.f ? acc[o] : 0.1f * acc[o];
+        op[o] = Elem<DT>::make(r);
+    }
+}
+
+sv_status tv_fe(const TvShape &s, const void *packed, const uint8_t *disp, const uint8_t *img, int B, int h, int w,
+                int f, void *L1, const int *cfg, int only, hipStream_t st) {
+    (void)cfg;
+    if (only >= 0 && only != T_FE) return SV_OK;
+    const dim3 grid(cdiv(w, FE_TW), cdiv(h, FE_TH), B);
+    const float sc = (float)f / 256.0f;
+    const float *bias = (const float *)((const char *)packed + s.b_off[T_FE]);
+    const void *wp = (const char *)packed + s.w_off[T_FE];
+    switch (s.dtype) {
+    case SV_F32: hipLaunchKernelGGL(k_tv_fe<SV_F32>, grid, dim3(256), 0, st, disp, img, h, w, sc, (const float *)wp, s.n_pad[T_FE], s.cin_pad[T_FE], bias, (float *)L1); break;
+    case SV_BF16: hipLaunchKernelGGL(k_tv_fe<SV_BF16>, grid, dim3(256), 0, st, disp, img, h, w, sc, (const uint16_t *)wp, s.n_pad[T_FE], s.cin_pad[T_FE], bias, (uint16_t *)L1); break;
+    default: hipLaunchKernelGGL(k_tv_fe<SV_F16>, grid, dim3(256), 0, st, disp, img, h, w, sc, (const uint16_t *)wp, s.n_pad[T_FE], s.cin_pad[T_FE], bias, (uint16_t *)L1); break;
+    }
+    SV_LAUNCH_CHECK("k_tv_fe");
+    return SV_OK;
+}
+
 // A stride-2 deconvolution (D_2 or D) as four 3x3 correlations over its
 // input, one per output parity class, each writing its pixels of the
 // interleaved Ho x Wo output.
@@ -548,7 +632,7 @@ sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t 
     x0.ptr = disp; x0.img = img; x0.kind = SRC_X0; x0.C = 2; x0.hs = h1; x0.ws = w1;
     x0.scale0 = (float)f / 256.0f;
     // feature extraction: [FE_1 | FE_2] into level 1, channels 16..79
-    SV_TRY_STATUS(tv_layer(s, packed, T_FE, x0, none, B, h1, w1, h1, w1, L1, L1C, 16, 0, 1, part, a.part_bytes, cfg, only, st));
+    SV_TRY_STATUS(tv_fe(s, packed, disp, img, B, h1, w1, f, L1, cfg, only, st));
     // encoder
     SV_TRY_STATUS(tv_layer(s, packed, T_EN1, tsrc(L1, 64, L1C, 16, h1, w1, SRC_TENSOR, 0), none, B, h1, w1, h2, w2,
                            L2, L2C, 16, 0, 1, part, a.part_bytes, cfg, only, st));
@@ -1149,8 +1233,10 @@ sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
         g_tv_tuned.erase(std::make_tuple(dtype, factor, B, H, W));
     }
     tv_layer_cfgs(dtype, factor, B, H, W, base);
+    for (int i = 0; i < T_NL; ++i) best[i] = base[i];
     const int reps = B >= 16 ? 4 : 12;
     for (int li = 0; li < T_NL && r == SV_OK; ++li) {
+        if (li == T_FE) continue;  // a direct stencil, no tile configuration
         const int dt = li == T_YP ? SV_F32 : dtype;
         const int k = kOutLevel[li];
         const long long npix = (long long)B * lv.h[k] * lv.w[k];
