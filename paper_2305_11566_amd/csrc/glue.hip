@@ -116,24 +116,21 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
         tb.cy1[r] = y1;
         tb.cly[r] = ly;
     }
-    // T and the coarse disparity on the window.  Work item = (group of three
-    // taps, coarse pixel), the tap group uniform across each wave (the pixel
-    // count is padded to a multiple of 64), so the weights are scalar loads;
-    // an item's channels are loaded 32 at a time, all in flight before any
-    // product.
+    // T and the coarse disparity on the window.  Work item = one coarse pixel:
+    // its channels are loaded once, 32 at a time (all in flight before any
+    // product), and feed the nine tap projections as fused multiply-adds; the
+    // weights are the same for every thread (scalar loads).
     const float inv_pw = 1.0f / (float)pw;
-    const int npx = ph * pw, qp = (npx + 63) & ~63;
-    for (int e = tid; e < 3 * qp; e += FIN_THREADS) {
-        const int tg = __builtin_amdgcn_readfirstlane((e >= qp) + (e >= 2 * qp));
-        const int q = e - tg * qp;
-        if (q >= npx) continue;
+    const int npx = ph * pw;
+    for (int q = tid; q < npx; q += FIN_THREADS) {
         const int r = fin_div(q, inv_pw), c = q - r * pw;
         const size_t gp = (size_t)(ya + r) * w + xa + c;
         const float dv = (float)db[gp];
         const float x0d = scale0 * dv, x0i = (float)ib[gp] * (1.0f / 256.0f);
         const typename Elem<DT>::T *g = G0 + gp * c1;
-        const float *wg = wF + (size_t)(3 * tg) * wf_pitch;
-        float a[3] = {0.f, 0.f, 0.f};
+        float a[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a[t] = 0.f;
         for (int c0 = 0; c0 < c1; c0 += 32) {
             float v[32];
 #pragma unroll
@@ -149,24 +146,24 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
                 }
             }
 #pragma unroll
-            for (int t = 0; t < 3; ++t) {
-                const float *wt = wg + (size_t)t * wf_pitch + c0;
+            for (int t = 0; t < 9; ++t) {
+                const float *wt = wF + (size_t)t * wf_pitch + c0;
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
                     if (c0 + 8 * k < c1) {
 #pragma unroll
-                        for (int i = 0; i < 8; ++i) a[t] += wt[8 * k + i] * v[8 * k + i];
+                        for (int i = 0; i < 8; ++i) a[t] = fmaf(wt[8 * k + i], v[8 * k + i], a[t]);
                     }
                 }
             }
         }
 #pragma unroll
-        for (int t = 0; t < 3; ++t) {
-            const float *wt = wg + (size_t)t * wf_pitch + c1;
-            a[t] += wt[0] * x0d + wt[1] * x0i;
-            sT[((3 * tg + t) * PHm + r) * PWm + c] = a[t];
+        for (int t = 0; t < 9; ++t) {
+            const float *wt = wF + (size_t)t * wf_pitch + c1;
+            a[t] = fmaf(wt[1], x0i, fmaf(wt[0], x0d, a[t]));
+            sT[(t * PHm + r) * PWm + c] = a[t];
         }
-        if (tg == 0) sd[r * PWm + c] = dv;
+        sd[r * PWm + c] = dv;
     }
     __syncthreads();
     // vertical pass: S_v(Y, x) and the residual base's row interpolation D(Y, x)
