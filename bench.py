@@ -85,8 +85,8 @@ def make_inputs(B, device):
     if (B, str(device)) in _INPUTS:
         return _INPUTS[(B, str(device))]
     import torch
-    from synth import gen_config
-    pairs = [gen_config(2, i) for i in range(B)]
+    from synth import gen_preset
+    pairs = [gen_preset("pair1242x375", i) for i in range(B)]
     left = torch.from_numpy(np.stack([p.left for p in pairs])).to(device)
     right = torch.from_numpy(np.stack([p.right for p in pairs])).to(device)
     gt = np.stack([p.gt for p in pairs])
@@ -158,9 +158,9 @@ def _oracle_frame(i):
     input generation is outside the timed part."""
     import oracle
     from oracle import vae
-    from synth import gen_config
+    from synth import gen_preset
     params, _ = make_params()
-    p = gen_config(2, i)
+    p = gen_preset("pair1242x375", i)
     t0 = time.perf_counter()
     lo, _, _, d = oracle.match(p.left, p.right, F, WIN_W, WIN_H, D)
     vae.forward(params, d, lo, F, H, W)
@@ -447,10 +447,10 @@ def run_int8(sv, torch, dev, flat, K, Wm, tune=True):
 def run_extras(sv, torch, dev, flat, K, Wm):
     """Uneven batch (64 pairs, one graph) vs the per-pair loop; BF16 / FP16 vs
     FP32 end-point error with briefly trained weights; training steps/s."""
-    from synth import gen_config
+    from synth import gen_preset
     out = {}
     # -- 64 uneven pairs, BF16 network ---------------------------------------------------
-    ps = [gen_config(4, i) for i in range(64)]
+    ps = [gen_preset("uneven64", i) for i in range(64)]
     pairs = [(torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev), p.D) for p in ps]
     maxH, maxW, maxD = max(p.left.shape[0] for p in ps), max(p.left.shape[1] for p in ps), max(p.D for p in ps)
     sv.sv_autotune(C1, C2, C3, LAT, F, "bf16", 8, maxH, maxW, maxD, WIN_W, WIN_H)
@@ -515,7 +515,7 @@ def run_extras(sv, torch, dev, flat, K, Wm):
     out["train_512x256_b16_bf16"] = {"steps_per_s": round(sps, 2), "steps": steps,
                                      "ms_per_step": round(1e3 / sps, 4)}
     w_trained = tr.w
-    vp = [gen_config(3, i) for i in range(8)]
+    vp = [gen_preset("batch8_256x128", i) for i in range(8)]
     vl = torch.from_numpy(np.stack([p.left for p in vp])).to(dev)
     vr = torch.from_numpy(np.stack([p.right for p in vp])).to(dev)
     vg = torch.from_numpy(np.stack([p.gt for p in vp])).to(dev)

@@ -55,10 +55,10 @@ def run() -> None:
     import torch
 
     import paper_2305_11566_amd as sv
-    from synth import gen_config, he_init_params
+    from synth import gen_preset, he_init_params
 
     dev = torch.device("cuda:0")
-    p = gen_config(2, 0)
+    p = gen_preset("pair1242x375", 0)
     left = torch.from_numpy(p.left[None]).to(dev)
     right = torch.from_numpy(p.right[None]).to(dev)
     shapes = [(C1, 2, 3), (C2, C1, 3), (C3, C2, 3), (2 * LAT, C3, 1), (C3, LAT, 1),

@@ -7,11 +7,11 @@ CPU oracle's tests and the GPU path's tests and bench can take their inputs
 from here without sharing any of the method's code.
 """
 from .stereo import (  # noqa: F401
-    CONFIGS,
+    PRESETS,
     StereoPair,
     gen_pair,
     gen_shift_pair,
-    gen_config,
+    gen_preset,
     he_init_params,
     gen_eps,
 )

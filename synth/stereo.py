@@ -13,18 +13,19 @@ import dataclasses
 import numpy as np
 
 # The five workload presets.  Shapes, factors and windows per preset; sizes of
-# the uneven batch are drawn in gen_config.
-CONFIGS = {
-    1: dict(H=128, W=256, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5, win_h=5,
-            D=16, channels=(16, 32, 64), latent=64, batch=1),
-    2: dict(H=375, W=1242, n_cells=18, dmin=0.0, dmax=190.0, factor=4, win_w=9, win_h=7,
-            D=48, channels=(32, 64, 128), latent=128, batch=1),
-    3: dict(H=128, W=256, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5, win_h=5,
-            D=16, channels=(16, 32, 64), latent=64, batch=8),
-    4: dict(n_cells=18, factor=4, win_w=9, win_h=7, channels=(32, 64, 128), latent=128,
-            batch=64),
-    5: dict(H=256, W=512, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5, win_h=5,
-            D=16, channels=(16, 32, 64), latent=64, batch=16),
+# the uneven batch are drawn in gen_preset.
+# Workload presets; pair `index` of a preset has seed seed0 + index.
+PRESETS = {
+    "pair256x128": dict(seed0=1000, H=128, W=256, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5,
+                        win_h=5, D=16, channels=(16, 32, 64), latent=64, batch=1),
+    "pair1242x375": dict(seed0=2000, H=375, W=1242, n_cells=18, dmin=0.0, dmax=190.0, factor=4, win_w=9,
+                         win_h=7, D=48, channels=(32, 64, 128), latent=128, batch=1),
+    "batch8_256x128": dict(seed0=3000, H=128, W=256, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5,
+                           win_h=5, D=16, channels=(16, 32, 64), latent=64, batch=8),
+    "uneven64": dict(seed0=4000, n_cells=18, factor=4, win_w=9, win_h=7, channels=(32, 64, 128), latent=128,
+                     batch=64),
+    "crops512x256": dict(seed0=5000, H=256, W=512, n_cells=6, dmin=4.0, dmax=24.0, factor=2, win_w=5,
+                         win_h=5, D=16, channels=(16, 32, 64), latent=64, batch=16),
 }
 
 
@@ -154,11 +155,13 @@ def gen_shift_pair(H: int, W: int, shift: int, seed: int) -> StereoPair:
     return StereoPair(left=left, right=right, gt=gt, noc=noc, occ=np.ones((H, W), dtype=bool))
 
 
-def gen_config(k: int, index: int = 0) -> StereoPair:
-    """Pair ``index`` of preset ``k`` (seed 1000*k + index)."""
-    seed = 1000 * k + index
-    c = CONFIGS[k]
-    if k == 4:
+def gen_preset(name: str, index: int = 0) -> StereoPair:
+    """Pair ``index`` of workload preset ``name`` (seed seed0 + index).  The
+    uneven preset draws its 64 sizes (W = 8 U{80..160}, H = 8 U{24..48}) from
+    seed 4999 and a disparity range of a quarter of the width."""
+    c = PRESETS[name]
+    seed = c["seed0"] + index
+    if name == "uneven64":
         size_rng = _rng(4999)
         Ws = 8 * size_rng.integers(80, 161, size=64)
         Hs = 8 * size_rng.integers(24, 49, size=64)

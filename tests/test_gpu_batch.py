@@ -9,7 +9,7 @@ import torch
 
 import oracle
 from oracle import vae
-from synth import gen_config, gen_pair
+from synth import gen_preset, gen_pair
 from tests.gpu_util import cuda, flat_params, normwise, vae_params
 
 pytestmark = pytest.mark.gpu
@@ -79,7 +79,7 @@ def test_uneven_workload_pairs_subset():
     params = vae_params(C, L, seed=15)
     ref = sv.Refiner(*C, L, F, "bf16")
     ref.pack(cuda(flat_params(params)))
-    ps = [gen_config(4, i) for i in range(0, 64, 8)]
+    ps = [gen_preset("uneven64", i) for i in range(0, 64, 8)]
     pairs = [(cuda(p.left), cuda(p.right), p.D) for p in ps]
     plan = sv.BatchPlan(*C, L, F, "bf16", 64, 384, 1280, 80, WW, WH)
     outs = plan.run(pairs, ref.packed)

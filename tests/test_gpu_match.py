@@ -4,7 +4,7 @@ import pytest
 import torch
 
 import oracle
-from synth import gen_config, gen_pair
+from synth import gen_preset, gen_pair
 from tests.gpu_util import bits, cuda
 
 pytestmark = pytest.mark.gpu
@@ -32,16 +32,16 @@ def _check(left, right, f, ww, wh, D):
     assert (gd == d).all(), f"disparity: {np.sum(gd != d)} of {d.size} differ"
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", ["pair256x128", "pair1242x375"])
 def test_workload_pairs(k):
-    p = gen_config(k)
-    c = {1: (2, 5, 5, 16), 2: (4, 9, 7, 48)}[k]
+    p = gen_preset(k)
+    c = {"pair256x128": (2, 5, 5, 16), "pair1242x375": (4, 9, 7, 48)}[k]
     _check(p.left, p.right, *c)
 
 
 def test_uneven_batch_pairs():
     for i in (0, 7, 63):
-        p = gen_config(4, i)
+        p = gen_preset("uneven64", i)
         _check(p.left, p.right, 4, 9, 7, p.D)
 
 
@@ -90,7 +90,7 @@ def test_identical_images_zero():
 @pytest.mark.parametrize("dsplit", [1, 2, 4, 8])
 def test_lane_split_variants_identical(dsplit):
     import paper_2305_11566_amd as sv
-    p = gen_config(2)
+    p = gen_preset("pair1242x375")
     try:
         sv.sv_set_cost_wta_split(dsplit)
         _check(p.left, p.right, 4, 9, 7, 48)
@@ -99,7 +99,7 @@ def test_lane_split_variants_identical(dsplit):
 
 
 def test_determinism_repeat():
-    p = gen_config(2)
+    p = gen_preset("pair1242x375")
     a = _run_gpu(p.left[None], p.right[None], 4, 9, 7, 48)
     b = _run_gpu(p.left[None], p.right[None], 4, 9, 7, 48)
     for x, y in zip(a, b):

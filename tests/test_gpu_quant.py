@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from oracle import quant, vae
-from synth import gen_config
+from synth import gen_preset
 from tests.gpu_util import cuda, flat_params, normwise, vae_params
 
 pytestmark = pytest.mark.gpu
@@ -40,14 +40,14 @@ def _compare(C, L, f, H, W, disp, img, seed=7):
     return out, t, params
 
 
-def test_i8_workload1():
-    p = gen_config(1)
+def test_i8_256x128():
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     _compare((16, 32, 64), 64, 2, 128, 256, d, lo)
 
 
-def test_i8_workload2_full_size():
-    p = gen_config(2)
+def test_i8_1242x375_full_size():
+    p = gen_preset("pair1242x375")
     lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
     _compare((32, 64, 128), 128, 4, 375, 1242, d, lo)
 
@@ -94,7 +94,7 @@ def test_i8_tile_shapes_bitwise_identical():
 
 
 def test_i8_epe_against_fp32():
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     C, L = (16, 32, 64), 64
     params = vae_params(C, L, 7)

@@ -5,7 +5,7 @@ import pytest
 import torch
 
 import oracle
-from synth import gen_config, gen_pair
+from synth import gen_preset, gen_pair
 from tests.gpu_util import bits, cuda
 
 pytestmark = pytest.mark.gpu
@@ -35,10 +35,10 @@ def _census_pair(left, right, f, ww, wh):
     return oracle.census(lo_l, ww, wh), oracle.census(lo_r, ww, wh)
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", ["pair256x128", "pair1242x375"])
 def test_workload_pairs(k):
-    p = gen_config(k)
-    f, ww, wh, D = {1: (2, 5, 5, 16), 2: (4, 9, 7, 48)}[k]
+    p = gen_preset(k)
+    f, ww, wh, D = {"pair256x128": (2, 5, 5, 16), "pair1242x375": (4, 9, 7, 48)}[k]
     cl, cr = _census_pair(p.left[None], p.right[None], f, ww, wh)
     _check(cl, cr, D, ww * wh - 1, 10, 120)
 
@@ -46,7 +46,7 @@ def test_workload_pairs(k):
 def test_uneven_batch_pairs_wide_ranges():
     # the 64-pair workload's ranges reach 80 (two and more disparities per lane)
     for i in (0, 7, 63):
-        p = gen_config(4, i)
+        p = gen_preset("uneven64", i)
         cl, cr = _census_pair(p.left[None], p.right[None], 4, 9, 7)
         _check(cl, cr, p.D, 62, 10, 120)
 
@@ -71,7 +71,7 @@ def test_edge_shapes(h, w, D, P1, P2):
 
 def test_sgm_then_network_runs_and_is_deterministic():
     import paper_2305_11566_amd as sv
-    p = gen_config(2)
+    p = gen_preset("pair1242x375")
     l, r = cuda(p.left[None]), cuda(p.right[None])
     cl, cr, low = sv.sv_census_pair(l, r, 4, 9, 7)
     a = sv.sv_smp_median(sv.sv_sgm(cl, cr, 48, 62, 10, 120), 48)
@@ -80,11 +80,11 @@ def test_sgm_then_network_runs_and_is_deterministic():
     assert torch.equal(a, b)
 
 
-@pytest.mark.parametrize("k", [1, 2])
+@pytest.mark.parametrize("k", ["pair256x128", "pair1242x375"])
 def test_zncc_cost_and_sgm_workload_pairs(k):
     import paper_2305_11566_amd as sv
-    p = gen_config(k)
-    f, ww, wh, D = {1: (2, 5, 5, 16), 2: (4, 9, 7, 48)}[k]
+    p = gen_preset(k)
+    f, ww, wh, D = {"pair256x128": (2, 5, 5, 16), "pair1242x375": (4, 9, 7, 48)}[k]
     lo_l, lo_r = oracle.downsample(p.left[None], f), oracle.downsample(p.right[None], f)
     tl, tr = cuda(lo_l), cuda(lo_r)
     c = sv.sv_zncc_cost(tl, tr, D, ww, wh)

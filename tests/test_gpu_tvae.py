@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from oracle import tvae
-from synth import gen_config, gen_pair, gen_eps, he_init_params
+from synth import gen_preset, gen_pair, gen_eps, he_init_params
 from tests.gpu_util import cuda, flat_params, normwise
 
 pytestmark = pytest.mark.gpu
@@ -59,13 +59,13 @@ def _rand_inputs(B, H, W, f, seed):
 
 
 def test_f32_full_size_1242x375(deconv_form):
-    p = gen_config(2)
+    p = gen_preset("pair1242x375")
     lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
     _compare(4, 375, 1242, d, lo)
 
 
 def test_f32_table_factor_2():
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     _compare(2, 128, 256, d, lo)
 
@@ -131,7 +131,7 @@ def test_tile_shapes_bitwise_identical(deconv_form):
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_reduced_precision_epe(dtype, deconv_form):
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     params = _params(7)
     t = tvae.forward(params, d, lo, 2, 128, 256)

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 from oracle import vae
-from synth import gen_config, gen_pair, gen_eps
+from synth import gen_preset, gen_pair, gen_eps
 from tests.gpu_util import cuda, flat_params, normwise, vae_params
 
 pytestmark = pytest.mark.gpu
@@ -51,14 +51,14 @@ def _compare(C, L, f, H, W, disp, img, seed=7, eps=None, dtype="f32", tol=TOL_F3
     return e_out, out, t
 
 
-def test_f32_workload1():
-    p = gen_config(1)
+def test_f32_256x128():
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     _compare((16, 32, 64), 64, 2, 128, 256, d, lo)
 
 
-def test_f32_workload2_full_size():
-    p = gen_config(2)
+def test_f32_1242x375_full_size():
+    p = gen_preset("pair1242x375")
     lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
     _compare((32, 64, 128), 128, 4, 375, 1242, d, lo)
 
@@ -79,7 +79,7 @@ def test_f32_shapes(H, W, f, C, L, B):
 
 
 def test_f32_training_forward_with_eps():
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     eps = gen_eps((1, 8, 16, 64), seed=9000)
     _compare((16, 32, 64), 64, 2, 128, 256, d, lo, eps=eps)
@@ -89,7 +89,7 @@ def test_f32_training_forward_with_eps():
 def test_reduced_precision_epe(dtype):
     """Mean end-point error against the FP64 oracle, in full-res px; He-init
     weights make the residual large, so the bound here is loose."""
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     params = vae_params((16, 32, 64), 64, 7)
     t = vae.forward(params, d, lo, 2, 128, 256)
@@ -142,7 +142,7 @@ def test_split_reduction_against_oracle():
     within 1e-5 normwise of the oracle at the paper-sized shape."""
     import paper_2305_11566_amd as sv
     names = [sv.sv_conv_cfg_name(c) for c in range(sv.sv_num_layer_cfgs())]
-    p = gen_config(2)
+    p = gen_preset("pair1242x375")
     lo, _, _, d = oracle.match(p.left, p.right, 4, 9, 7, 48)
     params = vae_params((32, 64, 128), 128, 7002)
     t = vae.forward(params, d, lo, 4, 375, 1242)

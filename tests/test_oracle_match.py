@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import gen_pair, gen_shift_pair, gen_config
+from synth import gen_pair, gen_shift_pair, gen_preset
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -209,7 +209,7 @@ def test_integer_shift_recovered(shift, f, ww, wh, D):
 
 
 def test_disparity_never_exceeds_column():
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     _, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     j = np.arange(d.shape[2])[None, None, :]
     assert (d <= j).all()

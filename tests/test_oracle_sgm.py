@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import gen_config
+from synth import gen_preset
 
 
 def _rand_cost(rng, B, h, w, D, hi=40):
@@ -148,7 +148,7 @@ def test_median_matches_numpy_median():
 def test_sgm_lowers_the_error_on_the_workload_pair():
     # smoothing along paths helps on piecewise-planar scenes: the refined map
     # beats plain winner-take-all against the ground truth at the reduced size
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     lo, cl, cr, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     _, raw, post = oracle.match_sgm(p.left, p.right, 2, 5, 5, 16, 10, 120)
     gt = (p.gt[::2, ::2] / 2)[:d.shape[1], :d.shape[2]]

@@ -1,7 +1,7 @@
 """Seeded generator: determinism, ranges and warp consistency."""
 import numpy as np
 
-from synth import gen_pair, gen_config, gen_shift_pair, he_init_params, gen_eps
+from synth import gen_pair, gen_preset, gen_shift_pair, he_init_params, gen_eps
 
 
 def test_deterministic_per_seed():
@@ -12,11 +12,11 @@ def test_deterministic_per_seed():
 
 
 def test_ranges_and_masks():
-    p = gen_config(1)
+    p = gen_preset("pair256x128")
     assert p.left.shape == (128, 256) and p.left.dtype == np.uint8
     assert p.gt.min() >= 4.0 - 1e-5 and p.gt.max() <= 24.0 + 1e-5
     assert p.occ.all() and 0.5 < p.noc.mean() < 1.0
-    p2 = gen_config(2)
+    p2 = gen_preset("pair1242x375")
     assert p2.left.shape == (375, 1242) and p2.D == 48 and p2.gt.max() <= 190.0 + 1e-4
 
 
@@ -31,7 +31,7 @@ def test_warp_consistency_on_visible_pixels():
 
 
 def test_uneven_batch_sizes():
-    sizes = [gen_config(4, i).left.shape for i in range(4)]
+    sizes = [gen_preset("uneven64", i).left.shape for i in range(4)]
     for (H, W) in sizes:
         assert H % 8 == 0 and W % 8 == 0 and 192 <= H <= 384 and 640 <= W <= 1280
     assert len(set(sizes)) > 1
