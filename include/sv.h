@@ -372,11 +372,24 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
 sv_status sv_set_layer_cfg(int layer, int cfg);
 int sv_num_layer_cfgs(void);
 
+/* 1 (the default): an inference pass of sv_vae_forward (eps and saved NULL;
+ * compute dtype FP32, BF16 or FP16; c3 and L at most 256, multiples of 16
+ * for FP32 and of 32 for 16-bit types) runs the
+ * latent head (Table I's latent layer, Eq. (8) with z = mu) and G3 as one
+ * kernel over the coarsest level:
+ * both are 1x1 convolutions, so a workgroup keeps E3 and then mu of its
+ * pixels in LDS.  The results are bitwise those of the two layers run one by
+ * one without a split; their tile configurations are then unused and the
+ * pair is profiled as stage 5 (stage 7 records nothing).  0: always two
+ * launches.  Process-wide.  Errors: SV_ERR_RANGE. */
+sv_status sv_set_latent_fusion(int on);
+
 /*
  * Profiling: after sv_profile_enable(max_calls) (1..4096), each of the first
  * max_calls launches of every stage records a hipEvent pair around itself on
  * its stream.  Stages: 0 census, 1 cost + WTA, then the network's launches
- * 2 E1, 3 E2, 4 E3, 5 HEAD, 6 reparameterisation (training), 7 G3, 8 G2,
+ * 2 E1, 3 E2, 4 E3, 5 HEAD (with G3 when fused, see sv_set_latent_fusion),
+ * 6 reparameterisation (training), 7 G3, 8 G2,
  * 9 G1, 10 G0, 11 (not recorded: the final layer's projection runs inside
  * stage 12), 12 final layer (projection and gather).
  * sv_profile_read synchronises on the recorded events, writes the summed

@@ -16,6 +16,7 @@ from .ops import (  # noqa: F401
     sv_set_cost_wta_split,
     sv_set_layer_cfg,
     sv_num_layer_cfgs,
+    sv_set_latent_fusion,
     sv_conv_cfg_name,
     Refiner,
     vae_param_count,

@@ -74,6 +74,7 @@ _SIGS = {
     "sv_adam_step": (ctypes.c_int32, [_P, _P, _P, _P, _I64, _I, _F, _F, _F, _F, _P]),
     "sv_set_layer_cfg": (ctypes.c_int32, [_I, _I]),
     "sv_num_layer_cfgs": (_I, []),
+    "sv_set_latent_fusion": (ctypes.c_int32, [_I]),
     "sv_batch_plan_create": (ctypes.c_int32, [_DESC, _I, _I, _I, _I, _I, _I, ctypes.POINTER(_P)]),
     "sv_batch_plan_destroy": (ctypes.c_int32, [_P]),
     "sv_stereo_batch": (ctypes.c_int32, [_P, ctypes.POINTER(Pair), _I, _P, _P]),

@@ -258,4 +258,10 @@ sv_status sv_set_layer_cfg(int layer, int cfg) {
 
 int sv_num_layer_cfgs(void) { return conv_num_cfgs(); }
 
+sv_status sv_set_latent_fusion(int on) {
+    if (on != 0 && on != 1) return SV_ERR_RANGE;
+    net_set_latent_fusion(on);
+    return SV_OK;
+}
+
 }  // extern "C"

@@ -754,7 +754,10 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 }
 
 // Second pass of a split reduction: adds the ksplit FP32 partials of four
-// channels of one pixel in range order, then applies the epilogue.
+// channels of one pixel in range order, then applies the epilogue.  Every
+// partial and the bias are loaded before the first addition (the ranges that
+// do not exist read range 0 and are not added), so one memory latency is
+// paid per element instead of one per range.
 template <int DT>
 __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, int npix)
 {
@@ -766,14 +769,22 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
         const size_t pix = e / ng;
         const int nbase = (int)(e - pix * ng) * 4;
         if (nbase >= p.Cout) continue;
-        f32x4 s = *(const f32x4 *)&p.part[pix * p.n_pad + nbase];
-        for (int z = 1; z < p.ksplit; ++z) {
-            const f32x4 q = *(const f32x4 *)&p.part[((size_t)z * npix + pix) * p.n_pad + nbase];
-            s[0] += q[0]; s[1] += q[1]; s[2] += q[2]; s[3] += q[3];
-        }
-        const float r[4] = {s[0], s[1], s[2], s[3]};
         float b[4];
         conv_bias4<DT>(p, nbase, b);
+        f32x4 q[CONV_MAX_SPLIT];
+#pragma unroll
+        for (int z = 0; z < CONV_MAX_SPLIT; ++z) {
+            const size_t zz = z < p.ksplit ? (size_t)z : 0;
+            q[z] = *(const f32x4 *)&p.part[(zz * npix + pix) * p.n_pad + nbase];
+        }
+        f32x4 s = q[0];
+#pragma unroll
+        for (int z = 1; z < CONV_MAX_SPLIT; ++z) {
+            if (z < p.ksplit) {
+                s[0] += q[z][0]; s[1] += q[z][1]; s[2] += q[z][2]; s[3] += q[z][3];
+            }
+        }
+        const float r[4] = {s[0], s[1], s[2], s[3]};
         lmax = fmaxf(lmax, conv_epilogue<DT>(p, pix, nbase, r, b));
     }
     if (p.amax_out) record_amax(p, lmax, (int)blockIdx.x);

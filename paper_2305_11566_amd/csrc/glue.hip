@@ -194,9 +194,18 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
         }
     }
     __syncthreads();
-    // horizontal pass, one output pixel per thread and row
+    // horizontal pass, one output pixel per thread and row; a thread keeps one
+    // column, so its three column taps are read from the table once
     const int tx = tid & 63;
     const int X = X0 + tx;
+    int hx0[3], hx1[3];
+    float hlx[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        hx0[v] = tb.cx0[tx + v];
+        hx1[v] = tb.cx1[tx + v];
+        hlx[v] = tb.clx[tx + v];
+    }
 #pragma unroll
     for (int ty = tid >> 6; ty < FIN_TILE_H; ty += FIN_THREADS / 64) {
         const int Y = Y0 + ty;
@@ -204,17 +213,12 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
             float acc = bias;
 #pragma unroll
             for (int v = 0; v < 3; ++v) {
-                const int x0 = tb.cx0[tx + v];
-                if (x0 < 0) continue;
-                const int x1 = tb.cx1[tx + v];
-                const float lx = tb.clx[tx + v];
+                if (hx0[v] < 0) continue;
                 const float *ss = sS + (ty * 3 + v) * PWm;
-                acc += (1.f - lx) * ss[x0] + lx * ss[x1];
+                acc += (1.f - hlx[v]) * ss[hx0[v]] + hlx[v] * ss[hx1[v]];
             }
-            const int x0 = tb.cx0[tx + 1], x1 = tb.cx1[tx + 1];
-            const float lx = tb.clx[tx + 1];
             const float *dd = sD + ty * PWm;
-            const float base = scale0 * ((1.f - lx) * dd[x0] + lx * dd[x1]);
+            const float base = scale0 * ((1.f - hlx[1]) * dd[hx0[1]] + hlx[1] * dd[hx1[1]]);
             out[(size_t)Y * W + X] = 256.0f * (acc + base);
         }
     }

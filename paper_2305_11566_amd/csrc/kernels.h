@@ -181,6 +181,12 @@ constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F1
 // weights [9][wf_pitch], x0 = [f * d / 256, img / 256]),
 // out[b][Y][X] = 256 * (bias + sum_taps resize(T[tap])(Y+u-1, X+v-1) + resize(f*d/256)(Y, X)).
 // G0: NHWC [B][h][w][c1] in dtype; disp, img: uint8 [B][h][w].
+// Inference: the latent head (ph, [mu | logvar] in FP32) and G3 (pg, reading
+// mu) as one kernel over npix pixels of the coarsest level; same bits as the
+// two layers launched one by one, unsplit.  latent_fusable tells whether the
+// widths allow it (whole base chunks, at most 256 channels).
+bool latent_fusable(int dtype, int c3, int L);
+sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix, hipStream_t st);
 sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
                        const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
                        int w, int H, int W, float *out, hipStream_t s);

@@ -32,6 +32,8 @@ struct Levels {
     int H, W, h[4], w[4];
 };
 Levels net_levels(const NetShape &ns, int H, int W);
+// 1 (default): an inference pass fuses the head and G3 where the widths allow
+void net_set_latent_fusion(int on);
 
 // Device tensors of one forward pass.  "saved" holds what the backward needs
 // beyond the recomputed encoder; at inference it lives inside the workspace.

@@ -178,10 +178,9 @@ static ConvSrc src_x0(const uint8_t *disp, const uint8_t *img, int hs, int ws, i
 // INT8 passes: the amax slots of the layer's sources and output
 struct LayerAmax { const uint32_t *in0, *in1; uint32_t *out; };
 
-static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
-                           int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
-                           int out_f32, int act, int cfg, float *part, size_t part_bytes,
-                           LayerAmax am, hipStream_t st) {
+static ConvParams layer_params(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
+                               int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
+                               int out_f32, int act, float *part, size_t part_bytes, LayerAmax am) {
     ConvParams p{};
     if (ns.dtype == SV_I8 && li != L_F) {
         p.wscale = (const float *)((const char *)packed + ns.s_off[li]);
@@ -202,10 +201,24 @@ static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvS
     p.bias = tsplit ? nullptr : (const float *)((const char *)packed + ns.b_off[li]);
     p.out = out; p.out_pitch = out_pitch; p.out_coff = 0;
     p.act = act; p.out_f32 = out_f32;
+    return p;
+}
+
+static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
+                           int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
+                           int out_f32, int act, int cfg, float *part, size_t part_bytes,
+                           LayerAmax am, hipStream_t st) {
+    const ConvParams p = layer_params(ns, packed, li, s0, s1, B, Hi, Wi, Ho, Wo, out, out_pitch,
+                                      out_f32, act, part, part_bytes, am);
+    const bool tsplit = li == L_F;
     const int ks = tsplit ? 1 : ns.ly[li].k;
     const int stride = tsplit ? 1 : ns.ly[li].stride;
     return launch_conv(tsplit ? SV_F32 : ns.dtype, ks, stride, cfg, p, st);
 }
+
+// 1: an inference pass runs the head and G3 as one kernel where the shapes allow
+static std::atomic<int> g_latent_fusion{1};
+void net_set_latent_fusion(int on) { g_latent_fusion.store(on ? 1 : 0); }
 
 // with only >= 0, a forward pass launches that layer alone (the autotuner
 // times one layer at a time on buffers a full pass has filled)
@@ -270,23 +283,36 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                      lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, am(AM_E2, -1, AM_E3), st));
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
-    ev_rec(3, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_HEAD, src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0), none, B,
-                     lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, am(AM_E3, -1, AM_ML), st));
-    ev_rec(3, 1, st);
-    ConvSrc zsrc;
-    if (eps) {
-        ev_rec(4, 0, st);
-        if (only < 0) SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
-        ev_rec(4, 1, st);
-        zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
+    const ConvSrc e3src = src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0);
+    const ConvSrc musrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], SDT_F32);  // z = mu
+    if (only < 0 && !eps && !train && g_latent_fusion.load() && latent_fusable(ns.dtype, c3, L)) {
+        // inference: head and G3 in one launch (profiled as the head's stage)
+        const int h3 = lv.h[3], w3 = lv.w[3];
+        const ConvParams ph = layer_params(ns, packed, L_HEAD, e3src, none, B, h3, w3, h3, w3, ML, 2 * L,
+                                           1, 0, nullptr, 0, LayerAmax{});
+        const ConvParams pg = layer_params(ns, packed, L_G3, musrc, none, B, h3, w3, h3, w3, G3, c3, 0,
+                                           1, nullptr, 0, LayerAmax{});
+        ev_rec(3, 0, st);
+        SV_TRY(launch_latent(ns.dtype, ph, pg, B * h3 * w3, st));
+        ev_rec(3, 1, st);
     } else {
-        zsrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], SDT_F32);  // z = mu
+        ev_rec(3, 0, st);
+        SV_TRY(run_layer_if(only, ns, packed, L_HEAD, e3src, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3],
+                            ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, am(AM_E3, -1, AM_ML), st));
+        ev_rec(3, 1, st);
+        ConvSrc zsrc = musrc;
+        if (eps) {
+            ev_rec(4, 0, st);
+            if (only < 0) SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
+            ev_rec(4, 1, st);
+            zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
+        }
+        // decoder
+        ev_rec(5, 0, st);
+        SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3,
+                            c3, 0, 1, cfg[L_G3], part, a.part_bytes, am(AM_ML, -1, AM_G3), st));
+        ev_rec(5, 1, st);
     }
-    // decoder
-    ev_rec(5, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part, a.part_bytes, am(AM_ML, -1, AM_G3), st));
-    ev_rec(5, 1, st);
     ev_rec(6, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],

@@ -161,6 +161,12 @@ def sv_num_layer_cfgs() -> int:
     return lib().sv_num_layer_cfgs()
 
 
+def sv_set_latent_fusion(on: bool):
+    """Inference passes run the latent head and G3 as one kernel (default) or
+    as two launches; both give the same bits."""
+    check(lib().sv_set_latent_fusion(1 if on else 0), "sv_set_latent_fusion")
+
+
 def sv_conv_cfg_name(cfg: int) -> str:
     """Name of a layer configuration: the tile shape, plus "_s<k>" for a
     k-way split of the channel reduction."""

@@ -5,9 +5,10 @@ Two modes:
 ``python -m paper_2305_11566_amd.profile_traffic run``
     One 1242x375 pair (the benchmark's inputs and weights), matched once, then
     one FP32 forward pass of the network per layer configuration with every
-    layer set to that configuration (a tile shape that does not fit a layer
-    runs as the fallback and is recorded under the fallback's name), then a
-    plain 64 MiB device copy.  Meant to run under
+    layer set to that configuration and each layer its own launch (a tile
+    shape that does not fit a layer runs as the fallback and is recorded under
+    the fallback's name), one pass as inference runs it (the head and G3 as one
+    kernel, recorded as HEAD+G3), then a plain 64 MiB device copy.  Meant to run under
     ``rocprofv3 --pmc FETCH_SIZE`` and, separately, ``--pmc WRITE_SIZE``.
 
 ``python -m paper_2305_11566_amd.profile_traffic summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON``
@@ -73,6 +74,9 @@ def run() -> None:
     out = torch.empty((1, H, W), dtype=torch.float32, device=dev)
     names = []
     try:
+        # every layer as its own launch, so that each configuration of the head
+        # and of G3 is counted too
+        sv.sv_set_latent_fusion(False)
         for c in range(sv.sv_num_layer_cfgs()):
             for layer in range(9):
                 sv.sv_set_layer_cfg(layer, c)
@@ -82,6 +86,11 @@ def run() -> None:
     finally:
         for layer in range(9):
             sv.sv_set_layer_cfg(layer, -1)
+        sv.sv_set_latent_fusion(True)
+    # then one pass as inference runs it: head and G3 in one kernel
+    names.append(sv.sv_layer_cfgs(C1, C2, C3, LAT, F, "f32", 1, H, W))
+    ref.forward(disp, low, H, W, out=out)
+    torch.cuda.synchronize()
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
     torch.cuda.synchronize()
@@ -128,7 +137,7 @@ def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) ->
         elif "k_conv_split_reduce" in n:
             cur[-1][1] += fb
             cur[-1][2] += wb
-        elif "k_conv<" in n:
+        elif "k_conv<" in n or "k_latent<" in n:
             cur.append([n, fb, wb])
         elif "k_final" in n:
             forwards.append((cur, (fb, wb)))
@@ -136,8 +145,13 @@ def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) ->
     assert len(forwards) == len(cfg_names), (len(forwards), len(cfg_names))
     final = None
     for (convs, fin), cfgs in zip(forwards, cfg_names):
-        assert len(convs) == len(LAYERS)
-        for layer, (n, fb, wb), cfg in zip(LAYERS, convs, cfgs):
+        if any("k_latent<" in c[0] for c in convs):  # head and G3 as one kernel
+            layers = LAYERS[:3] + ("HEAD+G3",) + LAYERS[5:]
+            cfgs = list(cfgs[:3]) + ["fused"] + list(cfgs[5:8])
+        else:
+            layers = LAYERS
+        assert len(convs) == len(layers)
+        for layer, (n, fb, wb), cfg in zip(layers, convs, cfgs):
             entries[f"f32|B1|{H}x{W}|{layer}|{cfg}"] = {"fetch_bytes": round(fb), "write_bytes": round(wb),
                                                         "kernel": n.split("(")[0]}
         final = {"fetch_bytes": round(fin[0]), "write_bytes": round(fin[1])}

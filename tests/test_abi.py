@@ -166,6 +166,13 @@ def test_tvae_loss_and_cfg_validation():
     assert all(0 <= c < lib().sv_num_layer_cfgs() for c in arr)
 
 
+def test_latent_fusion_switch():
+    assert lib().sv_set_latent_fusion(2) == -3
+    assert lib().sv_set_latent_fusion(-1) == -3
+    assert lib().sv_set_latent_fusion(0) == 0
+    assert lib().sv_set_latent_fusion(1) == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     import paper_2305_11566_amd._lib as L
     monkeypatch.setattr(L, "_lib", None)

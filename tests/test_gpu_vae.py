@@ -137,6 +137,38 @@ def test_tile_configs_bitwise_identical(dtype):
     assert sorted(per_split) == [1, 2, 3, 4]
 
 
+@pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
+@pytest.mark.parametrize("C,L,f,H,W,B", [
+    ((32, 64, 128), 128, 4, 375, 1242, 1),  # full size: 468 latent pixels, a tail of 4 past 16s
+    ((16, 32, 64), 64, 2, 128, 256, 2),     # 256x128 widths, two images
+    ((32, 64, 96), 32, 2, 50, 90, 3),       # 96 / 32 channels, 7x12 latent grids
+    ((16, 24, 48), 16, 2, 30, 40, 1),       # FP32 fused; L = 16 is not a whole 16-bit chunk: two launches
+])
+def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B):
+    """Inference runs the head and G3 as one kernel: same bits as the two
+    layers launched one by one, unsplit (their configurations pinned to an
+    unsplit tile shape)."""
+    import paper_2305_11566_amd as sv
+    rng = np.random.default_rng(H + W + B)
+    h, w = -(-H // f), -(-W // f)
+    disp = rng.integers(0, 40, (B, h, w)).astype(np.uint8)
+    img = rng.integers(0, 256, (B, h, w)).astype(np.uint8)
+    params = vae_params(C, L, 21)
+    try:
+        for layer in (3, 4):
+            sv.sv_set_layer_cfg(layer, 5)  # th4_tn16, no split
+        sv.sv_set_latent_fusion(True)
+        a, ma = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+        sv.sv_set_latent_fusion(False)
+        b, mb = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+    finally:
+        sv.sv_set_latent_fusion(True)
+        for layer in (3, 4):
+            sv.sv_set_layer_cfg(layer, -1)
+    assert np.array_equal(ma, mb), "mu / logvar"
+    assert np.array_equal(a, b), "refined map"
+
+
 def test_split_reduction_against_oracle():
     """Every layer forced to a 2-, 3- and 4-way channel split: FP32 forward
     within 1e-5 normwise of the oracle at the paper-sized shape."""
