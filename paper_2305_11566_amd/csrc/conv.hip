@@ -143,14 +143,20 @@ int conv_effective_split(int dtype, int cfg, int Cin, long long npix, int n_pad,
     return ksplit;
 }
 
-sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
+sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st,
+                            int *ksplit_used) {
     if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
     cfg = conv_resolve_cfg(dtype, ks, stride, cfg);
     ConvParams p = p0;
     p.ksplit = conv_effective_split(dtype, cfg, p.Cin, (long long)p.B * p.Ho * p.Wo, p.n_pad, p.part,
                                     p.part_bytes);
     if (p.ophase) p.ksplit = 1;  // a phase launch writes its pixels straight into the full map
+    if (ksplit_used) *ksplit_used = p.ksplit > 1 ? p.ksplit : 1;
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
+}
+
+sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {
+    return launch_conv_split(dtype, ks, stride, cfg, p0, st, nullptr);
 }
 
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p0, int grid,

@@ -808,7 +808,7 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), (unsigned)gz);
     hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
-    if (ksplit > 1) {
+    if (ksplit > 1 && !p.defer_sum) {
         const int npix = p.B * p.Ho * p.Wo;
         const long long work = (long long)npix * (p.n_pad / 4);
         const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);

@@ -126,12 +126,18 @@ struct ConvParams {
     // Ho_full x Wo_full map, ophase = 1 + 2 py + px (one parity class of a
     // stride-2 deconvolution)
     int ophase, Ho_full, Wo_full;
+    // 1: a split launch leaves its FP32 partials in part for the consumer to
+    // add (the fused latent kernel), instead of launching the second pass
+    int defer_sum;
 };
 constexpr int AMAX_SUB = 64;
 
 // cfg selects the tile shape and the reduction split (see conv.hip); ks = 1, 3
 // or 5, stride = 1 or 2 (ks = 1: stride 1 only).
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s);
+// launch_conv that also reports the reduction split it used (1: none)
+sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s,
+                            int *ksplit_used);
 // persistent launch over p.tab's tiles of stage p.stage with `grid` workgroups
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
                           hipStream_t s);
@@ -186,7 +192,12 @@ constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F1
 // two layers launched one by one, unsplit.  latent_fusable tells whether the
 // widths allow it (whole base chunks, at most 256 channels).
 bool latent_fusable(int dtype, int c3, int L);
-sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix, hipStream_t st);
+// e3part / e3split / e3bias: when E3 ran split with its sum deferred, its
+// FP32 partials (ranges in order), which the kernel adds, biases and passes
+// through the leaky ReLU as the second pass would (E3 itself is then never
+// stored); e3split <= 1 reads the stored E3.
+sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix,
+                        const float *e3part, int e3split, const float *e3bias, hipStream_t st);
 sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
                        const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
                        int w, int H, int W, float *out, hipStream_t s);

@@ -18,7 +18,9 @@ constexpr int LAT_PX = 16;     // pixels per workgroup (one MFMA block)
 constexpr int LAT_MAXC = 256;  // most channels of E3 and of mu held in LDS
 
 template <int DT>
-__global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, const ConvParams pg, int npix)
+__global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, const ConvParams pg, int npix,
+                                                        const float *__restrict__ e3part, int e3split,
+                                                        const float *__restrict__ e3bias)
 {
     using M = Mfma<DT>;
     using T = typename M::T;
@@ -34,14 +36,44 @@ __global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, con
     const int p0 = blockIdx.x * LAT_PX, pix = p0 + r16;
     const int c3 = ph.Cin, L = pg.Cin;
 
-    // E3 -> LDS; pixels past npix are zero and their results are not stored
+    // E3 -> LDS; pixels past npix are zero and their results are not stored.
+    // From a deferred split: the ranges' partials added in range order, then
+    // bias and leaky ReLU, rounded to the compute dtype -- the second pass of
+    // the split and E3's store, as the convolution kernels do them.
     {
         const T *e3 = (const T *)ph.src[0].ptr;
         const int ngrp = c3 / GS;
         for (int e = tid; e < LAT_PX * ngrp; e += LAT_THREADS) {
             const int r = e / ngrp, cg = e - r * ngrp;
             vec v;
-            if (p0 + r < npix) {
+            if (p0 + r < npix && e3split > 1) {
+                const size_t o = (size_t)(p0 + r) * c3 + cg * GS;
+                float a[GS];
+#pragma unroll
+                for (int i = 0; i < GS; i += 4) {
+                    f32x4 q[CONV_MAX_SPLIT];
+#pragma unroll
+                    for (int z = 0; z < CONV_MAX_SPLIT; ++z) {
+                        const size_t zz = z < e3split ? (size_t)z : 0;
+                        q[z] = *(const f32x4 *)&e3part[zz * npix * c3 + o + i];
+                    }
+                    f32x4 s = q[0];
+#pragma unroll
+                    for (int z = 1; z < CONV_MAX_SPLIT; ++z) {
+                        if (z < e3split) {
+                            s[0] += q[z][0]; s[1] += q[z][1]; s[2] += q[z][2]; s[3] += q[z][3];
+                        }
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        float val = s[j] + e3bias[cg * GS + i + j];
+                        val = val > 0.f ? val : 0.1f * val;
+                        a[i + j] = val;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < GS; ++i) v[i] = Elem<DT>::make(a[i]);
+            } else if (p0 + r < npix) {
                 v = *(const vec *)(e3 + (size_t)(p0 + r) * ph.src[0].pitch + cg * GS);
             } else {
 #pragma unroll
@@ -102,21 +134,23 @@ bool latent_fusable(int dtype, int c3, int L) {
     return c3 > 0 && L > 0 && c3 % kcb == 0 && L % kcb == 0 && c3 <= LAT_MAXC && L <= LAT_MAXC;
 }
 
-sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix, hipStream_t st) {
+sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix,
+                        const float *e3part, int e3split, const float *e3bias, hipStream_t st) {
     const int c3 = ph.Cin, L = pg.Cin;
     // shapes the kernel assumes: both reductions whole base chunks held in
     // LDS, mu the first L of the head's outputs, G3 reading exactly mu, and
     // packed rows long enough for every chunk
     if (!latent_fusable(dtype, c3, L) || ph.Cout != 2 * L || pg.Cout != c3 ||
         ph.cin_pad < c3 || pg.cin_pad < L || ph.n_pad < ph.Cout || pg.n_pad < pg.Cout ||
-        ph.n_pad % 16 || pg.n_pad % 16 || ph.src[0].pitch < c3 || !ph.out_f32)
+        ph.n_pad % 16 || pg.n_pad % 16 || ph.src[0].pitch < c3 || !ph.out_f32 ||
+        e3split > CONV_MAX_SPLIT || (e3split > 1 && (!e3part || !e3bias)))
         return SV_ERR_UNSUPPORTED;
     if (npix <= 0) return SV_OK;
     const dim3 grid((unsigned)cdiv(npix, LAT_PX));
     switch (dtype) {
-    case SV_F32: hipLaunchKernelGGL(k_latent<SV_F32>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix); break;
-    case SV_BF16: hipLaunchKernelGGL(k_latent<SV_BF16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix); break;
-    default: hipLaunchKernelGGL(k_latent<SV_F16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix); break;
+    case SV_F32: hipLaunchKernelGGL(k_latent<SV_F32>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
+    case SV_BF16: hipLaunchKernelGGL(k_latent<SV_BF16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
+    default: hipLaunchKernelGGL(k_latent<SV_F16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
     }
     SV_LAUNCH_CHECK("k_latent");
     return SV_OK;

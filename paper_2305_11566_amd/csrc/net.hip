@@ -278,14 +278,27 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     SV_TRY(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
                      lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2), st));
     ev_rec(1, 1, st);
+    // inference: the head and G3 run as one kernel, which also finishes E3's
+    // split sum when E3 runs split (E3 is then never stored)
+    const bool fuse_latent = only < 0 && !eps && !train && g_latent_fusion.load() && latent_fusable(ns.dtype, c3, L);
+    int e3split = 1;
     ev_rec(2, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
-                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, am(AM_E2, -1, AM_E3), st));
+    if (fuse_latent) {
+        ConvParams p3 = layer_params(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
+                                     lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, part, a.part_bytes,
+                                     LayerAmax{});
+        p3.defer_sum = 1;
+        SV_TRY(launch_conv_split(ns.dtype, ns.ly[L_E3].k, ns.ly[L_E3].stride, cfg[L_E3], p3, st, &e3split));
+    } else {
+        SV_TRY(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
+                            lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes,
+                            am(AM_E2, -1, AM_E3), st));
+    }
     ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     const ConvSrc e3src = src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0);
     const ConvSrc musrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], SDT_F32);  // z = mu
-    if (only < 0 && !eps && !train && g_latent_fusion.load() && latent_fusable(ns.dtype, c3, L)) {
+    if (fuse_latent) {
         // inference: head and G3 in one launch (profiled as the head's stage)
         const int h3 = lv.h[3], w3 = lv.w[3];
         const ConvParams ph = layer_params(ns, packed, L_HEAD, e3src, none, B, h3, w3, h3, w3, ML, 2 * L,
@@ -293,7 +306,8 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
         const ConvParams pg = layer_params(ns, packed, L_G3, musrc, none, B, h3, w3, h3, w3, G3, c3, 0,
                                            1, nullptr, 0, LayerAmax{});
         ev_rec(3, 0, st);
-        SV_TRY(launch_latent(ns.dtype, ph, pg, B * h3 * w3, st));
+        const float *e3bias = (const float *)((const char *)packed + ns.b_off[L_E3]);
+        SV_TRY(launch_latent(ns.dtype, ph, pg, B * h3 * w3, part, e3split, e3bias, st));
         ev_rec(3, 1, st);
     } else {
         ev_rec(3, 0, st);

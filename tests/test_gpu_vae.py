@@ -137,6 +137,7 @@ def test_tile_configs_bitwise_identical(dtype):
     assert sorted(per_split) == [1, 2, 3, 4]
 
 
+@pytest.mark.parametrize("e3cfg", [-1, 5 + 16, 5 + 48])  # E3 default, split in 2, split in 4 (capped)
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("C,L,f,H,W,B", [
     ((32, 64, 128), 128, 4, 375, 1242, 1),  # full size: 468 latent pixels, a tail of 4 past 16s
@@ -144,10 +145,11 @@ def test_tile_configs_bitwise_identical(dtype):
     ((32, 64, 96), 32, 2, 50, 90, 3),       # 96 / 32 channels, 7x12 latent grids
     ((16, 24, 48), 16, 2, 30, 40, 1),       # FP32 fused; L = 16 is not a whole 16-bit chunk: two launches
 ])
-def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B):
+def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B, e3cfg):
     """Inference runs the head and G3 as one kernel: same bits as the two
     layers launched one by one, unsplit (their configurations pinned to an
-    unsplit tile shape)."""
+    unsplit tile shape).  When E3 runs split, the fused kernel also adds E3's
+    partial sums in place of the second pass."""
     import paper_2305_11566_amd as sv
     rng = np.random.default_rng(H + W + B)
     h, w = -(-H // f), -(-W // f)
@@ -157,13 +159,14 @@ def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B):
     try:
         for layer in (3, 4):
             sv.sv_set_layer_cfg(layer, 5)  # th4_tn16, no split
+        sv.sv_set_layer_cfg(2, e3cfg)
         sv.sv_set_latent_fusion(True)
         a, ma = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
         sv.sv_set_latent_fusion(False)
         b, mb = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
     finally:
         sv.sv_set_latent_fusion(True)
-        for layer in (3, 4):
+        for layer in (2, 3, 4):
             sv.sv_set_layer_cfg(layer, -1)
     assert np.array_equal(ma, mb), "mu / logvar"
     assert np.array_equal(a, b), "refined map"
