@@ -22,6 +22,9 @@ the same order, so the integer codes this produces are the method's codes.
 """
 from __future__ import annotations
 
+import math
+from fractions import Fraction
+
 import numpy as np
 
 from . import conv2d, resize
@@ -60,22 +63,40 @@ def quantise_weights(w):
     return q, (a / F32(QMAX)).astype(np.float32)
 
 
+def f32_nearest(q):
+    """The binary32 value nearest to the exact rational q (a Fraction), ties
+    to the even significand: the rounding of IEEE 754 round-to-nearest.
+    Found by exact comparison of q with the candidates around a first guess,
+    so no intermediate rounding (e.g. through binary64) can shift it."""
+    g = np.float32(float(q))
+    cands = {g, np.nextafter(g, F32(np.inf)), np.nextafter(g, F32(-np.inf))}
+    best = None
+    for c in sorted(cands):
+        dist = abs(Fraction(float(c)) - q)
+        even = (int(np.asarray(c, np.float32).view(np.uint32)) & 1) == 0
+        key = (dist, not even)
+        if best is None or key < best[0]:
+            best = (key, c)
+    return F32(best[1])
+
+
 def _bilin_axis(o, n_in, n_out):
-    """Corner indices and FP32 weight along one axis: the position
-    ((2o+1) n_in - n_out) / (2 n_out) as an exact quotient plus a rounded remainder."""
-    num = (2 * o + 1) * n_in - n_out
-    if num <= 0:
-        i0, lam = 0, F32(0)
-    else:
-        den = 2 * n_out
-        i0 = num // den
-        lam = F32(num - i0 * den) / F32(den)
-    return i0, min(i0 + 1, n_in - 1), lam
+    """Corner indices and FP32 weight along one axis of a resize from n_in to
+    n_out samples with half-pixel centres: the exact source position is
+    s = max(0, (o + 1/2) n_in / n_out - 1/2); i0 = floor(s), i1 = min(i0 + 1,
+    n_in - 1), and the weight is the FP32 value nearest to s - i0."""
+    s = (Fraction(2 * o + 1, 2) * n_in) / n_out - Fraction(1, 2)
+    if s < 0:
+        s = Fraction(0)
+    i0 = math.floor(s)
+    return i0, min(i0 + 1, n_in - 1), f32_nearest(s - i0)
 
 
 def resize_f32(x, Ho, Wo):
-    """Bilinear resize (half-pixel centres) evaluated in FP32 as
-    (1-ly) * ((1-lx) x00 + lx x01) + ly * ((1-lx) x10 + lx x11)."""
+    """Bilinear resize (half-pixel centres) evaluated in FP32 with the
+    weights of _bilin_axis, in this order, every product and sum rounded to
+    FP32 (no fused multiply-add): top = (1-lx) x00 + lx x01, bot = (1-lx) x10
+    + lx x11 along the row, then (1-ly) top + ly bot down the column."""
     x = np.asarray(x, np.float32)
     Hi, Wi = x.shape[-2:]
     ys = [_bilin_axis(o, Hi, Ho) for o in range(Ho)]

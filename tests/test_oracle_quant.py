@@ -3,10 +3,16 @@
 BF16 storage rounding is pinned against torch's bfloat16 conversion; the
 quantiser by its closed-form properties; the integer convolution against the
 separately pinned FP64 convolution of the dequantised codes; the FP32
-bilinear resize against the FP64 one; the whole pass by a special case that
-reduces exactly to the FP network (bias-only weights) and by a loose bound
-on its distance from the FP64 network.
+bilinear resize bit for bit against its definition -- each weight the
+correctly rounded FP32 value of the exact fractional source position
+(derived here by integer arithmetic on the rational), the corners from the
+half-pixel formula in exact arithmetic, the value from a scalar FP32 loop in
+the stated order -- and loosely against the FP64 one; the whole pass by a
+special case that reduces exactly to the FP network (bias-only weights) and
+by a loose bound on its distance from the FP64 network.
 """
+from fractions import Fraction
+
 import numpy as np
 import pytest
 import torch
@@ -76,6 +82,99 @@ def test_fp32_resize_matches_fp64(Hi, Wi, Ho, Wo):
     x = np.random.default_rng(Hi * Wo).standard_normal((2, 3, Hi, Wi)).astype(np.float32)
     np.testing.assert_allclose(quant.resize_f32(x, Ho, Wo), oracle.resize(x.astype(np.float64), Ho, Wo),
                                rtol=0, atol=4e-7 * np.max(np.abs(x)))
+
+
+def _levels(H, W, f):
+    h, w = [-(-H // f)], [-(-W // f)]
+    for _ in range(3):
+        h.append(-(-h[-1] // 2))
+        w.append(-(-w[-1] // 2))
+    return h, w
+
+
+def _decoder_resizes():
+    """(n_in, n_out) of every decoder resize axis of the 1242x375 (f = 4) and
+    256x128 (f = 2) workloads and of the widest / narrowest uneven pairs."""
+    out = set()
+    for H, W, f in ((375, 1242, 4), (128, 256, 2), (384, 1280, 4), (192, 640, 4), (376, 1048, 4)):
+        h, w = _levels(H, W, f)
+        for k in range(3):
+            out.add((h[k + 1], h[k]))
+            out.add((w[k + 1], w[k]))
+    return sorted(out)
+
+
+def _rn_even_f32(q):
+    """Round a rational 0 <= q < 2 to binary32, nearest with ties to even, by
+    integer arithmetic: scale to a 24-bit significand and let Fraction's
+    round() (half to even) pick the integer."""
+    if q == 0:
+        return np.float32(0)
+    e = q.numerator.bit_length() - q.denominator.bit_length()
+    if Fraction(2) ** e > q:
+        e -= 1
+    assert Fraction(2) ** e <= q < Fraction(2) ** (e + 1)
+    m = round(q * Fraction(2) ** (23 - e))
+    return np.float32(float(m * Fraction(2) ** (e - 23)))
+
+
+def _axis_reference(o, n_in, n_out):
+    """Half-pixel source position o -> ((2o+1) n_in - n_out) / (2 n_out),
+    clamped at 0: integer floor, clamped upper corner, rounded remainder."""
+    num, den = (2 * o + 1) * n_in - n_out, 2 * n_out
+    if num < 0:
+        num = 0
+    i0 = num // den
+    return i0, min(i0 + 1, n_in - 1), _rn_even_f32(Fraction(num - i0 * den, den))
+
+
+@pytest.mark.parametrize("n_in,n_out", _decoder_resizes() + [(3, 7), (5, 2), (1, 4), (7, 7)])
+def test_bilinear_weights_are_the_correctly_rounded_exact_fraction(n_in, n_out):
+    for o in range(n_out):
+        got = quant._bilin_axis(o, n_in, n_out)
+        ref = _axis_reference(o, n_in, n_out)
+        assert got[:2] == ref[:2], (o, got, ref)
+        assert np.float32(got[2]).view(np.uint32) == ref[2].view(np.uint32), (o, got[2], ref[2])
+
+
+def test_fp32_expression_weights_would_fail_the_pin():
+    """The pin discriminates: evaluating the position as the FP32 expression
+    (o + 1/2) n_in / n_out - 1/2 rounds differently on a large share of the
+    workload's indices, and every such index differs from the reference."""
+    F = np.float32
+    differ = total = 0
+    for n_in, n_out in _decoder_resizes():
+        for o in range(n_out):
+            s = max((F(o) + F(0.5)) * F(n_in) / F(n_out) - F(0.5), F(0))
+            lam = F(s - np.floor(s))
+            total += 1
+            differ += int(lam.view(np.uint32) != _axis_reference(o, n_in, n_out)[2].view(np.uint32))
+    assert differ > total // 10, (differ, total)
+
+
+@pytest.mark.parametrize("Hi,Wi,Ho,Wo", [(12, 39, 24, 78), (24, 78, 47, 156), (47, 156, 94, 311),
+                                         (16, 32, 32, 64), (3, 5, 7, 2)])
+def test_fp32_resize_bitwise_equals_scalar_definition(Hi, Wi, Ho, Wo):
+    """Every output of resize_f32 equals a scalar FP32 evaluation of
+    (1-ly)((1-lx) x00 + lx x01) + ly((1-lx) x10 + lx x11), each operation
+    rounded, with the reference weights and corners."""
+    F = np.float32
+    x = np.random.default_rng(Hi * 1000 + Wo).standard_normal((1, 2, Hi, Wi)).astype(np.float32)
+    got = quant.resize_f32(x, Ho, Wo)
+    ys = [_axis_reference(o, Hi, Ho) for o in range(Ho)]
+    xs = [_axis_reference(o, Wi, Wo) for o in range(Wo)]
+    ref = np.empty((1, 2, Ho, Wo), np.float32)
+    one = F(1)
+    for c in range(2):
+        xc = x[0, c]
+        for oy, (y0, y1, ly) in enumerate(ys):
+            wy0 = F(one - ly)
+            for ox, (x0, x1, lx) in enumerate(xs):
+                wx0 = F(one - lx)
+                top = F(F(wx0 * xc[y0, x0]) + F(lx * xc[y0, x1]))
+                bot = F(F(wx0 * xc[y1, x0]) + F(lx * xc[y1, x1]))
+                ref[0, c, oy, ox] = F(F(wy0 * top) + F(ly * bot))
+    np.testing.assert_array_equal(got.view(np.uint32), ref.view(np.uint32))
 
 
 def _shapes(C, L):
