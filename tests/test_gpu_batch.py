@@ -73,6 +73,36 @@ def test_batch_f32_against_oracle():
     plan.close()
 
 
+# pairs of the 64-pair uneven workload: the widest (1280x256), the largest
+# (1152x384), the smallest (640x200) and every eighth
+UNEVEN_IDX = [1, 2, 29, 0, 8, 16, 24, 40, 56]
+
+
+def test_uneven_workload_f32_against_oracle():
+    """FP32 batch at the uneven workload's real sizes (widths 640-1280,
+    heights 200-384, D 40-80): coarse maps bit-exact with the oracle's
+    census + WTA, refined maps within 1e-5 normwise of the FP64 network."""
+    import paper_2305_11566_amd as sv
+    params = vae_params(C, L, seed=18)
+    ref = sv.Refiner(*C, L, F, "f32")
+    ref.pack(cuda(flat_params(params)))
+    ps = [gen_preset("uneven64", i) for i in UNEVEN_IDX]
+    pairs = [(cuda(p.left), cuda(p.right), p.D) for p in ps]
+    disp_outs = [torch.empty((-(-p.left.shape[0] // F), -(-p.left.shape[1] // F)), dtype=torch.uint8,
+                             device="cuda") for p in ps]
+    plan = sv.BatchPlan(*C, L, F, "f32", 64, 384, 1280, 80, WW, WH)
+    outs = plan.run(pairs, ref.packed, disp_outs=disp_outs)
+    torch.cuda.synchronize()
+    for i, p, o, dg in zip(UNEVEN_IDX, ps, outs, disp_outs):
+        H, W = p.left.shape
+        lo, _, _, d = oracle.match(p.left, p.right, F, WW, WH, p.D)
+        assert np.array_equal(dg.cpu().numpy(), d[0]), f"pair {i} ({W}x{H}, D {p.D}): coarse map"
+        t = vae.forward(params, d, lo, F, H, W)
+        e = normwise(o.cpu().numpy()[None], t["out"])
+        assert e <= 1e-5, f"pair {i} ({W}x{H}): normwise {e:.2e}"
+    plan.close()
+
+
 def test_uneven_workload_pairs_subset():
     """Eight pairs of the 64-pair uneven workload (widths 640-1280, heights 192-384)."""
     import paper_2305_11566_amd as sv
@@ -148,4 +178,4 @@ def test_autotune_cache_and_results_unchanged(tmp_path, monkeypatch):
     finally:
         for layer in range(9):
             sv.sv_set_layer_cfg(layer, -1)
-        sv.sv_set_cost_wta_split(4)
+        sv.sv_set_cost_wta_split(0)

@@ -75,10 +75,12 @@ def test_backward_f32_matches_oracle(H, W, f, C, L, B, with_eps):
     g_or, dout, _ = _oracle_grad(params, disp, img, f, H, W, eps, gt, klw)
     g_gpu, _ = _gpu_grad(C, L, f, "f32", params, disp, img, H, W, eps, dout, klw)
     names = vae.LAYERS
+    # the 32x16 instance (the finite-difference check's size) is held to 1e-5
+    tol = 1e-5 if (H, W) == (32, 16) else 1e-4
     for name, sl in zip(names, _layer_slices(C, L)):
         e = normwise(g_gpu[sl], g_or[sl])
-        assert e <= 1e-4, f"{name}: normwise {e:.2e}"
-    assert normwise(g_gpu, g_or) <= 1e-5 * 10
+        assert e <= tol, f"{name}: normwise {e:.2e}"
+    assert normwise(g_gpu, g_or) <= tol
 
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])

@@ -139,7 +139,9 @@ def test_reduced_precision_epe(dtype, deconv_form):
     epe = float(np.mean(np.abs(out - t["out"])))
     scale = float(np.mean(np.abs(t["out"])))
     print(f"{dtype}: mean EPE {epe:.4f} px, max {np.max(np.abs(out - t['out'])):.3f} px, mean |out| {scale:.2f}")
-    assert epe <= 0.02 * scale + 0.05
+    # He-init weights (outputs of about 52 px): measured 0.12 px (BF16) and
+    # 0.013 px (FP16); the bars leave about 1.7x of headroom
+    assert epe <= {"bf16": 0.2, "f16": 0.025}[dtype]
 
 
 def test_loss_matches_oracle():

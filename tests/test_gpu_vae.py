@@ -87,8 +87,10 @@ def test_f32_training_forward_with_eps():
 
 @pytest.mark.parametrize("dtype", ["bf16", "f16"])
 def test_reduced_precision_epe(dtype):
-    """Mean end-point error against the FP64 oracle, in full-res px; He-init
-    weights make the residual large, so the bound here is loose."""
+    """Mean end-point error against the FP64 oracle, in full-res px, on He-init
+    weights (a refinement term of about 50 px, so a stress case: the 0.05 px
+    bar applies to the realistic refinement of the precision workload
+    below)."""
     p = gen_preset("pair256x128")
     lo, _, _, d = oracle.match(p.left, p.right, 2, 5, 5, 16)
     params = vae_params((16, 32, 64), 64, 7)
@@ -97,7 +99,50 @@ def test_reduced_precision_epe(dtype):
     epe = float(np.mean(np.abs(out - t["out"])))
     scale = float(np.mean(np.abs(t["out"])))
     print(f"{dtype}: mean EPE {epe:.4f} px, max {np.max(np.abs(out - t['out'])):.3f} px, mean |out| {scale:.2f}")
-    assert epe <= 0.02 * scale + 0.05
+    # measured 0.15 px (BF16) and 0.018 px (FP16); about 1.7x of headroom
+    assert epe <= {"bf16": 0.25, "f16": 0.03}[dtype]
+
+
+def _precision_params(C, L, seed, f_scale):
+    """He-init weights with the final layer scaled by f_scale: 0.01 gives a
+    refinement term of a few px, as trained weights do, where He-init's is
+    of order 100 px."""
+    params = vae_params(C, L, seed)
+    wF, bF = params[8]
+    params[8] = ((wF * np.float32(f_scale)).astype(np.float32), (bF * np.float32(f_scale)).astype(np.float32))
+    return params
+
+
+@pytest.mark.parametrize("dtype", ["bf16", "f16"])
+def test_precision_bar_batch8_256x128(dtype):
+    """The 8-pair 256x128 precision workload (seeds 3000-3007) through census
+    + WTA and the 256x128 network with the final layer at 0.01 x He-init:
+    mean |out - out_f32| <= 0.05 px, and the same bar against the FP64
+    oracle."""
+    import paper_2305_11566_amd as sv
+    C, L, f, H, W, D = (16, 32, 64), 64, 2, 128, 256, 16
+    ps = [gen_preset("batch8_256x128", i) for i in range(8)]
+    left = cuda(np.stack([p.left for p in ps]))
+    right = cuda(np.stack([p.right for p in ps]))
+    cl, cr, low = sv.sv_census_pair(left, right, f, 5, 5)
+    disp = sv.sv_cost_wta(cl, cr, D, 24)
+    torch.cuda.synchronize()
+    d_np, lo_np = disp.cpu().numpy(), low.cpu().numpy()
+    ref_d = [oracle.match(p.left, p.right, f, 5, 5, D) for p in ps]
+    assert np.array_equal(d_np, np.concatenate([r[3] for r in ref_d]))
+    params = _precision_params(C, L, 7003, 0.01)
+    t = vae.forward(params, d_np, lo_np, f, H, W)
+    o32, _ = _gpu_forward(C, L, f, "f32", params, d_np, lo_np, H, W)
+    o16, _ = _gpu_forward(C, L, f, dtype, params, d_np, lo_np, H, W)
+    gt = np.stack([p.gt for p in ps])
+    vs32 = np.abs(o16.astype(np.float64) - o32)
+    vs64 = np.abs(o16 - t["out"])
+    print(f"{dtype} 8x256x128: vs f32 mean {vs32.mean():.4f} max {vs32.max():.4f} px; vs oracle mean "
+          f"{vs64.mean():.4f} max {vs64.max():.4f}; refinement term mean "
+          f"{np.mean(np.abs(t['out'] - 256 * t['base'])):.3f} px; f32 vs gt {np.mean(np.abs(o32 - gt)):.3f}")
+    assert normwise(o32, t["out"]) <= TOL_F32
+    assert vs32.mean() <= 0.05
+    assert vs64.mean() <= 0.05
 
 
 def _split_of(name):
