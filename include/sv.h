@@ -15,7 +15,19 @@
  *    allocates inside these calls, except sv_batch_plan_create/_destroy and
  *    sv_autotune, which own what they allocate.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
- *    call is asynchronous on it; nothing here synchronises the host.
+ *    call is asynchronous on it and returns without waiting for the device,
+ *    except the calls that say otherwise: sv_autotune and sv_tvae_autotune
+ *    (they time kernels), sv_profile_read (it reads the recorded events),
+ *    sv_batch_plan_destroy, and sv_stereo_batch only when the plan's ring of
+ *    pinned pair tables wraps onto a table whose upload is still in flight.
+ *  - Calls are re-entrant: several threads may call any entry point at once
+ *    on their own buffers and streams.  The process-wide settings
+ *    (sv_set_layer_cfg, sv_set_cost_wta_split, sv_set_latent_fusion,
+ *    sv_tvae_set_layer_cfg, sv_tvae_set_deconv_form, sv_profile_enable) are
+ *    atomic and apply to calls that start after the setter returns; the
+ *    autotuners pass the configurations they time with each call and change
+ *    no such setting; the autotune caches are guarded by a mutex.  A batch
+ *    plan is one mutable object: one thread at a time per plan.
  *  - All arguments are validated before anything is enqueued, and validation
  *    makes no HIP call; a failed check returns a negative code and enqueues
  *    nothing.  A HIP launch error is returned as SV_ERR_HIP; errors raised
@@ -121,8 +133,10 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
 sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D,
                       int nbits, uint8_t *disp_out, void *stream);
 
-/* Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8; default 4).  The
- * result does not depend on it.  Process-wide; not for concurrent use. */
+/* Lanes per pixel of the cost + WTA kernel for all later calls: 1, 2, 4 or 8,
+ * or 0 (the default) for the per-shape choice -- the split sv_autotune timed
+ * fastest for this (B, h, w, D) in this process, else 4.  The result does not
+ * depend on it.  Process-wide, atomic.  Errors: SV_ERR_RANGE. */
 sv_status sv_set_cost_wta_split(int dsplit);
 
 /* ------------------------------------------------------------------------ */
@@ -346,7 +360,12 @@ sv_status sv_batch_plan_destroy(sv_batch_plan *plan);
 
 /* Run n pairs (host array) through the plan on `stream`.  Uses the graph
  * unless the environment sets SV_DISABLE_GRAPH=1 (then: the same launches,
- * eager).  Results are bitwise identical either way. */
+ * eager).  Results are bitwise identical either way.  The pair table is
+ * written into the next of four pinned host copies and uploaded on `stream`;
+ * the call returns without waiting for the device unless that copy's upload
+ * from four calls earlier has not finished.  The plan's device buffers are
+ * reused by every call: successive calls on one plan must run on one stream
+ * (or be ordered by the caller). */
 sv_status sv_stereo_batch(sv_batch_plan *plan, const sv_pair *pairs, int n, const void *packed_w,
                           void *stream);
 

@@ -2,6 +2,10 @@
 // dispatch to the launchers.
 #include <string.h>
 
+#include <array>
+#include <atomic>
+#include <map>
+#include <mutex>
 #include <string>
 
 #include "net.h"
@@ -80,13 +84,27 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
 
 }  // extern "C"
 
-static int g_dsplit = 4;
+// Lanes per pixel of the cost + WTA kernel: an explicit setting
+// (sv_set_cost_wta_split), else the split the autotuner measured fastest for
+// this (B, h, w, D) in this process, else 4.  The result never depends on it.
+static std::atomic<int> g_dsplit_override{0};
+static std::mutex g_dsplit_mu;
+static std::map<std::array<int, 4>, int> g_dsplit_tuned;
 
 namespace sv {
-int cost_wta_split_get() { return g_dsplit; }
-void cost_wta_split_set(int d) {
-    if (d == 1 || d == 2 || d == 4 || d == 8) g_dsplit = d;
+int cost_wta_split_for(int B, int h, int w, int D) {
+    const int ov = g_dsplit_override.load();
+    if (ov > 0) return ov;
+    std::lock_guard<std::mutex> lk(g_dsplit_mu);
+    auto it = g_dsplit_tuned.find({B, h, w, D});
+    return it != g_dsplit_tuned.end() ? it->second : 4;
 }
+void cost_wta_split_tuned(int B, int h, int w, int D, int d) {
+    if (d != 1 && d != 2 && d != 4 && d != 8) return;
+    std::lock_guard<std::mutex> lk(g_dsplit_mu);
+    g_dsplit_tuned[{B, h, w, D}] = d;
+}
+int cost_wta_split_override() { return g_dsplit_override.load(); }
 }  // namespace sv
 
 extern "C" {
@@ -97,7 +115,7 @@ sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h
     if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > kMaxSide) return SV_ERR_SHAPE;
     if (D < 1 || D > 256 || nbits < 1 || nbits > 64) return SV_ERR_RANGE;
     prof_mark(PROF_COST_WTA, 0, (hipStream_t)stream);
-    sv_status r = launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, g_dsplit,
+    sv_status r = launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, cost_wta_split_for(B, h, w, D),
                                   (hipStream_t)stream);
     prof_mark(PROF_COST_WTA, 1, (hipStream_t)stream);
     return r;
@@ -163,10 +181,11 @@ sv_status sv_smp_median(const uint8_t *disp_in, int B, int h, int w, int D, uint
                              (hipStream_t)stream);
 }
 
-// Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8); for tuning and tests.
+// Lanes per pixel of the cost + WTA kernel (1, 2, 4 or 8; 0 restores the
+// per-shape choice); for tuning and tests.
 sv_status sv_set_cost_wta_split(int dsplit) {
-    if (dsplit != 1 && dsplit != 2 && dsplit != 4 && dsplit != 8) return SV_ERR_RANGE;
-    g_dsplit = dsplit;
+    if (dsplit != 0 && dsplit != 1 && dsplit != 2 && dsplit != 4 && dsplit != 8) return SV_ERR_RANGE;
+    g_dsplit_override.store(dsplit);
     return SV_OK;
 }
 

@@ -24,10 +24,16 @@
 
 namespace sv {
 
-int cost_wta_split_get();
-void cost_wta_split_set(int);
+int cost_wta_split_for(int B, int h, int w, int D);
+void cost_wta_split_tuned(int B, int h, int w, int D, int d);
+int cost_wta_split_override();
 
 static const int kStageGridMax = 1024;
+
+// Pinned host copies of the pair table a plan cycles through: a call waits
+// on the host only when the copy it takes is still being uploaded by the call
+// SV_TAB_RING calls earlier.
+#define SV_TAB_RING 4
 
 }  // namespace sv
 
@@ -44,7 +50,10 @@ struct sv_batch_plan {
     size_t cap[4];
     void *dev;
     PairTable *tab_dev;
-    PairTable *tab_host;
+    PairTable *tab_host[SV_TAB_RING];    // pinned staging copies, used in turn
+    hipEvent_t tab_done[SV_TAB_RING];    // recorded after the upload from that copy
+    bool tab_pending[SV_TAB_RING];
+    unsigned long long calls;
     uint64_t *cl, *cr;
     uint8_t *low, *disp;
     void *E1, *E2, *E3, *G3, *G2, *G1, *G0;
@@ -53,8 +62,6 @@ struct sv_batch_plan {
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void *graph_w;
-    hipEvent_t upload_done;
-    bool upload_pending;
 };
 
 namespace sv {
@@ -328,8 +335,8 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     pl->max_n = max_n; pl->max_H = max_H; pl->max_W = max_W; pl->max_D = max_D;
     pl->win_w = win_w; pl->win_h = win_h; pl->nbits = win_w * win_h - 1;
     // tile shapes: the autotune cache, else the single-call defaults
-    pl->dsplit = cost_wta_split_get();
     const Levels mx = net_levels(ns, max_H, max_W);
+    pl->dsplit = cost_wta_split_for(max_n, mx.h[0], mx.w[0], max_D);
     pl->cen_th = census_tile_height(max_n, mx.h[0], mx.w[0]);
     for (int i = 0; i < NLAYERS; ++i) {
         const int lvl = i == L_E1 ? 1 : (i == L_E2 ? 2 : (i <= L_G3 ? 3 : (i == L_G2 ? 2 : (i == L_G1 ? 1 : 0))));
@@ -338,7 +345,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     int ds;
     int cfg[NLAYERS];
     if (tuned_lookup(ns, max_n, max_H, max_W, cfg, &ds)) {
-        pl->dsplit = ds;
+        pl->dsplit = cost_wta_split_override() > 0 ? cost_wta_split_override() : ds;
         for (int i = 0; i < NLAYERS; ++i) {
             const int ov = net_get_cfg_override(ns.dtype, i);
             pl->cfg[i] = ov >= 0 ? ov : cfg[i];
@@ -380,9 +387,12 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     pl->low = (uint8_t *)(d + o_low); pl->disp = (uint8_t *)(d + o_disp);
     pl->E1 = d + o_E1; pl->E2 = d + o_E2; pl->E3 = d + o_E3; pl->ML = (float *)(d + o_ML);
     pl->G3 = d + o_G3; pl->G2 = d + o_G2; pl->G1 = d + o_G1; pl->G0 = d + o_G0;
-    if ((e = hipHostMalloc((void **)&pl->tab_host, sizeof(PairTable), hipHostMallocDefault)) != hipSuccess ||
-        (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&pl->upload_done, hipEventDisableTiming)) != hipSuccess) {
+    e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking);
+    for (int k = 0; k < SV_TAB_RING && e == hipSuccess; ++k) {
+        e = hipHostMalloc((void **)&pl->tab_host[k], sizeof(PairTable), hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->tab_done[k], hipEventDisableTiming);
+    }
+    if (e != hipSuccess) {
         sv_batch_plan_destroy(pl);
         return hip_fail(e, "batch plan resources");
     }
@@ -392,11 +402,14 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
 
 sv_status sv_batch_plan_destroy(sv_batch_plan *pl) {
     if (!pl) return SV_OK;
-    if (pl->upload_pending) (void)hipEventSynchronize(pl->upload_done);
+    for (int k = 0; k < SV_TAB_RING; ++k)
+        if (pl->tab_pending[k]) (void)hipEventSynchronize(pl->tab_done[k]);
     destroy_graph(pl);
-    if (pl->upload_done) (void)hipEventDestroy(pl->upload_done);
+    for (int k = 0; k < SV_TAB_RING; ++k) {
+        if (pl->tab_done[k]) (void)hipEventDestroy(pl->tab_done[k]);
+        if (pl->tab_host[k]) (void)hipHostFree(pl->tab_host[k]);
+    }
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
-    if (pl->tab_host) (void)hipHostFree(pl->tab_host);
     if (pl->dev) (void)hipFree(pl->dev);
     delete pl;
     return SV_OK;
@@ -414,9 +427,14 @@ sv_status sv_stereo_batch(sv_batch_plan *pl, const sv_pair *pairs, int n, const 
         if (p.D < 1 || p.D > pl->max_D) return SV_ERR_RANGE;
     }
     hipStream_t st = (hipStream_t)stream;
-    // the pinned table may still be read by the previous call's copy
-    if (pl->upload_pending) SV_HIP(hipEventSynchronize(pl->upload_done));
-    PairTable *t = pl->tab_host;
+    // the next pinned copy in turn; it may still be read by the upload of the
+    // call SV_TAB_RING calls ago, the only case in which the host waits
+    const int slot = (int)(pl->calls % SV_TAB_RING);
+    if (pl->tab_pending[slot]) {
+        SV_HIP(hipEventSynchronize(pl->tab_done[slot]));
+        pl->tab_pending[slot] = false;
+    }
+    PairTable *t = pl->tab_host[slot];
     t->n = n;
     long long off[4] = {0, 0, 0, 0};
     for (int s = 0; s < BS_NSTAGES; ++s) t->cum[s][0] = 0;
@@ -436,9 +454,12 @@ sv_status sv_stereo_batch(sv_batch_plan *pl, const sv_pair *pairs, int n, const 
         for (int s = 0; s < BS_NSTAGES; ++s) t->cum[s][i + 1] = t->cum[s][i] + tiles[s];
     }
     const size_t bytes = offsetof(PairTable, pair) + sizeof(PairGeo) * (size_t)n;
+    // the device table is single: stream order puts this upload after the
+    // previous call's kernels on the same stream
     SV_HIP(hipMemcpyAsync(pl->tab_dev, t, bytes, hipMemcpyHostToDevice, st));
-    SV_HIP(hipEventRecord(pl->upload_done, st));
-    pl->upload_pending = true;
+    SV_HIP(hipEventRecord(pl->tab_done[slot], st));
+    pl->tab_pending[slot] = true;
+    ++pl->calls;
     if (graph_disabled()) return enqueue_stages(pl, packed_w, st);
     if (!pl->exec || pl->graph_w != packed_w) {
         sv_status r = capture(pl, packed_w);
@@ -492,12 +513,12 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
     hipLaunchKernelGGL(k_zero_f32, dim3(256), dim3(256), 0, st, (float *)(d + o_par), (size_t)ns.nparams);
     r = net_pack(ns, (const float *)(d + o_par), d + o_pk, st);
     const int reps = 8;
-    int best_ds = cost_wta_split_get();
-    int best_cfg[NLAYERS], saved_ov[NLAYERS];
-    for (int i = 0; i < NLAYERS; ++i) {
-        best_cfg[i] = net_default_cfg(ns, i, 0);
-        saved_ov[i] = net_get_cfg_override(ns.dtype, i);
-    }
+    int best_ds = 4;
+    // the configurations under test travel with each forward call (cur), so
+    // tuning changes no process-wide setting and other threads' calls are
+    // unaffected
+    int best_cfg[NLAYERS], cur[NLAYERS];
+    for (int i = 0; i < NLAYERS; ++i) best_cfg[i] = cur[i] = net_heuristic_cfg(ns, i);
     if (r == SV_OK) {
         // census once, then every lane split of the cost + WTA kernel
         r = launch_reduce_census((uint8_t *)(d + o_l), (uint8_t *)(d + o_r), B, H, W, W, ns.f, win_w,
@@ -533,10 +554,9 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         // layer, the extra launch of a split reduction) count.
         constexpr int NKEEP = 5;
         int keep[NLAYERS][NKEEP], nkeep[NLAYERS] = {};
-        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
         auto fwd_on = [&](hipStream_t s_, int only) {
             return net_forward(ns, d + o_pk, (uint8_t *)(d + o_disp), (uint8_t *)(d + o_low), B, H, W,
-                               nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, s_, only);
+                               nullptr, (float *)(d + o_out), nullptr, nullptr, d + o_ws, s_, only, cur);
         };
         auto fwd = [&](int only) { return fwd_on(st, only); };
         // mean time per replay of a graph holding one whole forward pass, best
@@ -605,7 +625,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
                 // a split that falls back to one pass repeats an unsplit candidate
                 if (conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, c) != c) continue;
                 if (net_layer_split(ns, i, c, B, H, W) != c / conv_num_tiles() + 1) continue;
-                net_set_cfg_override(ns.dtype, i, c);
+                cur[i] = c;
                 const float t = timed(nrep, i);
                 if (r != SV_OK) break;
                 if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-14s alone %8.2f us\n",
@@ -623,7 +643,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
                 }
             }
             if (nkeep[i] > 0) best_cfg[i] = keep[i][0];
-            net_set_cfg_override(ns.dtype, i, best_cfg[i]);
+            cur[i] = best_cfg[i];
         }
         (void)hipStreamSynchronize(st);  // stage 1's launches are done before the replays
         const int nrep2 = B >= 16 ? 6 : 50;
@@ -633,24 +653,22 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
                 float best_t = 1e30f;
                 int best_c = best_cfg[i];
                 for (int k = 0; k < nkeep[i] && r == SV_OK; ++k) {
-                    net_set_cfg_override(ns.dtype, i, keep[i][k]);
+                    cur[i] = keep[i][k];
                     const float t = graph_timed(nrep2);
                     if (verbose) fprintf(stderr, "sv_autotune dt%d B%d %dx%d layer %d cfg %-14s whole pass %8.2f us\n",
                                          ns.dtype, B, H, W, i, conv_cfg_name(keep[i][k]), t * 1e3f);
                     if (t < best_t) { best_t = t; best_c = keep[i][k]; }
                 }
                 best_cfg[i] = best_c;
-                net_set_cfg_override(ns.dtype, i, best_c);
+                cur[i] = best_c;
             }
         }
-        for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, -1);
         if (cs) (void)hipStreamDestroy(cs);
     }
     (void)hipStreamSynchronize(st);
     (void)hipFree(mem);
-    for (int i = 0; i < NLAYERS; ++i) net_set_cfg_override(ns.dtype, i, saved_ov[i]);
     if (r != SV_OK) return r;
-    cost_wta_split_set(best_ds);
+    cost_wta_split_tuned(B, h, w, D, best_ds);
     TuneEntry e = make_key(ns, B, H, W);
     e.dsplit = best_ds;
     for (int i = 0; i < NLAYERS; ++i) e.cfg[i] = best_cfg[i];
@@ -676,7 +694,11 @@ sv_status sv_tile_config(int stage, char *buf, int buflen) {
         snprintf(buf, buflen, "census tile %dx4 (one frame) or %dx16 (from 512 tall tiles)", CEN_TILE_W,
                  CEN_TILE_W);
     } else if (stage == 1) {
-        snprintf(buf, buflen, "cost_wta dsplit=%d", cost_wta_split_get());
+        const int ov = cost_wta_split_override();
+        if (ov > 0)
+            snprintf(buf, buflen, "cost_wta dsplit=%d (set)", ov);
+        else
+            snprintf(buf, buflen, "cost_wta dsplit per shape (autotuned, else 4)");
     } else if (stage >= 2 && stage < 2 + NLAYERS) {
         const int o32 = net_get_cfg_override(SV_F32, stage - 2), o16 = net_get_cfg_override(SV_BF16, stage - 2);
         snprintf(buf, buflen, "layer %d override f32=%s bf16=%s", stage - 2,

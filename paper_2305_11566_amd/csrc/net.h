@@ -54,6 +54,8 @@ enum AmaxSlot { AM_E1 = 0, AM_E2, AM_E3, AM_ML, AM_G3, AM_G2, AM_G1, AM_G0, AM_X
 // Tile configuration per layer (index into the conv kernel's table); the
 // defaults may be replaced by the autotuner.
 int net_default_cfg(const NetShape &ns, int layer, int M);
+// The built-in choice for a layer, ignoring overrides and the autotune cache.
+int net_heuristic_cfg(const NetShape &ns, int layer);
 // Per-layer tile configuration of a forward pass of batch B at H x W: an
 // explicit override, else the autotune cache entry for this shape, else the
 // default.
@@ -66,10 +68,13 @@ bool tuned_lookup(const NetShape &ns, int B, int H, int W, int *cfg, int *dsplit
 void net_set_cfg_override(int dtype, int layer, int cfg);   // -1 restores the default
 int net_get_cfg_override(int dtype, int layer);
 
-// only >= 0: launch that network layer alone (for timing), nothing else
+// only >= 0: launch that network layer alone (for timing), nothing else;
+// cfg_in (nullable, NLAYERS entries): the layers' configurations for this call
+// in place of net_layer_cfgs (the autotuner passes its candidates this way)
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,
-                      float *ml_user, void *saved, void *ws, hipStream_t st, int only = -1);
+                      float *ml_user, void *saved, void *ws, hipStream_t st, int only = -1,
+                      const int *cfg_in = nullptr);
 
 sv_status net_backward(const NetShape &ns, const void *packed, const void *saved, int B, int H,
                        int W, const float *eps, const float *dout, const float *dml_extra,

@@ -122,14 +122,18 @@ int net_get_cfg_override(int dtype, int layer) {
                                                                        : -1;
 }
 
-int net_default_cfg(const NetShape &ns, int layer, int M) {
-    const int ov = net_get_cfg_override(ns.dtype, layer);
-    if (ov >= 0 && ov < conv_num_cfgs()) return ov;
+int net_heuristic_cfg(const NetShape &ns, int layer) {
     const int cout = layer == L_F ? 16 : ns.ly[layer].cout;
-    (void)M;
     if (cout <= 16) return 5;   // th4_tn16
     if (cout <= 32) return 2;   // th4_tn32
     return 0;                   // th4_tn64
+}
+
+int net_default_cfg(const NetShape &ns, int layer, int M) {
+    const int ov = net_get_cfg_override(ns.dtype, layer);
+    if (ov >= 0 && ov < conv_num_cfgs()) return ov;
+    (void)M;
+    return net_heuristic_cfg(ns, layer);
 }
 
 void net_layer_cfgs(const NetShape &ns, int B, int H, int W, int *cfg) {
@@ -239,11 +243,17 @@ static inline void ev_rec(int i, int which, hipStream_t st) { prof_mark(PROF_E1 
 
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,
-                      float *ml_user, void *saved, void *ws, hipStream_t st, int only) {
+                      float *ml_user, void *saved, void *ws, hipStream_t st, int only,
+                      const int *cfg_in) {
     const Levels lv = net_levels(ns, H, W);
     const ActLayout a = net_act_layout(ns, lv, B);
     int cfg[NLAYERS];
-    net_layer_cfgs(ns, B, H, W, cfg);
+    if (cfg_in) {
+        for (int i = 0; i < NLAYERS; ++i)
+            cfg[i] = i < L_F ? conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, cfg_in[i]) : cfg_in[i];
+    } else {
+        net_layer_cfgs(ns, B, H, W, cfg);
+    }
     char *w = (char *)ws;
     const bool train = saved != nullptr;                   // keep what the backward needs
     char *sv_ = train ? (char *)saved : w + a.ws_fwd;      // else it lives in the workspace

@@ -1,5 +1,6 @@
 // Optional per-stage timing with HIP events, recorded on the stream each
 // kernel is launched on (for the benchmark's roofline figures).
+#include <atomic>
 #include <mutex>
 #include <vector>
 
@@ -8,7 +9,7 @@
 namespace sv {
 
 static std::mutex g_mu;
-static bool g_on = false;
+static std::atomic<bool> g_on{false};
 static int g_max = 0;
 static std::vector<hipEvent_t> g_ev[PROF_NSTAGES];  // 2 * max per stage
 static int g_count[PROF_NSTAGES];
@@ -22,9 +23,9 @@ static void free_events() {
 }
 
 void prof_mark(int stage, int which, hipStream_t st) {
-    if (!g_on) return;
+    if (!g_on.load()) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_on || stage < 0 || stage >= PROF_NSTAGES) return;
+    if (!g_on.load() || stage < 0 || stage >= PROF_NSTAGES) return;
     const int i = g_count[stage];
     if (i >= g_max) return;
     (void)hipEventRecord(g_ev[stage][2 * i + which], st);

@@ -614,9 +614,14 @@ sv_status tv_layer(const TvShape &s, const void *packed, int li, ConvSrc s0, Con
 
 sv_status tv_forward(const TvShape &s, int f, const void *packed, const uint8_t *disp, const uint8_t *img,
                      int B, int H, int W, const float *eps, float *out, float *ml_user, void *ws,
-                     hipStream_t st, int only = -1) {
+                     hipStream_t st, int only = -1, const int *cfg_in = nullptr) {
+    // cfg_in (nullable): this call's configurations (the autotuner's candidates)
     int cfg[T_NL];
-    tv_layer_cfgs(s.dtype, f, B, H, W, cfg);
+    if (cfg_in) {
+        for (int i = 0; i < T_NL; ++i) cfg[i] = cfg_in[i];
+    } else {
+        tv_layer_cfgs(s.dtype, f, B, H, W, cfg);
+    }
     const TvLevels lv = tv_levels(f, H, W);
     const TvAct a = tv_act(s.es, lv, B);
     char *w = (char *)ws;
@@ -1207,9 +1212,12 @@ sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
     hipLaunchKernelGGL(k_zero_bytes, dim3(4096), dim3(256), 0, st, (uint32_t *)d, off / 4);
     sv_status r = tv_pack(s, (const float *)(d + o_par), d + o_pk, st);
     const uint8_t *disp = (const uint8_t *)(d + o_in), *img = disp + nlow;
+    // the configurations under test travel with each call (cur): tuning
+    // changes no process-wide setting, so other threads' calls are unaffected
+    int cur[T_NL], base[T_NL], best[T_NL];
     auto run = [&](int only) {
         return tv_forward(s, factor, d + o_pk, disp, img, B, H, W, nullptr, (float *)(d + o_out), nullptr,
-                          d + o_ws, st, only);
+                          d + o_ws, st, only, cur);
     };
     auto timed = [&](int only, int reps) {
         hipEvent_t a, b;
@@ -1226,14 +1234,11 @@ sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
         (void)hipEventDestroy(b);
         return t / reps;
     };
-    int saved[T_NL], base[T_NL], best[T_NL];
-    for (int i = 0; i < T_NL; ++i) saved[i] = g_tv_cfg[i].exchange(-1);
-    {
-        std::lock_guard<std::mutex> g(g_tv_mu);
-        g_tv_tuned.erase(std::make_tuple(dtype, factor, B, H, W));
+    for (int i = 0; i < T_NL; ++i) {
+        const int k = kOutLevel[i];
+        base[i] = tv_heuristic_cfg(i, B, lv.h[k], lv.w[k]);
+        best[i] = cur[i] = base[i];
     }
-    tv_layer_cfgs(dtype, factor, B, H, W, base);
-    for (int i = 0; i < T_NL; ++i) best[i] = base[i];
     const int reps = B >= 16 ? 4 : 12;
     for (int li = 0; li < T_NL && r == SV_OK; ++li) {
         if (li == T_FE) continue;  // a direct stencil, no tile configuration
@@ -1249,28 +1254,26 @@ sv_status sv_tvae_autotune(int dtype, int factor, int B, int H, int W) {
             static float dummy;
             const TvAct a = tv_act(s.es, lv, B);
             if (conv_effective_split(dt, c, kLayers[li].cin, npix, s.n_pad[li], &dummy, a.part_bytes) != want) continue;
-            g_tv_cfg[li].store(c);
+            cur[li] = c;
             const float t = timed(li, reps);
             if (t < bt) { bt = t; best[li] = c; }
         }
-        g_tv_cfg[li].store(-1);
+        cur[li] = base[li];
     }
     if (r == SV_OK) {
         // keep the tuned set only if the whole pass is faster than the defaults
         const float t0 = timed(-1, reps);
-        {
-            std::lock_guard<std::mutex> g(g_tv_mu);
+        for (int i = 0; i < T_NL; ++i) cur[i] = best[i];
+        const float t1 = timed(-1, reps);
+        std::lock_guard<std::mutex> g(g_tv_mu);
+        if (t1 < t0) {
             std::array<int, T_NL> a;
             for (int i = 0; i < T_NL; ++i) a[i] = best[i];
             g_tv_tuned[std::make_tuple(dtype, factor, B, H, W)] = a;
-        }
-        const float t1 = timed(-1, reps);
-        if (!(t1 < t0)) {
-            std::lock_guard<std::mutex> g(g_tv_mu);
+        } else {
             g_tv_tuned.erase(std::make_tuple(dtype, factor, B, H, W));
         }
     }
-    for (int i = 0; i < T_NL; ++i) g_tv_cfg[i].store(saved[i]);
     const hipError_t e = hipFree(mem);
     if (r == SV_OK && e != hipSuccess) r = hip_fail(e, "hipFree");
     return r;

@@ -16,13 +16,38 @@ def _cdiv(a, b):
     return -(-a // b)
 
 
-def _need(t, dtype, name):
+def _need(t, dtype, name, shape=None, device=None):
+    """Checks a tensor handed to the library: a contiguous GPU tensor of this
+    dtype and, when given, this shape and device.  The C ABI sees only a
+    pointer, so a buffer of the wrong size must be refused here, before any
+    call (a kernel would read or write past it)."""
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype != dtype:
         raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if device is not None and not _same_device(t.device, device):
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _same_device(a, b):
+    """torch.device("cuda") names the current device: compare indices."""
+    a, b = torch.device(a), torch.device(b)
+    if a.type != b.type:
+        return False
+    ia = a.index if a.index is not None else torch.cuda.current_device()
+    ib = b.index if b.index is not None else torch.cuda.current_device()
+    return ia == ib
+
+
+def _need_numel(t, dtype, name, n, device=None):
+    """As _need, for a flat buffer of at least n elements."""
+    _need(t, dtype, name, device=device)
+    if t.numel() < n:
+        raise ValueError(f"{name} must hold at least {n} elements, got {t.numel()}")
 
 
 # ---------------------------------------------------------------- matching
@@ -38,6 +63,9 @@ def sv_census(img: torch.Tensor, factor: int, win_w: int, win_h: int, want_low: 
     h, w = _cdiv(H, factor), _cdiv(W, factor)
     if out is not None:
         cen, low = out
+        _need(cen, torch.int64, "census out", (B, h, w), img.device)
+        if low is not None:
+            _need(low, torch.uint8, "reduced image out", (B, h, w), img.device)
     else:
         cen = torch.empty((B, h, w), dtype=torch.int64, device=img.device)
         low = torch.empty((B, h, w), dtype=torch.uint8, device=img.device) if want_low else None
@@ -64,6 +92,9 @@ def sv_census_pair(left: torch.Tensor, right: torch.Tensor, factor: int, win_w: 
         low = torch.empty((B, h, w), dtype=torch.uint8, device=left.device)
     else:
         cl, cr, low = out
+        _need(cl, torch.int64, "census L out", (B, h, w), left.device)
+        _need(cr, torch.int64, "census R out", (B, h, w), left.device)
+        _need(low, torch.uint8, "reduced image out", (B, h, w), left.device)
     check(lib().sv_census_pair(ptr(left), ptr(right), B, H, W, W, factor, win_w, win_h, ptr(low),
                                ptr(cl), ptr(cr), stream_ptr()), "sv_census_pair")
     return cl, cr, low
@@ -79,6 +110,7 @@ def sv_cost_wta(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int,
     B, h, w = cen_l.shape
     if out is None:
         out = torch.empty((B, h, w), dtype=torch.uint8, device=cen_l.device)
+    _need(out, torch.uint8, "out", (B, h, w), cen_l.device)
     check(lib().sv_cost_wta(ptr(cen_l), ptr(cen_r), B, h, w, D, nbits, ptr(out), stream_ptr()),
           "sv_cost_wta")
     return out
@@ -99,6 +131,8 @@ def sv_sgm(cen_l: torch.Tensor, cen_r: torch.Tensor, D: int, nbits: int, P1: int
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=cen_l.device)
     if out is None:
         out = torch.empty((B, h, w), dtype=torch.uint8, device=cen_l.device)
+    _need(out, torch.uint8, "out", (B, h, w), cen_l.device)
+    _need_numel(workspace, torch.uint8, "workspace", need, cen_l.device)
     check(lib().sv_sgm(ptr(cen_l), ptr(cen_r), B, h, w, D, nbits, P1, P2, ptr(out), ptr(workspace),
                        workspace.numel(), stream_ptr()), "sv_sgm")
     return out
@@ -117,6 +151,8 @@ def sv_zncc_sgm(low_l: torch.Tensor, low_r: torch.Tensor, D: int, win_w: int, wi
                                 device=low_l.device)
     if out is None:
         out = torch.empty((B, h, w), dtype=torch.uint8, device=low_l.device)
+    _need(out, torch.uint8, "out", (B, h, w), low_l.device)
+    _need_numel(workspace, torch.uint8, "workspace", lib().sv_sgm_workspace_bytes(B, h, w, D), low_l.device)
     check(lib().sv_zncc_sgm(ptr(low_l), ptr(low_r), B, h, w, D, win_w, win_h, P1, P2, ptr(out),
                             ptr(workspace), workspace.numel(), stream_ptr()), "sv_zncc_sgm")
     return out
@@ -125,8 +161,10 @@ def sv_zncc_sgm(low_l: torch.Tensor, low_r: torch.Tensor, D: int, win_w: int, wi
 def sv_zncc_cost(low_l: torch.Tensor, low_r: torch.Tensor, D: int, win_w: int, win_h: int):
     """Reduced images uint8 [B, h, w] -> integer ZNCC cost uint8 [B, h, w, D]."""
     _need(low_l, torch.uint8, "low_l")
-    _need(low_r, torch.uint8, "low_r")
+    if low_l.dim() != 3:
+        raise ValueError("low_l must be [B, h, w]")
     B, h, w = low_l.shape
+    _need(low_r, torch.uint8, "low_r", (B, h, w), low_l.device)
     out = torch.empty((B, h, w, D), dtype=torch.uint8, device=low_l.device)
     check(lib().sv_zncc_cost(ptr(low_l), ptr(low_r), B, h, w, D, win_w, win_h, ptr(out), stream_ptr()),
           "sv_zncc_cost")
@@ -144,6 +182,8 @@ def sv_smp_median(disp: torch.Tensor, D: int, out: torch.Tensor | None = None,
                                 device=disp.device)
     if out is None:
         out = torch.empty_like(disp)
+    _need(out, torch.uint8, "out", (B, h, w), disp.device)
+    _need_numel(workspace, torch.uint8, "workspace", lib().sv_smp_workspace_bytes(B, h, w), disp.device)
     check(lib().sv_smp_median(ptr(disp), B, h, w, D, ptr(out), ptr(workspace), workspace.numel(),
                               stream_ptr()), "sv_smp_median")
     return out
@@ -229,18 +269,28 @@ class Refiner:
 
     def forward(self, disp_low, img_low, H, W, eps=None, saved=None, out=None, mu_logvar=None):
         """-> (out [B, H, W] full-res px, mu_logvar [B, h3, w3, 2L])."""
-        _need(disp_low, torch.uint8, "disp_low")
-        _need(img_low, torch.uint8, "img_low")
+        if disp_low.dim() != 3:
+            raise ValueError("disp_low must be [B, h, w]")
         B = disp_low.shape[0]
+        f = self.desc.factor
+        low = (B, _cdiv(H, f), _cdiv(W, f))
+        dev = self.device
+        _need(disp_low, torch.uint8, "disp_low", low, dev)
+        _need(img_low, torch.uint8, "img_low", low, dev)
+        s = self.latent_shape(B, H, W)
         if out is None:
-            out = torch.empty((B, H, W), dtype=torch.float32, device=self.device)
+            out = torch.empty((B, H, W), dtype=torch.float32, device=dev)
         if mu_logvar is None:
-            s = self.latent_shape(B, H, W)
-            mu_logvar = torch.empty(s[:3] + (2 * s[3],), dtype=torch.float32, device=self.device)
+            mu_logvar = torch.empty(s[:3] + (2 * s[3],), dtype=torch.float32, device=dev)
+        _need(out, torch.float32, "out", (B, H, W), dev)
+        _need(mu_logvar, torch.float32, "mu_logvar", s[:3] + (2 * s[3],), dev)
         if eps is not None:
-            _need(eps, torch.float32, "eps")
+            _need(eps, torch.float32, "eps", s, dev)
             if saved is None:
                 raise ValueError("training forward needs a saved buffer")
+        if saved is not None:
+            _need_numel(saved, torch.uint8, "saved",
+                        lib().sv_vae_saved_bytes(ctypes.byref(self.desc), B, H, W), dev)
         ws = self.workspace(B, H, W)
         check(lib().sv_vae_forward(ctypes.byref(self.desc), ptr(self.packed), ptr(disp_low),
                                    ptr(img_low), B, H, W, ptr(eps), ptr(out), ptr(mu_logvar),
@@ -249,11 +299,18 @@ class Refiner:
 
     def backward(self, saved, B, H, W, eps, dout, kl_weight, grad=None, dmu_logvar=None):
         """Gradient of sum(dout * out) + kl_weight * KL (+ sum(dmu_logvar * mu_logvar))."""
-        _need(dout, torch.float32, "dout")
+        dev = self.device
+        s = self.latent_shape(B, H, W)
+        _need(dout, torch.float32, "dout", (B, H, W), dev)
+        _need_numel(saved, torch.uint8, "saved", lib().sv_vae_saved_bytes(ctypes.byref(self.desc), B, H, W),
+                    dev)
+        if eps is not None:
+            _need(eps, torch.float32, "eps", s, dev)
         if dmu_logvar is not None:
-            _need(dmu_logvar, torch.float32, "dmu_logvar")
+            _need(dmu_logvar, torch.float32, "dmu_logvar", s[:3] + (2 * s[3],), dev)
         if grad is None:
-            grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+            grad = torch.empty(self.nparams, dtype=torch.float32, device=dev)
+        _need(grad, torch.float32, "grad", (self.nparams,), dev)
         ws = self.workspace(B, H, W)
         check(lib().sv_vae_backward(ctypes.byref(self.desc), ptr(self.packed), ptr(saved), B, H, W,
                                     ptr(eps), ptr(dout), ptr(dmu_logvar), ctypes.c_float(kl_weight),
@@ -288,14 +345,21 @@ def vae_param_count(c1, c2, c3, latent, factor=2, dtype="f32") -> int:
 def sv_loss(out, gt, mu_logvar, latent, kl_weight, loss_out=None, dout=None, workspace=None):
     """-> (loss[3] = {total, data, KL} on the device, dout).  mu_logvar may be None."""
     _need(out, torch.float32, "out")
-    _need(gt, torch.float32, "gt")
     dev = out.device
+    _need(gt, torch.float32, "gt", out.shape, dev)
     if loss_out is None:
         loss_out = torch.empty(3, dtype=torch.float32, device=dev)
     if dout is None:
         dout = torch.empty_like(out)
     if workspace is None:
         workspace = torch.empty(lib().sv_loss_workspace_bytes(), dtype=torch.uint8, device=dev)
+    _need(loss_out, torch.float32, "loss_out", (3,), dev)
+    _need(dout, torch.float32, "dout", out.shape, dev)
+    _need_numel(workspace, torch.uint8, "workspace", lib().sv_loss_workspace_bytes(), dev)
+    if mu_logvar is not None:
+        _need(mu_logvar, torch.float32, "mu_logvar", device=dev)
+        if mu_logvar.shape[-1] != 2 * latent:
+            raise ValueError(f"mu_logvar rows must hold 2 * latent = {2 * latent} values")
     n_lat = 0 if mu_logvar is None else mu_logvar.numel() // (2 * latent)
     check(lib().sv_loss(ptr(out), ptr(gt), out.numel(), ptr(mu_logvar), n_lat, latent,
                         ctypes.c_float(kl_weight), ptr(loss_out), ptr(dout), ptr(workspace),
@@ -305,7 +369,7 @@ def sv_loss(out, gt, mu_logvar, latent, kl_weight, loss_out=None, dout=None, wor
 
 def sv_adam_step(w, g, m, v, step, lr=5e-4, beta1=0.99, beta2=0.999, eps=1e-8):
     for t, n in ((w, "w"), (g, "g"), (m, "m"), (v, "v")):
-        _need(t, torch.float32, n)
+        _need(t, torch.float32, n, w.shape, w.device)
     check(lib().sv_adam_step(ptr(w), ptr(g), ptr(m), ptr(v), w.numel(), step, ctypes.c_float(lr),
                              ctypes.c_float(beta1), ctypes.c_float(beta2), ctypes.c_float(eps),
                              stream_ptr()), "sv_adam_step")
@@ -332,11 +396,18 @@ class BatchPlan:
         arr = (Pair * n)()
         if outs is None:
             outs = [torch.empty(l.shape, dtype=torch.float32, device=l.device) for l, _, _ in pairs]
+        if len(outs) != n or (disp_outs is not None and len(disp_outs) != n):
+            raise ValueError("one output (and coarse map) per pair")
         for i, (l, r, D) in enumerate(pairs):
             _need(l, torch.uint8, "left")
-            _need(r, torch.uint8, "right")
+            if l.dim() != 2:
+                raise ValueError("left must be [H, W]")
             H, W = l.shape
+            _need(r, torch.uint8, "right", (H, W), l.device)
+            _need(outs[i], torch.float32, "out", (H, W), l.device)
             dl = disp_outs[i] if disp_outs is not None else None
+            if dl is not None:
+                _need(dl, torch.uint8, "disp_out", (_cdiv(H, self.factor), _cdiv(W, self.factor)), l.device)
             arr[i] = Pair(l.data_ptr(), r.data_ptr(), outs[i].data_ptr(),
                           dl.data_ptr() if dl is not None else None, H, W, D)
         check(lib().sv_stereo_batch(self._plan, arr, n, ptr(packed), stream_ptr()), "sv_stereo_batch")
@@ -442,16 +513,21 @@ class TableVAE:
 
     def forward(self, disp_low, img_low, H, W, eps=None, out=None, mu_sigma=None):
         """-> (out [B, H, W] full-res px, mu_sigma [B, h3, w3, 2])."""
-        _need(disp_low, torch.uint8, "disp_low")
-        _need(img_low, torch.uint8, "img_low")
+        if disp_low.dim() != 3:
+            raise ValueError("disp_low must be [B, h, w]")
         B = disp_low.shape[0]
+        dev = self.device
+        low = (B, _cdiv(H, self.factor), _cdiv(W, self.factor))
+        _need(disp_low, torch.uint8, "disp_low", low, dev)
+        _need(img_low, torch.uint8, "img_low", low, dev)
         if out is None:
-            out = torch.empty((B, H, W), dtype=torch.float32, device=self.device)
+            out = torch.empty((B, H, W), dtype=torch.float32, device=dev)
         if mu_sigma is None:
-            mu_sigma = torch.empty(self.latent_shape(B, H, W) + (2,), dtype=torch.float32,
-                                   device=self.device)
+            mu_sigma = torch.empty(self.latent_shape(B, H, W) + (2,), dtype=torch.float32, device=dev)
+        _need(out, torch.float32, "out", (B, H, W), dev)
+        _need(mu_sigma, torch.float32, "mu_sigma", self.latent_shape(B, H, W) + (2,), dev)
         if eps is not None:
-            _need(eps, torch.float32, "eps")
+            _need(eps, torch.float32, "eps", self.latent_shape(B, H, W), dev)
         ws = self.workspace(B, H, W)
         check(lib().sv_tvae_forward(self.dtype_code, self.factor, ptr(self.packed), ptr(disp_low),
                                     ptr(img_low), B, H, W, ptr(eps), ptr(out), ptr(mu_sigma), ptr(ws),
@@ -461,12 +537,21 @@ class TableVAE:
     def backward(self, disp_low, img_low, H, W, dout, eps=None, dmu_sigma=None, grad=None):
         """Gradient of sum(dout * out) + sum(dmu_sigma * mu_sigma) after forward() on the
         same inputs (its workspace holds the activations)."""
-        _need(dout, torch.float32, "dout")
         B = disp_low.shape[0]
+        dev = self.device
+        low = (B, _cdiv(H, self.factor), _cdiv(W, self.factor))
+        _need(disp_low, torch.uint8, "disp_low", low, dev)
+        _need(img_low, torch.uint8, "img_low", low, dev)
+        _need(dout, torch.float32, "dout", (B, H, W), dev)
+        if eps is not None:
+            _need(eps, torch.float32, "eps", self.latent_shape(B, H, W), dev)
+        if dmu_sigma is not None:
+            _need(dmu_sigma, torch.float32, "dmu_sigma", self.latent_shape(B, H, W) + (2,), dev)
         if self._ws_key != (B, H, W):
             raise ValueError("backward() needs the forward pass of the same shape just before")
         if grad is None:
-            grad = torch.empty(self.nparams, dtype=torch.float32, device=self.device)
+            grad = torch.empty(self.nparams, dtype=torch.float32, device=dev)
+        _need(grad, torch.float32, "grad", (self.nparams,), dev)
         key = ("bwd", B, H, W)
         if getattr(self, "_bws_key", None) != key:
             n = lib().sv_tvae_backward_workspace_bytes(self.dtype_code, self.factor, B, H, W)
@@ -482,10 +567,13 @@ class TableVAE:
 def sv_tvae_loss(out, gt, noc, occ, mu_sigma, want_grad=True):
     """Eqs. (9)-(11) -> (loss [3] = total, Loss_1, Loss_2; dout or None; dmu_sigma or None)."""
     _need(out, torch.float32, "out")
-    _need(gt, torch.float32, "gt")
-    _need(noc, torch.uint8, "noc")
-    _need(occ, torch.uint8, "occ")
-    _need(mu_sigma, torch.float32, "mu_sigma")
+    dev = out.device
+    _need(gt, torch.float32, "gt", out.shape, dev)
+    _need(noc, torch.uint8, "noc", out.shape, dev)
+    _need(occ, torch.uint8, "occ", out.shape, dev)
+    _need(mu_sigma, torch.float32, "mu_sigma", device=dev)
+    if mu_sigma.shape[-1] != 2:
+        raise ValueError("mu_sigma must be [..., 2]")
     loss = torch.empty(3, dtype=torch.float32, device=out.device)
     dout = torch.empty_like(out) if want_grad else None
     dml = torch.empty_like(mu_sigma) if want_grad else None

@@ -95,7 +95,7 @@ def test_lane_split_variants_identical(dsplit):
         sv.sv_set_cost_wta_split(dsplit)
         _check(p.left, p.right, 4, 9, 7, 48)
     finally:
-        sv.sv_set_cost_wta_split(4)
+        sv.sv_set_cost_wta_split(0)
 
 
 def test_determinism_repeat():
