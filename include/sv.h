@@ -290,6 +290,27 @@ sv_status sv_vae_forward(const sv_vae_desc *desc, const void *packed_w, const ui
                          void *stream);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): sv_vae_forward at
+ * inference (eps = NULL) with no workspace argument and no allocation.  Its
+ * workspace is a device array of the library, SV_STATIC_SCRATCH_BYTES (32 MiB)
+ * on every GPU it runs on, held until the process ends; the first call on a
+ * device looks up that device's copy.  Same arguments, layouts and results
+ * (bitwise) as sv_vae_forward with eps, saved and workspace omitted, for any
+ * compute dtype.  A shape whose inference workspace exceeds the array -- for
+ * the 1242x375 network (32-64-128, latent 128, f = 4) batches above 2 --
+ * returns SV_ERR_WORKSPACE and enqueues nothing.  Every call on one GPU
+ * shares the array: calls that overlap on a device (two streams, two threads)
+ * race and corrupt each other's results; order them.
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE, SV_ERR_DTYPE,
+ *         SV_ERR_WORKSPACE, SV_ERR_HIP.
+ */
+#define SV_STATIC_SCRATCH_BYTES (32u << 20)
+sv_status sv_vae_forward_static(const sv_vae_desc *desc, const void *packed_w,
+                                const uint8_t *disp_low, const uint8_t *img_low, int B, int H,
+                                int W, float *out, float *mu_logvar, void *stream);
+
+/*
  * Gradient of  sum(dout * out) + kl_weight * KL  with respect to every
  * parameter, for the training forward whose activations are in `saved`
  * (same desc, B, H, W, eps).  KL is the mean over latent elements of

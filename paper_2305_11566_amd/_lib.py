@@ -68,6 +68,7 @@ _SIGS = {
     "sv_vae_workspace_bytes": (_SZ, [_DESC, _I, _I, _I]),
     "sv_vae_saved_bytes": (_SZ, [_DESC, _I, _I, _I]),
     "sv_vae_forward": (ctypes.c_int32, [_DESC, _P, _P, _P, _I, _I, _I, _P, _P, _P, _P, _P, _SZ, _P]),
+    "sv_vae_forward_static": (ctypes.c_int32, [_DESC, _P, _P, _P, _I, _I, _I, _P, _P, _P]),
     "sv_vae_backward": (ctypes.c_int32, [_DESC, _P, _P, _I, _I, _I, _P, _P, _P, _F, _P, _P, _SZ, _P]),
     "sv_loss": (ctypes.c_int32, [_P, _P, _I64, _P, _I64, _I, _F, _P, _P, _P, _SZ, _P]),
     "sv_loss_workspace_bytes": (_SZ, []),

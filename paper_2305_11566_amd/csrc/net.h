@@ -45,6 +45,10 @@ struct ActLayout {
 };
 ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B);
 
+// Device bytes an inference pass uses: the workspace part plus the decoder
+// maps and [mu | logvar] that live behind it when nothing is saved.
+size_t net_infer_bytes(const NetShape &ns, const Levels &lv, int B);
+
 // Extra workspace of the backward pass (after the forward's workspace part).
 size_t net_bwd_workspace(const NetShape &ns, const Levels &lv, int B);
 

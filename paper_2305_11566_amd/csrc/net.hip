@@ -104,6 +104,11 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
     return a;
 }
 
+size_t net_infer_bytes(const NetShape &ns, const Levels &lv, int B) {
+    const ActLayout a = net_act_layout(ns, lv, B);
+    return a.ws_fwd + a.saved;
+}
+
 // ---- tile configuration per layer ----------------------------------------------
 // per compute dtype and layer; -1 = default
 static std::atomic<int> g_cfg_override[4][NLAYERS];

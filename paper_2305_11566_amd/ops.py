@@ -297,6 +297,29 @@ class Refiner:
                                    ptr(saved), ptr(ws), ws.numel(), stream_ptr()), "sv_vae_forward")
         return out, mu_logvar
 
+    def forward_static(self, disp_low, img_low, H, W, out=None, mu_logvar=None):
+        """Inference through sv_vae_forward_static (the library's own fixed
+        scratch, no workspace) -> (out [B, H, W], mu_logvar [B, h3, w3, 2L])."""
+        if disp_low.dim() != 3:
+            raise ValueError("disp_low must be [B, h, w]")
+        B = disp_low.shape[0]
+        f = self.desc.factor
+        low = (B, _cdiv(H, f), _cdiv(W, f))
+        dev = self.device
+        _need(disp_low, torch.uint8, "disp_low", low, dev)
+        _need(img_low, torch.uint8, "img_low", low, dev)
+        s = self.latent_shape(B, H, W)
+        if out is None:
+            out = torch.empty((B, H, W), dtype=torch.float32, device=dev)
+        if mu_logvar is None:
+            mu_logvar = torch.empty(s[:3] + (2 * s[3],), dtype=torch.float32, device=dev)
+        _need(out, torch.float32, "out", (B, H, W), dev)
+        _need(mu_logvar, torch.float32, "mu_logvar", s[:3] + (2 * s[3],), dev)
+        check(lib().sv_vae_forward_static(ctypes.byref(self.desc), ptr(self.packed), ptr(disp_low),
+                                          ptr(img_low), B, H, W, ptr(out), ptr(mu_logvar), stream_ptr()),
+              "sv_vae_forward_static")
+        return out, mu_logvar
+
     def backward(self, saved, B, H, W, eps, dout, kl_weight, grad=None, dmu_logvar=None):
         """Gradient of sum(dout * out) + kl_weight * KL (+ sum(dmu_logvar * mu_logvar))."""
         dev = self.device
