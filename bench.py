@@ -58,8 +58,11 @@ def stage_work(stage, B, dtype):
     (bound, amount, unit) with unit GB or TFLOP or Tops."""
     hs, ws = levels(B)
     px = [B * hs[k] * ws[k] for k in range(4)]
+    es = 4 if dtype == "f32" else 2
+    if stage == "E1":  # direct stencil: read the coarse maps, write E1
+        return "hbm", (2.0 * px[0] + px[1] * C1 * es) / 1e9, "GB"
     conv = {  # (M, N, K) of the implicit GEMM
-        "E1": (px[1], C1, 2 * 9), "E2": (px[2], C2, C1 * 9), "E3": (px[3], C3, C2 * 9),
+        "E2": (px[2], C2, C1 * 9), "E3": (px[3], C3, C2 * 9),
         "HEAD": (px[3], 2 * LAT, C3), "G3": (px[3], C3, LAT),
         "G2": (px[2], C2, (C3 + C2) * 9), "G1": (px[1], C1, (C2 + C1) * 9),
         "G0": (px[0], C1, (C1 + 2) * 9),
@@ -73,9 +76,8 @@ def stage_work(stage, B, dtype):
         return "hbm", (2.0 * B * H * W + 2 * 8.0 * px[0] + px[0]) / 1e9, "GB"
     if stage == "cost_wta":  # 6 integer ops per (pixel, d): 2 xor, 2 popcount, pack, min
         return "alu", 6.0 * D * px[0] / 1e12, "Tops"
-    if stage == "final_gather":  # write the full-res map; read G0, the coarse map and the reduced image
-        es = 4 if dtype == "f32" else 2
-        return "hbm", (4.0 * B * H * W + (C1 * es + 2.0) * px[0]) / 1e9, "GB"
+    if stage == "final_gather":  # write the full-res map; read the nine FP32 projections and the coarse map
+        return "hbm", (4.0 * B * H * W + (9 * 4 + 1.0) * px[0]) / 1e9, "GB"
     return None, 0.0, ""
 
 
@@ -685,16 +687,19 @@ def main():
                        "frames_per_s": round(bb * 1e3 / msb, 1)}
                 flop, sec = 0.0, 0.0
                 layers = {}
-                for st_ in ("E1", "E2", "E3", "HEAD", "G3", "HEAD+G3", "G2", "G1", "G0"):
+                for st_ in ("census", "cost_wta", "E1", "E2", "E3", "HEAD", "G3", "HEAD+G3", "G2", "G1", "G0",
+                            "final_gather"):
                     tot, cnt = profb.get(st_, (0.0, 0))
                     if cnt == 0:
                         continue
-                    _, tf, _ = stage_work(st_, bb, dt)
+                    bound, amount, _ = stage_work(st_, bb, dt)
                     us = tot / cnt * 1e3
-                    layers[st_] = {"avg_us": round(us, 2),
-                                   "mfma_frac": round(tf / (us * 1e-6) / PEAK["mfma_TFLOPs"][dt], 4)}
+                    rate = amount / (us * 1e-6)
+                    peak = {"mfma": PEAK["mfma_TFLOPs"][dt], "hbm": PEAK["hbm_GBs"],
+                            "alu": PEAK["alu_Tops"]}[bound]
+                    layers[st_] = {"avg_us": round(us, 2), "bound": bound, "frac": round(rate / peak, 4)}
                     if st_ in ("E2", "E3", "G2", "G1", "G0"):
-                        flop += tf
+                        flop += amount
                         sec += us * 1e-6
                 rec["layers"] = layers
                 rec["mfma_frac_dense_layers"] = round(flop / sec / PEAK["mfma_TFLOPs"][dt], 4) if sec else None

@@ -665,7 +665,9 @@ sv_status net_backward(const NetShape &ns, const void *packed, const void *saved
             p.out = out; p.out_pitch = cout; p.act = 1;
             return launch_conv(dt, 3, 2, net_default_cfg(ns, li, B * h[ko] * wd[ko]), p, st);
         };
-        SV_TRY(fwd(L_E1, x0, 0, 1, E1, c1));
+        SV_TRY(launch_enc1(dt, disp, img, (float)ns.f / 256.0f, B, h[0], wd[0], h[1], wd[1], c1,
+                           (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
+                           (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st));
         SV_TRY(fwd(L_E2, T_(E1, c1, 1), 1, 2, E2, c2));
         SV_TRY(fwd(L_E3, T_(E2, c2, 2), 2, 3, E3, c3));
     }

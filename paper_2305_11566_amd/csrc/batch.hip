@@ -216,6 +216,7 @@ static void pair_tiles(const sv_batch_plan *pl, const PairGeo &g, int *tiles) {
     for (const LayerRun &r : kRuns)
         tiles[r.stage] = conv_tiles(pl->cfg[r.li], g.h[r.out_level], g.w[r.out_level],
                                     run_cout(pl->ns, r.li));
+    tiles[BS_E1] = enc1_tiles(g.h[1], g.w[1]);  // E1 runs as a direct stencil
     tiles[BS_FINAL] = cdiv(g.W, FIN_TILE_W) * cdiv(g.H, FIN_TILE_H);
 }
 
@@ -256,8 +257,12 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
         {tsrc(pl->G2, SRC_RESIZE, c2, c2, 2, 0), tsrc(pl->E1, SRC_TENSOR, c1, c1, 1, 0), pl->G1, c1, 0, 1},
         {tsrc(pl->G1, SRC_RESIZE, c1, c1, 1, 0), x0, pl->G0, c1, 0, 1},
     };
+    r = launch_enc1_tab(ns.dtype, pl->tab_dev, pl->grid[BS_E1], pl->disp, pl->low, x0.scale0, c1,
+                        (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
+                        (const float *)((const char *)packed + ns.b_off[L_E1]), pl->E1, st);
+    if (r != SV_OK) return r;
     // the final layer's projection runs inside the final gather
-    for (int k = 0; k < 8; ++k) {
+    for (int k = 1; k < 8; ++k) {
         const LayerRun &run = kRuns[k];
         const int li = run.li;
         ConvParams p{};
@@ -269,11 +274,26 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
         p.bias = li == L_F ? nullptr : (const float *)((const char *)packed + ns.b_off[li]);
         p.out = ins[k].out; p.out_pitch = ins[k].pitch; p.out_f32 = ins[k].f32; p.act = ins[k].act;
         p.tab = pl->tab_dev; p.stage = run.stage; p.in_level = run.in_level; p.out_level = run.out_level;
+        if (li == L_G0 && net_projects(ns, false)) {
+            // G0's epilogue writes the final layer's tap projections (FP32
+            // planes of cap[0] pixels) into G0's buffer
+            p.proj_w = (const float *)((const char *)packed + ns.w_off[L_F]);
+            p.proj_pitch = ns.cin_pad[L_F];
+            p.proj_out = (float *)pl->G0;
+            p.proj_plane = (long long)pl->cap[0];
+            p.proj_disp = pl->disp;
+            p.proj_img = pl->low;
+            p.proj_scale0 = x0.scale0;
+        }
         const int ks = li == L_F ? 1 : ns.ly[li].k, stride = li == L_F ? 1 : ns.ly[li].stride;
         r = launch_conv_tab(li == L_F ? SV_F32 : ns.dtype, ks, stride, pl->cfg[li], p,
                             pl->grid[run.stage], st);
         if (r != SV_OK) return r;
     }
+    if (net_projects(ns, false))
+        return launch_final_gather_tab(pl->tab_dev, pl->grid[BS_FINAL], (const float *)pl->G0,
+                                       (long long)pl->cap[0], pl->disp, ns.f,
+                                       (const float *)((const char *)packed + ns.b_off[L_F]), st);
     return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], ns.dtype, pl->G0, c1, pl->disp, pl->low,
                             (const float *)((const char *)packed + ns.w_off[L_F]), ns.cin_pad[L_F],
                             ns.f, (const float *)((const char *)packed + ns.b_off[L_F]), st);
@@ -353,6 +373,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     }
     for (int i = 0; i < L_F; ++i)
         pl->cfg[i] = conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, pl->cfg[i]);
+    if (net_projects(ns, false)) pl->cfg[L_G0] = net_g0_proj_cfg(ns, pl->cfg[L_G0]);
     // capacities and persistent grid sizes from the largest pair
     for (int k = 0; k < 4; ++k) pl->cap[k] = (size_t)max_n * mx.h[k] * mx.w[k];
     PairGeo gmax{};
@@ -375,7 +396,8 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     const size_t o_E1 = take(pl->cap[1] * ns.c1 * es), o_E2 = take(pl->cap[2] * ns.c2 * es);
     const size_t o_E3 = take(pl->cap[3] * ns.c3 * es), o_ML = take(pl->cap[3] * 2 * ns.L * 4);
     const size_t o_G3 = take(pl->cap[3] * ns.c3 * es), o_G2 = take(pl->cap[2] * ns.c2 * es);
-    const size_t o_G1 = take(pl->cap[1] * ns.c1 * es), o_G0 = take(pl->cap[0] * ns.c1 * es);
+    const size_t o_G1 = take(pl->cap[1] * ns.c1 * es);
+    const size_t o_G0 = take(pl->cap[0] * std::max<size_t>((size_t)ns.c1 * es, 9 * sizeof(float)));
     hipError_t e = hipMalloc(&pl->dev, off);
     if (e != hipSuccess) {
         delete pl;
@@ -619,12 +641,16 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         r = fwd(-1);
         const int nrep = B >= 16 ? 6 : 24;
         for (int i = 0; i < L_F && r == SV_OK; ++i) {
+            if (i == L_E1 && ns.dtype != SV_I8) continue;  // a direct stencil, no tile configuration
             float kt[NKEEP];
             for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
                 // a tile shape that does not fit this layer would run as the fallback,
                 // a split that falls back to one pass repeats an unsplit candidate
                 if (conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, c) != c) continue;
                 if (net_layer_split(ns, i, c, B, H, W) != c / conv_num_tiles() + 1) continue;
+                // G0 carrying the final layer's projection runs unsplit on tiles that
+                // hold all of its channels: other candidates repeat one of those
+                if (i == L_G0 && net_projects(ns, false) && net_g0_proj_cfg(ns, c) != c) continue;
                 cur[i] = c;
                 const float t = timed(nrep, i);
                 if (r != SV_OK) break;

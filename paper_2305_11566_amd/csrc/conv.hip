@@ -151,6 +151,11 @@ sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvPa
     p.ksplit = conv_effective_split(dtype, cfg, p.Cin, (long long)p.B * p.Ho * p.Wo, p.n_pad, p.part,
                                     p.part_bytes);
     if (p.ophase) p.ksplit = 1;  // a phase launch writes its pixels straight into the full map
+    if (p.proj_out) {
+        // the projection epilogue needs whole sums and every channel in each wave
+        if (!conv_cfg_projects(cfg % kNumTiles, p.Cout) || dtype == SV_I8) return SV_ERR_UNSUPPORTED;
+        p.ksplit = 1;
+    }
     if (ksplit_used) *ksplit_used = p.ksplit > 1 ? p.ksplit : 1;
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
 }
@@ -164,9 +169,17 @@ sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvPara
     if (!p0.tab || grid <= 0) return SV_ERR_RANGE;
     if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
     cfg = conv_resolve_cfg(dtype, ks, stride, cfg);
+    if (p0.proj_out && (!conv_cfg_projects(cfg % kNumTiles, p0.Cout) || dtype == SV_I8))
+        return SV_ERR_UNSUPPORTED;
     ConvParams p = p0;
     p.ksplit = 1;  // the persistent path never splits
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, grid, st);
+}
+
+bool conv_cfg_projects(int cfg, int cout) {
+    if (cfg < 0) return false;
+    const CfgDesc &c = kCfgs[cfg % kNumTiles];
+    return c.TN >= cout && c.WM == 4;  // one channel tile; WN = 4 / WM = 1
 }
 
 void conv_cfg_tile(int cfg, int &TH, int &TN) {

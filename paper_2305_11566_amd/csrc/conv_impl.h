@@ -328,6 +328,96 @@ struct ConvTile {
         }
     }
 
+    // Final-layer projection epilogue (see ConvParams::proj_*), itself a small
+    // product on the matrix units: T[tap][pixel] = W_F[tap][c] . y[c][pixel]
+    // with the nine taps as the rows of A and the wave's 16-pixel blocks as
+    // the columns of B.  The wave holds every output channel of its pixels
+    // (one channel tile, WN = 1): lane (g, r16) has channels nb * 16 + 4 g + i
+    // of pixel r16, so B's k slots of lane group g are exactly those channels
+    // and A's rows are built with the same channel order.  FP32 runs the FP32
+    // instruction; 16-bit types feed y as stored (exact in the type) and the
+    // FP32 weights as a high and a low part, two products.  The accumulator
+    // comes back as taps 4 g' + i of pixel r16' in lane (g', r16'); the x0
+    // terms are added in FP32 and each lane writes its taps.
+    static __device__ __forceinline__ void project_epilogue(const ConvParams &p, const ConvGeo &G,
+                                                            const typename M::acc (&acc)[MBW][NBW],
+                                                            const float (&bpre)[NBW][4]) {
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int wm = wave % WM;
+        const int g = lane >> 4, r16 = lane & 15;
+        constexpr int SD = Store<DT>::v;
+        const int tap_row = r16 < 9 ? r16 : -1;   // A row = tap
+        // A: this lane's weights W_F[tap_row][nb * 16 + 4 g + i]
+        float wa[NBW][4];
+#pragma unroll
+        for (int nb = 0; nb < NBW; ++nb) {
+            const int n = nb * 16 + 4 * g;
+            const bool ok = tap_row >= 0 && n < p.Cout;  // Cout is a multiple of 8: all four or none
+            const f32x4 w4 = ok ? *(const f32x4 *)(p.proj_w + tap_row * p.proj_pitch + n) : f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) wa[nb][i] = w4[i];
+        }
+        // x0 weights of this lane's output taps 4 g + i
+        float wd[4], wi[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = 4 * g + i;
+            wd[i] = t < 9 ? p.proj_w[t * p.proj_pitch + p.Cout] : 0.f;
+            wi[i] = t < 9 ? p.proj_w[t * p.proj_pitch + p.Cout + 1] : 0.f;
+        }
+#pragma unroll
+        for (int mb = 0; mb < MBW; ++mb) {
+            // y as stored, this lane's channels of pixel r16
+            float val[NBW][4];
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float v = acc[mb][nb][i] + bpre[nb][i];
+                    v = v > 0.f ? v : 0.1f * v;
+                    const typename Elem<SD>::T st = Elem<SD>::make(v);
+                    val[nb][i] = nb * 16 + 4 * g + i < p.Cout ? Elem<SD>::load(&st) : 0.f;
+                }
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            if constexpr (DT == SV_F32) {
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) {
+                    const f32x4 a4 = {wa[nb][0], wa[nb][1], wa[nb][2], wa[nb][3]};
+                    const f32x4 b4 = {val[nb][0], val[nb][1], val[nb][2], val[nb][3]};
+                    c = M::run(a4, b4, c);
+                }
+            } else {
+#pragma unroll
+                for (int pr = 0; pr < (NBW + 1) / 2; ++pr) {
+                    float bv[8], ah[8], al[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const int nb = 2 * pr + j / 4, i = j % 4;
+                        const bool ok = nb < NBW;
+                        bv[j] = ok ? val[nb < NBW ? nb : 0][i] : 0.f;
+                        const float w = ok ? wa[nb < NBW ? nb : 0][i] : 0.f;
+                        const typename Elem<DT>::T wh = Elem<DT>::make(w);
+                        ah[j] = Elem<DT>::load(&wh);
+                        al[j] = w - ah[j];
+                    }
+                    const vec bq = pack_vec<DT, 8>(bv, 0.f);
+                    c = M::run(pack_vec<DT, 8>(ah, 0.f), bq, c);
+                    c = M::run(pack_vec<DT, 8>(al, 0.f), bq, c);
+                }
+            }
+            const int oy = G.oy0 + wm * MBW + mb, ox = G.ox0 + r16;
+            if (oy >= G.Ho || ox >= G.Wo) continue;
+            const size_t pix = (size_t)(G.obase + (long long)oy * G.Wo + ox);
+            const float xd = p.proj_scale0 * (float)p.proj_disp[pix];
+            const float xi = (float)p.proj_img[pix] * (1.0f / 256.0f);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int t = 4 * g + i;
+                if (t < 9) p.proj_out[t * p.proj_plane + pix] = fmaf(wi[i], xi, fmaf(wd[i], xd, c[i]));
+            }
+        }
+    }
+
     static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm,
                                                int kz) {
         T *patch = sm.patch, *wl = sm.wl;
@@ -368,7 +458,10 @@ struct ConvTile {
         const T *wpk = (const T *)p.wpk;
         int c_begin = 0, c_end = p.Cin;
         if (p.ksplit > 1) split_range(p.Cin, KCB, p.ksplit, kz, c_begin, c_end);
+        static_assert(KCGB == 4, "a base chunk is four channel groups, one per lane group");
         for (int c0 = c_begin; c0 < c_end; c0 += KC) {
+            // base chunks of this round that hold input channels
+            const int nsub = min(KCM, (c_end - c0 + KCB - 1) / KCB);
             __syncthreads();
             // ---- staging: the input patch (at the precomputed source pixels) and
             // the chunk of weights.  e = pix * KCG + cg and 256 is a multiple of
@@ -566,7 +659,19 @@ struct ConvTile {
                         }
                         *(vec *)&patch[pix * KCP] = pack_vec<DT, GS>(v, qinv);
                     }
-                } else if (!fast_resize && !fast_plain && kind != SRC_NONE) {
+                }
+                if (kind == SRC_NONE && c < c0 + nsub * KCB) {
+                    // a channel group past Cin (or past the range) that the MFMA
+                    // steps read: zeros (stale LDS could hold NaN, and NaN x 0 is NaN)
+                    vec z;
+#pragma unroll
+                    for (int i = 0; i < GS; ++i) z[i] = 0;
+#pragma unroll
+                    for (int k = 0; k < NE; ++k) {
+                        const int pix = pix0 + k * PSTEP;
+                        if (pix < NPIX) *(vec *)&patch[pix * KCP + cg * GS] = z;
+                    }
+                } else if (!x0_only && !fast_resize && !fast_plain && kind != SRC_NONE) {
 #pragma unroll
                     for (int k = 0; k < NE; ++k) {
                         const int pix = pix0 + k * PSTEP;
@@ -599,51 +704,43 @@ struct ConvTile {
                 }
             }
             __syncthreads();
-            // ---- MFMA over (tap, channel-group) pairs, base chunk by base chunk --
+            // ---- MFMA, base chunk by base chunk, tap by tap ---------------------
+            // Step = tap; lane group g supplies channel group g of the chunk
+            // (channels past Cin are zero in the patch and the weights), so each
+            // operand address is a per-lane base plus a compile-time offset.  The
+            // chunk loop stays rolled: one set of accumulator registers carried
+            // through it, no copies between branches.
+#pragma clang loop unroll(disable)
+            for (int sub = 0; sub < nsub; ++sub) {
+                const T *pb = patch + (size_t)((wm * MBW) * S * PW + r16 * S) * KCP + (sub * KCGB + g) * GS;
+                const T *pa = wl + (size_t)((wn * NBW) * 16 + r16) * KCP + (sub * KCGB + g) * GS;
 #pragma unroll
-            for (int sub = 0; sub < KCM; ++sub) {
-            if (c0 + sub * KCB >= c_end) break;
-            // channel groups of this base chunk that hold input channels (fewer
-            // than KCGB only in the chunk that ends at Cin): the (tap, group)
-            // pairs run over those alone, so a small Cin costs few steps
-            const int keff = min(KCGB, (c_end - c0 - sub * KCB + GS - 1) / GS);
-            const int npairs = TAPS * keff;
-            const int krcp = (256 + keff - 1) / keff;  // q / keff = (q * krcp) >> 8 for q < 128 (keff <= 4)
-            // unrolled so the LDS operand loads of later steps are issued ahead
-            // of the MFMAs of earlier ones
+                for (int tap = 0; tap < TAPS; ++tap) {
+                    const int u = tap / KS, v = tap % KS;
+                    vec bf[MBW], af[NBW];
 #pragma unroll
-            for (int st = 0; st < NSTEP; ++st) {
-                if (st * 4 >= npairs) break;
-                const int q = st * 4 + g;
-                const bool valid = q < npairs;
-                const int tap = valid ? (q * krcp) >> 8 : 0;
-                const int cg = sub * KCGB + (valid ? q - tap * keff : 0);
-                const int u = tap / KS, v = tap - (tap / KS) * KS;
-                vec bf[MBW], af[NBW];
+                    for (int mb = 0; mb < MBW; ++mb)
+                        bf[mb] = *(const vec *)(pb + ((mb * S + u) * PW + v) * KCP);
 #pragma unroll
-                for (int mb = 0; mb < MBW; ++mb) {
-                    const int ty = wm * MBW + mb;
-                    bf[mb] = *(const vec *)&patch[((ty * S + u) * PW + (r16 * S + v)) * KCP + cg * GS];
-                    if (!valid) {
+                    for (int nb = 0; nb < NBW; ++nb)
+                        af[nb] = *(const vec *)(pa + (tap * TN + nb * 16) * KCP);
 #pragma unroll
-                        for (int i = 0; i < GS; ++i) bf[mb][i] = 0;
-                    }
+                    for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                        for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = M::run(af[nb], bf[mb], acc[mb][nb]);
                 }
-#pragma unroll
-                for (int nb = 0; nb < NBW; ++nb) {
-                    const int n = (wn * NBW + nb) * 16 + r16;
-                    af[nb] = *(const vec *)&wl[(tap * TN + n) * KCP + cg * GS];
-                }
-#pragma unroll
-                for (int mb = 0; mb < MBW; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = M::run(af[nb], bf[mb], acc[mb][nb]);
-            }
             }
         }
 
-        // ---- epilogue: the FP32 partial of this channel range, or bias,
-        // activation, backward terms and the NHWC store ------------------------
+        // ---- epilogue -------------------------------------------------------
+        if constexpr (DT != SV_I8 && WN == 1) {
+            if (p.proj_out) {  // launches set it only for tiles that hold every channel
+                project_epilogue(p, G, acc, bpre);
+                return;
+            }
+        }
+        // the FP32 partial of this channel range, or bias, activation,
+        // backward terms and the NHWC store
         float lmax = 0.f;
 #pragma unroll
         for (int mb = 0; mb < MBW; ++mb) {

@@ -1,0 +1,193 @@
+// The first encoder layer E1 (Table I's encoder, first 3x3 stride-2
+// convolution + leaky ReLU) read straight from the coarse maps: its input x0
+// has two channels (f d / 256 and I / 256), so a direct stencil -- each thread
+// one output pixel and eight output channels, 18 fused multiply-adds per
+// channel -- does in a few registers what an implicit GEMM would pad to a full
+// channel chunk.  The weights are widened to FP32 in LDS once per workgroup
+// and read as one broadcast per wave (a wave owns one group of eight output
+// channels); the x0 patch of the tile is built in LDS as FP32.
+#include <algorithm>
+
+#include "kernels.h"
+
+namespace sv {
+
+constexpr int E1_TW = 16, E1_TH = 4;                      // output tile
+constexpr int E1_PW = 2 * E1_TW + 1, E1_PH = 2 * E1_TH + 1;  // x0 patch (stride 2, pad 1)
+constexpr int E1_MAXC = 256;
+
+struct Enc1Smem {
+    float x[2][E1_PH * E1_PW];
+    float w[9 * 2][E1_MAXC];   // [tap * 2 + channel][output channel]
+    float bias[E1_MAXC];
+};
+
+template <int DT>
+__device__ __forceinline__ void enc1_weights(Enc1Smem &sm, const typename Elem<DT>::T *__restrict__ wpk,
+                                             int n_pad, int cin_pad, const float *__restrict__ bias, int c1) {
+    for (int e = threadIdx.x; e < 18 * c1; e += 256) {
+        const int tc = e / c1, n = e - tc * c1;
+        const int tap = tc >> 1, c = tc & 1;
+        sm.w[tc][n] = Elem<DT>::load(wpk + ((size_t)tap * n_pad + n) * cin_pad + c);
+    }
+    for (int n = threadIdx.x; n < c1; n += 256) sm.bias[n] = bias[n];
+}
+
+// One tile: output rows [oy0, oy0 + E1_TH) and columns [ox0, ox0 + E1_TW) of
+// an h1 x w1 map from the h0 x w0 coarse maps.
+template <int DT>
+__device__ __forceinline__ void enc1_tile(Enc1Smem &sm, const uint8_t *__restrict__ disp,
+                                          const uint8_t *__restrict__ img, float scale0, int h0, int w0,
+                                          int h1, int w1, int c1, int oy0, int ox0,
+                                          typename Elem<DT>::T *__restrict__ out) {
+    const int tid = threadIdx.x;
+    const int iy0 = 2 * oy0 - 1, ix0 = 2 * ox0 - 1;
+    for (int e = tid; e < E1_PH * E1_PW; e += 256) {
+        const int py = e / E1_PW, px = e - py * E1_PW;
+        const int y = iy0 + py, x = ix0 + px;
+        float a = 0.f, c = 0.f;
+        if (y >= 0 && y < h0 && x >= 0 && x < w0) {
+            const size_t o = (size_t)y * w0 + x;
+            a = scale0 * (float)disp[o];
+            c = (float)img[o] * (1.0f / 256.0f);
+        }
+        sm.x[0][e] = a;
+        sm.x[1][e] = c;
+    }
+    __syncthreads();
+    const int lane = tid & 63;
+    const int grp = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform channel group
+    const int tx = lane & (E1_TW - 1), ty = lane / E1_TW;
+    const int oy = oy0 + ty, ox = ox0 + tx;
+    if (oy < h1 && ox < w1) {
+        // the 18 input values of this pixel, tap-major, disparity channel first
+        float xin[18];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int u = t / 3, v = t % 3;
+            const int q = (2 * ty + u) * E1_PW + 2 * tx + v;
+            xin[2 * t] = sm.x[0][q];
+            xin[2 * t + 1] = sm.x[1][q];
+        }
+        for (int g = grp; g * 8 < c1; g += 4) {
+            const int n0 = g * 8;
+            float acc[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = 0.f;
+#pragma unroll
+            for (int k = 0; k < 18; ++k) {
+                const f32x4 wa = *(const f32x4 *)&sm.w[k][n0];
+                const f32x4 wb = *(const f32x4 *)&sm.w[k][n0 + 4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    acc[i] = fmaf(wa[i], xin[k], acc[i]);
+                    acc[4 + i] = fmaf(wb[i], xin[k], acc[4 + i]);
+                }
+            }
+            float r[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const float s = acc[i] + sm.bias[n0 + i];
+                r[i] = s > 0.f ? s : 0.1f * s;
+            }
+            typename Elem<DT>::T *op = out + ((size_t)oy * w1 + ox) * c1 + n0;
+            if constexpr (DT == SV_F32) {
+                *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
+                *(f32x4 *)(op + 4) = f32x4{r[4], r[5], r[6], r[7]};
+            } else {
+                u16x8 q;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) q[i] = Elem<DT>::make(r[i]);
+                *(u16x8 *)op = q;
+            }
+        }
+    }
+    __syncthreads();  // the patch is reused by the next tile of a persistent loop
+}
+
+// Uniform batch: a persistent grid walks the tiles (image-major), so the
+// weights are widened into LDS once per workgroup.
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float scale0, int B, int h0, int w0,
+       int h1, int w1, int c1, const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad,
+       const float *__restrict__ bias, typename Elem<DT>::T *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) Enc1Smem sm;
+    enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
+    const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
+    const int per = tx * ty, total = per * B;
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int b = t / per, r = t - b * per;
+        const size_t i0 = (size_t)b * h0 * w0, o1 = (size_t)b * h1 * w1;
+        enc1_tile<DT>(sm, disp + i0, img + i0, scale0, h0, w0, h1, w1, c1, (r / tx) * E1_TH,
+                      (r % tx) * E1_TW, out + o1 * c1);
+    }
+}
+
+// Persistent variant over the pair table (flattened per-level buffers).
+template <int DT>
+__global__ void __launch_bounds__(256)
+k_enc1_tab(const PairTable *__restrict__ tab, const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img,
+           float scale0, int c1, const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad,
+           const float *__restrict__ bias, typename Elem<DT>::T *__restrict__ out) {
+    __shared__ __attribute__((aligned(16))) Enc1Smem sm;
+    enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
+    const int n = tab->n;
+    const int *cum = tab->cum[BS_E1];
+    const int total = cum[n];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &g = tab->pair[i];
+        const int local = t - cum[i];
+        const int tx = cdiv_d(g.w[1], E1_TW);
+        enc1_tile<DT>(sm, disp + g.off[0], img + g.off[0], scale0, g.h[0], g.w[0], g.h[1], g.w[1], c1,
+                      (local / tx) * E1_TH, (local % tx) * E1_TW, out + (size_t)g.off[1] * c1);
+    }
+}
+
+int enc1_tiles(int h1, int w1) { return cdiv(h1, E1_TH) * cdiv(w1, E1_TW); }
+
+sv_status launch_enc1(int dtype, const uint8_t *disp, const uint8_t *img, float scale0, int B, int h0, int w0,
+                      int h1, int w1, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
+                      void *out, hipStream_t st) {
+    if (c1 < 8 || c1 > E1_MAXC || c1 % 8) return SV_ERR_UNSUPPORTED;
+    const long long tiles = (long long)enc1_tiles(h1, w1) * B;
+    if (tiles >= (1ll << 31)) return SV_ERR_SHAPE;
+    const dim3 grid((unsigned)std::min<long long>(tiles, 2048));
+    switch (dtype) {
+#define SV_E1(D, T)                                                                                     \
+    case D:                                                                                             \
+        hipLaunchKernelGGL(k_enc1<D>, grid, dim3(256), 0, st, disp, img, scale0, B, h0, w0, h1, w1, c1, \
+                           (const T *)wpk, n_pad, cin_pad, bias, (T *)out);                             \
+        break;
+        SV_E1(SV_F32, float)
+        SV_E1(SV_BF16, uint16_t)
+        SV_E1(SV_F16, uint16_t)
+#undef SV_E1
+    default: return SV_ERR_DTYPE;
+    }
+    SV_LAUNCH_CHECK("k_enc1");
+    return SV_OK;
+}
+
+sv_status launch_enc1_tab(int dtype, const PairTable *tab, int grid, const uint8_t *disp, const uint8_t *img,
+                          float scale0, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
+                          void *out, hipStream_t st) {
+    if (c1 < 8 || c1 > E1_MAXC || c1 % 8) return SV_ERR_UNSUPPORTED;
+    switch (dtype) {
+#define SV_E1T(D, T)                                                                                    \
+    case D:                                                                                             \
+        hipLaunchKernelGGL(k_enc1_tab<D>, dim3(grid), dim3(256), 0, st, tab, disp, img, scale0, c1,     \
+                           (const T *)wpk, n_pad, cin_pad, bias, (T *)out);                             \
+        break;
+        SV_E1T(SV_F32, float)
+        SV_E1T(SV_BF16, uint16_t)
+        SV_E1T(SV_F16, uint16_t)
+#undef SV_E1T
+    default: return SV_ERR_DTYPE;
+    }
+    SV_LAUNCH_CHECK("k_enc1_tab");
+    return SV_OK;
+}
+
+}  // namespace sv

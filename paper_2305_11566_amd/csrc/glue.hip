@@ -67,14 +67,17 @@ __device__ __forceinline__ void load8(const typename Elem<DT>::T *p, float (&v)[
 // more than the rounding of the product (checked exhaustively for that range).
 __device__ __forceinline__ int fin_div(int q, float inv) { return (int)(((float)q + 0.5f) * inv); }
 
-template <int DT>
+// PRE: the nine projections are read from Tpre (FP32 [9][plane] at the
+// image's pixel offset; G0, ib and wF unused) instead of computed here.
+template <int DT, bool PRE = false>
 __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int PWm,
                                            const typename Elem<DT>::T *__restrict__ G0, int c1,
                                            const uint8_t *__restrict__ db,
                                            const uint8_t *__restrict__ ib,
                                            const float *__restrict__ wF, int wf_pitch,
                                            float scale0, float bias, int h, int w, int H, int W,
-                                           int X0, int Y0, float *__restrict__ out)
+                                           int X0, int Y0, float *__restrict__ out,
+                                           const float *__restrict__ Tpre = nullptr, long long plane = 0)
 {
     const int tid = threadIdx.x;
     float *sT = dyn;                           // [9][PHm][PWm]
@@ -122,7 +125,21 @@ __device__ __forceinline__ void final_tile(float *dyn, FinTab &tb, int PHm, int 
     // weights are the same for every thread (scalar loads).
     const float inv_pw = 1.0f / (float)pw;
     const int npx = ph * pw;
-    for (int q = tid; q < npx; q += FIN_THREADS) {
+    if constexpr (PRE) {
+        // nine planes and the coarse disparity on the window, loads first
+        for (int q = tid; q < npx; q += FIN_THREADS) {
+            const int r = fin_div(q, inv_pw), c = q - r * pw;
+            const size_t gp = (size_t)(ya + r) * w + xa + c;
+            float a[9];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) a[t] = Tpre[t * plane + gp];
+            const float dv = (float)db[gp];
+#pragma unroll
+            for (int t = 0; t < 9; ++t) sT[(t * PHm + r) * PWm + c] = a[t];
+            sd[r * PWm + c] = dv;
+        }
+    }
+    for (int q = PRE ? npx : tid; q < npx; q += FIN_THREADS) {
         const int r = fin_div(q, inv_pw), c = q - r * pw;
         const size_t gp = (size_t)(ya + r) * w + xa + c;
         const float dv = (float)db[gp];
@@ -267,6 +284,44 @@ k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__res
     }
 }
 
+// The gather from precomputed projections (uniform batch and pair table).
+__global__ void __launch_bounds__(FIN_THREADS)
+k_final_gather(const float *__restrict__ T, long long plane, const uint8_t *__restrict__ disp, float scale0,
+               const float *__restrict__ biasF, int h, int w, int H, int W, int PHm, int PWm,
+               float *__restrict__ out)
+{
+    extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
+    __shared__ FinTab tb;
+    const int b = blockIdx.z;
+    const size_t o = (size_t)b * h * w;
+    final_tile<SV_F32, true>(fin_dyn, tb, PHm, PWm, nullptr, 0, disp + o, nullptr, nullptr, 0, scale0,
+                             biasF[0], h, w, H, W, blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H,
+                             out + (size_t)b * H * W, T + o, plane);
+}
+
+__global__ void __launch_bounds__(FIN_THREADS)
+k_final_gather_tab(const PairTable *__restrict__ tab, const float *__restrict__ T, long long plane,
+                   const uint8_t *__restrict__ disp, float scale0, const float *__restrict__ biasF, int PHm,
+                   int PWm)
+{
+    extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
+    __shared__ FinTab tb;
+    const int n = tab->n;
+    const int *cum = tab->cum[BS_FINAL];
+    const int total = cum[n];
+    const float bias = biasF[0];
+    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = table_find(cum, n, t);
+        const PairGeo &g = tab->pair[i];
+        const int local = t - cum[i];
+        const int tx = cdiv_d(g.W, FIN_TILE_W);
+        const size_t o = (size_t)g.off[0];
+        final_tile<SV_F32, true>(fin_dyn, tb, PHm, PWm, nullptr, 0, disp + o, nullptr, nullptr, 0, scale0,
+                                 bias, g.h[0], g.w[0], g.H, g.W, (local % tx) * FIN_TILE_W,
+                                 (local / tx) * FIN_TILE_H, g.out, T + o, plane);
+    }
+}
+
 // The dynamic LDS of the final layer stays under 80 KB (f = 1); the kernels
 // are allowed that much once, before their first launch.
 static sv_status fin_allow_lds() {
@@ -274,9 +329,10 @@ static sv_status fin_allow_lds() {
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
         const int bytes = 96 * 1024;
-        const void *fns[6] = {(const void *)k_final<SV_F32>,     (const void *)k_final<SV_BF16>,
+        const void *fns[8] = {(const void *)k_final<SV_F32>,     (const void *)k_final<SV_BF16>,
                               (const void *)k_final<SV_F16>,     (const void *)k_final_tab<SV_F32>,
-                              (const void *)k_final_tab<SV_BF16>, (const void *)k_final_tab<SV_F16>};
+                              (const void *)k_final_tab<SV_BF16>, (const void *)k_final_tab<SV_F16>,
+                              (const void *)k_final_gather,      (const void *)k_final_gather_tab};
         for (const void *fn : fns) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
             if (e != hipSuccess && err == hipSuccess) err = e;
@@ -336,6 +392,32 @@ sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, c
     default: return SV_ERR_DTYPE;
     }
     SV_LAUNCH_CHECK("k_final");
+    return SV_OK;
+}
+
+sv_status launch_final_gather(const float *T, long long plane, const uint8_t *disp, int f,
+                              const float *biasF, int B, int h, int w, int H, int W, float *out,
+                              hipStream_t s)
+{
+    if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    int PHm, PWm;
+    fin_window(f, PHm, PWm);
+    dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
+    hipLaunchKernelGGL(k_final_gather, grid, dim3(FIN_THREADS), fin_lds_bytes(f), s, T, plane, disp,
+                       (float)f / 256.0f, biasF, h, w, H, W, PHm, PWm, out);
+    SV_LAUNCH_CHECK("k_final_gather");
+    return SV_OK;
+}
+
+sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T, long long plane,
+                                  const uint8_t *disp, int f, const float *biasF, hipStream_t s)
+{
+    if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    int PHm, PWm;
+    fin_window(f, PHm, PWm);
+    hipLaunchKernelGGL(k_final_gather_tab, dim3(grid), dim3(FIN_THREADS), fin_lds_bytes(f), s, tab, T, plane,
+                       disp, (float)f / 256.0f, biasF, PHm, PWm);
+    SV_LAUNCH_CHECK("k_final_gather_tab");
     return SV_OK;
 }
 

@@ -129,6 +129,20 @@ struct ConvParams {
     // 1: a split launch leaves its FP32 partials in part for the consumer to
     // add (the fused latent kernel), instead of launching the second pass
     int defer_sum;
+    // final-layer projection in the epilogue (G0 at inference; uniform or
+    // pair-table launches, never split, one channel tile per workgroup with
+    // all of it in each wave): instead of storing the output map y, write
+    //   proj_out[t * proj_plane + pix] = sum_c proj_w[t * proj_pitch + c] y_c
+    //       + proj_w[t * proj_pitch + Cout] * proj_scale0 * d
+    //       + proj_w[t * proj_pitch + Cout + 1] * img / 256
+    // for the nine taps t, y_c as it would have been stored (rounded to the
+    // storage dtype), d / img the coarse maps at the pixel.  NULL: store y.
+    const float *proj_w;
+    int proj_pitch;
+    float *proj_out;
+    long long proj_plane;
+    const uint8_t *proj_disp, *proj_img;
+    float proj_scale0;
 };
 constexpr int AMAX_SUB = 64;
 
@@ -182,6 +196,19 @@ sv_status launch_amax_prologue(uint32_t *amax, int nslots, int x0_slot, const ui
 // storage dtype code of a source (see ConvSrc::sdt)
 constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F16 = 1 + SV_F16;
 
+// The first encoder layer (3x3, stride 2, two input channels x0 = [scale0 * d,
+// img / 256], leaky ReLU) as a direct stencil, FP32 arithmetic, output NHWC
+// [B][h1][w1][c1] in the compute dtype (SV_F32, SV_BF16, SV_F16); weights
+// packed [9][n_pad][cin_pad] in that dtype, FP32 bias.  c1: multiple of 8, <= 256.
+sv_status launch_enc1(int dtype, const uint8_t *disp, const uint8_t *img, float scale0, int B, int h0, int w0,
+                      int h1, int w1, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
+                      void *out, hipStream_t st);
+// persistent variant over the pair table (stage BS_E1; level-0 inputs, level-1 output)
+sv_status launch_enc1_tab(int dtype, const PairTable *tab, int grid, const uint8_t *disp, const uint8_t *img,
+                          float scale0, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
+                          void *out, hipStream_t st);
+int enc1_tiles(int h1, int w1);
+
 // ---- network glue ---------------------------------------------------------------
 // The final layer from the coarse maps: with T[t] = W_F[t] . [G0, x0] (FP32
 // weights [9][wf_pitch], x0 = [f * d / 256, img / 256]),
@@ -198,6 +225,17 @@ bool latent_fusable(int dtype, int c3, int L);
 // stored); e3split <= 1 reads the stored E3.
 sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, int npix,
                         const float *e3part, int e3split, const float *e3bias, hipStream_t st);
+// The final layer from precomputed tap projections T (FP32 [9][plane], plane
+// = pixels of the coarse maps; written by G0's epilogue, ConvParams::proj_*):
+// the gather and the residual base of launch_final without the projection.
+sv_status launch_final_gather(const float *T, long long plane, const uint8_t *disp, int f,
+                              const float *biasF, int B, int h, int w, int H, int W, float *out,
+                              hipStream_t s);
+sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T, long long plane,
+                                  const uint8_t *disp, int f, const float *biasF, hipStream_t s);
+// whether a conv tile configuration can carry the projection epilogue for a
+// layer with cout output channels (one channel tile, all of it in each wave)
+bool conv_cfg_projects(int cfg, int cout);
 sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
                        const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
                        int w, int H, int W, float *out, hipStream_t s);

@@ -24,13 +24,53 @@ constexpr int CEN_THREADS = 256;
 template <int TH>
 using CenPatch = uint8_t[TH + 2 * CEN_MAXR][CEN_TW + 2 * CEN_MAXR];
 
+// The census word of the pixel at patch (py, px): bit k for the k-th window
+// neighbour (rows dy = -ry..ry outer, columns dx = -rx..rx inner, the centre
+// skipped) strictly darker than the centre.  RX, RY > 0: the window is a
+// compile-time constant and the loop is unrolled into byte reads at fixed LDS
+// offsets; RX = RY = 0: the window is read from rx, ry at run time.
+template <int TH, int RX, int RY>
+__device__ __forceinline__ uint64_t census_word(const CenPatch<TH> &patch, int py, int px, int rx, int ry) {
+    const uint32_t c = patch[py][px];
+    if constexpr (RX > 0) {
+        uint32_t lo = 0, hi = 0;
+        int k = 0;
+#pragma unroll
+        for (int dy = -RY; dy <= RY; ++dy)
+#pragma unroll
+            for (int dx = -RX; dx <= RX; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                // (v - c) wraps to a value with the top bit set exactly when v < c
+                const uint32_t bit = ((uint32_t)patch[py + dy][px + dx] - c) >> 31;
+                if (k < 32) lo |= bit << k;
+                else hi |= bit << (k - 32);
+                ++k;
+            }
+        return ((uint64_t)hi << 32) | lo;
+    } else {
+        uint64_t code = 0;
+        int k = 0;
+        for (int dy = -ry; dy <= ry; ++dy)
+            for (int dx = -rx; dx <= rx; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                code |= (uint64_t)(patch[py + dy][px + dx] < c) << k;
+                ++k;
+            }
+        return code;
+    }
+}
+
 // One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
-template <int F, int TH>
+template <int F, int TH, int RX = 0, int RY = 0>
 __device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *__restrict__ img,
                                             int H, int W, int pitch, int rx, int ry, int h, int w,
                                             int i0, int j0, uint8_t *__restrict__ low,
                                             uint64_t *__restrict__ cen)
 {
+    if constexpr (RX > 0) {
+        rx = RX;
+        ry = RY;
+    }
     // patch pixels per thread whose loads are issued before any is summed
     constexpr int R = F * F >= 48 ? 1 : (48 / (F * F) > 4 ? 4 : 48 / (F * F));
     const int PH = TH + 2 * ry, PW = CEN_TW + 2 * rx;
@@ -76,24 +116,16 @@ __device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *
     for (int ty = tid / CEN_TW; ty < TH; ty += CEN_THREADS / CEN_TW) {
         const int i = i0 + ty, j = j0 + tx;
         if (i < h && j < w) {
-            const uint8_t c = patch[ty + ry][tx + rx];
-            uint64_t code = 0;
-            int k = 0;
-            for (int dy = -ry; dy <= ry; ++dy)
-                for (int dx = -rx; dx <= rx; ++dx) {
-                    if (dy == 0 && dx == 0) continue;
-                    code |= (uint64_t)(patch[ty + ry + dy][tx + rx + dx] < c) << k;
-                    ++k;
-                }
+            const uint64_t code = census_word<TH, RX, RY>(patch, ty + ry, tx + rx, rx, ry);
             const size_t o = (size_t)i * w + j;
             cen[o] = code;
-            if (low) low[o] = c;
+            if (low) low[o] = patch[ty + ry][tx + rx];
         }
     }
     __syncthreads();  // the patch is reused by the next tile of a persistent loop
 }
 
-template <int F, int TH>
+template <int F, int TH, int RX = 0, int RY = 0>
 __global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ img1, int B, int H,
                 int W, int pitch, int rx, int ry, int h, int w, uint8_t *__restrict__ low0,
@@ -107,8 +139,8 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
     const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
     uint8_t *low = view ? low1 : low0;
     uint64_t *cen = (view ? cen1 : cen0) + (size_t)b * h * w;
-    census_tile<F, TH>(patch, img, H, W, pitch, rx, ry, h, w, blockIdx.y * TH, blockIdx.x * CEN_TW,
-                       low ? low + (size_t)b * h * w : nullptr, cen);
+    census_tile<F, TH, RX, RY>(patch, img, H, W, pitch, rx, ry, h, w, blockIdx.y * TH, blockIdx.x * CEN_TW,
+                               low ? low + (size_t)b * h * w : nullptr, cen);
 }
 
 #define SV_FACTOR_SWITCH(f, CALL) \
@@ -137,24 +169,33 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
     const int h = cdiv(H, f), w = cdiv(W, f);
     const int th = census_tile_height(B, h, w);
     dim3 grid(cdiv(w, CEN_TW), cdiv(h, th), 2 * B);
-#define SV_CEN_LAUNCH(F)                                                                          \
-    if (th == 16)                                                                                 \
-        hipLaunchKernelGGL((k_reduce_census<F, 16>), grid, dim3(CEN_THREADS), 0, s, img0, img1, B, \
-                           H, W, pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0,  \
-                           cen1);                                                                 \
-    else                                                                                          \
-        hipLaunchKernelGGL((k_reduce_census<F, 4>), grid, dim3(CEN_THREADS), 0, s, img0, img1, B,  \
-                           H, W, pitch, (win_w - 1) / 2, (win_h - 1) / 2, h, w, low0, low1, cen0,  \
-                           cen1)
+    const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+#define SV_CEN_L(F, TH, RX, RY)                                                                    \
+    hipLaunchKernelGGL((k_reduce_census<F, TH, RX, RY>), grid, dim3(CEN_THREADS), 0, s, img0, img1, \
+                       B, H, W, pitch, rx, ry, h, w, low0, low1, cen0, cen1)
+#define SV_CEN_W(F, TH)                                                                            \
+    if (rx == 4 && ry == 3) SV_CEN_L(F, TH, 4, 3);                                                 \
+    else if (rx == 2 && ry == 2) SV_CEN_L(F, TH, 2, 2);                                            \
+    else SV_CEN_L(F, TH, 0, 0)
+#define SV_CEN_LAUNCH(F)                                                                           \
+    if (F != 2 && F != 4) {                                                                        \
+        if (th == 16) SV_CEN_L(F, 16, 0, 0); else SV_CEN_L(F, 4, 0, 0);                            \
+    } else if (th == 16) {                                                                         \
+        SV_CEN_W(F, 16);                                                                           \
+    } else {                                                                                       \
+        SV_CEN_W(F, 4);                                                                            \
+    }
     SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
 #undef SV_CEN_LAUNCH
+#undef SV_CEN_W
+#undef SV_CEN_L
     SV_LAUNCH_CHECK("k_reduce_census");
     return SV_OK;
 }
 
 // Persistent variant: tiles of both views of every pair of the table; the
 // per-pair maps live in flattened buffers at the pair's level-0 offset.
-template <int F, int TH>
+template <int F, int TH, int RX = 0, int RY = 0>
 __global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *__restrict__ low0,
                     uint64_t *__restrict__ cen0, uint64_t *__restrict__ cen1)
@@ -170,7 +211,7 @@ k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *
         const int tw = cdiv_d(g.w[0], CEN_TW), th = cdiv_d(g.h[0], TH);
         const int view = local / (tw * th), r = local - view * tw * th;
         const long long o = g.off[0];
-        census_tile<F, TH>(patch, view ? g.right : g.left, g.H, g.W, g.W, rx, ry, g.h[0], g.w[0],
+        census_tile<F, TH, RX, RY>(patch, view ? g.right : g.left, g.H, g.W, g.W, rx, ry, g.h[0], g.w[0],
                            (r / tw) * TH, (r % tw) * CEN_TW, view ? nullptr : low0 + o,
                            (view ? cen1 : cen0) + o);
     }
@@ -181,15 +222,26 @@ sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int th
                                    hipStream_t s)
 {
     if (th != 4 && th != 16) return SV_ERR_RANGE;
-#define SV_CEN_LAUNCH(F)                                                                          \
-    if (th == 16)                                                                                 \
-        hipLaunchKernelGGL((k_reduce_census_tab<F, 16>), dim3(grid), dim3(CEN_THREADS), 0, s, tab, \
-                           (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1);                   \
-    else                                                                                          \
-        hipLaunchKernelGGL((k_reduce_census_tab<F, 4>), dim3(grid), dim3(CEN_THREADS), 0, s, tab,  \
-                           (win_w - 1) / 2, (win_h - 1) / 2, low0, cen0, cen1)
+    const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+#define SV_CEN_L(F, TH, RX, RY)                                                                    \
+    hipLaunchKernelGGL((k_reduce_census_tab<F, TH, RX, RY>), dim3(grid), dim3(CEN_THREADS), 0, s,   \
+                       tab, rx, ry, low0, cen0, cen1)
+#define SV_CEN_W(F, TH)                                                                            \
+    if (rx == 4 && ry == 3) SV_CEN_L(F, TH, 4, 3);                                                 \
+    else if (rx == 2 && ry == 2) SV_CEN_L(F, TH, 2, 2);                                            \
+    else SV_CEN_L(F, TH, 0, 0)
+#define SV_CEN_LAUNCH(F)                                                                           \
+    if (F != 2 && F != 4) {                                                                        \
+        if (th == 16) SV_CEN_L(F, 16, 0, 0); else SV_CEN_L(F, 4, 0, 0);                            \
+    } else if (th == 16) {                                                                         \
+        SV_CEN_W(F, 16);                                                                           \
+    } else {                                                                                       \
+        SV_CEN_W(F, 4);                                                                            \
+    }
     SV_FACTOR_SWITCH(f, SV_CEN_LAUNCH)
 #undef SV_CEN_LAUNCH
+#undef SV_CEN_W
+#undef SV_CEN_L
     SV_LAUNCH_CHECK("k_reduce_census_tab");
     return SV_OK;
 }

@@ -58,6 +58,12 @@ enum AmaxSlot { AM_E1 = 0, AM_E2, AM_E3, AM_ML, AM_G3, AM_G2, AM_G1, AM_G0, AM_X
 // Tile configuration per layer (index into the conv kernel's table); the
 // defaults may be replaced by the autotuner.
 int net_default_cfg(const NetShape &ns, int layer, int M);
+// Whether G0 carries the final layer's projection in its epilogue (inference
+// in FP32 / BF16 / FP16, c1 <= 64), and the tile configuration it then runs:
+// cfg's tile if it can hold every channel of G0 in each wave, else th4_tn32 /
+// th4_tn64; never split.
+bool net_projects(const NetShape &ns, bool train);
+int net_g0_proj_cfg(const NetShape &ns, int cfg);
 // The built-in choice for a layer, ignoring overrides and the autotune cache.
 int net_heuristic_cfg(const NetShape &ns, int layer);
 // Per-layer tile configuration of a forward pass of batch B at H x W: an

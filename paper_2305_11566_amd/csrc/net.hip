@@ -99,7 +99,9 @@ ActLayout net_act_layout(const NetShape &ns, const Levels &lv, int B) {
     a.G3 = o;   o = align256(o + px(3) * ns.c3 * ns.es);
     a.G2 = o;   o = align256(o + px(2) * ns.c2 * ns.es);
     a.G1 = o;   o = align256(o + px(1) * ns.c1 * ns.es);
-    a.G0 = o;   o = align256(o + px(0) * ns.c1 * ns.es);
+    // G0's slot: the map itself (training), or at inference the nine FP32
+    // tap projections of the final layer that G0's epilogue writes instead
+    a.G0 = o;   o = align256(o + px(0) * std::max<size_t>((size_t)ns.c1 * ns.es, 9 * sizeof(float)));
     a.saved = o;
     return a;
 }
@@ -132,6 +134,16 @@ int net_heuristic_cfg(const NetShape &ns, int layer) {
     if (cout <= 16) return 5;   // th4_tn16
     if (cout <= 32) return 2;   // th4_tn32
     return 0;                   // th4_tn64
+}
+
+bool net_projects(const NetShape &ns, bool train) {
+    return !train && ns.dtype != SV_I8 && ns.c1 <= 64;
+}
+
+int net_g0_proj_cfg(const NetShape &ns, int cfg) {
+    int c = conv_resolve_cfg(ns.dtype, 3, 1, cfg % conv_num_tiles());  // no split
+    if (!conv_cfg_projects(c, ns.c1)) c = ns.c1 <= 32 ? 2 /* th4_tn32 */ : 0 /* th4_tn64 */;
+    return c;
 }
 
 int net_default_cfg(const NetShape &ns, int layer, int M) {
@@ -285,9 +297,15 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     if (q8)
         SV_TRY(launch_amax_prologue(AM, AM_NSLOTS, AM_X0, disp, img, (long long)B * lv.h[0] * lv.w[0],
                                     (float)ns.f / 256.0f, st));
-    // encoder
+    // encoder; E1 reads the two x0 channels only: a direct stencil (INT8 keeps
+    // the quantised convolution its codes are defined on)
     ev_rec(0, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
+    if (q8)
+        SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
+    else if (only < 0 || only == L_E1)
+        SV_TRY(launch_enc1(ns.dtype, disp, img, (float)ns.f / 256.0f, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], c1,
+                           (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
+                           (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
     SV_TRY(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
@@ -352,16 +370,44 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
                      lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, am(AM_G2, AM_E1, AM_G1), st));
     ev_rec(7, 1, st);
+    // G0; at inference its epilogue writes the final layer's nine per-tap
+    // projections of [G0, x0] (FP32) in place of the map, and the final layer
+    // is the gather alone
+    const bool proj = net_projects(ns, train);
+    const float *wF = (const float *)((const char *)packed + ns.w_off[L_F]);
+    const long long plane0 = (long long)B * lv.h[0] * lv.w[0];
     ev_rec(8, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                     lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes, am(AM_G1, AM_X0, -1), st));
+    if (proj) {
+        if (only < 0 || only == L_G0) {
+            ConvParams p = layer_params(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
+                                        lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, part, a.part_bytes, LayerAmax{});
+            p.proj_w = wF;
+            p.proj_pitch = ns.cin_pad[L_F];
+            p.proj_out = (float *)G0;
+            p.proj_plane = plane0;
+            p.proj_disp = disp;
+            p.proj_img = img;
+            p.proj_scale0 = (float)ns.f / 256.0f;
+            SV_TRY(launch_conv(ns.dtype, 3, 1, net_g0_proj_cfg(ns, cfg[L_G0]), p, st));
+        }
+    } else {
+        SV_TRY(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
+                            lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes,
+                            am(AM_G1, AM_X0, -1), st));
+    }
     ev_rec(8, 1, st);
-    // final layer: per-tap projections of [G0, x0] and the gather, one kernel
+    // final layer: the gather of the projections (inference), or projections
+    // of the stored [G0, x0] and the gather in one kernel
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);
     ev_rec(10, 0, st);
-    if (only < 0)
-        SV_TRY(launch_final(q8 ? SV_BF16 : ns.dtype, G0, c1, disp, img, (const float *)((const char *)packed + ns.w_off[L_F]),
-                        ns.cin_pad[L_F], ns.f, biasF, B, lv.h[0], lv.w[0], H, W, out, st));
+    if (only < 0) {
+        if (proj)
+            SV_TRY(launch_final_gather((const float *)G0, plane0, disp, ns.f, biasF, B, lv.h[0], lv.w[0], H, W,
+                                       out, st));
+        else
+            SV_TRY(launch_final(q8 ? SV_BF16 : ns.dtype, G0, c1, disp, img, wF, ns.cin_pad[L_F], ns.f, biasF, B,
+                                lv.h[0], lv.w[0], H, W, out, st));
+    }
     ev_rec(10, 1, st);
     if (train && ml_user)
         SV_HIP(hipMemcpyAsync(ml_user, ML, (size_t)B * lv.h[3] * lv.w[3] * 2 * L * sizeof(float),
