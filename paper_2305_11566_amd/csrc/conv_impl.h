@@ -418,6 +418,89 @@ struct ConvTile {
         }
     }
 
+    // The x0 chunk: 2 channels x TAPS taps = 2 TAPS values per output pixel,
+    // packed into K as k = 2 tap + channel (zeros past 2 TAPS), so the chunk
+    // costs ceil(2 TAPS / (4 GS)) MFMA steps instead of TAPS.  The x0 values
+    // of the patch are staged as pairs xp[pix][2] (a zero pair after the last
+    // pixel serves taps past TAPS), the weights as wx[row][k]; lane group g
+    // supplies k = (4 s + g) GS .. + GS - 1 of step s to both operands.
+    static constexpr int NKX = 2 * TAPS;
+    static constexpr int NSX = (NKX + 4 * GS - 1) / (4 * GS);
+    static constexpr int KXP = NSX * 4 * GS + GS;
+    static_assert(2 * (NPIX + 1) <= NPIX * KCP && TN * KXP <= TAPS * TN * KCP, "x0 staging fits");
+
+    static __device__ __forceinline__ void x0_packed(const ConvParams &p, Smem &sm,
+                                                     typename M::acc (&acc)[MBW][NBW], float qinv,
+                                                     int n0, int wm, int wn, int g, int r16) {
+        const int tid = threadIdx.x;
+        const bool first = p.src[0].kind == SRC_X0;
+        const ConvSrc &sx = first ? p.src[0] : p.src[1];
+        const PixSrc *tx = sm.ps[first ? 0 : 1];
+        const int cx = first ? 0 : p.src[0].C;   // column of x0's first channel in the packed weights
+        T *xp = sm.patch, *wx = sm.wl;
+        __syncthreads();  // the last chunk's MFMA steps are done with the patch and weights
+        for (int pix = tid; pix <= NPIX; pix += 256) {
+            const int pi = pix < NPIX ? tx[pix].p[0] : -1;
+            float v0 = 0.f, v1 = 0.f;
+            if (pi >= 0) {
+                v0 = sx.scale0 * (float)((const uint8_t *)sx.ptr)[pi];
+                v1 = (float)sx.img[pi] * (1.0f / 256.0f);
+            }
+            if constexpr (DT == SV_I8) {
+                xp[2 * pix] = quant_i8(v0, qinv);
+                xp[2 * pix + 1] = quant_i8(v1, qinv);
+            } else {
+                xp[2 * pix] = Elem<DT>::make(v0);
+                xp[2 * pix + 1] = Elem<DT>::make(v1);
+            }
+        }
+        const T *wpk = (const T *)p.wpk;
+        for (int e = tid; e < TN * KXP; e += 256) {
+            const int n = e / KXP, k = e - n * KXP;
+            const int ng = n0 + n;
+            T w = (T)0;
+            if (k < NKX && ng < p.n_pad) w = wpk[((size_t)(k >> 1) * p.n_pad + ng) * p.cin_pad + cx + (k & 1)];
+            wx[e] = w;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < NSX; ++st) {
+            vec af[NBW], bf[MBW];
+#pragma unroll
+            for (int nb = 0; nb < NBW; ++nb)
+                af[nb] = *(const vec *)&wx[((wn * NBW + nb) * 16 + r16) * KXP + (st * 4 + g) * GS];
+#pragma unroll
+            for (int mb = 0; mb < MBW; ++mb) {
+                const int ty = wm * MBW + mb;
+                const int base = (ty * S) * PW + r16 * S;
+#pragma unroll
+                for (int m = 0; m < GS / 2; ++m) {
+                    const int tap = (st * 4 + g) * (GS / 2) + m;
+                    const int u = tap / KS, v = tap - (tap / KS) * KS;
+                    const int q = tap < TAPS ? base + u * PW + v : NPIX;
+                    // the pair (both channels of one tap) in one LDS read
+                    if constexpr (sizeof(T) == 4) {
+                        const float2 w2 = *(const float2 *)&xp[2 * q];
+                        bf[mb][2 * m] = w2.x;
+                        bf[mb][2 * m + 1] = w2.y;
+                    } else if constexpr (sizeof(T) == 2) {
+                        const uint32_t w2 = *(const uint32_t *)&xp[2 * q];
+                        bf[mb][2 * m] = (T)(w2 & 0xffffu);
+                        bf[mb][2 * m + 1] = (T)(w2 >> 16);
+                    } else {
+                        const uint16_t w2 = *(const uint16_t *)&xp[2 * q];
+                        bf[mb][2 * m] = (T)(int8_t)(w2 & 0xffu);
+                        bf[mb][2 * m + 1] = (T)(int8_t)(w2 >> 8);
+                    }
+                }
+            }
+#pragma unroll
+            for (int mb = 0; mb < MBW; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NBW; ++nb) acc[mb][nb] = M::run(af[nb], bf[mb], acc[mb][nb]);
+        }
+    }
+
     static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm,
                                                int kz) {
         T *patch = sm.patch, *wl = sm.wl;
@@ -459,9 +542,16 @@ struct ConvTile {
         int c_begin = 0, c_end = p.Cin;
         if (p.ksplit > 1) split_range(p.Cin, KCB, p.ksplit, kz, c_begin, c_end);
         static_assert(KCGB == 4, "a base chunk is four channel groups, one per lane group");
-        for (int c0 = c_begin; c0 < c_end; c0 += KC) {
+        // The network input x0 (two channels) in a base chunk of its own -- the
+        // whole input, or the second source starting on a chunk boundary -- is
+        // reduced after the other chunks with its taps packed into K (below);
+        // the chunk loop runs up to it.
+        int c_x0 = c_end;
+        if (p.src[0].kind == SRC_X0 && p.src[1].kind == SRC_NONE) c_x0 = c_begin == 0 ? 0 : c_end;
+        else if (p.src[1].kind == SRC_X0 && C0 % KCB == 0 && c_begin <= C0 && C0 < c_end) c_x0 = C0;
+        for (int c0 = c_begin; c0 < c_x0; c0 += KC) {
             // base chunks of this round that hold input channels
-            const int nsub = min(KCM, (c_end - c0 + KCB - 1) / KCB);
+            const int nsub = min(KCM, (c_x0 - c0 + KCB - 1) / KCB);
             __syncthreads();
             // ---- staging: the input patch (at the precomputed source pixels) and
             // the chunk of weights.  e = pix * KCG + cg and 256 is a multiple of
@@ -731,6 +821,8 @@ struct ConvTile {
                 }
             }
         }
+
+        if (c_x0 < c_end) x0_packed(p, sm, acc, qinv, n0, wm, wn, g, r16);
 
         // ---- epilogue -------------------------------------------------------
         if constexpr (DT != SV_I8 && WN == 1) {

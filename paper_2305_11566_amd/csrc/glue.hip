@@ -44,8 +44,9 @@ static inline size_t fin_lds_bytes(int f) {
 }
 
 struct FinTab {
-    int cx0[FIN_CX], cx1[FIN_CX], cy0[FIN_CY], cy1[FIN_CY];  // -1: outside the image
+    int cx0[FIN_CX], cx1[FIN_CX], cy0[FIN_CY], cy1[FIN_CY];  // -1: outside the image (final_tile)
     float clx[FIN_CX], cly[FIN_CY];
+    float cwx[FIN_CX], cwy[FIN_CY];  // gather_tile: weight of the lower corner, 0 outside the image
 };
 
 // Loads 8 consecutive stored channels as FP32.
@@ -284,6 +285,138 @@ k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__res
     }
 }
 
+// The gather from precomputed projections T (FP32 [9][plane]).  A thread
+// owns one output column X of the tile and keeps, in registers, the column
+// indices and weights of X - 1, X, X + 1 (zero outside the image: the 3 x 3
+// convolution's padding of the resized map).  Horizontal pass, per coarse row
+// i of the window and row tap u:
+//   H_u(i, X) = sum_v [(1 - lx_v) T_uv(i, x0_v) + lx_v T_uv(i, x1_v)],
+// and the base's H_d(i, X) from the coarse disparity at column X; vertical
+// pass, per output pixel:
+//   R(Y, X) = sum_u [(1 - ly_u) H_u(y0_u, X) + ly_u H_u(y1_u, X)],
+//   out = 256 (bias + R + f d(Y, X) / 256).
+// Dynamic LDS (floats): T[9][PHm][PWm], d[PHm][PWm], H[4][PHm][FIN_TILE_W].
+static inline size_t gather_lds_bytes(int f) {
+    int ph, pw;
+    fin_window(f, ph, pw);
+    return sizeof(float) * ((size_t)10 * ph * pw + (size_t)4 * ph * FIN_TILE_W);
+}
+
+__device__ __forceinline__ void gather_tile(float *dyn, FinTab &tb, int PHm, int PWm,
+                                            const float *__restrict__ Tp, long long plane,
+                                            const uint8_t *__restrict__ db, float scale0, float bias,
+                                            int h, int w, int H, int W, int X0, int Y0,
+                                            float *__restrict__ out)
+{
+    const int tid = threadIdx.x;
+    float *sT = dyn;                        // [9][PHm][PWm]
+    float *sd = sT + 9 * PHm * PWm;         // [PHm][PWm]
+    float *sH = sd + PHm * PWm;             // [4][PHm][FIN_TILE_W]
+    int xa, ya, xb, yb, i1;
+    float lam;
+    bilin(max(X0 - 1, 0), w, W, xa, i1, lam);
+    bilin(max(Y0 - 1, 0), h, H, ya, i1, lam);
+    bilin(min(X0 + FIN_TILE_W, W - 1), w, W, i1, xb, lam);
+    bilin(min(Y0 + FIN_TILE_H, H - 1), h, H, i1, yb, lam);
+    const int pw = xb - xa + 1, ph = yb - ya + 1;
+    if (ph > PHm || pw > PWm) return;  // excluded by the window bound
+    if (tid < FIN_CX) {
+        const int X = X0 - 1 + tid;
+        int x0 = 0, x1 = 0;
+        float lx = 0.f, wx = 0.f;  // wx: weight of the lower corner, 0 outside the image
+        if (X >= 0 && X < W) {
+            bilin(X, w, W, x0, x1, lx);
+            x0 -= xa;
+            x1 -= xa;
+            wx = 1.f - lx;
+        }
+        tb.cx0[tid] = x0;
+        tb.cx1[tid] = x1;
+        tb.clx[tid] = lx;
+        tb.cwx[tid] = wx;
+    } else if (tid >= 128 && tid < 128 + FIN_CY) {
+        const int r = tid - 128, Y = Y0 - 1 + r;
+        int y0 = 0, y1 = 0;
+        float ly = 0.f, wy = 0.f;
+        if (Y >= 0 && Y < H) {
+            bilin(Y, h, H, y0, y1, ly);
+            y0 -= ya;
+            y1 -= ya;
+            wy = 1.f - ly;
+        }
+        tb.cy0[r] = y0;
+        tb.cy1[r] = y1;
+        tb.cly[r] = ly;
+        tb.cwy[r] = wy;
+    }
+    // the nine projections and the coarse disparity on the window, loads first
+    const float inv_pw = 1.0f / (float)pw;
+    const int npx = ph * pw;
+    for (int q = tid; q < npx; q += FIN_THREADS) {
+        const int r = fin_div(q, inv_pw), c = q - r * pw;
+        const size_t gp = (size_t)(ya + r) * w + xa + c;
+        float a[9];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) a[t] = Tp[t * plane + gp];
+        const float dv = (float)db[gp];
+#pragma unroll
+        for (int t = 0; t < 9; ++t) sT[(t * PHm + r) * PWm + c] = a[t];
+        sd[r * PWm + c] = dv;
+    }
+    __syncthreads();
+    const int tx = tid & (FIN_TILE_W - 1), rg = tid / FIN_TILE_W;
+    constexpr int NRG = FIN_THREADS / FIN_TILE_W;
+    // this column's taps: X - 1, X, X + 1 are table entries tx, tx + 1, tx + 2
+    int hx0[3], hx1[3];
+    float hl[3], hw[3];
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+        hx0[v] = tb.cx0[tx + v];
+        hx1[v] = tb.cx1[tx + v];
+        hl[v] = tb.clx[tx + v];
+        hw[v] = tb.cwx[tx + v];
+    }
+    for (int i = rg; i < ph; i += NRG) {
+        float hu[3];
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            float acc = 0.f;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const float *row = sT + ((u * 3 + v) * PHm + i) * PWm;
+                acc = fmaf(hw[v], row[hx0[v]], acc);
+                acc = fmaf(hl[v], row[hx1[v]], acc);
+            }
+            hu[u] = acc;
+        }
+        const float *drow = sd + i * PWm;
+        const float hd = fmaf(hl[1], drow[hx1[1]], hw[1] * drow[hx0[1]]);
+#pragma unroll
+        for (int u = 0; u < 3; ++u) sH[(u * PHm + i) * FIN_TILE_W + tx] = hu[u];
+        sH[(3 * PHm + i) * FIN_TILE_W + tx] = hd;
+    }
+    __syncthreads();
+    const int X = X0 + tx;
+    for (int ty = rg; ty < FIN_TILE_H; ty += NRG) {
+        const int Y = Y0 + ty;
+        if (X < W && Y < H) {
+            float acc = bias;
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int e = ty + u;  // table entry of row Y + u - 1
+                const float *hp = sH + u * PHm * FIN_TILE_W + tx;
+                acc = fmaf(tb.cwy[e], hp[tb.cy0[e] * FIN_TILE_W], acc);
+                acc = fmaf(tb.cly[e], hp[tb.cy1[e] * FIN_TILE_W], acc);
+            }
+            const float *dp = sH + 3 * PHm * FIN_TILE_W + tx;
+            const int e = ty + 1;
+            const float base = fmaf(tb.cly[e], dp[tb.cy1[e] * FIN_TILE_W], tb.cwy[e] * dp[tb.cy0[e] * FIN_TILE_W]);
+            out[(size_t)Y * W + X] = 256.0f * fmaf(scale0, base, acc);
+        }
+    }
+    __syncthreads();  // the LDS is reused by the next tile of a persistent loop
+}
+
 // The gather from precomputed projections (uniform batch and pair table).
 __global__ void __launch_bounds__(FIN_THREADS)
 k_final_gather(const float *__restrict__ T, long long plane, const uint8_t *__restrict__ disp, float scale0,
@@ -294,9 +427,8 @@ k_final_gather(const float *__restrict__ T, long long plane, const uint8_t *__re
     __shared__ FinTab tb;
     const int b = blockIdx.z;
     const size_t o = (size_t)b * h * w;
-    final_tile<SV_F32, true>(fin_dyn, tb, PHm, PWm, nullptr, 0, disp + o, nullptr, nullptr, 0, scale0,
-                             biasF[0], h, w, H, W, blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H,
-                             out + (size_t)b * H * W, T + o, plane);
+    gather_tile(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, biasF[0], h, w, H, W,
+                blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H, out + (size_t)b * H * W);
 }
 
 __global__ void __launch_bounds__(FIN_THREADS)
@@ -316,9 +448,8 @@ k_final_gather_tab(const PairTable *__restrict__ tab, const float *__restrict__ 
         const int local = t - cum[i];
         const int tx = cdiv_d(g.W, FIN_TILE_W);
         const size_t o = (size_t)g.off[0];
-        final_tile<SV_F32, true>(fin_dyn, tb, PHm, PWm, nullptr, 0, disp + o, nullptr, nullptr, 0, scale0,
-                                 bias, g.h[0], g.w[0], g.H, g.W, (local % tx) * FIN_TILE_W,
-                                 (local / tx) * FIN_TILE_H, g.out, T + o, plane);
+        gather_tile(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, bias, g.h[0], g.w[0], g.H, g.W,
+                    (local % tx) * FIN_TILE_W, (local / tx) * FIN_TILE_H, g.out);
     }
 }
 
@@ -403,7 +534,7 @@ sv_status launch_final_gather(const float *T, long long plane, const uint8_t *di
     int PHm, PWm;
     fin_window(f, PHm, PWm);
     dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
-    hipLaunchKernelGGL(k_final_gather, grid, dim3(FIN_THREADS), fin_lds_bytes(f), s, T, plane, disp,
+    hipLaunchKernelGGL(k_final_gather, grid, dim3(FIN_THREADS), gather_lds_bytes(f), s, T, plane, disp,
                        (float)f / 256.0f, biasF, h, w, H, W, PHm, PWm, out);
     SV_LAUNCH_CHECK("k_final_gather");
     return SV_OK;
@@ -415,7 +546,7 @@ sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T
     if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
     int PHm, PWm;
     fin_window(f, PHm, PWm);
-    hipLaunchKernelGGL(k_final_gather_tab, dim3(grid), dim3(FIN_THREADS), fin_lds_bytes(f), s, tab, T, plane,
+    hipLaunchKernelGGL(k_final_gather_tab, dim3(grid), dim3(FIN_THREADS), gather_lds_bytes(f), s, tab, T, plane,
                        disp, (float)f / 256.0f, biasF, PHm, PWm);
     SV_LAUNCH_CHECK("k_final_gather_tab");
     return SV_OK;
