@@ -43,10 +43,12 @@ def _path(dtype, left, right, H, W):
     return step, bufs
 
 
-@pytest.mark.parametrize("e3cfg", [-1, 5 + 16])  # default; E3 split in two (its sum left to the fused kernel)
+@pytest.mark.parametrize("e3name", [None, "th4_tn16_s2"])  # default; E3 split in two (its sum left to the fused kernel)
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_graph_replays_equal_eager(dtype, e3cfg):
+def test_graph_replays_equal_eager(dtype, e3name):
     import paper_2305_11566_amd as sv
+    names = [sv.sv_conv_cfg_name(c) for c in range(sv.sv_num_layer_cfgs())]
+    e3cfg = -1 if e3name is None else names.index(e3name)
     p = gen_preset("pair1242x375")
     H, W = p.left.shape
     left, right = cuda(p.left[None]), cuda(p.right[None])

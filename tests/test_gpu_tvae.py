@@ -107,7 +107,7 @@ def test_tile_shapes_bitwise_identical(deconv_form):
     H, W, f, B = 45, 70, 4, 2
     d, im = _rand_inputs(B, H, W, f, 17)
     params = _params(3)
-    nt = 16
+    nt = sv.sv_num_layer_cfgs() // 4   # tile shapes; cfg = tile + nt * (split - 1)
 
     def run_all(cfg):
         for layer in range(sv.sv_tvae_num_layers()):

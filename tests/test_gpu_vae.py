@@ -182,7 +182,7 @@ def test_tile_configs_bitwise_identical(dtype):
     assert sorted(per_split) == [1, 2, 3, 4]
 
 
-@pytest.mark.parametrize("e3cfg", [-1, 5 + 16, 5 + 48])  # E3 default, split in 2, split in 4 (capped)
+@pytest.mark.parametrize("e3name", [None, "th4_tn16_s2", "th4_tn16_s4"])  # E3 default, split in 2, in 4 (capped)
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("C,L,f,H,W,B", [
     ((32, 64, 128), 128, 4, 375, 1242, 1),  # full size: 468 latent pixels, a tail of 4 past 16s
@@ -190,7 +190,7 @@ def test_tile_configs_bitwise_identical(dtype):
     ((32, 64, 96), 32, 2, 50, 90, 3),       # 96 / 32 channels, 7x12 latent grids
     ((16, 24, 48), 16, 2, 30, 40, 1),       # FP32 fused; L = 16 is not a whole 16-bit chunk: two launches
 ])
-def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B, e3cfg):
+def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B, e3name):
     """Inference runs the head and G3 as one kernel: same bits as the two
     layers launched one by one, unsplit (their configurations pinned to an
     unsplit tile shape).  When E3 runs split, the fused kernel also adds E3's
@@ -201,9 +201,12 @@ def test_fused_latent_bitwise_equals_two_launches(dtype, C, L, f, H, W, B, e3cfg
     disp = rng.integers(0, 40, (B, h, w)).astype(np.uint8)
     img = rng.integers(0, 256, (B, h, w)).astype(np.uint8)
     params = vae_params(C, L, 21)
+    names = [sv.sv_conv_cfg_name(c) for c in range(sv.sv_num_layer_cfgs())]
+    e3cfg = -1 if e3name is None else names.index(e3name)
+    th4_tn16 = names.index("th4_tn16")
     try:
         for layer in (3, 4):
-            sv.sv_set_layer_cfg(layer, 5)  # th4_tn16, no split
+            sv.sv_set_layer_cfg(layer, th4_tn16)  # no split
         sv.sv_set_layer_cfg(2, e3cfg)
         sv.sv_set_latent_fusion(True)
         a, ma = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
