@@ -36,6 +36,7 @@ H, W, F, WIN_W, WIN_H, D = 375, 1242, 4, 9, 7, 48
 C1, C2, C3, LAT = 32, 64, 128, 128
 NBITS = WIN_W * WIN_H - 1
 WEIGHT_SEED = 7002
+PROF_REPEAT = 10      # launches per event pair in the profiled pass at the headline batch
 
 PEAK = {  # MI355X published peaks
     "hbm_GBs": 8000.0,
@@ -181,10 +182,24 @@ def _oracle_frame(i):
     return time.perf_counter() - t0
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(budget_s=12.0, max_workers=16):
     """The oracle, as it stands, on whole frames of the workload: single thread
     until the budget is spent, then independent frames in parallel processes
-    (one thread each) on the host's cores."""
+    (one thread each), one per host thread this job may use (at most 16: the
+    host's share of a one-GPU job).  Also the oracle's FP64 outputs of the
+    256x128 precision workload, returned beside the record."""
     import concurrent.futures
     n, t0 = 0, time.perf_counter()
     while True:
@@ -194,7 +209,11 @@ def cpu_baseline(budget_s=12.0, max_workers=16):
         if el >= budget_s or n >= 8:
             break
     single = n / el
-    cores = max(1, min(os.cpu_count() or 1, max_workers))
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    cores = max(1, min(affinity, max_workers))
     frames = 2 * cores
     env_threads = os.environ.get("OMP_NUM_THREADS")
     os.environ["OMP_NUM_THREADS"] = "1"
@@ -212,10 +231,14 @@ def cpu_baseline(budget_s=12.0, max_workers=16):
             os.environ.pop("OMP_NUM_THREADS", None)
         else:
             os.environ["OMP_NUM_THREADS"] = env_threads
-    return {"value": frames / el_all, "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": (f"{frames} whole frames (1242x375, census+WTA+FP64 network) over {cores} processes "
-                       f"of one thread, {el_all:.1f} s; single thread: {n} frames in {el:.1f} s"),
-            "single_thread_value": single}
+    ref3, t3 = oracle_precision_reference()
+    rec = {"value": frames / el_all, "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": (f"{frames} whole frames (1242x375, census+WTA+FP64 network) over {cores} processes "
+                      f"of one thread, {el_all:.1f} s; single thread: {n} frames in {el:.1f} s"),
+           "single_thread_value": single, "host_cpu_count": os.cpu_count(), "host_threads_allowed": affinity,
+           "cpu_model": _cpu_model(),
+           "oracle_precision_reference_s": round(t3, 2)}
+    return rec, ref3
 
 
 TRAFFIC_JSON = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
@@ -461,8 +484,7 @@ def run_int8(sv, torch, dev, flat, K, Wm, tune=True):
 
 
 def run_extras(sv, torch, dev, flat, K, Wm):
-    """Uneven batch (64 pairs, one graph) vs the per-pair loop; BF16 / FP16 vs
-    FP32 end-point error with briefly trained weights; training steps/s."""
+    """Uneven batch (64 pairs, one graph) vs the per-pair loop."""
     from synth import gen_preset
     out = {}
     # -- 64 uneven pairs, BF16 network ---------------------------------------------------
@@ -508,15 +530,79 @@ def run_extras(sv, torch, dev, flat, K, Wm):
     plan.close()
     del plan, outs
 
-    # -- precision on briefly trained weights (256x128 shapes, batch 8) ---------------------
+    return out
+
+
+# ---- the 256x128 precision workload and the 512x256 training workload -------------------
+P_C, P_L, P_F, P_WIN, P_D = (16, 32, 64), 64, 2, (5, 5), 16
+PRECISION_SEED = 7003
+
+
+def precision_params():
+    """He-init weights of the 256x128 network (seed 7003) with the final
+    layer's weights and bias scaled by 0.01: a refinement term of a few px, as
+    trained weights give, where plain He-init's is of order 100 px."""
+    from synth import he_init_params
+    from paper_2305_11566_amd.train import layer_shapes
+    params = he_init_params(layer_shapes(*P_C, P_L), seed=PRECISION_SEED, bias_scale=0.1)
+    wF, bF = params[8]
+    params[8] = ((wF * np.float32(0.01)).astype(np.float32), (bF * np.float32(0.01)).astype(np.float32))
+    flat = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in params]).astype(np.float32)
+    return params, flat
+
+
+def precision_pairs():
+    from synth import gen_preset
+    return [gen_preset("batch8_256x128", i) for i in range(8)]   # seeds 3000-3007
+
+
+def oracle_precision_reference():
+    """The oracle's FP64 refined maps of the 8-pair 256x128 workload with the
+    precision weights (its own census + WTA feeding its own network): the
+    reference the GPU precisions are measured against."""
+    import oracle
+    from oracle import vae
+    params, _ = precision_params()
+    ps = precision_pairs()
+    t0 = time.perf_counter()
+    m = [oracle.match(p.left, p.right, P_F, P_WIN[0], P_WIN[1], P_D) for p in ps]
+    lo = np.concatenate([r[0] for r in m])
+    d = np.concatenate([r[3] for r in m])
+    outs = vae.forward(params, d, lo, P_F, 128, 256)["out"]
+    return outs, time.perf_counter() - t0
+
+
+def _epe(a, b):
+    e = (a.double() - b.double()).abs()
+    return {"mean_px": float(f"{float(e.mean()):.4g}"), "max_px": float(f"{float(e.max()):.4g}")}
+
+
+def run_config5(sv, torch, dev, steps=2000):
+    """Training on the GPU: 512x256 crops of 128 generated pairs (seeds
+    5000-5127), batch 16, BF16 compute with FP32 master weights and Adam,
+    smooth-L1 + 1e-3 KL; steps/s, then the end-point error on 16 disjoint
+    validation pairs (seeds 5500-5515) before and after training."""
     from paper_2305_11566_amd.train import Trainer, layer_shapes, make_pool, batch_indices
     from synth import he_init_params
-    c = (16, 32, 64)
-    p0 = he_init_params(layer_shapes(*c, 64), seed=7005)
+    p0 = he_init_params(layer_shapes(*P_C, P_L), seed=7005)
     f0 = np.concatenate([np.concatenate([w.ravel(), b.ravel()]) for w, b in p0])
-    tr = Trainer(f0, C=c, latent=64, dtype="bf16")
+    tr = Trainer(f0, C=P_C, latent=P_L, dtype="bf16")
     pl, pr, pg = make_pool(128, 256, 512, seed0=5000)
-    steps = 2000
+    vl, vr, vg = make_pool(16, 256, 512, seed0=5500)
+
+    def val(w):
+        disp, low = tr.coarse(vl, vr)
+        res = {}
+        for dt in ("f32", "bf16", "i8"):
+            r = sv.Refiner(*P_C, P_L, P_F, dt)
+            r.pack(w)
+            o, _ = r.forward(disp, low, 256, 512)
+            res[dt] = _epe(o, vg)
+        lin = torch.nn.functional.interpolate(disp[:, None].float() * P_F, size=(256, 512), mode="bilinear",
+                                              align_corners=False)[:, 0]
+        res["linear_upscaling"] = _epe(lin, vg)
+        return res
+    before = val(tr.w)
     for _ in range(5):
         idx = batch_indices(tr.step, 16, 128).to(dev)
         tr.train_step(pl[idx], pr[idx], pg[idx])
@@ -525,33 +611,86 @@ def run_extras(sv, torch, dev, flat, K, Wm):
     n0 = tr.step
     while tr.step < steps:
         idx = batch_indices(tr.step, 16, 128).to(dev)
-        tr.train_step(pl[idx], pr[idx], pg[idx])
+        loss = tr.train_step(pl[idx], pr[idx], pg[idx])
     torch.cuda.synchronize()
     sps = (tr.step - n0) / (time.perf_counter() - t0)
-    out["train_512x256_b16_bf16"] = {"steps_per_s": round(sps, 2), "steps": steps,
-                                     "ms_per_step": round(1e3 / sps, 4)}
-    w_trained = tr.w
-    vp = [gen_preset("batch8_256x128", i) for i in range(8)]
-    vl = torch.from_numpy(np.stack([p.left for p in vp])).to(dev)
-    vr = torch.from_numpy(np.stack([p.right for p in vp])).to(dev)
-    vg = torch.from_numpy(np.stack([p.gt for p in vp])).to(dev)
-    cl, cr, low = sv.sv_census_pair(vl, vr, 2, 5, 5)
-    disp = sv.sv_cost_wta(cl, cr, 16, 24)
-    res = {}
-    for dt in ("f32", "bf16", "f16"):
-        r = sv.Refiner(*c, 64, 2, dt)
-        r.pack(w_trained)
-        res[dt], _ = r.forward(disp, low, 128, 256)
-    lin = torch.nn.functional.interpolate(disp[:, None].float() * 2, size=(128, 256), mode="bilinear",
-                                          align_corners=False)[:, 0]
-    prec = {"weights": f"{steps} training steps (512x256, batch 16, BF16)", "shape": "8 x 256x128"}
-    for dt in ("bf16", "f16"):
-        d = (res[dt] - res["f32"]).abs()
-        prec[f"{dt}_vs_f32_mean_px"] = float(d.mean())
-        prec[f"{dt}_vs_f32_max_px"] = float(d.max())
-    prec["f32_vs_gt_mean_px"] = float((res["f32"] - vg).abs().mean())
-    prec["linear_vs_gt_mean_px"] = float((lin - vg).abs().mean())
-    out["precision_trained"] = prec
+    rec = {"steps_per_s": round(sps, 2), "ms_per_step": round(1e3 / sps, 4), "steps": steps,
+           "loss_last": [round(float(x), 5) for x in loss.cpu()],
+           "validation": {"pairs": "16 x 512x256, seeds 5500-5515 (training pool: seeds 5000-5127)",
+                          "vs_gt_before_training": before, "vs_gt_after_training": val(tr.w)}}
+    return rec, tr.w
+
+
+def run_config3(sv, torch, dev, K, Wm, trained_w, oracle_ref):
+    """The 8-pair 256x128 workload (seeds 3000-3007): census + WTA + the
+    (16, 32, 64), latent 64 network per compute dtype.  End-point error of
+    each dtype against FP32, against the FP64 oracle (precision weights; the
+    oracle runs in the CPU leg) and against ground truth, on the precision
+    weights and on the trained weights; frames/s per dtype, graph replayed."""
+    ps = precision_pairs()
+    B, H3, W3 = 8, 128, 256
+    left = torch.from_numpy(np.stack([p.left for p in ps])).to(dev)
+    right = torch.from_numpy(np.stack([p.right for p in ps])).to(dev)
+    gt = torch.from_numpy(np.stack([p.gt for p in ps])).to(dev)
+    nb = P_WIN[0] * P_WIN[1] - 1
+    cl, cr, low = sv.sv_census_pair(left, right, P_F, *P_WIN)
+    disp = sv.sv_cost_wta(cl, cr, P_D, nb)
+    _, pflat = precision_params()
+    dts = ("f32", "bf16", "f16", "i8")
+    out = {"shape": "8 x 256x128, f = 2, 5x5 census, D = 16, network (16, 32, 64), latent 64",
+           "reference": "oracle FP64 (its own census + WTA and network), computed in the CPU leg"}
+    for wname, w in (("precision_weights", torch.from_numpy(pflat).to(dev)), ("trained_weights", trained_w)):
+        if w is None:
+            continue
+        res = {}
+        for dt in dts:
+            r = sv.Refiner(*P_C, P_L, P_F, dt)
+            r.pack(w)
+            res[dt], _ = r.forward(disp, low, H3, W3)
+        rec = {}
+        for dt in dts:
+            e = {"vs_gt": _epe(res[dt], gt)}
+            if dt != "f32":
+                e["vs_f32"] = _epe(res[dt], res["f32"])
+            if wname == "precision_weights" and oracle_ref is not None:
+                e["vs_oracle_f64"] = _epe(res[dt], torch.from_numpy(oracle_ref).to(dev))
+            rec[dt] = e
+        out[wname] = rec
+    out["precision_weights"]["weights"] = "He-init seed 7003, final layer x 0.01"
+    if "trained_weights" in out:
+        out["trained_weights"]["weights"] = "after the 2000 training steps (512x256, batch 16, BF16)"
+    # frames/s per dtype: the whole step (census + WTA + network) replayed from a graph
+    cl_, cr_, low_, disp_ = (torch.empty_like(cl), torch.empty_like(cr), torch.empty_like(low),
+                             torch.empty_like(disp))
+    o_ = torch.empty((B, H3, W3), dtype=torch.float32, device=dev)
+    fps = {}
+    for dt in dts:
+        r = sv.Refiner(*P_C, P_L, P_F, dt)
+        r.pack(torch.from_numpy(pflat).to(dev))
+        r.workspace(B, H3, W3)
+        ls = r.latent_shape(B, H3, W3)
+        ml = torch.empty(ls[:3] + (2 * ls[3],), dtype=torch.float32, device=dev)
+
+        def step():
+            sv.sv_census_pair(left, right, P_F, *P_WIN, out=(cl_, cr_, low_))
+            sv.sv_cost_wta(cl_, cr_, P_D, nb, out=disp_)
+            r.forward(disp_, low_, H3, W3, out=o_, mu_logvar=ml)
+        step()
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            step()
+        for _ in range(Wm):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            g.replay()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / K
+        fps[dt] = {"ms_per_step": round(ms, 4), "frames_per_s": round(B * 1e3 / ms, 1)}
+        del g, r
+    out["throughput_batch8"] = fps
     return out
 
 
@@ -581,7 +720,7 @@ def main():
 
     # the CPU oracle first, while this process has not touched the GPU (its
     # worker processes are forked from here)
-    cpu = None if (args.no_cpu_baseline or args.section) else cpu_baseline()
+    cpu, ref3 = (None, None) if (args.no_cpu_baseline or args.section) else cpu_baseline()
 
     import torch
     import paper_2305_11566_amd as sv
@@ -610,10 +749,15 @@ def main():
     for _ in range(Wm):
         p32.step()
     torch.cuda.synchronize()
-    # profiled eager pass: per-kernel HIP events on the launch stream
-    sv.sv_profile_enable(K)
     eager_ms = p32.timed(K, 0, graph=False)
+    # profiled eager pass: HIP events on the launch stream around PROF_REPEAT
+    # back-to-back launches of every kernel, K times; a kernel's average
+    # duration is the summed event time over its launches
+    sv.sv_profile_enable(K)
+    sv.sv_profile_repeat(PROF_REPEAT)
+    p32.timed(K, 0, graph=False)
     prof = merge_latent(sv.sv_profile_read())
+    sv.sv_profile_repeat(1)
     sv.sv_profile_enable(0)
     p32.capture()
     ms = p32.timed(K, Wm, graph=True)
@@ -642,7 +786,9 @@ def main():
             "Tops/s": PEAK["alu_Tops"]}.get(d.get("unit"), None)
     roofline = {"kernel": dom, "bound": d.get("bound"), "achieved": d.get("achieved"), "peak": peak,
                 "unit": d.get("unit"), "frac": d.get("frac"), "traffic": None,
-                "avg_us": d["avg_us"]}
+                "avg_us": d["avg_us"],
+                "timing": f"HIP events on the launch stream around {PROF_REPEAT} back-to-back launches, "
+                          f"{K} times ({d['launches']} launches)"}
     if args.batch == 1 and hdt == "f32":
         roofline.update(traffic_lookup(dom, tiles["f32"]))
 
@@ -659,7 +805,7 @@ def main():
         obf = pbf.out.double().cpu().numpy()
         # He-init weights refine nothing: this compares the two precisions on the
         # same untrained network at full size; end-point errors against ground
-        # truth with trained weights are in extras.precision_trained
+        # truth with trained weights are in extras.precision_8x256x128
         epe = {"weights": "He-init (untrained), 1242x375",
                "bf16_vs_f32_mean_px": float(np.mean(np.abs(obf - o32))),
                "bf16_vs_f32_max_px": float(np.max(np.abs(obf - o32))),
@@ -709,6 +855,8 @@ def main():
 
     extras = {} if args.no_extras else run_extras(sv, torch, dev, flat, K, Wm)
     if not args.no_extras:
+        extras["train_512x256_b16"], trained = run_config5(sv, torch, dev)
+        extras["precision_8x256x128"] = run_config3(sv, torch, dev, K, Wm, trained, ref3)
         extras["census_sgm_1242x375"] = run_sgm(sv, torch, dev, flat, K, Wm)
         extras["table1_network_1242x375"] = run_table1(sv, torch, dev, K, Wm, not args.no_autotune)
         extras["int8_network_1242x375"] = run_int8(sv, torch, dev, flat, K, Wm, not args.no_autotune)

@@ -435,9 +435,15 @@ sv_status sv_set_latent_fusion(int on);
  * sv_profile_read synchronises on the recorded events, writes the summed
  * milliseconds and launch counts of each stage into ms_sum[13] / counts[13]
  * and restarts the counts.  sv_profile_enable(0) disables and frees.
+ * sv_profile_repeat(r) (1..64, default 1; errors: SV_ERR_RANGE): while
+ * profiling is on, each recorded stage is launched r times back to back
+ * between its two events (each launch rewrites the same outputs, so results
+ * are unchanged) and counts r launches, so ms_sum / counts is the time of one
+ * launch with the cost of the event pair spread over r launches.
  * Process-wide; the library creates and owns the events.
  */
 sv_status sv_profile_enable(int max_calls);
+sv_status sv_profile_repeat(int repeat);
 sv_status sv_profile_read(float *ms_sum, int *counts);
 
 /* The tile configuration (an index, see sv_conv_cfg_name) each of the 9

@@ -21,6 +21,7 @@ from .ops import (  # noqa: F401
     Refiner,
     vae_param_count,
     sv_profile_enable,
+    sv_profile_repeat,
     sv_profile_read,
     PROFILE_STAGES,
     BatchPlan,

@@ -82,6 +82,7 @@ _SIGS = {
     "sv_autotune": (ctypes.c_int32, [_DESC, _I, _I, _I, _I, _I, _I]),
     "sv_tile_config": (ctypes.c_int32, [_I, ctypes.c_char_p, _I]),
     "sv_profile_enable": (ctypes.c_int32, [_I]),
+    "sv_profile_repeat": (ctypes.c_int32, [_I]),
     "sv_layer_cfgs": (ctypes.c_int32, [_DESC, _I, _I, _I, ctypes.POINTER(ctypes.c_int)]),
     "sv_conv_cfg_name": (ctypes.c_char_p, [_I]),
     "sv_profile_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_int)]),

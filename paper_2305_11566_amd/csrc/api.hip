@@ -59,8 +59,9 @@ sv_status sv_census(const uint8_t *img, int B, int H, int W, int pitch, int fact
     sv_status r = check_window(win_w, win_h);
     if (r != SV_OK) return r;
     prof_mark(PROF_CENSUS, 0, (hipStream_t)stream);
-    r = launch_reduce_census(img, nullptr, B, H, W, pitch, factor, win_w, win_h, low_out, nullptr,
-                             census_out, nullptr, (hipStream_t)stream);
+    for (int rep = prof_repeat(); rep > 0 && r == SV_OK; --rep)
+        r = launch_reduce_census(img, nullptr, B, H, W, pitch, factor, win_w, win_h, low_out, nullptr,
+                                 census_out, nullptr, (hipStream_t)stream);
     prof_mark(PROF_CENSUS, 1, (hipStream_t)stream);
     return r;
 }
@@ -76,8 +77,9 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
     sv_status r = check_window(win_w, win_h);
     if (r != SV_OK) return r;
     prof_mark(PROF_CENSUS, 0, (hipStream_t)stream);
-    r = launch_reduce_census(left, right, B, H, W, pitch, factor, win_w, win_h, low_left, nullptr,
-                             cen_left, cen_right, (hipStream_t)stream);
+    for (int rep = prof_repeat(); rep > 0 && r == SV_OK; --rep)
+        r = launch_reduce_census(left, right, B, H, W, pitch, factor, win_w, win_h, low_left, nullptr,
+                                 cen_left, cen_right, (hipStream_t)stream);
     prof_mark(PROF_CENSUS, 1, (hipStream_t)stream);
     return r;
 }
@@ -115,8 +117,10 @@ sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h
     if (B <= 0 || h <= 0 || w <= 0 || h > kMaxSide || w > kMaxSide) return SV_ERR_SHAPE;
     if (D < 1 || D > 256 || nbits < 1 || nbits > 64) return SV_ERR_RANGE;
     prof_mark(PROF_COST_WTA, 0, (hipStream_t)stream);
-    sv_status r = launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, cost_wta_split_for(B, h, w, D),
-                                  (hipStream_t)stream);
+    const int dsplit = cost_wta_split_for(B, h, w, D);
+    sv_status r = SV_OK;
+    for (int rep = prof_repeat(); rep > 0 && r == SV_OK; --rep)
+        r = launch_cost_wta(cen_l, cen_r, B, h, w, D, nbits, disp_out, dsplit, (hipStream_t)stream);
     prof_mark(PROF_COST_WTA, 1, (hipStream_t)stream);
     return r;
 }

@@ -258,6 +258,11 @@ static inline void ev_rec(int i, int which, hipStream_t st) { prof_mark(PROF_E1 
         if (r_ != SV_OK) return r_;     \
     } while (0)
 
+// a profiled stage: launched prof_repeat() times back to back (once unless
+// profiling asks for repeats)
+#define SV_STAGE(x) \
+    for (int rep_ = prof_repeat(); rep_ > 0; --rep_) SV_TRY(x)
+
 sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *disp,
                       const uint8_t *img, int B, int H, int W, const float *eps, float *out,
                       float *ml_user, void *saved, void *ws, hipStream_t st, int only,
@@ -301,14 +306,14 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     // the quantised convolution its codes are defined on)
     ev_rec(0, 0, st);
     if (q8)
-        SV_TRY(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
+        SV_STAGE(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
     else if (only < 0 || only == L_E1)
-        SV_TRY(launch_enc1(ns.dtype, disp, img, (float)ns.f / 256.0f, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], c1,
+        SV_STAGE(launch_enc1(ns.dtype, disp, img, (float)ns.f / 256.0f, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], c1,
                            (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
                            (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st));
     ev_rec(0, 1, st);
     ev_rec(1, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
+    SV_STAGE(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
                      lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2), st));
     ev_rec(1, 1, st);
     // inference: the head and G3 run as one kernel, which also finishes E3's
@@ -321,9 +326,9 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                                      lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, part, a.part_bytes,
                                      LayerAmax{});
         p3.defer_sum = 1;
-        SV_TRY(launch_conv_split(ns.dtype, ns.ly[L_E3].k, ns.ly[L_E3].stride, cfg[L_E3], p3, st, &e3split));
+        SV_STAGE(launch_conv_split(ns.dtype, ns.ly[L_E3].k, ns.ly[L_E3].stride, cfg[L_E3], p3, st, &e3split));
     } else {
-        SV_TRY(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
+        SV_STAGE(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
                             lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes,
                             am(AM_E2, -1, AM_E3), st));
     }
@@ -340,33 +345,33 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
                                            1, nullptr, 0, LayerAmax{});
         ev_rec(3, 0, st);
         const float *e3bias = (const float *)((const char *)packed + ns.b_off[L_E3]);
-        SV_TRY(launch_latent(ns.dtype, ph, pg, B * h3 * w3, part, e3split, e3bias, st));
+        SV_STAGE(launch_latent(ns.dtype, ph, pg, B * h3 * w3, part, e3split, e3bias, st));
         ev_rec(3, 1, st);
     } else {
         ev_rec(3, 0, st);
-        SV_TRY(run_layer_if(only, ns, packed, L_HEAD, e3src, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3],
+        SV_STAGE(run_layer_if(only, ns, packed, L_HEAD, e3src, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3],
                             ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, am(AM_E3, -1, AM_ML), st));
         ev_rec(3, 1, st);
         ConvSrc zsrc = musrc;
         if (eps) {
             ev_rec(4, 0, st);
-            if (only < 0) SV_TRY(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
+            if (only < 0) SV_STAGE(launch_reparam(ML, eps, B * lv.h[3] * lv.w[3], L, Z, ns.dtype, st));
             ev_rec(4, 1, st);
             zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
         }
         // decoder
         ev_rec(5, 0, st);
-        SV_TRY(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3,
+        SV_STAGE(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3,
                             c3, 0, 1, cfg[L_G3], part, a.part_bytes, am(AM_ML, -1, AM_G3), st));
         ev_rec(5, 1, st);
     }
     ev_rec(6, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
+    SV_STAGE(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
                      src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
                      lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, am(AM_G3, AM_E2, AM_G2), st));
     ev_rec(6, 1, st);
     ev_rec(7, 0, st);
-    SV_TRY(run_layer_if(only, ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
+    SV_STAGE(run_layer_if(only, ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
                      src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
                      lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, am(AM_G2, AM_E1, AM_G1), st));
     ev_rec(7, 1, st);
@@ -388,10 +393,10 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
             p.proj_disp = disp;
             p.proj_img = img;
             p.proj_scale0 = (float)ns.f / 256.0f;
-            SV_TRY(launch_conv(ns.dtype, 3, 1, net_g0_proj_cfg(ns, cfg[L_G0]), p, st));
+            SV_STAGE(launch_conv(ns.dtype, 3, 1, net_g0_proj_cfg(ns, cfg[L_G0]), p, st));
         }
     } else {
-        SV_TRY(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
+        SV_STAGE(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
                             lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes,
                             am(AM_G1, AM_X0, -1), st));
     }
@@ -402,10 +407,10 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     ev_rec(10, 0, st);
     if (only < 0) {
         if (proj)
-            SV_TRY(launch_final_gather((const float *)G0, plane0, disp, ns.f, biasF, B, lv.h[0], lv.w[0], H, W,
+            SV_STAGE(launch_final_gather((const float *)G0, plane0, disp, ns.f, biasF, B, lv.h[0], lv.w[0], H, W,
                                        out, st));
         else
-            SV_TRY(launch_final(q8 ? SV_BF16 : ns.dtype, G0, c1, disp, img, wF, ns.cin_pad[L_F], ns.f, biasF, B,
+            SV_STAGE(launch_final(q8 ? SV_BF16 : ns.dtype, G0, c1, disp, img, wF, ns.cin_pad[L_F], ns.f, biasF, B,
                                 lv.h[0], lv.w[0], H, W, out, st));
     }
     ev_rec(10, 1, st);

@@ -14,4 +14,10 @@ enum ProfStage {
 // profiling is enabled; a no-op otherwise.
 void prof_mark(int stage, int which, hipStream_t st);
 
+// How many times a profiled stage is launched back to back between its two
+// events: the sv_profile_repeat setting while profiling is on, else 1.  Every
+// stage rewrites the same outputs from the same inputs, so a repeat leaves
+// the results unchanged.
+int prof_repeat();
+
 }  // namespace sv

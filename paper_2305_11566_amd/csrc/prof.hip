@@ -10,15 +10,18 @@ namespace sv {
 
 static std::mutex g_mu;
 static std::atomic<bool> g_on{false};
+static std::atomic<int> g_rep{1};
 static int g_max = 0;
 static std::vector<hipEvent_t> g_ev[PROF_NSTAGES];  // 2 * max per stage
-static int g_count[PROF_NSTAGES];
+static int g_count[PROF_NSTAGES];                   // event pairs recorded
+static int g_launches[PROF_NSTAGES];                // launches inside them
 
 static void free_events() {
     for (int s = 0; s < PROF_NSTAGES; ++s) {
         for (hipEvent_t e : g_ev[s]) (void)hipEventDestroy(e);
         g_ev[s].clear();
         g_count[s] = 0;
+        g_launches[s] = 0;
     }
 }
 
@@ -29,8 +32,13 @@ void prof_mark(int stage, int which, hipStream_t st) {
     const int i = g_count[stage];
     if (i >= g_max) return;
     (void)hipEventRecord(g_ev[stage][2 * i + which], st);
-    if (which == 1) g_count[stage] = i + 1;
+    if (which == 1) {
+        g_count[stage] = i + 1;
+        g_launches[stage] += g_rep.load();
+    }
 }
+
+int prof_repeat() { return g_on.load() ? g_rep.load() : 1; }
 
 }  // namespace sv
 
@@ -53,6 +61,13 @@ sv_status sv_profile_enable(int max_calls) {
     return SV_OK;
 }
 
+sv_status sv_profile_repeat(int repeat) {
+    if (repeat < 1 || repeat > 64) return SV_ERR_RANGE;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_rep = repeat;
+    return SV_OK;
+}
+
 sv_status sv_profile_read(float *ms_sum, int *counts) {
     if (!ms_sum || !counts) return SV_ERR_NULL;
     std::lock_guard<std::mutex> lk(g_mu);
@@ -65,8 +80,9 @@ sv_status sv_profile_read(float *ms_sum, int *counts) {
             tot += ms;
         }
         ms_sum[s] = tot;
-        counts[s] = g_count[s];
+        counts[s] = g_launches[s];
         g_count[s] = 0;
+        g_launches[s] = 0;
     }
     return SV_OK;
 }

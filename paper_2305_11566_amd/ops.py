@@ -345,6 +345,10 @@ def sv_profile_enable(max_calls: int):
     check(lib().sv_profile_enable(max_calls), "sv_profile_enable")
 
 
+def sv_profile_repeat(repeat: int):
+    check(lib().sv_profile_repeat(repeat), "sv_profile_repeat")
+
+
 PROFILE_STAGES = ("census", "cost_wta", "E1", "E2", "E3", "HEAD", "reparam", "G3", "G2", "G1",
                   "G0", "final_proj", "final_gather")
 

@@ -18,6 +18,12 @@ Two modes:
     keyed by a hash of the HIP sources so that a reader can tell whether the
     kernels have changed since.
 
+``python -m paper_2305_11566_amd.profile_traffic trace TRACE_DIR``
+    Per-launch durations from a ``rocprofv3 --kernel-trace`` collection,
+    grouped by kernel and launch shape (grid and workgroup), so that layers
+    which share a kernel template are told apart: a markdown table of calls
+    and average / min / max duration in order of first launch.
+
 ``python -m paper_2305_11566_amd.profile_traffic busy PMC_DIR N``
     MFMA busy fraction of the last N dispatches of a run profiled with
     ``rocprofv3 --pmc SQ_VALU_MFMA_BUSY_CYCLES ... GRBM_GUI_ACTIVE``.
@@ -137,7 +143,7 @@ def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) ->
         elif "k_conv_split_reduce" in n:
             cur[-1][1] += fb
             cur[-1][2] += wb
-        elif "k_conv<" in n or "k_latent<" in n:
+        elif "k_conv<" in n or "k_latent<" in n or "k_enc1<" in n:
             cur.append([n, fb, wb])
         elif "k_final" in n:
             forwards.append((cur, (fb, wb)))
@@ -160,6 +166,32 @@ def summarize(fetch_dir: str, write_dir: str, names_json: str, out_json: str) ->
     with open(out_json, "w") as f:
         json.dump(doc, f, indent=1, sort_keys=True)
     print(f"wrote {out_json}: {len(entries)} layer entries, scales {s_fetch:.3f} / {s_write:.3f}")
+
+
+def _short(name: str) -> str:
+    return name.replace("(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+
+def trace(trace_dir: str) -> None:
+    rows = []
+    for path in glob.glob(os.path.join(trace_dir, "**", "*kernel_trace.csv"), recursive=True):
+        with open(path) as f:
+            rows += list(csv.DictReader(f))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    groups = {}
+    for r in rows:
+        if "Grid_Size_X" in r:
+            grid = f"{r['Grid_Size_X']}x{r['Grid_Size_Y']}x{r['Grid_Size_Z']}"
+            wg = f"{r['Workgroup_Size_X']}x{r['Workgroup_Size_Y']}x{r['Workgroup_Size_Z']}"
+        else:
+            grid, wg = r.get("Grid_Size", "?"), r.get("Workgroup_Size", "?")
+        key = (_short(r["Kernel_Name"]), grid, wg)
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        groups.setdefault(key, []).append(us)
+    print("| kernel | grid (threads) | workgroup | calls | avg us | min us | max us |")
+    print("|---|---|---|---|---|---|---|")
+    for (name, grid, wg), v in groups.items():
+        print(f"| `{name}` | {grid} | {wg} | {len(v)} | {sum(v) / len(v):.2f} | {min(v):.2f} | {max(v):.2f} |")
 
 
 def busy(pmc_dir: str, nkernels: int) -> None:
@@ -199,7 +231,10 @@ if __name__ == "__main__":
         run()
     elif sys.argv[1] == "summarize":
         summarize(*sys.argv[2:6])
+    elif sys.argv[1] == "trace":
+        trace(sys.argv[2])
     elif sys.argv[1] == "busy":
         busy(sys.argv[2], int(sys.argv[3]))
     else:
-        raise SystemExit("usage: profile_traffic run | summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON | busy PMC_DIR N")
+        raise SystemExit("usage: profile_traffic run | summarize FETCH_DIR WRITE_DIR NAMES_JSON OUT_JSON | "
+                         "trace TRACE_DIR | busy PMC_DIR N")

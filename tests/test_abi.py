@@ -173,6 +173,13 @@ def test_latent_fusion_switch():
     assert lib().sv_set_latent_fusion(1) == 0
 
 
+def test_profile_repeat_range():
+    assert lib().sv_profile_repeat(0) == -3
+    assert lib().sv_profile_repeat(65) == -3
+    assert lib().sv_profile_repeat(64) == 0
+    assert lib().sv_profile_repeat(1) == 0
+
+
 def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     import paper_2305_11566_amd._lib as L
     monkeypatch.setattr(L, "_lib", None)
