@@ -5,6 +5,8 @@
 // of Sec. IV-C); the definition used is the usual one: a bit per window
 // neighbour, set when the neighbour is strictly darker than the centre.
 // Winner-take-all is Eq. (6) on the raw (unaggregated) Hamming cost.
+#include <type_traits>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -15,9 +17,10 @@ namespace sv {
 // of one image, TH = 4 or 16 (taller tiles re-read less halo; shorter ones
 // give more workgroups for a single small frame).  The reduced patch with its
 // clamped halo is built once in LDS (each patch pixel is the block mean of
-// F x F full-resolution bytes; F is a template parameter so that the F * F
-// byte loads of several patch pixels are unrolled and in flight together),
-// then every thread packs the census words of its pixels from LDS.
+// F x F full-resolution bytes: for F = 2, 4 four patch pixels per lane from
+// one vector load per full-resolution row, else byte loads of several pixels
+// unrolled and in flight together), then every thread packs the census words
+// of its pixels from LDS.
 // ---------------------------------------------------------------------------
 constexpr int CEN_TW = CEN_TILE_W, CEN_MAXR = 8;
 constexpr int CEN_THREADS = 256;
@@ -60,18 +63,130 @@ __device__ __forceinline__ uint64_t census_word(const CenPatch<TH> &patch, int p
     }
 }
 
-// One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
-template <int F, int TH, int RX = 0, int RY = 0>
-__device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *__restrict__ img,
-                                            int H, int W, int pitch, int rx, int ry, int h, int w,
-                                            int i0, int j0, uint8_t *__restrict__ low,
-                                            uint64_t *__restrict__ cen)
-{
-    if constexpr (RX > 0) {
-        rx = RX;
-        ry = RY;
+// The census words of the four pixels at patch (py, c0 + RX .. c0 + RX + 3)
+// for a compile-time window: every window row is read once as the aligned
+// words that hold columns c0 .. c0 + 3 + 2 RX (the patch rows are 4-byte
+// aligned, c0 a multiple of 4), and the bytes are taken from registers.  Bit
+// order and comparison as in census_word.
+template <int TH, int RX, int RY>
+__device__ __forceinline__ void census_words4(const CenPatch<TH> &patch, int py, int c0, uint64_t code[4]) {
+    constexpr int NW = (4 + 2 * RX + 3) / 4, NR = 2 * RY + 1;
+    uint32_t row[NR][NW];
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int k = 0; k < NW; ++k) row[r][k] = *(const uint32_t *)&patch[py - RY + r][c0 + 4 * k];
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+        const uint32_t c = (row[RY][(g + RX) >> 2] >> (8 * ((g + RX) & 3))) & 0xffu;
+        uint32_t lo = 0, hi = 0;
+        int k = 0;
+#pragma unroll
+        for (int dy = -RY; dy <= RY; ++dy)
+#pragma unroll
+            for (int dx = -RX; dx <= RX; ++dx) {
+                if (dy == 0 && dx == 0) continue;
+                const int col = g + RX + dx;
+                const uint32_t v = (row[dy + RY][col >> 2] >> (8 * (col & 3))) & 0xffu;
+                const uint32_t bit = (v - c) >> 31;
+                if (k < 32) lo |= bit << k;
+                else hi |= bit << (k - 32);
+                ++k;
+            }
+        code[g] = ((uint64_t)hi << 32) | lo;
     }
-    // patch pixels per thread whose loads are issued before any is summed
+}
+
+// The block mean of reduced pixel (i, j), clamped into the reduced image; a
+// block cut by the image edge averages the bytes it holds (round half up).
+template <int F>
+__device__ __forceinline__ uint32_t block_mean(const uint8_t *__restrict__ img, int H, int W, int pitch,
+                                               int h, int w, int i, int j) {
+    i = min(max(i, 0), h - 1);
+    j = min(max(j, 0), w - 1);
+    const int ny = min(F, H - F * i), nx = min(F, W - F * j);
+    const uint8_t *src = img + (size_t)(F * i) * pitch + F * j;
+    uint32_t sum = 0;
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) sum += src[(size_t)y * pitch + x];
+    const uint32_t n = (uint32_t)(ny * nx);
+    return (sum + n / 2) / n;
+}
+
+// The reduced patch of a tile for F = 2 or 4 and a compile-time window: a lane
+// builds four horizontally adjacent patch pixels from F full-resolution rows,
+// one vector load of 4F bytes per row (the rows of an image of odd pitch are
+// not 4-byte aligned: these loads rely on the unaligned global access the
+// GPU runs in), summed with v_sad_u8 and stored to LDS as one word.  Groups
+// that reach a clamped or edge-cut block take the per-pixel path.
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
+template <int F, int TH, int RX, int RY>
+__device__ __forceinline__ void reduce_patch4(CenPatch<TH> &patch, const uint8_t *__restrict__ img, int H,
+                                              int W, int pitch, int h, int w, int i0, int j0) {
+    static_assert(F == 2 || F == 4, "vector path for F = 2, 4");
+    constexpr int PH = TH + 2 * RY, PW = CEN_TW + 2 * RX, NG = (PW + 3) / 4;
+    static_assert(4 * NG <= CEN_TW + 2 * CEN_MAXR, "groups fit the patch row");
+    // groups per thread, all of whose loads are issued before any is summed
+    constexpr int NI = (PH * NG + CEN_THREADS - 1) / CEN_THREADS;
+    using V = typename std::conditional<F == 4, u32x4_a4, u32x2_a4>::type;
+    const int hc = H / F, wc = W / F;  // whole blocks
+    V v[NI][F];
+    bool fast[NI];
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int e = threadIdx.x + k * CEN_THREADS;
+        const int pr = e / NG, cg = e - pr * NG;
+        const int i = i0 + pr - RY, jg = j0 - RX + 4 * cg;
+        fast[k] = e < PH * NG && i >= 0 && i < hc && jg >= 0 && jg + 3 < wc;
+        if (fast[k]) {
+            const uint8_t *src = img + (size_t)(F * i) * pitch + F * jg;
+#pragma unroll
+            for (int y = 0; y < F; ++y) v[k][y] = *(const V *)(src + (size_t)y * pitch);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NI; ++k) {
+        const int e = threadIdx.x + k * CEN_THREADS;
+        if (e >= PH * NG) break;
+        const int pr = e / NG, cg = e - pr * NG;
+        uint32_t word;
+        if (fast[k]) {
+            uint32_t s0 = F * F / 2, s1 = s0, s2 = s0, s3 = s0;
+#pragma unroll
+            for (int y = 0; y < F; ++y) {
+                if constexpr (F == 4) {
+                    s0 = __builtin_amdgcn_sad_u8(v[k][y][0], 0u, s0);
+                    s1 = __builtin_amdgcn_sad_u8(v[k][y][1], 0u, s1);
+                    s2 = __builtin_amdgcn_sad_u8(v[k][y][2], 0u, s2);
+                    s3 = __builtin_amdgcn_sad_u8(v[k][y][3], 0u, s3);
+                } else {
+                    s0 = __builtin_amdgcn_sad_u8(v[k][y][0] & 0xffffu, 0u, s0);
+                    s1 = __builtin_amdgcn_sad_u8(v[k][y][0] >> 16, 0u, s1);
+                    s2 = __builtin_amdgcn_sad_u8(v[k][y][1] & 0xffffu, 0u, s2);
+                    s3 = __builtin_amdgcn_sad_u8(v[k][y][1] >> 16, 0u, s3);
+                }
+            }
+            constexpr int SH = F == 4 ? 4 : 2;  // / (F * F)
+            word = (s0 >> SH) | ((s1 >> SH) << 8) | ((s2 >> SH) << 16) | ((s3 >> SH) << 24);
+        } else {
+            const int i = i0 + pr - RY, jg = j0 - RX + 4 * cg;
+            word = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                word |= block_mean<F>(img, H, W, pitch, h, w, i, jg + q) << (8 * q);
+        }
+        *(uint32_t *)&patch[pr][4 * cg] = word;
+    }
+}
+
+// The reduced patch of a tile, any F and window: a thread reads the F x F
+// bytes of several patch pixels (F is a template parameter so that the loads
+// of R pixels are unrolled and in flight together) before summing any.
+template <int F, int TH>
+__device__ __forceinline__ void reduce_patch(CenPatch<TH> &patch, const uint8_t *__restrict__ img, int H,
+                                             int W, int pitch, int rx, int ry, int h, int w, int i0, int j0) {
     constexpr int R = F * F >= 48 ? 1 : (48 / (F * F) > 4 ? 4 : 48 / (F * F));
     const int PH = TH + 2 * ry, PW = CEN_TW + 2 * rx;
     const int tid = threadIdx.x;
@@ -111,15 +226,55 @@ __device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *
             patch[py][px] = (uint8_t)(n == F * F ? (sum + F * F / 2) / (F * F) : (sum + n / 2) / n);
         }
     }
+}
+
+// One tile of one image: img is that image ([H][pitch]), low/cen its [h][w] maps.
+// The reduced patch with its clamped halo is built in LDS, then every thread
+// packs the census words of its pixels from LDS.
+template <int F, int TH, int RX = 0, int RY = 0>
+__device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *__restrict__ img,
+                                            int H, int W, int pitch, int rx, int ry, int h, int w,
+                                            int i0, int j0, uint8_t *__restrict__ low,
+                                            uint64_t *__restrict__ cen)
+{
+    if constexpr (RX > 0) {
+        rx = RX;
+        ry = RY;
+    }
+    if constexpr (RX > 0 && (F == 2 || F == 4))
+        reduce_patch4<F, TH, RX, RY>(patch, img, H, W, pitch, h, w, i0, j0);
+    else
+        reduce_patch<F, TH>(patch, img, H, W, pitch, rx, ry, h, w, i0, j0);
+    const int tid = threadIdx.x;
     __syncthreads();
-    const int tx = tid % CEN_TW;
-    for (int ty = tid / CEN_TW; ty < TH; ty += CEN_THREADS / CEN_TW) {
-        const int i = i0 + ty, j = j0 + tx;
-        if (i < h && j < w) {
-            const uint64_t code = census_word<TH, RX, RY>(patch, ty + ry, tx + rx, rx, ry);
-            const size_t o = (size_t)i * w + j;
-            cen[o] = code;
-            if (low) low[o] = patch[ty + ry][tx + rx];
+    if constexpr (RX > 0) {
+        // four horizontally adjacent pixels per thread, from aligned words
+        constexpr int NQ = CEN_TW / 4;
+        const int q = tid % NQ, jq = j0 + 4 * q;
+        for (int ty = tid / NQ; ty < TH; ty += CEN_THREADS / NQ) {
+            const int i = i0 + ty;
+            if (i >= h || jq >= w) continue;
+            uint64_t code[4];
+            census_words4<TH, RX, RY>(patch, ty + RY, 4 * q, code);
+            const size_t o = (size_t)i * w + jq;
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                if (jq + g < w) {
+                    cen[o + g] = code[g];
+                    if (low) low[o + g] = patch[ty + RY][4 * q + g + RX];
+                }
+            }
+        }
+    } else {
+        const int tx = tid % CEN_TW;
+        for (int ty = tid / CEN_TW; ty < TH; ty += CEN_THREADS / CEN_TW) {
+            const int i = i0 + ty, j = j0 + tx;
+            if (i < h && j < w) {
+                const uint64_t code = census_word<TH, RX, RY>(patch, ty + ry, tx + rx, rx, ry);
+                const size_t o = (size_t)i * w + j;
+                cen[o] = code;
+                if (low) low[o] = patch[ty + ry][tx + rx];
+            }
         }
     }
     __syncthreads();  // the patch is reused by the next tile of a persistent loop
@@ -132,7 +287,7 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
                 uint8_t *__restrict__ low1, uint64_t *__restrict__ cen0,
                 uint64_t *__restrict__ cen1)
 {
-    __shared__ CenPatch<TH> patch;
+    __shared__ __attribute__((aligned(16))) CenPatch<TH> patch;
     const int view = blockIdx.z % 2;
     const int b = blockIdx.z / 2;
     if (view && !img1) return;
@@ -200,7 +355,7 @@ __global__ void __launch_bounds__(CEN_THREADS)
 k_reduce_census_tab(const PairTable *__restrict__ tab, int rx, int ry, uint8_t *__restrict__ low0,
                     uint64_t *__restrict__ cen0, uint64_t *__restrict__ cen1)
 {
-    __shared__ CenPatch<TH> patch;
+    __shared__ __attribute__((aligned(16))) CenPatch<TH> patch;
     const int n = tab->n;
     const int *cum = tab->cum[BS_CENSUS];
     const int total = cum[n];
@@ -291,15 +446,21 @@ __device__ __forceinline__ void cost_wta_seg(uint64_t *rseg, const uint64_t *__r
     __syncthreads();
 }
 
+// A workgroup takes rows blockIdx.y * rpw .. + rpw - 1 of its column segment
+// (several rows per workgroup at large batch: short-lived workgroups cost more
+// to launch than they compute).
 template <int DSPLIT>
 __global__ void __launch_bounds__(CW_THREADS)
 k_cost_wta(const uint64_t *__restrict__ cl, const uint64_t *__restrict__ cr, int h, int w, int D,
-           int nbits, uint8_t *__restrict__ disp)
+           int nbits, int rpw, uint8_t *__restrict__ disp)
 {
     __shared__ uint64_t rseg[CW_THREADS / DSPLIT + 256];
-    const size_t row = ((size_t)blockIdx.z * h + blockIdx.y) * w;
-    cost_wta_seg<DSPLIT>(rseg, cl + row, cr + row, w, D, nbits, disp + row, nullptr,
-                         blockIdx.x * (CW_THREADS / DSPLIT));
+    const int r1 = min(h, (int)(blockIdx.y + 1) * rpw);
+    for (int r = blockIdx.y * rpw; r < r1; ++r) {
+        const size_t row = ((size_t)blockIdx.z * h + r) * w;
+        cost_wta_seg<DSPLIT>(rseg, cl + row, cr + row, w, D, nbits, disp + row, nullptr,
+                             blockIdx.x * (CW_THREADS / DSPLIT));
+    }
 }
 
 template <int DSPLIT>
@@ -348,12 +509,15 @@ sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl
 sv_status launch_cost_wta(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D,
                           int nbits, uint8_t *disp, int dsplit, hipStream_t s)
 {
+    // rows per workgroup: 4 once that still leaves 8 workgroups per CU
+    const long long wgs = (long long)cdiv(w, CW_THREADS / dsplit) * h * B;
+    const int rpw = wgs >= 4 * 2048 ? 4 : 1;
     switch (dsplit) {
 #define SV_CW_CASE(N)                                                                      \
     case N: {                                                                              \
-        dim3 grid(cdiv(w, CW_THREADS / N), h, B);                                          \
+        dim3 grid(cdiv(w, CW_THREADS / N), cdiv(h, rpw), B);                               \
         hipLaunchKernelGGL(k_cost_wta<N>, grid, dim3(CW_THREADS), 0, s, cl, cr, h, w, D,   \
-                           nbits, disp);                                                   \
+                           nbits, rpw, disp);                                              \
         break;                                                                             \
     }
         SV_CW_CASE(1)
