@@ -45,6 +45,7 @@ struct sv_batch_plan {
     int max_n, max_H, max_W, max_D, win_w, win_h, nbits;
     int dsplit;
     int cen_th;  // census tile height (4 or 16)
+    int fin_th;  // final gather tile height (16, 32 or 64)
     int cfg[NLAYERS];
     int grid[BS_NSTAGES];
     size_t cap[4];
@@ -217,7 +218,9 @@ static void pair_tiles(const sv_batch_plan *pl, const PairGeo &g, int *tiles) {
         tiles[r.stage] = conv_tiles(pl->cfg[r.li], g.h[r.out_level], g.w[r.out_level],
                                     run_cout(pl->ns, r.li));
     tiles[BS_E1] = enc1_tiles(g.h[1], g.w[1]);  // E1 runs as a direct stencil
-    tiles[BS_FINAL] = cdiv(g.W, FIN_TILE_W) * cdiv(g.H, FIN_TILE_H);
+    // the final layer: the gather's tiles when G0 projects, else k_final's
+    const int final_tile_h = net_projects(pl->ns, false) ? pl->fin_th : FIN_TILE_H;
+    tiles[BS_FINAL] = cdiv(g.W, FIN_TILE_W) * cdiv(g.H, final_tile_h);
 }
 
 static void fill_geo(const NetShape &ns, int H, int W, PairGeo &g) {
@@ -292,7 +295,7 @@ static sv_status enqueue_stages(sv_batch_plan *pl, const void *packed, hipStream
     }
     if (net_projects(ns, false))
         return launch_final_gather_tab(pl->tab_dev, pl->grid[BS_FINAL], (const float *)pl->G0,
-                                       (long long)pl->cap[0], pl->disp, ns.f,
+                                       (long long)pl->cap[0], pl->disp, ns.f, pl->fin_th,
                                        (const float *)((const char *)packed + ns.b_off[L_F]), st);
     return launch_final_tab(pl->tab_dev, pl->grid[BS_FINAL], ns.dtype, pl->G0, c1, pl->disp, pl->low,
                             (const float *)((const char *)packed + ns.w_off[L_F]), ns.cin_pad[L_F],
@@ -358,6 +361,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
     const Levels mx = net_levels(ns, max_H, max_W);
     pl->dsplit = cost_wta_split_for(max_n, mx.h[0], mx.w[0], max_D);
     pl->cen_th = census_tile_height(max_n, mx.h[0], mx.w[0]);
+    pl->fin_th = gather_tile_h(ns.f, (long long)max_n * max_H * max_W);
     for (int i = 0; i < NLAYERS; ++i) {
         const int lvl = i == L_E1 ? 1 : (i == L_E2 ? 2 : (i <= L_G3 ? 3 : (i == L_G2 ? 2 : (i == L_G1 ? 1 : 0))));
         pl->cfg[i] = net_default_cfg(ns, i, mx.h[lvl] * mx.w[lvl]);

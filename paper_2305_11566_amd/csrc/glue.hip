@@ -285,24 +285,47 @@ k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__res
     }
 }
 
-// The gather from precomputed projections T (FP32 [9][plane]).  A thread
-// owns one output column X of the tile and keeps, in registers, the column
-// indices and weights of X - 1, X, X + 1 (zero outside the image: the 3 x 3
-// convolution's padding of the resized map).  Horizontal pass, per coarse row
-// i of the window and row tap u:
+// The gather from precomputed projections T (FP32 [9][plane]).  Tiles are
+// FIN_TILE_W x TH output pixels, TH = gather_tile_h(f, output pixels): taller
+// tiles at larger f, where a coarse window row covers more output rows, so
+// that the window's halo is re-read less, while there are enough of them to
+// fill the GPU.  Horizontal pass, per coarse row i of the
+// window and row tap u, by a thread that owns output column X (it keeps the
+// column indices and weights of X - 1, X, X + 1, zero outside the image: the
+// 3 x 3 convolution's padding of the resized map):
 //   H_u(i, X) = sum_v [(1 - lx_v) T_uv(i, x0_v) + lx_v T_uv(i, x1_v)],
 // and the base's H_d(i, X) from the coarse disparity at column X; vertical
-// pass, per output pixel:
+// pass, four adjacent output pixels per thread (one 16-byte store):
 //   R(Y, X) = sum_u [(1 - ly_u) H_u(y0_u, X) + ly_u H_u(y1_u, X)],
 //   out = 256 (bias + R + f d(Y, X) / 256).
 // Dynamic LDS (floats): T[9][PHm][PWm], d[PHm][PWm], H[4][PHm][FIN_TILE_W].
-static inline size_t gather_lds_bytes(int f) {
-    int ph, pw;
-    fin_window(f, ph, pw);
-    return sizeof(float) * ((size_t)10 * ph * pw + (size_t)4 * ph * FIN_TILE_W);
+int gather_tile_h(int f, long long out_px) {
+    int th = f >= 4 ? 64 : (f >= 2 ? 32 : 16);
+    while (th > 16 && out_px < 1024LL * FIN_TILE_W * th) th /= 2;
+    return th;
 }
 
-__device__ __forceinline__ void gather_tile(float *dyn, FinTab &tb, int PHm, int PWm,
+static inline void gather_window(int f, int th, int &ph, int &pw) {
+    ph = std::min(th + 3, cdiv(th + 1, f) + 3);
+    pw = std::min(FIN_TILE_W + 3, cdiv(FIN_TILE_W + 1, f) + 3);
+}
+
+static inline size_t gather_lds_bytes(int f, int th) {
+    int ph, pw;
+    gather_window(f, th, ph, pw);
+    return sizeof(float) * ((((size_t)10 * ph * pw + 3) & ~(size_t)3) + (size_t)4 * ph * FIN_TILE_W);
+}
+
+template <int TH>
+struct GatherTab {
+    int cx0[FIN_CX], cx1[FIN_CX], cy0[TH + 2], cy1[TH + 2];
+    float clx[FIN_CX], cwx[FIN_CX], cly[TH + 2], cwy[TH + 2];  // cw: weight of the lower corner, 0 outside
+};
+
+typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+template <int TH>
+__device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int PHm, int PWm,
                                             const float *__restrict__ Tp, long long plane,
                                             const uint8_t *__restrict__ db, float scale0, float bias,
                                             int h, int w, int H, int W, int X0, int Y0,
@@ -311,19 +334,19 @@ __device__ __forceinline__ void gather_tile(float *dyn, FinTab &tb, int PHm, int
     const int tid = threadIdx.x;
     float *sT = dyn;                        // [9][PHm][PWm]
     float *sd = sT + 9 * PHm * PWm;         // [PHm][PWm]
-    float *sH = sd + PHm * PWm;             // [4][PHm][FIN_TILE_W]
+    float *sH = dyn + ((10 * PHm * PWm + 3) & ~3);  // [4][PHm][FIN_TILE_W], 16-byte aligned
     int xa, ya, xb, yb, i1;
     float lam;
     bilin(max(X0 - 1, 0), w, W, xa, i1, lam);
     bilin(max(Y0 - 1, 0), h, H, ya, i1, lam);
     bilin(min(X0 + FIN_TILE_W, W - 1), w, W, i1, xb, lam);
-    bilin(min(Y0 + FIN_TILE_H, H - 1), h, H, i1, yb, lam);
+    bilin(min(Y0 + TH, H - 1), h, H, i1, yb, lam);
     const int pw = xb - xa + 1, ph = yb - ya + 1;
     if (ph > PHm || pw > PWm) return;  // excluded by the window bound
     if (tid < FIN_CX) {
         const int X = X0 - 1 + tid;
         int x0 = 0, x1 = 0;
-        float lx = 0.f, wx = 0.f;  // wx: weight of the lower corner, 0 outside the image
+        float lx = 0.f, wx = 0.f;
         if (X >= 0 && X < W) {
             bilin(X, w, W, x0, x1, lx);
             x0 -= xa;
@@ -334,7 +357,7 @@ __device__ __forceinline__ void gather_tile(float *dyn, FinTab &tb, int PHm, int
         tb.cx1[tid] = x1;
         tb.clx[tid] = lx;
         tb.cwx[tid] = wx;
-    } else if (tid >= 128 && tid < 128 + FIN_CY) {
+    } else if (tid >= 128 && tid < 128 + TH + 2) {
         const int r = tid - 128, Y = Y0 - 1 + r;
         int y0 = 0, y1 = 0;
         float ly = 0.f, wy = 0.f;
@@ -349,95 +372,129 @@ __device__ __forceinline__ void gather_tile(float *dyn, FinTab &tb, int PHm, int
         tb.cly[r] = ly;
         tb.cwy[r] = wy;
     }
-    // the nine projections and the coarse disparity on the window, loads first
+    // the nine projections and the coarse disparity on the window; two
+    // window pixels per thread and round, all of their loads issued first
     const float inv_pw = 1.0f / (float)pw;
     const int npx = ph * pw;
-    for (int q = tid; q < npx; q += FIN_THREADS) {
-        const int r = fin_div(q, inv_pw), c = q - r * pw;
-        const size_t gp = (size_t)(ya + r) * w + xa + c;
-        float a[9];
+    for (int q0 = tid; q0 < npx; q0 += 2 * FIN_THREADS) {
+        float a[2][10];
+        int rr[2], cc[2];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) a[t] = Tp[t * plane + gp];
-        const float dv = (float)db[gp];
+        for (int k = 0; k < 2; ++k) {
+            const int q = min(q0 + k * FIN_THREADS, npx - 1);
+            rr[k] = fin_div(q, inv_pw);
+            cc[k] = q - rr[k] * pw;
+            const size_t gp = (size_t)(ya + rr[k]) * w + xa + cc[k];
 #pragma unroll
-        for (int t = 0; t < 9; ++t) sT[(t * PHm + r) * PWm + c] = a[t];
-        sd[r * PWm + c] = dv;
-    }
-    __syncthreads();
-    const int tx = tid & (FIN_TILE_W - 1), rg = tid / FIN_TILE_W;
-    constexpr int NRG = FIN_THREADS / FIN_TILE_W;
-    // this column's taps: X - 1, X, X + 1 are table entries tx, tx + 1, tx + 2
-    int hx0[3], hx1[3];
-    float hl[3], hw[3];
-#pragma unroll
-    for (int v = 0; v < 3; ++v) {
-        hx0[v] = tb.cx0[tx + v];
-        hx1[v] = tb.cx1[tx + v];
-        hl[v] = tb.clx[tx + v];
-        hw[v] = tb.cwx[tx + v];
-    }
-    for (int i = rg; i < ph; i += NRG) {
-        float hu[3];
-#pragma unroll
-        for (int u = 0; u < 3; ++u) {
-            float acc = 0.f;
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const float *row = sT + ((u * 3 + v) * PHm + i) * PWm;
-                acc = fmaf(hw[v], row[hx0[v]], acc);
-                acc = fmaf(hl[v], row[hx1[v]], acc);
-            }
-            hu[u] = acc;
+            for (int t = 0; t < 9; ++t) a[k][t] = Tp[t * plane + gp];
+            a[k][9] = (float)db[gp];
         }
-        const float *drow = sd + i * PWm;
-        const float hd = fmaf(hl[1], drow[hx1[1]], hw[1] * drow[hx0[1]]);
 #pragma unroll
-        for (int u = 0; u < 3; ++u) sH[(u * PHm + i) * FIN_TILE_W + tx] = hu[u];
-        sH[(3 * PHm + i) * FIN_TILE_W + tx] = hd;
+        for (int k = 0; k < 2; ++k) {
+            if (q0 + k * FIN_THREADS < npx) {
+#pragma unroll
+                for (int t = 0; t < 9; ++t) sT[(t * PHm + rr[k]) * PWm + cc[k]] = a[k][t];
+                sd[rr[k] * PWm + cc[k]] = a[k][9];
+            }
+        }
     }
     __syncthreads();
-    const int X = X0 + tx;
-    for (int ty = rg; ty < FIN_TILE_H; ty += NRG) {
-        const int Y = Y0 + ty;
-        if (X < W && Y < H) {
-            float acc = bias;
+    {
+        const int tx = tid & (FIN_TILE_W - 1), rg = tid / FIN_TILE_W;
+        constexpr int NRG = FIN_THREADS / FIN_TILE_W;
+        // this column's taps: X - 1, X, X + 1 are table entries tx, tx + 1, tx + 2
+        int hx0[3], hx1[3];
+        float hl[3], hw[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+            hx0[v] = tb.cx0[tx + v];
+            hx1[v] = tb.cx1[tx + v];
+            hl[v] = tb.clx[tx + v];
+            hw[v] = tb.cwx[tx + v];
+        }
+        for (int i = rg; i < ph; i += NRG) {
+            float hu[3];
 #pragma unroll
             for (int u = 0; u < 3; ++u) {
-                const int e = ty + u;  // table entry of row Y + u - 1
-                const float *hp = sH + u * PHm * FIN_TILE_W + tx;
-                acc = fmaf(tb.cwy[e], hp[tb.cy0[e] * FIN_TILE_W], acc);
-                acc = fmaf(tb.cly[e], hp[tb.cy1[e] * FIN_TILE_W], acc);
+                float acc = 0.f;
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const float *row = sT + ((u * 3 + v) * PHm + i) * PWm;
+                    acc = fmaf(hw[v], row[hx0[v]], acc);
+                    acc = fmaf(hl[v], row[hx1[v]], acc);
+                }
+                hu[u] = acc;
             }
-            const float *dp = sH + 3 * PHm * FIN_TILE_W + tx;
-            const int e = ty + 1;
-            const float base = fmaf(tb.cly[e], dp[tb.cy1[e] * FIN_TILE_W], tb.cwy[e] * dp[tb.cy0[e] * FIN_TILE_W]);
-            out[(size_t)Y * W + X] = 256.0f * fmaf(scale0, base, acc);
+            const float *drow = sd + i * PWm;
+            const float hd = fmaf(hl[1], drow[hx1[1]], hw[1] * drow[hx0[1]]);
+#pragma unroll
+            for (int u = 0; u < 3; ++u) sH[(u * PHm + i) * FIN_TILE_W + tx] = hu[u];
+            sH[(3 * PHm + i) * FIN_TILE_W + tx] = hd;
+        }
+    }
+    __syncthreads();
+    constexpr int QW = FIN_TILE_W / 4;  // threads per output row
+    const int c4 = (tid % QW) * 4, X = X0 + c4;
+    for (int ty = tid / QW; ty < TH; ty += FIN_THREADS / QW) {
+        const int Y = Y0 + ty;
+        if (Y >= H || X >= W) continue;
+        f32x4 acc = {bias, bias, bias, bias};
+#pragma unroll
+        for (int u = 0; u < 3; ++u) {
+            const int e = ty + u;  // table entry of row Y + u - 1
+            const float *hp = sH + u * PHm * FIN_TILE_W + c4;
+            const f32x4 h0 = *(const f32x4 *)(hp + tb.cy0[e] * FIN_TILE_W);
+            const f32x4 h1 = *(const f32x4 *)(hp + tb.cy1[e] * FIN_TILE_W);
+            const float wy = tb.cwy[e], ly = tb.cly[e];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) acc[k] = fmaf(ly, h1[k], fmaf(wy, h0[k], acc[k]));
+        }
+        const int e = ty + 1;
+        const float *dp = sH + 3 * PHm * FIN_TILE_W + c4;
+        const f32x4 d0 = *(const f32x4 *)(dp + tb.cy0[e] * FIN_TILE_W);
+        const f32x4 d1 = *(const f32x4 *)(dp + tb.cy1[e] * FIN_TILE_W);
+        f32x4 r;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const float base = fmaf(tb.cly[e], d1[k], tb.cwy[e] * d0[k]);
+            r[k] = 256.0f * fmaf(scale0, base, acc[k]);
+        }
+        float *op = out + (size_t)Y * W + X;
+        if (X + 3 < W) {
+            // rows of odd W are not 16-byte aligned: relies on unaligned global access
+            *(f32x4_a4 *)op = f32x4_a4{r[0], r[1], r[2], r[3]};
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                if (X + k < W) op[k] = r[k];
         }
     }
     __syncthreads();  // the LDS is reused by the next tile of a persistent loop
 }
 
 // The gather from precomputed projections (uniform batch and pair table).
+template <int TH>
 __global__ void __launch_bounds__(FIN_THREADS)
 k_final_gather(const float *__restrict__ T, long long plane, const uint8_t *__restrict__ disp, float scale0,
                const float *__restrict__ biasF, int h, int w, int H, int W, int PHm, int PWm,
                float *__restrict__ out)
 {
     extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
-    __shared__ FinTab tb;
+    __shared__ GatherTab<TH> tb;
     const int b = blockIdx.z;
     const size_t o = (size_t)b * h * w;
-    gather_tile(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, biasF[0], h, w, H, W,
-                blockIdx.x * FIN_TILE_W, blockIdx.y * FIN_TILE_H, out + (size_t)b * H * W);
+    gather_tile<TH>(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, biasF[0], h, w, H, W,
+                    blockIdx.x * FIN_TILE_W, blockIdx.y * TH, out + (size_t)b * H * W);
 }
 
+template <int TH>
 __global__ void __launch_bounds__(FIN_THREADS)
 k_final_gather_tab(const PairTable *__restrict__ tab, const float *__restrict__ T, long long plane,
                    const uint8_t *__restrict__ disp, float scale0, const float *__restrict__ biasF, int PHm,
                    int PWm)
 {
     extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
-    __shared__ FinTab tb;
+    __shared__ GatherTab<TH> tb;
     const int n = tab->n;
     const int *cum = tab->cum[BS_FINAL];
     const int total = cum[n];
@@ -448,8 +505,8 @@ k_final_gather_tab(const PairTable *__restrict__ tab, const float *__restrict__ 
         const int local = t - cum[i];
         const int tx = cdiv_d(g.W, FIN_TILE_W);
         const size_t o = (size_t)g.off[0];
-        gather_tile(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, bias, g.h[0], g.w[0], g.H, g.W,
-                    (local % tx) * FIN_TILE_W, (local / tx) * FIN_TILE_H, g.out);
+        gather_tile<TH>(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, bias, g.h[0], g.w[0], g.H, g.W,
+                        (local % tx) * FIN_TILE_W, (local / tx) * TH, g.out);
     }
 }
 
@@ -460,10 +517,12 @@ static sv_status fin_allow_lds() {
     static hipError_t err = hipSuccess;
     std::call_once(once, [] {
         const int bytes = 96 * 1024;
-        const void *fns[8] = {(const void *)k_final<SV_F32>,     (const void *)k_final<SV_BF16>,
-                              (const void *)k_final<SV_F16>,     (const void *)k_final_tab<SV_F32>,
-                              (const void *)k_final_tab<SV_BF16>, (const void *)k_final_tab<SV_F16>,
-                              (const void *)k_final_gather,      (const void *)k_final_gather_tab};
+        const void *fns[12] = {(const void *)k_final<SV_F32>,          (const void *)k_final<SV_BF16>,
+                               (const void *)k_final<SV_F16>,          (const void *)k_final_tab<SV_F32>,
+                               (const void *)k_final_tab<SV_BF16>,     (const void *)k_final_tab<SV_F16>,
+                               (const void *)k_final_gather<16>,       (const void *)k_final_gather_tab<16>,
+                               (const void *)k_final_gather<32>,       (const void *)k_final_gather_tab<32>,
+                               (const void *)k_final_gather<64>,       (const void *)k_final_gather_tab<64>};
         for (const void *fn : fns) {
             hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
             if (e != hipSuccess && err == hipSuccess) err = e;
@@ -531,23 +590,35 @@ sv_status launch_final_gather(const float *T, long long plane, const uint8_t *di
                               hipStream_t s)
 {
     if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    const int th = gather_tile_h(f, (long long)B * H * W);
     int PHm, PWm;
-    fin_window(f, PHm, PWm);
-    dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, FIN_TILE_H), B);
-    hipLaunchKernelGGL(k_final_gather, grid, dim3(FIN_THREADS), gather_lds_bytes(f), s, T, plane, disp,
-                       (float)f / 256.0f, biasF, h, w, H, W, PHm, PWm, out);
+    gather_window(f, th, PHm, PWm);
+    dim3 grid(cdiv(W, FIN_TILE_W), cdiv(H, th), B);
+#define SV_FG(TH)                                                                                         \
+    hipLaunchKernelGGL(k_final_gather<TH>, grid, dim3(FIN_THREADS), gather_lds_bytes(f, th), s, T, plane, disp, \
+                       (float)f / 256.0f, biasF, h, w, H, W, PHm, PWm, out)
+    if (th == 64) SV_FG(64);
+    else if (th == 32) SV_FG(32);
+    else SV_FG(16);
+#undef SV_FG
     SV_LAUNCH_CHECK("k_final_gather");
     return SV_OK;
 }
 
 sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T, long long plane,
-                                  const uint8_t *disp, int f, const float *biasF, hipStream_t s)
+                                  const uint8_t *disp, int f, int th, const float *biasF, hipStream_t s)
 {
     if (sv_status r = fin_allow_lds(); r != SV_OK) return r;
+    if (th != 16 && th != 32 && th != 64) return SV_ERR_RANGE;
     int PHm, PWm;
-    fin_window(f, PHm, PWm);
-    hipLaunchKernelGGL(k_final_gather_tab, dim3(grid), dim3(FIN_THREADS), gather_lds_bytes(f), s, tab, T, plane,
-                       disp, (float)f / 256.0f, biasF, PHm, PWm);
+    gather_window(f, th, PHm, PWm);
+#define SV_FG(TH)                                                                                          \
+    hipLaunchKernelGGL(k_final_gather_tab<TH>, dim3(grid), dim3(FIN_THREADS), gather_lds_bytes(f, th), s, tab, T, \
+                       plane, disp, (float)f / 256.0f, biasF, PHm, PWm)
+    if (th == 64) SV_FG(64);
+    else if (th == 32) SV_FG(32);
+    else SV_FG(16);
+#undef SV_FG
     SV_LAUNCH_CHECK("k_final_gather_tab");
     return SV_OK;
 }

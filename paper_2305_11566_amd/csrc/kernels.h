@@ -228,11 +228,14 @@ sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, i
 // The final layer from precomputed tap projections T (FP32 [9][plane], plane
 // = pixels of the coarse maps; written by G0's epilogue, ConvParams::proj_*):
 // the gather and the residual base of launch_final without the projection.
+// Output rows per tile of the final gather at factor f for a launch over
+// out_px output pixels (tiles are FIN_TILE_W wide): 16, 32 or 64.
+int gather_tile_h(int f, long long out_px);
 sv_status launch_final_gather(const float *T, long long plane, const uint8_t *disp, int f,
                               const float *biasF, int B, int h, int w, int H, int W, float *out,
                               hipStream_t s);
 sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T, long long plane,
-                                  const uint8_t *disp, int f, const float *biasF, hipStream_t s);
+                                  const uint8_t *disp, int f, int th, const float *biasF, hipStream_t s);
 // whether a conv tile configuration can carry the projection epilogue for a
 // layer with cout output channels (one channel tile, all of it in each wave)
 bool conv_cfg_projects(int cfg, int cout);

@@ -99,6 +99,8 @@ __device__ __forceinline__ void census_words4(const CenPatch<TH> &patch, int py,
 
 // The block mean of reduced pixel (i, j), clamped into the reduced image; a
 // block cut by the image edge averages the bytes it holds (round half up).
+// Every load is issued before the sum (a row or column past the edge re-reads
+// the block's first byte and is left out).
 template <int F>
 __device__ __forceinline__ uint32_t block_mean(const uint8_t *__restrict__ img, int H, int W, int pitch,
                                                int h, int w, int i, int j) {
@@ -106,9 +108,16 @@ __device__ __forceinline__ uint32_t block_mean(const uint8_t *__restrict__ img, 
     j = min(max(j, 0), w - 1);
     const int ny = min(F, H - F * i), nx = min(F, W - F * j);
     const uint8_t *src = img + (size_t)(F * i) * pitch + F * j;
+    uint32_t v[F * F];
+#pragma unroll
+    for (int y = 0; y < F; ++y)
+#pragma unroll
+        for (int x = 0; x < F; ++x) v[y * F + x] = src[(y < ny ? (size_t)y * pitch : 0) + (x < nx ? x : 0)];
     uint32_t sum = 0;
-    for (int y = 0; y < ny; ++y)
-        for (int x = 0; x < nx; ++x) sum += src[(size_t)y * pitch + x];
+#pragma unroll
+    for (int y = 0; y < F; ++y)
+#pragma unroll
+        for (int x = 0; x < F; ++x) sum += (y < ny && x < nx) ? v[y * F + x] : 0u;
     const uint32_t n = (uint32_t)(ny * nx);
     return (sum + n / 2) / n;
 }
@@ -247,8 +256,9 @@ __device__ __forceinline__ void census_tile(CenPatch<TH> &patch, const uint8_t *
         reduce_patch<F, TH>(patch, img, H, W, pitch, rx, ry, h, w, i0, j0);
     const int tid = threadIdx.x;
     __syncthreads();
-    if constexpr (RX > 0) {
+    if constexpr (RX > 0 && TH >= 16) {
         // four horizontally adjacent pixels per thread, from aligned words
+        // (short tiles keep one pixel per thread: all four waves busy)
         constexpr int NQ = CEN_TW / 4;
         const int q = tid % NQ, jq = j0 + 4 * q;
         for (int ty = tid / NQ; ty < TH; ty += CEN_THREADS / NQ) {
