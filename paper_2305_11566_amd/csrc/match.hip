@@ -64,18 +64,21 @@ __device__ __forceinline__ uint64_t census_word(const CenPatch<TH> &patch, int p
 }
 
 // The census words of the four pixels at patch (py, c0 + RX .. c0 + RX + 3)
-// for a compile-time window: every window row is read once as the aligned
-// words that hold columns c0 .. c0 + 3 + 2 RX (the patch rows are 4-byte
-// aligned, c0 a multiple of 4), and the bytes are taken from registers.  Bit
-// order and comparison as in census_word.
-template <int TH, int RX, int RY>
-__device__ __forceinline__ void census_words4(const CenPatch<TH> &patch, int py, int c0, uint64_t code[4]) {
+// for a compile-time window, the patch a byte array with rows of `stride`
+// bytes (both the array and stride 4-byte aligned, c0 a multiple of 4):
+// every window row is read once as the aligned words that hold columns
+// c0 .. c0 + 3 + 2 RX, and the bytes are taken from registers.  Bit order and
+// comparison as in census_word.
+template <int RX, int RY>
+__device__ __forceinline__ void census_words4_p(const uint8_t *patch, int stride, int py, int c0,
+                                                uint64_t code[4]) {
     constexpr int NW = (4 + 2 * RX + 3) / 4, NR = 2 * RY + 1;
     uint32_t row[NR][NW];
 #pragma unroll
     for (int r = 0; r < NR; ++r)
 #pragma unroll
-        for (int k = 0; k < NW; ++k) row[r][k] = *(const uint32_t *)&patch[py - RY + r][c0 + 4 * k];
+        for (int k = 0; k < NW; ++k)
+            row[r][k] = *(const uint32_t *)(patch + (size_t)(py - RY + r) * stride + c0 + 4 * k);
 #pragma unroll
     for (int g = 0; g < 4; ++g) {
         const uint32_t c = (row[RY][(g + RX) >> 2] >> (8 * ((g + RX) & 3))) & 0xffu;
@@ -95,6 +98,11 @@ __device__ __forceinline__ void census_words4(const CenPatch<TH> &patch, int py,
             }
         code[g] = ((uint64_t)hi << 32) | lo;
     }
+}
+
+template <int TH, int RX, int RY>
+__device__ __forceinline__ void census_words4(const CenPatch<TH> &patch, int py, int c0, uint64_t code[4]) {
+    census_words4_p<RX, RY>(&patch[0][0], CEN_TW + 2 * CEN_MAXR, py, c0, code);
 }
 
 // The block mean of reduced pixel (i, j), clamped into the reduced image; a
@@ -440,13 +448,16 @@ __device__ __forceinline__ void cost_wta_seg(uint64_t *rseg, const uint64_t *__r
     const int j = j0 + p;
     const uint64_t lv = (j < w) ? cl[j] : 0;
     uint32_t best = 0xffffffffu;
-    const uint32_t sentinel = (uint32_t)(nbits + 1) << 8;
-    for (int d = k; d < D; d += DSPLIT) {
-        // column j - d of the right view sits at rseg[p + D - 1 - d]
-        const uint32_t c = (j - d >= 0) ? ((uint32_t)__popcll(lv ^ rseg[p + D - 1 - d]) << 8)
-                                        : sentinel;
-        best = min(best, c | (uint32_t)d);
-    }
+    // d <= j compares with column j - d, which sits at rseg[p + D - 1 - d];
+    // every d > j costs the sentinel, so of those only the lowest of this
+    // lane's sequence k, k + DSPLIT, ... can win
+    const int dend = min(D, j + 1);
+    const uint64_t *rp = rseg + p + D - 1;
+#pragma unroll 4
+    for (int d = k; d < dend; d += DSPLIT)
+        best = min(best, ((uint32_t)__popcll(lv ^ rp[-d]) << 8) | (uint32_t)d);
+    const int dfirst = k + DSPLIT * ((max(dend - k, 0) + DSPLIT - 1) / DSPLIT);
+    if (dfirst < D) best = min(best, ((uint32_t)(nbits + 1) << 8) | (uint32_t)dfirst);
 #pragma unroll
     for (int m = 1; m < DSPLIT; m <<= 1) best = min(best, (uint32_t)__shfl_xor((int)best, m));
     if (k == 0 && j < w) {
