@@ -133,12 +133,11 @@ sv_status sv_census_pair(const uint8_t *left, const uint8_t *right, int B, int H
 sv_status sv_cost_wta(const uint64_t *cen_l, const uint64_t *cen_r, int B, int h, int w, int D,
                       int nbits, uint8_t *disp_out, void *stream);
 
-/* Split of the cost + WTA sweep for all later calls: 2, 4 or 8 lanes per
- * pixel, each sweeping every 2nd / 4th / 8th d; 1: each lane sweeps all D for
- * four adjacent pixels with the right-view words in registers; or 0 (the
- * default) for the per-shape choice -- the split sv_autotune timed fastest
- * for this (B, h, w, D) in this process, else 4.  The result does not depend
- * on it.  Process-wide, atomic.  Errors: SV_ERR_RANGE. */
+/* Lanes per pixel of the cost + WTA kernel for all later calls: 1, 2, 4 or 8
+ * (lane k of a pixel sweeps d = k, k + split, ...), or 0 (the default) for
+ * the per-shape choice -- the split sv_autotune timed fastest for this
+ * (B, h, w, D) in this process, else 4.  The result does not depend on it.
+ * Process-wide, atomic.  Errors: SV_ERR_RANGE. */
 sv_status sv_set_cost_wta_split(int dsplit);
 
 /* ------------------------------------------------------------------------ */
