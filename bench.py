@@ -834,12 +834,15 @@ def main():
                 flop, sec = 0.0, 0.0
                 layers = {}
                 for st_ in ("census", "cost_wta", "E1", "E2", "E3", "HEAD", "G3", "HEAD+G3", "G2", "G1", "G0",
-                            "final_gather"):
+                            "final_gather", "split_sum"):
                     tot, cnt = profb.get(st_, (0.0, 0))
                     if cnt == 0:
                         continue
                     bound, amount, _ = stage_work(st_, bb, dt)
                     us = tot / cnt * 1e3
+                    if bound is None:  # the split sums of several layers
+                        layers[st_] = {"avg_us": round(us, 2), "launches": cnt}
+                        continue
                     rate = amount / (us * 1e-6)
                     peak = {"mfma": PEAK["mfma_TFLOPs"][dt], "hbm": PEAK["hbm_GBs"],
                             "alu": PEAK["alu_Tops"]}[bound]

@@ -432,9 +432,11 @@ sv_status sv_set_latent_fusion(int on);
  * 2 E1, 3 E2, 4 E3, 5 HEAD (with G3 when fused, see sv_set_latent_fusion),
  * 6 reparameterisation (training), 7 G3, 8 G2,
  * 9 G1, 10 G0, 11 (not recorded: the final layer's projection runs inside
- * stage 12), 12 final layer (projection and gather).
+ * stage 12), 12 final layer (projection and gather), 13 the second pass
+ * (the sum of the partial sums) of every layer that runs a split reduction;
+ * the layer's own stage times its first pass alone.
  * sv_profile_read synchronises on the recorded events, writes the summed
- * milliseconds and launch counts of each stage into ms_sum[13] / counts[13]
+ * milliseconds and launch counts of each stage into ms_sum[14] / counts[14]
  * and restarts the counts.  sv_profile_enable(0) disables and frees.
  * sv_profile_repeat(r) (1..64, default 1; errors: SV_ERR_RANGE): while
  * profiling is on, each recorded stage is launched r times back to back

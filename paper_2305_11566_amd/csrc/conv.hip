@@ -62,6 +62,9 @@ const char *conv_cfg_name(int cfg) {
 }
 
 sv_status launch_conv_f32(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
+sv_status launch_split_sum_f32(const ConvParams &p, hipStream_t st);
+sv_status launch_split_sum_bf16(const ConvParams &p, hipStream_t st);
+sv_status launch_split_sum_f16(const ConvParams &p, hipStream_t st);
 sv_status launch_conv_bf16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 sv_status launch_conv_f16(int ks, int stride, int cfg, const ConvParams &p, int pg, hipStream_t st);
 bool conv_fits_f32(int ks, int stride, int tile);
@@ -158,6 +161,19 @@ sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvPa
     }
     if (ksplit_used) *ksplit_used = p.ksplit > 1 ? p.ksplit : 1;
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, 0, st);
+}
+
+sv_status launch_split_sum(int dtype, const ConvParams &p0, int ksplit, hipStream_t st) {
+    if (ksplit <= 1) return SV_OK;
+    ConvParams p = p0;
+    p.ksplit = ksplit;
+    p.defer_sum = 0;
+    switch (dtype) {
+    case SV_F32: return launch_split_sum_f32(p, st);
+    case SV_BF16: return launch_split_sum_bf16(p, st);
+    case SV_F16: return launch_split_sum_f16(p, st);
+    default: return SV_ERR_DTYPE;  // INT8 never splits
+    }
 }
 
 sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &p0, hipStream_t st) {

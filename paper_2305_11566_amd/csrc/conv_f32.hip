@@ -9,4 +9,6 @@ sv_status launch_conv_f32(int ks, int stride, int cfg, const ConvParams &p, int 
 
 bool conv_fits_f32(int ks, int stride, int tile) { return fits_dt<SV_F32>(ks, stride, tile); }
 
+sv_status launch_split_sum_f32(const ConvParams &p, hipStream_t st) { return launch_reduce<SV_F32>(p, st); }
+
 }  // namespace sv

@@ -979,6 +979,17 @@ __global__ void __launch_bounds__(256) k_conv_split_reduce(const ConvParams p, i
     if (p.amax_out) record_amax(p, lmax, (int)blockIdx.x);
 }
 
+// The second pass of a split reduction over the B Ho Wo output pixels of p.
+template <int DT>
+static sv_status launch_reduce(const ConvParams &p, hipStream_t st) {
+    const int npix = p.B * p.Ho * p.Wo;
+    const long long work = (long long)npix * (p.n_pad / 4);
+    const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_conv_split_reduce<DT>, dim3(blocks), dim3(256), 0, st, p, npix);
+    SV_LAUNCH_CHECK("k_conv_split_reduce");
+    return SV_OK;
+}
+
 // grid <= 0: uniform launch (split over p.ksplit channel ranges when p.ksplit > 1);
 // grid > 0: persistent launch over p.tab.
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
@@ -997,13 +1008,7 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), (unsigned)gz);
     hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
-    if (ksplit > 1 && !p.defer_sum) {
-        const int npix = p.B * p.Ho * p.Wo;
-        const long long work = (long long)npix * (p.n_pad / 4);
-        const int blocks = (int)std::min<long long>((work + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_conv_split_reduce<DT>, dim3(blocks), dim3(256), 0, st, p, npix);
-        SV_LAUNCH_CHECK("k_conv_split_reduce");
-    }
+    if (ksplit > 1 && !p.defer_sum) return launch_reduce<DT>(p, st);
     return SV_OK;
     }
 }

@@ -152,6 +152,9 @@ sv_status launch_conv(int dtype, int ks, int stride, int cfg, const ConvParams &
 // launch_conv that also reports the reduction split it used (1: none)
 sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvParams &p, hipStream_t s,
                             int *ksplit_used);
+// the second pass of a split reduction (ksplit > 1) of a launch made with
+// p.defer_sum set: sums the partials and applies the epilogue; a no-op for 1
+sv_status launch_split_sum(int dtype, const ConvParams &p, int ksplit, hipStream_t s);
 // persistent launch over p.tab's tiles of stage p.stage with `grid` workgroups
 sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvParams &p, int grid,
                           hipStream_t s);

@@ -225,16 +225,37 @@ static ConvParams layer_params(const NetShape &ns, const void *packed, int li, C
     return p;
 }
 
+// A layer's launch; a split reduction leaves its partial sums for the
+// second pass, which the caller runs after the layer's profiling stage
+// (recorded as a stage of its own, see SplitSum).
+struct SplitSum {
+    ConvParams p;
+    int dtype = 0, ksplit = 1;
+};
+
 static sv_status run_layer(const NetShape &ns, const void *packed, int li, ConvSrc s0, ConvSrc s1,
                            int B, int Hi, int Wi, int Ho, int Wo, void *out, int out_pitch,
                            int out_f32, int act, int cfg, float *part, size_t part_bytes,
-                           LayerAmax am, hipStream_t st) {
-    const ConvParams p = layer_params(ns, packed, li, s0, s1, B, Hi, Wi, Ho, Wo, out, out_pitch,
-                                      out_f32, act, part, part_bytes, am);
+                           LayerAmax am, hipStream_t st, SplitSum *ss) {
+    ConvParams p = layer_params(ns, packed, li, s0, s1, B, Hi, Wi, Ho, Wo, out, out_pitch,
+                                out_f32, act, part, part_bytes, am);
+    p.defer_sum = 1;
     const bool tsplit = li == L_F;
     const int ks = tsplit ? 1 : ns.ly[li].k;
     const int stride = tsplit ? 1 : ns.ly[li].stride;
-    return launch_conv(tsplit ? SV_F32 : ns.dtype, ks, stride, cfg, p, st);
+    ss->p = p;
+    ss->dtype = tsplit ? SV_F32 : ns.dtype;
+    return launch_conv_split(ss->dtype, ks, stride, cfg, p, st, &ss->ksplit);
+}
+
+// The second pass of a split layer, as profiling stage PROF_SPLIT.
+static sv_status run_split_sum(const SplitSum &ss, hipStream_t st) {
+    if (ss.ksplit <= 1) return SV_OK;
+    prof_mark(PROF_SPLIT, 0, st);
+    sv_status r = SV_OK;
+    for (int rep = prof_repeat(); rep > 0 && r == SV_OK; --rep) r = launch_split_sum(ss.dtype, ss.p, ss.ksplit, st);
+    prof_mark(PROF_SPLIT, 1, st);
+    return r;
 }
 
 // 1: an inference pass runs the head and G3 as one kernel where the shapes allow
@@ -248,6 +269,15 @@ static sv_status run_layer_if(int only, const NetShape &ns, const void *packed, 
     if (only >= 0 && only != li) return SV_OK;
     return run_layer(ns, packed, li, args...);
 }
+// a layer (profiling stage ev) and then its split sum (stage PROF_SPLIT)
+#define SV_LAYER(ev, li, ...)                                                     \
+    do {                                                                          \
+        SplitSum ss_;                                                             \
+        ev_rec(ev, 0, st);                                                        \
+        SV_STAGE(run_layer_if(only, ns, packed, li, __VA_ARGS__, st, &ss_));      \
+        ev_rec(ev, 1, st);                                                        \
+        if (only < 0 || only == li) SV_TRY(run_split_sum(ss_, st));               \
+    } while (0)
 
 // launch i of the forward pass is profiling stage PROF_E1 + i
 static inline void ev_rec(int i, int which, hipStream_t st) { prof_mark(PROF_E1 + i, which, st); }
@@ -305,34 +335,33 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     // encoder; E1 reads the two x0 channels only: a direct stencil (INT8 keeps
     // the quantised convolution its codes are defined on)
     ev_rec(0, 0, st);
-    if (q8)
-        SV_STAGE(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1, cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st));
-    else if (only < 0 || only == L_E1)
+    if (q8) {
+        SplitSum ss0;  // (INT8 never splits)
+        SV_STAGE(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1,
+                              cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st, &ss0));
+    } else if (only < 0 || only == L_E1)
         SV_STAGE(launch_enc1(ns.dtype, disp, img, (float)ns.f / 256.0f, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], c1,
                            (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
                            (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st));
     ev_rec(0, 1, st);
-    ev_rec(1, 0, st);
-    SV_STAGE(run_layer_if(only, ns, packed, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B,
-                     lv.h[1], lv.w[1], lv.h[2], lv.w[2], E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2), st));
-    ev_rec(1, 1, st);
+    SV_LAYER(1, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B, lv.h[1], lv.w[1], lv.h[2], lv.w[2],
+             E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2));
     // inference: the head and G3 run as one kernel, which also finishes E3's
     // split sum when E3 runs split (E3 is then never stored)
     const bool fuse_latent = only < 0 && !eps && !train && g_latent_fusion.load() && latent_fusable(ns.dtype, c3, L);
     int e3split = 1;
-    ev_rec(2, 0, st);
     if (fuse_latent) {
         ConvParams p3 = layer_params(ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
                                      lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, part, a.part_bytes,
                                      LayerAmax{});
         p3.defer_sum = 1;
+        ev_rec(2, 0, st);
         SV_STAGE(launch_conv_split(ns.dtype, ns.ly[L_E3].k, ns.ly[L_E3].stride, cfg[L_E3], p3, st, &e3split));
+        ev_rec(2, 1, st);
     } else {
-        SV_STAGE(run_layer_if(only, ns, packed, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B,
-                            lv.h[2], lv.w[2], lv.h[3], lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes,
-                            am(AM_E2, -1, AM_E3), st));
+        SV_LAYER(2, L_E3, src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), none, B, lv.h[2], lv.w[2], lv.h[3],
+                 lv.w[3], E3, c3, 0, 1, cfg[L_E3], part, a.part_bytes, am(AM_E2, -1, AM_E3));
     }
-    ev_rec(2, 1, st);
     // latent head -> [mu | logvar] in FP32
     const ConvSrc e3src = src_tensor(E3, c3, c3, 0, lv.h[3], lv.w[3], 0);
     const ConvSrc musrc = src_tensor(ML, L, 2 * L, 0, lv.h[3], lv.w[3], SDT_F32);  // z = mu
@@ -348,10 +377,8 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
         SV_STAGE(launch_latent(ns.dtype, ph, pg, B * h3 * w3, part, e3split, e3bias, st));
         ev_rec(3, 1, st);
     } else {
-        ev_rec(3, 0, st);
-        SV_STAGE(run_layer_if(only, ns, packed, L_HEAD, e3src, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3],
-                            ML, 2 * L, 1, 0, cfg[L_HEAD], part, a.part_bytes, am(AM_E3, -1, AM_ML), st));
-        ev_rec(3, 1, st);
+        SV_LAYER(3, L_HEAD, e3src, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], ML, 2 * L, 1, 0, cfg[L_HEAD],
+                 part, a.part_bytes, am(AM_E3, -1, AM_ML));
         ConvSrc zsrc = musrc;
         if (eps) {
             ev_rec(4, 0, st);
@@ -360,29 +387,23 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
             zsrc = src_tensor(Z, L, L, 0, lv.h[3], lv.w[3], 0);
         }
         // decoder
-        ev_rec(5, 0, st);
-        SV_STAGE(run_layer_if(only, ns, packed, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3,
-                            c3, 0, 1, cfg[L_G3], part, a.part_bytes, am(AM_ML, -1, AM_G3), st));
-        ev_rec(5, 1, st);
+        SV_LAYER(5, L_G3, zsrc, none, B, lv.h[3], lv.w[3], lv.h[3], lv.w[3], G3, c3, 0, 1, cfg[L_G3], part,
+                 a.part_bytes, am(AM_ML, -1, AM_G3));
     }
-    ev_rec(6, 0, st);
-    SV_STAGE(run_layer_if(only, ns, packed, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]),
-                     src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B, lv.h[2], lv.w[2], lv.h[2],
-                     lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes, am(AM_G3, AM_E2, AM_G2), st));
-    ev_rec(6, 1, st);
-    ev_rec(7, 0, st);
-    SV_STAGE(run_layer_if(only, ns, packed, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]),
-                     src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B, lv.h[1], lv.w[1], lv.h[1],
-                     lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes, am(AM_G2, AM_E1, AM_G1), st));
-    ev_rec(7, 1, st);
+    SV_LAYER(6, L_G2, src_resize(G3, c3, lv.h[3], lv.w[3]), src_tensor(E2, c2, c2, 0, lv.h[2], lv.w[2], 0), B,
+             lv.h[2], lv.w[2], lv.h[2], lv.w[2], G2, c2, 0, 1, cfg[L_G2], part, a.part_bytes,
+             am(AM_G3, AM_E2, AM_G2));
+    SV_LAYER(7, L_G1, src_resize(G2, c2, lv.h[2], lv.w[2]), src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), B,
+             lv.h[1], lv.w[1], lv.h[1], lv.w[1], G1, c1, 0, 1, cfg[L_G1], part, a.part_bytes,
+             am(AM_G2, AM_E1, AM_G1));
     // G0; at inference its epilogue writes the final layer's nine per-tap
     // projections of [G0, x0] (FP32) in place of the map, and the final layer
     // is the gather alone
     const bool proj = net_projects(ns, train);
     const float *wF = (const float *)((const char *)packed + ns.w_off[L_F]);
     const long long plane0 = (long long)B * lv.h[0] * lv.w[0];
-    ev_rec(8, 0, st);
     if (proj) {
+        ev_rec(8, 0, st);
         if (only < 0 || only == L_G0) {
             ConvParams p = layer_params(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
                                         lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, part, a.part_bytes, LayerAmax{});
@@ -395,12 +416,11 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
             p.proj_scale0 = (float)ns.f / 256.0f;
             SV_STAGE(launch_conv(ns.dtype, 3, 1, net_g0_proj_cfg(ns, cfg[L_G0]), p, st));
         }
+        ev_rec(8, 1, st);
     } else {
-        SV_STAGE(run_layer_if(only, ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                            lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, cfg[L_G0], part, a.part_bytes,
-                            am(AM_G1, AM_X0, -1), st));
+        SV_LAYER(8, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0], lv.w[0], lv.h[0], lv.w[0], G0, c1,
+                 0, 1, cfg[L_G0], part, a.part_bytes, am(AM_G1, AM_X0, -1));
     }
-    ev_rec(8, 1, st);
     // final layer: the gather of the projections (inference), or projections
     // of the stored [G0, x0] and the gather in one kernel
     const float *biasF = (const float *)((const char *)packed + ns.b_off[L_F]);

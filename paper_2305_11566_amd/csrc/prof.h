@@ -7,7 +7,7 @@ namespace sv {
 
 enum ProfStage {
     PROF_CENSUS = 0, PROF_COST_WTA, PROF_E1, PROF_E2, PROF_E3, PROF_HEAD, PROF_REPARAM, PROF_G3,
-    PROF_G2, PROF_G1, PROF_G0, PROF_FPROJ, PROF_FINAL, PROF_NSTAGES
+    PROF_G2, PROF_G1, PROF_G0, PROF_FPROJ, PROF_FINAL, PROF_SPLIT, PROF_NSTAGES
 };
 
 // Records the start (which = 0) or end (1) event of `stage` on `st` when

@@ -350,7 +350,7 @@ def sv_profile_repeat(repeat: int):
 
 
 PROFILE_STAGES = ("census", "cost_wta", "E1", "E2", "E3", "HEAD", "reparam", "G3", "G2", "G1",
-                  "G0", "final_proj", "final_gather")
+                  "G0", "final_proj", "final_gather", "split_sum")
 
 
 def sv_profile_read():
