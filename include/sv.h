@@ -392,6 +392,37 @@ sv_status sv_stereo_batch(sv_batch_plan *plan, const sv_pair *pairs, int n, cons
                           void *stream);
 
 /*
+ * The paper's whole system on n pairs of uneven sizes (Sec. III, Sec. IV-A):
+ * per pair, in pair order on `stream`, the reduction of both views
+ * (sv_census_pair), the coarse matcher -- ZNCC + SGM (sv_zncc_sgm, Eqs.
+ * (1)-(6), the paper's main one) or census + SGM (sv_sgm) --, when `median`
+ * is 1 the single matching phase and 3 x 3 median (sv_smp_median, Eq. (7)),
+ * and the Table I network (sv_tvae_forward, inference) writing pair.out.
+ * The coarse map goes to pair.disp_low when it is non-NULL.  Results are
+ * bitwise those of the per-pair calls.  No allocation and no host wait:
+ * a call can be captured in a hipGraph and replayed.  The pairs reuse one
+ * workspace (device, 256-byte aligned) of sv_paper_batch_workspace_bytes for
+ * the largest pair (0 on invalid arguments).  Every argument and pair is
+ * checked before the first launch.
+ * Errors: SV_ERR_NULL, SV_ERR_SHAPE, SV_ERR_RANGE (factor, window, penalties
+ * as sv_sgm / sv_zncc_sgm, D), SV_ERR_DTYPE, SV_ERR_UNSUPPORTED (a ZNCC
+ * window without a kernel), SV_ERR_WORKSPACE.
+ */
+#define SV_MATCH_ZNCC_SGM 0
+#define SV_MATCH_CENSUS_SGM 1
+typedef struct sv_paper_desc {
+    int32_t matcher;        /* SV_MATCH_ZNCC_SGM or SV_MATCH_CENSUS_SGM */
+    int32_t factor;         /* reduction factor, 1..8 */
+    int32_t win_w, win_h;   /* census / ZNCC window (odd) */
+    int32_t P1, P2;         /* SGM penalties */
+    int32_t median;         /* 1: single matching phase + 3 x 3 median; 0: the SGM map as it is */
+    int32_t dtype;          /* Table I network compute dtype: SV_F32, SV_BF16, SV_F16 */
+} sv_paper_desc;
+size_t sv_paper_batch_workspace_bytes(const sv_paper_desc *desc, int max_H, int max_W, int max_D);
+sv_status sv_paper_batch(const sv_paper_desc *desc, const sv_pair *pairs, int n, const void *packed_w,
+                         void *workspace, size_t ws_bytes, void *stream);
+
+/*
  * Time the candidate configurations of every stage for this desc and shape
  * on the current device and store the fastest in the autotune cache (a text
  * file at $SV_AUTOTUNE_CACHE, default ~/.cache/sv_autotune.tsv, one line per

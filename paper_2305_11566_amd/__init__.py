@@ -25,6 +25,7 @@ from .ops import (  # noqa: F401
     sv_profile_read,
     PROFILE_STAGES,
     BatchPlan,
+    PaperBatch,
     sv_autotune,
     sv_tile_config,
     sv_layer_cfgs,

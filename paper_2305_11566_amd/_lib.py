@@ -35,6 +35,12 @@ class VaeDesc(ctypes.Structure):
                 ("latent", ctypes.c_int32), ("factor", ctypes.c_int32), ("dtype", ctypes.c_int32)]
 
 
+class PaperDesc(ctypes.Structure):
+    _fields_ = [("matcher", ctypes.c_int32), ("factor", ctypes.c_int32), ("win_w", ctypes.c_int32),
+                ("win_h", ctypes.c_int32), ("P1", ctypes.c_int32), ("P2", ctypes.c_int32),
+                ("median", ctypes.c_int32), ("dtype", ctypes.c_int32)]
+
+
 class Pair(ctypes.Structure):
     _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("out", ctypes.c_void_p),
                 ("disp_low", ctypes.c_void_p), ("H", ctypes.c_int32), ("W", ctypes.c_int32),
@@ -81,6 +87,8 @@ _SIGS = {
     "sv_stereo_batch": (ctypes.c_int32, [_P, ctypes.POINTER(Pair), _I, _P, _P]),
     "sv_autotune": (ctypes.c_int32, [_DESC, _I, _I, _I, _I, _I, _I]),
     "sv_tile_config": (ctypes.c_int32, [_I, ctypes.c_char_p, _I]),
+    "sv_paper_batch_workspace_bytes": (ctypes.c_size_t, [_P, _I, _I, _I]),
+    "sv_paper_batch": (ctypes.c_int32, [_P, _P, _I, _P, _P, ctypes.c_size_t, _P]),
     "sv_profile_enable": (ctypes.c_int32, [_I]),
     "sv_profile_repeat": (ctypes.c_int32, [_I]),
     "sv_layer_cfgs": (ctypes.c_int32, [_DESC, _I, _I, _I, ctypes.POINTER(ctypes.c_int)]),

@@ -49,6 +49,8 @@ sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int th
                                    hipStream_t s);
 // census tile height (4 or 16 reduced rows) for a uniform launch of B images
 int census_tile_height(int B, int h, int w);
+// The windows the ZNCC cost kernel is instantiated for.
+bool zncc_window_supported(int win_w, int win_h);
 size_t sgm_volume_bytes(int B, int h, int w, int D);
 sv_status launch_sgm(const uint64_t *cl, const uint64_t *cr, int B, int h, int w, int D, int nbits,
                      int P1, int P2, uint8_t *vol, uint8_t *disp, hipStream_t s);

@@ -466,6 +466,13 @@ k_zncc_cost(const uint8_t *__restrict__ ll, const uint8_t *__restrict__ lr, int 
     }
 }
 
+bool zncc_window_supported(int win_w, int win_h) {
+    const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
+    if (win_w % 2 == 0 || win_h % 2 == 0) return false;
+    return (rx == 1 && ry == 1) || (rx == 2 && ry == 2) || (rx == 3 && ry == 3) || (rx == 4 && ry == 3) ||
+           (rx == 3 && ry == 4) || (rx == 4 && ry == 4) || (rx == 2 && ry == 1) || (rx == 1 && ry == 2);
+}
+
 sv_status launch_zncc_cost(const uint8_t *ll, const uint8_t *lr, int B, int h, int w, int D, int Dp,
                            int win_w, int win_h, uint8_t *cost, hipStream_t s)
 {

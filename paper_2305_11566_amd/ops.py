@@ -452,6 +452,55 @@ class BatchPlan:
             pass
 
 
+class PaperBatch:
+    """sv_paper_batch: the paper's whole system (reduction, ZNCC + SGM or census
+    + SGM, single matching phase + median, Table I network) on pairs of uneven
+    sizes, one launch sequence per call on the current stream (capturable in
+    one graph); the workspace is sized for the largest pair."""
+
+    MATCHERS = {"zncc": 0, "census": 1}
+
+    def __init__(self, matcher, factor, win_w, win_h, P1, P2, dtype="f32", median=True, max_H=384, max_W=1280,
+                 max_D=80, device="cuda"):
+        from ._lib import PaperDesc
+        if matcher not in self.MATCHERS or dtype not in DTYPES:
+            raise ValueError(f"matcher in {list(self.MATCHERS)}, dtype in {list(DTYPES)}")
+        self.desc = PaperDesc(self.MATCHERS[matcher], factor, win_w, win_h, P1, P2, 1 if median else 0,
+                              DTYPES[dtype])
+        self.factor = factor
+        n = lib().sv_paper_batch_workspace_bytes(ctypes.byref(self.desc), max_H, max_W, max_D)
+        if n == 0:
+            raise ValueError("invalid matcher settings or sizes")
+        self.workspace = _aligned_bytes(n, torch.device(device))
+
+    def run(self, pairs, packed, outs=None, disp_outs=None):
+        """pairs: list of (left uint8 [H,W], right uint8 [H,W], D); packed: the
+        Table I network's packed weights (TableVAE.packed).  Returns the
+        network's outputs (float32 [H,W] each, full-res px)."""
+        from ._lib import Pair
+        n = len(pairs)
+        arr = (Pair * n)()
+        if outs is None:
+            outs = [torch.empty(l.shape, dtype=torch.float32, device=l.device) for l, _, _ in pairs]
+        if len(outs) != n or (disp_outs is not None and len(disp_outs) != n):
+            raise ValueError("one output (and coarse map) per pair")
+        for i, (l, r, D) in enumerate(pairs):
+            _need(l, torch.uint8, "left")
+            if l.dim() != 2:
+                raise ValueError("left must be [H, W]")
+            H, W = l.shape
+            _need(r, torch.uint8, "right", (H, W), l.device)
+            _need(outs[i], torch.float32, "out", (H, W), l.device)
+            dl = disp_outs[i] if disp_outs is not None else None
+            if dl is not None:
+                _need(dl, torch.uint8, "disp_out", (_cdiv(H, self.factor), _cdiv(W, self.factor)), l.device)
+            arr[i] = Pair(l.data_ptr(), r.data_ptr(), outs[i].data_ptr(),
+                          dl.data_ptr() if dl is not None else None, H, W, D)
+        check(lib().sv_paper_batch(ctypes.byref(self.desc), arr, n, ptr(packed), ptr(self.workspace),
+                                   self.workspace.numel(), stream_ptr()), "sv_paper_batch")
+        return outs
+
+
 def sv_autotune(c1, c2, c3, latent, factor, dtype, B, H, W, D, win_w, win_h):
     d = make_desc(c1, c2, c3, latent, factor, dtype)
     check(lib().sv_autotune(ctypes.byref(d), B, H, W, D, win_w, win_h), "sv_autotune")

@@ -173,6 +173,31 @@ def test_latent_fusion_switch():
     assert lib().sv_set_latent_fusion(1) == 0
 
 
+def test_paper_batch_validation():
+    """sv_paper_batch checks its settings and every pair before any launch
+    (dummy device pointers: nothing is dereferenced)."""
+    from paper_2305_11566_amd._lib import PaperDesc, Pair
+    ok = PaperDesc(0, 2, 5, 5, 10, 120, 1, 0)
+    need = lib().sv_paper_batch_workspace_bytes(ctypes.byref(ok), 128, 256, 16)
+    assert need > 0
+    assert lib().sv_paper_batch_workspace_bytes(ctypes.byref(PaperDesc(2, 2, 5, 5, 10, 120, 1, 0)), 128, 256, 16) == 0
+    dummy, ws = 0x10000, 0x20000
+    pairs = (Pair * 1)(Pair(dummy, dummy, dummy, None, 128, 256, 16))
+    call = lambda d, pr=pairs, n=1, w=ws, nb=need: lib().sv_paper_batch(ctypes.byref(d), pr, n, dummy, w, nb, None)
+    assert call(PaperDesc(2, 2, 5, 5, 10, 120, 1, 0)) == -3           # matcher
+    assert call(PaperDesc(0, 9, 5, 5, 10, 120, 1, 0)) == -3           # factor
+    assert call(PaperDesc(0, 2, 5, 5, 10, 200, 1, 0)) == -3           # ZNCC: 64 + P2 > 255
+    assert call(PaperDesc(1, 2, 5, 5, 10, 240, 1, 0)) == -3           # census: nbits + 1 + P2 > 255
+    assert call(PaperDesc(0, 2, 5, 5, 20, 10, 1, 0)) == -3            # P2 < P1
+    assert call(PaperDesc(0, 2, 7, 5, 10, 120, 1, 0)) == -6           # no ZNCC kernel for 7x5
+    assert call(PaperDesc(0, 2, 5, 5, 10, 120, 1, 3)) == -4           # INT8 network not offered
+    assert lib().sv_paper_batch(ctypes.byref(ok), None, 1, dummy, ws, need, None) == -1
+    assert call(ok, pr=(Pair * 1)(Pair(dummy, dummy, dummy, None, 0, 256, 16))) == -2
+    assert call(ok, pr=(Pair * 1)(Pair(dummy, dummy, dummy, None, 128, 256, 300))) == -2
+    assert call(ok, pr=(Pair * 1)(Pair(dummy, dummy, dummy, None, 256, 512, 16))) == -5   # larger than sized for
+    assert call(ok, w=ws + 16) == -3                                   # misaligned workspace
+
+
 def test_profile_repeat_range():
     assert lib().sv_profile_repeat(0) == -3
     assert lib().sv_profile_repeat(65) == -3
