@@ -4,7 +4,9 @@
 // [mu | logvar] = 1x1 convolution of E3, then G3 = leaky ReLU of a 1x1
 // convolution of mu.  Both layers are pointwise in the pixels, so one
 // workgroup owns 16 pixels of the coarsest level for both: E3's channels, and
-// then mu, sit in LDS, and each wave takes 16-channel output blocks.  The
+// then mu, sit in LDS, and each wave takes 16-channel output blocks (with few
+// pixels, two workgroups share the 16: one computes mu and G3, the other
+// logvar, halving the longest chain of blocks a wave runs).  The
 // reduction runs over the input channels in base chunks in ascending order
 // with the same MFMA steps as the unsplit convolution kernel, and the values
 // go through the same epilogue and the same conversion into the compute dtype,
@@ -20,7 +22,7 @@ constexpr int LAT_MAXC = 256;  // most channels of E3 and of mu held in LDS
 template <int DT>
 __global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, const ConvParams pg, int npix,
                                                         const float *__restrict__ e3part, int e3split,
-                                                        const float *__restrict__ e3bias)
+                                                        const float *__restrict__ e3bias, int roles)
 {
     using M = Mfma<DT>;
     using T = typename M::T;
@@ -33,7 +35,11 @@ __global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, con
     __shared__ __attribute__((aligned(16))) T zs[LAT_PX * KP];  // mu of the pixels
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int p0 = blockIdx.x * LAT_PX, pix = p0 + r16;
+    // few pixels (small batches): two workgroups per 16 pixels, role 0
+    // computing mu and then G3, role 1 logvar, so that each wave's chain
+    // holds at most two output blocks; else one workgroup does all (role -1)
+    const int role = roles == 2 ? (int)(blockIdx.x & 1) : -1;
+    const int p0 = (roles == 2 ? blockIdx.x >> 1 : blockIdx.x) * LAT_PX, pix = p0 + r16;
     const int c3 = ph.Cin, L = pg.Cin;
 
     // E3 -> LDS; pixels past npix are zero and their results are not stored.
@@ -87,8 +93,8 @@ __global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, con
     // head: output block blk of 16 channels of [mu | logvar]
     {
         const T *w = (const T *)ph.wpk;
-        const int nblk = ph.n_pad / 16, nkb = c3 / KCB;
-        for (int blk = wave; blk < nblk; blk += NWAVE) {
+        const int nblk = ph.n_pad / 16, nkb = c3 / KCB, nmu = L / 16;
+        for (int blk = wave + (role == 1 ? nmu : 0); blk < (role == 0 ? nmu : nblk); blk += NWAVE) {
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
             const T *wr = w + (size_t)(blk * 16 + r16) * ph.cin_pad + g * GS;
             const T *xr = xs + r16 * KP + g * GS;
@@ -106,6 +112,7 @@ __global__ void __launch_bounds__(LAT_THREADS) k_latent(const ConvParams ph, con
                 if (nbase + i < L) zs[r16 * KP + nbase + i] = Elem<DT>::make(r[i] + bias[i]);
         }
     }
+    if (role == 1) return;
     __syncthreads();
 
     // G3: output block blk of 16 channels
@@ -146,11 +153,13 @@ sv_status launch_latent(int dtype, const ConvParams &ph, const ConvParams &pg, i
         e3split > CONV_MAX_SPLIT || (e3split > 1 && (!e3part || !e3bias)))
         return SV_ERR_UNSUPPORTED;
     if (npix <= 0) return SV_OK;
-    const dim3 grid((unsigned)cdiv(npix, LAT_PX));
+    const int groups = cdiv(npix, LAT_PX);
+    const int roles = groups < 256 ? 2 : 1;  // two roles while the groups leave CUs idle
+    const dim3 grid((unsigned)(roles * groups));
     switch (dtype) {
-    case SV_F32: hipLaunchKernelGGL(k_latent<SV_F32>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
-    case SV_BF16: hipLaunchKernelGGL(k_latent<SV_BF16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
-    default: hipLaunchKernelGGL(k_latent<SV_F16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias); break;
+    case SV_F32: hipLaunchKernelGGL(k_latent<SV_F32>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias, roles); break;
+    case SV_BF16: hipLaunchKernelGGL(k_latent<SV_BF16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias, roles); break;
+    default: hipLaunchKernelGGL(k_latent<SV_F16>, grid, dim3(LAT_THREADS), 0, st, ph, pg, npix, e3part, e3split, e3bias, roles); break;
     }
     SV_LAUNCH_CHECK("k_latent");
     return SV_OK;

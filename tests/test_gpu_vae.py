@@ -186,6 +186,7 @@ def test_tile_configs_bitwise_identical(dtype):
 @pytest.mark.parametrize("dtype", ["f32", "bf16", "f16"])
 @pytest.mark.parametrize("C,L,f,H,W,B", [
     ((32, 64, 128), 128, 4, 375, 1242, 1),  # full size: 468 latent pixels, a tail of 4 past 16s
+    ((32, 64, 128), 128, 4, 375, 1242, 9),  # 4212 latent pixels: one workgroup per 16 pixels (not two roles)
     ((16, 32, 64), 64, 2, 128, 256, 2),     # 256x128 widths, two images
     ((32, 64, 96), 32, 2, 50, 90, 3),       # 96 / 32 channels, 7x12 latent grids
     ((16, 24, 48), 16, 2, 30, 40, 1),       # FP32 fused; L = 16 is not a whole 16-bit chunk: two launches
