@@ -25,7 +25,8 @@
     X(12, 2, 64, 2, 2, "th2_tn64_k2")      \
     X(13, 4, 16, 4, 8, "th4_tn16_k8")      \
     X(14, 2, 32, 2, 4, "th2_tn32_k4")      \
-    X(15, 4, 32, 4, 4, "th4_tn32_k4")
+    X(15, 4, 32, 4, 4, "th4_tn32_k4")      \
+    X(16, 16, 32, 4, 1, "th16_tn32")
 
 namespace sv {
 
@@ -288,43 +289,102 @@ struct ConvTile {
         float ly, lx;
     };
 
+    // One axis of the table: the source row (column) pair and weight of each
+    // patch row (column); i0 < 0 outside the input grid or on an inserted zero.
+    struct AxSrc {
+        int i0, i1;
+        float lam;
+    };
+
     struct Smem {
         T patch[NPIX * KCP];
         T wl[TAPS * TN * KCP];
         PixSrc ps[2][NPIX];
+        AxSrc ax[2][PH + PW];
     };
     // tiles whose LDS exceeds a CU's 160 KB are never instantiated (conv_fits)
     static constexpr bool FITS = sizeof(Smem) <= 160 * 1024;
 
-    // Computed once per tile; every channel chunk reuses it.
+    // Computed once per tile; every channel chunk reuses it.  A resized
+    // source's index and weight along y depend on the patch row only and along
+    // x on the patch column only, so on tiles with more table entries than
+    // threads the PH + PW axis entries (with the resize's divisions) are formed
+    // first and each pixel combines one of each; otherwise (and for sources
+    // read in place, whose entries cost no division) every entry is formed
+    // directly, without the second LDS round trip.
     static __device__ __forceinline__ void pix_table(const ConvParams &p, const ConvGeo &G, Smem &sm) {
         const int iy0 = G.oy0 * S - PAD, ix0 = G.ox0 * S - PAD;
-        for (int e = threadIdx.x; e < 2 * NPIX; e += 256) {
-            const int si = e >= NPIX ? 1 : 0, pix = e - si * NPIX;
-            const int py = pix / PW, px = pix - py * PW;
-            const int yi = iy0 + py, xi = ix0 + px;
-            const int kind = si ? p.src[1].kind : p.src[0].kind;
-            PixSrc q;
-            q.p[0] = q.p[1] = q.p[2] = q.p[3] = -1;
-            q.ly = q.lx = 0.f;
-            if (kind != SRC_NONE && yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi) {
-                const long long sb = si ? G.sbase[1] : G.sbase[0];
-                const int hs = si ? G.hs[1] : G.hs[0], ws = si ? G.ws[1] : G.ws[0];
-                if (kind == SRC_RESIZE) {
-                    int y0, y1, x0, x1;
-                    bilin(yi, hs, G.Hi, y0, y1, q.ly);
-                    bilin(xi, ws, G.Wi, x0, x1, q.lx);
-                    q.p[0] = (int)(sb + (long long)y0 * ws + x0);
-                    q.p[1] = (int)(sb + (long long)y0 * ws + x1);
-                    q.p[2] = (int)(sb + (long long)y1 * ws + x0);
-                    q.p[3] = (int)(sb + (long long)y1 * ws + x1);
-                } else if (kind == SRC_ZINS) {
-                    if (((yi | xi) & 1) == 0) q.p[0] = (int)(sb + (long long)(yi >> 1) * ws + (xi >> 1));
-                } else {
-                    q.p[0] = (int)(sb + (long long)yi * ws + xi);
+        const bool sep = 2 * NPIX > 256 && (p.src[0].kind == SRC_RESIZE || p.src[1].kind == SRC_RESIZE);
+        if (!sep) {
+            for (int e = threadIdx.x; e < 2 * NPIX; e += 256) {
+                const int si = e >= NPIX ? 1 : 0, pix = e - si * NPIX;
+                const int py = pix / PW, px = pix - py * PW;
+                const int yi = iy0 + py, xi = ix0 + px;
+                const int kind = si ? p.src[1].kind : p.src[0].kind;
+                PixSrc q;
+                q.p[0] = q.p[1] = q.p[2] = q.p[3] = -1;
+                q.ly = q.lx = 0.f;
+                if (kind != SRC_NONE && yi >= 0 && yi < G.Hi && xi >= 0 && xi < G.Wi) {
+                    // a pixel index of the batch fits an int (as the table stores it)
+                    const int sb = (int)(si ? G.sbase[1] : G.sbase[0]);
+                    const int hs = si ? G.hs[1] : G.hs[0], ws = si ? G.ws[1] : G.ws[0];
+                    if (kind == SRC_RESIZE) {
+                        int y0, y1, x0, x1;
+                        bilin(yi, hs, G.Hi, y0, y1, q.ly);
+                        bilin(xi, ws, G.Wi, x0, x1, q.lx);
+                        q.p[0] = sb + y0 * ws + x0;
+                        q.p[1] = sb + y0 * ws + x1;
+                        q.p[2] = sb + y1 * ws + x0;
+                        q.p[3] = sb + y1 * ws + x1;
+                    } else if (kind == SRC_ZINS) {
+                        if (((yi | xi) & 1) == 0) q.p[0] = q.p[1] = q.p[2] = q.p[3] = sb + (yi >> 1) * ws + (xi >> 1);
+                    } else {
+                        q.p[0] = q.p[1] = q.p[2] = q.p[3] = sb + yi * ws + xi;
+                    }
                 }
+                sm.ps[si][pix] = q;
             }
-            sm.ps[si][pix] = q;
+        } else {
+            for (int e = threadIdx.x; e < 2 * (PH + PW); e += 256) {
+                const int si = e >= PH + PW ? 1 : 0, j = e - si * (PH + PW);
+                const bool row = j < PH;
+                const int o = row ? iy0 + j : ix0 + (j - PH);
+                const int n = row ? G.Hi : G.Wi;
+                // one level of selection per value (a nested one would index G in memory)
+                const int hsi = si ? G.hs[1] : G.hs[0], wsi = si ? G.ws[1] : G.ws[0];
+                const int nin = row ? hsi : wsi;
+                const int kind = si ? p.src[1].kind : p.src[0].kind;
+                AxSrc a;
+                a.i0 = a.i1 = -1;
+                a.lam = 0.f;
+                if (kind != SRC_NONE && o >= 0 && o < n) {
+                    if (kind == SRC_RESIZE) bilin(o, nin, n, a.i0, a.i1, a.lam);
+                    else if (kind == SRC_ZINS) a.i0 = a.i1 = (o & 1) == 0 ? o >> 1 : -1;
+                    else a.i0 = a.i1 = o;
+                }
+                sm.ax[si][j] = a;
+            }
+            __syncthreads();
+            for (int e = threadIdx.x; e < 2 * NPIX; e += 256) {
+                const int si = e >= NPIX ? 1 : 0, pix = e - si * NPIX;
+                const int py = pix / PW, px = pix - py * PW;
+                const AxSrc ay = sm.ax[si][py], ax = sm.ax[si][PH + px];
+                PixSrc q;
+                q.p[0] = q.p[1] = q.p[2] = q.p[3] = -1;
+                q.ly = q.lx = 0.f;
+                if (ay.i0 >= 0 && ax.i0 >= 0) {
+                    const int sb = (int)(si ? G.sbase[1] : G.sbase[0]);
+                    const int ws = si ? G.ws[1] : G.ws[0];
+                    const int r0 = sb + ay.i0 * ws, r1 = sb + ay.i1 * ws;
+                    q.p[0] = r0 + ax.i0;
+                    q.p[1] = r0 + ax.i1;
+                    q.p[2] = r1 + ax.i0;
+                    q.p[3] = r1 + ax.i1;
+                    q.ly = ay.lam;
+                    q.lx = ax.lam;
+                }
+                sm.ps[si][pix] = q;
+            }
         }
     }
 
