@@ -273,7 +273,12 @@ k_final_tab(const PairTable *__restrict__ tab, const typename Elem<DT>::T *__res
     const int *cum = tab->cum[BS_FINAL];
     const int total = cum[n];
     const float bias = biasF[0];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // round k takes tiles k G .. k G + G - 1 (G = gridDim.x); hardware id i
+    // takes tile (i % 8) (G / 8) + i / 8 of the round, so that each XCD covers
+    // a contiguous run of tiles (workgroups go round robin to the XCDs)
+    const int G = (int)gridDim.x, q8 = G / 8, hw = (int)blockIdx.x;
+    const int lid = hw < 8 * q8 ? (hw % 8) * q8 + hw / 8 : hw;
+    for (int t = lid; t < total; t += G) {
         const int i = table_find(cum, n, t);
         const PairGeo &g = tab->pair[i];
         const int local = t - cum[i];
@@ -324,33 +329,40 @@ struct GatherTab {
 
 typedef float f32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
+// The coarse window [ya, ya + ph) x [xa, xa + pw) that the tile at (X0, Y0)
+// reads (its 3 x 3 neighbourhood reaches one output pixel past each edge).
+struct GatherWin {
+    int xa, ya, pw, ph;
+};
+
 template <int TH>
-__device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int PHm, int PWm,
-                                            const float *__restrict__ Tp, long long plane,
-                                            const uint8_t *__restrict__ db, float scale0, float bias,
-                                            int h, int w, int H, int W, int X0, int Y0,
-                                            float *__restrict__ out)
-{
-    const int tid = threadIdx.x;
-    float *sT = dyn;                        // [9][PHm][PWm]
-    float *sd = sT + 9 * PHm * PWm;         // [PHm][PWm]
-    float *sH = dyn + ((10 * PHm * PWm + 3) & ~3);  // [4][PHm][FIN_TILE_W], 16-byte aligned
-    int xa, ya, xb, yb, i1;
+__device__ __forceinline__ GatherWin gather_win(int h, int w, int H, int W, int X0, int Y0) {
+    GatherWin g;
+    int xb, yb, i1;
     float lam;
-    bilin(max(X0 - 1, 0), w, W, xa, i1, lam);
-    bilin(max(Y0 - 1, 0), h, H, ya, i1, lam);
+    bilin(max(X0 - 1, 0), w, W, g.xa, i1, lam);
+    bilin(max(Y0 - 1, 0), h, H, g.ya, i1, lam);
     bilin(min(X0 + FIN_TILE_W, W - 1), w, W, i1, xb, lam);
     bilin(min(Y0 + TH, H - 1), h, H, i1, yb, lam);
-    const int pw = xb - xa + 1, ph = yb - ya + 1;
-    if (ph > PHm || pw > PWm) return;  // excluded by the window bound
+    g.pw = xb - g.xa + 1;
+    g.ph = yb - g.ya + 1;
+    return g;
+}
+
+// The tile's column and row tables: source indices relative to the window,
+// bilinear weights, and zero weights outside the image.
+template <int TH>
+__device__ __forceinline__ void gather_tables(GatherTab<TH> &tb, const GatherWin &g, int h, int w, int H,
+                                              int W, int X0, int Y0) {
+    const int tid = threadIdx.x;
     if (tid < FIN_CX) {
         const int X = X0 - 1 + tid;
         int x0 = 0, x1 = 0;
         float lx = 0.f, wx = 0.f;
         if (X >= 0 && X < W) {
             bilin(X, w, W, x0, x1, lx);
-            x0 -= xa;
-            x1 -= xa;
+            x0 -= g.xa;
+            x1 -= g.xa;
             wx = 1.f - lx;
         }
         tb.cx0[tid] = x0;
@@ -363,8 +375,8 @@ __device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int P
         float ly = 0.f, wy = 0.f;
         if (Y >= 0 && Y < H) {
             bilin(Y, h, H, y0, y1, ly);
-            y0 -= ya;
-            y1 -= ya;
+            y0 -= g.ya;
+            y1 -= g.ya;
             wy = 1.f - ly;
         }
         tb.cy0[r] = y0;
@@ -372,33 +384,56 @@ __device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int P
         tb.cly[r] = ly;
         tb.cwy[r] = wy;
     }
-    // the nine projections and the coarse disparity on the window; two
-    // window pixels per thread and round, all of their loads issued first
-    const float inv_pw = 1.0f / (float)pw;
-    const int npx = ph * pw;
-    for (int q0 = tid; q0 < npx; q0 += 2 * FIN_THREADS) {
-        float a[2][10];
-        int rr[2], cc[2];
+}
+
+// One round of the window's loads: window pixels q0 and q0 + FIN_THREADS, the
+// nine projections and the coarse disparity of each (past the window's end
+// the last pixel is read again and not stored).
+struct GatherRound {
+    float a[2][10];
+    int rr[2], cc[2];
+};
+
+__device__ __forceinline__ void gather_fetch(GatherRound &R, const float *__restrict__ Tp, long long plane,
+                                             const uint8_t *__restrict__ db, int w, const GatherWin &g,
+                                             int q0) {
+    const float inv_pw = 1.0f / (float)g.pw;
+    const int npx = g.ph * g.pw;
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            const int q = min(q0 + k * FIN_THREADS, npx - 1);
-            rr[k] = fin_div(q, inv_pw);
-            cc[k] = q - rr[k] * pw;
-            const size_t gp = (size_t)(ya + rr[k]) * w + xa + cc[k];
+    for (int k = 0; k < 2; ++k) {
+        const int q = min(q0 + k * FIN_THREADS, npx - 1);
+        R.rr[k] = fin_div(q, inv_pw);
+        R.cc[k] = q - R.rr[k] * g.pw;
+        const size_t gp = (size_t)(g.ya + R.rr[k]) * w + g.xa + R.cc[k];
 #pragma unroll
-            for (int t = 0; t < 9; ++t) a[k][t] = Tp[t * plane + gp];
-            a[k][9] = (float)db[gp];
-        }
+        for (int t = 0; t < 9; ++t) R.a[k][t] = Tp[t * plane + gp];
+        R.a[k][9] = (float)db[gp];
+    }
+}
+
+__device__ __forceinline__ void gather_put(const GatherRound &R, float *sT, float *sd, int PHm, int PWm,
+                                           int npx, int q0) {
 #pragma unroll
-        for (int k = 0; k < 2; ++k) {
-            if (q0 + k * FIN_THREADS < npx) {
+    for (int k = 0; k < 2; ++k) {
+        if (q0 + k * FIN_THREADS < npx) {
 #pragma unroll
-                for (int t = 0; t < 9; ++t) sT[(t * PHm + rr[k]) * PWm + cc[k]] = a[k][t];
-                sd[rr[k] * PWm + cc[k]] = a[k][9];
-            }
+            for (int t = 0; t < 9; ++t) sT[(t * PHm + R.rr[k]) * PWm + R.cc[k]] = R.a[k][t];
+            sd[R.rr[k] * PWm + R.cc[k]] = R.a[k][9];
         }
     }
-    __syncthreads();
+}
+
+// The two passes over a staged window (the LDS holds T, d and the tables),
+// then the stores; ends with a barrier, so the LDS can take the next tile.
+template <int TH>
+__device__ __forceinline__ void gather_passes(float *dyn, const GatherTab<TH> &tb, int PHm, int PWm, int ph,
+                                              float scale0, float bias, int H, int W, int X0, int Y0,
+                                              float *__restrict__ out)
+{
+    const int tid = threadIdx.x;
+    const float *sT = dyn;                   // [9][PHm][PWm]
+    const float *sd = sT + 9 * PHm * PWm;    // [PHm][PWm]
+    float *sH = dyn + ((10 * PHm * PWm + 3) & ~3);  // [4][PHm][FIN_TILE_W], 16-byte aligned
     {
         const int tx = tid & (FIN_TILE_W - 1), rg = tid / FIN_TILE_W;
         constexpr int NRG = FIN_THREADS / FIN_TILE_W;
@@ -472,6 +507,29 @@ __device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int P
     __syncthreads();  // the LDS is reused by the next tile of a persistent loop
 }
 
+template <int TH>
+__device__ __forceinline__ void gather_tile(float *dyn, GatherTab<TH> &tb, int PHm, int PWm,
+                                            const float *__restrict__ Tp, long long plane,
+                                            const uint8_t *__restrict__ db, float scale0, float bias,
+                                            int h, int w, int H, int W, int X0, int Y0,
+                                            float *__restrict__ out)
+{
+    const GatherWin g = gather_win<TH>(h, w, H, W, X0, Y0);
+    if (g.ph > PHm || g.pw > PWm) return;  // excluded by the window bound
+    gather_tables<TH>(tb, g, h, w, H, W, X0, Y0);
+    // the nine projections and the coarse disparity on the window; two
+    // window pixels per thread and round, all of their loads issued first
+    float *sT = dyn, *sd = dyn + 9 * PHm * PWm;
+    const int npx = g.ph * g.pw;
+    for (int q0 = threadIdx.x; q0 < npx; q0 += 2 * FIN_THREADS) {
+        GatherRound R;
+        gather_fetch(R, Tp, plane, db, w, g, q0);
+        gather_put(R, sT, sd, PHm, PWm, npx, q0);
+    }
+    __syncthreads();
+    gather_passes<TH>(dyn, tb, PHm, PWm, g.ph, scale0, bias, H, W, X0, Y0, out);
+}
+
 // The gather from precomputed projections (uniform batch and pair table).
 template <int TH>
 __global__ void __launch_bounds__(FIN_THREADS)
@@ -481,10 +539,20 @@ k_final_gather(const float *__restrict__ T, long long plane, const uint8_t *__re
 {
     extern __shared__ __attribute__((aligned(16))) float fin_dyn[];
     __shared__ GatherTab<TH> tb;
-    const int b = blockIdx.z;
+    // XCD-aware order (workgroups go round robin to the eight XCDs, each with
+    // its own L2): hardware id i takes tile (i % 8) q + i / 8, q = N / 8, so
+    // each XCD covers a contiguous run of tiles and the windows' overlapping
+    // rows and columns are re-read from its own L2
+    const int gx = (int)gridDim.x, gy = (int)gridDim.y;
+    const int nblk = gx * gy * (int)gridDim.z;
+    const int hw = (int)blockIdx.x + gx * ((int)blockIdx.y + gy * (int)blockIdx.z);
+    const int q8 = nblk / 8;
+    const int lid = hw < 8 * q8 ? (hw % 8) * q8 + hw / 8 : hw;
+    const int b = lid / (gx * gy), rem = lid - b * (gx * gy);
+    const int by = rem / gx, bx = rem - by * gx;
     const size_t o = (size_t)b * h * w;
     gather_tile<TH>(fin_dyn, tb, PHm, PWm, T + o, plane, disp + o, scale0, biasF[0], h, w, H, W,
-                    blockIdx.x * FIN_TILE_W, blockIdx.y * TH, out + (size_t)b * H * W);
+                    bx * FIN_TILE_W, by * TH, out + (size_t)b * H * W);
 }
 
 template <int TH>
@@ -499,7 +567,12 @@ k_final_gather_tab(const PairTable *__restrict__ tab, const float *__restrict__ 
     const int *cum = tab->cum[BS_FINAL];
     const int total = cum[n];
     const float bias = biasF[0];
-    for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    // round k takes tiles k G .. k G + G - 1 (G = gridDim.x); hardware id i
+    // takes tile (i % 8) (G / 8) + i / 8 of the round, so that each XCD covers
+    // a contiguous run of tiles (workgroups go round robin to the XCDs)
+    const int G = (int)gridDim.x, q8 = G / 8, hw = (int)blockIdx.x;
+    const int lid = hw < 8 * q8 ? (hw % 8) * q8 + hw / 8 : hw;
+    for (int t = lid; t < total; t += G) {
         const int i = table_find(cum, n, t);
         const PairGeo &g = tab->pair[i];
         const int local = t - cum[i];

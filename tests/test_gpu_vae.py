@@ -241,3 +241,31 @@ def test_split_reduction_against_oracle():
     finally:
         for layer in range(9):
             sv.sv_set_layer_cfg(layer, -1)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_many_tile_batch_equals_single_images(dtype):
+    """Three full-size images in one call (1,440 tiles of the final gather,
+    spread over the XCDs in another order than one image's 480) give the same
+    bits as three single-image calls, with every layer on the same unsplit
+    tile shape; FP32 also within 1e-5 of the oracle."""
+    import paper_2305_11566_amd as sv
+    C, L, f, H, W, B = (32, 64, 128), 128, 4, 375, 1242, 3
+    disp, img = _inputs(H, W, f, 9, 7, 48, seed=7100, B=B)
+    params = vae_params(C, L, 7002)
+    names = [sv.sv_conv_cfg_name(c) for c in range(sv.sv_num_layer_cfgs())]
+    th4_tn16 = names.index("th4_tn16")
+    try:
+        for layer in range(1, 8):
+            sv.sv_set_layer_cfg(layer, th4_tn16)
+        a, ma = _gpu_forward(C, L, f, dtype, params, disp, img, H, W)
+        for b in range(B):
+            o, m = _gpu_forward(C, L, f, dtype, params, disp[b:b + 1], img[b:b + 1], H, W)
+            assert np.array_equal(m[0], ma[b]), f"image {b}: mu / logvar"
+            assert np.array_equal(o[0], a[b]), f"image {b}: refined map"
+    finally:
+        for layer in range(1, 8):
+            sv.sv_set_layer_cfg(layer, -1)
+    if dtype == "f32":
+        t = vae.forward(params, disp, img, f, H, W)
+        assert normwise(a, t["out"]) <= TOL_F32
