@@ -376,7 +376,7 @@ sv_status sv_batch_plan_create(const sv_vae_desc *desc, int max_n, int max_H, in
         }
     }
     for (int i = 0; i < L_F; ++i)
-        pl->cfg[i] = conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, pl->cfg[i]);
+        pl->cfg[i] = conv_resolve_cfg(ns.dtype, ns.ly[i].k, ns.ly[i].stride, conv_persistent_cfg(pl->cfg[i]));
     if (net_projects(ns, false)) pl->cfg[L_G0] = net_g0_proj_cfg(ns, pl->cfg[L_G0]);
     // capacities and persistent grid sizes from the largest pair
     for (int k = 0; k < 4; ++k) pl->cap[k] = (size_t)max_n * mx.h[k] * mx.w[k];

@@ -192,6 +192,20 @@ sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvPara
     return launch_any(dtype, ks, stride, cfg % kNumTiles, p, grid, st);
 }
 
+// The tile shape a persistent pair-table launch uses for configuration cfg:
+// 16-row tiles (tuned on uniform batches) become the 8-row tile of the same
+// width, which runs faster there (twice the resident workgroups and twice
+// the tiles to balance over uneven pairs).
+int conv_persistent_cfg(int cfg) {
+    if (cfg < 0 || cfg >= conv_num_cfgs()) return cfg;
+    const CfgDesc &c = kCfgs[cfg % kNumTiles];
+    if (c.TH != 16) return cfg;
+    for (int t = 0; t < kNumTiles; ++t)
+        if (kCfgs[t].TH == 8 && kCfgs[t].TN == c.TN && kCfgs[t].WM == c.WM && kCfgs[t].KCM == c.KCM)
+            return t + (cfg / kNumTiles) * kNumTiles;
+    return cfg;
+}
+
 bool conv_cfg_projects(int cfg, int cout) {
     if (cfg < 0) return false;
     const CfgDesc &c = kCfgs[cfg % kNumTiles];

@@ -312,9 +312,10 @@ struct ConvTile {
     // first and each pixel combines one of each; otherwise (and for sources
     // read in place, whose entries cost no division) every entry is formed
     // directly, without the second LDS round trip.
+    template <bool SEP>
     static __device__ __forceinline__ void pix_table(const ConvParams &p, const ConvGeo &G, Smem &sm) {
         const int iy0 = G.oy0 * S - PAD, ix0 = G.ox0 * S - PAD;
-        const bool sep = 2 * NPIX > 256 && (p.src[0].kind == SRC_RESIZE || p.src[1].kind == SRC_RESIZE);
+        const bool sep = SEP && 2 * NPIX > 256 && (p.src[0].kind == SRC_RESIZE || p.src[1].kind == SRC_RESIZE);
         if (!sep) {
             for (int e = threadIdx.x; e < 2 * NPIX; e += 256) {
                 const int si = e >= NPIX ? 1 : 0, pix = e - si * NPIX;
@@ -561,6 +562,7 @@ struct ConvTile {
         }
     }
 
+    template <bool SEP = true>
     static __device__ __forceinline__ void run(const ConvParams &p, const ConvGeo &G, Smem &sm,
                                                int kz) {
         T *patch = sm.patch, *wl = sm.wl;
@@ -597,7 +599,7 @@ struct ConvTile {
         }
 
         __syncthreads();  // the previous tile of a persistent loop is done with LDS
-        pix_table(p, G, sm);
+        pix_table<SEP>(p, G, sm);
         const T *wpk = (const T *)p.wpk;
         int c_begin = 0, c_end = p.Cin;
         if (p.ksplit > 1) split_range(p.Cin, KCB, p.ksplit, kz, c_begin, c_end);
@@ -966,7 +968,10 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
     CT::run(p, G, sm, kz);
 }
 
-// Pair table: persistent loop over the stage's tiles of every pair.
+// Pair table: persistent loop over the stage's tiles of every pair.  It
+// forms the pixel table directly (no separable form): the separable form's
+// registers would take some of these kernels past 256 VGPRs (AGPRs
+// included), one wave per SIMD instead of two.
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
 __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
 {
@@ -997,7 +1002,7 @@ __global__ void __launch_bounds__(256) k_conv_tab(const ConvParams p)
         G.n0 = nt * TN;
         G.oy0 = (r / tx) * TH;
         G.ox0 = (r % tx) * CT::TW;
-        CT::run(p, G, sm, 0);
+        CT::template run<false>(p, G, sm, 0);
         (void)ntn;
     }
 }
@@ -1058,7 +1063,8 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
         return SV_ERR_UNSUPPORTED;
     } else {
     if (pgrid > 0) {
-        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM>), dim3(pgrid), dim3(256), 0, st, p);
+        const long long g = resident_grid((const void *)k_conv_tab<DT, KS, S, TH, TN, WM, KCM>, 0, pgrid);
+        hipLaunchKernelGGL((k_conv_tab<DT, KS, S, TH, TN, WM, KCM>), dim3((unsigned)g), dim3(256), 0, st, p);
         SV_LAUNCH_CHECK("k_conv_tab");
         return SV_OK;
     }

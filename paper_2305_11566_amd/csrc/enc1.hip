@@ -5,9 +5,9 @@
 // channel -- does in a few registers what an implicit GEMM would pad to a full
 // channel chunk.  The weights are widened to FP32 in LDS once per workgroup
 // and read as one broadcast per wave (a wave owns one group of eight output
-// channels); the x0 patch of the tile is built in LDS as FP32.
+// channels); the x0 patch of the tile is built in LDS as FP32.  The LDS is
+// sized by the layer's width, so narrow layers keep many workgroups per CU.
 #include <algorithm>
-
 #include "kernels.h"
 
 namespace sv {
@@ -15,20 +15,35 @@ namespace sv {
 constexpr int E1_TW = 16, E1_TH = 4;                      // output tile
 constexpr int E1_PW = 2 * E1_TW + 1, E1_PH = 2 * E1_TH + 1;  // x0 patch (stride 2, pad 1)
 constexpr int E1_MAXC = 256;
+constexpr int E1_XN = (2 * E1_PH * E1_PW + 3) & ~3;        // x0 patch floats, 16-byte multiple
 
+// Dynamic LDS: x[2][E1_PH * E1_PW] (padded to E1_XN floats), then
+// w[9 * 2][c1] ([tap * 2 + channel][output channel]) and bias[c1].
 struct Enc1Smem {
-    float x[2][E1_PH * E1_PW];
-    float w[9 * 2][E1_MAXC];   // [tap * 2 + channel][output channel]
-    float bias[E1_MAXC];
+    float *x[2];
+    float *w;
+    float *bias;
+    int c1;
 };
+static inline size_t enc1_lds_bytes(int c1) { return sizeof(float) * ((size_t)E1_XN + 19 * (size_t)c1); }
+
+__device__ __forceinline__ Enc1Smem enc1_smem(float *dyn, int c1) {
+    Enc1Smem sm;
+    sm.x[0] = dyn;
+    sm.x[1] = dyn + E1_PH * E1_PW;
+    sm.w = dyn + E1_XN;
+    sm.bias = sm.w + 18 * c1;
+    sm.c1 = c1;
+    return sm;
+}
 
 template <int DT>
-__device__ __forceinline__ void enc1_weights(Enc1Smem &sm, const typename Elem<DT>::T *__restrict__ wpk,
+__device__ __forceinline__ void enc1_weights(const Enc1Smem &sm, const typename Elem<DT>::T *__restrict__ wpk,
                                              int n_pad, int cin_pad, const float *__restrict__ bias, int c1) {
     for (int e = threadIdx.x; e < 18 * c1; e += 256) {
         const int tc = e / c1, n = e - tc * c1;
         const int tap = tc >> 1, c = tc & 1;
-        sm.w[tc][n] = Elem<DT>::load(wpk + ((size_t)tap * n_pad + n) * cin_pad + c);
+        sm.w[tc * c1 + n] = Elem<DT>::load(wpk + ((size_t)tap * n_pad + n) * cin_pad + c);
     }
     for (int n = threadIdx.x; n < c1; n += 256) sm.bias[n] = bias[n];
 }
@@ -36,7 +51,7 @@ __device__ __forceinline__ void enc1_weights(Enc1Smem &sm, const typename Elem<D
 // One tile: output rows [oy0, oy0 + E1_TH) and columns [ox0, ox0 + E1_TW) of
 // an h1 x w1 map from the h0 x w0 coarse maps.
 template <int DT>
-__device__ __forceinline__ void enc1_tile(Enc1Smem &sm, const uint8_t *__restrict__ disp,
+__device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__restrict__ disp,
                                           const uint8_t *__restrict__ img, float scale0, int h0, int w0,
                                           int h1, int w1, int c1, int oy0, int ox0,
                                           typename Elem<DT>::T *__restrict__ out) {
@@ -76,8 +91,8 @@ __device__ __forceinline__ void enc1_tile(Enc1Smem &sm, const uint8_t *__restric
             for (int i = 0; i < 8; ++i) acc[i] = 0.f;
 #pragma unroll
             for (int k = 0; k < 18; ++k) {
-                const f32x4 wa = *(const f32x4 *)&sm.w[k][n0];
-                const f32x4 wb = *(const f32x4 *)&sm.w[k][n0 + 4];
+                const f32x4 wa = *(const f32x4 *)&sm.w[k * c1 + n0];
+                const f32x4 wb = *(const f32x4 *)&sm.w[k * c1 + n0 + 4];
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     acc[i] = fmaf(wa[i], xin[k], acc[i]);
@@ -112,7 +127,8 @@ __global__ void __launch_bounds__(256)
 k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float scale0, int B, int h0, int w0,
        int h1, int w1, int c1, const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad,
        const float *__restrict__ bias, typename Elem<DT>::T *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) Enc1Smem sm;
+    extern __shared__ __attribute__((aligned(16))) float e1_dyn[];
+    const Enc1Smem sm = enc1_smem(e1_dyn, c1);
     enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
     const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
     const int per = tx * ty, total = per * B;
@@ -130,7 +146,8 @@ __global__ void __launch_bounds__(256)
 k_enc1_tab(const PairTable *__restrict__ tab, const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img,
            float scale0, int c1, const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad,
            const float *__restrict__ bias, typename Elem<DT>::T *__restrict__ out) {
-    __shared__ __attribute__((aligned(16))) Enc1Smem sm;
+    extern __shared__ __attribute__((aligned(16))) float e1_dyn[];
+    const Enc1Smem sm = enc1_smem(e1_dyn, c1);
     enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
     const int n = tab->n;
     const int *cum = tab->cum[BS_E1];
@@ -153,13 +170,14 @@ sv_status launch_enc1(int dtype, const uint8_t *disp, const uint8_t *img, float 
     if (c1 < 8 || c1 > E1_MAXC || c1 % 8) return SV_ERR_UNSUPPORTED;
     const long long tiles = (long long)enc1_tiles(h1, w1) * B;
     if (tiles >= (1ll << 31)) return SV_ERR_SHAPE;
-    const dim3 grid((unsigned)std::min<long long>(tiles, 2048));
     switch (dtype) {
 #define SV_E1(D, T)                                                                                     \
-    case D:                                                                                             \
-        hipLaunchKernelGGL(k_enc1<D>, grid, dim3(256), 0, st, disp, img, scale0, B, h0, w0, h1, w1, c1, \
-                           (const T *)wpk, n_pad, cin_pad, bias, (T *)out);                             \
-        break;
+    case D: {                                                                                           \
+        const dim3 grid((unsigned)resident_grid((const void *)k_enc1<D>, enc1_lds_bytes(c1), tiles));     \
+        hipLaunchKernelGGL(k_enc1<D>, grid, dim3(256), enc1_lds_bytes(c1), st, disp, img, scale0, B, h0, \
+                           w0, h1, w1, c1, (const T *)wpk, n_pad, cin_pad, bias, (T *)out);             \
+        break;                                                                                          \
+    }
         SV_E1(SV_F32, float)
         SV_E1(SV_BF16, uint16_t)
         SV_E1(SV_F16, uint16_t)
@@ -177,7 +195,9 @@ sv_status launch_enc1_tab(int dtype, const PairTable *tab, int grid, const uint8
     switch (dtype) {
 #define SV_E1T(D, T)                                                                                    \
     case D:                                                                                             \
-        hipLaunchKernelGGL(k_enc1_tab<D>, dim3(grid), dim3(256), 0, st, tab, disp, img, scale0, c1,     \
+        hipLaunchKernelGGL(k_enc1_tab<D>, dim3(resident_grid((const void *)k_enc1_tab<D>, enc1_lds_bytes(c1), grid)), \
+                           dim3(256), enc1_lds_bytes(c1), st, tab, disp, img,                           \
+                           scale0, c1,                                                                  \
                            (const T *)wpk, n_pad, cin_pad, bias, (T *)out);                             \
         break;
         SV_E1T(SV_F32, float)

@@ -617,7 +617,8 @@ sv_status launch_final_tab(const PairTable *tab, int grid, int dtype, const void
     switch (dtype) {
 #define SV_FT(D)                                                                                      \
     case D:                                                                                           \
-        hipLaunchKernelGGL(k_final_tab<D>, dim3(grid), dim3(FIN_THREADS), lds, s, tab,                \
+        hipLaunchKernelGGL(k_final_tab<D>, dim3((unsigned)resident_grid((const void *)k_final_tab<D>, lds, grid)), \
+                           dim3(FIN_THREADS), lds, s, tab,                                            \
                            (const typename Elem<D>::T *)G0, c1, disp, img, wF, wf_pitch, scale0,      \
                            biasF, PHm, PWm);                                                          \
         break;
@@ -686,8 +687,9 @@ sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T
     int PHm, PWm;
     gather_window(f, th, PHm, PWm);
 #define SV_FG(TH)                                                                                          \
-    hipLaunchKernelGGL(k_final_gather_tab<TH>, dim3(grid), dim3(FIN_THREADS), gather_lds_bytes(f, th), s, tab, T, \
-                       plane, disp, (float)f / 256.0f, biasF, PHm, PWm)
+    hipLaunchKernelGGL(k_final_gather_tab<TH>,                                                             \
+                       dim3((unsigned)resident_grid((const void *)k_final_gather_tab<TH>, gather_lds_bytes(f, th), grid)), \
+                       dim3(FIN_THREADS), gather_lds_bytes(f, th), s, tab, T, plane, disp, (float)f / 256.0f, biasF, PHm, PWm)
     if (th == 64) SV_FG(64);
     else if (th == 32) SV_FG(32);
     else SV_FG(16);

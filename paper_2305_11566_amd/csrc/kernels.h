@@ -198,6 +198,12 @@ sv_status launch_wgrad_partials(int dtype, int ks, int stride, ConvSrc s0, ConvS
 sv_status launch_amax_prologue(uint32_t *amax, int nslots, int x0_slot, const uint8_t *disp,
                                const uint8_t *img, long long n, float scale0, hipStream_t s);
 
+// The grid of a persistent launch of fn (256 threads, dyn_lds bytes of
+// dynamic LDS) that wants `want` workgroups: at most what the current device
+// holds at once.  Host-side queries only (cached per device, kernel and LDS
+// size), nothing is enqueued, so it may run during stream capture.
+long long resident_grid(const void *fn, size_t dyn_lds, long long want);
+
 // storage dtype code of a source (see ConvSrc::sdt)
 constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F16 = 1 + SV_F16;
 
@@ -244,6 +250,8 @@ sv_status launch_final_gather_tab(const PairTable *tab, int grid, const float *T
 // whether a conv tile configuration can carry the projection epilogue for a
 // layer with cout output channels (one channel tile, all of it in each wave)
 bool conv_cfg_projects(int cfg, int cout);
+// the configuration a persistent pair-table launch runs for cfg
+int conv_persistent_cfg(int cfg);
 sv_status launch_final(int dtype, const void *G0, int c1, const uint8_t *disp, const uint8_t *img,
                        const float *wF, int wf_pitch, int f, const float *biasF, int B, int h,
                        int w, int H, int W, float *out, hipStream_t s);

@@ -397,8 +397,9 @@ sv_status launch_reduce_census_tab(const PairTable *tab, int grid, int f, int th
     if (th != 4 && th != 16) return SV_ERR_RANGE;
     const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
 #define SV_CEN_L(F, TH, RX, RY)                                                                    \
-    hipLaunchKernelGGL((k_reduce_census_tab<F, TH, RX, RY>), dim3(grid), dim3(CEN_THREADS), 0, s,   \
-                       tab, rx, ry, low0, cen0, cen1)
+    hipLaunchKernelGGL((k_reduce_census_tab<F, TH, RX, RY>),                                       \
+                       dim3((unsigned)resident_grid((const void *)k_reduce_census_tab<F, TH, RX, RY>, 0, grid)), \
+                       dim3(CEN_THREADS), 0, s, tab, rx, ry, low0, cen0, cen1)
 #define SV_CEN_W(F, TH)                                                                            \
     if (rx == 4 && ry == 3) SV_CEN_L(F, TH, 4, 3);                                                 \
     else if (rx == 2 && ry == 2) SV_CEN_L(F, TH, 2, 2);                                            \
@@ -512,8 +513,8 @@ sv_status launch_cost_wta_tab(const PairTable *tab, int grid, const uint64_t *cl
     switch (dsplit) {
 #define SV_CWT_CASE(N)                                                                             \
     case N:                                                                                        \
-        hipLaunchKernelGGL(k_cost_wta_tab<N>, dim3(grid), dim3(CW_THREADS), 0, s, tab, cl, cr,     \
-                           nbits, disp);                                                           \
+        hipLaunchKernelGGL(k_cost_wta_tab<N>, dim3((unsigned)resident_grid((const void *)k_cost_wta_tab<N>, 0, grid)), \
+                           dim3(CW_THREADS), 0, s, tab, cl, cr, nbits, disp);                      \
         break;
         SV_CWT_CASE(1)
         SV_CWT_CASE(2)
