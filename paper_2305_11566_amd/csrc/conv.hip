@@ -156,7 +156,7 @@ sv_status launch_conv_split(int dtype, int ks, int stride, int cfg, const ConvPa
     if (p.ophase) p.ksplit = 1;  // a phase launch writes its pixels straight into the full map
     if (p.proj_out) {
         // the projection epilogue needs whole sums and every channel in each wave
-        if (!conv_cfg_projects(cfg % kNumTiles, p.Cout) || dtype == SV_I8) return SV_ERR_UNSUPPORTED;
+        if (!conv_cfg_projects(cfg % kNumTiles, p.Cout)) return SV_ERR_UNSUPPORTED;
         p.ksplit = 1;
     }
     if (ksplit_used) *ksplit_used = p.ksplit > 1 ? p.ksplit : 1;
@@ -185,7 +185,7 @@ sv_status launch_conv_tab(int dtype, int ks, int stride, int cfg, const ConvPara
     if (!p0.tab || grid <= 0) return SV_ERR_RANGE;
     if (cfg < 0 || cfg >= conv_num_cfgs()) return SV_ERR_RANGE;
     cfg = conv_resolve_cfg(dtype, ks, stride, cfg);
-    if (p0.proj_out && (!conv_cfg_projects(cfg % kNumTiles, p0.Cout) || dtype == SV_I8))
+    if (p0.proj_out && !conv_cfg_projects(cfg % kNumTiles, p0.Cout))
         return SV_ERR_UNSUPPORTED;
     ConvParams p = p0;
     p.ksplit = 1;  // the persistent path never splits

@@ -396,13 +396,16 @@ struct ConvTile {
     // (one channel tile, WN = 1): lane (g, r16) has channels nb * 16 + 4 g + i
     // of pixel r16, so B's k slots of lane group g are exactly those channels
     // and A's rows are built with the same channel order.  FP32 runs the FP32
-    // instruction; 16-bit types feed y as stored (exact in the type) and the
-    // FP32 weights as a high and a low part, two products.  The accumulator
+    // instruction; 16-bit types (and INT8 layers, whose maps are stored as
+    // BF16: y is the dequantised sum, biased, activated and rounded to BF16)
+    // feed y as stored (exact in the type) and the FP32 weights as a high and
+    // a low part, two products in the storage type.  The accumulator
     // comes back as taps 4 g' + i of pixel r16' in lane (g', r16'); the x0
     // terms are added in FP32 and each lane writes its taps.
     static __device__ __forceinline__ void project_epilogue(const ConvParams &p, const ConvGeo &G,
                                                             const typename M::acc (&acc)[MBW][NBW],
-                                                            const float (&bpre)[NBW][4]) {
+                                                            const float (&bpre)[NBW][4],
+                                                            const float (&spre)[NBW][4]) {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int wm = wave % WM;
         const int g = lane >> 4, r16 = lane & 15;
@@ -434,7 +437,9 @@ struct ConvTile {
             for (int nb = 0; nb < NBW; ++nb)
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    float v = acc[mb][nb][i] + bpre[nb][i];
+                    // (INT8: the integer sum times s_in s_w first, as the plain epilogue)
+                    const float a = DT == SV_I8 ? (float)acc[mb][nb][i] * spre[nb][i] : (float)acc[mb][nb][i];
+                    float v = a + bpre[nb][i];
                     v = v > 0.f ? v : 0.1f * v;
                     const typename Elem<SD>::T st = Elem<SD>::make(v);
                     val[nb][i] = nb * 16 + 4 * g + i < p.Cout ? Elem<SD>::load(&st) : 0.f;
@@ -457,13 +462,14 @@ struct ConvTile {
                         const bool ok = nb < NBW;
                         bv[j] = ok ? val[nb < NBW ? nb : 0][i] : 0.f;
                         const float w = ok ? wa[nb < NBW ? nb : 0][i] : 0.f;
-                        const typename Elem<DT>::T wh = Elem<DT>::make(w);
-                        ah[j] = Elem<DT>::load(&wh);
+                        const typename Elem<SD>::T wh = Elem<SD>::make(w);
+                        ah[j] = Elem<SD>::load(&wh);
                         al[j] = w - ah[j];
                     }
-                    const vec bq = pack_vec<DT, 8>(bv, 0.f);
-                    c = M::run(pack_vec<DT, 8>(ah, 0.f), bq, c);
-                    c = M::run(pack_vec<DT, 8>(al, 0.f), bq, c);
+                    using MP = Mfma<SD>;
+                    const typename MP::vec bq = pack_vec<SD, 8>(bv, 0.f);
+                    c = MP::run(pack_vec<SD, 8>(ah, 0.f), bq, c);
+                    c = MP::run(pack_vec<SD, 8>(al, 0.f), bq, c);
                 }
             }
             const int oy = G.oy0 + wm * MBW + mb, ox = G.ox0 + r16;
@@ -887,9 +893,9 @@ struct ConvTile {
         if (c_x0 < c_end) x0_packed(p, sm, acc, qinv, n0, wm, wn, g, r16);
 
         // ---- epilogue -------------------------------------------------------
-        if constexpr (DT != SV_I8 && WN == 1) {
+        if constexpr (WN == 1) {
             if (p.proj_out) {  // launches set it only for tiles that hold every channel
-                project_epilogue(p, G, acc, bpre);
+                project_epilogue(p, G, acc, bpre, spre);
                 return;
             }
         }

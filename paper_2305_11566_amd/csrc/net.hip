@@ -137,7 +137,7 @@ int net_heuristic_cfg(const NetShape &ns, int layer) {
 }
 
 bool net_projects(const NetShape &ns, bool train) {
-    return !train && ns.dtype != SV_I8 && ns.c1 <= 64;
+    return !train && ns.c1 <= 64;
 }
 
 int net_g0_proj_cfg(const NetShape &ns, int cfg) {
@@ -406,7 +406,8 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
         ev_rec(8, 0, st);
         if (only < 0 || only == L_G0) {
             ConvParams p = layer_params(ns, packed, L_G0, src_resize(G1, c1, lv.h[1], lv.w[1]), x0, B, lv.h[0],
-                                        lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, part, a.part_bytes, LayerAmax{});
+                                        lv.w[0], lv.h[0], lv.w[0], G0, c1, 0, 1, part, a.part_bytes,
+                                        am(AM_G1, AM_X0, -1));
             p.proj_w = wF;
             p.proj_pitch = ns.cin_pad[L_F];
             p.proj_out = (float *)G0;
