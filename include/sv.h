@@ -69,8 +69,11 @@ typedef int32_t sv_status;
  * tensor (every convolution's epilogue records max |stored value| of its
  * output; a layer quantises what it reads with 127 / m, m the largest amax of
  * its sources; x0's amax comes from the coarse maps), exact INT32 sums on the
- * MFMA units, then y = float(sum) * (s_in * s_w) + bias in FP32, activations
- * stored in BF16.  The final layer stays FP32 as in every mode. */
+ * MFMA units (E1, two input channels: the same exact sums in a direct
+ * stencil), then y = float(sum) * (s_in * s_w) + bias in FP32, activations
+ * stored in BF16.  The final layer keeps FP32 weights as in every mode (at
+ * inference applied by G0's epilogue to the BF16-rounded G0, as for the
+ * 16-bit types). */
 #define SV_F32 0
 #define SV_BF16 1
 #define SV_F16 2

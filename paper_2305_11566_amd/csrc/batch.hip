@@ -645,7 +645,7 @@ sv_status sv_autotune(const sv_vae_desc *desc, int B, int H, int W, int D, int w
         r = fwd(-1);
         const int nrep = B >= 16 ? 6 : 24;
         for (int i = 0; i < L_F && r == SV_OK; ++i) {
-            if (i == L_E1 && ns.dtype != SV_I8) continue;  // a direct stencil, no tile configuration
+            if (i == L_E1) continue;  // a direct stencil, no tile configuration
             float kt[NKEEP];
             for (int c = 0; c < conv_num_cfgs() && r == SV_OK; ++c) {
                 // a tile shape that does not fit this layer would run as the fallback,

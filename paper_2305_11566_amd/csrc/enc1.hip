@@ -7,6 +7,14 @@
 // and read as one broadcast per wave (a wave owns one group of eight output
 // channels); the x0 patch of the tile is built in LDS as FP32.  The LDS is
 // sized by the layer's width, so narrow layers keep many workgroups per CU.
+//
+// INT8 networks run the same stencil on the quantised layer's codes: x0
+// quantised with the input scale (127 / amax of x0, as the convolution's
+// staging does), the weights' INT8 codes, and the products summed in FP32,
+// which is exact here (at most 18 x 127 x 127 < 2^24, every partial sum an
+// integer), so the sum equals the matrix units' INT32 sum; then the same
+// dequantisation (sum x s_in s_w), bias, leaky ReLU, BF16 store and record
+// of the output's max |value| as the convolution's epilogue.
 #include <algorithm>
 #include "kernels.h"
 
@@ -50,11 +58,22 @@ __device__ __forceinline__ void enc1_weights(const Enc1Smem &sm, const typename 
 
 // One tile: output rows [oy0, oy0 + E1_TH) and columns [ox0, ox0 + E1_TW) of
 // an h1 x w1 map from the h0 x w0 coarse maps.
+// stored element type of E1's output (INT8 layers store BF16 maps)
+template <int DT> using E1Out = typename Elem<DT == SV_I8 ? SV_BF16 : DT>::T;
+
+// INT8 pass state: the input's quantisation step and scale, the weights'
+// per-channel scales, and this workgroup's running max |stored value|
+struct Enc1Q {
+    float qinv, s_in;
+    const float *wscale;
+    float lmax;
+};
+
 template <int DT>
 __device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__restrict__ disp,
                                           const uint8_t *__restrict__ img, float scale0, int h0, int w0,
                                           int h1, int w1, int c1, int oy0, int ox0,
-                                          typename Elem<DT>::T *__restrict__ out) {
+                                          E1Out<DT> *__restrict__ out, Enc1Q &q) {
     const int tid = threadIdx.x;
     const int iy0 = 2 * oy0 - 1, ix0 = 2 * ox0 - 1;
     for (int e = tid; e < E1_PH * E1_PW; e += 256) {
@@ -65,6 +84,10 @@ __device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__r
             const size_t o = (size_t)y * w0 + x;
             a = scale0 * (float)disp[o];
             c = (float)img[o] * (1.0f / 256.0f);
+            if constexpr (DT == SV_I8) {  // the INT8 codes, as values
+                a = fminf(fmaxf(rintf(a * q.qinv), -127.0f), 127.0f);
+                c = fminf(fmaxf(rintf(c * q.qinv), -127.0f), 127.0f);
+            }
         }
         sm.x[0][e] = a;
         sm.x[1][e] = c;
@@ -102,11 +125,21 @@ __device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__r
             float r[8];
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-                const float s = acc[i] + sm.bias[n0 + i];
+                float a = acc[i];
+                if constexpr (DT == SV_I8) a = acc[i] * (q.s_in * q.wscale[n0 + i]);
+                const float s = a + sm.bias[n0 + i];
                 r[i] = s > 0.f ? s : 0.1f * s;
             }
-            typename Elem<DT>::T *op = out + ((size_t)oy * w1 + ox) * c1 + n0;
-            if constexpr (DT == SV_F32) {
+            E1Out<DT> *op = out + ((size_t)oy * w1 + ox) * c1 + n0;
+            if constexpr (DT == SV_I8) {
+                u16x8 v;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    v[i] = Elem<SV_BF16>::make(r[i]);
+                    q.lmax = fmaxf(q.lmax, fabsf(bf16_bits_to_f32(v[i])));
+                }
+                *(u16x8 *)op = v;
+            } else if constexpr (DT == SV_F32) {
                 *(f32x4 *)op = f32x4{r[0], r[1], r[2], r[3]};
                 *(f32x4 *)(op + 4) = f32x4{r[4], r[5], r[6], r[7]};
             } else {
@@ -126,17 +159,33 @@ template <int DT>
 __global__ void __launch_bounds__(256)
 k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float scale0, int B, int h0, int w0,
        int h1, int w1, int c1, const typename Elem<DT>::T *__restrict__ wpk, int n_pad, int cin_pad,
-       const float *__restrict__ bias, typename Elem<DT>::T *__restrict__ out) {
+       const float *__restrict__ bias, E1Out<DT> *__restrict__ out, const float *__restrict__ wscale,
+       const uint32_t *__restrict__ amax_in, uint32_t *__restrict__ amax_out) {
     extern __shared__ __attribute__((aligned(16))) float e1_dyn[];
     const Enc1Smem sm = enc1_smem(e1_dyn, c1);
     enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
+    Enc1Q q{0.f, 0.f, wscale, 0.f};
+    if constexpr (DT == SV_I8) {
+        // the input scale from x0's recorded maxima (lane j reads word j)
+        float m = __uint_as_float(amax_in[threadIdx.x & (AMAX_SUB - 1)]);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        q.qinv = m > 0.f ? 127.0f / m : 0.f;
+        q.s_in = m / 127.0f;
+    }
     const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
     const int per = tx * ty, total = per * B;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int b = t / per, r = t - b * per;
         const size_t i0 = (size_t)b * h0 * w0, o1 = (size_t)b * h1 * w1;
         enc1_tile<DT>(sm, disp + i0, img + i0, scale0, h0, w0, h1, w1, c1, (r / tx) * E1_TH,
-                      (r % tx) * E1_TW, out + o1 * c1);
+                      (r % tx) * E1_TW, out + o1 * c1, q);
+    }
+    if constexpr (DT == SV_I8) {
+        float m = q.lmax;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+        if ((threadIdx.x & 63) == 0) atomicMax(amax_out + (blockIdx.x & (AMAX_SUB - 1)), __float_as_uint(m));
     }
 }
 
@@ -157,8 +206,9 @@ k_enc1_tab(const PairTable *__restrict__ tab, const uint8_t *__restrict__ disp, 
         const PairGeo &g = tab->pair[i];
         const int local = t - cum[i];
         const int tx = cdiv_d(g.w[1], E1_TW);
+        Enc1Q q{0.f, 0.f, nullptr, 0.f};  // (no INT8 pair-table path)
         enc1_tile<DT>(sm, disp + g.off[0], img + g.off[0], scale0, g.h[0], g.w[0], g.h[1], g.w[1], c1,
-                      (local / tx) * E1_TH, (local % tx) * E1_TW, out + (size_t)g.off[1] * c1);
+                      (local / tx) * E1_TH, (local % tx) * E1_TW, out + (size_t)g.off[1] * c1, q);
     }
 }
 
@@ -166,21 +216,25 @@ int enc1_tiles(int h1, int w1) { return cdiv(h1, E1_TH) * cdiv(w1, E1_TW); }
 
 sv_status launch_enc1(int dtype, const uint8_t *disp, const uint8_t *img, float scale0, int B, int h0, int w0,
                       int h1, int w1, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
-                      void *out, hipStream_t st) {
+                      void *out, hipStream_t st, const float *wscale, const uint32_t *amax_in,
+                      uint32_t *amax_out) {
     if (c1 < 8 || c1 > E1_MAXC || c1 % 8) return SV_ERR_UNSUPPORTED;
+    if (dtype == SV_I8 && (!wscale || !amax_in || !amax_out)) return SV_ERR_NULL;
     const long long tiles = (long long)enc1_tiles(h1, w1) * B;
     if (tiles >= (1ll << 31)) return SV_ERR_SHAPE;
     switch (dtype) {
-#define SV_E1(D, T)                                                                                     \
+#define SV_E1(D, TW, TO)                                                                                \
     case D: {                                                                                           \
         const dim3 grid((unsigned)resident_grid((const void *)k_enc1<D>, enc1_lds_bytes(c1), tiles));     \
         hipLaunchKernelGGL(k_enc1<D>, grid, dim3(256), enc1_lds_bytes(c1), st, disp, img, scale0, B, h0, \
-                           w0, h1, w1, c1, (const T *)wpk, n_pad, cin_pad, bias, (T *)out);             \
+                           w0, h1, w1, c1, (const TW *)wpk, n_pad, cin_pad, bias, (TO *)out, wscale,    \
+                           amax_in, amax_out);                                                          \
         break;                                                                                          \
     }
-        SV_E1(SV_F32, float)
-        SV_E1(SV_BF16, uint16_t)
-        SV_E1(SV_F16, uint16_t)
+        SV_E1(SV_F32, float, float)
+        SV_E1(SV_BF16, uint16_t, uint16_t)
+        SV_E1(SV_F16, uint16_t, uint16_t)
+        SV_E1(SV_I8, int8_t, uint16_t)
 #undef SV_E1
     default: return SV_ERR_DTYPE;
     }

@@ -211,9 +211,13 @@ constexpr int SDT_SAME = 0, SDT_F32 = 1 + SV_F32, SDT_BF16 = 1 + SV_BF16, SDT_F1
 // img / 256], leaky ReLU) as a direct stencil, FP32 arithmetic, output NHWC
 // [B][h1][w1][c1] in the compute dtype (SV_F32, SV_BF16, SV_F16); weights
 // packed [9][n_pad][cin_pad] in that dtype, FP32 bias.  c1: multiple of 8, <= 256.
+// SV_I8: INT8 weight codes with per-channel scales wscale, x0 quantised with
+// the scale from its recorded maxima amax_in (AMAX_SUB words), exact integer
+// sums, BF16 output, its max |value| recorded in amax_out (all three required).
 sv_status launch_enc1(int dtype, const uint8_t *disp, const uint8_t *img, float scale0, int B, int h0, int w0,
                       int h1, int w1, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,
-                      void *out, hipStream_t st);
+                      void *out, hipStream_t st, const float *wscale = nullptr,
+                      const uint32_t *amax_in = nullptr, uint32_t *amax_out = nullptr);
 // persistent variant over the pair table (stage BS_E1; level-0 inputs, level-1 output)
 sv_status launch_enc1_tab(int dtype, const PairTable *tab, int grid, const uint8_t *disp, const uint8_t *img,
                           float scale0, int c1, const void *wpk, int n_pad, int cin_pad, const float *bias,

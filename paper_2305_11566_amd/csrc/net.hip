@@ -332,17 +332,17 @@ sv_status net_forward(const NetShape &ns, const void *packed, const uint8_t *dis
     if (q8)
         SV_TRY(launch_amax_prologue(AM, AM_NSLOTS, AM_X0, disp, img, (long long)B * lv.h[0] * lv.w[0],
                                     (float)ns.f / 256.0f, st));
-    // encoder; E1 reads the two x0 channels only: a direct stencil (INT8 keeps
-    // the quantised convolution its codes are defined on)
+    // encoder; E1 reads the two x0 channels only: a direct stencil (INT8: on
+    // the quantised layer's codes, with exact integer sums)
     ev_rec(0, 0, st);
-    if (q8) {
-        SplitSum ss0;  // (INT8 never splits)
-        SV_STAGE(run_layer_if(only, ns, packed, L_E1, x0, none, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], E1, c1, 0, 1,
-                              cfg[L_E1], part, a.part_bytes, am(AM_X0, -1, AM_E1), st, &ss0));
-    } else if (only < 0 || only == L_E1)
+    if (only < 0 || only == L_E1) {
+        const LayerAmax a1 = am(AM_X0, -1, AM_E1);
         SV_STAGE(launch_enc1(ns.dtype, disp, img, (float)ns.f / 256.0f, B, lv.h[0], lv.w[0], lv.h[1], lv.w[1], c1,
-                           (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
-                           (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st));
+                             (const char *)packed + ns.w_off[L_E1], ns.n_pad[L_E1], ns.cin_pad[L_E1],
+                             (const float *)((const char *)packed + ns.b_off[L_E1]), E1, st,
+                             q8 ? (const float *)((const char *)packed + ns.s_off[L_E1]) : nullptr, a1.in0,
+                             a1.out));
+    }
     ev_rec(0, 1, st);
     SV_LAYER(1, L_E2, src_tensor(E1, c1, c1, 0, lv.h[1], lv.w[1], 0), none, B, lv.h[1], lv.w[1], lv.h[2], lv.w[2],
              E2, c2, 0, 1, cfg[L_E2], part, a.part_bytes, am(AM_E1, -1, AM_E2));
