@@ -218,6 +218,20 @@ __device__ __forceinline__ void record_amax(const ConvParams &p, float m, int sl
     if ((threadIdx.x & 63) == 0) atomicMax(p.amax_out + (slot & (AMAX_SUB - 1)), __float_as_uint(m));
 }
 
+// The same with one atomic per workgroup of four waves: the waves' maxima
+// meet in red[4] (LDS); every thread of the workgroup calls it.  Atomics to
+// one slot serialise, so a quarter of them shortens layers with many
+// workgroups.
+__device__ __forceinline__ void record_amax_wg(const ConvParams &p, float m, int slot, float *red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        atomicMax(p.amax_out + (slot & (AMAX_SUB - 1)),
+                  __float_as_uint(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))));
+}
+
 // The input scale of an INT8 layer: m = the largest recorded amax of its
 // sources; qinv = 127 / m and s_in = m / 127 (both 0 when m = 0).  Lane j
 // reads word j of each source's slots, then a wave-wide max.
@@ -301,6 +315,7 @@ struct ConvTile {
         T wl[TAPS * TN * KCP];
         PixSrc ps[2][NPIX];
         AxSrc ax[2][PH + PW];
+        float red[4];  // the waves' output maxima (INT8)
     };
     // tiles whose LDS exceeds a CU's 160 KB are never instantiated (conv_fits)
     static constexpr bool FITS = sizeof(Smem) <= 160 * 1024;
@@ -933,7 +948,7 @@ struct ConvTile {
             }
         }
         if (p.amax_out && p.ksplit <= 1)
-            record_amax(p, lmax, (int)(blockIdx.x * 7u + blockIdx.y * 13u + blockIdx.z));
+            record_amax_wg(p, lmax, (int)(blockIdx.x * 7u + blockIdx.y * 13u + blockIdx.z), sm.red);
     }
 };
 

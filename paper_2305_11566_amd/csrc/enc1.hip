@@ -26,14 +26,16 @@ constexpr int E1_MAXC = 256;
 constexpr int E1_XN = (2 * E1_PH * E1_PW + 3) & ~3;        // x0 patch floats, 16-byte multiple
 
 // Dynamic LDS: x[2][E1_PH * E1_PW] (padded to E1_XN floats), then
-// w[9 * 2][c1] ([tap * 2 + channel][output channel]) and bias[c1].
+// w[9 * 2][c1] ([tap * 2 + channel][output channel]), bias[c1] and, for INT8,
+// the dequantisation factors scale[c1] = s_in * s_w.
 struct Enc1Smem {
     float *x[2];
     float *w;
     float *bias;
+    float *scale;
     int c1;
 };
-static inline size_t enc1_lds_bytes(int c1) { return sizeof(float) * ((size_t)E1_XN + 19 * (size_t)c1); }
+static inline size_t enc1_lds_bytes(int c1) { return sizeof(float) * ((size_t)E1_XN + 20 * (size_t)c1); }
 
 __device__ __forceinline__ Enc1Smem enc1_smem(float *dyn, int c1) {
     Enc1Smem sm;
@@ -41,6 +43,7 @@ __device__ __forceinline__ Enc1Smem enc1_smem(float *dyn, int c1) {
     sm.x[1] = dyn + E1_PH * E1_PW;
     sm.w = dyn + E1_XN;
     sm.bias = sm.w + 18 * c1;
+    sm.scale = sm.bias + c1;
     sm.c1 = c1;
     return sm;
 }
@@ -126,7 +129,7 @@ __device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__r
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
                 float a = acc[i];
-                if constexpr (DT == SV_I8) a = acc[i] * (q.s_in * q.wscale[n0 + i]);
+                if constexpr (DT == SV_I8) a = acc[i] * sm.scale[n0 + i];
                 const float s = a + sm.bias[n0 + i];
                 r[i] = s > 0.f ? s : 0.1f * s;
             }
@@ -172,6 +175,7 @@ k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float 
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
         q.qinv = m > 0.f ? 127.0f / m : 0.f;
         q.s_in = m / 127.0f;
+        for (int n = threadIdx.x; n < c1; n += 256) sm.scale[n] = q.s_in * wscale[n];
     }
     const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
     const int per = tx * ty, total = per * B;
@@ -182,10 +186,17 @@ k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float 
                       (r % tx) * E1_TW, out + o1 * c1, q);
     }
     if constexpr (DT == SV_I8) {
+        // the workgroup's max: waves through the (free) patch area, then one
+        // atomic per workgroup
         float m = q.lmax;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-        if ((threadIdx.x & 63) == 0) atomicMax(amax_out + (blockIdx.x & (AMAX_SUB - 1)), __float_as_uint(m));
+        if ((threadIdx.x & 63) == 0) sm.x[0][threadIdx.x >> 6] = m;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            const float w = fmaxf(fmaxf(sm.x[0][0], sm.x[0][1]), fmaxf(sm.x[0][2], sm.x[0][3]));
+            atomicMax(amax_out + (blockIdx.x & (AMAX_SUB - 1)), __float_as_uint(w));
+        }
     }
 }
 
