@@ -59,8 +59,6 @@ __device__ __forceinline__ void enc1_weights(const Enc1Smem &sm, const typename 
     for (int n = threadIdx.x; n < c1; n += 256) sm.bias[n] = bias[n];
 }
 
-// One tile: output rows [oy0, oy0 + E1_TH) and columns [ox0, ox0 + E1_TW) of
-// an h1 x w1 map from the h0 x w0 coarse maps.
 // stored element type of E1's output (INT8 layers store BF16 maps)
 template <int DT> using E1Out = typename Elem<DT == SV_I8 ? SV_BF16 : DT>::T;
 
@@ -72,21 +70,41 @@ struct Enc1Q {
     float lmax;
 };
 
-template <int DT>
-__device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__restrict__ disp,
-                                          const uint8_t *__restrict__ img, float scale0, int h0, int w0,
-                                          int h1, int w1, int c1, int oy0, int ox0,
-                                          E1Out<DT> *__restrict__ out, Enc1Q &q) {
-    const int tid = threadIdx.x;
+// The raw coarse bytes of one tile's x0 patch, entries tid and tid + 256 of
+// the E1_PH x E1_PW patch per thread: loaded ahead of their use (before the
+// weights, and during the previous tile's arithmetic), converted when they
+// are written to LDS.  Entries outside the map read byte 0 and are zeroed.
+static_assert(E1_PH * E1_PW <= 512, "two patch entries per thread");
+struct E1Patch {
+    uint32_t d[2], im[2];
+    bool in[2];
+};
+
+__device__ __forceinline__ void enc1_fetch(E1Patch &P, const uint8_t *__restrict__ disp,
+                                           const uint8_t *__restrict__ img, int h0, int w0, int oy0, int ox0) {
     const int iy0 = 2 * oy0 - 1, ix0 = 2 * ox0 - 1;
-    for (int e = tid; e < E1_PH * E1_PW; e += 256) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = threadIdx.x + 256 * k;
         const int py = e / E1_PW, px = e - py * E1_PW;
         const int y = iy0 + py, x = ix0 + px;
+        P.in[k] = e < E1_PH * E1_PW && y >= 0 && y < h0 && x >= 0 && x < w0;
+        const size_t o = P.in[k] ? (size_t)y * w0 + x : 0;
+        P.d[k] = disp[o];
+        P.im[k] = img[o];
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ void enc1_put(const E1Patch &P, const Enc1Smem &sm, float scale0, const Enc1Q &q) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int e = threadIdx.x + 256 * k;
+        if (e >= E1_PH * E1_PW) continue;
         float a = 0.f, c = 0.f;
-        if (y >= 0 && y < h0 && x >= 0 && x < w0) {
-            const size_t o = (size_t)y * w0 + x;
-            a = scale0 * (float)disp[o];
-            c = (float)img[o] * (1.0f / 256.0f);
+        if (P.in[k]) {
+            a = scale0 * (float)P.d[k];
+            c = (float)P.im[k] * (1.0f / 256.0f);
             if constexpr (DT == SV_I8) {  // the INT8 codes, as values
                 a = fminf(fmaxf(rintf(a * q.qinv), -127.0f), 127.0f);
                 c = fminf(fmaxf(rintf(c * q.qinv), -127.0f), 127.0f);
@@ -95,7 +113,16 @@ __device__ __forceinline__ void enc1_tile(const Enc1Smem &sm, const uint8_t *__r
         sm.x[0][e] = a;
         sm.x[1][e] = c;
     }
-    __syncthreads();
+}
+
+// One tile's arithmetic and stores, the patch already in LDS (a barrier
+// after enc1_put): output rows [oy0, oy0 + E1_TH) and columns
+// [ox0, ox0 + E1_TW) of an h1 x w1 map.  Ends with a barrier, after which
+// the patch can take the next tile.
+template <int DT>
+__device__ __forceinline__ void enc1_compute(const Enc1Smem &sm, int h1, int w1, int c1, int oy0, int ox0,
+                                             E1Out<DT> *__restrict__ out, Enc1Q &q) {
+    const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int grp = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform channel group
     const int tx = lane & (E1_TW - 1), ty = lane / E1_TW;
@@ -166,6 +193,15 @@ k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float 
        const uint32_t *__restrict__ amax_in, uint32_t *__restrict__ amax_out) {
     extern __shared__ __attribute__((aligned(16))) float e1_dyn[];
     const Enc1Smem sm = enc1_smem(e1_dyn, c1);
+    const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
+    const int per = tx * ty, total = per * B;
+    // the first tile's patch loads go out before the weights'
+    E1Patch P;
+    if ((int)blockIdx.x < total) {
+        const int b = blockIdx.x / per, r = blockIdx.x - b * per;
+        const size_t i0 = (size_t)b * h0 * w0;
+        enc1_fetch(P, disp + i0, img + i0, h0, w0, (r / tx) * E1_TH, (r % tx) * E1_TW);
+    }
     enc1_weights<DT>(sm, wpk, n_pad, cin_pad, bias, c1);
     Enc1Q q{0.f, 0.f, wscale, 0.f};
     if constexpr (DT == SV_I8) {
@@ -177,13 +213,18 @@ k_enc1(const uint8_t *__restrict__ disp, const uint8_t *__restrict__ img, float 
         q.s_in = m / 127.0f;
         for (int n = threadIdx.x; n < c1; n += 256) sm.scale[n] = q.s_in * wscale[n];
     }
-    const int tx = cdiv_d(w1, E1_TW), ty = cdiv_d(h1, E1_TH);
-    const int per = tx * ty, total = per * B;
     for (int t = blockIdx.x; t < total; t += gridDim.x) {
         const int b = t / per, r = t - b * per;
-        const size_t i0 = (size_t)b * h0 * w0, o1 = (size_t)b * h1 * w1;
-        enc1_tile<DT>(sm, disp + i0, img + i0, scale0, h0, w0, h1, w1, c1, (r / tx) * E1_TH,
-                      (r % tx) * E1_TW, out + o1 * c1, q);
+        const size_t o1 = (size_t)b * h1 * w1;
+        enc1_put<DT>(P, sm, scale0, q);
+        __syncthreads();
+        const int tn = t + (int)gridDim.x;  // the next tile's patch, loaded during this one's arithmetic
+        if (tn < total) {
+            const int bn = tn / per, rn = tn - bn * per;
+            const size_t in0 = (size_t)bn * h0 * w0;
+            enc1_fetch(P, disp + in0, img + in0, h0, w0, (rn / tx) * E1_TH, (rn % tx) * E1_TW);
+        }
+        enc1_compute<DT>(sm, h1, w1, c1, (r / tx) * E1_TH, (r % tx) * E1_TW, out + o1 * c1, q);
     }
     if constexpr (DT == SV_I8) {
         // the workgroup's max: waves through the (free) patch area, then one
@@ -218,8 +259,12 @@ k_enc1_tab(const PairTable *__restrict__ tab, const uint8_t *__restrict__ disp, 
         const int local = t - cum[i];
         const int tx = cdiv_d(g.w[1], E1_TW);
         Enc1Q q{0.f, 0.f, nullptr, 0.f};  // (no INT8 pair-table path)
-        enc1_tile<DT>(sm, disp + g.off[0], img + g.off[0], scale0, g.h[0], g.w[0], g.h[1], g.w[1], c1,
-                      (local / tx) * E1_TH, (local % tx) * E1_TW, out + (size_t)g.off[1] * c1, q);
+        E1Patch P;
+        enc1_fetch(P, disp + g.off[0], img + g.off[0], g.h[0], g.w[0], (local / tx) * E1_TH, (local % tx) * E1_TW);
+        enc1_put<DT>(P, sm, scale0, q);
+        __syncthreads();
+        enc1_compute<DT>(sm, g.h[1], g.w[1], c1, (local / tx) * E1_TH, (local % tx) * E1_TW,
+                         out + (size_t)g.off[1] * c1, q);
     }
 }
 
