@@ -18,42 +18,11 @@
 //     projection gradient and, through the 9 x (c1+2) weights, the gradient of
 //     G0's pre-activation;
 //   * the encoder activations are recomputed from x0 (checkpointing).
+#include "mfma.h"
 #include "net.h"
 #include "prof.h"
 
 namespace sv {
-
-template <int DT> struct MfmaB;
-template <> struct MfmaB<SV_BF16> {
-    static constexpr int GS = 8;
-    typedef uint16_t T;
-    typedef u16x8 vec;
-    static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a),
-                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
-    }
-};
-template <> struct MfmaB<SV_F16> {
-    static constexpr int GS = 8;
-    typedef uint16_t T;
-    typedef u16x8 vec;
-    static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
-        return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, a),
-                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
-    }
-};
-template <> struct MfmaB<SV_F32> {
-    static constexpr int GS = 4;
-    typedef float T;
-    typedef f32x4 vec;
-    static __device__ __forceinline__ f32x4 run(vec a, vec b, f32x4 c) {
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[0], b[0], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[1], b[1], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[2], b[2], c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[3], b[3], c, 0, 0, 0);
-        return c;
-    }
-};
 
 // One element of a map stored in dtype sdt, as FP32.
 __device__ __forceinline__ float ld_el(const void *p, size_t i, int sdt) {
@@ -87,7 +56,7 @@ static inline int wg_kcw(int ks) { return ks == 1 ? 64 : 16; }
 template <int DT, int KS, int S>
 __global__ void __launch_bounds__(256) k_wgrad(const WgradParams p)
 {
-    using M = MfmaB<DT>;
+    using M = Mfma<DT>;
     using T = typename M::T;
     using vec = typename M::vec;
     constexpr int GS = M::GS;

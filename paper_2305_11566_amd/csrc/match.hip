@@ -306,9 +306,10 @@ k_reduce_census(const uint8_t *__restrict__ img0, const uint8_t *__restrict__ im
                 uint64_t *__restrict__ cen1)
 {
     __shared__ __attribute__((aligned(16))) CenPatch<TH> patch;
-    const int view = blockIdx.z % 2;
-    const int b = blockIdx.z / 2;
-    if (view && !img1) return;
+    // z = image x view (one view when img1 is NULL)
+    const int nv = img1 ? 2 : 1;
+    const int view = blockIdx.z % nv;
+    const int b = blockIdx.z / nv;
     const uint8_t *img = (view ? img1 : img0) + (size_t)b * H * pitch;
     uint8_t *low = view ? low1 : low0;
     uint64_t *cen = (view ? cen1 : cen0) + (size_t)b * h * w;
@@ -341,7 +342,7 @@ sv_status launch_reduce_census(const uint8_t *img0, const uint8_t *img1, int B, 
 {
     const int h = cdiv(H, f), w = cdiv(W, f);
     const int th = census_tile_height(B, h, w);
-    dim3 grid(cdiv(w, CEN_TW), cdiv(h, th), 2 * B);
+    dim3 grid(cdiv(w, CEN_TW), cdiv(h, th), (img1 ? 2 : 1) * B);
     const int rx = (win_w - 1) / 2, ry = (win_h - 1) / 2;
 #define SV_CEN_L(F, TH, RX, RY)                                                                    \
     hipLaunchKernelGGL((k_reduce_census<F, TH, RX, RY>), grid, dim3(CEN_THREADS), 0, s, img0, img1, \
