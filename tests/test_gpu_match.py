@@ -104,3 +104,23 @@ def test_determinism_repeat():
     b = _run_gpu(p.left[None], p.right[None], 4, 9, 7, 48)
     for x, y in zip(a, b):
         assert (x == y).all()
+
+
+def test_large_batch_equals_single_images():
+    """36 full-size pairs at f = 4 in one call (16-row census tiles, several
+    rows per cost + WTA workgroup): every image's words, reduced image and
+    disparities equal its single-image call (4-row tiles, one row per
+    workgroup), and two of them equal the oracle."""
+    import paper_2305_11566_amd as sv
+    B = 36
+    ps = [gen_pair(375, 1242, 5, 1.0, 150.0, seed=7300 + b) for b in range(B)]
+    left = np.stack([p.left for p in ps])
+    right = np.stack([p.right for p in ps])
+    gl, gr, glow, gd = _run_gpu(left, right, 4, 9, 7, 48)
+    for b in range(B):
+        sl, sr, slow, sd = _run_gpu(left[b:b + 1], right[b:b + 1], 4, 9, 7, 48)
+        assert (gl[b] == sl[0]).all() and (gr[b] == sr[0]).all(), f"image {b}: census"
+        assert (glow[b] == slow[0]).all() and (gd[b] == sd[0]).all(), f"image {b}: reduced / disparity"
+    for b in (0, B - 1):
+        lo, cl, cr, d = oracle.match(left[b:b + 1], right[b:b + 1], 4, 9, 7, 48)
+        assert (gl[b] == cl[0]).all() and (gr[b] == cr[0]).all() and (gd[b] == d[0]).all()
