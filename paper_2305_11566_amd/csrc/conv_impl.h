@@ -903,10 +903,10 @@ struct ConvTile {
 
 // Uniform batch: one workgroup per (column tile, row tile, image x channel tile).
 template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
-__global__ void __launch_bounds__(256) k_conv(const ConvParams p)
+__device__ __forceinline__ void conv_uniform(const ConvParams &p,
+                                             typename ConvTile<DT, KS, S, TH, TN, WM, KCM>::Smem &sm)
 {
     using CT = ConvTile<DT, KS, S, TH, TN, WM, KCM>;
-    __shared__ __attribute__((aligned(16))) typename CT::Smem sm;
     const int ntn = (p.Cout + TN - 1) / TN;
     const int ksplit = p.ksplit > 1 ? p.ksplit : 1;
     // XCD-aware order: workgroups go round robin to the eight XCDs (each with
@@ -936,6 +936,23 @@ __global__ void __launch_bounds__(256) k_conv(const ConvParams p)
     G.oy0 = by * TH;
     G.ox0 = bx * CT::TW;
     CT::run(p, G, sm, kz);
+}
+
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+__global__ void __launch_bounds__(256) k_conv(const ConvParams p)
+{
+    __shared__ __attribute__((aligned(16))) typename ConvTile<DT, KS, S, TH, TN, WM, KCM>::Smem sm;
+    conv_uniform<DT, KS, S, TH, TN, WM, KCM>(p, sm);
+}
+
+// The same, its registers held to two waves per SIMD (256 VGPRs, AGPRs
+// included), for the INT8 16-row stride-1 tiles, which the compiler would otherwise
+// take a few registers past that (one wave per SIMD, half the workgroups).
+template <int DT, int KS, int S, int TH, int TN, int WM, int KCM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_conv_w2(const ConvParams p)
+{
+    __shared__ __attribute__((aligned(16))) typename ConvTile<DT, KS, S, TH, TN, WM, KCM>::Smem sm;
+    conv_uniform<DT, KS, S, TH, TN, WM, KCM>(p, sm);
 }
 
 // Pair table: persistent loop over the stage's tiles of every pair.  It
@@ -1042,7 +1059,10 @@ static sv_status launch_one(const ConvParams &p, int pgrid, hipStream_t st) {
     const long long gz = (long long)p.B * cdiv(p.Cout, TN) * ksplit;
     if (gz > 65535) return SV_ERR_SHAPE;
     dim3 grid(cdiv(p.Wo, 16), cdiv(p.Ho, TH), (unsigned)gz);
-    hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
+    if constexpr (DT == SV_I8 && TH == 16 && S == 1)
+        hipLaunchKernelGGL((k_conv_w2<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
+    else
+        hipLaunchKernelGGL((k_conv<DT, KS, S, TH, TN, WM, KCM>), grid, dim3(256), 0, st, p);
     SV_LAUNCH_CHECK("k_conv");
     if (ksplit > 1 && !p.defer_sum) return launch_reduce<DT>(p, st);
     return SV_OK;
